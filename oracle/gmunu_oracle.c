@@ -1,0 +1,1022 @@
+/*
+ * Gmunu GRMHD finite-volume step -- CPU ORACLE (test infrastructure only).
+ *
+ * This file is the slow, plain, obviously-correct FP64 statement of what the
+ * GPU path computes.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load it.  The GPU library never links, includes or
+ * calls anything here, and this file includes nothing from the GPU library.
+ *
+ * Source: Cheong, Lam, Ng, Li et al., "Gmunu: paralleled, grid-adaptive,
+ * general-relativistic magnetohydrodynamics in curvilinear geometries in
+ * dynamical space-times" (arXiv 2012.07322).  Every function cites the section
+ * or equation it follows.  Where the paper is silent or garbled, the reading
+ * taken is stated at the spot (and listed in the design notes).
+ *
+ * Conventions
+ *   - Arrays are structure-of-arrays [var][k][j][i], i fastest, including
+ *     ghost cells: nt[a] = n[a] + 2*g[a], g[a] = ng on active axes, 0 else.
+ *   - prim = (rho, W v^1, W v^2, W v^3, p, B^1, B^2, B^3)  (contravariant,
+ *     coordinate basis, B undensitised).
+ *   - q    = psi^6 (D, S_1, S_2, S_3, tau, B^1, B^2, B^3)  (S covariant).
+ *   - metric = (psi, alpha, beta^1, beta^2, beta^3) at cell centres, ghosts
+ *     supplied by the caller.
+ *   - coordinates: 0 Cartesian (x,y,z); 1 cylindrical (R,z,phi);
+ *     2 spherical (r,theta,phi).
+ *
+ * Parity unpinned: the extrinsic-curvature terms of the energy source (only
+ * non-zero for a non-zero shift) are checked against the GPU path only.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NV 8
+
+enum { RHO = 0, WV1 = 1, PRS = 4, BB1 = 5 };
+enum { QD = 0, QS1 = 1, QTAU = 4, QB1 = 5 };
+enum { CART = 0, CYL = 1, SPH = 2 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_AXIS = 3, BC_CENTER = 4, BC_NONE = 5 };
+enum {
+  F_ATMO = 1, F_EPS_CLAMP = 2, F_V_CLAMP = 4, F_FATAL_RHO = 8,
+  F_FATAL_EPS = 16, F_FATAL_V = 32, F_NOCONV = 64
+};
+#define F_FATAL_MASK (F_FATAL_RHO | F_FATAL_EPS | F_FATAL_V | F_NOCONV)
+
+typedef struct {
+  int ndim, coord, n[3], ng;
+  double xmin[3], dx[3];
+  int bc[3][2];
+  double gamma;
+  double rho_atmo, k_atmo, gamma_atmo;
+  double rho_low_factor, alpha_bh;
+  double rho_max, eps_max, w_max;
+  int c2p_maxit;
+  double c2p_tol;
+  int rk;
+} og_desc;
+
+/* ------------------------------------------------------------------ grid */
+
+static int gh(const og_desc *d, int a) { return a < d->ndim ? d->ng : 0; }
+static int ntl(const og_desc *d, int a) { return d->n[a] + 2 * gh(d, a); }
+static long ntot(const og_desc *d) { return (long)ntl(d, 0) * ntl(d, 1) * ntl(d, 2); }
+
+/* linear index of cell (i,j,k); interior indices run 0..n-1, ghosts outside */
+static long at(const og_desc *d, int i, int j, int k) {
+  return ((long)(k + gh(d, 2)) * ntl(d, 1) + (j + gh(d, 1))) * ntl(d, 0) + (i + gh(d, 0));
+}
+
+static double centre(const og_desc *d, int a, int i) { return d->xmin[a] + (i + 0.5) * d->dx[a]; }
+static double face_pos(const og_desc *d, int a, int f) { return d->xmin[a] + f * d->dx[a]; }
+
+/* Diagonal of the reference (flat) metric at a point (Appendix A:
+ * cylindrical diag(1,1,R^2), spherical diag(1,r^2,r^2 sin^2 theta)). */
+static void ref_metric(int coord, double x1, double x2, double g[3]) {
+  g[0] = 1.0; g[1] = 1.0; g[2] = 1.0;
+  if (coord == CYL) {
+    g[2] = x1 * x1;
+  } else if (coord == SPH) {
+    double s = sin(x2);
+    g[1] = x1 * x1;
+    g[2] = x1 * x1 * s * s;
+  }
+}
+
+/* Cell volume Delta V = integral of sqrt(ref det) over the cell
+ * (Appendix A, cylindrical and spherical cell volumes). */
+static double cell_volume(const og_desc *d, int i, int j, int k) {
+  double x1 = centre(d, 0, i), x2 = centre(d, 1, j);
+  double d1 = d->dx[0], d2 = d->dx[1], d3 = d->dx[2];
+  (void)k;
+  if (d->coord == CYL) return x1 * d1 * d2 * d3;
+  if (d->coord == SPH) return (x1 * x1 + d1 * d1 / 12.0) * d1 * (2.0 * sin(x2) * sin(0.5 * d2)) * d3;
+  return d1 * d2 * d3;
+}
+
+/* Area of the face of index f along axis a (face between cells f-1 and f),
+ * at transverse cell (i,j,k) -- the other index along a is ignored
+ * (Appendix A, cylindrical and spherical cell surfaces). */
+static double face_area(const og_desc *d, int a, int f, int i, int j, int k) {
+  double d1 = d->dx[0], d2 = d->dx[1], d3 = d->dx[2];
+  (void)k;
+  if (d->coord == CART) {
+    if (a == 0) return d2 * d3;
+    if (a == 1) return d1 * d3;
+    return d1 * d2;
+  }
+  if (d->coord == CYL) {
+    if (a == 0) return face_pos(d, 0, f) * d2 * d3;
+    double R = centre(d, 0, i);
+    if (a == 1) return R * d1 * d3;
+    return R * d1 * d2;
+  }
+  /* spherical */
+  if (a == 0) {
+    double rf = face_pos(d, 0, f), th = centre(d, 1, j);
+    return rf * rf * (2.0 * sin(th) * sin(0.5 * d2)) * d3;
+  }
+  {
+    double r = centre(d, 0, i);
+    double radial = (r * r + d1 * d1 / 12.0) * d1;
+    if (a == 1) return radial * sin(face_pos(d, 1, f)) * d3;
+    return radial * (2.0 * sin(centre(d, 1, j)) * sin(0.5 * d2));
+  }
+}
+
+/* ------------------------------------------------------------ point state */
+
+/* Everything the conserved variables, fluxes and wave speeds need at one
+ * point, from the primitives and the CFC metric (section 2.1, magnetic
+ * four-vector and energy-momentum tensor). */
+typedef struct {
+  double gd[3], gu[3];           /* gamma_ii = psi^4 ref_ii and its inverse */
+  double psi6, alpha, beta[3];
+  double rho, p, eps, h, W;
+  double vu[3], vd[3];           /* Eulerian 3-velocity */
+  double Bu[3], Bd[3], Bv, B2;
+  double b0, bd[3], b2;
+  double rhohs, ps;              /* rho h*, p* */
+  double vhat[3];                /* alpha v^i - beta^i */
+} pstate;
+
+static void point_state(double gam, const double pr[NV], double psi, double alpha,
+                        const double beta[3], const double ref[3], pstate *s) {
+  double psi2 = psi * psi, psi4 = psi2 * psi2;
+  s->psi6 = psi4 * psi2;
+  s->alpha = alpha;
+  for (int i = 0; i < 3; i++) {
+    s->gd[i] = psi4 * ref[i];
+    s->gu[i] = 1.0 / s->gd[i];
+    s->beta[i] = beta[i];
+  }
+  s->rho = pr[RHO];
+  s->p = pr[PRS];
+  double u2 = 0.0;
+  for (int i = 0; i < 3; i++) u2 += s->gd[i] * pr[WV1 + i] * pr[WV1 + i];
+  s->W = sqrt(1.0 + u2);
+  s->Bv = 0.0;
+  s->B2 = 0.0;
+  for (int i = 0; i < 3; i++) {
+    s->vu[i] = pr[WV1 + i] / s->W;
+    s->vd[i] = s->gd[i] * s->vu[i];
+    s->Bu[i] = pr[BB1 + i];
+    s->Bd[i] = s->gd[i] * s->Bu[i];
+    s->Bv += s->Bu[i] * s->vd[i];
+    s->B2 += s->Bu[i] * s->Bd[i];
+  }
+  /* b^0 = W B^k v_k / alpha ; b_i = B_i / W + alpha b^0 v_i ;
+   * b^2 = B^i B_i / W^2 + (B^k v_k)^2 */
+  s->b0 = s->W * s->Bv / alpha;
+  for (int i = 0; i < 3; i++) s->bd[i] = s->Bd[i] / s->W + alpha * s->b0 * s->vd[i];
+  s->b2 = s->B2 / (s->W * s->W) + s->Bv * s->Bv;
+  /* ideal gas p = (Gamma-1) rho eps (section 3.1.1) */
+  s->eps = s->p / ((gam - 1.0) * s->rho);
+  s->h = 1.0 + s->eps + s->p / s->rho;
+  s->rhohs = s->rho * s->h + s->b2;
+  s->ps = s->p + 0.5 * s->b2;
+  for (int i = 0; i < 3; i++) s->vhat[i] = alpha * s->vu[i] - beta[i];
+}
+
+/* Densitised conserved variables (section 2.1, definitions of q). */
+static void cons_from_state(const pstate *s, double q[NV]) {
+  double D = s->rho * s->W;
+  double ab0 = s->alpha * s->b0;
+  q[QD] = s->psi6 * D;
+  for (int j = 0; j < 3; j++) q[QS1 + j] = s->psi6 * (s->rhohs * s->W * s->W * s->vd[j] - ab0 * s->bd[j]);
+  q[QTAU] = s->psi6 * (s->rhohs * s->W * s->W - s->ps - ab0 * ab0 - D);
+  for (int j = 0; j < 3; j++) q[QB1 + j] = s->psi6 * s->Bu[j];
+}
+
+/* Densitised flux along direction a (section 2.1, fluxes f^i).  The
+ * induction flux with j == a is identically zero and is set to zero rather
+ * than evaluated as a difference of equal products. */
+static void flux_from_state(const pstate *s, int a, double f[NV]) {
+  double D = s->rho * s->W;
+  double ab0 = s->alpha * s->b0;
+  double W2 = s->W * s->W;
+  double va = s->vhat[a];
+  double Ba = s->Bu[a];
+  f[QD] = s->psi6 * D * va;
+  for (int j = 0; j < 3; j++) {
+    double Sj = s->rhohs * W2 * s->vd[j] - ab0 * s->bd[j];
+    double fj = Sj * va - s->alpha * s->bd[j] * Ba / s->W;
+    if (j == a) fj += s->alpha * s->ps;
+    f[QS1 + j] = s->psi6 * fj;
+  }
+  {
+    double tau = s->rhohs * W2 - s->ps - ab0 * ab0 - D;
+    f[QTAU] = s->psi6 * (tau * va + s->alpha * s->ps * s->vu[a] - s->alpha * ab0 * Ba / s->W);
+  }
+  for (int j = 0; j < 3; j++)
+    f[QB1 + j] = (j == a) ? 0.0 : s->psi6 * (va * s->Bu[j] - s->vhat[j] * Ba);
+}
+
+/* Bounds of the characteristic speeds along a (section 2.3). */
+static void speeds_from_state(double gam, const pstate *s, int a, double *lm, double *lp) {
+  double cs2 = gam * s->p / (s->rho * s->h);
+  double ca2 = s->b2 / s->rhohs;
+  double a2 = cs2 + ca2 - cs2 * ca2;
+  double v2 = 0.0;
+  for (int i = 0; i < 3; i++) v2 += s->vu[i] * s->vd[i];
+  double va = s->vu[a];
+  double disc = a2 * (1.0 - v2) * ((1.0 - v2 * a2) * s->gu[a] - (1.0 - a2) * va * va);
+  double sq = sqrt(disc > 0.0 ? disc : 0.0);
+  double den = 1.0 - v2 * a2;
+  double lbm = ((1.0 - a2) * va - sq) / den;
+  double lbp = ((1.0 - a2) * va + sq) / den;
+  *lm = s->alpha * lbm - s->beta[a];
+  *lp = s->alpha * lbp - s->beta[a];
+}
+
+/* ------------------------------------------------------------------- c2p */
+
+typedef struct {
+  double D, qq, r2, B2c, rB, rperp2B2, h0, v0sq;
+  double rho_min, rho_max, eps_min, eps_max, gam;
+} c2p_consts;
+
+typedef struct {
+  double chi, rbar2, qbar, vhat2, What, rho, eps;
+} c2p_eval;
+
+/* Master function of the GRMHD recovery (section 2.5.2, step 3):
+ * f(mu) = mu - 1/(nu_hat + mu rbar^2), with rho and eps limited to the EOS
+ * validity range inside every evaluation. */
+static double c2p_f(const c2p_consts *c, double mu, c2p_eval *e) {
+  double chi = 1.0 / (1.0 + mu * c->B2c);
+  double rbar2 = c->r2 * chi * chi + mu * chi * (1.0 + chi) * c->rB * c->rB;
+  double qbar = c->qq - 0.5 * c->B2c - 0.5 * mu * mu * chi * chi * c->rperp2B2;
+  double vh2 = mu * mu * rbar2;
+  if (vh2 > c->v0sq) vh2 = c->v0sq;
+  double What = 1.0 / sqrt(1.0 - vh2);
+  double rho = c->D / What;
+  double eps = What * (qbar - mu * rbar2) + vh2 * What * What / (1.0 + What);
+  if (e) { e->chi = chi; e->rbar2 = rbar2; e->qbar = qbar; e->vhat2 = vh2; e->What = What; e->rho = rho; e->eps = eps; }
+  rho = fmax(fmin(c->rho_max, rho), c->rho_min);
+  eps = fmax(fmin(c->eps_max, eps), c->eps_min);
+  double p = (c->gam - 1.0) * rho * eps;
+  double ahat = p / (rho * (1.0 + eps));
+  double nuA = (1.0 + ahat) * (1.0 + eps) / What;
+  double nuB = (1.0 + ahat) * (1.0 + qbar - mu * rbar2);
+  double nu = nuA > nuB ? nuA : nuB;
+  return mu - 1.0 / (nu + mu * rbar2);
+}
+
+/* f_a(mu) = mu sqrt(h0^2 + rbar^2(mu)) - 1 and its derivative (section 2.5.2,
+ * step 2), whose root mu_+ bounds the root of the master function. */
+static double c2p_fa(const c2p_consts *c, double mu, double *dfa) {
+  double chi = 1.0 / (1.0 + mu * c->B2c);
+  double dchi = -c->B2c * chi * chi;
+  double rB2 = c->rB * c->rB;
+  double rbar2 = c->r2 * chi * chi + mu * chi * (1.0 + chi) * rB2;
+  double drbar2 = 2.0 * c->r2 * chi * dchi + rB2 * (chi * (1.0 + chi) + mu * dchi * (1.0 + 2.0 * chi));
+  double s = sqrt(c->h0 * c->h0 + rbar2);
+  if (dfa) *dfa = s + mu * drbar2 / (2.0 * s);
+  return mu * s - 1.0;
+}
+
+/* Illinois (modified regula falsi) root of g on the bracket [a, b] with
+ * g(a) < 0 < g(b) (Dowell & Jarratt 1971, as used in section 2.5). */
+typedef double (*scalar_fn)(const c2p_consts *, double);
+static double fa_only(const c2p_consts *c, double mu) { return c2p_fa(c, mu, NULL); }
+static double f_only(const c2p_consts *c, double mu) { return c2p_f(c, mu, NULL); }
+
+static double illinois(const c2p_consts *c, scalar_fn g, double a, double b, double tol, int maxit, int *iters, int *ok) {
+  double fa = g(c, a), fb = g(c, b);
+  *ok = 1;
+  *iters = 0;
+  if (fb == 0.0) return b;
+  if (fa == 0.0) return a;
+  if (fa * fb > 0.0) { *ok = 0; return fabs(fa) < fabs(fb) ? a : b; }
+  for (int it = 0; it < maxit; it++) {
+    double cc = b - fb * (b - a) / (fb - fa);
+    double fc = g(c, cc);
+    *iters = it + 1;
+    if (fc == 0.0) return cc;
+    if (fc * fb < 0.0) {
+      a = b;
+      fa = fb;
+    } else {
+      fa *= 0.5;
+    }
+    b = cc;
+    fb = fc;
+    if (fabs(b - a) <= tol * fabs(b)) return b;
+  }
+  *ok = 0;
+  return b;
+}
+
+static void atmosphere_prim(const og_desc *d, double B[3], double pr[NV]) {
+  pr[RHO] = d->rho_atmo;
+  pr[WV1] = pr[WV1 + 1] = pr[WV1 + 2] = 0.0;
+  pr[PRS] = d->k_atmo * pow(d->rho_atmo, d->gamma_atmo);
+  for (int i = 0; i < 3; i++) pr[BB1 + i] = B[i];
+}
+
+/* Recovery of the primitives from the densitised conserved variables at one
+ * cell (section 2.5.2 steps 1-4) followed by the error handling of section
+ * 2.5.3.  Returns the flag bits; *iters receives the master-function
+ * iteration count. */
+int og_c2p_point(const og_desc *d, const double qc[NV], double psi, double alpha,
+                 const double ref[3], double pr[NV], int *iters_out) {
+  double psi2 = psi * psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
+  double gd[3], gu[3];
+  for (int i = 0; i < 3; i++) { gd[i] = psi4 * ref[i]; gu[i] = 1.0 / gd[i]; }
+  double D = qc[QD] / psi6, tau = qc[QTAU] / psi6;
+  double Sd[3], Bu[3];
+  for (int i = 0; i < 3; i++) { Sd[i] = qc[QS1 + i] / psi6; Bu[i] = qc[QB1 + i] / psi6; }
+  int flags = 0;
+  if (iters_out) *iters_out = 0;
+  double rho_min = d->rho_atmo;
+
+  /* rho = D / W <= D, so D below rho_min already means rho < rho_min */
+  if (!(D >= rho_min)) {
+    atmosphere_prim(d, Bu, pr);
+    return F_ATMO;
+  }
+
+  /* step 1: rescaled variables */
+  c2p_consts c;
+  c.D = D;
+  c.qq = tau / D;
+  double ru[3], rd[3], Bcu[3];
+  double sqD = sqrt(D);
+  c.r2 = 0.0; c.B2c = 0.0; c.rB = 0.0;
+  for (int i = 0; i < 3; i++) {
+    rd[i] = Sd[i] / D;
+    ru[i] = gu[i] * rd[i];
+    Bcu[i] = Bu[i] / sqD;
+    c.r2 += ru[i] * rd[i];
+    c.B2c += gd[i] * Bcu[i] * Bcu[i];
+    c.rB += rd[i] * Bcu[i];
+  }
+  c.rperp2B2 = c.B2c * c.r2 - c.rB * c.rB;
+  if (c.rperp2B2 < 0.0) c.rperp2B2 = 0.0;
+  c.h0 = 1.0; /* ideal gas: h = 1 + eps + p/rho >= 1 over eps >= 0 */
+  c.v0sq = c.r2 / (c.h0 * c.h0 + c.r2);
+  c.rho_min = rho_min;
+  c.rho_max = d->rho_max;
+  c.eps_min = 0.0;
+  c.eps_max = d->eps_max;
+  c.gam = d->gamma;
+
+  /* step 2: mu_+ by Newton-Raphson from 1/h0, Illinois if that fails */
+  double muplus = 1.0 / c.h0;
+  {
+    double mu = 1.0 / c.h0;
+    int good = 0;
+    for (int it = 0; it < 60; it++) {
+      double dfa;
+      double fa = c2p_fa(&c, mu, &dfa);
+      if (fa == 0.0) { good = 1; break; }
+      double mn = mu - fa / dfa;
+      if (!(mn > 0.0 && mn <= 1.0 / c.h0)) break;
+      if (fabs(mn - mu) <= 1e-15 * mn) { mu = mn; good = 1; break; }
+      mu = mn;
+    }
+    if (!good) {
+      int it2, ok2;
+      mu = illinois(&c, fa_only, 0.0, 1.0 / c.h0, 1e-15, 200, &it2, &ok2);
+    }
+    muplus = mu;
+  }
+
+  /* step 3: the master function root on (0, mu_+] */
+  int iters = 0, ok = 1;
+  double mu;
+  {
+    double fb = c2p_f(&c, muplus, NULL);
+    if (fb <= 0.0) {
+      mu = muplus;
+    } else {
+      mu = illinois(&c, f_only, 0.0, muplus, d->c2p_tol, d->c2p_maxit, &iters, &ok);
+    }
+  }
+  if (iters_out) *iters_out = iters;
+  if (!ok) flags |= F_NOCONV;
+
+  /* step 4: primitives from mu (raw values, before the limits) */
+  c2p_eval e;
+  c2p_f(&c, mu, &e);
+  double W = e.What;
+  double rho = e.rho;
+  double eps = e.eps;
+  double vu[3];
+  for (int i = 0; i < 3; i++) vu[i] = mu * e.chi * (ru[i] + mu * c.rB * Bcu[i]);
+
+  /* error handling, section 2.5.3 */
+  double rho_low = d->rho_low_factor * d->rho_atmo;
+  if (rho < rho_min) {
+    atmosphere_prim(d, Bu, pr);
+    return flags | F_ATMO;
+  }
+  if (rho > d->rho_max) {
+    flags |= F_FATAL_RHO;
+    rho = d->rho_max;
+  }
+  int soft = (rho < rho_low) || (alpha < d->alpha_bh);
+  if (eps < 0.0) {
+    eps = 0.0;
+    flags |= F_EPS_CLAMP;
+  }
+  if (eps > d->eps_max) {
+    eps = d->eps_max;
+    flags |= soft ? F_EPS_CLAMP : F_FATAL_EPS;
+  }
+  if (W > d->w_max) {
+    if (soft) {
+      /* rescale v to v_max keeping D: rho = D / W_max, then re-limit */
+      double vmax2 = 1.0 - 1.0 / (d->w_max * d->w_max);
+      double v2 = 0.0;
+      for (int i = 0; i < 3; i++) v2 += vu[i] * gd[i] * vu[i];
+      double sc = sqrt(vmax2 / v2);
+      for (int i = 0; i < 3; i++) vu[i] *= sc;
+      W = d->w_max;
+      rho = D / W;
+      if (rho < rho_min) rho = rho_min;
+      if (rho > d->rho_max) rho = d->rho_max;
+      if (eps < 0.0) eps = 0.0;
+      if (eps > d->eps_max) eps = d->eps_max;
+      flags |= F_V_CLAMP;
+    } else {
+      flags |= F_FATAL_V;
+    }
+  }
+  pr[RHO] = rho;
+  for (int i = 0; i < 3; i++) pr[WV1 + i] = W * vu[i];
+  pr[PRS] = (d->gamma - 1.0) * rho * eps;
+  for (int i = 0; i < 3; i++) pr[BB1 + i] = Bu[i];
+  return flags;
+}
+
+/* --------------------------------------------------- exported point calls */
+
+void og_point_prim2con(double gam, const double pr[NV], const double met[5], const double ref[3], double q[NV]) {
+  pstate s;
+  point_state(gam, pr, met[0], met[1], met + 2, ref, &s);
+  cons_from_state(&s, q);
+}
+
+void og_point_flux(double gam, const double pr[NV], const double met[5], const double ref[3], int a,
+                   double f[NV], double lam[2]) {
+  pstate s;
+  point_state(gam, pr, met[0], met[1], met + 2, ref, &s);
+  flux_from_state(&s, a, f);
+  speeds_from_state(gam, &s, a, &lam[0], &lam[1]);
+}
+
+/* --------------------------------------------------------- reconstruction */
+
+/* Monotonised-central slope (van Leer 1977, the "MC" limiter of section 3):
+ * minmod(2 dl, (dl+dr)/2, 2 dr), zero where dl and dr differ in sign. */
+static double mc_slope(double um, double u0, double up) {
+  double dl = u0 - um, dr = up - u0;
+  if (dl * dr <= 0.0) return 0.0;
+  double c = 0.5 * (dl + dr);
+  double m = fmin(fmin(fabs(2.0 * dl), fabs(c)), fabs(2.0 * dr));
+  return dl > 0.0 ? m : -m;
+}
+
+/* HLLE flux (Harten, Lax & van Leer 1983; Einfeldt 1988), with the signal
+ * speeds bounded by zero.  If both bounds vanish the average is used. */
+static void hlle(const double fl[NV], const double fr[NV], const double ql[NV], const double qr[NV],
+                 double lm, double lp, double f[NV]) {
+  double ap = fmax(0.0, lp), am = fmin(0.0, lm);
+  double den = ap - am;
+  if (den < 1e-300) {
+    for (int v = 0; v < NV; v++) f[v] = 0.5 * (fl[v] + fr[v]);
+    return;
+  }
+  for (int v = 0; v < NV; v++) f[v] = (ap * fl[v] - am * fr[v] + ap * am * (qr[v] - ql[v])) / den;
+}
+
+static void load_metric(const og_desc *d, const double *met, long c, double m[5]) {
+  long nt = ntot(d);
+  for (int v = 0; v < 5; v++) m[v] = met[v * nt + c];
+}
+
+/* Flux times area through face f along axis a of the transverse cell
+ * (i,j,k): MC-reconstructed left/right primitives, face metric as the mean
+ * of the two neighbouring centres, then HLLE (section 2.1 discretised
+ * equation; section 3 solver settings). */
+static void face_flux(const og_desc *d, const double *prim, const double *met, int a, int f,
+                      int i, int j, int k, double out[NV]) {
+  int cell[3] = {i, j, k};
+  double area = face_area(d, a, f, i, j, k);
+  if (area == 0.0) {
+    for (int v = 0; v < NV; v++) out[v] = 0.0;
+    return;
+  }
+  long nt = ntot(d);
+  long idx[4];
+  for (int s = 0; s < 4; s++) {
+    int c[3] = {cell[0], cell[1], cell[2]};
+    c[a] = f - 2 + s;
+    idx[s] = at(d, c[0], c[1], c[2]);
+  }
+  double pl[NV], pr[NV];
+  for (int v = 0; v < NV; v++) {
+    double u0 = prim[v * nt + idx[0]], u1 = prim[v * nt + idx[1]];
+    double u2 = prim[v * nt + idx[2]], u3 = prim[v * nt + idx[3]];
+    pl[v] = u1 + 0.5 * mc_slope(u0, u1, u2);
+    pr[v] = u2 - 0.5 * mc_slope(u1, u2, u3);
+  }
+  double m1[5], m2[5], mf[5];
+  load_metric(d, met, idx[1], m1);
+  load_metric(d, met, idx[2], m2);
+  for (int v = 0; v < 5; v++) mf[v] = 0.5 * (m1[v] + m2[v]);
+  double x[3] = {centre(d, 0, i), centre(d, 1, j), centre(d, 2, k)};
+  x[a] = face_pos(d, a, f);
+  double ref[3];
+  ref_metric(d->coord, x[0], x[1], ref);
+  pstate sl, sr;
+  point_state(d->gamma, pl, mf[0], mf[1], mf + 2, ref, &sl);
+  point_state(d->gamma, pr, mf[0], mf[1], mf + 2, ref, &sr);
+  double ql[NV], qr[NV], fl[NV], fr[NV], lml, lpl, lmr, lpr;
+  cons_from_state(&sl, ql);
+  cons_from_state(&sr, qr);
+  flux_from_state(&sl, a, fl);
+  flux_from_state(&sr, a, fr);
+  speeds_from_state(d->gamma, &sl, a, &lml, &lpl);
+  speeds_from_state(d->gamma, &sr, a, &lmr, &lpr);
+  double fh[NV];
+  hlle(fl, fr, ql, qr, fmin(lml, lmr), fmax(lpl, lpr), fh);
+  for (int v = 0; v < NV; v++) out[v] = fh[v] * area;
+}
+
+/* -------------------------------------------------------------- sources */
+
+/* Point value of the reference-metric Christoffel symbols G[l][i][k]
+ * (Appendix A). */
+static void christoffel_point(int coord, double x1, double x2, double G[3][3][3]) {
+  memset(G, 0, sizeof(double) * 27);
+  if (coord == CYL) {
+    G[0][2][2] = -x1;
+    G[2][0][2] = G[2][2][0] = 1.0 / x1;
+  } else if (coord == SPH) {
+    double s = sin(x2), c = cos(x2);
+    G[0][1][1] = -x1;
+    G[0][2][2] = -x1 * s * s;
+    G[1][0][1] = G[1][1][0] = 1.0 / x1;
+    G[1][2][2] = -s * c;
+    G[2][0][2] = G[2][2][0] = 1.0 / x1;
+    G[2][1][2] = G[2][2][1] = c / s;
+  }
+}
+
+/* Gravitational sources s_S_i and s_tau at the centre of cell (i,j,k)
+ * (section 2.1, source terms), with centred differences of the metric
+ * (second-order, as the derivative stencils of section 2.7) and K_ij of the
+ * CFC metric under maximal slicing from the shift (section 2.6).  The result
+ * is added to s[]. */
+static void grav_sources(const og_desc *d, const double *met, const pstate *st, double psi, int i, int j, int k,
+                         const double ref[3], double x1, double x2, double s[NV]) {
+  int cell[3] = {i, j, k};
+  double dalpha[3] = {0, 0, 0}, dpsi[3] = {0, 0, 0}, dbeta[3][3] = {{0}};
+  long nt = ntot(d);
+  for (int a = 0; a < d->ndim; a++) {
+    int cp[3] = {cell[0], cell[1], cell[2]}, cm[3] = {cell[0], cell[1], cell[2]};
+    cp[a] += 1;
+    cm[a] -= 1;
+    long ip = at(d, cp[0], cp[1], cp[2]), im = at(d, cm[0], cm[1], cm[2]);
+    double inv = 1.0 / (2.0 * d->dx[a]);
+    dpsi[a] = (met[0 * nt + ip] - met[0 * nt + im]) * inv;
+    dalpha[a] = (met[1 * nt + ip] - met[1 * nt + im]) * inv;
+    for (int m = 0; m < 3; m++) dbeta[a][m] = (met[(2 + m) * nt + ip] - met[(2 + m) * nt + im]) * inv;
+  }
+  double alpha = st->alpha;
+  const double *beta = st->beta;
+  double G[3][3][3];
+  christoffel_point(d->coord, x1, x2, G);
+  /* covariant derivative of the shift, nb[i][k] = d_i beta^k + G^k_il beta^l */
+  double nb[3][3];
+  for (int a = 0; a < 3; a++)
+    for (int m = 0; m < 3; m++) {
+      double v = dbeta[a][m];
+      for (int l = 0; l < 3; l++) v += G[m][a][l] * beta[l];
+      nb[a][m] = v;
+    }
+  /* K_ij = psi^4/(2 alpha) (nb_i beta_j + nb_j beta_i - 2/3 ref_ij div beta) */
+  double K[3][3];
+  double divb = nb[0][0] + nb[1][1] + nb[2][2];
+  double psi4 = psi * psi * psi * psi;
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) {
+      double v = ref[b] * nb[a][b] + ref[a] * nb[b][a];
+      if (a == b) v -= 2.0 / 3.0 * ref[a] * divb;
+      K[a][b] = psi4 / (2.0 * alpha) * v;
+    }
+  /* T^{mu nu} = rho h* u^mu u^nu + p* g^{mu nu} - b^mu b^nu */
+  double W = st->W;
+  double u[4], bu[4];
+  u[0] = W / alpha;
+  for (int m = 0; m < 3; m++) u[1 + m] = W * (st->vu[m] - beta[m] / alpha);
+  bu[0] = st->b0;
+  for (int m = 0; m < 3; m++) bu[1 + m] = st->Bu[m] / W + st->b0 * st->vhat[m];
+  double ginv[4][4];
+  double ia2 = 1.0 / (alpha * alpha);
+  ginv[0][0] = -ia2;
+  for (int m = 0; m < 3; m++) { ginv[0][1 + m] = ginv[1 + m][0] = beta[m] * ia2; }
+  for (int m = 0; m < 3; m++)
+    for (int l = 0; l < 3; l++) ginv[1 + m][1 + l] = (m == l ? st->gu[m] : 0.0) - beta[m] * beta[l] * ia2;
+  double T[4][4];
+  for (int m = 0; m < 4; m++)
+    for (int l = 0; l < 4; l++) T[m][l] = st->rhohs * u[m] * u[l] + st->ps * ginv[m][l] - bu[m] * bu[l];
+  /* T^0_k = T^00 beta_k + T^0j gamma_jk */
+  double T0d[3];
+  for (int m = 0; m < 3; m++) T0d[m] = T[0][0] * st->gd[m] * beta[m] + T[0][1 + m] * st->gd[m];
+  double pre = alpha * st->psi6;
+  for (int a = 0; a < 3; a++) {
+    double v = -T[0][0] * alpha * dalpha[a];
+    for (int m = 0; m < 3; m++) v += T0d[m] * nb[a][m];
+    /* nabla_i gamma_jk = 4 psi^3 d_i psi ref_jk (diagonal) */
+    double dg = 4.0 * psi * psi * psi * dpsi[a];
+    for (int m = 0; m < 3; m++) {
+      double Tjk = T[0][0] * beta[m] * beta[m] + 2.0 * T[0][1 + m] * beta[m] + T[1 + m][1 + m];
+      v += 0.5 * Tjk * dg * ref[m];
+    }
+    s[QS1 + a] += pre * v;
+  }
+  {
+    double Kbb = 0.0, bda = 0.0, TK = 0.0, T0K = 0.0;
+    for (int a = 0; a < 3; a++) {
+      bda += beta[a] * dalpha[a];
+      for (int b = 0; b < 3; b++) {
+        Kbb += K[a][b] * beta[a] * beta[b];
+        TK += T[1 + a][1 + b] * K[a][b];
+      }
+    }
+    for (int a = 0; a < 3; a++) {
+      double Kb = 0.0;
+      for (int b = 0; b < 3; b++) Kb += K[a][b] * beta[b];
+      T0K += T[0][1 + a] * (2.0 * Kb - dalpha[a]);
+    }
+    s[QTAU] += pre * (T[0][0] * (Kbb - bda) + T0K + TK);
+  }
+}
+
+/* Geometric sources <Gamma^l_ik> (f_S_l)^k with the fluxes taken at the cell
+ * centre (section 2.1 and Appendix A).  The row of the ignorable phi
+ * coordinate is zero by construction.  The spherical <Gamma^phi_theta phi>
+ * is taken as the exact cell average, (A_theta+ - A_theta-)/dV, of which the
+ * printed cot(theta) is the point value. */
+static void geom_sources(const og_desc *d, const pstate *st, int i, int j, int k, double s[NV]) {
+  if (d->coord == CART) return;
+  double f[3][NV];
+  for (int a = 0; a < 3; a++) flux_from_state(st, a, f[a]);
+  double dV = cell_volume(d, i, j, k);
+  if (d->coord == CYL) {
+    double R = centre(d, 0, i);
+    s[QS1 + 0] += (1.0 / R) * f[2][QS1 + 2];
+    return;
+  }
+  double rp = face_pos(d, 0, i + 1), rm = face_pos(d, 0, i);
+  double Arp = face_area(d, 0, i + 1, i, j, k), Arm = face_area(d, 0, i, i, j, k);
+  double Atp = face_area(d, 1, j + 1, i, j, k), Atm = face_area(d, 1, j, i, j, k);
+  double g_th_rth = 0.5 * (Arp - Arm) / dV;          /* <G^th_r th> = <G^ph_r ph> */
+  double g_r_thth = -0.25 * (rp * rp * Arp - rm * rm * Arm) / dV; /* <G^r_th th> */
+  double g_ph_thph = (Atp - Atm) / dV;                /* <G^ph_th ph> */
+  s[QS1 + 0] += g_th_rth * f[1][QS1 + 1] + g_th_rth * f[2][QS1 + 2];
+  s[QS1 + 1] += g_r_thth * f[1][QS1 + 0] + g_th_rth * f[0][QS1 + 1] + g_ph_thph * f[2][QS1 + 2];
+}
+
+/* ------------------------------------------------------------------- RHS */
+
+/* d<q>/dt at interior cell (i,j,k): minus the flux-area divergence over the
+ * cell volume plus the gravitational and geometric sources (section 2.1,
+ * the discretised equation; the minus sign on the flux bracket follows from
+ * the conservation law and the positivity-limiter form of section 2.4). */
+void og_rhs_cell(const og_desc *d, const double *prim, const double *met, int i, int j, int k, double dq[NV]) {
+  int cell[3] = {i, j, k};
+  for (int v = 0; v < NV; v++) dq[v] = 0.0;
+  double dV = cell_volume(d, i, j, k);
+  for (int a = 0; a < d->ndim; a++) {
+    double fm[NV], fp[NV];
+    face_flux(d, prim, met, a, cell[a], i, j, k, fm);
+    face_flux(d, prim, met, a, cell[a] + 1, i, j, k, fp);
+    for (int v = 0; v < NV; v++) dq[v] -= (fp[v] - fm[v]) / dV;
+  }
+  long nt = ntot(d), c = at(d, i, j, k);
+  double pr[NV], m[5];
+  for (int v = 0; v < NV; v++) pr[v] = prim[v * nt + c];
+  load_metric(d, met, c, m);
+  double x1 = centre(d, 0, i), x2 = centre(d, 1, j);
+  double ref[3];
+  ref_metric(d->coord, x1, x2, ref);
+  pstate st;
+  point_state(d->gamma, pr, m[0], m[1], m + 2, ref, &st);
+  double s[NV] = {0};
+  grav_sources(d, met, &st, m[0], i, j, k, ref, x1, x2, s);
+  geom_sources(d, &st, i, j, k, s);
+  for (int v = 0; v < NV; v++) dq[v] += s[v];
+}
+
+void og_rhs(const og_desc *d, const double *prim, const double *met, double *dqdt) {
+  long nt = ntot(d);
+  for (int k = 0; k < d->n[2]; k++)
+    for (int j = 0; j < d->n[1]; j++)
+      for (int i = 0; i < d->n[0]; i++) {
+        double dq[NV];
+        og_rhs_cell(d, prim, met, i, j, k, dq);
+        long c = at(d, i, j, k);
+        for (int v = 0; v < NV; v++) dqdt[v * nt + c] = dq[v];
+      }
+}
+
+/* RHS at a list of interior cells given as (i,j,k) triples; out is [n][8]. */
+void og_rhs_cells(const og_desc *d, const double *prim, const double *met, long ncell, const int *ijk, double *out) {
+  for (long c = 0; c < ncell; c++) og_rhs_cell(d, prim, met, ijk[3 * c], ijk[3 * c + 1], ijk[3 * c + 2], out + NV * c);
+}
+
+/* Each cell's contribution magnitudes: sum over faces of |F A|/dV plus
+ * |sources|; the scale against which a RHS difference is measured. */
+void og_rhs_scale_cells(const og_desc *d, const double *prim, const double *met, long ncell, const int *ijk, double *out) {
+  long nt = ntot(d);
+  for (long c = 0; c < ncell; c++) {
+    int i = ijk[3 * c], j = ijk[3 * c + 1], k = ijk[3 * c + 2];
+    int cell[3] = {i, j, k};
+    double *o = out + NV * c;
+    for (int v = 0; v < NV; v++) o[v] = 0.0;
+    double dV = cell_volume(d, i, j, k);
+    for (int a = 0; a < d->ndim; a++) {
+      double fm[NV], fp[NV];
+      face_flux(d, prim, met, a, cell[a], i, j, k, fm);
+      face_flux(d, prim, met, a, cell[a] + 1, i, j, k, fp);
+      for (int v = 0; v < NV; v++) o[v] += (fabs(fp[v]) + fabs(fm[v])) / dV;
+    }
+    long cc = at(d, i, j, k);
+    double pr[NV], m[5];
+    for (int v = 0; v < NV; v++) pr[v] = prim[v * nt + cc];
+    load_metric(d, met, cc, m);
+    double x1 = centre(d, 0, i), x2 = centre(d, 1, j);
+    double ref[3];
+    ref_metric(d->coord, x1, x2, ref);
+    pstate st;
+    point_state(d->gamma, pr, m[0], m[1], m + 2, ref, &st);
+    double s1[NV] = {0}, s2[NV] = {0};
+    grav_sources(d, met, &st, m[0], i, j, k, ref, x1, x2, s1);
+    geom_sources(d, &st, i, j, k, s2);
+    for (int v = 0; v < NV; v++) o[v] += fabs(s1[v]) + fabs(s2[v]);
+  }
+}
+
+/* ------------------------------------------------------ prim2con / c2p */
+
+void og_prim2con(const og_desc *d, const double *prim, const double *met, double *q) {
+  long nt = ntot(d);
+  for (int k = -gh(d, 2); k < d->n[2] + gh(d, 2); k++)
+    for (int j = -gh(d, 1); j < d->n[1] + gh(d, 1); j++)
+      for (int i = -gh(d, 0); i < d->n[0] + gh(d, 0); i++) {
+        long c = at(d, i, j, k);
+        double pr[NV], m[5], ref[3], qq[NV];
+        for (int v = 0; v < NV; v++) pr[v] = prim[v * nt + c];
+        load_metric(d, met, c, m);
+        ref_metric(d->coord, centre(d, 0, i), centre(d, 1, j), ref);
+        og_point_prim2con(d->gamma, pr, m, ref, qq);
+        for (int v = 0; v < NV; v++) q[v * nt + c] = qq[v];
+      }
+}
+
+/* c2p over interior cells.  Cells whose primitives were corrected (atmosphere
+ * or clamps) get q rewritten from the corrected primitives.  Returns the
+ * number of cells with a fatal flag. */
+long og_c2p(const og_desc *d, double *q, const double *met, double *prim, uint8_t *flags) {
+  long nt = ntot(d), nfatal = 0;
+  for (int k = 0; k < d->n[2]; k++)
+    for (int j = 0; j < d->n[1]; j++)
+      for (int i = 0; i < d->n[0]; i++) {
+        long c = at(d, i, j, k);
+        double qc[NV], pr[NV], m[5], ref[3];
+        for (int v = 0; v < NV; v++) qc[v] = q[v * nt + c];
+        load_metric(d, met, c, m);
+        ref_metric(d->coord, centre(d, 0, i), centre(d, 1, j), ref);
+        int fl = og_c2p_point(d, qc, m[0], m[1], ref, pr, NULL);
+        for (int v = 0; v < NV; v++) prim[v * nt + c] = pr[v];
+        if (fl & (F_ATMO | F_EPS_CLAMP | F_V_CLAMP)) {
+          double qn[NV];
+          og_point_prim2con(d->gamma, pr, m, ref, qn);
+          for (int v = 0; v < NV; v++) q[v * nt + c] = qn[v];
+        }
+        if (fl & F_FATAL_MASK) nfatal++;
+        if (flags) flags[c] = (uint8_t)fl;
+      }
+  return nfatal;
+}
+
+/* ----------------------------------------------------------- ghost fill */
+
+/* Sign of variable v when mirrored through a boundary of type bc on axis a.
+ * Vectors are contravariant coordinate components, so the parities follow
+ * from continuing the coordinates through the boundary: the ghost at the
+ * formal position (-R, z) or (r, -theta) is the point at phi + pi, the ghost
+ * at (-r, theta) is the point (r, pi - theta, phi + pi).
+ *   REFLECT (a wall): the normal component is odd.
+ *   AXIS (R = 0, theta = 0 or pi): the normal component is odd; the phi
+ *     component (an angular rate) is even.
+ *   CENTER (r = 0): the r and theta components are odd, phi is even. */
+static double mirror_sign(int bc, int a, int v) {
+  int comp = -1;
+  if (v >= WV1 && v < WV1 + 3) comp = v - WV1;
+  if (v >= BB1 && v < BB1 + 3) comp = v - BB1;
+  if (comp < 0) return 1.0;
+  if (bc == BC_REFLECT || bc == BC_AXIS) return comp == a ? -1.0 : 1.0;
+  if (bc == BC_CENTER) return (comp == 0 || comp == 1) ? -1.0 : 1.0;
+  return 1.0;
+}
+
+/* Fill the ghost cells that share a face-normal line with the interior (the
+ * only ghosts any stencil of the scheme reads). */
+void og_fill_ghosts(const og_desc *d, double *prim) {
+  long nt = ntot(d);
+  for (int a = 0; a < d->ndim; a++) {
+    int g = d->ng, n = d->n[a];
+    int lo[3] = {0, 0, 0}, hi[3] = {d->n[0], d->n[1], d->n[2]};
+    for (int side = 0; side < 2; side++) {
+      int bc = d->bc[a][side];
+      if (bc == BC_NONE) continue;
+      lo[a] = 0; hi[a] = 1;
+      for (int k = lo[2]; k < hi[2]; k++)
+        for (int j = lo[1]; j < hi[1]; j++)
+          for (int i = lo[0]; i < hi[0]; i++)
+            for (int l = 0; l < g; l++) {
+              int dst[3] = {i, j, k}, src[3] = {i, j, k};
+              int gi = side == 0 ? -1 - l : n + l;   /* ghost index along a */
+              dst[a] = gi;
+              double sgn[NV];
+              for (int v = 0; v < NV; v++) sgn[v] = 1.0;
+              if (bc == BC_PERIODIC) {
+                src[a] = side == 0 ? gi + n : gi - n;
+              } else if (bc == BC_OUTFLOW) {
+                src[a] = side == 0 ? 0 : n - 1;
+              } else {
+                src[a] = side == 0 ? -1 - gi : 2 * n - 1 - gi;
+                for (int v = 0; v < NV; v++) sgn[v] = mirror_sign(bc, a, v);
+                if (bc == BC_CENTER && d->ndim > 1) src[1] = d->n[1] - 1 - src[1];
+                if ((bc == BC_CENTER || bc == BC_AXIS) && d->ndim > 2) src[2] = (src[2] + d->n[2] / 2) % d->n[2];
+              }
+              long cd = at(d, dst[0], dst[1], dst[2]), cs = at(d, src[0], src[1], src[2]);
+              for (int v = 0; v < NV; v++) prim[v * nt + cd] = sgn[v] * prim[v * nt + cs];
+            }
+      lo[a] = 0; hi[a] = d->n[a];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------ CFL */
+
+/* Time step by the "maxsum" rule (section 2.9): dt = c / max over cells of
+ * sum over active axes of max|lambda|/dx, with coordinate speeds and
+ * coordinate spacings; dt is capped at t_end - t. */
+double og_cfl_dt(const og_desc *d, const double *prim, const double *met, double cfl, double t, double t_end) {
+  long nt = ntot(d);
+  double mx = 0.0;
+  for (int k = 0; k < d->n[2]; k++)
+    for (int j = 0; j < d->n[1]; j++)
+      for (int i = 0; i < d->n[0]; i++) {
+        long c = at(d, i, j, k);
+        double pr[NV], m[5], ref[3];
+        for (int v = 0; v < NV; v++) pr[v] = prim[v * nt + c];
+        load_metric(d, met, c, m);
+        ref_metric(d->coord, centre(d, 0, i), centre(d, 1, j), ref);
+        pstate st;
+        point_state(d->gamma, pr, m[0], m[1], m + 2, ref, &st);
+        double sum = 0.0;
+        for (int a = 0; a < d->ndim; a++) {
+          double lm, lp;
+          speeds_from_state(d->gamma, &st, a, &lm, &lp);
+          sum += fmax(fabs(lm), fabs(lp)) / d->dx[a];
+        }
+        if (sum > mx) mx = sum;
+      }
+  double dt = mx > 0.0 ? cfl / mx : t_end - t;
+  if (t + dt > t_end) dt = t_end - t;
+  return dt;
+}
+
+/* -------------------------------------------------------------- stepping */
+
+/* One stage of the strong-stability-preserving Runge-Kutta integrators
+ * (SSPRK3 is the default of section 3; SSPRK2 the setting of the convergence
+ * tests).  Shu-Osher form:
+ *   SSPRK3: u1 = un + dt L(un); u2 = 3/4 un + 1/4 (u1 + dt L(u1));
+ *           un+1 = 1/3 un + 2/3 (u2 + dt L(u2))
+ *   SSPRK2: u1 = un + dt L(un); un+1 = 1/2 un + 1/2 (u1 + dt L(u1)).
+ * prim must hold the primitives of the current stage state with ghosts.
+ * On return qs holds the new stage state and prim its primitives (c2p, then
+ * ghost fill).  Returns the number of fatal c2p cells. */
+long og_rk_stage(const og_desc *d, int stage, double dt, const double *qn, double *qs, double *prim,
+                 const double *met, uint8_t *flags) {
+  long nt = ntot(d);
+  double a, b;
+  if (stage == 0) { a = 0.0; b = 1.0; }
+  else if (d->rk == 2) { a = 0.5; b = 0.5; }
+  else if (stage == 1) { a = 0.75; b = 0.25; }
+  else { a = 1.0 / 3.0; b = 2.0 / 3.0; }
+  double *L = (double *)malloc(sizeof(double) * NV * nt);
+  og_rhs(d, prim, met, L);
+  for (int k = 0; k < d->n[2]; k++)
+    for (int j = 0; j < d->n[1]; j++)
+      for (int i = 0; i < d->n[0]; i++) {
+        long c = at(d, i, j, k);
+        for (int v = 0; v < NV; v++) {
+          long o = v * nt + c;
+          double us = stage == 0 ? qn[o] : qs[o];
+          qs[o] = a * qn[o] + b * (us + dt * L[o]);
+        }
+      }
+  free(L);
+  long nf = og_c2p(d, qs, met, prim, flags);
+  og_fill_ghosts(d, prim);
+  return nf;
+}
+
+/* Advance q (and prim, which must be consistent with q, ghosts filled) by up
+ * to nsteps steps or until t_end.  Returns the number of steps taken; *t is
+ * advanced.  *nfatal accumulates fatal c2p cells. */
+long og_evolve(const og_desc *d, double *q, double *prim, const double *met, double cfl, double *t,
+               double t_end, long nsteps, long *nfatal) {
+  long nt = ntot(d);
+  double *qs = (double *)malloc(sizeof(double) * NV * nt);
+  memcpy(qs, q, sizeof(double) * NV * nt);
+  long s = 0;
+  int nst = d->rk == 2 ? 2 : 3;
+  while (s < nsteps && *t < t_end) {
+    double dt = og_cfl_dt(d, prim, met, cfl, *t, t_end);
+    if (!(dt > 0.0)) break;
+    for (int st = 0; st < nst; st++) *nfatal += og_rk_stage(d, st, dt, q, qs, prim, met, NULL);
+    memcpy(q, qs, sizeof(double) * NV * nt);
+    *t += dt;
+    s++;
+  }
+  free(qs);
+  return s;
+}
+
+/* ---------------------------------------------------------- diagnostics */
+
+/* Cell volumes of the interior (for volume-weighted norms and the rest-mass
+ * integral of section 3.3). */
+void og_cell_volumes(const og_desc *d, double *out) {
+  long nt = ntot(d);
+  for (long c = 0; c < nt; c++) out[c] = 0.0;
+  for (int k = 0; k < d->n[2]; k++)
+    for (int j = 0; j < d->n[1]; j++)
+      for (int i = 0; i < d->n[0]; i++) out[at(d, i, j, k)] = cell_volume(d, i, j, k);
+}
+
+/* Geometry exported for checks: cell volume, the two face areas along each
+ * axis, and the averaged Christoffel symbols of cell (i,j,k):
+ * out = [dV, A0-, A0+, A1-, A1+, A2-, A2+, <G^th_r th>, <G^r_th th>,
+ *        <G^ph_th ph>, <G^R_ph ph>, <G^ph_R ph>] */
+void og_cell_geometry(const og_desc *d, int i, int j, int k, double out[12]) {
+  int cell[3] = {i, j, k};
+  double dV = cell_volume(d, i, j, k);
+  out[0] = dV;
+  for (int a = 0; a < 3; a++) {
+    out[1 + 2 * a] = face_area(d, a, cell[a], i, j, k);
+    out[2 + 2 * a] = face_area(d, a, cell[a] + 1, i, j, k);
+  }
+  for (int v = 7; v < 12; v++) out[v] = 0.0;
+  if (d->coord == SPH) {
+    double rp = face_pos(d, 0, i + 1), rm = face_pos(d, 0, i);
+    out[7] = 0.5 * (out[2] - out[1]) / dV;
+    out[8] = -0.25 * (rp * rp * out[2] - rm * rm * out[1]) / dV;
+    out[9] = (out[4] - out[3]) / dV;
+  } else if (d->coord == CYL) {
+    double R = centre(d, 0, i), dR = d->dx[0];
+    out[10] = -(R * R + dR * dR / 12.0) / R;
+    out[11] = 1.0 / R;
+  }
+}
+
+long og_ntot(const og_desc *d) { return ntot(d); }
+long og_index(const og_desc *d, int i, int j, int k) { return at(d, i, j, k); }
+int og_desc_size(void) { return (int)sizeof(og_desc); }
+
+/* MC-reconstructed face values of one variable on a line: for each face
+ * f = 1..n-3 between cells f and f+1 of u[0..n-1], left value from cell f,
+ * right value from cell f+1.  out_l/out_r have n-3 entries. */
+void og_mc_faces(int n, const double *u, double *out_l, double *out_r) {
+  for (int f = 1; f + 2 < n; f++) {
+    out_l[f - 1] = u[f] + 0.5 * mc_slope(u[f - 1], u[f], u[f + 1]);
+    out_r[f - 1] = u[f + 1] - 0.5 * mc_slope(u[f], u[f + 1], u[f + 2]);
+  }
+}
+
+/* HLLE flux between two primitive states at one point (flux, not times area). */
+void og_point_hlle(double gam, const double pl[NV], const double pr[NV], const double met[5], const double ref[3],
+                   int a, double f[NV]) {
+  pstate sl, sr;
+  point_state(gam, pl, met[0], met[1], met + 2, ref, &sl);
+  point_state(gam, pr, met[0], met[1], met + 2, ref, &sr);
+  double ql[NV], qr[NV], fl[NV], fr[NV], lml, lpl, lmr, lpr;
+  cons_from_state(&sl, ql);
+  cons_from_state(&sr, qr);
+  flux_from_state(&sl, a, fl);
+  flux_from_state(&sr, a, fr);
+  speeds_from_state(gam, &sl, a, &lml, &lpl);
+  speeds_from_state(gam, &sr, a, &lmr, &lpr);
+  hlle(fl, fr, ql, qr, fmin(lml, lmr), fmax(lpl, lpr), f);
+}

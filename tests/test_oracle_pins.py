@@ -1,0 +1,499 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types an oracle formula: each compares against an
+independent construction (numerical quadrature, 4D tensor algebra, an exact
+Riemann solver, exact wave solutions, closed forms, conservation laws,
+printed convergence rates of the paper).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import workloads as W
+from exact_srhd import RiemannSRHD, jump_residuals
+
+# ------------------------------------------------------------------ geometry
+
+
+@pytest.mark.parametrize("coord", [W.CYL, W.SPH])
+def test_geometry_against_quadrature(coord):
+    """Cell volume, face areas and averaged Christoffel symbols (Appendix A)
+    against 2D numerical quadrature of sqrt(ref det) and of Gamma sqrt(ref det)."""
+    if coord == W.SPH:
+        p = W.grid(3, W.SPH, [8, 6, 4], [0.0, 0.0, 0.0], [2.0, math.pi, 2 * math.pi], [[1, 1]] * 3)
+    else:
+        p = W.grid(3, W.CYL, [8, 6, 4], [0.0, -1.0, 0.0], [2.0, 1.0, 2 * math.pi], [[1, 1]] * 3)
+    dx = p["dx"]
+    for (i, j, k) in [(0, 0, 0), (3, 2, 1), (7, 5, 3), (1, 3, 2)]:
+        g = oracle.cell_geometry(p, i, j, k)
+        lo = [p["xmin"][a] + [i, j, k][a] * dx[a] for a in range(3)]
+        hi = [lo[a] + dx[a] for a in range(3)]
+        if coord == W.SPH:
+            sq = lambda th, r: r * r * math.sin(th)
+            vol = integrate.dblquad(sq, lo[0], hi[0], lo[1], hi[1], epsabs=1e-17, epsrel=1e-13)[0] * dx[2]
+            a_rm = lo[0] ** 2 * (math.cos(lo[1]) - math.cos(hi[1])) * dx[2]
+            a_rp = hi[0] ** 2 * (math.cos(lo[1]) - math.cos(hi[1])) * dx[2]
+            r2 = (hi[0] ** 3 - lo[0] ** 3) / 3.0
+            a_tm, a_tp = r2 * math.sin(lo[1]) * dx[2], r2 * math.sin(hi[1]) * dx[2]
+            # <Gamma^th_r th> = <1/r>,  <Gamma^r_th th> = <-r>,  <Gamma^ph_th ph> = <cot th>
+            g1 = integrate.dblquad(lambda th, r: r * math.sin(th), lo[0], hi[0], lo[1], hi[1],
+                                   epsabs=1e-17, epsrel=1e-13)[0] * dx[2] / vol
+            g2 = integrate.dblquad(lambda th, r: -r ** 3 * math.sin(th), lo[0], hi[0], lo[1], hi[1],
+                                   epsabs=1e-17, epsrel=1e-13)[0] * dx[2] / vol
+            g3 = integrate.dblquad(lambda th, r: r * r * math.cos(th), lo[0], hi[0], lo[1], hi[1],
+                                   epsabs=1e-17, epsrel=1e-13)[0] * dx[2] / vol
+            want = [vol, a_rm, a_rp, a_tm, a_tp]
+            got = [g[0], g[1], g[2], g[3], g[4]]
+            np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-15)
+            np.testing.assert_allclose([g[7], g[8], g[9]], [g1, g2, g3], rtol=1e-12, atol=1e-14)
+        else:
+            vol = integrate.quad(lambda R: R, lo[0], hi[0], epsabs=1e-17, epsrel=1e-13)[0] * dx[1] * dx[2]
+            g_rpp = integrate.quad(lambda R: -R * R, lo[0], hi[0], epsabs=1e-17, epsrel=1e-13)[0] * dx[1] * dx[2] / vol
+            g_prp = integrate.quad(lambda R: 1.0, lo[0], hi[0], epsabs=1e-17, epsrel=1e-13)[0] * dx[1] * dx[2] / vol
+            np.testing.assert_allclose([g[0], g[1], g[2]], [vol, lo[0] * dx[1] * dx[2], hi[0] * dx[1] * dx[2]],
+                                       rtol=1e-13, atol=1e-15)
+            np.testing.assert_allclose([g[10], g[11]], [g_rpp, g_prp], rtol=1e-13)
+
+
+# ------------------------------------------------------- point-wise physics
+
+def tensor_construction(gamma, prim, psi, alpha, beta, ref):
+    """Conserved variables and fluxes from the 4D energy-momentum tensor,
+    built with plain tensor algebra: u^mu from (W, v), b^mu by projecting the
+    Eulerian field, T^{mu nu}, then D = rho W, S_j = alpha T^0_j,
+    tau = alpha^2 T^00 - D, f^i_S_j = alpha T^i_j, f^i_tau = alpha^2 T^0i - D vhat^i,
+    f^i_B^j = alpha (b^j u^i - b^i u^j), all times psi^6."""
+    gd = psi ** 4 * np.asarray(ref)
+    beta = np.asarray(beta, dtype=float)
+    g4 = np.zeros((4, 4))
+    bd = gd * beta
+    g4[0, 0] = -alpha * alpha + (bd * beta).sum()
+    g4[0, 1:] = g4[1:, 0] = bd
+    g4[1:, 1:] = np.diag(gd)
+    ginv = np.linalg.inv(g4)
+    Wv = np.asarray(prim[1:4])
+    W = math.sqrt(1.0 + (gd * Wv * Wv).sum())
+    v = Wv / W
+    u = np.concatenate([[W / alpha], W * (v - beta / alpha)])
+    ud = g4 @ u
+    B4 = np.concatenate([[0.0], prim[5:8]])
+    b = (B4 + (ud @ B4) * u) / W
+    b2 = b @ g4 @ b
+    rho, p = prim[0], prim[4]
+    h = 1.0 + gamma / (gamma - 1.0) * p / rho
+    T = (rho * h + b2) * np.outer(u, u) + (p + 0.5 * b2) * ginv - np.outer(b, b)
+    Tm = T @ g4  # T^mu_nu
+    s6 = psi ** 6
+    D = rho * W
+    q = np.concatenate([[D], alpha * Tm[0, 1:], [alpha ** 2 * T[0, 0] - D], prim[5:8]]) * s6
+    fl = []
+    for i in range(3):
+        vhat = alpha * u[1 + i] / W
+        f = [D * vhat]
+        f += [alpha * Tm[1 + i, 1 + j] for j in range(3)]
+        f += [alpha ** 2 * T[0, 1 + i] - D * vhat]
+        f += [alpha * (b[1 + j] * u[1 + i] - b[1 + i] * u[1 + j]) for j in range(3)]
+        fl.append(np.array(f) * s6)
+    return q, fl, b2, W
+
+
+def test_prim2con_and_flux_against_tensor_algebra():
+    pr, psi, al, ref = W.random_states(300, seed=11, rho=(1e-3, 10), eps=(1e-3, 10), vmax=0.9, bmax=2)
+    rng = W.uniform(3, np.arange(900)).reshape(3, 300)
+    for c in range(pr.shape[1]):
+        beta = 0.2 * rng[:, c]
+        met = np.concatenate([[psi[c], al[c]], beta])
+        q, fl, _, _ = tensor_construction(5 / 3, pr[:, c], psi[c], al[c], beta, ref[:, c])
+        qo = oracle.point_prim2con(5 / 3, pr[:, c], met, ref[:, c])
+        scale = np.abs(q).max()
+        np.testing.assert_allclose(qo, q, rtol=0, atol=2e-13 * scale)
+        for a in range(3):
+            fo, _ = oracle.point_flux(5 / 3, pr[:, c], met, ref[:, c], a)
+            sc = max(np.abs(fl[a]).max(), scale)
+            np.testing.assert_allclose(fo, fl[a], rtol=0, atol=2e-13 * sc)
+
+
+def test_prim2con_closed_forms():
+    """Static unmagnetised state: D = rho, S = 0, tau = rho eps.  Flow
+    parallel to the field in flat space: S = rho h W^2 v,
+    tau = rho h W^2 - p - D + B^2/2, tau-flux = (rho h W^2 - D) v."""
+    g = 5 / 3
+    rho, p = 2.0, 0.7
+    eps = p / ((g - 1) * rho)
+    q = oracle.point_prim2con(g, [rho, 0, 0, 0, p, 0, 0, 0], [1, 1, 0, 0, 0], [1, 1, 1])
+    np.testing.assert_allclose(q, [rho, 0, 0, 0, rho * eps, 0, 0, 0], rtol=1e-15)
+    v, B = 0.6, 1.3
+    Wl = 1 / math.sqrt(1 - v * v)
+    h = 1 + g / (g - 1) * p / rho
+    prim = [rho, Wl * v, 0, 0, p, B, 0, 0]
+    q = oracle.point_prim2con(g, prim, [1, 1, 0, 0, 0], [1, 1, 1])
+    D = rho * Wl
+    np.testing.assert_allclose(q[:5], [D, rho * h * Wl * Wl * v, 0, 0, rho * h * Wl * Wl - p - D + B * B / 2],
+                               rtol=1e-14)
+    f, _ = oracle.point_flux(g, prim, [1, 1, 0, 0, 0], [1, 1, 1], 0)
+    np.testing.assert_allclose(f[4], (rho * h * Wl * Wl - D) * v, rtol=1e-14)
+    assert f[5] == 0.0
+
+
+def test_wave_speeds_closed_forms():
+    """B = 0 along x: lambda = (v -+ c_s)/(1 -+ v c_s) (relativistic velocity
+    addition).  v = 0 with B along x: lambda = -+ a, a^2 = cs^2 + ca^2 - cs^2 ca^2.
+    All speeds are causal."""
+    g = 4 / 3
+    rho, p = 1.5, 0.8
+    h = 1 + g / (g - 1) * p / rho
+    cs = math.sqrt(g * p / (rho * h))
+    for v in (-0.7, 0.0, 0.3, 0.95):
+        Wl = 1 / math.sqrt(1 - v * v)
+        _, lam = oracle.point_flux(g, [rho, Wl * v, 0, 0, p, 0, 0, 0], [1, 1, 0, 0, 0], [1, 1, 1], 0)
+        np.testing.assert_allclose(lam, [(v - cs) / (1 - v * cs), (v + cs) / (1 + v * cs)], rtol=1e-14, atol=1e-15)
+    B = 0.9
+    ca2 = B * B / (rho * h + B * B)
+    a = math.sqrt(cs * cs + ca2 - cs * cs * ca2)
+    _, lam = oracle.point_flux(g, [rho, 0, 0, 0, p, B, 0, 0], [1, 1, 0, 0, 0], [1, 1, 1], 0)
+    np.testing.assert_allclose(lam, [-a, a], rtol=1e-14)
+    pr, psi, al, ref = W.random_states(200, seed=5)
+    for c in range(200):
+        for ax in range(3):
+            _, lam = oracle.point_flux(5 / 3, pr[:, c], [psi[c], 1.0, 0, 0, 0], ref[:, c], ax)
+            # coordinate speed times sqrt(gamma_aa) is a physical speed: |.| <= 1
+            s = math.sqrt(psi[c] ** 4 * ref[ax, c])
+            assert np.all(np.abs(lam) * s <= 1.0 + 1e-12)
+
+
+def test_hlle_consistency_and_upwinding():
+    """F(U, U) = f(U); fully supersonic flow takes the upwind flux."""
+    pr, psi, al, ref = W.random_states(100, seed=7)
+    for c in range(100):
+        met = [psi[c], al[c], 0, 0, 0]
+        for ax in range(3):
+            f, _ = oracle.point_flux(5 / 3, pr[:, c], met, ref[:, c], ax)
+            fh = oracle.point_hlle(5 / 3, pr[:, c], pr[:, c], met, ref[:, c], ax)
+            np.testing.assert_allclose(fh, f, rtol=0, atol=1e-13 * (np.abs(f).max() + 1e-300))
+    Wl = 1 / math.sqrt(1 - 0.99 ** 2)
+    a = [1.0, Wl * 0.99, 0, 0, 0.01, 0, 0, 0]
+    b = [0.5, Wl * 0.98, 0, 0, 0.02, 0, 0, 0]
+    fl, lam = oracle.point_flux(5 / 3, a, [1, 1, 0, 0, 0], [1, 1, 1], 0)
+    assert lam[0] > 0
+    fb, lamb = oracle.point_flux(5 / 3, b, [1, 1, 0, 0, 0], [1, 1, 1], 0)
+    assert lamb[0] > 0
+    np.testing.assert_array_equal(oracle.point_hlle(5 / 3, a, b, [1, 1, 0, 0, 0], [1, 1, 1], 0), fl)
+
+
+def test_mc_reconstruction_properties():
+    """Exact on linear data, zero slope at extrema, face values within the
+    neighbouring cell values (TVD), and second-order accurate on smooth data."""
+    lo, hi = oracle.mc_faces(3.0 + 0.5 * np.arange(10))
+    np.testing.assert_allclose(lo, 3.0 + 0.5 * (np.arange(1, 8) + 0.5), rtol=1e-15)
+    np.testing.assert_allclose(hi, lo, rtol=1e-15)
+    u = np.array([0.0, 1.0, 3.0, 2.0, 2.0, 5.0, -1.0, 0.5, 0.4, 0.45])
+    lo, hi = oracle.mc_faces(u)
+    for f in range(1, len(u) - 2):
+        a, b = u[f], u[f + 1]
+        assert min(u[f - 1], a, b) - 1e-15 <= lo[f - 1] <= max(u[f - 1], a, b) + 1e-15
+        assert min(a, b, u[f + 2]) - 1e-15 <= hi[f - 1] <= max(a, b, u[f + 2]) + 1e-15
+    assert lo[1] == u[2] and hi[0] == u[2]  # cell 2 is a local maximum
+    errs = []
+    for n in (32, 64, 128):
+        x = (np.arange(n) + 0.5) / n
+        u = np.exp(np.sin(2 * math.pi * 0.3 * x))
+        lo, _ = oracle.mc_faces(u)
+        xf = (np.arange(1, n - 2) + 1.0) / n
+        errs.append(np.max(np.abs(lo - np.exp(np.sin(2 * math.pi * 0.3 * xf)))[5:-5]))
+    assert errs[1] / errs[2] > 3.0
+
+
+# ---------------------------------------------------------------------- c2p
+
+def _c2p_desc(**kw):
+    p = dict(ndim=1, coord=0, n=[1, 1, 1], xmin=[0, 0, 0], dx=[1, 1, 1], bc=[[1, 1]] * 3, gamma=5 / 3,
+             rho_atmo=1e-20)
+    p.update(kw)
+    return p
+
+
+def test_c2p_round_trip():
+    """prim -> con -> prim recovers rho and W v^i to 1e-12 and eps to 1e-12 of
+    max(eps, tau/D) on states with b^2/rho <= 100 and tau/D <= 1e3 eps."""
+    pr, psi, al, ref = W.random_states(1500, seed=1)
+    p = _c2p_desc()
+    checked = 0
+    for c in range(pr.shape[1]):
+        met = np.array([psi[c], al[c], 0, 0, 0])
+        q = oracle.point_prim2con(5 / 3, pr[:, c], met, ref[:, c])
+        gd = psi[c] ** 4 * ref[:, c]
+        if (gd * pr[5:8, c] ** 2).sum() / pr[0, c] > 100:
+            continue
+        eps = pr[4, c] / (2 / 3 * pr[0, c])
+        tD = q[4] / q[0]
+        if tD > 1e3 * eps:
+            continue
+        r, fl, it = oracle.c2p_point(p, q, psi[c], al[c], ref[:, c])
+        assert fl == 0
+        checked += 1
+        assert abs(r[0] - pr[0, c]) <= 1e-12 * pr[0, c]
+        u = np.sqrt((gd * pr[1:4, c] ** 2).sum())
+        assert np.all(np.abs(r[1:4] - pr[1:4, c]) * np.sqrt(gd) <= 1e-12 * max(u, 1e-3))
+        e_r = r[4] / (2 / 3 * r[0])
+        assert abs(e_r - eps) <= 1e-12 * max(eps, tD)
+        np.testing.assert_allclose(r[5:8], pr[5:8, c], rtol=4e-16, atol=1e-300)
+    assert checked > 500
+
+
+def test_c2p_extreme_magnetisation_converges():
+    """The recovery converges for rescaled fields |B|/sqrt(D) ~ 1e4 (the
+    paper quotes about 40 iterations there)."""
+    p = _c2p_desc()
+    for Bmag in (1e2, 1e3, 1e4):
+        prim = np.array([1e-8, 0.5, -0.3, 0.2, 1e-9, Bmag * 1e-4, 0.3 * Bmag * 1e-4, -0.2 * Bmag * 1e-4])
+        q = oracle.point_prim2con(5 / 3, prim, [1, 1, 0, 0, 0], [1, 1, 1])
+        r, fl, it = oracle.c2p_point(p, q, 1.0, 1.0, [1, 1, 1])
+        assert fl & oracle.FLAG_NOCONV == 0
+        assert it <= 60
+        assert abs(r[0] - prim[0]) < 1e-6 * prim[0]
+
+
+def test_c2p_error_handling():
+    """Section 2.5.3: rho < rho_min -> atmosphere; eps < 0 -> clamped to 0;
+    W above W_max -> rescaled in low density, fatal otherwise."""
+    p = _c2p_desc(rho_atmo=1e-10, k_atmo=100.0, gamma_atmo=2.0, w_max=10.0)
+    q = oracle.point_prim2con(5 / 3, [1e-12, 0.1, 0, 0, 1e-14, 0, 0, 0], [1, 1, 0, 0, 0], [1, 1, 1])
+    r, fl, _ = oracle.c2p_point(p, q, 1.0, 1.0, [1, 1, 1])
+    assert fl & oracle.FLAG_ATMO
+    np.testing.assert_allclose(r[:5], [1e-10, 0, 0, 0, 100.0 * 1e-20], rtol=1e-14)
+    # tau slightly below the zero-temperature value: eps < 0 -> clamp
+    q = oracle.point_prim2con(5 / 3, [1.0, 0.3, 0, 0, 1e-10, 0, 0, 0], [1, 1, 0, 0, 0], [1, 1, 1])
+    q[4] -= 1e-6
+    r, fl, _ = oracle.c2p_point(p, q, 1.0, 1.0, [1, 1, 1])
+    assert fl & oracle.FLAG_EPS_CLAMP and r[4] == 0.0
+    # W = 50 > W_max = 10 at high density: fatal; at low density: clamp
+    Wl = 50.0
+    u = math.sqrt(Wl * Wl - 1)
+    q = oracle.point_prim2con(5 / 3, [1.0, u, 0, 0, 0.1, 0, 0, 0], [1, 1, 0, 0, 0], [1, 1, 1])
+    r, fl, _ = oracle.c2p_point(p, q, 1.0, 1.0, [1, 1, 1])
+    assert fl & oracle.FLAG_FATAL_V
+    q = oracle.point_prim2con(5 / 3, [5e-9, u, 0, 0, 1e-12, 0, 0, 0], [1, 1, 0, 0, 0], [1, 1, 1])
+    r, fl, _ = oracle.c2p_point(p, q, 1.0, 1.0, [1, 1, 1])
+    assert fl & oracle.FLAG_V_CLAMP
+    np.testing.assert_allclose(math.sqrt(1 + r[1] ** 2), 10.0, rtol=1e-12)
+    np.testing.assert_allclose(r[0] * 10.0, q[0], rtol=1e-12)
+
+
+# --------------------------------------------------- full-scheme invariants
+
+@pytest.mark.parametrize("coord,ndim", [(W.CYL, 1), (W.CYL, 2), (W.CYL, 3), (W.SPH, 1), (W.SPH, 2), (W.SPH, 3)])
+def test_uniform_static_state_is_preserved(coord, ndim):
+    """The reference-metric form keeps a uniform static fluid static: flux
+    divergence and geometric sources cancel to round-off (section 2.1)."""
+    p, pr, met = W.uniform_state(coord, ndim=ndim, n=(8, 8, 4), pres=0.7)
+    oracle.fill_ghosts(p, pr)
+    L = oracle.interior(p, oracle.rhs(p, pr, met))
+    g = oracle.cell_geometry(p, 0, 0, 0)
+    scale = 0.7 * (abs(g[2]) + abs(g[1])) / g[0]
+    assert np.abs(L).max() <= 8e-16 * max(scale, 1.0)
+
+
+def test_ghost_fill_continues_coordinate_components():
+    """CENTER and AXIS ghosts of contravariant vector components equal the
+    components of a smooth Cartesian field (uniform z-field, rigid rotation
+    about z, radial flow) evaluated at the formal ghost coordinates."""
+    p = W.grid(2, W.SPH, [8, 8], [0.0, 0.0, 0.0], [2.0, math.pi, 2 * math.pi], [[W.CENTER, W.OUTFLOW], [W.AXIS, W.AXIS]])
+    r, th, ph = W.centres(p)
+    Vz, Om, f = 0.3, 0.7, 0.2
+    # contravariant coordinate components of V = Vz z + Om z x X + f X
+    vr = Vz * np.cos(th) + f * r
+    vth = -Vz * np.sin(th) / r
+    vph = Om + 0 * r
+    pr = W.empty_prim(p)
+    pr[0] = 1.0
+    pr[4] = 1.0
+    pr[1], pr[2], pr[3] = vr, vth, vph
+    pr[5], pr[6], pr[7] = 2 * vr, 2 * vth, 2 * vph
+    want = pr.copy()
+    oracle.fill_ghosts(p, pr)
+    g = 2
+    for sl in [np.s_[:, :, g:-g, :g], np.s_[:, :, :g, g:-g], np.s_[:, :, -g:, g:-g]]:
+        np.testing.assert_allclose(pr[sl], want[sl], rtol=1e-13, atol=1e-13)
+
+
+def test_cfl_time_step_closed_form():
+    """dt = c_CFL dx / max|lambda| for a uniform 1D state (maxsum rule)."""
+    g = 5 / 3
+    p = W.grid(1, W.CART, [10], [0, 0, 0], [1, 1, 1], [[1, 1]], gamma=g)
+    pr = W.empty_prim(p)
+    v, rho, pp = 0.4, 1.0, 2.0
+    pr[0] = rho
+    pr[4] = pp
+    pr[1] = v / math.sqrt(1 - v * v)
+    met = W.flat_metric(p)
+    h = 1 + g / (g - 1) * pp / rho
+    cs = math.sqrt(g * pp / (rho * h))
+    lam = (v + cs) / (1 + v * cs)
+    dt = oracle.cfl_dt(p, pr, met, 0.4)
+    np.testing.assert_allclose(dt, 0.4 * 0.1 / lam, rtol=1e-14)
+    assert oracle.cfl_dt(p, pr, met, 0.4, 0.99, 1.0) == pytest.approx(0.01, rel=1e-12)
+
+
+def test_periodic_conservation_3d():
+    """With periodic boundaries the volume integrals of q_D, q_S and q_tau
+    stay constant to round-off over several SSPRK3 steps."""
+    p, pr, met = W.periodic_wave_3d(8)
+    oracle.fill_ghosts(p, pr)
+    q = oracle.prim2con(p, pr, met)
+    tot0 = oracle.interior(p, q).sum(axis=(1, 2, 3))
+    oracle.evolve(p, q, pr, met, 0.4, 0.0, 1.0, nsteps=5)
+    tot1 = oracle.interior(p, q).sum(axis=(1, 2, 3))
+    for v in range(8):
+        assert abs(tot1[v] - tot0[v]) <= 1e-13 * np.abs(oracle.interior(p, q)[v]).sum() + 1e-300
+
+
+def test_angular_momentum_conserved_to_round_off():
+    """Axisymmetric spherical rotating flow: total q_S_phi is conserved to
+    machine precision because its geometric source vanishes (section 2.1,
+    Appendix A); reflecting outer wall, axis and centre boundaries carry no
+    flux of it."""
+    p = W.grid(2, W.SPH, [16, 12], [0.0, 0.0, 0.0], [1.0, math.pi, 2 * math.pi],
+               [[W.CENTER, W.REFLECT], [W.AXIS, W.AXIS]], gamma=5 / 3, rk=3)
+    r, th, _ = W.centres(p)
+    pr = W.empty_prim(p)
+    pr[0] = 1.0 + 0.5 * np.exp(-4 * r * r)
+    pr[4] = 1.0 + 0.3 * np.cos(th) * r
+    pr[3] = 0.4 * np.exp(-r * r)          # W v^phi (an angular rate)
+    pr[1] = 0.1 * r * np.sin(th)
+    pr[7] = 0.05
+    met = W.flat_metric(p)
+    oracle.fill_ghosts(p, pr)
+    q = oracle.prim2con(p, pr, met)
+    dV = oracle.interior(p, oracle.cell_volumes(p))
+    Lz0 = (oracle.interior(p, q)[3] * dV).sum()
+    M0 = (oracle.interior(p, q)[0] * dV).sum()
+    oracle.evolve(p, q, pr, met, 0.3, 0.0, 1.0, nsteps=6)
+    Lz1 = (oracle.interior(p, q)[3] * dV).sum()
+    M1 = (oracle.interior(p, q)[0] * dV).sum()
+    scale = (np.abs(oracle.interior(p, q)[3]) * dV).sum()
+    assert abs(Lz1 - Lz0) <= 1e-14 * scale
+    assert abs(M1 - M0) <= 1e-14 * M0
+
+
+# ---------------------------------------------------------- exact solutions
+
+def test_exact_riemann_solver_itself():
+    """Jump conditions hold across the computed shocks; the tube of section
+    3.1.2 has the known star state."""
+    rs = RiemannSRHD((10, 40 / 3, 0), (1, 0, 0), 5 / 3)
+    assert max(jump_residuals((1, 0, 0), rs.ps, 5 / 3, +1)) < 1e-13
+    assert max(jump_residuals((1, 1, 0.2), 5.0, 5 / 3, -1)) < 1e-13
+    assert rs.right_shock and not rs.left_shock
+    np.testing.assert_allclose([rs.ps, rs.vs, rs.VR], [1.44794, 0.714021, 0.828398], rtol=2e-5)
+
+
+def _run_tube(n, bx=0.0):
+    p, pr, met = W.srhd_shock_tube(n, bx=bx)
+    oracle.fill_ghosts(p, pr)
+    q = oracle.prim2con(p, pr, met)
+    s, t, nf = oracle.evolve(p, q, pr, met, 0.4, 0.0, 0.4)
+    assert nf == 0 and abs(t - 0.4) < 1e-14
+    return p, oracle.interior(p, pr)[:, 0, 0]
+
+
+@pytest.mark.parametrize("bx", [0.0, 0.7])
+def test_shock_tube_converges_to_exact_solution(bx):
+    """Relativistic shock tube (section 3.1.2) converges to the exact
+    solution at first order in L1; a field parallel to the flow changes
+    nothing."""
+    rs = RiemannSRHD((10, 40 / 3, 0), (1, 0, 0), 5 / 3)
+    errs = []
+    for n in (100, 400):
+        p, prim = _run_tube(n, bx)
+        dx = p["dx"][0]
+        ex = np.array([rs.cell_average(i * dx, (i + 1) * dx, 0.4, 0.5)[0] for i in range(n)])
+        errs.append(np.sum(np.abs(prim[0] - ex)) * dx)
+        if bx:
+            np.testing.assert_array_equal(prim[5], bx)
+            assert np.abs(prim[6:8]).max() == 0.0
+    assert errs[1] < 0.035
+    assert errs[0] / errs[1] > 2.8
+
+
+def test_alfven_wave_convergence_matches_paper_rates():
+    """Circularly polarised Alfven wave (section 3.2.1): v_A = 1/2 exactly, so
+    at t = 2 the exact state is the initial one.  HLL + MC + SSPRK2 rates of
+    ||B^z(2) - B^z(0)||_1 against the printed R_N of Table 2 (2.32, 2.11,
+    2.04 at N = 64, 128, 256)."""
+    assert W.alfven_speed2() == pytest.approx(0.25, abs=1e-15)
+    errs = []
+    for n in (32, 64, 128, 256):
+        p, pr, met = W.alfven_wave(n, rk=2)
+        oracle.fill_ghosts(p, pr)
+        q = oracle.prim2con(p, pr, met)
+        bz0 = oracle.interior(p, pr)[7].copy()
+        s, t, nf = oracle.evolve(p, q, pr, met, 0.4, 0.0, 2.0)
+        assert nf == 0 and abs(t - 2.0) < 1e-13
+        errs.append(np.mean(np.abs(oracle.interior(p, pr)[7] - bz0)))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    np.testing.assert_allclose(rates, [2.32, 2.11, 2.04], atol=0.1)
+
+
+def test_smooth_wave_second_order():
+    """2D advected sine wave (section 3.1.1) with exact-solution boundary
+    data: second-order L1 convergence of rho."""
+    ds = []
+    for n in (16, 32):
+        p, pr, met = W.smooth_wave_2d(n, rk=2)
+        q = oracle.prim2con(p, pr, met)
+        t = 0.0
+        while t < 2.0:
+            _, pi, _, _ = oracle.c2p(p, q, met)
+            pr = W.smooth_wave_prim(p, t)
+            oracle.interior(p, pr)[:] = oracle.interior(p, pi)
+            dt = oracle.cfl_dt(p, pr, met, 0.4, t, 2.0)
+            qs = q.copy()
+            oracle.rk_stage(p, 0, dt, q, qs, pr, met)
+            pr2 = W.smooth_wave_prim(p, t + dt)
+            oracle.interior(p, pr2)[:] = oracle.interior(p, pr)
+            oracle.rk_stage(p, 1, dt, q, qs, pr2, met)
+            q = qs
+            t += dt
+        _, pi, _, _ = oracle.c2p(p, q, met)
+        ex = oracle.interior(p, W.smooth_wave_prim(p, 2.0))[0]
+        ds.append(np.abs(oracle.interior(p, pi)[0] - ex).sum() / np.abs(ex).sum())
+    assert math.log2(ds[0] / ds[1]) > 1.8
+    assert ds[1] < 1e-2
+
+
+def test_static_star_residual_converges_second_order():
+    """A TOV star on its own frozen metric is an equilibrium: the interior
+    RHS (pressure-gradient flux against the gravitational and geometric
+    sources) vanishes at second order under refinement (1D spherical)."""
+    star = W.tov_isotropic(1.28e-3)
+    res = []
+    for n in (32, 64, 128):
+        p = W.grid(1, W.SPH, [n], [0.0, 0.0, 0.0], [6.0, math.pi, 2 * math.pi], [[W.CENTER, W.OUTFLOW]],
+                   gamma=2.0, rk=3, rho_atmo=1e-10, k_atmo=100.0, gamma_atmo=2.0)
+        r, _, _ = W.centres(p)
+        rho, psi, alpha = W.tov_fields(star, r)
+        pr = W.empty_prim(p)
+        pr[0] = rho
+        pr[4] = 100.0 * rho ** 2
+        met = np.zeros((5,) + W.shape(p))
+        met[0], met[1] = psi, alpha
+        oracle.fill_ghosts(p, pr)
+        L = oracle.interior(p, oracle.rhs(p, pr, met))[1, 0, 0]
+        rr = oracle.interior(p, r)[0, 0]
+        m = (rr > 1.0) & (rr < 5.0)
+        res.append(np.abs(L[m]).max())
+    assert math.log2(res[0] / res[1]) > 1.7 and math.log2(res[1] / res[2]) > 1.7
+
+
+def test_tov_fixture_matches_printed_star_numbers():
+    """The star fixture reproduces the numbers the paper prints for its
+    migration test (section 3.3): the SU star (rho_c = 8e-3) has isotropic
+    radius 4.267, and its stable partner of equal baryon mass has
+    rho_c = 1.346e-3."""
+    su = W.tov_isotropic(8e-3)
+    assert su["R_iso"] == pytest.approx(4.267, abs=1e-3)
+    st = W.tov_isotropic(1.346e-3)
+    assert st["Mb"] == pytest.approx(su["Mb"], rel=3e-4)
