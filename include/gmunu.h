@@ -1,0 +1,173 @@
+/*
+ * gmunu.h -- C ABI of the MI355X GRMHD finite-volume step.
+ *
+ * The library advances the ideal GRMHD equations in reference-metric form on
+ * a given, frozen conformally flat (CFC) metric (psi, alpha, beta^i), as in
+ * Cheong et al., "Gmunu" (arXiv 2012.07322), section 2.1 (equations,
+ * conserved variables, fluxes, sources, discretised update), section 2.3
+ * (wave speeds), section 2.5 (conservative-to-primitive recovery and its
+ * error handling), section 2.9 (time step) and Appendix A (cell volumes,
+ * face areas and averaged Christoffel symbols).  Reconstruction is MC, the
+ * Riemann solver HLLE, the integrator SSPRK3 (or SSPRK2), as in section 3.
+ *
+ * Every array argument is a DEVICE pointer (HIP), FP64 unless stated, in
+ * structure-of-arrays layout [var][k][j][i] with i fastest, ghost cells
+ * included: nt[a] = n[a] + 2*g[a] cells along axis a, g[a] = ng on the active
+ * axes (the first ndim) and 0 on the inactive ones.  The cell (i,j,k) of the
+ * interior (0 <= i < n[0] ...) is at linear offset
+ *     ((k+g[2]) * nt[1] + (j+g[1])) * nt[0] + (i+g[0]),
+ * and variable v of an array is at v * ntot + offset, ntot = nt[0]nt[1]nt[2].
+ *   prim   (8 vars): rho, W v^1, W v^2, W v^3, p, B^1, B^2, B^3
+ *          (contravariant coordinate components; B not densitised)
+ *   q      (8 vars): psi^6 (D, S_1, S_2, S_3, tau, B^1, B^2, B^3), S covariant
+ *   metric (5 vars): psi, alpha, beta^1, beta^2, beta^3 at cell centres; the
+ *          caller fills its ghost cells (it is never written).
+ *   flags  (uint8, one per cell, nullable): c2p outcome bits GMUNU_FLAG_*.
+ * Pointers must be 8-byte aligned (flags: any alignment).  The caller owns
+ * all arrays and the stream; the context owns only geometry tables and small
+ * scratch.  No call allocates or synchronises after gmunu_create, so a
+ * sequence of calls can be captured into a HIP graph.
+ *
+ * Error convention: 0 on success; a negative GMUNU_E* code for invalid
+ * arguments or HIP errors.  Physical failures of the recovery are never
+ * return codes: they are per-cell flag bits and a device counter (nfatal)
+ * the caller reads after synchronising.  The library never aborts (the
+ * paper stops the code on a fatal recovery error, section 2.5.3).
+ */
+#ifndef GMUNU_H
+#define GMUNU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { GMUNU_CART = 0, GMUNU_CYL = 1 /* (R, z, phi) */, GMUNU_SPH = 2 /* (r, theta, phi) */ };
+
+/* Boundary kinds for the ghost fill of the primitives (the paper names the
+ * ghost layers but not these rules; see gmunu_fill_ghosts). */
+enum {
+  GMUNU_BC_PERIODIC = 0,
+  GMUNU_BC_OUTFLOW = 1, /* copy of the nearest interior cell */
+  GMUNU_BC_REFLECT = 2, /* mirror; normal vector components odd */
+  GMUNU_BC_AXIS = 3,    /* R = 0 or theta = 0, pi: mirror, normal component odd */
+  GMUNU_BC_CENTER = 4,  /* r = 0: mirror to (r, pi - theta, phi + pi); r, theta comps odd */
+  GMUNU_BC_NONE = 5     /* ghosts left as the caller set them */
+};
+
+enum {
+  GMUNU_FLAG_ATMO = 1,      /* rho < rho_min: reset to atmosphere, q rewritten */
+  GMUNU_FLAG_EPS_CLAMP = 2, /* eps limited to [0, eps_max], q rewritten */
+  GMUNU_FLAG_V_CLAMP = 4,   /* velocity rescaled to W_max (low density), q rewritten */
+  GMUNU_FLAG_FATAL_RHO = 8, /* rho > rho_max */
+  GMUNU_FLAG_FATAL_EPS = 16,/* eps > eps_max at high density */
+  GMUNU_FLAG_FATAL_V = 32,  /* W > W_max at high density */
+  GMUNU_FLAG_NOCONV = 64    /* root finder did not converge */
+};
+
+enum {
+  GMUNU_OK = 0,
+  GMUNU_EINVAL = -1,  /* invalid descriptor or argument */
+  GMUNU_ENULL = -2,   /* required pointer is NULL */
+  GMUNU_EALIGN = -3,  /* pointer not 8-byte aligned */
+  GMUNU_EHIP = -4,    /* a HIP runtime call failed */
+  GMUNU_ENOMEM = -5   /* device allocation at create time failed */
+};
+
+/* Grid and physics description (host struct, copied at create). */
+typedef struct gmunu_grid_desc {
+  int ndim;            /* 1, 2 or 3 active axes (the first ndim) */
+  int coord;           /* GMUNU_CART / CYL / SPH */
+  int n[3];            /* interior cells per axis (1 on inactive axes) */
+  int ng;              /* ghost layers on active axes; MC needs >= 2 */
+  double xmin[3];      /* lower edge of the interior, per axis */
+  double dx[3];        /* uniform coordinate spacing (inactive phi: 2 pi) */
+  int bc[3][2];        /* GMUNU_BC_* per axis and side (lower, upper) */
+  double gamma;        /* ideal gas p = (Gamma - 1) rho eps */
+  double rho_atmo;     /* atmosphere density; also the EOS floor rho_min */
+  double k_atmo, gamma_atmo; /* atmosphere polytrope p = K rho^Gamma_atmo */
+  double rho_low_factor;     /* low-density region rho < factor * rho_atmo (100) */
+  double alpha_bh;           /* black-hole interior alpha < alpha_bh (1e-2) */
+  double rho_max, eps_max;   /* EOS validity limits (may be +inf) */
+  double w_max;              /* Lorentz factor limit */
+  int c2p_maxit;             /* root-finder iteration limit */
+  double c2p_tol;            /* relative tolerance of the recovered root */
+  int rk;                    /* 3: SSPRK3, 2: SSPRK2 */
+} gmunu_grid_desc;
+
+typedef struct gmunu_ctx gmunu_ctx;
+
+/* Validate the descriptor, build the geometry tables (Appendix A) on the
+ * current HIP device and allocate the context's scratch.  Host call;
+ * synchronous.  *out is set only on success. */
+int gmunu_create(const gmunu_grid_desc *desc, gmunu_ctx **out);
+int gmunu_destroy(gmunu_ctx *ctx);
+
+/* Cells in one array (ntot) and the byte size of the 8-variable state. */
+long gmunu_ntot(const gmunu_ctx *ctx);
+
+/* q = prim2con(prim) on every cell including ghosts (section 2.1, the
+ * definitions of the conserved variables).  Enqueued on `stream`
+ * (a hipStream_t; NULL = default stream). */
+int gmunu_prim2con(gmunu_ctx *ctx, const double *prim, const double *metric, double *q, void *stream);
+
+/* Primitive recovery on the interior cells (section 2.5.2, then the error
+ * handling of section 2.5.3).  Cells flagged ATMO, EPS_CLAMP or V_CLAMP get q
+ * rewritten from the corrected primitives.  flags (nullable) receives the
+ * bits per cell; nfatal_dev (nullable, one unsigned int) is incremented by
+ * the number of cells with a fatal bit.  Ghost cells of prim are untouched. */
+int gmunu_c2p(gmunu_ctx *ctx, double *q, const double *metric, double *prim, uint8_t *flags,
+              unsigned int *nfatal_dev, void *stream);
+
+/* Fill the ghost cells of prim that share a face-normal line with the
+ * interior (edge and corner ghosts are never read by the scheme and are left
+ * untouched), per the descriptor's boundary kinds. */
+int gmunu_fill_ghosts(gmunu_ctx *ctx, double *prim, void *stream);
+
+/* dq/dt on the interior cells: minus the flux-area divergence over the cell
+ * volume plus gravitational and geometric sources (section 2.1, the
+ * discretised equation), from primitives whose ghosts are filled.  Ghost
+ * entries of dqdt are untouched. */
+int gmunu_rhs(gmunu_ctx *ctx, const double *prim, const double *metric, double *dqdt, void *stream);
+
+/* Time step by the maxsum rule (section 2.9): dt = cfl / max over interior
+ * cells of sum_axes max|lambda_a|/dx_a, capped at t_end - *t_dev, written to
+ * dt_dev (one double).  t_dev may be NULL (then t = 0). */
+int gmunu_cfl_dt(gmunu_ctx *ctx, const double *prim, const double *metric, double cfl, double t_end,
+                 const double *t_dev, double *dt_dev, void *stream);
+
+/* One Runge-Kutta stage (Shu-Osher form):
+ *   q_out = a q_n + b (q_s + dt L(prim_in)),  (a,b) = (0,1) for stage 0,
+ *   SSPRK3 stage 1 (3/4, 1/4), stage 2 (1/3, 2/3); SSPRK2 stage 1 (1/2, 1/2);
+ * then q_out -> prim_out by gmunu_c2p and the ghost fill.  q_s is not read in
+ * stage 0.  q_out may alias q_n or q_s (each cell reads only its own q).
+ * prim_out may alias prim_in.  dt is read from dt_dev. */
+int gmunu_rk_stage(gmunu_ctx *ctx, int stage, const double *dt_dev, const double *q_n, const double *q_s,
+                   double *q_out, const double *prim_in, double *prim_out, const double *metric,
+                   uint8_t *flags, unsigned int *nfatal_dev, void *stream);
+
+/* One full time step: dt = gmunu_cfl_dt(prim), the RK stages (q_n is
+ * overwritten with q^{n+1}, q_s is scratch of the same size), prim ends
+ * consistent with q^{n+1} with ghosts filled, and *t_dev += dt.  Device-side
+ * time keeps the call graph-capturable. */
+int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, double cfl,
+               double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
+               void *stream);
+
+/* Kernel timing, for measurement only (not for use under graph capture).
+ * With enable != 0, every launch made through this context afterwards is
+ * bracketed by HIP events on its stream (up to max_launches pairs; creating
+ * them allocates, so enable outside any timed or captured region).
+ * gmunu_profile_read synchronises those events and returns, per kernel kind
+ * GMUNU_K_*, the summed milliseconds and the launch counts, then clears them. */
+enum { GMUNU_K_STAGE = 0, GMUNU_K_C2P = 1, GMUNU_K_GHOSTS = 2, GMUNU_K_CFL = 3, GMUNU_K_OTHER = 4, GMUNU_NK = 5 };
+int gmunu_profile(gmunu_ctx *ctx, int enable, int max_launches);
+int gmunu_profile_read(gmunu_ctx *ctx, double *ms_out /* [GMUNU_NK] */, long *count_out /* [GMUNU_NK] */);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMUNU_H */

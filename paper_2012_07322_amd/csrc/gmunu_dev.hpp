@@ -1,0 +1,421 @@
+// Device-side physics of the GRMHD finite-volume step on gfx950.
+//
+// Cheong et al., "Gmunu" (arXiv 2012.07322): conserved variables, fluxes and
+// sources of section 2.1, wave-speed bounds of section 2.3, primitive
+// recovery of section 2.5, geometry of Appendix A.  All FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gm {
+
+constexpr int NV = 8;
+constexpr int NT = 256;  // threads per workgroup of the cell kernels
+
+enum { CART = 0, CYL = 1, SPH = 2 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_AXIS = 3, BC_CENTER = 4, BC_NONE = 5 };
+enum {
+  FL_ATMO = 1, FL_EPS = 2, FL_V = 4, FL_FRHO = 8, FL_FEPS = 16, FL_FV = 32, FL_NOCONV = 64,
+  FL_FATAL = FL_FRHO | FL_FEPS | FL_FV | FL_NOCONV,
+  FL_REWRITE = FL_ATMO | FL_EPS | FL_V
+};
+
+// Per-axis 1D geometry.  Every cell volume and face area of Appendix A is a
+// product of one factor per axis: dV = cv0 cv1 cv2 and the area of an
+// axis-a face is fa_a * prod_{b != a} cv_b, so (F dA)_+ - (F dA)_-) / dV
+// reduces to (F fa)_+ - (F fa)_-) / cv_a.  Indices include ghosts: cell I in
+// [0, nt), face F in [0, nt] between cells F-1 and F.
+struct Geo {
+  const double *icv[3];  // 1 / cv per cell
+  const double *fa[3];   // face factor per face
+  const double *r2c;     // axis-0 coordinate squared at centres
+  const double *r2f;     // ... at faces
+  const double *s2c;     // sin^2 of axis-1 coordinate at centres (spherical)
+  const double *s2f;     // ... at faces
+  const double *xc0;     // axis-0 centre coordinate
+  const double *sc1, *cc1;  // sin, cos of axis-1 centre coordinate
+  const double *gA;      // per axis-0 cell: sph <G^th_r th> = <G^ph_r ph>, cyl <G^ph_R ph>
+  const double *gB;      // per axis-0 cell: sph <G^r_th th>
+  const double *gC;      // per axis-1 cell: sph <G^ph_th ph>
+};
+
+struct Grid {
+  int ndim, coord;
+  int n[3], g[3], nt[3];
+  long s[3];   // element strides of the three axes
+  long nv;     // stride between variables (cells per array)
+  double dx[3];
+  double i2dx[3];   // 1 / (2 dx) for centred metric derivatives
+  double idx[3];    // 1 / dx for the CFL rate
+  double gam, gfac;  // Gamma and Gamma / (Gamma - 1)
+  double gm1;        // Gamma - 1
+  double rho_atmo, p_atmo, rho_low, alpha_bh, rho_max, eps_max, w_max;
+  int maxit;
+  double tol;
+  int bc[3][2];
+  Geo geo;
+};
+
+__device__ __forceinline__ long cell_offset(const Grid &G, int i, int j, int k) {
+  return (long)(k + G.g[2]) * G.s[2] + (long)(j + G.g[1]) * G.s[1] + (i + G.g[0]);
+}
+
+// Diagonal of the reference metric from the squared axis-0 coordinate and
+// sin^2 of the axis-1 coordinate at the evaluation point.
+__device__ __forceinline__ void ref_diag(int coord, double r2, double s2, double &g1, double &g2) {
+  if (coord == SPH) {
+    g1 = r2;
+    g2 = r2 * s2;
+  } else if (coord == CYL) {
+    g1 = 1.0;
+    g2 = r2;
+  } else {
+    g1 = 1.0;
+    g2 = 1.0;
+  }
+}
+
+// Monotonised-central limited slope: minmod(2 dl, (dl + dr) / 2, 2 dr).
+__device__ __forceinline__ double mc_slope(double a, double b, double c) {
+  double dl = b - a, dr = c - b;
+  double cen = 0.5 * (dl + dr);
+  double m = fmin(fmin(fabs(2.0 * dl), fabs(cen)), fabs(2.0 * dr));
+  return (dl * dr > 0.0) ? copysign(m, cen) : 0.0;
+}
+
+// Conserved vector U, flux F along direction D and the two wave-speed bounds
+// of one primitive state at one point (section 2.1 and 2.3).  g1, g2: the
+// reference metric diagonal (the first entry is 1 in every coordinate
+// system used here).
+template <int D>
+__device__ __forceinline__ void state_flux(const double gam, const double gfac, const double *pr, double psi,
+                                           double alpha, const double *beta, double g1, double g2, double *U,
+                                           double *F, double &lm, double &lp) {
+  const double psi2 = psi * psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
+  const double gd[3] = {psi4, psi4 * g1, psi4 * g2};
+  const double u2 = gd[0] * pr[1] * pr[1] + gd[1] * pr[2] * pr[2] + gd[2] * pr[3] * pr[3];
+  const double W2 = 1.0 + u2;
+  const double W = sqrt(W2);
+  const double iW = 1.0 / W;
+  double v[3], vd[3], Bd[3];
+  double Bv = 0.0, BB = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    v[a] = pr[1 + a] * iW;
+    vd[a] = gd[a] * v[a];
+    Bd[a] = gd[a] * pr[5 + a];
+    Bv += pr[5 + a] * vd[a];
+    BB += pr[5 + a] * Bd[a];
+  }
+  const double ab0 = W * Bv;  // alpha b^0
+  double bd[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) bd[a] = Bd[a] * iW + ab0 * vd[a];
+  const double b2 = BB * iW * iW + Bv * Bv;
+  const double rho = pr[0], p = pr[4];
+  const double rhoh = rho + gfac * p;
+  const double rhohs = rhoh + b2;
+  const double ps = p + 0.5 * b2;
+  const double E = rhohs * W2;
+  const double Dn = rho * W;
+  U[0] = psi6 * Dn;
+#pragma unroll
+  for (int a = 0; a < 3; a++) U[1 + a] = psi6 * (E * vd[a] - ab0 * bd[a]);
+  U[4] = psi6 * (E - ps - ab0 * ab0 - Dn);
+#pragma unroll
+  for (int a = 0; a < 3; a++) U[5 + a] = psi6 * pr[5 + a];
+
+  const double vhd = alpha * v[D] - beta[D];
+  const double Bdir = pr[5 + D];
+  const double aBW = alpha * Bdir * iW;
+  F[0] = U[0] * vhd;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    double f = U[1 + a] * vhd - psi6 * aBW * bd[a];
+    if (a == D) f += psi6 * alpha * ps;
+    F[1 + a] = f;
+  }
+  F[4] = U[4] * vhd + psi6 * (alpha * ps * v[D] - ab0 * aBW);
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    const double vha = alpha * v[a] - beta[a];
+    F[5 + a] = (a == D) ? 0.0 : psi6 * (vhd * pr[5 + a] - vha * Bdir);
+  }
+
+  // wave-speed bounds: a^2 = cs^2 + ca^2 - cs^2 ca^2 (section 2.3)
+  const double c_s2 = gam * p / rhoh;
+  const double c_a2 = b2 / rhohs;
+  const double a2 = c_s2 + c_a2 - c_s2 * c_a2;
+  const double v2 = v[0] * vd[0] + v[1] * vd[1] + v[2] * vd[2];
+  const double gud = 1.0 / gd[D];
+  const double one_a2 = 1.0 - a2;
+  const double va = v[D];
+  double disc = a2 * (1.0 - v2) * ((1.0 - v2 * a2) * gud - one_a2 * va * va);
+  disc = disc > 0.0 ? disc : 0.0;
+  const double sq = sqrt(disc);
+  const double iden = 1.0 / (1.0 - v2 * a2);
+  lm = alpha * ((one_a2 * va - sq) * iden) - beta[D];
+  lp = alpha * ((one_a2 * va + sq) * iden) - beta[D];
+}
+
+// CFL rate of one cell: sum over the active axes of max|lambda_a| / dx_a
+// (section 2.9, maxsum), wave speeds as in section 2.3.
+__device__ __forceinline__ double cfl_rate(const double gam, const double gfac, const double *pr, double psi,
+                                           double alpha, const double *beta, double g1, double g2, int ndim,
+                                           const double *idx) {
+  const double psi2 = psi * psi, psi4 = psi2 * psi2;
+  const double gd[3] = {psi4, psi4 * g1, psi4 * g2};
+  const double W2 = 1.0 + gd[0] * pr[1] * pr[1] + gd[1] * pr[2] * pr[2] + gd[2] * pr[3] * pr[3];
+  const double W = sqrt(W2);
+  const double iW = 1.0 / W;
+  double v[3], Bv = 0.0, BB = 0.0, v2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    v[a] = pr[1 + a] * iW;
+    Bv += pr[5 + a] * gd[a] * v[a];
+    BB += pr[5 + a] * gd[a] * pr[5 + a];
+    v2 += v[a] * gd[a] * v[a];
+  }
+  const double b2 = BB * iW * iW + Bv * Bv;
+  const double rhoh = pr[0] + gfac * pr[4];
+  const double c_s2 = gam * pr[4] / rhoh;
+  const double c_a2 = b2 / (rhoh + b2);
+  const double a2 = c_s2 + c_a2 - c_s2 * c_a2;
+  const double one_a2 = 1.0 - a2;
+  const double iden = 1.0 / (1.0 - v2 * a2);
+  double rate = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    if (a < ndim) {
+      double disc = a2 * (1.0 - v2) * ((1.0 - v2 * a2) / gd[a] - one_a2 * v[a] * v[a]);
+      disc = disc > 0.0 ? disc : 0.0;
+      const double sq = sqrt(disc);
+      const double lm = alpha * ((one_a2 * v[a] - sq) * iden) - beta[a];
+      const double lp = alpha * ((one_a2 * v[a] + sq) * iden) - beta[a];
+      rate += fmax(fabs(lm), fabs(lp)) * idx[a];
+    }
+  }
+  return rate;
+}
+
+}  // namespace gm
+
+namespace gm {
+
+// Rescaled conserved quantities of one cell (section 2.5.2, step 1).
+struct C2PConst {
+  double D, q, r2, b2, rb, rpb2, v0sq;
+};
+
+// Evaluation of the master function at mu (section 2.5.2, step 3), with
+// rho and eps limited to the EOS range inside the evaluation.  Optionally
+// returns W and the unlimited rho, eps.
+__device__ __forceinline__ double c2p_master(const Grid &G, const C2PConst &c, double mu, double *Wout,
+                                             double *rho_raw, double *eps_raw, double *chi_out) {
+  const double chi = 1.0 / (1.0 + mu * c.b2);
+  const double rbar2 = c.r2 * chi * chi + mu * chi * (1.0 + chi) * c.rb * c.rb;
+  const double qbar = c.q - 0.5 * c.b2 - 0.5 * mu * mu * chi * chi * c.rpb2;
+  const double vh2 = fmin(mu * mu * rbar2, c.v0sq);
+  const double Wh = 1.0 / sqrt(1.0 - vh2);
+  const double rho_r = c.D / Wh;
+  const double eps_r = Wh * (qbar - mu * rbar2) + vh2 * Wh * Wh / (1.0 + Wh);
+  if (Wout) {
+    *Wout = Wh;
+    *rho_raw = rho_r;
+    *eps_raw = eps_r;
+    *chi_out = chi;
+  }
+  const double rho = fmax(fmin(G.rho_max, rho_r), G.rho_atmo);
+  const double eps = fmax(fmin(G.eps_max, eps_r), 0.0);
+  // ideal gas: a = p / (rho (1 + eps)) = (Gamma - 1) eps / (1 + eps)
+  const double ah = G.gm1 * eps / (1.0 + eps);
+  const double nuA = (1.0 + ah) * (1.0 + eps) / Wh;
+  const double nuB = (1.0 + ah) * (1.0 + qbar - mu * rbar2);
+  const double nu = fmax(nuA, nuB);
+  (void)rho;
+  return mu - 1.0 / (nu + mu * rbar2);
+}
+
+// f_a(mu) = mu sqrt(1 + rbar^2(mu)) - 1 (h0 = 1 for the ideal gas) and its
+// derivative (section 2.5.2, step 2).
+__device__ __forceinline__ double c2p_fa(const C2PConst &c, double mu, double &df) {
+  const double chi = 1.0 / (1.0 + mu * c.b2);
+  const double dchi = -c.b2 * chi * chi;
+  const double rb2 = c.rb * c.rb;
+  const double rbar2 = c.r2 * chi * chi + mu * chi * (1.0 + chi) * rb2;
+  const double drbar2 = 2.0 * c.r2 * chi * dchi + rb2 * (chi + chi * chi + mu * dchi * (1.0 + 2.0 * chi));
+  const double sq = sqrt(1.0 + rbar2);
+  df = sq + 0.5 * mu * drbar2 / sq;
+  return mu * sq - 1.0;
+}
+
+// Regula falsi with the Illinois modification on a sign-changing bracket.
+// Returns the final iterate; sets ok = false when maxit is reached.
+template <typename Fn>
+__device__ __forceinline__ double illinois_root(Fn f, double lo, double hi, double flo, double fhi, double tol,
+                                                int maxit, int &iters, bool &ok) {
+  // invariant: f(x_old) and f(x_new) bracket the root
+  double xa = lo, fa = flo, xb = hi, fb = fhi;
+  ok = true;
+  iters = 0;
+  for (int it = 0; it < maxit; ++it) {
+    const double xc = xb - fb * (xb - xa) / (fb - fa);
+    const double fc = f(xc);
+    iters = it + 1;
+    if (fc == 0.0) return xc;
+    if ((fc < 0.0) != (fb < 0.0)) {
+      xa = xb;
+      fa = fb;
+    } else {
+      fa *= 0.5;
+    }
+    xb = xc;
+    fb = fc;
+    if (fabs(xb - xa) <= tol * fabs(xb)) return xb;
+  }
+  ok = false;
+  return xb;
+}
+
+// Primitive recovery of one cell from densitised q (section 2.5.2) and the
+// error handling of section 2.5.3.  Returns flag bits; pr receives the
+// primitives (atmosphere / limited values where flagged).
+__device__ __forceinline__ int c2p_cell(const Grid &G, const double *qc, double psi, double alpha, double g1,
+                                        double g2, double *pr) {
+  const double psi2 = psi * psi, psi4 = psi2 * psi2;
+  const double ipsi6 = 1.0 / (psi4 * psi2);
+  const double gd[3] = {psi4, psi4 * g1, psi4 * g2};
+  const double D = qc[0] * ipsi6;
+  double B[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) B[a] = qc[5 + a] * ipsi6;
+  pr[5] = B[0];
+  pr[6] = B[1];
+  pr[7] = B[2];
+  if (!(D >= G.rho_atmo)) {  // rho <= D, so rho < rho_min already
+    pr[0] = G.rho_atmo;
+    pr[1] = pr[2] = pr[3] = 0.0;
+    pr[4] = G.p_atmo;
+    return FL_ATMO;
+  }
+  const double iD = 1.0 / D;
+  const double isD = sqrt(iD);
+  C2PConst c;
+  c.D = D;
+  c.q = qc[4] * ipsi6 * iD;
+  double ru[3], Bc[3];
+  c.r2 = 0.0;
+  c.b2 = 0.0;
+  c.rb = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    const double rd = qc[1 + a] * ipsi6 * iD;
+    ru[a] = rd / gd[a];
+    Bc[a] = B[a] * isD;
+    c.r2 += ru[a] * rd;
+    c.b2 += gd[a] * Bc[a] * Bc[a];
+    c.rb += rd * Bc[a];
+  }
+  c.rpb2 = fmax(c.b2 * c.r2 - c.rb * c.rb, 0.0);
+  c.v0sq = c.r2 / (1.0 + c.r2);
+
+  // step 2: mu_+ by Newton-Raphson from 1/h0 = 1, Illinois as the fallback
+  double mup = 1.0;
+  {
+    double mu = 1.0;
+    bool good = false;
+    for (int it = 0; it < 60; ++it) {
+      double df;
+      const double fv = c2p_fa(c, mu, df);
+      if (fv == 0.0) {
+        good = true;
+        break;
+      }
+      const double mn = mu - fv / df;
+      if (!(mn > 0.0 && mn <= 1.0)) break;
+      if (fabs(mn - mu) <= 1e-15 * mn) {
+        mu = mn;
+        good = true;
+        break;
+      }
+      mu = mn;
+    }
+    if (!good) {
+      int its;
+      bool ok;
+      double dd;
+      auto fa = [&](double x) { return c2p_fa(c, x, dd); };
+      mu = illinois_root(fa, 0.0, 1.0, -1.0, fa(1.0), 1e-15, 200, its, ok);
+    }
+    mup = mu;
+  }
+
+  // step 3: root of the master function on (0, mu_+]
+  int flags = 0;
+  double mu;
+  {
+    auto f = [&](double x) { return c2p_master(G, c, x, nullptr, nullptr, nullptr, nullptr); };
+    const double fhi = f(mup);
+    if (fhi <= 0.0) {
+      mu = mup;
+    } else {
+      const double flo = f(0.0);
+      int its;
+      bool ok;
+      mu = illinois_root(f, 0.0, mup, flo, fhi, G.tol, G.maxit, its, ok);
+      if (!ok) flags |= FL_NOCONV;
+    }
+  }
+
+  // step 4: primitives at the root
+  double W, rho, eps, chi;
+  c2p_master(G, c, mu, &W, &rho, &eps, &chi);
+  double v[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) v[a] = mu * chi * (ru[a] + mu * c.rb * Bc[a]);
+
+  // error handling, section 2.5.3
+  if (rho < G.rho_atmo) {
+    pr[0] = G.rho_atmo;
+    pr[1] = pr[2] = pr[3] = 0.0;
+    pr[4] = G.p_atmo;
+    return flags | FL_ATMO;
+  }
+  if (rho > G.rho_max) {
+    flags |= FL_FRHO;
+    rho = G.rho_max;
+  }
+  const bool soft = (rho < G.rho_low) || (alpha < G.alpha_bh);
+  if (eps < 0.0) {
+    eps = 0.0;
+    flags |= FL_EPS;
+  }
+  if (eps > G.eps_max) {
+    eps = G.eps_max;
+    flags |= soft ? FL_EPS : FL_FEPS;
+  }
+  if (W > G.w_max) {
+    if (soft) {
+      const double vmax2 = 1.0 - 1.0 / (G.w_max * G.w_max);
+      const double v2 = gd[0] * v[0] * v[0] + gd[1] * v[1] * v[1] + gd[2] * v[2] * v[2];
+      const double sc = sqrt(vmax2 / v2);
+#pragma unroll
+      for (int a = 0; a < 3; a++) v[a] *= sc;
+      W = G.w_max;
+      rho = fmax(fmin(D / W, G.rho_max), G.rho_atmo);
+      eps = fmax(fmin(eps, G.eps_max), 0.0);
+      flags |= FL_V;
+    } else {
+      flags |= FL_FV;
+    }
+  }
+  pr[0] = rho;
+  pr[1] = W * v[0];
+  pr[2] = W * v[1];
+  pr[3] = W * v[2];
+  pr[4] = G.gm1 * rho * eps;
+  return flags;
+}
+
+}  // namespace gm
