@@ -501,12 +501,14 @@ static void load_metric(const og_desc *d, const double *met, long c, double m[5]
  * (i,j,k): MC-reconstructed left/right primitives, face metric as the mean
  * of the two neighbouring centres, then HLLE (section 2.1 discretised
  * equation; section 3 solver settings). */
-static void face_flux(const og_desc *d, const double *prim, const double *met, int a, int f,
-                      int i, int j, int k, double out[NV]) {
+static void face_flux_x(const og_desc *d, const double *prim, const double *met, int a, int f,
+                        int i, int j, int k, double out[NV], double *absterms) {
   int cell[3] = {i, j, k};
   double area = face_area(d, a, f, i, j, k);
   if (area == 0.0) {
     for (int v = 0; v < NV; v++) out[v] = 0.0;
+    if (absterms)
+      for (int v = 0; v < NV; v++) absterms[v] = 0.0;
     return;
   }
   long nt = ntot(d);
@@ -544,6 +546,20 @@ static void face_flux(const og_desc *d, const double *prim, const double *met, i
   double fh[NV];
   hlle(fl, fr, ql, qr, fmin(lml, lmr), fmax(lpl, lpr), fh);
   for (int v = 0; v < NV; v++) out[v] = fh[v] * area;
+  if (absterms) {
+    /* magnitude of the terms summed by the HLLE formula (error scale) */
+    double ap = fmax(0.0, fmax(lpl, lpr)), am = fmin(0.0, fmin(lml, lmr)), den = ap - am;
+    for (int v = 0; v < NV; v++) {
+      double t = den < 1e-300 ? 0.5 * (fabs(fl[v]) + fabs(fr[v]))
+                              : (ap * fabs(fl[v]) - am * fabs(fr[v]) - ap * am * (fabs(qr[v]) + fabs(ql[v]))) / den;
+      absterms[v] = t * area;
+    }
+  }
+}
+
+static void face_flux(const og_desc *d, const double *prim, const double *met, int a, int f, int i, int j, int k,
+                      double out[NV]) {
+  face_flux_x(d, prim, met, a, f, i, j, k, out, NULL);
 }
 
 /* -------------------------------------------------------------- sources */
@@ -571,8 +587,9 @@ static void christoffel_point(int coord, double x1, double x2, double G[3][3][3]
  * (second-order, as the derivative stencils of section 2.7) and K_ij of the
  * CFC metric under maximal slicing from the shift (section 2.6).  The result
  * is added to s[]. */
-static void grav_sources(const og_desc *d, const double *met, const pstate *st, double psi, int i, int j, int k,
-                         const double ref[3], double x1, double x2, double s[NV]) {
+static void grav_sources_x(const og_desc *d, const double *met, const pstate *st, double psi, int i, int j, int k,
+                           const double ref[3], double x1, double x2, double s[NV], int absmode) {
+#define TERM(x) (absmode ? fabs(x) : (x))
   int cell[3] = {i, j, k};
   double dalpha[3] = {0, 0, 0}, dpsi[3] = {0, 0, 0}, dbeta[3][3] = {{0}};
   long nt = ntot(d);
@@ -629,32 +646,41 @@ static void grav_sources(const og_desc *d, const double *met, const pstate *st, 
   for (int m = 0; m < 3; m++) T0d[m] = T[0][0] * st->gd[m] * beta[m] + T[0][1 + m] * st->gd[m];
   double pre = alpha * st->psi6;
   for (int a = 0; a < 3; a++) {
-    double v = -T[0][0] * alpha * dalpha[a];
-    for (int m = 0; m < 3; m++) v += T0d[m] * nb[a][m];
+    double v = TERM(-T[0][0] * alpha * dalpha[a]);
+    for (int m = 0; m < 3; m++) v += TERM(T0d[m] * nb[a][m]);
     /* nabla_i gamma_jk = 4 psi^3 d_i psi ref_jk (diagonal) */
     double dg = 4.0 * psi * psi * psi * dpsi[a];
     for (int m = 0; m < 3; m++) {
       double Tjk = T[0][0] * beta[m] * beta[m] + 2.0 * T[0][1 + m] * beta[m] + T[1 + m][1 + m];
-      v += 0.5 * Tjk * dg * ref[m];
+      v += TERM(0.5 * Tjk * dg * ref[m]);
     }
-    s[QS1 + a] += pre * v;
+    s[QS1 + a] += TERM(pre * v);
   }
   {
     double Kbb = 0.0, bda = 0.0, TK = 0.0, T0K = 0.0;
     for (int a = 0; a < 3; a++) {
-      bda += beta[a] * dalpha[a];
+      bda += TERM(beta[a] * dalpha[a]);
       for (int b = 0; b < 3; b++) {
-        Kbb += K[a][b] * beta[a] * beta[b];
-        TK += T[1 + a][1 + b] * K[a][b];
+        Kbb += TERM(K[a][b] * beta[a] * beta[b]);
+        TK += TERM(T[1 + a][1 + b] * K[a][b]);
       }
     }
     for (int a = 0; a < 3; a++) {
       double Kb = 0.0;
-      for (int b = 0; b < 3; b++) Kb += K[a][b] * beta[b];
-      T0K += T[0][1 + a] * (2.0 * Kb - dalpha[a]);
+      for (int b = 0; b < 3; b++) Kb += TERM(K[a][b] * beta[b]);
+      T0K += TERM(T[0][1 + a] * (2.0 * Kb - TERM(dalpha[a])));
     }
-    s[QTAU] += pre * (T[0][0] * (Kbb - bda) + T0K + TK);
+    if (absmode)
+      s[QTAU] += fabs(pre) * (fabs(T[0][0]) * (Kbb + bda) + T0K + TK);
+    else
+      s[QTAU] += pre * (T[0][0] * (Kbb - bda) + T0K + TK);
   }
+#undef TERM
+}
+
+static void grav_sources(const og_desc *d, const double *met, const pstate *st, double psi, int i, int j, int k,
+                         const double ref[3], double x1, double x2, double s[NV]) {
+  grav_sources_x(d, met, st, psi, i, j, k, ref, x1, x2, s, 0);
 }
 
 /* Geometric sources <Gamma^l_ik> (f_S_l)^k with the fluxes taken at the cell
@@ -662,14 +688,17 @@ static void grav_sources(const og_desc *d, const double *met, const pstate *st, 
  * coordinate is zero by construction.  The spherical <Gamma^phi_theta phi>
  * is taken as the exact cell average, (A_theta+ - A_theta-)/dV, of which the
  * printed cot(theta) is the point value. */
-static void geom_sources(const og_desc *d, const pstate *st, int i, int j, int k, double s[NV]) {
+static void geom_sources_x(const og_desc *d, const pstate *st, int i, int j, int k, double s[NV], int absmode) {
   if (d->coord == CART) return;
   double f[3][NV];
   for (int a = 0; a < 3; a++) flux_from_state(st, a, f[a]);
   double dV = cell_volume(d, i, j, k);
+  if (absmode)
+    for (int a = 0; a < 3; a++)
+      for (int v = 0; v < NV; v++) f[a][v] = fabs(f[a][v]);
   if (d->coord == CYL) {
     double R = centre(d, 0, i);
-    s[QS1 + 0] += (1.0 / R) * f[2][QS1 + 2];
+    s[QS1 + 0] += (absmode ? fabs(1.0 / R) : 1.0 / R) * f[2][QS1 + 2];
     return;
   }
   double rp = face_pos(d, 0, i + 1), rm = face_pos(d, 0, i);
@@ -678,8 +707,17 @@ static void geom_sources(const og_desc *d, const pstate *st, int i, int j, int k
   double g_th_rth = 0.5 * (Arp - Arm) / dV;          /* <G^th_r th> = <G^ph_r ph> */
   double g_r_thth = -0.25 * (rp * rp * Arp - rm * rm * Arm) / dV; /* <G^r_th th> */
   double g_ph_thph = (Atp - Atm) / dV;                /* <G^ph_th ph> */
+  if (absmode) {
+    g_th_rth = fabs(g_th_rth);
+    g_r_thth = fabs(g_r_thth);
+    g_ph_thph = fabs(g_ph_thph);
+  }
   s[QS1 + 0] += g_th_rth * f[1][QS1 + 1] + g_th_rth * f[2][QS1 + 2];
   s[QS1 + 1] += g_r_thth * f[1][QS1 + 0] + g_th_rth * f[0][QS1 + 1] + g_ph_thph * f[2][QS1 + 2];
+}
+
+static void geom_sources(const og_desc *d, const pstate *st, int i, int j, int k, double s[NV]) {
+  geom_sources_x(d, st, i, j, k, s, 0);
 }
 
 /* ------------------------------------------------------------------- RHS */
@@ -730,8 +768,11 @@ void og_rhs_cells(const og_desc *d, const double *prim, const double *met, long 
   for (long c = 0; c < ncell; c++) og_rhs_cell(d, prim, met, ijk[3 * c], ijk[3 * c + 1], ijk[3 * c + 2], out + NV * c);
 }
 
-/* Each cell's contribution magnitudes: sum over faces of |F A|/dV plus
- * |sources|; the scale against which a RHS difference is measured. */
+/* Error scale of each cell's RHS (test helper): the sum over the cell's
+ * faces of the magnitudes of the terms the HLLE flux adds up, times area over
+ * volume, plus the summed magnitudes of every source term.  A floating-point
+ * evaluation of the RHS is accurate relative to this sum, not to the RHS
+ * itself, which cancels to near zero in smooth or static regions. */
 void og_rhs_scale_cells(const og_desc *d, const double *prim, const double *met, long ncell, const int *ijk, double *out) {
   long nt = ntot(d);
   for (long c = 0; c < ncell; c++) {
@@ -741,10 +782,10 @@ void og_rhs_scale_cells(const og_desc *d, const double *prim, const double *met,
     for (int v = 0; v < NV; v++) o[v] = 0.0;
     double dV = cell_volume(d, i, j, k);
     for (int a = 0; a < d->ndim; a++) {
-      double fm[NV], fp[NV];
-      face_flux(d, prim, met, a, cell[a], i, j, k, fm);
-      face_flux(d, prim, met, a, cell[a] + 1, i, j, k, fp);
-      for (int v = 0; v < NV; v++) o[v] += (fabs(fp[v]) + fabs(fm[v])) / dV;
+      double fm[NV], fp[NV], am[NV], ap[NV];
+      face_flux_x(d, prim, met, a, cell[a], i, j, k, fm, am);
+      face_flux_x(d, prim, met, a, cell[a] + 1, i, j, k, fp, ap);
+      for (int v = 0; v < NV; v++) o[v] += (ap[v] + am[v]) / dV;
     }
     long cc = at(d, i, j, k);
     double pr[NV], m[5];
@@ -756,9 +797,9 @@ void og_rhs_scale_cells(const og_desc *d, const double *prim, const double *met,
     pstate st;
     point_state(d->gamma, pr, m[0], m[1], m + 2, ref, &st);
     double s1[NV] = {0}, s2[NV] = {0};
-    grav_sources(d, met, &st, m[0], i, j, k, ref, x1, x2, s1);
-    geom_sources(d, &st, i, j, k, s2);
-    for (int v = 0; v < NV; v++) o[v] += fabs(s1[v]) + fabs(s2[v]);
+    grav_sources_x(d, met, &st, m[0], i, j, k, ref, x1, x2, s1, 1);
+    geom_sources_x(d, &st, i, j, k, s2, 1);
+    for (int v = 0; v < NV; v++) o[v] += s1[v] + s2[v];
   }
 }
 

@@ -3,10 +3,13 @@
 Tolerances (FP64 on both sides, different operation order and FMA use):
   prim2con            1e-13 relative to the largest component of the cell
   c2p                 1e-12 on rho, W v (relative to |W v| + 1e-3), p relative
-                      to max(p, (Gamma-1) rho tau/D); identical flags
+                      to max(p, (Gamma-1) rho tau/D), or 30x the cell's own
+                      sensitivity to 2-ulp input perturbations where the
+                      recovery is ill-conditioned (high b^2/rho); identical flags
   ghost fill          bit-exact (copies with sign flips)
-  RHS                 1e-12 of the cell's sum of absolute contributions
-                      (flux terms |F dA|/dV plus |sources|)
+  RHS                 1e-12 of the cell's error scale: the summed magnitudes
+                      of the terms each HLLE face flux adds up (times dA/dV)
+                      plus the summed magnitudes of the source terms
   CFL dt              1e-13 relative
   100 steps, smooth   1e-9 volume-weighted relative L1 per variable
 """
@@ -152,15 +155,28 @@ def test_c2p_parity(coord):
     assert np.array_equal(fo_i, fg_i)
     assert int(host(nf)[0]) == nfo
     po_i, pg_i = W.interior(p, po), W.interior(p, pg)
-    rel_rho = np.abs(pg_i[0] - po_i[0]) / po_i[0]
-    u = np.sqrt(np.sum(po_i[1:4] ** 2, axis=0)) + 1e-3
-    rel_u = np.abs(pg_i[1:4] - po_i[1:4]).max(axis=0) / u
     qi = W.interior(p, q)
-    pscale = np.maximum(po_i[4], (p.get("gamma", 5 / 3) - 1) * po_i[0] * np.abs(qi[4] / qi[0]))
-    rel_p = np.abs(pg_i[4] - po_i[4]) / pscale
-    note(f"  c2p worst rho={rel_rho.max():.2e} Wv={rel_u.max():.2e} p={rel_p.max():.2e} "
-         f"flags={np.unique(fo_i)}")
-    assert rel_rho.max() < 1e-12 and rel_u.max() < 1e-12 and rel_p.max() < 1e-12
+    gm1 = p.get("gamma", 5 / 3) - 1
+
+    def scaled(pa, pb):
+        rho = np.abs(pa[0] - pb[0]) / pb[0]
+        u = np.abs(pa[1:4] - pb[1:4]).max(axis=0) / (np.sqrt(np.sum(pb[1:4] ** 2, axis=0)) + 1e-3)
+        ps = np.maximum(pb[4], gm1 * pb[0] * np.abs(qi[4] / qi[0]))
+        return np.maximum(np.maximum(rho, u), np.abs(pa[4] - pb[4]) / ps)
+
+    # conditioning of the recovery: the oracle's own response to 2-ulp
+    # relative perturbations of its input q (same scaled measure)
+    rng = np.random.default_rng(9)
+    sens = np.zeros(po_i.shape[1:])
+    for _ in range(4):
+        qp = q * (1.0 + 4.4e-16 * rng.uniform(-1, 1, q.shape))
+        _, pp, _, _ = oracle.c2p(p, qp, met)
+        sens = np.maximum(sens, scaled(W.interior(p, pp), po_i))
+    tol = np.maximum(1e-12, 30.0 * sens)
+    err = scaled(pg_i, po_i)
+    note(f"  c2p worst scaled err={err.max():.2e}; cells with tol > 1e-12 from conditioning: "
+         f"{int((tol > 1e-12).sum())}/{tol.size}; worst err/tol={np.max(err / tol):.2f}; flags={np.unique(fo_i)}")
+    assert np.all(err <= tol)
     np.testing.assert_allclose(W.interior(p, qg), W.interior(p, qo), rtol=1e-13, atol=1e-300)
 
 
