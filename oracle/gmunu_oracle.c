@@ -212,6 +212,26 @@ static void flux_from_state(const pstate *s, int a, double f[NV]) {
     f[QB1 + j] = (j == a) ? 0.0 : s->psi6 * (va * s->Bu[j] - s->vhat[j] * Ba);
 }
 
+/* Magnitudes of the terms that make up each conserved variable and each
+ * flux component along a (error scale for tests; tau and its flux are
+ * differences of much larger terms in cold or static gas). */
+static void abs_terms_from_state(const pstate *s, int a, double Ua[NV], double Fa[NV]) {
+  double D = s->rho * s->W, W2 = s->W * s->W, ab0 = fabs(s->alpha * s->b0);
+  double vh = fabs(s->alpha * s->vu[a]) + fabs(s->beta[a]);
+  double Ba = fabs(s->Bu[a]);
+  Ua[QD] = s->psi6 * D;
+  for (int j = 0; j < 3; j++) Ua[QS1 + j] = s->psi6 * (fabs(s->rhohs * W2 * s->vd[j]) + ab0 * fabs(s->bd[j]));
+  Ua[QTAU] = s->psi6 * (s->rhohs * W2 + s->ps + ab0 * ab0 + D);
+  for (int j = 0; j < 3; j++) Ua[QB1 + j] = s->psi6 * fabs(s->Bu[j]);
+  Fa[QD] = Ua[QD] * vh;
+  for (int j = 0; j < 3; j++)
+    Fa[QS1 + j] = Ua[QS1 + j] * vh + s->psi6 * (fabs(s->alpha * s->bd[j] * Ba / s->W) + (j == a ? s->alpha * s->ps : 0.0));
+  Fa[QTAU] = Ua[QTAU] * vh + s->psi6 * (s->alpha * s->ps * fabs(s->vu[a]) + ab0 * s->alpha * Ba / s->W);
+  for (int j = 0; j < 3; j++)
+    Fa[QB1 + j] = (j == a) ? 0.0
+                           : s->psi6 * (vh * fabs(s->Bu[j]) + (fabs(s->alpha * s->vu[j]) + fabs(s->beta[j])) * Ba);
+}
+
 /* Bounds of the characteristic speeds along a (section 2.3). */
 static void speeds_from_state(double gam, const pstate *s, int a, double *lm, double *lp) {
   double cs2 = gam * s->p / (s->rho * s->h);
@@ -547,11 +567,15 @@ static void face_flux_x(const og_desc *d, const double *prim, const double *met,
   hlle(fl, fr, ql, qr, fmin(lml, lmr), fmax(lpl, lpr), fh);
   for (int v = 0; v < NV; v++) out[v] = fh[v] * area;
   if (absterms) {
-    /* magnitude of the terms summed by the HLLE formula (error scale) */
+    /* magnitude of the terms summed by the HLLE formula, with the states'
+     * and fluxes' own term magnitudes (error scale) */
+    double ual[NV], fal[NV], uar[NV], far_[NV];
+    abs_terms_from_state(&sl, a, ual, fal);
+    abs_terms_from_state(&sr, a, uar, far_);
     double ap = fmax(0.0, fmax(lpl, lpr)), am = fmin(0.0, fmin(lml, lmr)), den = ap - am;
     for (int v = 0; v < NV; v++) {
-      double t = den < 1e-300 ? 0.5 * (fabs(fl[v]) + fabs(fr[v]))
-                              : (ap * fabs(fl[v]) - am * fabs(fr[v]) - ap * am * (fabs(qr[v]) + fabs(ql[v]))) / den;
+      double t = den < 1e-300 ? 0.5 * (fal[v] + far_[v])
+                              : (ap * fal[v] - am * far_[v] - ap * am * (uar[v] + ual[v])) / den;
       absterms[v] = t * area;
     }
   }
