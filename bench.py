@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-slab", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design note, "
@@ -86,6 +88,16 @@ def main():
 
     import paper_2012_07322_amd as gmu
     import workloads as W
+
+    if args.calibrate_copy:
+        nb = args.calibrate_copy << 20
+        a = torch.ones(nb // 8, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nb, "copies": 3}), flush=True)
+        return
 
     n = args.n
     log(f"[bench] building {n}^3 blast wave inputs")

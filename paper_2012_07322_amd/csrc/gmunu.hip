@@ -6,9 +6,9 @@
 //             divergence, gravitational + geometric sources, RK combination;
 //   k_c2p     per interior cell: primitive recovery with error handling;
 //   k_ghosts  per face-adjacent ghost cell: boundary fill of the primitives.
-// The time step is a per-cell rate with a wavefront max-reduction and one
-// 64-bit atomicMax per workgroup, finished by a one-thread kernel that also
-// clears the accumulator (no memset, so the sequence is graph-capturable).
+// The time step is a per-cell rate reduced by wavefront shuffles to one
+// maximum per workgroup (a fixed number of grid-stride workgroups), then by
+// one workgroup that writes dt: no atomics, no memset, graph-capturable.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -27,7 +27,7 @@ struct gmunu_ctx {
   Grid G;
   int device;
   double *geo;                 // packed 1D geometry tables (device)
-  unsigned long long *acc;     // CFL max accumulator (device, 1 word)
+  double *acc;                 // CFL partial maxima (device, kCflParts words)
   // launch timing (measurement only)
   int prof;
   std::vector<hipEvent_t> ev;  // pairs
@@ -59,86 +59,98 @@ struct ProfScope {
 namespace {
 
 constexpr double kTiny = 1e-300;
+constexpr int kCflParts = 2048;  // workgroups of the CFL reduction
 
 // Face flux times face factor through the lower face (along D) of cell
 // (i,j,k): MC reconstruction from the four cells across the face, metric as
 // the mean of the two adjacent centres, HLLE.
+// Load variable v at byte offset ob from a tile base (scalar base, 32-bit
+// per-lane offset).
+__device__ __forceinline__ double ld(const double *__restrict__ base, long nv, int v, unsigned ob) {
+  return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base + v * nv) + ob);
+}
+
+// Face flux times face factor through the lower face (along D) of cell
+// (i,j,k): MC reconstruction from the four cells across the face, metric as
+// the mean of the two adjacent centres, HLLE.  pb, mb: prim and metric
+// bases of the tile; rel: offset of cell (i,j,k) from them (in cells).
 template <int D>
-__device__ __forceinline__ void face_flux(const Grid &G, const double *__restrict__ prim,
-                                          const double *__restrict__ met, int i, int j, int k, double *Fo) {
+__device__ __forceinline__ void face_flux(const Grid &G, const double *__restrict__ pb,
+                                          const double *__restrict__ mb, int i, int j, int k, unsigned rel,
+                                          double *Fo) {
   const int cd = (D == 0 ? i : D == 1 ? j : k) + G.g[D];
+  // zero-area faces (r = 0, theta = 0 or pi) are evaluated like any other
+  // and their flux replaced by 0 at the end; no load-dependent branch here
   const double fa = G.geo.fa[D][cd];
-  if (fa == 0.0) {
-#pragma unroll
-    for (int v = 0; v < NV; v++) Fo[v] = 0.0;
-    return;
-  }
-  const long sd = G.s[D];
-  const long c = cell_offset(G, i, j, k);
+  const unsigned sd8 = (unsigned)G.s[D] * 8u;
+  const unsigned o2 = rel * 8u;  // cell f (right of the face)
+  const unsigned o1 = o2 - sd8, o0 = o1 - sd8, o3 = o2 + sd8;
   double pl[NV], pr[NV];
 #pragma unroll
   for (int v = 0; v < NV; v++) {
-    const double *P = prim + v * G.nv + c;
-    const double a = P[-2 * sd], b = P[-sd], e = P[0], f = P[sd];
+    const double a = ld(pb, G.nv, v, o0), b = ld(pb, G.nv, v, o1), e = ld(pb, G.nv, v, o2),
+                 f = ld(pb, G.nv, v, o3);
     pl[v] = b + 0.5 * mc_slope(a, b, e);
     pr[v] = e - 0.5 * mc_slope(b, e, f);
   }
-  const double psi = 0.5 * (met[c - sd] + met[c]);
-  const double alpha = 0.5 * (met[G.nv + c - sd] + met[G.nv + c]);
+  const double psi = 0.5 * (ld(mb, G.nv, 0, o1) + ld(mb, G.nv, 0, o2));
+  const double alpha = 0.5 * (ld(mb, G.nv, 1, o1) + ld(mb, G.nv, 1, o2));
   double beta[3];
 #pragma unroll
-  for (int a = 0; a < 3; a++) beta[a] = 0.5 * (met[(2 + a) * G.nv + c - sd] + met[(2 + a) * G.nv + c]);
+  for (int a = 0; a < 3; a++) beta[a] = 0.5 * (ld(mb, G.nv, 2 + a, o1) + ld(mb, G.nv, 2 + a, o2));
   double g1 = 1.0, g2 = 1.0;
   if (G.coord != CART) {
     const double r2 = (D == 0) ? G.geo.r2f[i + G.g[0]] : G.geo.r2c[i + G.g[0]];
     const double s2 = (D == 1) ? G.geo.s2f[j + G.g[1]] : G.geo.s2c[j + G.g[1]];
     ref_diag(G.coord, r2, s2, g1, g2);
   }
+  const double psi2 = psi * psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
+  const double gD = D == 0 ? 1.0 : D == 1 ? g1 : g2;
+  const double gud = rcp(psi4 * gD);
   double UL[NV], FL[NV], UR[NV], FR[NV], lmL, lpL, lmR, lpR;
-  state_flux<D>(G.gam, G.gfac, pl, psi, alpha, beta, g1, g2, UL, FL, lmL, lpL);
-  state_flux<D>(G.gam, G.gfac, pr, psi, alpha, beta, g1, g2, UR, FR, lmR, lpR);
+  state_flux<D>(G.gam, G.gfac, pl, psi4, psi6, alpha, beta, g1, g2, gud, UL, FL, lmL, lpL);
+  state_flux<D>(G.gam, G.gfac, pr, psi4, psi6, alpha, beta, g1, g2, gud, UR, FR, lmR, lpR);
   const double ap = fmax(0.0, fmax(lpL, lpR));
   const double am = fmin(0.0, fmin(lmL, lmR));
   const double den = ap - am;
-  if (den < kTiny) {
+  const bool avg = den < kTiny;
+  const double s = fa * rcp(avg ? 1.0 : den);
 #pragma unroll
-    for (int v = 0; v < NV; v++) Fo[v] = 0.5 * (FL[v] + FR[v]) * fa;
-  } else {
-    const double s = fa / den;
-#pragma unroll
-    for (int v = 0; v < NV; v++) Fo[v] = (ap * FL[v] - am * FR[v] + ap * am * (UR[v] - UL[v])) * s;
+  for (int v = 0; v < NV; v++) {
+    const double f = avg ? 0.5 * (FL[v] + FR[v]) * fa : (ap * FL[v] - am * FR[v] + ap * am * (UR[v] - UL[v])) * s;
+    Fo[v] = fa == 0.0 ? 0.0 : f;
   }
 }
 
 // Gravitational sources (section 2.1) with centred metric derivatives, and
 // geometric sources <Gamma^l_ik> (f_S_l)^k with cell-centre fluxes
 // (Appendix A), added into s[].
-__device__ __forceinline__ void cell_sources(const Grid &G, const double *__restrict__ prim,
-                                             const double *__restrict__ met, int i, int j, int k, double *s) {
-  const long c = cell_offset(G, i, j, k);
-  double pr[NV];
-#pragma unroll
-  for (int v = 0; v < NV; v++) pr[v] = prim[v * G.nv + c];
-  const double psi = met[c], alpha = met[G.nv + c];
+__device__ __forceinline__ void cell_sources(const Grid &G, const double *__restrict__ pb,
+                                             const double *__restrict__ mb, int i, int j, int k, unsigned rel,
+                                             double *s) {
+  const unsigned oc = rel * 8u;
+  const double psi = ld(mb, G.nv, 0, oc), alpha = ld(mb, G.nv, 1, oc);
   double beta[3];
 #pragma unroll
-  for (int a = 0; a < 3; a++) beta[a] = met[(2 + a) * G.nv + c];
+  for (int a = 0; a < 3; a++) beta[a] = ld(mb, G.nv, 2 + a, oc);
   double dpsi[3] = {0, 0, 0}, dal[3] = {0, 0, 0}, db[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   bool grav = (beta[0] != 0.0) || (beta[1] != 0.0) || (beta[2] != 0.0);
 #pragma unroll
   for (int a = 0; a < 3; a++) {
     if (a < G.ndim) {
-      const long sa = G.s[a];
-      dpsi[a] = (met[c + sa] - met[c - sa]) * G.i2dx[a];
-      dal[a] = (met[G.nv + c + sa] - met[G.nv + c - sa]) * G.i2dx[a];
+      const unsigned op = oc + (unsigned)G.s[a] * 8u, om = oc - (unsigned)G.s[a] * 8u;
+      dpsi[a] = (ld(mb, G.nv, 0, op) - ld(mb, G.nv, 0, om)) * G.i2dx[a];
+      dal[a] = (ld(mb, G.nv, 1, op) - ld(mb, G.nv, 1, om)) * G.i2dx[a];
 #pragma unroll
-      for (int m = 0; m < 3; m++)
-        db[a][m] = (met[(2 + m) * G.nv + c + sa] - met[(2 + m) * G.nv + c - sa]) * G.i2dx[a];
+      for (int m = 0; m < 3; m++) db[a][m] = (ld(mb, G.nv, 2 + m, op) - ld(mb, G.nv, 2 + m, om)) * G.i2dx[a];
       grav = grav || dpsi[a] != 0.0 || dal[a] != 0.0 || db[a][0] != 0.0 || db[a][1] != 0.0 || db[a][2] != 0.0;
     }
   }
   const bool geom = G.coord != CART;
   if (!grav && !geom) return;
+  double pr[NV];
+#pragma unroll
+  for (int v = 0; v < NV; v++) pr[v] = ld(pb, G.nv, v, oc);
 
   double g1 = 1.0, g2 = 1.0;
   if (geom) ref_diag(G.coord, G.geo.r2c[i + G.g[0]], G.geo.s2c[j + G.g[1]], g1, g2);
@@ -146,7 +158,7 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
   const double psi2 = psi * psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
   const double gd[3] = {psi4, psi4 * g1, psi4 * g2};
   const double W2 = 1.0 + gd[0] * pr[1] * pr[1] + gd[1] * pr[2] * pr[2] + gd[2] * pr[3] * pr[3];
-  const double W = sqrt(W2), iW = 1.0 / W;
+  const double iW = rsq(W2), W = W2 * iW;
   double v[3], vd[3], vh[3];
   double Bv = 0.0, BB = 0.0;
 #pragma unroll
@@ -160,7 +172,7 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
   const double b2 = BB * iW * iW + Bv * Bv;
   const double rhohs = pr[0] + G.gfac * pr[4] + b2;
   const double ps = pr[4] + 0.5 * b2;
-  const double ia = 1.0 / alpha;
+  const double ia = rcp(alpha);
   const double b0 = W * Bv * ia;
 
   if (grav) {
@@ -180,7 +192,7 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
       T0[a] = rhohs * u0 * ui[a] + ps * beta[a] * ia2 - b0 * bi[a];
 #pragma unroll
       for (int m = 0; m < 3; m++)
-        T[a][m] = rhohs * ui[a] * ui[m] + ps * ((a == m ? 1.0 / gd[a] : 0.0) - beta[a] * beta[m] * ia2) -
+        T[a][m] = rhohs * ui[a] * ui[m] + ps * ((a == m ? rcp(gd[a]) : 0.0) - beta[a] * beta[m] * ia2) -
                   bi[a] * bi[m];
     }
     // covariant derivative of the shift with point Christoffel symbols
@@ -194,16 +206,16 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
     if (G.coord == CYL) {
       const double R = G.geo.xc0[i + G.g[0]];
       Gm[0][2][2] = -R;
-      Gm[2][0][2] = Gm[2][2][0] = 1.0 / R;
+      Gm[2][0][2] = Gm[2][2][0] = rcp(R);
     } else if (G.coord == SPH) {
       const double r = G.geo.xc0[i + G.g[0]];
       const double sn = G.geo.sc1[j + G.g[1]], cs = G.geo.cc1[j + G.g[1]];
       Gm[0][1][1] = -r;
       Gm[0][2][2] = -r * sn * sn;
-      Gm[1][0][1] = Gm[1][1][0] = 1.0 / r;
+      Gm[1][0][1] = Gm[1][1][0] = rcp(r);
       Gm[1][2][2] = -sn * cs;
-      Gm[2][0][2] = Gm[2][2][0] = 1.0 / r;
-      Gm[2][1][2] = Gm[2][2][1] = cs / sn;
+      Gm[2][0][2] = Gm[2][2][0] = rcp(r);
+      Gm[2][1][2] = Gm[2][2][1] = cs * rcp(sn);
     }
     double nb[3][3];  // nb[i][k] = d_i beta^k + Gamma^k_il beta^l
 #pragma unroll
@@ -262,19 +274,20 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
       if (l == kk) f += alpha * ps;
       return psi6 * f;
     };
-    if (G.coord == CYL) {
-      s[1] += G.geo.gA[i + G.g[0]] * fS(2, 2);
-    } else {
-      const double gA = G.geo.gA[i + G.g[0]], gB = G.geo.gB[i + G.g[0]], gC = G.geo.gC[j + G.g[1]];
-      s[1] += gA * fS(1, 1) + gA * fS(2, 2);
-      s[2] += gB * fS(0, 1) + gA * fS(1, 0) + gC * fS(2, 2);
-    }
+    // (branch-free accumulation keeps s[] in registers)
+    const double gA = G.geo.gA[i + G.g[0]];
+    const bool sph = G.coord == SPH;
+    const double gB = sph ? G.geo.gB[i + G.g[0]] : 0.0, gC = sph ? G.geo.gC[j + G.g[1]] : 0.0;
+    const double add1 = sph ? gA * fS(1, 1) + gA * fS(2, 2) : gA * fS(2, 2);
+    const double add2 = sph ? gB * fS(0, 1) + gA * fS(1, 0) + gC * fS(2, 2) : 0.0;
+    s[1] += add1;
+    s[2] += add2;
   }
 }
 
 template <int TX, int TY, int TZ, int D>
-__device__ __forceinline__ void face_pass(const Grid &G, const double *__restrict__ prim,
-                                          const double *__restrict__ met, double *sF, int i0, int j0, int k0,
+__device__ __forceinline__ void face_pass(const Grid &G, const double *__restrict__ pb,
+                                          const double *__restrict__ mb, double *sF, int i0, int j0, int k0,
                                           int tx, int ty, int tz, bool valid, double *acc) {
   constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2);
   constexpr int NF = FX * FY * FZ;
@@ -286,7 +299,9 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *__restric
                     (D == 2 ? ck <= G.n[2] : ck < G.n[2]);
     double Fo[NV];
     if (ok) {
-      face_flux<D>(G, prim, met, ci, cj, ck, Fo);
+      // offset from the tile base (the cell at i0 - g0, j0 - g1, k0 - g2)
+      const unsigned rel = (unsigned)((ck - k0 + G.g[2]) * G.s[2] + (cj - j0 + G.g[1]) * G.s[1] + (ci - i0 + G.g[0]));
+      face_flux<D>(G, pb, mb, ci, cj, ck, rel, Fo);
     } else {
 #pragma unroll
       for (int v = 0; v < NV; v++) Fo[v] = 0.0;
@@ -306,6 +321,20 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *__restric
   __syncthreads();
 }
 
+// Tile of this workgroup.  Workgroups are dispatched round-robin over the
+// eight XCDs (each with its own L2), so the linear block index is remapped
+// to give each XCD one contiguous run of tiles (x fastest, then y, then z):
+// neighbouring tiles, whose stencils overlap, then share an L2.
+__device__ __forceinline__ void xcd_tile(const Grid &G, int TX, int TY, int TZ, int &bx, int &by, int &bz) {
+  const int gx = (G.n[0] + TX - 1) / TX, gy = (G.n[1] + TY - 1) / TY, gz = (G.n[2] + TZ - 1) / TZ;
+  const int nb = gx * gy * gz;
+  const int b = blockIdx.x, x = b % 8, ii = b / 8, q = nb / 8, r = nb % 8;
+  const int L = x * q + (x < r ? x : r) + ii;
+  bx = L % gx;
+  by = (L / gx) % gy;
+  bz = L / (gx * gy);
+}
+
 template <int TX, int TY, int TZ, int ND>
 constexpr int max_faces() {
   constexpr int a = (TX + 1) * TY * TZ;
@@ -316,36 +345,50 @@ constexpr int max_faces() {
 
 // MODE 0: dqdt = L(prim).  MODE 1: q_out = ca q_n + cb (q_s + dt L(prim)).
 template <int TX, int TY, int TZ, int ND, int MODE>
-__global__ __launch_bounds__(TX *TY *TZ) void k_stage(const Grid G, const double *__restrict__ prim,
+__global__ __launch_bounds__(TX *TY *TZ, 3) void k_stage(const Grid G, const double *__restrict__ prim,
                                                       const double *__restrict__ met, const double *qn,
                                                       const double *qs, double *out,
                                                       const double *__restrict__ dtp, double ca, double cb) {
   __shared__ double sF[NV * max_faces<TX, TY, TZ, ND>()];
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
-  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY, k0 = blockIdx.z * TZ;
+  int bx, by, bz;
+  xcd_tile(G, TX, TY, TZ, bx, by, bz);
+  const int i0 = bx * TX, j0 = by * TY, k0 = bz * TZ;
   const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
   const bool valid = (i < G.n[0]) && (j < G.n[1]) && (k < G.n[2]);
+  // tile base: the cell (i0 - g0, j0 - g1, k0 - g2); every access of this
+  // workgroup is at a non-negative offset from it
+  const long lo = cell_offset(G, i0 - G.g[0], j0 - G.g[1], k0 - G.g[2]);
+  const double *__restrict__ pb = prim + lo;
+  const double *__restrict__ mb = met + lo;
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; v++) acc[v] = 0.0;
-  face_pass<TX, TY, TZ, 0>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
-  if constexpr (ND > 1) face_pass<TX, TY, TZ, 1>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
-  if constexpr (ND > 2) face_pass<TX, TY, TZ, 2>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
+  face_pass<TX, TY, TZ, 0>(G, pb, mb, sF, i0, j0, k0, tx, ty, tz, valid, acc);
+  if constexpr (ND > 1) face_pass<TX, TY, TZ, 1>(G, pb, mb, sF, i0, j0, k0, tx, ty, tz, valid, acc);
+  if constexpr (ND > 2) face_pass<TX, TY, TZ, 2>(G, pb, mb, sF, i0, j0, k0, tx, ty, tz, valid, acc);
   if (!valid) return;
-  cell_sources(G, prim, met, i, j, k, acc);
-  const long c = cell_offset(G, i, j, k);
+  const unsigned rel = (unsigned)((tz + G.g[2]) * G.s[2] + (ty + G.g[1]) * G.s[1] + (tx + G.g[0]));
+  cell_sources(G, pb, mb, i, j, k, rel, acc);
+  const unsigned oc = rel * 8u;
   if (MODE == 0) {
 #pragma unroll
-    for (int v = 0; v < NV; v++) out[v * G.nv + c] = acc[v];
+    for (int v = 0; v < NV; v++)
+      *reinterpret_cast<double *>(reinterpret_cast<char *>(out + lo + v * G.nv) + oc) = acc[v];
   } else {
     const double dt = *dtp;
+    const double *qnb = qn + lo;
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-      const long o = v * G.nv + c;
-      const double us = (ca == 0.0) ? qn[o] : qs[o];
-      const double base = (ca == 0.0) ? 0.0 : ca * qn[o];
-      out[o] = base + cb * (us + dt * acc[v]);
+      double *o = reinterpret_cast<double *>(reinterpret_cast<char *>(out + lo + v * G.nv) + oc);
+      const double un = ld(qnb, G.nv, v, oc);
+      if (ca == 0.0) {
+        *o = cb * (un + dt * acc[v]);
+      } else {
+        const double us = ld(qs + lo, G.nv, v, oc);
+        *o = ca * un + cb * (us + dt * acc[v]);
+      }
     }
   }
 }
@@ -369,9 +412,9 @@ __global__ __launch_bounds__(NT) void k_c2p(const Grid G, double *q, const doubl
 #pragma unroll
   for (int v = 0; v < NV; v++) prim[v * G.nv + c] = pr[v];
   if (fl & FL_REWRITE) {
-    double U[NV], F[NV], lm, lp;
+    double U[NV];
     const double beta[3] = {met[2 * G.nv + c], met[3 * G.nv + c], met[4 * G.nv + c]};
-    state_flux<0>(G.gam, G.gfac, pr, psi, alpha, beta, g1, g2, U, F, lm, lp);
+    prim_to_cons(G.gam, G.gfac, pr, psi, alpha, beta, g1, g2, U);
 #pragma unroll
     for (int v = 0; v < NV; v++) q[v * G.nv + c] = U[v];
   }
@@ -391,8 +434,8 @@ __global__ __launch_bounds__(NT) void k_prim2con(const Grid G, const double *__r
   double g1 = 1.0, g2 = 1.0;
   if (G.coord != CART) ref_diag(G.coord, G.geo.r2c[I], G.geo.s2c[J], g1, g2);
   const double beta[3] = {met[2 * G.nv + c], met[3 * G.nv + c], met[4 * G.nv + c]};
-  double U[NV], F[NV], lm, lp;
-  state_flux<0>(G.gam, G.gfac, pr, met[c], met[G.nv + c], beta, g1, g2, U, F, lm, lp);
+  double U[NV];
+  prim_to_cons(G.gam, G.gfac, pr, met[c], met[G.nv + c], beta, g1, g2, U);
 #pragma unroll
   for (int v = 0; v < NV; v++) q[v * G.nv + c] = U[v];
 }
@@ -459,12 +502,13 @@ __device__ __forceinline__ double wave_max(double x) {
   return x;
 }
 
+// Per-workgroup maxima of the CFL rate over a grid-stride range of interior
+// cells, written to part[blockIdx] (no atomics).
 __global__ __launch_bounds__(NT) void k_cfl(const Grid G, const double *__restrict__ prim,
-                                            const double *__restrict__ met, unsigned long long *acc) {
-  const long t = (long)blockIdx.x * NT + threadIdx.x;
+                                            const double *__restrict__ met, double *part) {
   const long nin = (long)G.n[0] * G.n[1] * G.n[2];
   double rate = 0.0;
-  if (t < nin) {
+  for (long t = (long)blockIdx.x * NT + threadIdx.x; t < nin; t += (long)gridDim.x * NT) {
     const int i = (int)(t % G.n[0]);
     const int j = (int)((t / G.n[0]) % G.n[1]);
     const int k = (int)(t / ((long)G.n[0] * G.n[1]));
@@ -475,7 +519,7 @@ __global__ __launch_bounds__(NT) void k_cfl(const Grid G, const double *__restri
     double g1 = 1.0, g2 = 1.0;
     if (G.coord != CART) ref_diag(G.coord, G.geo.r2c[i + G.g[0]], G.geo.s2c[j + G.g[1]], g1, g2);
     const double beta[3] = {met[2 * G.nv + c], met[3 * G.nv + c], met[4 * G.nv + c]};
-    rate = cfl_rate(G.gam, G.gfac, pr, met[c], met[G.nv + c], beta, g1, g2, G.ndim, G.idx);
+    rate = fmax(rate, cfl_rate(G.gam, G.gfac, pr, met[c], met[G.nv + c], beta, g1, g2, G.ndim, G.idx));
   }
   rate = wave_max(rate);
   __shared__ double red[NT / 64];
@@ -484,18 +528,27 @@ __global__ __launch_bounds__(NT) void k_cfl(const Grid G, const double *__restri
   if (threadIdx.x == 0) {
     double m = red[0];
     for (int w = 1; w < NT / 64; w++) m = fmax(m, red[w]);
-    // non-negative doubles are ordered like their bit patterns
-    if (m > 0.0) atomicMax(acc, (unsigned long long)__double_as_longlong(m));
+    part[blockIdx.x] = m;
   }
 }
 
-__global__ void k_cfl_finish(unsigned long long *acc, double cfl, double t_end, const double *tp, double *dtp) {
-  const double mx = __longlong_as_double((long long)*acc);
-  const double t = tp ? *tp : 0.0;
-  double dt = mx > 0.0 ? cfl / mx : t_end - t;
-  if (t + dt > t_end) dt = t_end - t;
-  *dtp = dt;
-  *acc = 0ull;
+// dt = cfl / max(part), capped at t_end - t.
+__global__ __launch_bounds__(NT) void k_cfl_finish(const double *part, int nparts, double cfl, double t_end,
+                                                   const double *tp, double *dtp) {
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += NT) m = fmax(m, part[b]);
+  m = wave_max(m);
+  __shared__ double red[NT / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mx = red[0];
+    for (int w = 1; w < NT / 64; w++) mx = fmax(mx, red[w]);
+    const double t = tp ? *tp : 0.0;
+    double dt = mx > 0.0 ? cfl / mx : t_end - t;
+    if (t + dt > t_end) dt = t_end - t;
+    *dtp = dt;
+  }
 }
 
 __global__ void k_advance(double *tp, const double *dtp) { *tp += *dtp; }
@@ -512,7 +565,7 @@ template <int TX, int TY, int TZ, int ND, int MODE>
 void launch_stage_t(const gmunu_ctx *ctx, const double *prim, const double *met, const double *qn,
                     const double *qs, double *out, const double *dtp, double ca, double cb, hipStream_t st) {
   const Grid &G = ctx->G;
-  dim3 grid((G.n[0] + TX - 1) / TX, (G.n[1] + TY - 1) / TY, (G.n[2] + TZ - 1) / TZ);
+  dim3 grid(((G.n[0] + TX - 1) / TX) * ((G.n[1] + TY - 1) / TY) * ((G.n[2] + TZ - 1) / TZ));
   hipLaunchKernelGGL((k_stage<TX, TY, TZ, ND, MODE>), grid, dim3(TX * TY * TZ), 0, st, G, prim, met, qn, qs, out,
                      dtp, ca, cb);
 }
@@ -525,7 +578,7 @@ void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, c
   else if (ctx->G.ndim == 2)
     launch_stage_t<32, 8, 1, 2, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, st);
   else
-    launch_stage_t<8, 8, 4, 3, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, st);
+    launch_stage_t<16, 4, 4, 3, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, st);
 }
 
 long interior_cells(const Grid &G) { return (long)G.n[0] * G.n[1] * G.n[2]; }
@@ -673,13 +726,13 @@ int gmunu_create(const gmunu_grid_desc *desc, gmunu_ctx **out) {
     delete ctx;
     return GMUNU_ENOMEM;
   }
-  if (hipMalloc(&ctx->acc, sizeof(unsigned long long)) != hipSuccess) {
+  if (hipMalloc(&ctx->acc, kCflParts * sizeof(double)) != hipSuccess) {
     (void)hipFree(ctx->geo);
     delete ctx;
     return GMUNU_ENOMEM;
   }
   if (hipMemcpy(ctx->geo, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(ctx->acc, 0, sizeof(unsigned long long)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      hipMemset(ctx->acc, 0, kCflParts * sizeof(double)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(ctx->geo);
     (void)hipFree(ctx->acc);
     delete ctx;
@@ -759,14 +812,15 @@ int gmunu_cfl_dt(gmunu_ctx *ctx, const double *prim, const double *metric, doubl
   if (!ctx || !prim || !metric || !dt_dev) return GMUNU_ENULL;
   if (!aligned8(prim) || !aligned8(metric) || !aligned8(dt_dev)) return GMUNU_EALIGN;
   if (!(cfl > 0.0)) return GMUNU_EINVAL;
+  const long nb = blocks(interior_cells(ctx->G));
+  const int nparts = (int)(nb < kCflParts ? nb : kCflParts);
   {
     ProfScope ps(ctx, S(stream), GMUNU_K_CFL);
-    hipLaunchKernelGGL(k_cfl, dim3(blocks(interior_cells(ctx->G))), dim3(NT), 0, S(stream), ctx->G, prim, metric,
-                       ctx->acc);
+    hipLaunchKernelGGL(k_cfl, dim3(nparts), dim3(NT), 0, S(stream), ctx->G, prim, metric, ctx->acc);
   }
   {
     ProfScope ps(ctx, S(stream), GMUNU_K_OTHER);
-    hipLaunchKernelGGL(k_cfl_finish, dim3(1), dim3(1), 0, S(stream), ctx->acc, cfl, t_end, t_dev, dt_dev);
+    hipLaunchKernelGGL(k_cfl_finish, dim3(1), dim3(NT), 0, S(stream), ctx->acc, nparts, cfl, t_end, t_dev, dt_dev);
   }
   return launch_status();
 }

@@ -76,6 +76,29 @@ __device__ __forceinline__ void ref_diag(int coord, double r2, double s2, double
   }
 }
 
+// 1/x: hardware reciprocal estimate refined by two Newton steps (matches the
+// correctly rounded quotient on measured samples; finite non-zero x).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// 1/sqrt(x) for finite x > 0: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-h * y, y, 0.5);
+  return fma(y, e, y);
+}
+
+// sqrt(x) for x >= 0 (0 below 1e-300).
+__device__ __forceinline__ double sqrt_pos(double x) { return x > 1e-300 ? x * rsq(x) : 0.0; }
+
 // Monotonised-central limited slope: minmod(2 dl, (dl + dr) / 2, 2 dr).
 __device__ __forceinline__ double mc_slope(double a, double b, double c) {
   double dl = b - a, dr = c - b;
@@ -89,15 +112,14 @@ __device__ __forceinline__ double mc_slope(double a, double b, double c) {
 // reference metric diagonal (the first entry is 1 in every coordinate
 // system used here).
 template <int D>
-__device__ __forceinline__ void state_flux(const double gam, const double gfac, const double *pr, double psi,
-                                           double alpha, const double *beta, double g1, double g2, double *U,
-                                           double *F, double &lm, double &lp) {
-  const double psi2 = psi * psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
+__device__ __forceinline__ void state_flux(const double gam, const double gfac, const double *pr, double psi4,
+                                           double psi6, double alpha, const double *beta, double g1, double g2,
+                                           double gud, double *U, double *F, double &lm, double &lp) {
   const double gd[3] = {psi4, psi4 * g1, psi4 * g2};
   const double u2 = gd[0] * pr[1] * pr[1] + gd[1] * pr[2] * pr[2] + gd[2] * pr[3] * pr[3];
   const double W2 = 1.0 + u2;
-  const double W = sqrt(W2);
-  const double iW = 1.0 / W;
+  const double iW = rsq(W2);
+  const double W = W2 * iW;
   double v[3], vd[3], Bd[3];
   double Bv = 0.0, BB = 0.0;
 #pragma unroll
@@ -143,20 +165,28 @@ __device__ __forceinline__ void state_flux(const double gam, const double gfac, 
     F[5 + a] = (a == D) ? 0.0 : psi6 * (vhd * pr[5 + a] - vha * Bdir);
   }
 
-  // wave-speed bounds: a^2 = cs^2 + ca^2 - cs^2 ca^2 (section 2.3)
-  const double c_s2 = gam * p / rhoh;
-  const double c_a2 = b2 / rhohs;
+  // wave-speed bounds: a^2 = cs^2 + ca^2 - cs^2 ca^2 (section 2.3), with
+  // cs^2 = Gamma p / (rho h) and ca^2 = b^2 / (rho h*) from one reciprocal
+  const double t = rcp(rhoh * rhohs);
+  const double c_s2 = gam * p * rhohs * t;
+  const double c_a2 = b2 * rhoh * t;
   const double a2 = c_s2 + c_a2 - c_s2 * c_a2;
   const double v2 = v[0] * vd[0] + v[1] * vd[1] + v[2] * vd[2];
-  const double gud = 1.0 / gd[D];
   const double one_a2 = 1.0 - a2;
   const double va = v[D];
-  double disc = a2 * (1.0 - v2) * ((1.0 - v2 * a2) * gud - one_a2 * va * va);
-  disc = disc > 0.0 ? disc : 0.0;
-  const double sq = sqrt(disc);
-  const double iden = 1.0 / (1.0 - v2 * a2);
+  const double va2a = 1.0 - v2 * a2;
+  const double sq = sqrt_pos(a2 * (1.0 - v2) * (va2a * gud - one_a2 * va * va));
+  const double iden = rcp(va2a);
   lm = alpha * ((one_a2 * va - sq) * iden) - beta[D];
   lp = alpha * ((one_a2 * va + sq) * iden) - beta[D];
+}
+
+// Conserved vector of one point (prim2con), with the same arithmetic.
+__device__ __forceinline__ void prim_to_cons(double gam, double gfac, const double *pr, double psi, double alpha,
+                                             const double *beta, double g1, double g2, double *U) {
+  const double psi2 = psi * psi, psi4 = psi2 * psi2;
+  double F[NV], lm, lp;
+  state_flux<0>(gam, gfac, pr, psi4, psi4 * psi2, alpha, beta, g1, g2, rcp(psi4), U, F, lm, lp);
 }
 
 // CFL rate of one cell: sum over the active axes of max|lambda_a| / dx_a
@@ -167,8 +197,7 @@ __device__ __forceinline__ double cfl_rate(const double gam, const double gfac, 
   const double psi2 = psi * psi, psi4 = psi2 * psi2;
   const double gd[3] = {psi4, psi4 * g1, psi4 * g2};
   const double W2 = 1.0 + gd[0] * pr[1] * pr[1] + gd[1] * pr[2] * pr[2] + gd[2] * pr[3] * pr[3];
-  const double W = sqrt(W2);
-  const double iW = 1.0 / W;
+  const double iW = rsq(W2);
   double v[3], Bv = 0.0, BB = 0.0, v2 = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; a++) {
@@ -179,18 +208,18 @@ __device__ __forceinline__ double cfl_rate(const double gam, const double gfac, 
   }
   const double b2 = BB * iW * iW + Bv * Bv;
   const double rhoh = pr[0] + gfac * pr[4];
-  const double c_s2 = gam * pr[4] / rhoh;
-  const double c_a2 = b2 / (rhoh + b2);
+  const double t = rcp(rhoh * (rhoh + b2));
+  const double c_s2 = gam * pr[4] * (rhoh + b2) * t;
+  const double c_a2 = b2 * rhoh * t;
   const double a2 = c_s2 + c_a2 - c_s2 * c_a2;
   const double one_a2 = 1.0 - a2;
-  const double iden = 1.0 / (1.0 - v2 * a2);
+  const double va2a = 1.0 - v2 * a2;
+  const double iden = rcp(va2a);
   double rate = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; a++) {
     if (a < ndim) {
-      double disc = a2 * (1.0 - v2) * ((1.0 - v2 * a2) / gd[a] - one_a2 * v[a] * v[a]);
-      disc = disc > 0.0 ? disc : 0.0;
-      const double sq = sqrt(disc);
+      const double sq = sqrt_pos(a2 * (1.0 - v2) * (va2a * rcp(gd[a]) - one_a2 * v[a] * v[a]));
       const double lm = alpha * ((one_a2 * v[a] - sq) * iden) - beta[a];
       const double lp = alpha * ((one_a2 * v[a] + sq) * iden) - beta[a];
       rate += fmax(fabs(lm), fabs(lp)) * idx[a];
@@ -213,13 +242,14 @@ struct C2PConst {
 // returns W and the unlimited rho, eps.
 __device__ __forceinline__ double c2p_master(const Grid &G, const C2PConst &c, double mu, double *Wout,
                                              double *rho_raw, double *eps_raw, double *chi_out) {
-  const double chi = 1.0 / (1.0 + mu * c.b2);
+  const double chi = rcp(1.0 + mu * c.b2);
   const double rbar2 = c.r2 * chi * chi + mu * chi * (1.0 + chi) * c.rb * c.rb;
   const double qbar = c.q - 0.5 * c.b2 - 0.5 * mu * mu * chi * chi * c.rpb2;
   const double vh2 = fmin(mu * mu * rbar2, c.v0sq);
-  const double Wh = 1.0 / sqrt(1.0 - vh2);
-  const double rho_r = c.D / Wh;
-  const double eps_r = Wh * (qbar - mu * rbar2) + vh2 * Wh * Wh / (1.0 + Wh);
+  const double iWh = sqrt_pos(1.0 - vh2);  // 1 / W_hat
+  const double Wh = rcp(iWh);
+  const double rho_r = c.D * iWh;
+  const double eps_r = Wh * (qbar - mu * rbar2) + vh2 * Wh * Wh * rcp(1.0 + Wh);
   if (Wout) {
     *Wout = Wh;
     *rho_raw = rho_r;
@@ -229,24 +259,25 @@ __device__ __forceinline__ double c2p_master(const Grid &G, const C2PConst &c, d
   const double rho = fmax(fmin(G.rho_max, rho_r), G.rho_atmo);
   const double eps = fmax(fmin(G.eps_max, eps_r), 0.0);
   // ideal gas: a = p / (rho (1 + eps)) = (Gamma - 1) eps / (1 + eps)
-  const double ah = G.gm1 * eps / (1.0 + eps);
-  const double nuA = (1.0 + ah) * (1.0 + eps) / Wh;
+  const double ah = G.gm1 * eps * rcp(1.0 + eps);
+  const double nuA = (1.0 + ah) * (1.0 + eps) * iWh;
   const double nuB = (1.0 + ah) * (1.0 + qbar - mu * rbar2);
   const double nu = fmax(nuA, nuB);
   (void)rho;
-  return mu - 1.0 / (nu + mu * rbar2);
+  return mu - rcp(nu + mu * rbar2);
 }
 
 // f_a(mu) = mu sqrt(1 + rbar^2(mu)) - 1 (h0 = 1 for the ideal gas) and its
 // derivative (section 2.5.2, step 2).
 __device__ __forceinline__ double c2p_fa(const C2PConst &c, double mu, double &df) {
-  const double chi = 1.0 / (1.0 + mu * c.b2);
+  const double chi = rcp(1.0 + mu * c.b2);
   const double dchi = -c.b2 * chi * chi;
   const double rb2 = c.rb * c.rb;
   const double rbar2 = c.r2 * chi * chi + mu * chi * (1.0 + chi) * rb2;
   const double drbar2 = 2.0 * c.r2 * chi * dchi + rb2 * (chi + chi * chi + mu * dchi * (1.0 + 2.0 * chi));
-  const double sq = sqrt(1.0 + rbar2);
-  df = sq + 0.5 * mu * drbar2 / sq;
+  const double isq = rsq(1.0 + rbar2);
+  const double sq = (1.0 + rbar2) * isq;
+  df = sq + 0.5 * mu * drbar2 * isq;
   return mu * sq - 1.0;
 }
 
@@ -260,7 +291,7 @@ __device__ __forceinline__ double illinois_root(Fn f, double lo, double hi, doub
   ok = true;
   iters = 0;
   for (int it = 0; it < maxit; ++it) {
-    const double xc = xb - fb * (xb - xa) / (fb - fa);
+    const double xc = xb - fb * (xb - xa) * rcp(fb - fa);
     const double fc = f(xc);
     iters = it + 1;
     if (fc == 0.0) return xc;
@@ -284,7 +315,7 @@ __device__ __forceinline__ double illinois_root(Fn f, double lo, double hi, doub
 __device__ __forceinline__ int c2p_cell(const Grid &G, const double *qc, double psi, double alpha, double g1,
                                         double g2, double *pr) {
   const double psi2 = psi * psi, psi4 = psi2 * psi2;
-  const double ipsi6 = 1.0 / (psi4 * psi2);
+  const double ipsi6 = rcp(psi4 * psi2);
   const double gd[3] = {psi4, psi4 * g1, psi4 * g2};
   const double D = qc[0] * ipsi6;
   double B[3];
@@ -299,8 +330,8 @@ __device__ __forceinline__ int c2p_cell(const Grid &G, const double *qc, double 
     pr[4] = G.p_atmo;
     return FL_ATMO;
   }
-  const double iD = 1.0 / D;
-  const double isD = sqrt(iD);
+  const double iD = rcp(D);
+  const double isD = rsq(D);
   C2PConst c;
   c.D = D;
   c.q = qc[4] * ipsi6 * iD;
@@ -311,14 +342,14 @@ __device__ __forceinline__ int c2p_cell(const Grid &G, const double *qc, double 
 #pragma unroll
   for (int a = 0; a < 3; a++) {
     const double rd = qc[1 + a] * ipsi6 * iD;
-    ru[a] = rd / gd[a];
+    ru[a] = rd * rcp(gd[a]);
     Bc[a] = B[a] * isD;
     c.r2 += ru[a] * rd;
     c.b2 += gd[a] * Bc[a] * Bc[a];
     c.rb += rd * Bc[a];
   }
   c.rpb2 = fmax(c.b2 * c.r2 - c.rb * c.rb, 0.0);
-  c.v0sq = c.r2 / (1.0 + c.r2);
+  c.v0sq = c.r2 * rcp(1.0 + c.r2);
 
   // step 2: mu_+ by Newton-Raphson from 1/h0 = 1, Illinois as the fallback
   double mup = 1.0;
@@ -332,7 +363,7 @@ __device__ __forceinline__ int c2p_cell(const Grid &G, const double *qc, double 
         good = true;
         break;
       }
-      const double mn = mu - fv / df;
+      const double mn = mu - fv * rcp(df);
       if (!(mn > 0.0 && mn <= 1.0)) break;
       if (fabs(mn - mu) <= 1e-15 * mn) {
         mu = mn;
@@ -397,9 +428,9 @@ __device__ __forceinline__ int c2p_cell(const Grid &G, const double *qc, double 
   }
   if (W > G.w_max) {
     if (soft) {
-      const double vmax2 = 1.0 - 1.0 / (G.w_max * G.w_max);
+      const double vmax2 = 1.0 - rcp(G.w_max * G.w_max);
       const double v2 = gd[0] * v[0] * v[0] + gd[1] * v[1] * v[1] + gd[2] * v[2] * v[2];
-      const double sc = sqrt(vmax2 / v2);
+      const double sc = sqrt(vmax2 * rcp(v2));
 #pragma unroll
       for (int a = 0; a < 3; a++) v[a] *= sc;
       W = G.w_max;
