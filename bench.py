@@ -25,6 +25,24 @@ HBM_PEAK_GBS = 8000.0
 STAGE_BYTES = {0: 29 * 8, 1: 37 * 8, 2: 37 * 8}
 
 
+def kernel_traffic():
+    """HBM bytes per stage launch from the committed rocprofv3 counters, if
+    the kernel sources are unchanged since they were taken (else None)."""
+    import glob
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_stage_blast3d_256_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2012_07322_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -143,6 +161,7 @@ def main():
     st_ms, st_cnt = prof["stage"]
     bytes_total = cells * sum(STAGE_BYTES[s] for s in range(3)) * args.steps
     achieved = bytes_total / (st_ms * 1e-3) / 1e9 if st_ms > 0 else None
+    traffic = kernel_traffic() if n == 256 else None
     breakdown = {k: {"ms_avg": (v[0] / v[1] if v[1] else None), "launches": v[1]} for k, v in prof.items()}
     out = {
         "metric": METRIC,
@@ -161,7 +180,7 @@ def main():
                    "stages_per_step": 3, "integrator": "SSPRK3", "recon": "MC", "riemann": "HLLE",
                    "cfl": args.cfl, "gamma": 4.0 / 3.0, "seed": args.seed},
         "roofline": {"bound": "hbm", "kernel": "k_stage", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS if achieved else None), "traffic": None,
+                     "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS if achieved else None), "traffic": traffic,
                      "bytes_per_cell_step": sum(STAGE_BYTES.values()), "stage_ms_avg": st_ms / max(st_cnt, 1)},
         "breakdown": breakdown,
         "nfatal": nfatal,
