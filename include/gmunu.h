@@ -156,6 +156,61 @@ int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const dou
                double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
                void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched stage: many independent grids ("blocks": uneven AMR-style blocks
+ * of one simulation, or many simulations) advanced together by persistent
+ * kernels over uniform (block, tile) work items, the whole step captured
+ * once into a HIP graph and replayed.  The paper advances block-tree blocks
+ * of N_grid^ndim cells with one time step for all blocks (section 2.8 and
+ * 2.9); here blocks are grouped: all blocks of one group share one dt (the
+ * minimum over the group's cells) and one time, groups are independent.
+ *
+ * Blocks live in slots.  gmunu_batch_set_block / clear_block edit the host
+ * table; gmunu_batch_commit uploads it (synchronous on `stream`).  Kernels
+ * read the item counts from device memory, so a captured step stays valid
+ * across commits.  A group whose dt is 0 (t >= t_end, or no time set) is
+ * left untouched by a step.  Every block uses its own grid description and
+ * arrays exactly as a single-grid context would.
+ * ------------------------------------------------------------------------ */
+typedef struct gmunu_batch gmunu_batch;
+
+typedef struct gmunu_block {
+  gmunu_grid_desc desc;  /* the block's grid */
+  double *q_n, *q_s, *prim; /* device arrays, layout of the block's grid */
+  const double *metric;     /* device, never written */
+  uint8_t *flags;           /* nullable */
+  int group;                /* 0 <= group < max_groups */
+} gmunu_block;
+
+/* Capacities: slots, groups, and work items per list (one item = one tile of
+ * at most 256 cells, or 256 cells / ghosts).  Allocates device tables. */
+int gmunu_batch_create(int max_blocks, int max_groups, long max_items, gmunu_batch **out);
+int gmunu_batch_destroy(gmunu_batch *b);
+int gmunu_batch_set_block(gmunu_batch *b, int slot, const gmunu_block *blk);
+int gmunu_batch_clear_block(gmunu_batch *b, int slot);
+/* Time and end time of a group (applied at the next commit). */
+int gmunu_batch_set_group(gmunu_batch *b, int group, double t, double t_end);
+/* Rebuild the work lists and upload them; synchronises `stream`. */
+int gmunu_batch_commit(gmunu_batch *b, void *stream);
+/* Time the compiled tile shapes per block-size class on the committed
+ * blocks and keep the fastest (writes q_s of the blocks as scratch);
+ * recommits.  Results do not depend on the choice. */
+int gmunu_batch_autotune(gmunu_batch *b, void *stream);
+/* Initial data of the given committed slots (all if slots is NULL): fill the
+ * ghosts of prim, q_n = prim2con(prim) on the interior, recover prim from
+ * q_n, fill the ghosts again.  Other slots are not touched; synchronises
+ * `stream` once (to upload the slot list). */
+int gmunu_batch_init(gmunu_batch *b, const int *slots, int nslots, void *stream);
+/* One step for every group with dt > 0: dt per group (section 2.9), the RK
+ * stages (q_n <- q^{n+1}, q_s scratch, prim consistent, ghosts filled),
+ * t += dt.  use_graph != 0: capture once (per cfl value) and replay. */
+int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int use_graph, void *stream);
+/* Copy the groups' t and last dt to host arrays (synchronises `stream`). */
+int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, void *stream);
+/* Number of committed items per list: [stage, c2p, ghosts]; tile variant
+ * chosen per block (out_variant[slot], -1 for empty slots). */
+int gmunu_batch_info(gmunu_batch *b, long *items_out, int *out_variant);
+
 /* Kernel timing, for measurement only (not for use under graph capture).
  * With enable != 0, every launch made through this context afterwards is
  * bracketed by HIP events on its stream (up to max_launches pairs; creating

@@ -202,3 +202,138 @@ class Grid:
         _check(lib().gmunu_step(self._h, self._chk(q_n, 8, "q_n"), self._chk(q_s, 8, "q_s"),
                                 self._chk(prim, 8, "prim"), self._chk(metric, 5, "metric"), cfl, t_end,
                                 _ptr(t_dev, "t"), _ptr(dt_dev, "dt"), fp, npn, _stream()), "gmunu_step")
+
+
+# ------------------------------------------------------------------- batch
+
+class BlockSpec(ctypes.Structure):
+    """Mirror of gmunu_block."""
+    _fields_ = [("desc", GridDesc), ("q_n", _P), ("q_s", _P), ("prim", _P), ("metric", _P), ("flags", _P),
+                ("group", ctypes.c_int)]
+
+
+def _batch_sigs(L):
+    I, D = ctypes.c_int, ctypes.c_double
+    L.gmunu_batch_create.argtypes = [I, I, ctypes.c_long, ctypes.POINTER(_P)]
+    L.gmunu_batch_destroy.argtypes = [_P]
+    L.gmunu_batch_set_block.argtypes = [_P, I, ctypes.POINTER(BlockSpec)]
+    L.gmunu_batch_clear_block.argtypes = [_P, I]
+    L.gmunu_batch_set_group.argtypes = [_P, I, D, D]
+    L.gmunu_batch_commit.argtypes = [_P, _P]
+    L.gmunu_batch_autotune.argtypes = [_P, _P]
+    L.gmunu_batch_init.argtypes = [_P, _P, I, _P]
+    L.gmunu_batch_step.argtypes = [_P, D, _P, I, _P]
+    L.gmunu_batch_times.argtypes = [_P, _P, _P, _P]
+    L.gmunu_batch_info.argtypes = [_P, _P, _P]
+
+
+def state_shape(p: dict):
+    d = make_desc(p)
+    g = [d.ng if a < d.ndim else 0 for a in range(3)]
+    return (d.n[2] + 2 * g[2], d.n[1] + 2 * g[1], d.n[0] + 2 * g[0])
+
+
+class Arena:
+    """One device allocation sliced into 256-byte aligned views."""
+
+    def __init__(self, ndoubles, device="cuda"):
+        self.buf = torch.empty(int(ndoubles), dtype=torch.float64, device=device)
+        self.off = 0
+
+    @staticmethod
+    def size_of(shapes):
+        tot = 0
+        for s in shapes:
+            n = 1
+            for x in s:
+                n *= x
+            tot += (n + 31) // 32 * 32
+        return tot
+
+    def take(self, shape):
+        n = 1
+        for x in shape:
+            n *= x
+        v = self.buf[self.off:self.off + n].view(shape)
+        self.off += (n + 31) // 32 * 32
+        return v
+
+
+class Batch:
+    """Many grids advanced together (gmunu_batch_*): blocks in slots, groups
+    sharing a time step, persistent kernels, a graph-captured step."""
+
+    def __init__(self, max_blocks, max_groups, max_items):
+        L = lib()
+        if not hasattr(L, "_batch_sigs_set"):
+            _batch_sigs(L)
+            L._batch_sigs_set = True
+        h = _P()
+        _check(L.gmunu_batch_create(max_blocks, max_groups, max_items, ctypes.byref(h)), "gmunu_batch_create")
+        self._h = h
+        self.max_blocks, self.max_groups = max_blocks, max_groups
+        self.keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gmunu_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_block(self, slot, params, q_n, q_s, prim, metric, group, flags=None):
+        shp = state_shape(params)
+        for t, nv, nm in ((q_n, 8, "q_n"), (q_s, 8, "q_s"), (prim, 8, "prim"), (metric, 5, "metric")):
+            if tuple(t.shape) != (nv,) + shp:
+                raise ValueError(f"{nm} has shape {tuple(t.shape)}, expected {(nv,) + shp}")
+        spec = BlockSpec()
+        spec.desc = make_desc(params)
+        spec.q_n, spec.q_s, spec.prim = _ptr(q_n, "q_n"), _ptr(q_s, "q_s"), _ptr(prim, "prim")
+        spec.metric = _ptr(metric, "metric")
+        spec.flags = _ptr(flags, "flags", torch.uint8) if flags is not None else None
+        spec.group = group
+        _check(lib().gmunu_batch_set_block(self._h, slot, ctypes.byref(spec)), "gmunu_batch_set_block")
+        self.keep[slot] = (q_n, q_s, prim, metric, flags)
+
+    def clear_block(self, slot):
+        _check(lib().gmunu_batch_clear_block(self._h, slot), "gmunu_batch_clear_block")
+        self.keep.pop(slot, None)
+
+    def set_group(self, group, t, t_end):
+        _check(lib().gmunu_batch_set_group(self._h, group, t, t_end), "gmunu_batch_set_group")
+
+    def commit(self):
+        _check(lib().gmunu_batch_commit(self._h, _stream()), "gmunu_batch_commit")
+
+    def autotune(self):
+        _check(lib().gmunu_batch_autotune(self._h, _stream()), "gmunu_batch_autotune")
+
+    def init(self, slots=None):
+        if slots is None:
+            _check(lib().gmunu_batch_init(self._h, None, 0, _stream()), "gmunu_batch_init")
+        else:
+            arr = (ctypes.c_int * len(slots))(*slots)
+            _check(lib().gmunu_batch_init(self._h, arr, len(slots), _stream()), "gmunu_batch_init")
+
+    def step(self, cfl, nfatal=None, use_graph=True):
+        npn = _ptr(nfatal, "nfatal", torch.int32) if nfatal is not None else None
+        _check(lib().gmunu_batch_step(self._h, cfl, npn, 1 if use_graph else 0, _stream()), "gmunu_batch_step")
+
+    def times(self):
+        import numpy as np
+        t = np.zeros(self.max_groups)
+        dt = np.zeros(self.max_groups)
+        _check(lib().gmunu_batch_times(self._h, t.ctypes.data_as(_P), dt.ctypes.data_as(_P), _stream()),
+               "gmunu_batch_times")
+        return t, dt
+
+    def info(self):
+        import numpy as np
+        items = np.zeros(3, dtype=np.int64)
+        var = np.zeros(self.max_blocks, dtype=np.int32)
+        _check(lib().gmunu_batch_info(self._h, items.ctypes.data_as(_P), var.ctypes.data_as(_P)), "gmunu_batch_info")
+        return items, var

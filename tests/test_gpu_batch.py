@@ -1,0 +1,194 @@
+"""Batched stage (gmunu_batch_*) on the GPU.
+
+A block advanced inside a batch runs the single-grid per-cell arithmetic on
+the same inputs, so it must equal the block advanced alone bit for bit
+(whatever tile shape the autotuner picks); a group of blocks sharing one
+time step is checked against the oracle advanced with that step.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2012_07322_amd as gmu
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STAR = None
+
+
+def star():
+    global STAR
+    if STAR is None:
+        STAR = W.tov_isotropic(1.28e-3)
+    return STAR
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mixed_blocks(nb=12, seed=3, **kw):
+    ps = W.amr_block_params(nb, seed=seed, sizes=(8, 16), **kw)
+    out = []
+    for b, p in enumerate(ps):
+        pr, met = W.amr_block_state(p, b, star(), seed=seed)
+        out.append((p, pr, met))
+    return out
+
+
+def blast_like_blocks():
+    """1D, 2D and 3D Cartesian blocks with flat metric (serving-style mix)."""
+    out = []
+    p, pr, met = W.mhd_shock_tube(300)
+    out.append((p, pr, met))
+    p, pr, met = W.blast_wave_2d(48)
+    out.append((p, pr, met))
+    p, pr, met = W.blast_wave_3d(20)
+    out.append((p, pr, met))
+    return out
+
+
+def alone(p, pr, met, nsteps, cfl=0.4, t_end=1e30):
+    g = gmu.Grid(p)
+    prd, metd = torch.from_numpy(pr.copy()).cuda(), torch.from_numpy(met).cuda()
+    g.fill_ghosts(prd)
+    qn = g.prim2con(prd, metd)
+    g.c2p(qn, metd, prd)
+    g.fill_ghosts(prd)
+    qs = torch.zeros_like(qn)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt = torch.zeros_like(t)
+    for _ in range(nsteps):
+        g.step(qn, qs, prd, metd, cfl, t_end, t, dt)
+    torch.cuda.synchronize()
+    return qn.cpu().numpy(), prd.cpu().numpy(), float(t.item())
+
+
+def make_batch(blocks, groups, max_groups=None, t_end=1e30):
+    shapes = []
+    for p, _, _ in blocks:
+        s = gmu.state_shape(p)
+        shapes += [(8,) + s] * 3 + [(5,) + s]
+    ar = gmu.Arena(gmu.Arena.size_of(shapes))
+    B = gmu.Batch(len(blocks) + 2, max_groups or (max(groups) + 1), 1 << 16)
+    views = []
+    for slot, ((p, pr, met), grp) in enumerate(zip(blocks, groups)):
+        s = gmu.state_shape(p)
+        qn, qs, prim, m = ar.take((8,) + s), ar.take((8,) + s), ar.take((8,) + s), ar.take((5,) + s)
+        prim.copy_(torch.from_numpy(pr))
+        m.copy_(torch.from_numpy(met))
+        qs.zero_()
+        B.set_block(slot, p, qn, qs, prim, m, grp)
+        views.append((qn, prim))
+    for g in sorted(set(groups)):
+        B.set_group(g, 0.0, t_end)
+    B.commit()
+    B.init()
+    return B, views, ar
+
+
+@pytest.mark.parametrize("tune,graph", [(False, True), (True, True), (True, False)])
+def test_batch_equals_each_block_alone(tune, graph):
+    blocks = mixed_blocks(10) + blast_like_blocks()
+    groups = list(range(len(blocks)))
+    B, views, _ = make_batch(blocks, groups)
+    if tune:
+        B.autotune()
+        items, var = B.info()
+        note(f"  tuned variants {var[:len(blocks)].tolist()} items {items.tolist()}")
+    nst = 3
+    for _ in range(nst):
+        B.step(0.4, use_graph=graph)
+    torch.cuda.synchronize()
+    t_b, _ = B.times()
+    for slot, (p, pr, met) in enumerate(blocks):
+        qa, pa, ta = alone(p, pr, met, nst)
+        qb, pb = views[slot][0].cpu().numpy(), views[slot][1].cpu().numpy()
+        assert t_b[slot] == ta
+        assert np.array_equal(W.interior(p, qa), W.interior(p, qb)), f"block {slot} q differs"
+        assert np.array_equal(pa, pb), f"block {slot} prim differs"
+
+
+def test_batch_shared_dt_group_against_oracle():
+    # blocks inside the star (density far above the atmosphere floor, where
+    # the atmosphere threshold cannot flip between the two implementations)
+    blocks = mixed_blocks(6, seed=5, r_range=(0.5, 5.0), box=2.5)
+    for p, pr, _ in blocks:
+        assert W.interior(p, pr)[0].min() > 1e4 * p["rho_atmo"]
+    B, views, _ = make_batch(blocks, [0] * len(blocks))
+    B.step(0.4)
+    torch.cuda.synchronize()
+    t, dt = B.times()
+    dts = [oracle.cfl_dt(p, oracle.fill_ghosts(p, pr.copy()), met, 0.4) for p, pr, met in blocks]
+    note(f"  shared dt {dt[0]:.15e} oracle min {min(dts):.15e}")
+    assert abs(dt[0] - min(dts)) <= 1e-13 * min(dts)
+    assert t[0] == dt[0]
+    for slot in (0, 3, 5):
+        p, pr, met = blocks[slot]
+        po = pr.copy()
+        oracle.fill_ghosts(p, po)
+        q0 = oracle.prim2con(p, po, met)
+        q0, po, _, _ = oracle.c2p(p, q0, met)
+        oracle.fill_ghosts(p, po)
+        qs = q0.copy()
+        for s in range(3):
+            oracle.rk_stage(p, s, dt[0], q0, qs, po, met)
+            if s == 2:
+                q0 = qs.copy()
+        qb = views[slot][0].cpu().numpy()
+        A, Bq = W.interior(p, qb), W.interior(p, q0)
+        for v in range(8):
+            den = np.abs(Bq[v]).max()
+            if den > 0:
+                assert np.abs(A[v] - Bq[v]).max() <= 1e-11 * den, (slot, v)
+
+
+def test_finished_group_left_untouched():
+    blocks = blast_like_blocks()
+    B, views, _ = make_batch(blocks, [0, 1, 2])
+    B.set_group(1, 0.5, 0.5)  # block 1 has reached its end time
+    B.commit()
+    before = [v[0].clone() for v in views]
+    B.step(0.4)
+    B.step(0.4)
+    torch.cuda.synchronize()
+    t, dt = B.times()
+    assert dt[1] == 0.0 and t[1] == 0.5
+    assert torch.equal(before[1], views[1][0])
+    assert not torch.equal(before[0], views[0][0])
+
+
+def test_slots_change_between_graph_replays():
+    blocks = blast_like_blocks()
+    B, views, ar = make_batch(blocks, [0, 1, 2], max_groups=4)
+    B.step(0.4)
+    # replace block 1 by a new 2D blast of a different seed in group 3
+    p, pr, met = W.blast_wave_2d(48, seed=9)
+    s = gmu.state_shape(p)
+    ar2 = gmu.Arena(gmu.Arena.size_of([(8,) + s] * 3 + [(5,) + s]))
+    qn, qs, prim, m = ar2.take((8,) + s), ar2.take((8,) + s), ar2.take((8,) + s), ar2.take((5,) + s)
+    prim.copy_(torch.from_numpy(pr))
+    m.copy_(torch.from_numpy(met))
+    B.clear_block(1)
+    B.set_block(1, p, qn, qs, prim, m, 3)
+    B.set_group(3, 0.0, 1e30)
+    B.commit()
+    B.init([1])
+    B.step(0.4)
+    B.step(0.4)
+    torch.cuda.synchronize()
+    qa, pa, ta = alone(p, pr, met, 2)
+    assert np.array_equal(W.interior(p, qa), W.interior(p, qn.cpu().numpy()))
+    t, _ = B.times()
+    assert t[3] == ta
+    # the blocks that kept running were not re-initialised: they match three
+    # uninterrupted steps alone
+    for slot in (0, 2):
+        pb, prb, metb = blast_like_blocks()[slot]
+        qa, _, _ = alone(pb, prb, metb, 3)
+        assert np.array_equal(W.interior(pb, qa), W.interior(pb, views[slot][0].cpu().numpy()))

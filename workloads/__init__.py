@@ -434,3 +434,73 @@ def poloidal_field(p, r, th, pres, psi, b_peak):
     mi = interior(p, mag).max()
     s = b_peak / mi if mi > 0 else 0.0
     return np.stack([Br * s, Bth * s])
+
+
+# ----------------------------------------------------- AMR-style block set
+
+def amr_block_params(nblocks=3000, seed=0, sizes=(8, 16, 32), rho_atmo=1e-10, K=100.0, Gamma=2.0,
+                     r_range=(0.5, 18.0), box=20.0):
+    """Grid descriptions of a set of independent AMR-style blocks: interior
+    size n^3 with n drawn from `sizes`, coordinates Cartesian or spherical
+    50/50 (counter-based draws keyed by block index).  Spherical blocks sit at
+    r0 in [0.5, 18] with d_theta = d_phi = 0.02 and dr = 0.02 r0; Cartesian
+    blocks lie inside [-20, 20]^3 with dx in {0.05, 0.1, 0.2}.  Outflow ghosts."""
+    idx = np.arange(nblocks, dtype=np.uint64)
+    u = [0.5 * (uniform(seed, idx, 100 + s) + 1.0) for s in range(8)]
+    out = []
+    for b in range(nblocks):
+        n = sizes[min(int(u[0][b] * len(sizes)), len(sizes) - 1)]
+        sph = u[1][b] < 0.5
+        if sph:
+            dth = 0.02
+            r0 = r_range[0] + (r_range[1] - r_range[0]) * u[2][b]
+            th0 = 0.05 + (np.pi - 0.1 - n * dth) * u[3][b]
+            ph0 = 2 * np.pi * u[4][b]
+            dr = dth * r0
+            p = grid(3, SPH, [n, n, n], [r0, th0, ph0], [r0 + n * dr, th0 + n * dth, ph0 + n * dth],
+                     [[OUTFLOW, OUTFLOW]] * 3)
+        else:
+            dx = (0.05, 0.1, 0.2)[min(int(u[5][b] * 3), 2)]
+            span = n * dx
+            x0 = [-box + (2 * box - span) * u[2 + a][b] for a in range(3)]
+            p = grid(3, CART, [n, n, n], x0, [x0[a] + span for a in range(3)], [[OUTFLOW, OUTFLOW]] * 3)
+        p.update(gamma=Gamma, rk=3, rho_atmo=rho_atmo, k_atmo=K, gamma_atmo=Gamma, rho_low_factor=100.0,
+                 alpha_bh=1e-2)
+        out.append(p)
+    return out
+
+
+def amr_block_state(p, block_index, star, seed=0, b_peak=1e-4, v_noise=1e-3):
+    """Primitives and metric of one block: the star's rho, p = K rho^Gamma,
+    psi, alpha at cell centres (isotropic radius), beta = 0, a dipole-like
+    field of peak b_peak weighted by rho / rho_c, and a velocity of physical
+    size v_noise * u, u in [-1, 1) keyed by (seed, block, cell, component)."""
+    x1, x2, x3 = centres(p)
+    if p["coord"] == SPH:
+        r = np.abs(x1)
+        cth, sth = np.cos(x2), np.sin(x2)
+        scale = [np.ones_like(r), r, r * np.abs(sth)]
+    else:
+        r = np.sqrt(x1 * x1 + x2 * x2 + x3 * x3)
+        scale = [np.ones_like(r)] * 3
+    rho, psi, alpha = tov_fields(star, r)
+    rho = np.maximum(rho, p["rho_atmo"])
+    pr = empty_prim(p)
+    pr[0] = rho
+    pr[4] = p["k_atmo"] * rho ** p["gamma"]
+    f = b_peak * rho / star["rho"][0]
+    if p["coord"] == SPH:
+        pr[5] = f * 2.0 * cth
+        pr[6] = f * sth / np.maximum(r, 1e-300)
+    else:
+        rr = np.maximum(r * r, 1e-300)
+        pr[5] = f * 3.0 * x3 * x1 / rr
+        pr[6] = f * 3.0 * x3 * x2 / rr
+        pr[7] = f * (3.0 * x3 * x3 - rr) / rr
+    gidx = global_index(p).astype(np.uint64) + np.uint64(block_index) * np.uint64(1 << 20)
+    for a in range(3):
+        pr[1 + a] = v_noise * uniform(seed, gidx, 10 + a) / np.maximum(scale[a], 1e-300)
+    met = np.zeros((5,) + shape(p))
+    met[0] = psi
+    met[1] = alpha
+    return pr, met
