@@ -83,6 +83,127 @@ def cpu_baseline(n, slab, seed=0):
                       f"{el:.1f} s on 1 host core"}
 
 
+def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True):
+    """Many AMR-style blocks (8^3, 16^3, 32^3 interiors, spherical and
+    Cartesian, TOV-profile magnetised states), each its own simulation with
+    its own time step, advanced (a) by the batched graph-captured step and
+    (b) by one gmunu_step launch sequence per block; both from the same
+    initial data, the results compared bit for bit."""
+    import ctypes
+
+    import torch
+
+    import paper_2012_07322_amd as gmu
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    ps = W.amr_block_params(nblocks, seed=seed)
+    star = W.tov_isotropic(1.28e-3)
+    shapes = [gmu.state_shape(p) for p in ps]
+    per = [[(8,) + s] * 6 + [(5,) + s] for s in shapes]
+    ar = gmu.Arena(gmu.Arena.size_of([x for v in per for x in v]), device=dev)
+    log(f"[blocks] {nblocks} blocks, {ar.buf.numel() * 8 / 2**30:.1f} GiB of state; generating")
+    views = []
+    for b, p in enumerate(ps):
+        pr, met = W.amr_block_state(p, b, star, seed=seed)
+        s = shapes[b]
+        v = {k: ar.take((8,) + s) for k in ("qn_b", "qs_b", "pr_b", "qn_p", "qs_p", "pr_p")}
+        v["met"] = ar.take((5,) + s)
+        v["pr_b"].copy_(torch.from_numpy(pr))
+        v["pr_p"].copy_(v["pr_b"])
+        v["met"].copy_(torch.from_numpy(met))
+        v["qs_b"].zero_()
+        v["qs_p"].zero_()
+        views.append(v)
+    interior = sum(p["n"][0] * p["n"][1] * p["n"][2] for p in ps)
+    with_ghosts = sum(s[0] * s[1] * s[2] for s in shapes)
+    # (a) batched: one group per block
+    B = gmu.Batch(nblocks, nblocks, 1 << 19)
+    for b, p in enumerate(ps):
+        v = views[b]
+        B.set_block(b, p, v["qn_b"], v["qs_b"], v["pr_b"], v["met"], b)
+        B.set_group(b, 0.0, 1e30)
+    B.commit()
+    B.init()
+    tune_s = 0.0
+    if tune:
+        t0 = time.perf_counter()
+        B.autotune()
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - t0
+    items, var = B.info()
+    for _ in range(warmup):
+        B.step(cfl)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        B.step(cfl)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    log(f"[blocks] batched: {ms_b / steps:.3f} ms/step (autotune {tune_s:.1f} s)")
+    # (b) plain: one launch sequence per block (direct C-ABI calls)
+    L = gmu.lib()
+    grids = [gmu.Grid(p) for p in ps]
+    tt = torch.zeros(nblocks, dtype=torch.float64, device=dev)
+    dtt = torch.zeros(nblocks, dtype=torch.float64, device=dev)
+    for b, g in enumerate(grids):
+        v = views[b]
+        g.fill_ghosts(v["pr_p"])
+        q = g.prim2con(v["pr_p"], v["met"])
+        v["qn_p"].copy_(q)
+        g.c2p(v["qn_p"], v["met"], v["pr_p"])
+        g.fill_ghosts(v["pr_p"])
+    P = ctypes.c_void_p
+    calls = []
+    for b, g in enumerate(grids):
+        v = views[b]
+        calls.append((g._h, P(v["qn_p"].data_ptr()), P(v["qs_p"].data_ptr()), P(v["pr_p"].data_ptr()),
+                      P(v["met"].data_ptr()), P(tt.data_ptr() + 8 * b), P(dtt.data_ptr() + 8 * b)))
+    st = P(torch.cuda.current_stream().cuda_stream)
+
+    def plain_step():
+        for h, qn, qs, pr, met, tp, dtp in calls:
+            rc = L.gmunu_step(h, qn, qs, pr, met, cfl, 1e30, tp, dtp, None, None, st)
+            if rc:
+                raise RuntimeError(f"gmunu_step failed ({rc})")
+
+    for _ in range(warmup):
+        plain_step()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        plain_step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1)
+    log(f"[blocks] plain: {ms_p / steps:.3f} ms/step")
+    # identical results
+    t_b, _ = B.times()
+    same = bool((torch.from_numpy(t_b[:nblocks]).to(dev) == tt).all().item())
+    for b, p in enumerate(ps):
+        v = views[b]
+        same = same and torch.equal(W.interior(p, v["qn_b"]), W.interior(p, v["qn_p"]))
+        same = same and torch.equal(v["pr_b"], v["pr_p"])
+    nvar = {}
+    for x in var[:nblocks].tolist():
+        nvar[x] = nvar.get(x, 0) + 1
+    res = {
+        "workload": f"amr_blocks_{nblocks}", "blocks": nblocks, "interior_cells": interior,
+        "cells_with_ghosts": with_ghosts, "steps": steps, "warmup": warmup,
+        "batched": {"value": interior * 3 * steps / (ms_b * 1e-3), "ms_per_step": ms_b / steps,
+                    "graph": True, "autotune_s": tune_s, "tile_variants": nvar, "stage_items": int(items[0])},
+        "plain": {"value": interior * 3 * steps / (ms_p * 1e-3), "ms_per_step": ms_p / steps,
+                  "launches_per_step": 12 * nblocks},
+        "unit": "cell-updates/s", "speedup": ms_p / ms_b, "bitwise_identical": same,
+    }
+    for g in grids:
+        g.close()
+    B.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +214,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-slab", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--blocks", type=int, default=3000,
+                    help="AMR-style blocks for the batched-vs-plain comparison (0: skip)")
+    ap.add_argument("--block-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -185,6 +309,12 @@ def main():
         "breakdown": breakdown,
         "nfatal": nfatal,
     }
+    del qn, qs, prim, metric
+    g.close()
+    torch.cuda.empty_cache()
+    if args.blocks > 0:
+        out["blocks"] = bench_blocks(args.blocks, steps=args.block_steps, cfl=args.cfl, seed=args.seed)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on a {n}x{n}x{args.cpu_slab} slab")
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_slab, args.seed)

@@ -151,7 +151,9 @@ int gmunu_rk_stage(gmunu_ctx *ctx, int stage, const double *dt_dev, const double
 /* One full time step: dt = gmunu_cfl_dt(prim), the RK stages (q_n is
  * overwritten with q^{n+1}, q_s is scratch of the same size), prim ends
  * consistent with q^{n+1} with ghosts filled, and *t_dev += dt.  Device-side
- * time keeps the call graph-capturable. */
+ * time keeps the call graph-capturable.  Once *t_dev has reached t_end the
+ * computed dt is 0 and the step changes nothing (q_n, q_s, prim and flags
+ * are left as they are), so a caller may issue steps past the end. */
 int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, double cfl,
                double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
                void *stream);
@@ -188,8 +190,10 @@ int gmunu_batch_create(int max_blocks, int max_groups, long max_items, gmunu_bat
 int gmunu_batch_destroy(gmunu_batch *b);
 int gmunu_batch_set_block(gmunu_batch *b, int slot, const gmunu_block *blk);
 int gmunu_batch_clear_block(gmunu_batch *b, int slot);
-/* Time and end time of a group (applied at the next commit). */
-int gmunu_batch_set_group(gmunu_batch *b, int group, double t, double t_end);
+/* Time, end time and step limit of a group (applied at the next commit,
+ * which also resets the group's step count to 0).  A group stops (dt = 0)
+ * when t reaches t_end or after max_steps steps; max_steps <= 0: no limit. */
+int gmunu_batch_set_group(gmunu_batch *b, int group, double t, double t_end, int max_steps);
 /* Rebuild the work lists and upload them; synchronises `stream`. */
 int gmunu_batch_commit(gmunu_batch *b, void *stream);
 /* Time the compiled tile shapes per block-size class on the committed
@@ -205,8 +209,9 @@ int gmunu_batch_init(gmunu_batch *b, const int *slots, int nslots, void *stream)
  * stages (q_n <- q^{n+1}, q_s scratch, prim consistent, ghosts filled),
  * t += dt.  use_graph != 0: capture once (per cfl value) and replay. */
 int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int use_graph, void *stream);
-/* Copy the groups' t and last dt to host arrays (synchronises `stream`). */
-int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, void *stream);
+/* Copy the groups' t, last dt and step counts to host arrays of max_groups
+ * entries (each nullable); synchronises `stream`. */
+int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, int *nstep_host, void *stream);
 /* Number of committed items per list: [stage, c2p, ghosts]; tile variant
  * chosen per block (out_variant[slot], -1 for empty slots). */
 int gmunu_batch_info(gmunu_batch *b, long *items_out, int *out_variant);

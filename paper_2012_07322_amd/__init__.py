@@ -218,12 +218,12 @@ def _batch_sigs(L):
     L.gmunu_batch_destroy.argtypes = [_P]
     L.gmunu_batch_set_block.argtypes = [_P, I, ctypes.POINTER(BlockSpec)]
     L.gmunu_batch_clear_block.argtypes = [_P, I]
-    L.gmunu_batch_set_group.argtypes = [_P, I, D, D]
+    L.gmunu_batch_set_group.argtypes = [_P, I, D, D, I]
     L.gmunu_batch_commit.argtypes = [_P, _P]
     L.gmunu_batch_autotune.argtypes = [_P, _P]
     L.gmunu_batch_init.argtypes = [_P, _P, I, _P]
     L.gmunu_batch_step.argtypes = [_P, D, _P, I, _P]
-    L.gmunu_batch_times.argtypes = [_P, _P, _P, _P]
+    L.gmunu_batch_times.argtypes = [_P, _P, _P, _P, _P]
     L.gmunu_batch_info.argtypes = [_P, _P, _P]
 
 
@@ -303,8 +303,8 @@ class Batch:
         _check(lib().gmunu_batch_clear_block(self._h, slot), "gmunu_batch_clear_block")
         self.keep.pop(slot, None)
 
-    def set_group(self, group, t, t_end):
-        _check(lib().gmunu_batch_set_group(self._h, group, t, t_end), "gmunu_batch_set_group")
+    def set_group(self, group, t, t_end, max_steps=0):
+        _check(lib().gmunu_batch_set_group(self._h, group, t, t_end, max_steps), "gmunu_batch_set_group")
 
     def commit(self):
         _check(lib().gmunu_batch_commit(self._h, _stream()), "gmunu_batch_commit")
@@ -323,13 +323,14 @@ class Batch:
         npn = _ptr(nfatal, "nfatal", torch.int32) if nfatal is not None else None
         _check(lib().gmunu_batch_step(self._h, cfl, npn, 1 if use_graph else 0, _stream()), "gmunu_batch_step")
 
-    def times(self):
+    def times(self, with_steps=False):
         import numpy as np
         t = np.zeros(self.max_groups)
         dt = np.zeros(self.max_groups)
-        _check(lib().gmunu_batch_times(self._h, t.ctypes.data_as(_P), dt.ctypes.data_as(_P), _stream()),
-               "gmunu_batch_times")
-        return t, dt
+        ns = np.zeros(self.max_groups, dtype=np.int32)
+        _check(lib().gmunu_batch_times(self._h, t.ctypes.data_as(_P), dt.ctypes.data_as(_P),
+                                       ns.ctypes.data_as(_P), _stream()), "gmunu_batch_times")
+        return (t, dt, ns) if with_steps else (t, dt)
 
     def info(self):
         import numpy as np

@@ -2,22 +2,28 @@
 //
 // Work is cut into uniform items: a stage item is one tile (at most 256
 // cells) of one block, a recovery / CFL item is 256 interior cells of one
-// block, a ghost item 256 ghost cells.  Persistent kernels walk the item
-// lists; each XCD takes one contiguous run of items so that the tiles of a
-// block share that XCD's L2.  Item counts, block records and group times
-// live in device memory, so a step captured into a HIP graph stays valid
-// when blocks are added or removed between steps.  Per-cell arithmetic is
-// the single-grid path's (gmunu_tile.hpp): a block advanced here is bitwise
-// equal to the same block advanced alone, whatever tile shape is used.
+// block, a ghost item 256 ghost cells.  Each work list is stored as a table
+// of entries, one per block (the block's slot and the index of its first
+// item); a workgroup finds the block of an item by search in that table and
+// the tile from the item's rank inside the block.  Tables, block records and
+// group times live in device memory, so a step captured into a HIP graph
+// stays valid when blocks are added or removed, and a commit costs O(blocks)
+// host work and upload.  Persistent kernels walk each list; each XCD takes
+// one contiguous run of items so that the tiles of a block share that XCD's
+// L2.  Per-cell arithmetic is the single-grid path's (gmunu_tile.hpp): a
+// block advanced here is bitwise equal to the same block advanced alone,
+// whatever tile shape is used.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <map>
 #include <new>
 #include <tuple>
 #include <vector>
 
 #include "../../include/gmunu.h"
+#include "batch_internal.hpp"
 #include "gmunu_dev.hpp"
 #include "gmunu_host.hpp"
 #include "gmunu_tile.hpp"
@@ -42,11 +48,27 @@ struct Variant {
 constexpr int NVAR = 8;
 constexpr Variant kVar[NVAR] = {{8, 8, 4, 3},  {16, 4, 4, 3}, {32, 4, 2, 3}, {8, 4, 8, 3},
                                 {32, 8, 1, 2}, {16, 16, 1, 2}, {64, 4, 1, 2}, {256, 1, 1, 1}};
-enum { L_C2P = NVAR, L_GH = NVAR + 1, L_CFL = NVAR + 2, L_IC2P = NVAR + 3, L_IGH = NVAR + 4, NLIST = NVAR + 5 };
+// Work lists: one per tile variant, then recovery, ghosts, CFL (entries
+// ordered by group), and the recovery / ghost lists of an init.
+enum { L_C2P = NVAR, L_GH, L_CFL, L_IC2P, L_IGH, NLIST };
+
+// Entry table of one list on the device: blk[e] is the slot of entry e,
+// start[e] the index of its first item (start[nent] = total), meta = {nent,
+// total}.
+struct DList {
+  const int *blk, *start, *meta;
+};
 
 // Item range of this workgroup: a contiguous share of the list per XCD
-// (workgroups are dispatched round-robin over the eight XCDs).
+// (workgroups are dispatched round-robin over the eight XCDs); a grid of
+// fewer than eight workgroups strides over the whole list.
 __device__ __forceinline__ void xcd_range(int n, int &first, int &end, int &stride) {
+  if (gridDim.x < 8) {
+    first = blockIdx.x;
+    end = n;
+    stride = gridDim.x;
+    return;
+  }
   const int G = gridDim.x, x = blockIdx.x % 8, l = blockIdx.x / 8;
   const int gx = (G - x + 7) / 8;
   const int lo = (int)((long)n * x / 8), hi = (int)((long)n * (x + 1) / 8);
@@ -55,45 +77,63 @@ __device__ __forceinline__ void xcd_range(int n, int &first, int &end, int &stri
   stride = gx;
 }
 
+// Entry holding item `it` (start[e] <= it < start[e+1]); e is the previous
+// answer of this workgroup (items only increase) or -1.
+__device__ __forceinline__ int find_entry(const int *start, int nent, int it, int e) {
+  if (e >= 0 && it < start[e + 1]) return e;
+  int lo = e < 0 ? 0 : e + 1, hi = nent - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= it)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 template <int TX, int TY, int TZ, int ND, int MODE>
-__global__ __launch_bounds__(TX *TY *TZ, 3) void k_bstage(const BlockRec *__restrict__ B,
-                                                          const int4 *__restrict__ items,
-                                                          const int *__restrict__ count, const double *dts,
-                                                          double ca, double cb, int out_qn) {
+__global__ __launch_bounds__(TX *TY *TZ, 3) void k_bstage(const BlockRec *__restrict__ B, DList L,
+                                                          const double *dts, double ca, double cb, int out_qn) {
   __shared__ double sF[NV * max_faces<TX, TY, TZ, ND>()];
+  const int nent = L.meta[0];
   int it, end, stride;
-  xcd_range(*count, it, end, stride);
+  xcd_range(L.meta[1], it, end, stride);
+  int e = -1;
   for (; it < end; it += stride) {
-    const int4 w = items[it];
-    const BlockRec &b = B[w.x];
+    e = find_entry(L.start, nent, it, e);
+    const BlockRec &b = B[L.blk[e]];
     const double *dtp = dts + b.group;
     if (MODE == 1 && *dtp == 0.0) continue;
+    const int l = it - L.start[e];
+    const int gx = (b.G.n[0] + TX - 1) / TX, gy = (b.G.n[1] + TY - 1) / TY;
+    const int i0 = (l % gx) * TX, j0 = ((l / gx) % gy) * TY, k0 = (l / (gx * gy)) * TZ;
     double *out = (MODE == 0 || !out_qn) ? b.qs : b.qn;
-    stage_tile<TX, TY, TZ, ND, MODE>(b.G, w.y, w.z, w.w, b.prim, b.met, b.qn, b.qs, out, dtp, ca, cb, sF);
+    stage_tile<TX, TY, TZ, ND, MODE>(b.G, i0, j0, k0, b.prim, b.met, b.qn, b.qs, out, dtp, ca, cb, sF);
   }
 }
 
 // Recovery on 256-cell items: from q_n (use_qn) or q_s.  force: ignore dt.
-__global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, const int2 *__restrict__ items,
-                                             const int *__restrict__ count, const double *dts, int use_qn,
+__global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, DList L, const double *dts, int use_qn,
                                              int force, unsigned int *nfatal) {
-  const int n = *count;
+  const int nent = L.meta[0], n = L.meta[1];
+  int e = -1;
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
-    const int2 w = items[it];
-    const BlockRec &b = B[w.x];
+    e = find_entry(L.start, nent, it, e);
+    const BlockRec &b = B[L.blk[e]];
     if (!force && dts[b.group] == 0.0) continue;
-    const long t = (long)w.y + threadIdx.x;
+    const long t = (long)(it - L.start[e]) * NT + threadIdx.x;
     if (t < interior_count(b.G)) c2p_one(b.G, use_qn ? b.qn : b.qs, b.met, b.prim, b.flags, nfatal, t);
   }
 }
 
-__global__ __launch_bounds__(NT) void k_bprim2con(const BlockRec *__restrict__ B, const int2 *__restrict__ items,
-                                                  const int *__restrict__ count) {
-  const int n = *count;
+__global__ __launch_bounds__(NT) void k_bprim2con(const BlockRec *__restrict__ B, DList L) {
+  const int nent = L.meta[0], n = L.meta[1];
+  int e = -1;
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
-    const int2 w = items[it];
-    const BlockRec &b = B[w.x];
-    const long t = (long)w.y + threadIdx.x;
+    e = find_entry(L.start, nent, it, e);
+    const BlockRec &b = B[L.blk[e]];
+    const long t = (long)(it - L.start[e]) * NT + threadIdx.x;
     if (t < interior_count(b.G)) {
       const int i = (int)(t % b.G.n[0]), j = (int)((t / b.G.n[0]) % b.G.n[1]);
       const int k = (int)(t / ((long)b.G.n[0] * b.G.n[1]));
@@ -102,26 +142,27 @@ __global__ __launch_bounds__(NT) void k_bprim2con(const BlockRec *__restrict__ B
   }
 }
 
-__global__ __launch_bounds__(NT) void k_bghosts(const BlockRec *__restrict__ B, const int2 *__restrict__ items,
-                                                const int *__restrict__ count, const double *dts, int force) {
-  const int n = *count;
+__global__ __launch_bounds__(NT) void k_bghosts(const BlockRec *__restrict__ B, DList L, const double *dts,
+                                                int force) {
+  const int nent = L.meta[0], n = L.meta[1];
+  int e = -1;
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
-    const int2 w = items[it];
-    const BlockRec &b = B[w.x];
+    e = find_entry(L.start, nent, it, e);
+    const BlockRec &b = B[L.blk[e]];
     if (!force && dts[b.group] == 0.0) continue;
-    const long t = (long)w.y + threadIdx.x;
+    const long t = (long)(it - L.start[e]) * NT + threadIdx.x;
     if (t < ghost_count(b.G)) ghost_one(b.G, b.prim, t);
   }
 }
 
-// Per-item maxima of the CFL rate (items ordered by group).
-__global__ __launch_bounds__(NT) void k_bcfl(const BlockRec *__restrict__ B, const int2 *__restrict__ items,
-                                             const int *__restrict__ count, double *part) {
-  const int n = *count;
+// Per-item maxima of the CFL rate (entries ordered by group).
+__global__ __launch_bounds__(NT) void k_bcfl(const BlockRec *__restrict__ B, DList L, double *part) {
+  const int nent = L.meta[0], n = L.meta[1];
+  int e = -1;
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
-    const int2 w = items[it];
-    const BlockRec &b = B[w.x];
-    const long t = (long)w.y + threadIdx.x;
+    e = find_entry(L.start, nent, it, e);
+    const BlockRec &b = B[L.blk[e]];
+    const long t = (long)(it - L.start[e]) * NT + threadIdx.x;
     const double r = t < interior_count(b.G) ? cfl_one(b.G, b.prim, b.met, t) : 0.0;
     const double m = block_max(r);
     if (threadIdx.x == 0) part[it] = m;
@@ -129,47 +170,51 @@ __global__ __launch_bounds__(NT) void k_bcfl(const BlockRec *__restrict__ B, con
 }
 
 // dt of each group: cfl / max rate over its items, capped at t_end - t,
-// zero for a group without blocks or past its end.
+// zero for a group without blocks, past its end time or at its step limit.
 __global__ __launch_bounds__(NT) void k_bcfl_finish(const int *__restrict__ gfirst, const int *__restrict__ gcount,
                                                     const double *__restrict__ part, int ngroups, double cfl,
-                                                    const double *t, const double *t_end, double *dt) {
+                                                    const double *t, const double *t_end, const int *nstep,
+                                                    const int *maxstep, double *dt) {
   for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
     const int f = gfirst[g], c = gcount[g];
     double m = 0.0;
     for (int k = threadIdx.x; k < c; k += NT) m = fmax(m, part[f + k]);
     m = block_max(m);
     if (threadIdx.x == 0) {
-      const double d = c > 0 ? dt_from_rate(m, cfl, t[g], t_end[g]) : 0.0;
+      const double d = (c > 0 && nstep[g] < maxstep[g]) ? dt_from_rate(m, cfl, t[g], t_end[g]) : 0.0;
       dt[g] = d > 0.0 ? d : 0.0;
     }
   }
 }
 
-__global__ void k_badvance(double *t, const double *dt, int ngroups) {
+__global__ void k_badvance(double *t, int *nstep, const double *dt, int ngroups) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < ngroups) t[g] += dt[g];
+  if (g < ngroups && dt[g] > 0.0) {
+    t[g] += dt[g];
+    nstep[g] += 1;
+  }
 }
 
 template <int V, int MODE>
-void launch_variant(const BlockRec *B, const int4 *items, const int *count, const double *dts, double ca, double cb,
-                    int out_qn, int grid, hipStream_t st) {
+void launch_variant(const BlockRec *B, DList L, const double *dts, double ca, double cb, int out_qn, int grid,
+                    hipStream_t st) {
   constexpr Variant v = kVar[V];
-  hipLaunchKernelGGL((k_bstage<v.tx, v.ty, v.tz, v.nd, MODE>), dim3(grid), dim3(NT), 0, st, B, items, count, dts, ca,
-                     cb, out_qn);
+  hipLaunchKernelGGL((k_bstage<v.tx, v.ty, v.tz, v.nd, MODE>), dim3(grid), dim3(NT), 0, st, B, L, dts, ca, cb,
+                     out_qn);
 }
 
 template <int MODE>
-void launch_variant_any(int v, const BlockRec *B, const int4 *items, const int *count, const double *dts, double ca,
-                        double cb, int out_qn, int grid, hipStream_t st) {
+void launch_variant_any(int v, const BlockRec *B, DList L, const double *dts, double ca, double cb, int out_qn,
+                        int grid, hipStream_t st) {
   switch (v) {
-    case 0: launch_variant<0, MODE>(B, items, count, dts, ca, cb, out_qn, grid, st); break;
-    case 1: launch_variant<1, MODE>(B, items, count, dts, ca, cb, out_qn, grid, st); break;
-    case 2: launch_variant<2, MODE>(B, items, count, dts, ca, cb, out_qn, grid, st); break;
-    case 3: launch_variant<3, MODE>(B, items, count, dts, ca, cb, out_qn, grid, st); break;
-    case 4: launch_variant<4, MODE>(B, items, count, dts, ca, cb, out_qn, grid, st); break;
-    case 5: launch_variant<5, MODE>(B, items, count, dts, ca, cb, out_qn, grid, st); break;
-    case 6: launch_variant<6, MODE>(B, items, count, dts, ca, cb, out_qn, grid, st); break;
-    default: launch_variant<7, MODE>(B, items, count, dts, ca, cb, out_qn, grid, st); break;
+    case 0: launch_variant<0, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
+    case 1: launch_variant<1, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
+    case 2: launch_variant<2, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
+    case 3: launch_variant<3, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
+    case 4: launch_variant<4, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
+    case 5: launch_variant<5, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
+    case 6: launch_variant<6, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
+    default: launch_variant<7, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
   }
 }
 
@@ -181,6 +226,33 @@ int default_variant(const gmunu_grid_desc &d) {
 }
 
 std::tuple<int, int, int, int> bucket_of(const gmunu_grid_desc &d) { return {d.ndim, d.n[0], d.n[1], d.n[2]}; }
+
+long ceil_div(long a, long b) { return (a + b - 1) / b; }
+
+long stage_items(const gmunu_grid_desc &d, int v) {
+  return ceil_div(d.n[0], kVar[v].tx) * ceil_div(d.n[1], kVar[v].ty) * ceil_div(d.n[2], kVar[v].tz);
+}
+
+long cell_items(const gmunu_grid_desc &d) { return ceil_div((long)d.n[0] * d.n[1] * d.n[2], NT); }
+
+long ghost_items(const gmunu_grid_desc &d) {
+  const long nin = (long)d.n[0] * d.n[1] * d.n[2];
+  long tot = 0;
+  for (int a = 0; a < d.ndim; a++) tot += 2L * d.ng * (nin / d.n[a]);
+  return ceil_div(tot, NT);
+}
+
+// Host copy of one list's entry table.
+struct HList {
+  std::vector<int> blk, start;
+  long total = 0;
+  void add(int slot, long items) {
+    if (items <= 0) return;
+    blk.push_back(slot);
+    start.push_back((int)total);
+    total += items;
+  }
+};
 
 }  // namespace
 
@@ -194,16 +266,21 @@ struct gmunu_batch {
   std::vector<double *> geo;
   std::vector<int> var;
   std::map<std::tuple<int, int, int, int>, int> tuned;
-  std::vector<std::pair<int, std::pair<double, double>>> time_set;
+  struct TimeSet {
+    int group;
+    double t, t_end;
+    int max_steps;
+  };
+  std::vector<TimeSet> time_set;
   long counts[NLIST];
   unsigned var_mask;
+  int rec_lo, rec_hi;  // slots whose records changed since the last upload
   // device tables
   BlockRec *d_rec;
-  int4 *d_items[NVAR];
-  int2 *d_list[5];  // c2p, ghosts, cfl, and the c2p / ghost items of an init
-  int *d_count;
+  int *d_blk, *d_start, *d_meta;  // NLIST entry tables of maxb (+1) ints, meta 2 ints per list
   int *d_gfirst, *d_gcount;
   double *d_part, *d_t, *d_dt, *d_tend;
+  int *d_nstep, *d_maxstep;
   // captured step, replayed on a private stream ordered against the
   // caller's stream by events (capture is not possible on the null stream)
   hipStream_t pstream;
@@ -214,6 +291,14 @@ struct gmunu_batch {
   double graph_cfl;
   unsigned graph_mask;
   unsigned int *graph_nfatal;
+
+  DList list(int l) const {
+    return DList{d_blk + (size_t)l * maxb, d_start + (size_t)l * (maxb + 1), d_meta + 2 * l};
+  }
+  void touch(int s) {
+    rec_lo = std::min(rec_lo, s);
+    rec_hi = std::max(rec_hi, s + 1);
+  }
 };
 
 namespace {
@@ -228,16 +313,44 @@ void free_batch(gmunu_batch *b) {
   for (auto g : b->geo)
     if (g) (void)hipFree(g);
   (void)hipFree(b->d_rec);
-  for (int v = 0; v < NVAR; v++) (void)hipFree(b->d_items[v]);
-  for (int l = 0; l < 5; l++) (void)hipFree(b->d_list[l]);
-  (void)hipFree(b->d_count);
+  (void)hipFree(b->d_blk);
+  (void)hipFree(b->d_start);
+  (void)hipFree(b->d_meta);
   (void)hipFree(b->d_gfirst);
   (void)hipFree(b->d_gcount);
   (void)hipFree(b->d_part);
   (void)hipFree(b->d_t);
   (void)hipFree(b->d_dt);
   (void)hipFree(b->d_tend);
+  (void)hipFree(b->d_nstep);
+  (void)hipFree(b->d_maxstep);
   delete b;
+}
+
+// Enqueue the upload of one list's entry table (host vectors must live until
+// the stream is synchronised).
+bool upload_list(gmunu_batch *b, int l, HList &h, int *meta_host, hipStream_t st) {
+  const int nent = (int)h.blk.size();
+  h.start.push_back((int)h.total);
+  meta_host[0] = nent;
+  meta_host[1] = (int)h.total;
+  bool ok = true;
+  if (nent) {
+    ok = hipMemcpyAsync(b->d_blk + (size_t)l * b->maxb, h.blk.data(), sizeof(int) * nent, hipMemcpyHostToDevice,
+                        st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(b->d_start + (size_t)l * (b->maxb + 1), h.start.data(), sizeof(int) * (nent + 1),
+                              hipMemcpyHostToDevice, st) == hipSuccess;
+  }
+  return ok && hipMemcpyAsync(b->d_meta + 2 * l, meta_host, sizeof(int) * 2, hipMemcpyHostToDevice, st) == hipSuccess;
+}
+
+bool upload_records(gmunu_batch *b, hipStream_t st) {
+  if (b->rec_hi <= b->rec_lo) return true;
+  const bool ok = hipMemcpyAsync(b->d_rec + b->rec_lo, b->rec.data() + b->rec_lo,
+                                 sizeof(BlockRec) * (b->rec_hi - b->rec_lo), hipMemcpyHostToDevice, st) == hipSuccess;
+  b->rec_lo = INT_MAX;
+  b->rec_hi = 0;
+  return ok;
 }
 
 int persist_grid(const gmunu_batch *b, long items, int per_cu) {
@@ -249,11 +362,11 @@ int persist_grid(const gmunu_batch *b, long items, int per_cu) {
 int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, hipStream_t st) {
   const int gsm = persist_grid(b, b->maxi, 8);
   const int gst = b->ncu * 4;
-  hipLaunchKernelGGL(k_bcfl, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->d_list[2], b->d_count + L_CFL, b->d_part);
+  hipLaunchKernelGGL(k_bcfl, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_CFL), b->d_part);
   hipLaunchKernelGGL(k_bcfl_finish, dim3(std::min(b->maxg, 4096)), dim3(NT), 0, st, b->d_gfirst, b->d_gcount,
-                     b->d_part, b->maxg, cfl, b->d_t, b->d_tend, b->d_dt);
-  // RK stages (same coefficients as gmunu_rk_stage); blocks of a batch may
-  // mix SSPRK2 and SSPRK3 only by group, so use the first block's choice
+                     b->d_part, b->maxg, cfl, b->d_t, b->d_tend, b->d_nstep, b->d_maxstep, b->d_dt);
+  // RK stages (same coefficients as gmunu_rk_stage); a batch holds one
+  // integrator (checked at commit)
   int nst = 3;
   for (size_t s = 0; s < b->blk.size(); s++)
     if (b->used[s]) {
@@ -276,17 +389,32 @@ int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, hipStream_t s
     }
     const int last = s == nst - 1;
     for (int v = 0; v < NVAR; v++)
-      if (b->var_mask & (1u << v))
-        launch_variant_any<1>(v, b->d_rec, b->d_items[v], b->d_count + v, b->d_dt, ca, cb, last, gst, st);
-    hipLaunchKernelGGL(k_bc2p, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->d_list[0], b->d_count + L_C2P, b->d_dt,
-                       last, 0, nfatal);
-    hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->d_list[1], b->d_count + L_GH, b->d_dt, 0);
+      if (b->var_mask & (1u << v)) launch_variant_any<1>(v, b->d_rec, b->list(v), b->d_dt, ca, cb, last, gst, st);
+    hipLaunchKernelGGL(k_bc2p, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_C2P), b->d_dt, last, 0, nfatal);
+    hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_GH), b->d_dt, 0);
   }
-  hipLaunchKernelGGL(k_badvance, dim3((b->maxg + NT - 1) / NT), dim3(NT), 0, st, b->d_t, b->d_dt, b->maxg);
+  hipLaunchKernelGGL(k_badvance, dim3((b->maxg + NT - 1) / NT), dim3(NT), 0, st, b->d_t, b->d_nstep, b->d_dt,
+                     b->maxg);
   return launch_status();
 }
 
 }  // namespace
+
+namespace gm {
+
+BatchItems batch_items_for(const gmunu_batch *b, const gmunu_grid_desc &d) {
+  BatchItems r;
+  auto it = b->tuned.find(bucket_of(d));
+  r.variant = it != b->tuned.end() ? it->second : default_variant(d);
+  r.stage = stage_items(d, r.variant);
+  r.cells = cell_items(d);
+  r.ghosts = ghost_items(d);
+  return r;
+}
+
+long batch_max_items(const gmunu_batch *b) { return b->maxi; }
+
+}  // namespace gm
 
 extern "C" {
 
@@ -306,6 +434,8 @@ int gmunu_batch_create(int max_blocks, int max_groups, long max_items, gmunu_bat
   b->var.assign(max_blocks, -1);
   for (long &c : b->counts) c = 0;
   b->var_mask = 0;
+  b->rec_lo = INT_MAX;
+  b->rec_hi = 0;
   b->have_graph = false;
   b->have_stream = false;
   int dev = 0;
@@ -314,27 +444,32 @@ int gmunu_batch_create(int max_blocks, int max_groups, long max_items, gmunu_bat
     delete b;
     return GMUNU_EHIP;
   }
-  bool ok = hipMalloc(&b->d_rec, sizeof(BlockRec) * max_blocks) == hipSuccess;
-  for (int v = 0; v < NVAR; v++) ok = ok && hipMalloc(&b->d_items[v], sizeof(int4) * max_items) == hipSuccess;
-  for (int l = 0; l < 5; l++) ok = ok && hipMalloc(&b->d_list[l], sizeof(int2) * max_items) == hipSuccess;
-  ok = ok && hipMalloc(&b->d_count, sizeof(int) * NLIST) == hipSuccess;
-  ok = ok && hipMalloc(&b->d_gfirst, sizeof(int) * max_groups) == hipSuccess;
-  ok = ok && hipMalloc(&b->d_gcount, sizeof(int) * max_groups) == hipSuccess;
+  const size_t nb = max_blocks, ng = max_groups;
+  bool ok = hipMalloc(&b->d_rec, sizeof(BlockRec) * nb) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_blk, sizeof(int) * NLIST * nb) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_start, sizeof(int) * NLIST * (nb + 1)) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_meta, sizeof(int) * 2 * NLIST) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_gfirst, sizeof(int) * ng) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_gcount, sizeof(int) * ng) == hipSuccess;
   ok = ok && hipMalloc(&b->d_part, sizeof(double) * max_items) == hipSuccess;
-  ok = ok && hipMalloc(&b->d_t, sizeof(double) * max_groups) == hipSuccess;
-  ok = ok && hipMalloc(&b->d_dt, sizeof(double) * max_groups) == hipSuccess;
-  ok = ok && hipMalloc(&b->d_tend, sizeof(double) * max_groups) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_t, sizeof(double) * ng) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_dt, sizeof(double) * ng) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_tend, sizeof(double) * ng) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_nstep, sizeof(int) * ng) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_maxstep, sizeof(int) * ng) == hipSuccess;
   if (!ok) {
     free_batch(b);
     return GMUNU_ENOMEM;
   }
-  ok = hipMemset(b->d_rec, 0, sizeof(BlockRec) * max_blocks) == hipSuccess &&
-       hipMemset(b->d_count, 0, sizeof(int) * NLIST) == hipSuccess &&
-       hipMemset(b->d_gcount, 0, sizeof(int) * max_groups) == hipSuccess &&
-       hipMemset(b->d_gfirst, 0, sizeof(int) * max_groups) == hipSuccess &&
-       hipMemset(b->d_t, 0, sizeof(double) * max_groups) == hipSuccess &&
-       hipMemset(b->d_dt, 0, sizeof(double) * max_groups) == hipSuccess &&
-       hipMemset(b->d_tend, 0, sizeof(double) * max_groups) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  ok = hipMemset(b->d_rec, 0, sizeof(BlockRec) * nb) == hipSuccess &&
+       hipMemset(b->d_meta, 0, sizeof(int) * 2 * NLIST) == hipSuccess &&
+       hipMemset(b->d_gcount, 0, sizeof(int) * ng) == hipSuccess &&
+       hipMemset(b->d_gfirst, 0, sizeof(int) * ng) == hipSuccess &&
+       hipMemset(b->d_t, 0, sizeof(double) * ng) == hipSuccess &&
+       hipMemset(b->d_dt, 0, sizeof(double) * ng) == hipSuccess &&
+       hipMemset(b->d_tend, 0, sizeof(double) * ng) == hipSuccess &&
+       hipMemset(b->d_nstep, 0, sizeof(int) * ng) == hipSuccess &&
+       hipMemset(b->d_maxstep, 0, sizeof(int) * ng) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     free_batch(b);
     return GMUNU_EHIP;
@@ -396,6 +531,7 @@ int gmunu_batch_set_block(gmunu_batch *b, int slot, const gmunu_block *blk) {
   b->rec[slot] = r;
   b->blk[slot] = *blk;
   b->used[slot] = 1;
+  b->touch(slot);
   auto it = b->tuned.find(bucket_of(blk->desc));
   b->var[slot] = it != b->tuned.end() ? it->second : default_variant(blk->desc);
   return GMUNU_OK;
@@ -407,13 +543,14 @@ int gmunu_batch_clear_block(gmunu_batch *b, int slot) {
   b->used[slot] = 0;
   b->rec[slot].active = 0;
   b->var[slot] = -1;
+  b->touch(slot);
   return GMUNU_OK;
 }
 
-int gmunu_batch_set_group(gmunu_batch *b, int group, double t, double t_end) {
+int gmunu_batch_set_group(gmunu_batch *b, int group, double t, double t_end, int max_steps) {
   if (!b) return GMUNU_ENULL;
   if (group < 0 || group >= b->maxg || !(t_end >= t)) return GMUNU_EINVAL;
-  b->time_set.push_back({group, {t, t_end}});
+  b->time_set.push_back({group, t, t_end, max_steps > 0 ? max_steps : INT_MAX});
   return GMUNU_OK;
 }
 
@@ -426,69 +563,44 @@ int gmunu_batch_commit(gmunu_batch *b, void *stream) {
       if (rk && b->blk[s].desc.rk != rk) return GMUNU_EINVAL;  // one integrator per batch
       rk = b->blk[s].desc.rk;
     }
-  std::vector<int4> items[NVAR];
-  std::vector<int2> lc2p, lgh;
-  std::vector<std::vector<int2>> cfl_by_group(b->maxg);
+  HList h[L_IC2P];
+  std::vector<std::vector<int>> by_group(b->maxg);
   for (int s = 0; s < b->maxb; s++) {
     if (!b->used[s]) continue;
-    const Grid &G = b->rec[s].G;
-    const Variant v = kVar[b->var[s]];
-    for (int k0 = 0; k0 < G.n[2]; k0 += v.tz)
-      for (int j0 = 0; j0 < G.n[1]; j0 += v.ty)
-        for (int i0 = 0; i0 < G.n[0]; i0 += v.tx) items[b->var[s]].push_back(make_int4(s, i0, j0, k0));
-    const long nin = interior_cells(G), ngh = ghost_total(G);
-    for (long f = 0; f < nin; f += NT) {
-      lc2p.push_back(make_int2(s, (int)f));
-      cfl_by_group[b->rec[s].group].push_back(make_int2(s, (int)f));
-    }
-    for (long f = 0; f < ngh; f += NT) lgh.push_back(make_int2(s, (int)f));
+    const gmunu_grid_desc &d = b->blk[s].desc;
+    h[b->var[s]].add(s, stage_items(d, b->var[s]));
+    h[L_C2P].add(s, cell_items(d));
+    h[L_GH].add(s, ghost_items(d));
+    by_group[b->rec[s].group].push_back(s);
   }
-  std::vector<int2> lcfl;
   std::vector<int> gfirst(b->maxg), gcount(b->maxg);
   for (int g = 0; g < b->maxg; g++) {
-    gfirst[g] = (int)lcfl.size();
-    gcount[g] = (int)cfl_by_group[g].size();
-    lcfl.insert(lcfl.end(), cfl_by_group[g].begin(), cfl_by_group[g].end());
+    gfirst[g] = (int)h[L_CFL].total;
+    for (int s : by_group[g]) h[L_CFL].add(s, cell_items(b->blk[s].desc));
+    gcount[g] = (int)(h[L_CFL].total - gfirst[g]);
   }
-  int cnt[NLIST];
   unsigned mask = 0;
-  for (int v = 0; v < NVAR; v++) {
-    if ((long)items[v].size() > b->maxi) return GMUNU_EINVAL;
-    cnt[v] = (int)items[v].size();
-    if (cnt[v]) mask |= 1u << v;
-  }
-  if ((long)lc2p.size() > b->maxi || (long)lgh.size() > b->maxi) return GMUNU_EINVAL;
-  cnt[L_C2P] = (int)lc2p.size();
-  cnt[L_GH] = (int)lgh.size();
-  cnt[L_CFL] = (int)lcfl.size();
-  bool ok = hipMemcpyAsync(b->d_rec, b->rec.data(), sizeof(BlockRec) * b->maxb, hipMemcpyHostToDevice, st) ==
-            hipSuccess;
+  for (int l = 0; l < L_IC2P; l++)
+    if (h[l].total > b->maxi) return GMUNU_EINVAL;
   for (int v = 0; v < NVAR; v++)
-    if (cnt[v])
-      ok = ok && hipMemcpyAsync(b->d_items[v], items[v].data(), sizeof(int4) * cnt[v], hipMemcpyHostToDevice, st) ==
-                     hipSuccess;
-  if (cnt[L_C2P])
-    ok = ok && hipMemcpyAsync(b->d_list[0], lc2p.data(), sizeof(int2) * cnt[L_C2P], hipMemcpyHostToDevice, st) ==
-                   hipSuccess;
-  if (cnt[L_GH])
-    ok = ok &&
-         hipMemcpyAsync(b->d_list[1], lgh.data(), sizeof(int2) * cnt[L_GH], hipMemcpyHostToDevice, st) == hipSuccess;
-  if (cnt[L_CFL])
-    ok = ok && hipMemcpyAsync(b->d_list[2], lcfl.data(), sizeof(int2) * cnt[L_CFL], hipMemcpyHostToDevice, st) ==
-                   hipSuccess;
+    if (h[v].total) mask |= 1u << v;
+  int meta[2 * L_IC2P];
+  bool ok = upload_records(b, st);
+  for (int l = 0; l < L_IC2P; l++) ok = ok && upload_list(b, l, h[l], meta + 2 * l, st);
   ok = ok && hipMemcpyAsync(b->d_gfirst, gfirst.data(), sizeof(int) * b->maxg, hipMemcpyHostToDevice, st) == hipSuccess;
   ok = ok && hipMemcpyAsync(b->d_gcount, gcount.data(), sizeof(int) * b->maxg, hipMemcpyHostToDevice, st) == hipSuccess;
-  ok = ok && hipMemcpyAsync(b->d_count, cnt, sizeof(int) * L_IC2P, hipMemcpyHostToDevice, st) == hipSuccess;
+  static const int zero = 0;
   for (auto &ts : b->time_set) {
-    ok = ok && hipMemcpyAsync(b->d_t + ts.first, &ts.second.first, sizeof(double), hipMemcpyHostToDevice, st) ==
-                   hipSuccess;
-    ok = ok && hipMemcpyAsync(b->d_tend + ts.first, &ts.second.second, sizeof(double), hipMemcpyHostToDevice, st) ==
-                   hipSuccess;
+    ok = ok && hipMemcpyAsync(b->d_t + ts.group, &ts.t, sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(b->d_tend + ts.group, &ts.t_end, sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(b->d_nstep + ts.group, &zero, sizeof(int), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok &&
+         hipMemcpyAsync(b->d_maxstep + ts.group, &ts.max_steps, sizeof(int), hipMemcpyHostToDevice, st) == hipSuccess;
   }
   ok = ok && hipStreamSynchronize(st) == hipSuccess;
   b->time_set.clear();
   if (!ok) return GMUNU_EHIP;
-  for (int l = 0; l < L_IC2P; l++) b->counts[l] = cnt[l];
+  for (int l = 0; l < L_IC2P; l++) b->counts[l] = h[l].total;
   b->var_mask = mask;
   return GMUNU_OK;
 }
@@ -503,29 +615,24 @@ int gmunu_batch_init(gmunu_batch *b, const int *slots, int nslots, void *stream)
       if (slots[k] < 0 || slots[k] >= b->maxb) return GMUNU_EINVAL;
       sel[slots[k]] = 1;
     }
-  std::vector<int2> lc, lg;
+  HList hc, hg;
   for (int s = 0; s < b->maxb; s++) {
     if (!b->used[s] || !sel[s]) continue;
-    const Grid &G = b->rec[s].G;
-    for (long f = 0; f < interior_cells(G); f += NT) lc.push_back(make_int2(s, (int)f));
-    for (long f = 0; f < ghost_total(G); f += NT) lg.push_back(make_int2(s, (int)f));
+    hc.add(s, cell_items(b->blk[s].desc));
+    hg.add(s, ghost_items(b->blk[s].desc));
   }
-  if ((long)lc.size() > b->maxi || (long)lg.size() > b->maxi) return GMUNU_EINVAL;
-  const int cnt[2] = {(int)lc.size(), (int)lg.size()};
-  bool ok = true;
-  if (cnt[0])
-    ok = hipMemcpyAsync(b->d_list[3], lc.data(), sizeof(int2) * cnt[0], hipMemcpyHostToDevice, st) == hipSuccess;
-  if (cnt[1])
-    ok = ok && hipMemcpyAsync(b->d_list[4], lg.data(), sizeof(int2) * cnt[1], hipMemcpyHostToDevice, st) == hipSuccess;
-  ok = ok && hipMemcpyAsync(b->d_count + L_IC2P, cnt, sizeof(int) * 2, hipMemcpyHostToDevice, st) == hipSuccess;
+  if (hc.total > b->maxi || hg.total > b->maxi) return GMUNU_EINVAL;
+  int meta[4];
+  bool ok = upload_records(b, st);
+  ok = ok && upload_list(b, L_IC2P, hc, meta, st) && upload_list(b, L_IGH, hg, meta + 2, st);
   ok = ok && hipStreamSynchronize(st) == hipSuccess;
   if (!ok) return GMUNU_EHIP;
   const int gsm = persist_grid(b, b->maxi, 8);
-  hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->d_list[4], b->d_count + L_IGH, b->d_dt, 1);
-  hipLaunchKernelGGL(k_bprim2con, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->d_list[3], b->d_count + L_IC2P);
-  hipLaunchKernelGGL(k_bc2p, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->d_list[3], b->d_count + L_IC2P, b->d_dt, 1, 1,
+  hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_IGH), b->d_dt, 1);
+  hipLaunchKernelGGL(k_bprim2con, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_IC2P));
+  hipLaunchKernelGGL(k_bc2p, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_IC2P), b->d_dt, 1, 1,
                      (unsigned int *)nullptr);
-  hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->d_list[4], b->d_count + L_IGH, b->d_dt, 1);
+  hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_IGH), b->d_dt, 1);
   return launch_status();
 }
 
@@ -536,40 +643,33 @@ int gmunu_batch_autotune(gmunu_batch *b, void *stream) {
   for (int s = 0; s < b->maxb; s++)
     if (b->used[s]) buckets[bucket_of(b->blk[s].desc)].push_back(s);
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return GMUNU_EHIP;
-  const std::vector<int> saved = b->var;
-  int rc = GMUNU_OK;
+  if (hipEventCreate(&e0) != hipSuccess) return GMUNU_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return GMUNU_EHIP;
+  }
+  int rc = upload_records(b, st) ? GMUNU_OK : GMUNU_EHIP;
+  const int gst = b->ncu * 4;
   for (auto &bk : buckets) {
+    if (rc) break;
     const int nd = std::get<0>(bk.first);
     int best = -1;
     float best_ms = 0.f;
     for (int v = 0; v < NVAR; v++) {
       if (kVar[v].nd != nd) continue;
-      // only this bucket's blocks, all on variant v
-      for (int s = 0; s < b->maxb; s++)
-        if (b->used[s]) b->var[s] = -2;
-      for (int s : bk.second) b->var[s] = v;
-      std::vector<int4> items;
-      for (int s : bk.second) {
-        const Grid &G = b->rec[s].G;
-        for (int k0 = 0; k0 < G.n[2]; k0 += kVar[v].tz)
-          for (int j0 = 0; j0 < G.n[1]; j0 += kVar[v].ty)
-            for (int i0 = 0; i0 < G.n[0]; i0 += kVar[v].tx) items.push_back(make_int4(s, i0, j0, k0));
-      }
-      if ((long)items.size() > b->maxi) continue;
-      const int n = (int)items.size();
-      if (hipMemcpyAsync(b->d_items[v], items.data(), sizeof(int4) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
-          hipMemcpyAsync(b->d_count + v, &n, sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
-          hipMemcpyAsync(b->d_rec, b->rec.data(), sizeof(BlockRec) * b->maxb, hipMemcpyHostToDevice, st) !=
-              hipSuccess) {
+      // only this bucket's blocks, all on variant v, in list v (MODE 0
+      // writes the right-hand side into q_s, which is scratch)
+      HList h;
+      for (int s : bk.second) h.add(s, stage_items(b->blk[s].desc, v));
+      if (h.total > b->maxi) continue;
+      int meta[2];
+      if (!upload_list(b, v, h, meta, st) || hipStreamSynchronize(st) != hipSuccess) {
         rc = GMUNU_EHIP;
         break;
       }
-      const int gst = b->ncu * 4;
-      launch_variant_any<0>(v, b->d_rec, b->d_items[v], b->d_count + v, b->d_dt, 0.0, 1.0, 0, gst, st);  // warm-up
+      launch_variant_any<0>(v, b->d_rec, b->list(v), b->d_dt, 0.0, 1.0, 0, gst, st);  // warm-up
       (void)hipEventRecord(e0, st);
-      for (int r = 0; r < 3; r++)
-        launch_variant_any<0>(v, b->d_rec, b->d_items[v], b->d_count + v, b->d_dt, 0.0, 1.0, 0, gst, st);
+      for (int r = 0; r < 3; r++) launch_variant_any<0>(v, b->d_rec, b->list(v), b->d_dt, 0.0, 1.0, 0, gst, st);
       (void)hipEventRecord(e1, st);
       if (hipEventSynchronize(e1) != hipSuccess) {
         rc = GMUNU_EHIP;
@@ -582,19 +682,18 @@ int gmunu_batch_autotune(gmunu_batch *b, void *stream) {
         best_ms = ms;
       }
     }
-    if (rc) break;
     if (best >= 0) b->tuned[bk.first] = best;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  b->var = saved;
-  if (rc) return rc;
   for (int s = 0; s < b->maxb; s++)
     if (b->used[s]) {
       auto it = b->tuned.find(bucket_of(b->blk[s].desc));
       if (it != b->tuned.end()) b->var[s] = it->second;
     }
-  return gmunu_batch_commit(b, stream);
+  // restore every list from the (re-chosen) variants, also after a failure
+  const int rc2 = gmunu_batch_commit(b, stream);
+  return rc ? rc : rc2;
 }
 
 int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int use_graph, void *stream) {
@@ -630,13 +729,15 @@ int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int u
   return ok ? GMUNU_OK : GMUNU_EHIP;
 }
 
-int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, void *stream) {
+int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, int *nstep_host, void *stream) {
   if (!b) return GMUNU_ENULL;
   hipStream_t st = as_stream(stream);
   bool ok = true;
   if (t_host) ok = hipMemcpyAsync(t_host, b->d_t, sizeof(double) * b->maxg, hipMemcpyDeviceToHost, st) == hipSuccess;
   if (dt_host)
     ok = ok && hipMemcpyAsync(dt_host, b->d_dt, sizeof(double) * b->maxg, hipMemcpyDeviceToHost, st) == hipSuccess;
+  if (nstep_host)
+    ok = ok && hipMemcpyAsync(nstep_host, b->d_nstep, sizeof(int) * b->maxg, hipMemcpyDeviceToHost, st) == hipSuccess;
   ok = ok && hipStreamSynchronize(st) == hipSuccess;
   return ok ? GMUNU_OK : GMUNU_EHIP;
 }

@@ -72,19 +72,23 @@ __device__ __forceinline__ void xcd_tile(const Grid &G, int TX, int TY, int TZ, 
 }
 
 // MODE 0: dqdt = L(prim).  MODE 1: q_out = ca q_n + cb (q_s + dt L(prim)).
+// skipp (nullable): nothing is done when *skipp == 0 (a step past t_end).
 template <int TX, int TY, int TZ, int ND, int MODE>
 __global__ __launch_bounds__(TX *TY *TZ, 3) void k_stage(const Grid G, const double *__restrict__ prim,
                                                          const double *__restrict__ met, const double *qn,
                                                          const double *qs, double *out,
-                                                         const double *__restrict__ dtp, double ca, double cb) {
+                                                         const double *__restrict__ dtp, double ca, double cb,
+                                                         const double *__restrict__ skipp) {
   __shared__ double sF[NV * max_faces<TX, TY, TZ, ND>()];
+  if (skipp && *skipp == 0.0) return;
   int bx, by, bz;
   xcd_tile(G, TX, TY, TZ, bx, by, bz);
   stage_tile<TX, TY, TZ, ND, MODE>(G, bx * TX, by * TY, bz * TZ, prim, met, qn, qs, out, dtp, ca, cb, sF);
 }
 
 __global__ __launch_bounds__(NT) void k_c2p(const Grid G, double *q, const double *__restrict__ met, double *prim,
-                                            uint8_t *flags, unsigned int *nfatal) {
+                                            uint8_t *flags, unsigned int *nfatal, const double *__restrict__ skipp) {
+  if (skipp && *skipp == 0.0) return;
   const long t = (long)blockIdx.x * NT + threadIdx.x;
   if (t < interior_count(G)) c2p_one(G, q, met, prim, flags, nfatal, t);
 }
@@ -95,7 +99,9 @@ __global__ __launch_bounds__(NT) void k_prim2con(const Grid G, const double *__r
   if (c < G.nv) prim2con_one(G, prim, met, q, c);
 }
 
-__global__ __launch_bounds__(NT) void k_ghosts(const Grid G, double *prim, long total) {
+__global__ __launch_bounds__(NT) void k_ghosts(const Grid G, double *prim, long total,
+                                               const double *__restrict__ skipp) {
+  if (skipp && *skipp == 0.0) return;
   const long t = (long)blockIdx.x * NT + threadIdx.x;
   if (t < total) ghost_one(G, prim, t);
 }
@@ -125,22 +131,69 @@ __global__ void k_advance(double *tp, const double *dtp) { *tp += *dtp; }
 
 template <int TX, int TY, int TZ, int ND, int MODE>
 void launch_stage_t(const gmunu_ctx *ctx, const double *prim, const double *met, const double *qn,
-                    const double *qs, double *out, const double *dtp, double ca, double cb, hipStream_t st) {
+                    const double *qs, double *out, const double *dtp, double ca, double cb, const double *skipp,
+                    hipStream_t st) {
   const Grid &G = ctx->G;
   dim3 grid(((G.n[0] + TX - 1) / TX) * ((G.n[1] + TY - 1) / TY) * ((G.n[2] + TZ - 1) / TZ));
   hipLaunchKernelGGL((k_stage<TX, TY, TZ, ND, MODE>), grid, dim3(TX * TY * TZ), 0, st, G, prim, met, qn, qs, out,
-                     dtp, ca, cb);
+                     dtp, ca, cb, skipp);
 }
 
 template <int MODE>
 void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, const double *qn,
-                  const double *qs, double *out, const double *dtp, double ca, double cb, hipStream_t st) {
+                  const double *qs, double *out, const double *dtp, double ca, double cb, const double *skipp,
+                  hipStream_t st) {
   if (ctx->G.ndim == 1)
-    launch_stage_t<256, 1, 1, 1, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, st);
+    launch_stage_t<256, 1, 1, 1, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);
   else if (ctx->G.ndim == 2)
-    launch_stage_t<32, 8, 1, 2, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, st);
+    launch_stage_t<32, 8, 1, 2, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);
   else
-    launch_stage_t<16, 4, 4, 3, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, st);
+    launch_stage_t<16, 4, 4, 3, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);
+}
+
+int launch_c2p(gmunu_ctx *ctx, double *q, const double *metric, double *prim, uint8_t *flags,
+               unsigned int *nfatal_dev, const double *skipp, hipStream_t st) {
+  ProfScope ps(ctx, st, GMUNU_K_C2P);
+  hipLaunchKernelGGL(k_c2p, dim3(nblocks(interior_cells(ctx->G))), dim3(NT), 0, st, ctx->G, q, metric, prim, flags,
+                     nfatal_dev, skipp);
+  return launch_status();
+}
+
+int launch_ghosts(gmunu_ctx *ctx, double *prim, const double *skipp, hipStream_t st) {
+  const long tot = ghost_total(ctx->G);
+  if (tot == 0) return GMUNU_OK;
+  ProfScope ps(ctx, st, GMUNU_K_GHOSTS);
+  hipLaunchKernelGGL(k_ghosts, dim3(nblocks(tot)), dim3(NT), 0, st, ctx->G, prim, tot, skipp);
+  return launch_status();
+}
+
+// One RK stage; with skipp non-null nothing is changed when *skipp == 0.
+int rk_stage_impl(gmunu_ctx *ctx, int stage, const double *dt_dev, const double *q_n, const double *q_s,
+                  double *q_out, const double *prim_in, double *prim_out, const double *metric, uint8_t *flags,
+                  unsigned int *nfatal_dev, const double *skipp, hipStream_t st) {
+  const int nst = ctx->d.rk;
+  double ca = 0.0, cb = 1.0;
+  if (stage > 0) {
+    if (nst == 2) {
+      ca = 0.5;
+      cb = 0.5;
+    } else if (stage == 1) {
+      ca = 0.75;
+      cb = 0.25;
+    } else {
+      ca = 1.0 / 3.0;
+      cb = 2.0 / 3.0;
+    }
+  }
+  {
+    ProfScope ps(ctx, st, GMUNU_K_STAGE);
+    launch_stage<1>(ctx, prim_in, metric, q_n, q_s, q_out, dt_dev, ca, cb, skipp, st);
+  }
+  int rc = launch_status();
+  if (rc) return rc;
+  rc = launch_c2p(ctx, q_out, metric, prim_out, flags, nfatal_dev, skipp, st);
+  if (rc) return rc;
+  return launch_ghosts(ctx, prim_out, skipp, st);
 }
 
 }  // namespace
@@ -209,20 +262,13 @@ int gmunu_c2p(gmunu_ctx *ctx, double *q, const double *metric, double *prim, uin
               unsigned int *nfatal_dev, void *stream) {
   if (!ctx || !q || !metric || !prim) return GMUNU_ENULL;
   if (!aligned8(prim) || !aligned8(metric) || !aligned8(q)) return GMUNU_EALIGN;
-  ProfScope ps(ctx, as_stream(stream), GMUNU_K_C2P);
-  hipLaunchKernelGGL(k_c2p, dim3(nblocks(interior_cells(ctx->G))), dim3(NT), 0, as_stream(stream), ctx->G, q, metric, prim,
-                     flags, nfatal_dev);
-  return launch_status();
+  return launch_c2p(ctx, q, metric, prim, flags, nfatal_dev, nullptr, as_stream(stream));
 }
 
 int gmunu_fill_ghosts(gmunu_ctx *ctx, double *prim, void *stream) {
   if (!ctx || !prim) return GMUNU_ENULL;
   if (!aligned8(prim)) return GMUNU_EALIGN;
-  const long tot = ghost_total(ctx->G);
-  if (tot == 0) return GMUNU_OK;
-  ProfScope ps(ctx, as_stream(stream), GMUNU_K_GHOSTS);
-  hipLaunchKernelGGL(k_ghosts, dim3(nblocks(tot)), dim3(NT), 0, as_stream(stream), ctx->G, prim, tot);
-  return launch_status();
+  return launch_ghosts(ctx, prim, nullptr, as_stream(stream));
 }
 
 int gmunu_rhs(gmunu_ctx *ctx, const double *prim, const double *metric, double *dqdt, void *stream) {
@@ -230,7 +276,7 @@ int gmunu_rhs(gmunu_ctx *ctx, const double *prim, const double *metric, double *
   if (!aligned8(prim) || !aligned8(metric) || !aligned8(dqdt)) return GMUNU_EALIGN;
   {
     ProfScope ps(ctx, as_stream(stream), GMUNU_K_STAGE);
-    launch_stage<0>(ctx, prim, metric, nullptr, nullptr, dqdt, nullptr, 0.0, 0.0, as_stream(stream));
+    launch_stage<0>(ctx, prim, metric, nullptr, nullptr, dqdt, nullptr, 0.0, 0.0, nullptr, as_stream(stream));
   }
   return launch_status();
 }
@@ -258,31 +304,9 @@ int gmunu_rk_stage(gmunu_ctx *ctx, int stage, const double *dt_dev, const double
                    unsigned int *nfatal_dev, void *stream) {
   if (!ctx || !dt_dev || !q_n || !q_out || !prim_in || !prim_out || !metric) return GMUNU_ENULL;
   if (stage > 0 && !q_s) return GMUNU_ENULL;
-  const int nst = ctx->d.rk;
-  if (stage < 0 || stage >= nst) return GMUNU_EINVAL;
-  double ca = 0.0, cb = 1.0;
-  if (stage > 0) {
-    if (nst == 2) {
-      ca = 0.5;
-      cb = 0.5;
-    } else if (stage == 1) {
-      ca = 0.75;
-      cb = 0.25;
-    } else {
-      ca = 1.0 / 3.0;
-      cb = 2.0 / 3.0;
-    }
-  }
-  hipStream_t st = as_stream(stream);
-  {
-    ProfScope ps(ctx, st, GMUNU_K_STAGE);
-    launch_stage<1>(ctx, prim_in, metric, q_n, q_s, q_out, dt_dev, ca, cb, st);
-  }
-  int rc = launch_status();
-  if (rc) return rc;
-  rc = gmunu_c2p(ctx, q_out, metric, prim_out, flags, nfatal_dev, stream);
-  if (rc) return rc;
-  return gmunu_fill_ghosts(ctx, prim_out, stream);
+  if (stage < 0 || stage >= ctx->d.rk) return GMUNU_EINVAL;
+  return rk_stage_impl(ctx, stage, dt_dev, q_n, q_s, q_out, prim_in, prim_out, metric, flags, nfatal_dev, nullptr,
+                       as_stream(stream));
 }
 
 int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, double cfl,
@@ -294,7 +318,8 @@ int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const dou
   const int nst = ctx->d.rk;
   for (int s = 0; s < nst; s++) {
     double *out = (s == nst - 1) ? q_n : q_s;
-    rc = gmunu_rk_stage(ctx, s, dt_dev, q_n, q_s, out, prim, prim, metric, flags, nfatal_dev, stream);
+    rc = rk_stage_impl(ctx, s, dt_dev, q_n, q_s, out, prim, prim, metric, flags, nfatal_dev, dt_dev,
+                       as_stream(stream));
     if (rc) return rc;
   }
   {

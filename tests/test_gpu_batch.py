@@ -192,3 +192,54 @@ def test_slots_change_between_graph_replays():
         pb, prb, metb = blast_like_blocks()[slot]
         qa, _, _ = alone(pb, prb, metb, 3)
         assert np.array_equal(W.interior(pb, qa), W.interior(pb, views[slot][0].cpu().numpy()))
+
+
+def test_group_limits_and_steps_past_the_end():
+    # group 0 stops after 2 steps, group 1 at t = 0.01 (a few steps of the 1D
+    # tube), group 2 after 1 step; further steps leave each group untouched
+    blocks = blast_like_blocks()
+    blocks = [blocks[1], blocks[0], blocks[2]]
+    B2, views2, _ = make_batch(blocks, [0, 1, 2])
+    B2.set_group(0, 0.0, 1e30, max_steps=2)
+    B2.set_group(1, 0.0, 0.01)
+    B2.set_group(2, 0.0, 1e30, max_steps=1)
+    B2.commit()
+    for _ in range(12):
+        B2.step(0.4)
+    torch.cuda.synchronize()
+    t, dt, ns = B2.times(with_steps=True)
+    note(f"  steps {ns[:3].tolist()} t {t[:3].tolist()}")
+    assert ns[0] == 2 and ns[2] == 1 and 2 < ns[1] < 12
+    assert t[1] == 0.01 and dt[1] == 0.0
+    for slot, nst, t_end in ((0, 2, 1e30), (1, 12, 0.01), (2, 1, 1e30)):
+        p, pr, met = blocks[slot]
+        qa, pa, ta = alone(p, pr, met, nst, t_end=t_end)
+        assert t[slot] == ta
+        assert np.array_equal(W.interior(p, qa), W.interior(p, views2[slot][0].cpu().numpy())), slot
+        assert np.array_equal(pa, views2[slot][1].cpu().numpy()), slot
+
+
+def test_single_grid_step_past_end_changes_nothing():
+    p, pr, met = W.mhd_shock_tube(64)
+    g = gmu.Grid(p)
+    prd, metd = torch.from_numpy(pr.copy()).cuda(), torch.from_numpy(met).cuda()
+    g.fill_ghosts(prd)
+    qn = g.prim2con(prd, metd)
+    g.c2p(qn, metd, prd)
+    g.fill_ghosts(prd)
+    qs = torch.zeros_like(qn)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt = torch.zeros_like(t)
+    t_end = 0.05
+    for _ in range(200):
+        g.step(qn, qs, prd, metd, 0.4, t_end, t, dt)
+        if float(t.item()) >= t_end:
+            break
+    assert float(t.item()) == t_end
+    snap = [x.clone() for x in (qn, qs, prd, t)]
+    for _ in range(3):
+        g.step(qn, qs, prd, metd, 0.4, t_end, t, dt)
+    torch.cuda.synchronize()
+    assert float(dt.item()) == 0.0
+    for a, b in zip(snap, (qn, qs, prd, t)):
+        assert torch.equal(a, b)
