@@ -73,7 +73,10 @@ enum {
   GMUNU_ENULL = -2,   /* required pointer is NULL */
   GMUNU_EALIGN = -3,  /* pointer not 8-byte aligned */
   GMUNU_EHIP = -4,    /* a HIP runtime call failed */
-  GMUNU_ENOMEM = -5   /* device allocation at create time failed */
+  GMUNU_ENOMEM = -5,  /* device allocation at create time failed */
+  GMUNU_ESTALL = -6,  /* a served solve stopped advancing (dt not positive
+                         before its end, e.g. a non-finite wave speed) */
+  GMUNU_ESTOP = -7    /* the server has stopped (after a HIP error) */
 };
 
 /* Grid and physics description (host struct, copied at create). */
@@ -207,11 +210,14 @@ int gmunu_batch_autotune(gmunu_batch *b, void *stream);
 int gmunu_batch_init(gmunu_batch *b, const int *slots, int nslots, void *stream);
 /* One step for every group with dt > 0: dt per group (section 2.9), the RK
  * stages (q_n <- q^{n+1}, q_s scratch, prim consistent, ghosts filled),
- * t += dt.  use_graph != 0: capture once (per cfl value) and replay. */
+ * t += dt, step count += 1.  use_graph != 0: capture once and replay
+ * (captured again when cfl, nfatal_dev or a new tile shape appears). */
 int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int use_graph, void *stream);
-/* Copy the groups' t, last dt and step counts to host arrays of max_groups
- * entries (each nullable); synchronises `stream`. */
-int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, int *nstep_host, void *stream);
+/* Copy the groups' t, last dt, step counts and fatal-recovery counts (cells
+ * flagged FATAL_* summed over stages since the group's set_group) to host
+ * arrays of max_groups entries (each nullable); synchronises `stream`. */
+int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, int *nstep_host, unsigned int *nfatal_host,
+                      void *stream);
 /* Number of committed items per list: [stage, c2p, ghosts]; tile variant
  * chosen per block (out_variant[slot], -1 for empty slots). */
 int gmunu_batch_info(gmunu_batch *b, long *items_out, int *out_variant);
@@ -225,6 +231,77 @@ int gmunu_batch_info(gmunu_batch *b, long *items_out, int *out_variant);
 enum { GMUNU_K_STAGE = 0, GMUNU_K_C2P = 1, GMUNU_K_GHOSTS = 2, GMUNU_K_CFL = 3, GMUNU_K_OTHER = 4, GMUNU_NK = 5 };
 int gmunu_profile(gmunu_ctx *ctx, int enable, int max_launches);
 int gmunu_profile_read(gmunu_ctx *ctx, double *ms_out /* [GMUNU_NK] */, long *count_out /* [GMUNU_NK] */);
+
+/* ------------------------------------------------------------------------
+ * Request server: continuous batching of independent solves on one GPU.
+ *
+ * Callers submit solves (a grid, initial primitives and metric, an end time
+ * and/or a step count) from any thread.  A worker thread admits them in
+ * arrival order as soon as a slot and a contiguous range of the server's
+ * device arena (its HBM budget, allocated once at create) are free, uploads
+ * the initial data on a copy stream while the GPU keeps stepping the
+ * resident solves, adds the solve to a gmunu_batch (one per integrator,
+ * each solve its own group with its own dt), and replays the captured batch
+ * step `steps_per_sync` times between checks.  A solve that reaches its end
+ * is copied out (copy stream), removed from the batch and its memory
+ * returned; its result is then available to gmunu_server_poll.  Each solve
+ * is advanced by exactly the arithmetic of gmunu_step on its own grid, so a
+ * served result equals the same solve advanced alone, bit for bit.  This
+ * serving layer is not part of the paper; its numerics are the batch's.
+ * ------------------------------------------------------------------------ */
+typedef struct gmunu_server gmunu_server;
+
+typedef struct gmunu_request {
+  gmunu_grid_desc desc;  /* the solve's grid (validated at submit) */
+  const double *prim;    /* initial primitives [8][layout of desc]; host or
+                            device memory; ghost values are not used */
+  const double *metric;  /* metric [5][layout], ghosts filled; host or device */
+  double t_end;          /* the solve ends when t reaches t_end ... */
+  int max_steps;         /* ... or after max_steps steps (<= 0: no limit) */
+  double *q_out;         /* nullable, host or device: final q [8][layout]
+                            (interior cells meaningful) */
+  double *prim_out;      /* nullable, host or device: final primitives [8][layout]
+                            with ghosts filled */
+  unsigned long long tag; /* caller's label, returned in the result */
+} gmunu_request;
+/* prim and metric must stay valid and unchanged until the request's result
+ * has been polled; q_out / prim_out are written before the result appears. */
+
+typedef struct gmunu_result {
+  unsigned long long id, tag;
+  int status;     /* GMUNU_OK, GMUNU_ESTALL or GMUNU_ESTOP */
+  int steps;      /* steps taken */
+  unsigned int nfatal; /* fatal recoveries (cells x stages) during the solve */
+  double t;       /* final time */
+  double t_submit, t_admit, t_done; /* gmunu_server_clock(): submitted;
+                                       memory granted (upload starts);
+                                       outputs written */
+  size_t bytes;   /* device footprint (q_n, q_s, prim, metric) */
+} gmunu_result;
+
+typedef struct gmunu_server_info {
+  long submitted, admitted, completed, pending, resident;
+  long replays;        /* batched steps issued */
+  size_t pool_bytes, pool_used, pool_peak;
+  double busy_s;       /* worker time with at least one solve resident */
+} gmunu_server_info;
+
+/* Monotonic clock of the server, in seconds. */
+double gmunu_server_clock(void);
+/* hbm_bytes: arena for solve state (q_n, q_s, prim: 8 doubles per cell each,
+ * metric 5; 232 bytes per cell with ghosts); max_slots: solves resident at
+ * once; cfl: Courant number of every solve; steps_per_sync >= 1: replays
+ * between completion checks.  Starts the worker on the current device. */
+int gmunu_server_create(size_t hbm_bytes, int max_slots, double cfl, int steps_per_sync, gmunu_server **out);
+/* Queue a solve (non-blocking).  GMUNU_EINVAL if the descriptor is invalid
+ * or the solve can never fit the arena; GMUNU_ESTOP after a worker error. */
+int gmunu_server_submit(gmunu_server *s, const gmunu_request *req, unsigned long long *id_out);
+/* Move up to `max` finished results into out; waits up to timeout_ms for the
+ * first one if none is ready.  Returns the number moved (>= 0) or an error. */
+int gmunu_server_poll(gmunu_server *s, gmunu_result *out, int max, int timeout_ms);
+int gmunu_server_status(gmunu_server *s, gmunu_server_info *out);
+/* Stop the worker (solves not finished are dropped) and free everything. */
+int gmunu_server_destroy(gmunu_server *s);
 
 #ifdef __cplusplus
 }

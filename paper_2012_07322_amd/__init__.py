@@ -22,7 +22,7 @@ FLAG_ATMO, FLAG_EPS_CLAMP, FLAG_V_CLAMP = 1, 2, 4
 FLAG_FATAL_RHO, FLAG_FATAL_EPS, FLAG_FATAL_V, FLAG_NOCONV = 8, 16, 32, 64
 
 ERRORS = {-1: "invalid argument", -2: "null pointer", -3: "misaligned pointer", -4: "HIP error",
-          -5: "out of device memory"}
+          -5: "out of device memory", -6: "solve stalled", -7: "server stopped"}
 
 
 class GridDesc(ctypes.Structure):
@@ -204,6 +204,39 @@ class Grid:
                                 _ptr(t_dev, "t"), _ptr(dt_dev, "dt"), fp, npn, _stream()), "gmunu_step")
 
 
+    def run(self, prim, metric, cfl, t_end=1e30, max_steps=0, check_every=16):
+        """Advance one solve on its own (one launch sequence per step):
+        ghosts of prim filled, q_n from prim, prim recovered, then gmunu_step
+        until t reaches t_end or max_steps steps were taken (steps past t_end
+        change nothing, so t is checked every `check_every` steps).  prim is
+        updated in place; returns (q_n, q_s, t)."""
+        if max_steps <= 0 and not (t_end < 1e300):
+            raise ValueError("run needs a finite t_end or a step limit")
+        self.fill_ghosts(prim)
+        qn = self.prim2con(prim, metric)
+        self.c2p(qn, metric, prim)
+        self.fill_ghosts(prim)
+        qs = torch.zeros_like(qn)
+        t = torch.zeros(1, dtype=torch.float64, device=prim.device)
+        dt = torch.zeros_like(t)
+        L, st = lib(), _stream()
+        args = (self._h, _ptr(qn, "q_n"), _ptr(qs, "q_s"), _ptr(prim, "prim"), self._chk(metric, 5, "metric"))
+        tp, dtp = _ptr(t, "t"), _ptr(dt, "dt")
+        done = 0
+        while True:
+            k = max_steps - done if max_steps > 0 else check_every
+            if max_steps > 0 and t_end < 1e300:
+                k = min(k, check_every)
+            for _ in range(k):
+                _check(L.gmunu_step(*args, cfl, t_end, tp, dtp, None, None, st), "gmunu_step")
+            done += k
+            if max_steps > 0 and done >= max_steps:
+                break
+            if float(t.item()) >= t_end:
+                break
+        return qn, qs, float(t.item())
+
+
 # ------------------------------------------------------------------- batch
 
 class BlockSpec(ctypes.Structure):
@@ -223,7 +256,7 @@ def _batch_sigs(L):
     L.gmunu_batch_autotune.argtypes = [_P, _P]
     L.gmunu_batch_init.argtypes = [_P, _P, I, _P]
     L.gmunu_batch_step.argtypes = [_P, D, _P, I, _P]
-    L.gmunu_batch_times.argtypes = [_P, _P, _P, _P, _P]
+    L.gmunu_batch_times.argtypes = [_P, _P, _P, _P, _P, _P]
     L.gmunu_batch_info.argtypes = [_P, _P, _P]
 
 
@@ -324,13 +357,16 @@ class Batch:
         _check(lib().gmunu_batch_step(self._h, cfl, npn, 1 if use_graph else 0, _stream()), "gmunu_batch_step")
 
     def times(self, with_steps=False):
+        """(t, dt) per group; with_steps: (t, dt, steps, fatal recoveries)."""
         import numpy as np
         t = np.zeros(self.max_groups)
         dt = np.zeros(self.max_groups)
         ns = np.zeros(self.max_groups, dtype=np.int32)
+        nf = np.zeros(self.max_groups, dtype=np.uint32)
         _check(lib().gmunu_batch_times(self._h, t.ctypes.data_as(_P), dt.ctypes.data_as(_P),
-                                       ns.ctypes.data_as(_P), _stream()), "gmunu_batch_times")
-        return (t, dt, ns) if with_steps else (t, dt)
+                                       ns.ctypes.data_as(_P), nf.ctypes.data_as(_P), _stream()),
+               "gmunu_batch_times")
+        return (t, dt, ns, nf) if with_steps else (t, dt)
 
     def info(self):
         import numpy as np
@@ -338,3 +374,138 @@ class Batch:
         var = np.zeros(self.max_blocks, dtype=np.int32)
         _check(lib().gmunu_batch_info(self._h, items.ctypes.data_as(_P), var.ctypes.data_as(_P)), "gmunu_batch_info")
         return items, var
+
+
+# ------------------------------------------------------------------ server
+
+class RequestSpec(ctypes.Structure):
+    """Mirror of gmunu_request."""
+    _fields_ = [("desc", GridDesc), ("prim", _P), ("metric", _P), ("t_end", ctypes.c_double),
+                ("max_steps", ctypes.c_int), ("q_out", _P), ("prim_out", _P), ("tag", ctypes.c_ulonglong)]
+
+
+class Result(ctypes.Structure):
+    """Mirror of gmunu_result."""
+    _fields_ = [("id", ctypes.c_ulonglong), ("tag", ctypes.c_ulonglong), ("status", ctypes.c_int),
+                ("steps", ctypes.c_int), ("nfatal", ctypes.c_uint), ("t", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("bytes", ctypes.c_size_t)]
+
+
+class ServerInfo(ctypes.Structure):
+    """Mirror of gmunu_server_info."""
+    _fields_ = [("submitted", ctypes.c_long), ("admitted", ctypes.c_long), ("completed", ctypes.c_long),
+                ("pending", ctypes.c_long), ("resident", ctypes.c_long), ("replays", ctypes.c_long),
+                ("pool_bytes", ctypes.c_size_t), ("pool_used", ctypes.c_size_t), ("pool_peak", ctypes.c_size_t),
+                ("busy_s", ctypes.c_double)]
+
+
+def _server_sigs(L):
+    I = ctypes.c_int
+    L.gmunu_server_clock.argtypes = []
+    L.gmunu_server_clock.restype = ctypes.c_double
+    L.gmunu_server_create.argtypes = [ctypes.c_size_t, I, ctypes.c_double, I, ctypes.POINTER(_P)]
+    L.gmunu_server_submit.argtypes = [_P, ctypes.POINTER(RequestSpec), ctypes.POINTER(ctypes.c_ulonglong)]
+    L.gmunu_server_poll.argtypes = [_P, ctypes.POINTER(Result), I, I]
+    L.gmunu_server_status.argtypes = [_P, ctypes.POINTER(ServerInfo)]
+    L.gmunu_server_destroy.argtypes = [_P]
+
+
+def _addr(a, what, nvars, shape):
+    """Address of a float64 C-contiguous numpy array or torch tensor (host
+    or device) of shape (nvars,) + shape; None passes through."""
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        if a.dtype != torch.float64 or not a.is_contiguous():
+            raise TypeError(f"{what} must be a contiguous float64 tensor")
+        got = tuple(a.shape)
+        ptr = a.data_ptr()
+    else:
+        import numpy as np
+        if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags["C_CONTIGUOUS"]:
+            raise TypeError(f"{what} must be a C-contiguous float64 array")
+        got = a.shape
+        ptr = a.ctypes.data
+    if got != (nvars,) + tuple(shape):
+        raise ValueError(f"{what} has shape {got}, expected {(nvars,) + tuple(shape)}")
+    return ctypes.c_void_p(ptr)
+
+
+class Server:
+    """Continuous-batching request server (gmunu_server_*): solves of any
+    size share the GPU through one batched, graph-replayed step; each is
+    admitted when its state fits the HBM budget."""
+
+    def __init__(self, hbm_bytes, max_slots=256, cfl=0.4, steps_per_sync=2):
+        L = lib()
+        if not hasattr(L, "_batch_sigs_set"):
+            _batch_sigs(L)
+            L._batch_sigs_set = True
+        if not hasattr(L, "_server_sigs_set"):
+            _server_sigs(L)
+            L._server_sigs_set = True
+        h = _P()
+        _check(L.gmunu_server_create(int(hbm_bytes), max_slots, cfl, steps_per_sync, ctypes.byref(h)),
+               "gmunu_server_create")
+        self._h = h
+        self._keep = {}
+
+    @staticmethod
+    def clock():
+        L = lib()
+        if not hasattr(L, "_server_sigs_set"):
+            _server_sigs(L)
+            L._server_sigs_set = True
+        return L.gmunu_server_clock()
+
+    def submit(self, params, prim, metric, t_end=1e30, max_steps=0, q_out=None, prim_out=None, tag=0):
+        """Queue one solve; prim / metric / outputs are numpy arrays or torch
+        tensors (host or device) in the grid's layout.  Device inputs must be
+        complete on the device: the current stream is synchronised first."""
+        shp = state_shape(params)
+        spec = RequestSpec()
+        spec.desc = make_desc(params)
+        spec.prim = _addr(prim, "prim", 8, shp)
+        spec.metric = _addr(metric, "metric", 5, shp)
+        spec.t_end = float(t_end)
+        spec.max_steps = int(max_steps)
+        spec.q_out = _addr(q_out, "q_out", 8, shp)
+        spec.prim_out = _addr(prim_out, "prim_out", 8, shp)
+        spec.tag = int(tag)
+        if any(isinstance(x, torch.Tensor) and x.is_cuda for x in (prim, metric, q_out, prim_out)):
+            torch.cuda.current_stream().synchronize()
+        rid = ctypes.c_ulonglong()
+        _check(lib().gmunu_server_submit(self._h, ctypes.byref(spec), ctypes.byref(rid)), "gmunu_server_submit")
+        self._keep[rid.value] = (prim, metric, q_out, prim_out)
+        return rid.value
+
+    def poll(self, max_results=256, timeout_ms=0):
+        buf = (Result * max_results)()
+        n = lib().gmunu_server_poll(self._h, buf, max_results, int(timeout_ms))
+        _check(n if n < 0 else 0, "gmunu_server_poll")
+        out = []
+        for k in range(n):
+            r = buf[k]
+            self._keep.pop(r.id, None)
+            out.append({f: getattr(r, f) for f, _ in Result._fields_})
+        return out
+
+    def status(self):
+        info = ServerInfo()
+        rc = lib().gmunu_server_status(self._h, ctypes.byref(info))
+        d = {f: getattr(info, f) for f, _ in ServerInfo._fields_}
+        d["error"] = rc
+        return d
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gmunu_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

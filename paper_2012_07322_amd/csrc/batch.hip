@@ -115,7 +115,7 @@ __global__ __launch_bounds__(TX *TY *TZ, 3) void k_bstage(const BlockRec *__rest
 
 // Recovery on 256-cell items: from q_n (use_qn) or q_s.  force: ignore dt.
 __global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, DList L, const double *dts, int use_qn,
-                                             int force, unsigned int *nfatal) {
+                                             int force, unsigned int *nfatal, unsigned int *gfatal) {
   const int nent = L.meta[0], n = L.meta[1];
   int e = -1;
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
@@ -123,7 +123,8 @@ __global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, DLi
     const BlockRec &b = B[L.blk[e]];
     if (!force && dts[b.group] == 0.0) continue;
     const long t = (long)(it - L.start[e]) * NT + threadIdx.x;
-    if (t < interior_count(b.G)) c2p_one(b.G, use_qn ? b.qn : b.qs, b.met, b.prim, b.flags, nfatal, t);
+    if (t < interior_count(b.G))
+      c2p_one(b.G, use_qn ? b.qn : b.qs, b.met, b.prim, b.flags, nfatal, t, gfatal ? gfatal + b.group : nullptr);
   }
 }
 
@@ -281,6 +282,7 @@ struct gmunu_batch {
   int *d_gfirst, *d_gcount;
   double *d_part, *d_t, *d_dt, *d_tend;
   int *d_nstep, *d_maxstep;
+  unsigned int *d_gfatal;  // fatal recoveries per group since its set_group
   // captured step, replayed on a private stream ordered against the
   // caller's stream by events (capture is not possible on the null stream)
   hipStream_t pstream;
@@ -324,6 +326,7 @@ void free_batch(gmunu_batch *b) {
   (void)hipFree(b->d_tend);
   (void)hipFree(b->d_nstep);
   (void)hipFree(b->d_maxstep);
+  (void)hipFree(b->d_gfatal);
   delete b;
 }
 
@@ -358,8 +361,9 @@ int persist_grid(const gmunu_batch *b, long items, int per_cu) {
   return (int)std::max(1L, std::min(g, std::max(items, 1L)));
 }
 
-// Enqueue one full step (cfl, stages, advance) on st.
-int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, hipStream_t st) {
+// Enqueue one full step (cfl, stages, advance) on st, with the stage
+// kernels of the tile variants in `mask`.
+int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, unsigned mask, hipStream_t st) {
   const int gsm = persist_grid(b, b->maxi, 8);
   const int gst = b->ncu * 4;
   hipLaunchKernelGGL(k_bcfl, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_CFL), b->d_part);
@@ -389,8 +393,9 @@ int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, hipStream_t s
     }
     const int last = s == nst - 1;
     for (int v = 0; v < NVAR; v++)
-      if (b->var_mask & (1u << v)) launch_variant_any<1>(v, b->d_rec, b->list(v), b->d_dt, ca, cb, last, gst, st);
-    hipLaunchKernelGGL(k_bc2p, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_C2P), b->d_dt, last, 0, nfatal);
+      if (mask & (1u << v)) launch_variant_any<1>(v, b->d_rec, b->list(v), b->d_dt, ca, cb, last, gst, st);
+    hipLaunchKernelGGL(k_bc2p, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_C2P), b->d_dt, last, 0, nfatal,
+                       b->d_gfatal);
     hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_GH), b->d_dt, 0);
   }
   hipLaunchKernelGGL(k_badvance, dim3((b->maxg + NT - 1) / NT), dim3(NT), 0, st, b->d_t, b->d_nstep, b->d_dt,
@@ -457,6 +462,7 @@ int gmunu_batch_create(int max_blocks, int max_groups, long max_items, gmunu_bat
   ok = ok && hipMalloc(&b->d_tend, sizeof(double) * ng) == hipSuccess;
   ok = ok && hipMalloc(&b->d_nstep, sizeof(int) * ng) == hipSuccess;
   ok = ok && hipMalloc(&b->d_maxstep, sizeof(int) * ng) == hipSuccess;
+  ok = ok && hipMalloc(&b->d_gfatal, sizeof(unsigned int) * ng) == hipSuccess;
   if (!ok) {
     free_batch(b);
     return GMUNU_ENOMEM;
@@ -469,7 +475,8 @@ int gmunu_batch_create(int max_blocks, int max_groups, long max_items, gmunu_bat
        hipMemset(b->d_dt, 0, sizeof(double) * ng) == hipSuccess &&
        hipMemset(b->d_tend, 0, sizeof(double) * ng) == hipSuccess &&
        hipMemset(b->d_nstep, 0, sizeof(int) * ng) == hipSuccess &&
-       hipMemset(b->d_maxstep, 0, sizeof(int) * ng) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+       hipMemset(b->d_maxstep, 0, sizeof(int) * ng) == hipSuccess &&
+       hipMemset(b->d_gfatal, 0, sizeof(unsigned int) * ng) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     free_batch(b);
     return GMUNU_EHIP;
@@ -595,6 +602,8 @@ int gmunu_batch_commit(gmunu_batch *b, void *stream) {
     ok = ok && hipMemcpyAsync(b->d_tend + ts.group, &ts.t_end, sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess;
     ok = ok && hipMemcpyAsync(b->d_nstep + ts.group, &zero, sizeof(int), hipMemcpyHostToDevice, st) == hipSuccess;
     ok = ok &&
+         hipMemcpyAsync(b->d_gfatal + ts.group, &zero, sizeof(unsigned int), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok &&
          hipMemcpyAsync(b->d_maxstep + ts.group, &ts.max_steps, sizeof(int), hipMemcpyHostToDevice, st) == hipSuccess;
   }
   ok = ok && hipStreamSynchronize(st) == hipSuccess;
@@ -631,7 +640,7 @@ int gmunu_batch_init(gmunu_batch *b, const int *slots, int nslots, void *stream)
   hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_IGH), b->d_dt, 1);
   hipLaunchKernelGGL(k_bprim2con, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_IC2P));
   hipLaunchKernelGGL(k_bc2p, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_IC2P), b->d_dt, 1, 1,
-                     (unsigned int *)nullptr);
+                     (unsigned int *)nullptr, (unsigned int *)nullptr);
   hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_IGH), b->d_dt, 1);
   return launch_status();
 }
@@ -700,15 +709,19 @@ int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int u
   if (!b) return GMUNU_ENULL;
   if (!(cfl > 0.0)) return GMUNU_EINVAL;
   hipStream_t st = as_stream(stream);
-  if (!use_graph) return enqueue_step(b, cfl, nfatal_dev, st);
-  if (!b->have_graph || b->graph_cfl != cfl || b->graph_mask != b->var_mask || b->graph_nfatal != nfatal_dev) {
+  if (!use_graph) return enqueue_step(b, cfl, nfatal_dev, b->var_mask, st);
+  // the captured step keeps the kernels of every variant used since the
+  // capture (an empty list costs one short launch), so blocks of new shapes
+  // coming and going do not force a capture each time
+  const unsigned mask = b->var_mask | (b->have_graph ? b->graph_mask : 0u);
+  if (!b->have_graph || b->graph_cfl != cfl || b->graph_mask != mask || b->graph_nfatal != nfatal_dev) {
     if (b->have_graph) {
       (void)hipGraphExecDestroy(b->exec);
       b->have_graph = false;
     }
     hipGraph_t graph;
     if (hipStreamBeginCapture(b->pstream, hipStreamCaptureModeThreadLocal) != hipSuccess) return GMUNU_EHIP;
-    const int rc = enqueue_step(b, cfl, nfatal_dev, b->pstream);
+    const int rc = enqueue_step(b, cfl, nfatal_dev, mask, b->pstream);
     const bool ended = hipStreamEndCapture(b->pstream, &graph) == hipSuccess;
     if (!ended || rc) {
       if (ended) (void)hipGraphDestroy(graph);
@@ -719,7 +732,7 @@ int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int u
     if (!ok) return GMUNU_EHIP;
     b->have_graph = true;
     b->graph_cfl = cfl;
-    b->graph_mask = b->var_mask;
+    b->graph_mask = mask;
     b->graph_nfatal = nfatal_dev;
   }
   // order: caller's prior work -> replay on the private stream -> caller's later work
@@ -729,7 +742,8 @@ int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int u
   return ok ? GMUNU_OK : GMUNU_EHIP;
 }
 
-int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, int *nstep_host, void *stream) {
+int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, int *nstep_host, unsigned int *nfatal_host,
+                      void *stream) {
   if (!b) return GMUNU_ENULL;
   hipStream_t st = as_stream(stream);
   bool ok = true;
@@ -738,6 +752,9 @@ int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, int *nste
     ok = ok && hipMemcpyAsync(dt_host, b->d_dt, sizeof(double) * b->maxg, hipMemcpyDeviceToHost, st) == hipSuccess;
   if (nstep_host)
     ok = ok && hipMemcpyAsync(nstep_host, b->d_nstep, sizeof(int) * b->maxg, hipMemcpyDeviceToHost, st) == hipSuccess;
+  if (nfatal_host)
+    ok = ok && hipMemcpyAsync(nfatal_host, b->d_gfatal, sizeof(unsigned int) * b->maxg, hipMemcpyDeviceToHost, st) ==
+                   hipSuccess;
   ok = ok && hipStreamSynchronize(st) == hipSuccess;
   return ok ? GMUNU_OK : GMUNU_EHIP;
 }

@@ -328,9 +328,11 @@ __device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0
   }
 }
 
-// Primitive recovery of interior cell number t (x fastest) of grid G.
+// Primitive recovery of interior cell number t (x fastest) of grid G; a
+// fatal outcome increments *nfatal and *nfatal2 (each nullable).
 __device__ __forceinline__ void c2p_one(const Grid &G, double *q, const double *__restrict__ met, double *prim,
-                                        uint8_t *flags, unsigned int *nfatal, long t) {
+                                        uint8_t *flags, unsigned int *nfatal, long t,
+                                        unsigned int *nfatal2 = nullptr) {
   const int i = (int)(t % G.n[0]);
   const int j = (int)((t / G.n[0]) % G.n[1]);
   const int k = (int)(t / ((long)G.n[0] * G.n[1]));
@@ -353,6 +355,7 @@ __device__ __forceinline__ void c2p_one(const Grid &G, double *q, const double *
   }
   if (flags) flags[c] = (uint8_t)fl;
   if ((fl & FL_FATAL) && nfatal) atomicAdd(nfatal, 1u);
+  if ((fl & FL_FATAL) && nfatal2) atomicAdd(nfatal2, 1u);
 }
 
 // Conserved variables of cell c (linear index, ghosts included) of grid G.

@@ -68,3 +68,67 @@ def test_null_arguments_are_rejected():
 def test_binding_raises_without_device_tensors():
     with pytest.raises(TypeError):
         gmu._ptr(object(), "x")
+
+
+def _c_layout(structs):
+    """sizeof and field offsets of header structs, from a C program built
+    with the host compiler against include/gmunu.h."""
+    import subprocess
+    import tempfile
+
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gmunu.h"', "int main(void) {"]
+    for st, fields in structs.items():
+        lines.append(f'  printf("{st} size %zu\\n", sizeof({st}));')
+        for f in fields:
+            lines.append(f'  printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    lines += ["  return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(src, "w").write("\n".join(lines))
+        subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
+        out = subprocess.check_output([exe], text=True)
+    res = {}
+    for ln in out.splitlines():
+        st, f, v = ln.split()
+        res[(st, f)] = int(v)
+    return res
+
+
+def test_struct_mirrors_match_the_header():
+    mirrors = {"gmunu_grid_desc": gmu.GridDesc, "gmunu_block": gmu.BlockSpec, "gmunu_request": gmu.RequestSpec,
+               "gmunu_result": gmu.Result, "gmunu_server_info": gmu.ServerInfo}
+    lay = _c_layout({k: [f for f, _ in v._fields_] for k, v in mirrors.items()})
+    for st, cls in mirrors.items():
+        assert lay[(st, "size")] == ctypes.sizeof(cls), st
+        for f, _ in cls._fields_:
+            assert lay[(st, f)] == getattr(cls, f).offset, (st, f)
+
+
+def test_server_rejects_bad_arguments_before_touching_the_device():
+    L = gmu.lib()
+    gmu._server_sigs(L)
+    h = ctypes.c_void_p()
+    assert L.gmunu_server_create(1 << 30, 0, 0.4, 1, ctypes.byref(h)) == -1
+    assert L.gmunu_server_create(1 << 30, 8, -1.0, 1, ctypes.byref(h)) == -1
+    assert L.gmunu_server_create(1 << 30, 8, 0.4, 0, ctypes.byref(h)) == -1
+    assert L.gmunu_server_create(1 << 30, 8, 0.4, 1, None) == -2
+    assert L.gmunu_server_submit(None, None, None) == -2
+    assert L.gmunu_server_poll(None, None, 0, 0) == -2
+    assert L.gmunu_server_destroy(None) == -2
+    assert L.gmunu_server_clock() > 0.0
+
+
+def test_range_pool_host_logic():
+    """The server's arena allocator (header-only, host code) under random
+    alloc / release: ranges aligned, disjoint, inside the arena, and merged
+    back into one free range when everything is returned."""
+    import subprocess
+    import tempfile
+
+    src = os.path.join(ROOT, "tests", "pool_check.cpp")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "pool_check")
+        subprocess.check_call(["g++", "-std=c++17", "-O1", "-I", os.path.join(ROOT, "paper_2012_07322_amd", "csrc"),
+                               src, "-o", exe])
+        out = subprocess.check_output([exe], text=True)
+    assert out.strip().endswith("ok"), out

@@ -207,7 +207,8 @@ def test_group_limits_and_steps_past_the_end():
     for _ in range(12):
         B2.step(0.4)
     torch.cuda.synchronize()
-    t, dt, ns = B2.times(with_steps=True)
+    t, dt, ns, nf = B2.times(with_steps=True)
+    assert not nf[:3].any()
     note(f"  steps {ns[:3].tolist()} t {t[:3].tolist()}")
     assert ns[0] == 2 and ns[2] == 1 and 2 < ns[1] < 12
     assert t[1] == 0.01 and dt[1] == 0.0

@@ -504,3 +504,85 @@ def amr_block_state(p, block_index, star, seed=0, b_peak=1e-4, v_noise=1e-3):
     met[0] = psi
     met[1] = alpha
     return pr, met
+
+
+# ---------------------------------------------------------------- serving
+
+SERVE_RANGES = ((200, 4096), (64, 1024), (32, 128))
+
+
+def serving_requests(nreq, seed=0, ranges=SERVE_RANGES):
+    """A stream of independent solves: dimension 1, 2 or 3 with equal odds,
+    linear size N uniform in that dimension's range (1D shock tubes of N
+    cells, 2D / 3D blast waves of N^2 / N^3 cells), an input seed, and
+    arrival times of a unit-rate Poisson process (divide by the rate)."""
+    idx = np.arange(nreq, dtype=np.uint64)
+    u = [0.5 * (uniform(seed, idx, 300 + s) + 1.0) for s in range(3)]
+    out = []
+    t = 0.0
+    for r in range(nreq):
+        kind = 1 + min(int(u[0][r] * 3), 2)
+        lo, hi = ranges[kind - 1]
+        n = min(lo + int(u[1][r] * (hi - lo + 1)), hi)
+        t += -math.log1p(-float(u[2][r]))
+        out.append({"kind": kind, "n": n, "seed": int(seed) * 1000003 + r, "arrival": t})
+    return out
+
+
+def serving_problem(req, device="cpu"):
+    """Grid, initial primitives, metric (torch float64 tensors on `device`)
+    and stopping rule of one request.  1D: the relativistic MHD shock tube
+    with its jump position moved by up to 0.1 and left / right density and
+    pressure scaled by up to +-10% (seeded), run to t = 0.4.  2D / 3D: the
+    magnetised blast wave with seeded 1e-4 density noise, 50 steps."""
+    import torch
+
+    kind, n, seed = req["kind"], req["n"], req["seed"]
+    if kind == 1:
+        p = grid(1, CART, [n], [-0.5, 0, 0], [0.5, 1, 1], [[OUTFLOW, OUTFLOW]], gamma=5.0 / 3.0, rk=3,
+                 rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=5.0 / 3.0)
+    elif kind == 2:
+        p = grid(2, CART, [n, n], [-0.5, -0.5, 0], [0.5, 0.5, 1], [[OUTFLOW, OUTFLOW]] * 2, gamma=4.0 / 3.0, rk=3,
+                 rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=4.0 / 3.0)
+    else:
+        p = grid(3, CART, [n, n, n], [-0.5] * 3, [0.5] * 3, [[OUTFLOW, OUTFLOW]] * 3, gamma=4.0 / 3.0, rk=3,
+                 rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=4.0 / 3.0)
+    g = ghosts(p)
+    shp = shape(p)
+    ax = [p["xmin"][a] + (torch.arange(-g[a], p["n"][a] + g[a], dtype=torch.float64, device=device) + 0.5) * p["dx"][a]
+          for a in range(3)]
+    x1 = ax[0].view(1, 1, -1).expand(shp)
+    pr = torch.zeros((8,) + shp, dtype=torch.float64, device=device)
+    if kind == 1:
+        v = uniform(seed, np.arange(5, dtype=np.uint64), 400)
+        left = x1 < 0.1 * float(v[0])
+        pr[0] = torch.where(left, 1.0 * (1 + 0.1 * float(v[1])), 0.125 * (1 + 0.1 * float(v[2])))
+        pr[4] = torch.where(left, 1.0 * (1 + 0.1 * float(v[3])), 0.1 * (1 + 0.1 * float(v[4])))
+        pr[5] = 0.5
+        pr[6] = torch.where(left, 1.0, -1.0)
+        t_end, max_steps = 0.4, 0
+    else:
+        x2 = ax[1].view(1, -1, 1).expand(shp)
+        r2 = x1 * x1 + x2 * x2
+        if kind == 3:
+            x3 = ax[2].view(-1, 1, 1).expand(shp)
+            r2 = r2 + x3 * x3
+        gen = torch.Generator(device=device)
+        gen.manual_seed(seed)
+        noise = torch.rand(shp, dtype=torch.float64, device=device, generator=gen) * 2.0 - 1.0
+        pr[0] = 0.01 * (1.0 + 1e-4 * noise)
+        pr[4] = torch.where(r2 <= 0.01, 1.0, 0.01)
+        pr[5] = 0.1
+        t_end, max_steps = 1e30, 50
+    met = torch.zeros((5,) + shp, dtype=torch.float64, device=device)
+    met[0] = 1.0
+    met[1] = 1.0
+    return p, pr, met, t_end, max_steps
+
+
+def serving_footprint(req):
+    """Device bytes of one request's state: q_n, q_s, prim (8 doubles per
+    cell each) and metric (5), ghosts included."""
+    n, k = req["n"], req["kind"]
+    cells = (n + 4) ** k
+    return cells * 29 * 8
