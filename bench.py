@@ -214,9 +214,11 @@ def _serve_cells(r, steps):
     return (r["n"] ** r["kind"]) * 3 * steps
 
 
-def _drive_server(S, reqs, offsets, dev):
-    """Submit reqs at start + offsets (inputs built on the device at arrival)
-    and collect every result; returns per-request records and the start."""
+def _drive_server(S, reqs, dev, offsets=None, concurrency=None):
+    """Feed reqs to the server, inputs built on the device at arrival, and
+    collect every result.  Open loop: request k arrives at start +
+    offsets[k].  Closed loop: `concurrency` requests outstanding, the next
+    one arriving when one completes."""
     import paper_2012_07322_amd as gmu
     import torch
     import workloads as W
@@ -225,15 +227,25 @@ def _drive_server(S, reqs, offsets, dev):
     t0 = clock() + 0.02
     arrival, recs = {}, []
     i = 0
+
+    def submit(k, at):
+        p, pr, met, te, ms = W.serving_problem(reqs[k], dev)
+        S.submit(p, pr, met, te, ms, prim_out=torch.empty_like(pr), tag=k)
+        arrival[k] = at
+
     while len(recs) < len(reqs):
         now = clock()
-        while i < len(reqs) and t0 + offsets[i] <= now:
-            p, pr, met, te, ms = W.serving_problem(reqs[i], dev)
-            S.submit(p, pr, met, te, ms, prim_out=torch.empty_like(pr), tag=i)
-            arrival[i] = t0 + offsets[i]
-            i += 1
-            now = clock()
-        wait = 50 if i >= len(reqs) else int(max(0.0, min(0.05, t0 + offsets[i] - clock())) * 1000)
+        if concurrency is None:
+            while i < len(reqs) and t0 + offsets[i] <= now:
+                submit(i, t0 + offsets[i])
+                i += 1
+                now = clock()
+            wait = 50 if i >= len(reqs) else int(max(0.0, min(0.05, t0 + offsets[i] - clock())) * 1000)
+        else:
+            while i < len(reqs) and i - len(recs) < concurrency:
+                submit(i, max(now, t0))
+                i += 1
+            wait = 50
         for r in S.poll(512, wait):
             k = r["tag"]
             if r["status"] != 0:
@@ -272,32 +284,33 @@ def _drive_plain(reqs, offsets, dev, cfl):
     return recs, t0, busy
 
 
-def bench_serve(nreq=1000, probe=300, plain_n=60, load=0.8, seed=0, budget_gb=64.0, slots=512, spsync=2,
-                cfl=0.4):
+def bench_serve(nreq=1000, probe=300, plain_n=300, plain_open=100, concurrency=64, load=0.8, seed=0,
+                budget_gb=64.0, slots=512, spsync=2, cfl=0.4):
     """Serving workload: independent 1D shock tubes (200-4096 cells, to
-    t = 0.4) and 2D / 3D blast waves (64^2-1024^2, 32^3-128^3, 50 steps)
-    with Poisson arrivals.  (1) Capacity: `probe` requests submitted at once
-    to the server, and the first `plain_n` both to the server and to the
-    plain loop.  (2) Open loop at `load` x the server's capacity: p50 / p99
-    arrival-to-result latency for `nreq` requests on the server and for the
-    first `plain_n` on the plain loop (same arrival times)."""
+    t = 0.4) and 2D / 3D blast waves (64^2-1024^2, 32^3-128^3, 50 steps),
+    Poisson arrivals.  (1) Capacity: the first `probe` requests with
+    `concurrency` outstanding on the server, and the first `plain_n` one
+    after another on the plain loop.  (2) Open loop at `load` x the server's
+    capacity: p50 / p99 arrival-to-result latency of `nreq` requests on the
+    server and of the first `plain_open` on the plain loop (same arrival
+    times)."""
     import torch
 
     import paper_2012_07322_amd as gmu
     import workloads as W
 
     dev = torch.device("cuda:0")
-    reqs = W.serving_requests(max(nreq, probe, plain_n), seed=seed)
+    reqs = W.serving_requests(max(nreq, probe, plain_n, plain_open), seed=seed)
     S = gmu.Server(int(budget_gb * 2**30), max_slots=slots, cfl=cfl, steps_per_sync=spsync)
-    # warm-up: one small solve of each kind (graph capture, allocator)
-    warm = [{"kind": k, "n": n, "seed": 7, "arrival": 0.0} for k, n in ((1, 200), (2, 64), (3, 32))]
-    _drive_server(S, warm, [0.0] * 3, dev)
+    # warm-up: one small and one large solve of each kind (graph capture)
+    warm = [{"kind": k, "n": n, "seed": 7, "arrival": 0.0} for k, n in ((1, 200), (2, 64), (3, 32), (2, 512), (3, 64))]
+    _drive_server(S, warm, dev, concurrency=8)
 
     def summary(recs, t0, busy=None):
         span = max(r["done"] for r in recs) - t0
+        lat = [r["lat"] for r in recs]
         out = {"requests": len(recs), "makespan_s": span, "req_per_s": len(recs) / span,
-               "p50_ms": 1e3 * _pct([r["lat"] for r in recs], 50), "p99_ms": 1e3 * _pct([r["lat"] for r in recs], 99),
-               "mean_ms": 1e3 * sum(r["lat"] for r in recs) / len(recs)}
+               "p50_ms": 1e3 * _pct(lat, 50), "p99_ms": 1e3 * _pct(lat, 99), "mean_ms": 1e3 * sum(lat) / len(lat)}
         if "cells" in recs[0]:
             out["cell_updates_per_s"] = sum(r["cells"] for r in recs) / span
         if busy is not None:
@@ -308,39 +321,43 @@ def bench_serve(nreq=1000, probe=300, plain_n=60, load=0.8, seed=0, budget_gb=64
                          for d in (1, 2, 3)}
         return out
 
-    log(f"[serve] capacity probe: {probe} requests at once")
-    recs, t0 = _drive_server(S, reqs[:probe], [0.0] * probe, dev)
+    log(f"[serve] capacity: {probe} requests, {concurrency} outstanding")
+    recs, t0 = _drive_server(S, reqs[:probe], dev, concurrency=concurrency)
     cap = summary(recs, t0)
-    log(f"[serve]   {cap['req_per_s']:.1f} req/s, {cap['cell_updates_per_s']:.3e} cell-updates/s")
-    recs, t0 = _drive_server(S, reqs[:plain_n], [0.0] * plain_n, dev)
-    cap_small = summary(recs, t0)
-    log(f"[serve] plain loop: {plain_n} requests back to back")
+    log(f"[serve]   server {cap['req_per_s']:.1f} req/s, {cap['cell_updates_per_s']:.3e} cell-updates/s")
+    log(f"[serve] plain loop: first {plain_n} one after another")
+    steps = {r["k"]: r["steps"] for r in recs}
     precs, pt0, pbusy = _drive_plain(reqs[:plain_n], [0.0] * plain_n, dev, cfl)
+    if all(r["k"] in steps for r in precs):
+        # same solves, same step counts (the results are identical)
+        for r in precs:
+            r["cells"] = _serve_cells(reqs[r["k"]], steps[r["k"]])
     cap_plain = summary(precs, pt0, pbusy)
-    log(f"[serve]   server {cap_small['req_per_s']:.1f} req/s vs plain {cap_plain['req_per_s']:.1f} req/s "
-        f"on the same {plain_n}")
+    log(f"[serve]   plain {cap_plain['req_per_s']:.1f} req/s")
     rate = load * cap["req_per_s"]
     offs = [r["arrival"] / rate for r in reqs[:nreq]]
-    log(f"[serve] open loop: {nreq} requests at {rate:.1f} req/s ({load:.0%} of capacity)")
-    recs, t0 = _drive_server(S, reqs[:nreq], offs, dev)
+    log(f"[serve] open loop: {nreq} requests at {rate:.1f} req/s ({load:.0%} of the server's capacity)")
+    recs, t0 = _drive_server(S, reqs[:nreq], dev, offsets=offs)
     opn = summary(recs, t0)
     info = S.status()
     S.close()
     log(f"[serve]   p50 {opn['p50_ms']:.1f} ms, p99 {opn['p99_ms']:.1f} ms")
-    log(f"[serve] plain loop, open loop: first {plain_n} at the same arrival times")
-    precs, pt0, pbusy = _drive_plain(reqs[:plain_n], offs[:plain_n], dev, cfl)
+    log(f"[serve] plain loop, open loop: first {plain_open} at the same arrival times")
+    precs, pt0, pbusy = _drive_plain(reqs[:plain_open], offs[:plain_open], dev, cfl)
     opn_plain = summary(precs, pt0, pbusy)
-    sub = [r for r in recs if r["k"] < plain_n]
+    sub = [r for r in recs if r["k"] < plain_open]
     opn_sub = {"p50_ms": 1e3 * _pct([r["lat"] for r in sub], 50), "p99_ms": 1e3 * _pct([r["lat"] for r in sub], 99)}
     log(f"[serve]   plain p50 {opn_plain['p50_ms']:.1f} ms, p99 {opn_plain['p99_ms']:.1f} ms "
         f"(server on the same requests: p50 {opn_sub['p50_ms']:.1f}, p99 {opn_sub['p99_ms']:.1f})")
+    # plain capacity on exactly the requests of the server's probe
+    same = min(probe, plain_n)
     return {
-        "workload": "serving_poisson", "seed": seed, "budget_gib": budget_gb, "slots": slots,
+        "workload": "serving_poisson", "seed": seed, "budget_gib": budget_gb, "slots_per_lane": slots,
         "steps_per_sync": spsync, "cfl": cfl,
         "mix": "1D tube N in [200,4096] to t=0.4; 2D blast N^2, N in [64,1024]; 3D blast N^3, N in [32,128]; "
                "50 steps; dimension equally likely, N uniform",
-        "capacity": {"server": cap, "server_first_n": cap_small, "plain_first_n": cap_plain,
-                     "speedup_first_n": cap_small["req_per_s"] / cap_plain["req_per_s"]},
+        "capacity": {"server": cap, "plain": cap_plain, "same_requests": same == probe == plain_n,
+                     "speedup": cap["req_per_s"] / cap_plain["req_per_s"]},
         "open_loop": {"load": load, "rate_req_per_s": rate, "server": opn, "server_first_n": opn_sub,
                       "plain_first_n": opn_plain},
         "server_info": {k: info[k] for k in ("replays", "pool_peak", "busy_s")},
@@ -363,7 +380,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="open-loop requests for the serving measurement (0: skip)")
     ap.add_argument("--serve-probe", type=int, default=300)
-    ap.add_argument("--serve-plain", type=int, default=60)
+    ap.add_argument("--serve-plain", type=int, default=300)
+    ap.add_argument("--serve-plain-open", type=int, default=100)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -464,7 +482,7 @@ def main():
         torch.cuda.empty_cache()
     if args.serve_requests > 0:
         out["serving"] = bench_serve(args.serve_requests, probe=args.serve_probe, plain_n=args.serve_plain,
-                                     seed=args.seed, cfl=args.cfl)
+                                     plain_open=args.serve_plain_open, seed=args.seed, cfl=args.cfl)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on a {n}x{n}x{args.cpu_slab} slab")

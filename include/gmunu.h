@@ -188,7 +188,10 @@ typedef struct gmunu_block {
 } gmunu_block;
 
 /* Capacities: slots, groups, and work items per list (one item = one tile of
- * at most 256 cells, or 256 cells / ghosts).  Allocates device tables. */
+ * at most 256 cells, or 256 cells / ghosts).  Allocates device tables.
+ * set_block, clear_block, set_group, commit, init and autotune must not be
+ * called while a step of this batch may still run on the device (a slot's
+ * geometry table is rewritten in place by set_block). */
 int gmunu_batch_create(int max_blocks, int max_groups, long max_items, gmunu_batch **out);
 int gmunu_batch_destroy(gmunu_batch *b);
 int gmunu_batch_set_block(gmunu_batch *b, int slot, const gmunu_block *blk);
@@ -240,9 +243,12 @@ int gmunu_profile_read(gmunu_ctx *ctx, double *ms_out /* [GMUNU_NK] */, long *co
  * arrival order as soon as a slot and a contiguous range of the server's
  * device arena (its HBM budget, allocated once at create) are free, uploads
  * the initial data on a copy stream while the GPU keeps stepping the
- * resident solves, adds the solve to a gmunu_batch (one per integrator,
- * each solve its own group with its own dt), and replays the captured batch
- * step `steps_per_sync` times between checks.  A solve that reaches its end
+ * resident solves, and adds the solve to a lane: a gmunu_batch with its own
+ * stream (each solve its own group with its own dt), one lane per
+ * integrator and size class (at most 65536 interior cells, or more), so
+ * small solves are not paced by large ones and both lanes run concurrently.
+ * Each lane replays its captured step in rounds of about 2 ms of device
+ * work (at least `steps_per_sync` replays).  A solve that reaches its end
  * is copied out (copy stream), removed from the batch and its memory
  * returned; its result is then available to gmunu_server_poll.  Each solve
  * is advanced by exactly the arithmetic of gmunu_step on its own grid, so a
@@ -290,8 +296,9 @@ typedef struct gmunu_server_info {
 double gmunu_server_clock(void);
 /* hbm_bytes: arena for solve state (q_n, q_s, prim: 8 doubles per cell each,
  * metric 5; 232 bytes per cell with ghosts); max_slots: solves resident at
- * once; cfl: Courant number of every solve; steps_per_sync >= 1: replays
- * between completion checks.  Starts the worker on the current device. */
+ * once per lane; cfl: Courant number of every solve; steps_per_sync >= 1:
+ * least replays between completion checks.  Starts the worker on the
+ * current device. */
 int gmunu_server_create(size_t hbm_bytes, int max_slots, double cfl, int steps_per_sync, gmunu_server **out);
 /* Queue a solve (non-blocking).  GMUNU_EINVAL if the descriptor is invalid
  * or the solve can never fit the arena; GMUNU_ESTOP after a worker error. */

@@ -41,13 +41,13 @@ struct BlockRec {
   int active;
 };
 
-// Compiled tile shapes (all 256 threads).
+// Compiled tile shapes (256 threads; each pass has at most 256 faces).
 struct Variant {
   int tx, ty, tz, nd;
 };
 constexpr int NVAR = 8;
-constexpr Variant kVar[NVAR] = {{8, 8, 4, 3},  {16, 4, 4, 3}, {32, 4, 2, 3}, {8, 4, 8, 3},
-                                {32, 8, 1, 2}, {16, 16, 1, 2}, {64, 4, 1, 2}, {256, 1, 1, 1}};
+constexpr Variant kVar[NVAR] = {{8, 8, 3, 3},   {8, 5, 5, 3},  {16, 4, 3, 3}, {8, 6, 4, 3},
+                                {16, 15, 1, 2}, {32, 7, 1, 2}, {8, 28, 1, 2}, {255, 1, 1, 1}};
 // Work lists: one per tile variant, then recovery, ghosts, CFL (entries
 // ordered by group), and the recovery / ghost lists of an init.
 enum { L_C2P = NVAR, L_GH, L_CFL, L_IC2P, L_IGH, NLIST };
@@ -93,9 +93,9 @@ __device__ __forceinline__ int find_entry(const int *start, int nent, int it, in
 }
 
 template <int TX, int TY, int TZ, int ND, int MODE>
-__global__ __launch_bounds__(TX *TY *TZ, 3) void k_bstage(const BlockRec *__restrict__ B, DList L,
+__global__ __launch_bounds__(NT, 3) void k_bstage(const BlockRec *__restrict__ B, DList L,
                                                           const double *dts, double ca, double cb, int out_qn) {
-  __shared__ double sF[NV * max_faces<TX, TY, TZ, ND>()];
+  __shared__ double sF[stage_lds<TX, TY, TZ, ND>()];
   const int nent = L.meta[0];
   int it, end, stride;
   xcd_range(L.meta[1], it, end, stride);
@@ -223,7 +223,7 @@ void launch_variant_any(int v, const BlockRec *B, DList L, const double *dts, do
 int default_variant(const gmunu_grid_desc &d) {
   if (d.ndim == 1) return 7;
   if (d.ndim == 2) return 4;
-  return (d.n[0] <= 8 || d.n[1] <= 4) ? 0 : 1;
+  return d.n[0] <= 8 ? 0 : 1;
 }
 
 std::tuple<int, int, int, int> bucket_of(const gmunu_grid_desc &d) { return {d.ndim, d.n[0], d.n[1], d.n[2]}; }
@@ -264,7 +264,8 @@ struct gmunu_batch {
   std::vector<gmunu_block> blk;
   std::vector<char> used;
   std::vector<BlockRec> rec;
-  std::vector<double *> geo;
+  std::vector<double *> geo;  // per-slot geometry tables, grown, never shrunk
+  std::vector<size_t> geo_cap;
   std::vector<int> var;
   std::map<std::tuple<int, int, int, int>, int> tuned;
   struct TimeSet {
@@ -436,6 +437,7 @@ int gmunu_batch_create(int max_blocks, int max_groups, long max_items, gmunu_bat
   b->rec.resize(max_blocks);
   std::memset(b->rec.data(), 0, sizeof(BlockRec) * max_blocks);
   b->geo.assign(max_blocks, nullptr);
+  b->geo_cap.assign(max_blocks, 0);
   b->var.assign(max_blocks, -1);
   for (long &c : b->counts) c = 0;
   b->var_mask = 0;
@@ -519,12 +521,17 @@ int gmunu_batch_set_block(gmunu_batch *b, int slot, const gmunu_block *blk) {
   BlockRec r;
   std::memset(&r, 0, sizeof(r));
   const GeoOffsets off = setup_grid(blk->desc, r.G, tab);
-  double *g = nullptr;
-  if (hipMalloc(&g, tab.size() * sizeof(double)) != hipSuccess) return GMUNU_ENOMEM;
-  if (hipMemcpy(g, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(g);
-    return GMUNU_EHIP;
+  // the slot's table buffer is reused when large enough (the slot is not in
+  // use by a running step, so it may be overwritten)
+  if (tab.size() > b->geo_cap[slot]) {
+    double *g = nullptr;
+    if (hipMalloc(&g, tab.size() * sizeof(double)) != hipSuccess) return GMUNU_ENOMEM;
+    if (b->geo[slot]) (void)hipFree(b->geo[slot]);
+    b->geo[slot] = g;
+    b->geo_cap[slot] = tab.size();
   }
+  double *g = b->geo[slot];
+  if (hipMemcpy(g, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) return GMUNU_EHIP;
   bind_geo(r.G, g, off);
   r.qn = blk->q_n;
   r.qs = blk->q_s;
@@ -533,8 +540,6 @@ int gmunu_batch_set_block(gmunu_batch *b, int slot, const gmunu_block *blk) {
   r.flags = blk->flags;
   r.group = blk->group;
   r.active = 1;
-  if (b->geo[slot]) (void)hipFree(b->geo[slot]);
-  b->geo[slot] = g;
   b->rec[slot] = r;
   b->blk[slot] = *blk;
   b->used[slot] = 1;

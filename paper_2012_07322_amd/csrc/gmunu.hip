@@ -2,9 +2,12 @@
 // C ABI.
 //
 // One RK stage is three launches on the caller's stream:
-//   k_stage   per tile of cells: MC reconstruction, HLLE face fluxes (each
-//             face computed once and exchanged through LDS), flux-area
-//             divergence, gravitational + geometric sources, RK combination;
+//   k_stage   per tile of cells (8x5x5 in 3D, 16x15 in 2D, 255 in 1D, so
+//             that each direction's faces fit one per thread): per direction
+//             the tile's stencil region of prim and metric is staged in LDS,
+//             each face is reconstructed (MC) and its HLLE flux computed once,
+//             fluxes are exchanged through LDS into the flux-area divergence;
+//             then gravitational + geometric sources and the RK combination;
 //   k_c2p     per interior cell: primitive recovery with error handling;
 //   k_ghosts  per face-adjacent ghost cell: boundary fill of the primitives.
 // The time step is a per-cell rate reduced by wavefront shuffles to one
@@ -74,12 +77,12 @@ __device__ __forceinline__ void xcd_tile(const Grid &G, int TX, int TY, int TZ, 
 // MODE 0: dqdt = L(prim).  MODE 1: q_out = ca q_n + cb (q_s + dt L(prim)).
 // skipp (nullable): nothing is done when *skipp == 0 (a step past t_end).
 template <int TX, int TY, int TZ, int ND, int MODE>
-__global__ __launch_bounds__(TX *TY *TZ, 3) void k_stage(const Grid G, const double *__restrict__ prim,
+__global__ __launch_bounds__(NT, 3) void k_stage(const Grid G, const double *__restrict__ prim,
                                                          const double *__restrict__ met, const double *qn,
                                                          const double *qs, double *out,
                                                          const double *__restrict__ dtp, double ca, double cb,
                                                          const double *__restrict__ skipp) {
-  __shared__ double sF[NV * max_faces<TX, TY, TZ, ND>()];
+  __shared__ double sF[stage_lds<TX, TY, TZ, ND>()];
   if (skipp && *skipp == 0.0) return;
   int bx, by, bz;
   xcd_tile(G, TX, TY, TZ, bx, by, bz);
@@ -135,7 +138,7 @@ void launch_stage_t(const gmunu_ctx *ctx, const double *prim, const double *met,
                     hipStream_t st) {
   const Grid &G = ctx->G;
   dim3 grid(((G.n[0] + TX - 1) / TX) * ((G.n[1] + TY - 1) / TY) * ((G.n[2] + TZ - 1) / TZ));
-  hipLaunchKernelGGL((k_stage<TX, TY, TZ, ND, MODE>), grid, dim3(TX * TY * TZ), 0, st, G, prim, met, qn, qs, out,
+  hipLaunchKernelGGL((k_stage<TX, TY, TZ, ND, MODE>), grid, dim3(NT), 0, st, G, prim, met, qn, qs, out,
                      dtp, ca, cb, skipp);
 }
 
@@ -144,11 +147,11 @@ void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, c
                   const double *qs, double *out, const double *dtp, double ca, double cb, const double *skipp,
                   hipStream_t st) {
   if (ctx->G.ndim == 1)
-    launch_stage_t<256, 1, 1, 1, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);
+    launch_stage_t<255, 1, 1, 1, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);
   else if (ctx->G.ndim == 2)
-    launch_stage_t<32, 8, 1, 2, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);
+    launch_stage_t<16, 15, 1, 2, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);
   else
-    launch_stage_t<16, 4, 4, 3, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);
+    launch_stage_t<8, 5, 5, 3, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);
 }
 
 int launch_c2p(gmunu_ctx *ctx, double *q, const double *metric, double *prim, uint8_t *flags,

@@ -22,37 +22,37 @@ __device__ __forceinline__ double ld(const double *__restrict__ base, long nv, i
 
 // Face flux times face factor through the lower face (along D) of cell
 // (i,j,k): MC reconstruction from the four cells across the face, metric as
-// the mean of the two adjacent centres, HLLE.  pb, mb: prim and metric
-// bases of the tile; rel: offset of cell (i,j,k) from them (in cells).
+// the mean of the two adjacent centres, HLLE.  The stencil comes from the
+// workgroup's staged region S (RC cells per variable, prim variables 0-7,
+// metric 8-12): r0 is the region index of the cell two below the face, rs
+// the region stride along D.
 template <int D>
-__device__ __forceinline__ void face_flux(const Grid &G, const double *__restrict__ pb,
-                                          const double *__restrict__ mb, int i, int j, int k, unsigned rel,
-                                          double *Fo) {
+__device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC, int r0, int rs, int i, int j,
+                                          int k, double *Fo) {
   const int cd = (D == 0 ? i : D == 1 ? j : k) + G.g[D];
   // zero-area faces (r = 0, theta = 0 or pi) are evaluated like any other
   // and their flux replaced by 0 at the end; no load-dependent branch here
   const double fa = G.geo.fa[D][cd];
-  const unsigned sd8 = (unsigned)G.s[D] * 8u;
-  const unsigned o2 = rel * 8u;  // cell f (right of the face)
-  const unsigned o1 = o2 - sd8, o0 = o1 - sd8, o3 = o2 + sd8;
+  const int r1 = r0 + rs, r2 = r1 + rs, r3 = r2 + rs;
   double pl[NV], pr[NV];
 #pragma unroll
   for (int v = 0; v < NV; v++) {
-    const double a = ld(pb, G.nv, v, o0), b = ld(pb, G.nv, v, o1), e = ld(pb, G.nv, v, o2),
-                 f = ld(pb, G.nv, v, o3);
+    const double *Sv = S + v * RC;
+    const double a = Sv[r0], b = Sv[r1], e = Sv[r2], f = Sv[r3];
     pl[v] = b + 0.5 * mc_slope(a, b, e);
     pr[v] = e - 0.5 * mc_slope(b, e, f);
   }
-  const double psi = 0.5 * (ld(mb, G.nv, 0, o1) + ld(mb, G.nv, 0, o2));
-  const double alpha = 0.5 * (ld(mb, G.nv, 1, o1) + ld(mb, G.nv, 1, o2));
+  const double *Sm = S + NV * RC;
+  const double psi = 0.5 * (Sm[r1] + Sm[r2]);
+  const double alpha = 0.5 * (Sm[RC + r1] + Sm[RC + r2]);
   double beta[3];
 #pragma unroll
-  for (int a = 0; a < 3; a++) beta[a] = 0.5 * (ld(mb, G.nv, 2 + a, o1) + ld(mb, G.nv, 2 + a, o2));
+  for (int a = 0; a < 3; a++) beta[a] = 0.5 * (Sm[(2 + a) * RC + r1] + Sm[(2 + a) * RC + r2]);
   double g1 = 1.0, g2 = 1.0;
   if (G.coord != CART) {
-    const double r2 = (D == 0) ? G.geo.r2f[i + G.g[0]] : G.geo.r2c[i + G.g[0]];
+    const double r2c = (D == 0) ? G.geo.r2f[i + G.g[0]] : G.geo.r2c[i + G.g[0]];
     const double s2 = (D == 1) ? G.geo.s2f[j + G.g[1]] : G.geo.s2c[j + G.g[1]];
-    ref_diag(G.coord, r2, s2, g1, g2);
+    ref_diag(G.coord, r2c, s2, g1, g2);
   }
   const double psi2 = psi * psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
   const double gD = D == 0 ? 1.0 : D == 1 ? g1 : g2;
@@ -235,29 +235,82 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
   }
 }
 
+// Staged region of the face pass along D of a TX x TY x TZ tile: the tile's
+// cells plus two on each side along D.
 template <int TX, int TY, int TZ, int D>
-__device__ __forceinline__ void face_pass(const Grid &G, const double *__restrict__ pb,
-                                          const double *__restrict__ mb, double *sF, int i0, int j0, int k0,
+constexpr int region_cells() {
+  return (TX + 4 * (D == 0)) * (TY + 4 * (D == 1)) * (TZ + 4 * (D == 2));
+}
+
+// Faces of the pass along D (the tile's lower faces plus the upper layer).
+template <int TX, int TY, int TZ, int D>
+constexpr int pass_faces() {
+  return (TX + (D == 0)) * (TY + (D == 1)) * (TZ + (D == 2));
+}
+
+// LDS doubles per workgroup: the staged region (prim and metric) of the
+// largest pass, reused for the face fluxes.
+template <int TX, int TY, int TZ, int ND>
+constexpr int stage_lds() {
+  constexpr int r0 = region_cells<TX, TY, TZ, 0>(), r1 = ND > 1 ? region_cells<TX, TY, TZ, 1>() : 0,
+                r2 = ND > 2 ? region_cells<TX, TY, TZ, 2>() : 0;
+  constexpr int r = r0 > r1 ? (r0 > r2 ? r0 : r2) : (r1 > r2 ? r1 : r2);
+  return (NV + 5) * r;
+}
+
+// Tile shapes whose passes have at most one face per thread.
+template <int TX, int TY, int TZ, int ND>
+constexpr bool tile_fits() {
+  return pass_faces<TX, TY, TZ, 0>() <= NT && (ND < 2 || pass_faces<TX, TY, TZ, 1>() <= NT) &&
+         (ND < 3 || pass_faces<TX, TY, TZ, 2>() <= NT) && TX * TY * TZ <= NT;
+}
+
+// Flux divergence along D, accumulated into acc of the thread's cell:
+// (1) stage prim and metric of the pass's region into LDS (coalesced, each
+// value read once from memory), (2) one face per thread from LDS, (3) the
+// fluxes through LDS to the cells on both sides of each face.
+template <int TX, int TY, int TZ, int D>
+__device__ __forceinline__ void face_pass(const Grid &G, const double *__restrict__ prim,
+                                          const double *__restrict__ met, double *S, int i0, int j0, int k0,
                                           int tx, int ty, int tz, bool valid, double *acc) {
-  constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2);
-  constexpr int NF = FX * FY * FZ;
+  constexpr int RX = TX + 4 * (D == 0), RY = TY + 4 * (D == 1), RZ = TZ + 4 * (D == 2), RC = RX * RY * RZ;
+  constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2), NF = FX * FY * FZ;
   const int tid = threadIdx.x;
-  for (int f = tid; f < NF; f += TX * TY * TZ) {
-    const int fx = f % FX, fy = (f / FX) % FY, fz = f / (FX * FY);
-    const int ci = i0 + fx, cj = j0 + fy, ck = k0 + fz;
-    const bool ok = (D == 0 ? ci <= G.n[0] : ci < G.n[0]) && (D == 1 ? cj <= G.n[1] : cj < G.n[1]) &&
-                    (D == 2 ? ck <= G.n[2] : ck < G.n[2]);
-    double Fo[NV];
-    if (ok) {
-      // offset from the tile base (the cell at i0 - g0, j0 - g1, k0 - g2)
-      const unsigned rel = (unsigned)((ck - k0 + G.g[2]) * G.s[2] + (cj - j0 + G.g[1]) * G.s[1] + (ci - i0 + G.g[0]));
-      face_flux<D>(G, pb, mb, ci, cj, ck, rel, Fo);
-    } else {
+  // (1) region origin: the tile origin moved two cells down along D
+  const int ai = i0 - 2 * (D == 0), aj = j0 - 2 * (D == 1), ak = k0 - 2 * (D == 2);
+  for (int c = tid; c < RC; c += NT) {
+    const int ri = c % RX, rj = (c / RX) % RY, rk = c / (RX * RY);
+    const int gi = ai + ri, gj = aj + rj, gk = ak + rk;
+    // cells outside the array (ragged tiles) are not needed by any valid face
+    if (gi < G.n[0] + G.g[0] && gj < G.n[1] + G.g[1] && gk < G.n[2] + G.g[2]) {
+      const long o = cell_offset(G, gi, gj, gk);
 #pragma unroll
-      for (int v = 0; v < NV; v++) Fo[v] = 0.0;
+      for (int v = 0; v < NV; v++) S[v * RC + c] = prim[v * G.nv + o];
+#pragma unroll
+      for (int w = 0; w < 5; w++) S[(NV + w) * RC + c] = met[w * G.nv + o];
     }
+  }
+  __syncthreads();
+  // (2) face tid: region index of the cell two below it along D
+  double Fo[NV];
+  const int f = tid;
+  const int fx = f % FX, fy = (f / FX) % FY, fz = f / (FX * FY);
+  const int ci = i0 + fx, cj = j0 + fy, ck = k0 + fz;
+  const bool ok = f < NF && (D == 0 ? ci <= G.n[0] : ci < G.n[0]) && (D == 1 ? cj <= G.n[1] : cj < G.n[1]) &&
+                  (D == 2 ? ck <= G.n[2] : ck < G.n[2]);
+  if (ok) {
+    constexpr int rs = D == 0 ? 1 : D == 1 ? RX : RX * RY;
+    const int r0 = fx + RX * (fy + RY * fz);  // region coordinate = face coordinate - 2 + 2 along D
+    face_flux<D>(G, S, RC, r0, rs, ci, cj, ck, Fo);
+  } else {
 #pragma unroll
-    for (int v = 0; v < NV; v++) sF[v * NF + f] = Fo[v];
+    for (int v = 0; v < NV; v++) Fo[v] = 0.0;
+  }
+  __syncthreads();
+  // (3) fluxes through LDS (over the staged region, no longer needed)
+  if (f < NF) {
+#pragma unroll
+    for (int v = 0; v < NV; v++) S[v * NF + f] = Fo[v];
   }
   __syncthreads();
   if (valid) {
@@ -266,32 +319,25 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *__restric
     const int cd = (D == 0 ? i0 + tx : D == 1 ? j0 + ty : k0 + tz) + G.g[D];
     const double icv = G.geo.icv[D][cd];
 #pragma unroll
-    for (int v = 0; v < NV; v++) acc[v] -= (sF[v * NF + fu] - sF[v * NF + fl]) * icv;
+    for (int v = 0; v < NV; v++) acc[v] -= (S[v * NF + fu] - S[v * NF + fl]) * icv;
   }
   __syncthreads();
 }
 
-template <int TX, int TY, int TZ, int ND>
-constexpr int max_faces() {
-  constexpr int a = (TX + 1) * TY * TZ;
-  constexpr int b = ND > 1 ? TX * (TY + 1) * TZ : 0;
-  constexpr int c = ND > 2 ? TX * TY * (TZ + 1) : 0;
-  return a > b ? (a > c ? a : c) : (b > c ? b : c);
-}
-
 // One RK stage (MODE 1: q_out = ca q_n + cb (q_s + dt L)) or the RHS alone
 // (MODE 0: out = L) on the tile of TX x TY x TZ cells with origin (i0,j0,k0).
-// Every thread of the workgroup must call it (it synchronises); sF is the
-// workgroup's LDS face buffer of NV * max_faces<TX,TY,TZ,ND>() doubles.
+// Every thread of the workgroup (NT threads) must call it (it synchronises);
+// sF is the workgroup's LDS buffer of stage_lds<TX,TY,TZ,ND>() doubles.
 template <int TX, int TY, int TZ, int ND, int MODE>
 __device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0, const double *__restrict__ prim,
                                            const double *__restrict__ met, const double *qn, const double *qs,
                                            double *out, const double *__restrict__ dtp, double ca, double cb,
                                            double *sF) {
+  static_assert(tile_fits<TX, TY, TZ, ND>(), "tile passes must have at most one face per thread");
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
   const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
-  const bool valid = (i < G.n[0]) && (j < G.n[1]) && (k < G.n[2]);
+  const bool valid = tid < TX * TY * TZ && (i < G.n[0]) && (j < G.n[1]) && (k < G.n[2]);
   // tile base: the cell (i0 - g0, j0 - g1, k0 - g2); every access of this
   // workgroup is at a non-negative offset from it
   const long lo = cell_offset(G, i0 - G.g[0], j0 - G.g[1], k0 - G.g[2]);
@@ -300,9 +346,9 @@ __device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; v++) acc[v] = 0.0;
-  face_pass<TX, TY, TZ, 0>(G, pb, mb, sF, i0, j0, k0, tx, ty, tz, valid, acc);
-  if constexpr (ND > 1) face_pass<TX, TY, TZ, 1>(G, pb, mb, sF, i0, j0, k0, tx, ty, tz, valid, acc);
-  if constexpr (ND > 2) face_pass<TX, TY, TZ, 2>(G, pb, mb, sF, i0, j0, k0, tx, ty, tz, valid, acc);
+  face_pass<TX, TY, TZ, 0>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
+  if constexpr (ND > 1) face_pass<TX, TY, TZ, 1>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
+  if constexpr (ND > 2) face_pass<TX, TY, TZ, 2>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
   if (!valid) return;
   const unsigned rel = (unsigned)((tz + G.g[2]) * G.s[2] + (ty + G.g[1]) * G.s[1] + (tx + G.g[0]));
   cell_sources(G, pb, mb, i, j, k, rel, acc);

@@ -1,24 +1,28 @@
 // Request server: continuous batching of independent solves on one GPU.
 //
-// One worker thread owns the GPU side: a compute stream that replays the
-// captured batch step, a copy stream for uploads of admitted solves and
-// downloads of finished ones, one gmunu_batch per integrator (each solve is
-// one block in its own group), and a range pool over one device arena (the
-// HBM budget).  Callers only touch the pending queue and the result queue,
-// both under one mutex.
+// One worker thread owns the GPU side: a range pool over one device arena
+// (the HBM budget), a copy stream for uploads of admitted solves and
+// downloads of finished ones, and four lanes.  A lane is one gmunu_batch
+// (each solve one block in its own group) with its own stream; solves go to
+// a lane by integrator and by size: small solves (at most kSmallCells
+// interior cells) share a lane of their own, so a 1D tube that needs
+// thousands of steps is not paced by the large 3D solves, and the two lanes'
+// kernels run concurrently on the device.  Callers only touch the pending
+// queue and the result queue, both under one mutex.
 //
 // Loop: admit pending solves in arrival order while a slot, list capacity
-// and arena space are free (upload on the copy stream) -> solves whose
-// upload finished join their batch (commit + init of the new slots) ->
-// replay every non-empty batch steps_per_sync times -> while the GPU runs,
-// retire finished downloads -> wait for the replays, read each group's
-// (t, dt, steps) -> solves at their end start their download and leave the
-// batch.  Admission and retirement therefore overlap the GPU work of the
-// other solves.
+// and arena space are free (upload on the copy stream) -> for every lane
+// whose round of replays has finished: read each group's (t, dt, steps),
+// start the download of finished solves and drop them from the lane -> every
+// idle lane takes in its uploaded solves, commits, initialises the new ones
+// and launches its next round of replays -> finished downloads return their
+// memory.  A batch is only changed while its lane is idle.  Each lane sizes
+// its rounds to about kRoundSeconds of device work.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -41,6 +45,10 @@ double now_s() {
 }
 
 constexpr size_t kAlign = 256;
+constexpr long kSmallCells = 1L << 16;  // interior cells of a "small" solve
+constexpr double kRoundSeconds = 2e-3;  // device time per round of replays
+constexpr int kMaxRound = 64;           // replays per round, at most
+constexpr int NLANE = 4;                // (SSPRK2, SSPRK3) x (large, small)
 
 struct Req {
   unsigned long long id = 0;
@@ -57,13 +65,19 @@ struct Req {
   bool in_batch = false;
 };
 
-// One batch and its slots (all solves of one integrator).
+// One batch, its stream and its slots.
 struct Lane {
   gmunu_batch *b = nullptr;
-  std::vector<Req *> slot;  // resident or loading, by slot
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  bool inflight = false;
+  int round = 1;  // replays per round
+  double t_launch = 0.0;
+  std::vector<Req *> slot;  // resident or uploading, by slot
   std::vector<int> free_slots;
   long stage[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   long cells = 0, ghosts = 0;
+  std::vector<Req *> joining;  // uploaded, to be added when the lane is idle
   std::vector<int> newly;
   bool dirty = false;
   int resident = 0;
@@ -102,9 +116,8 @@ struct gmunu_server {
   int max_slots = 0;
   long maxi = 0;
   char *arena = nullptr;
-  hipStream_t cs = nullptr, xs = nullptr;
-  hipEvent_t ev_step = nullptr;
-  Lane lane[2];  // SSPRK2, SSPRK3
+  hipStream_t xs = nullptr;
+  Lane lane[NLANE];
 
   // shared with callers (under mu)
   std::mutex mu;
@@ -121,8 +134,21 @@ struct gmunu_server {
   std::vector<Req *> loading, unloading;
   std::thread worker;
 
+  static int lane_index(const gmunu_grid_desc &d) {
+    const long cells = (long)d.n[0] * d.n[1] * d.n[2];
+    return (d.rk == 3 ? 2 : 0) + (cells <= kSmallCells ? 1 : 0);
+  }
   Lane &lane_of(const Req *r) { return lane[r->lane]; }
-  int resident_total() const { return lane[0].resident + lane[1].resident; }
+  int resident_total() const {
+    int n = 0;
+    for (const Lane &L : lane) n += L.resident;
+    return n;
+  }
+  bool any_inflight() const {
+    for (const Lane &L : lane)
+      if (L.inflight) return true;
+    return false;
+  }
 
   void finish(Req *r, int status) {
     gmunu_result res{};
@@ -160,23 +186,31 @@ struct gmunu_server {
     r->qs = reinterpret_cast<double *>(base + r->arr8);
     r->prim = reinterpret_cast<double *>(base + 2 * r->arr8);
     r->met = reinterpret_cast<double *>(base + 3 * r->arr8);
+    loading.push_back(r);
     if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) return false;
     bool ok = hipMemcpyAsync(r->prim, r->r.prim, sizeof(double) * 8 * r->nv, hipMemcpyDefault, xs) == hipSuccess;
     ok = ok && hipMemcpyAsync(r->met, r->r.metric, sizeof(double) * 5 * r->nv, hipMemcpyDefault, xs) == hipSuccess;
-    ok = ok && hipEventRecord(r->ev, xs) == hipSuccess;
-    loading.push_back(r);
-    return ok;
+    return ok && hipEventRecord(r->ev, xs) == hipSuccess;
   }
 
-  // Solves whose upload finished join their batch.
-  bool finish_loads() {
+  // Solves whose upload finished wait for their lane to be idle.
+  bool finish_loads(bool &progress) {
     size_t k = 0;
     for (; k < loading.size(); k++) {
       Req *r = loading[k];
       const hipError_t q = hipEventQuery(r->ev);
       if (q == hipErrorNotReady) break;  // uploads complete in order
       if (q != hipSuccess) return false;
-      Lane &L = lane_of(r);
+      lane_of(r).joining.push_back(r);
+      progress = true;
+    }
+    loading.erase(loading.begin(), loading.begin() + k);
+    return true;
+  }
+
+  // An idle lane takes its uploaded solves into its batch.
+  bool join(Lane &L) {
+    for (Req *r : L.joining) {
       gmunu_block blk;
       blk.desc = r->r.desc;
       blk.q_n = r->qn;
@@ -192,20 +226,7 @@ struct gmunu_server {
       L.resident++;
       r->in_batch = true;
     }
-    loading.erase(loading.begin(), loading.begin() + k);
-    return true;
-  }
-
-  bool commit_lanes() {
-    for (Lane &L : lane) {
-      if (!L.dirty) continue;
-      if (gmunu_batch_commit(L.b, cs) != GMUNU_OK) return false;
-      if (!L.newly.empty() &&
-          gmunu_batch_init(L.b, L.newly.data(), (int)L.newly.size(), cs) != GMUNU_OK)
-        return false;
-      L.newly.clear();
-      L.dirty = false;
-    }
+    L.joining.clear();
     return true;
   }
 
@@ -226,8 +247,10 @@ struct gmunu_server {
     return ok;
   }
 
-  // Finished downloads: return the memory and publish the result.
-  bool finish_unloads() {
+  // Finished downloads: return the memory and publish the result.  A solve
+  // leaves its lane (commit) before its memory returns, so no later round
+  // reads it.
+  bool finish_unloads(bool &progress) {
     size_t k = 0;
     for (; k < unloading.size(); k++) {
       Req *r = unloading[k];
@@ -236,29 +259,74 @@ struct gmunu_server {
       if (q != hipSuccess) return false;
       pool.release(r->off, r->bytes);
       finish(r, r->status);
+      progress = true;
     }
     unloading.erase(unloading.begin(), unloading.begin() + k);
     return true;
   }
 
-  // After the replays: solves at their end (or stalled) leave.
-  bool check_lanes() {
-    for (Lane &L : lane) {
-      if (!L.resident) continue;
-      if (gmunu_batch_times(L.b, L.t.data(), L.dt.data(), L.ns.data(), L.nf.data(), cs) != GMUNU_OK) return false;
-      for (int s = 0; s < max_slots; s++) {
-        Req *r = L.slot[s];
-        if (!r || !r->in_batch) continue;  // empty, or still uploading
-        r->t = L.t[s];
-        r->steps = L.ns[s];
-        r->nfatal = L.nf[s];
-        const bool done = r->t >= r->r.t_end || (r->r.max_steps > 0 && r->steps >= r->r.max_steps);
-        if (done) {
-          if (!start_unload(L, r, GMUNU_OK)) return false;
-        } else if (!(L.dt[s] > 0.0)) {
-          if (!start_unload(L, r, GMUNU_ESTALL)) return false;
-        }
+  // A lane's round finished: solves at their end (or stalled) leave it.
+  bool check_lane(Lane &L) {
+    if (gmunu_batch_times(L.b, L.t.data(), L.dt.data(), L.ns.data(), L.nf.data(), L.st) != GMUNU_OK) return false;
+    for (int s = 0; s < max_slots; s++) {
+      Req *r = L.slot[s];
+      if (!r || !r->in_batch) continue;  // empty, or still uploading
+      r->t = L.t[s];
+      r->steps = L.ns[s];
+      r->nfatal = L.nf[s];
+      const bool done = r->t >= r->r.t_end || (r->r.max_steps > 0 && r->steps >= r->r.max_steps);
+      if (done) {
+        if (!start_unload(L, r, GMUNU_OK)) return false;
+      } else if (!(L.dt[s] > 0.0)) {
+        if (!start_unload(L, r, GMUNU_ESTALL)) return false;
       }
+    }
+    return true;
+  }
+
+  // Rounds that finished: adapt the round length, retire finished solves.
+  bool poll_lanes(bool &progress) {
+    for (Lane &L : lane) {
+      if (!L.inflight) continue;
+      const hipError_t q = hipEventQuery(L.ev);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return false;
+      L.inflight = false;
+      const double dur = now_s() - L.t_launch;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        info.busy_s += dur;
+      }
+      const double per = dur / L.round;
+      const int want = per > 0.0 ? (int)std::lround(kRoundSeconds / per) : kMaxRound;
+      L.round = std::max(spsync, std::min(kMaxRound, want));
+      if (!check_lane(L)) return false;
+      progress = true;
+    }
+    return true;
+  }
+
+  // Idle lanes: commit changes, initialise new solves, launch a round.
+  bool launch_lanes(bool &progress) {
+    for (Lane &L : lane) {
+      if (L.inflight) continue;
+      if (!L.joining.empty() && !join(L)) return false;
+      if (L.dirty) {
+        if (gmunu_batch_commit(L.b, L.st) != GMUNU_OK) return false;
+        if (!L.newly.empty() && gmunu_batch_init(L.b, L.newly.data(), (int)L.newly.size(), L.st) != GMUNU_OK)
+          return false;
+        L.newly.clear();
+        L.dirty = false;
+      }
+      if (!L.resident) continue;
+      L.t_launch = now_s();
+      for (int k = 0; k < L.round; k++)
+        if (gmunu_batch_step(L.b, cfl, nullptr, 1, L.st) != GMUNU_OK) return false;
+      if (hipEventRecord(L.ev, L.st) != hipSuccess) return false;
+      L.inflight = true;
+      progress = true;
+      std::lock_guard<std::mutex> lk(mu);
+      info.replays += L.round;
     }
     return true;
   }
@@ -294,7 +362,7 @@ struct gmunu_server {
       {
         std::unique_lock<std::mutex> lk(mu);
         if (stop) break;
-        if (resident_total() == 0 && loading.empty() && unloading.empty() && pending.empty())
+        if (resident_total() == 0 && loading.empty() && unloading.empty() && pending.empty() && !any_inflight())
           cv_work.wait(lk, [&] { return stop || !pending.empty(); });
         if (stop) break;
         while (!pending.empty()) {
@@ -310,36 +378,21 @@ struct gmunu_server {
           adm.push_back(r);
         }
       }
-      bool ok = true;
+      bool ok = true, progress = !adm.empty();
       for (Req *r : adm) ok = ok && start_load(r);
-      ok = ok && finish_loads() && commit_lanes();
-      const double t0 = now_s();
-      bool stepped = false;
-      for (Lane &L : lane) {
-        if (!ok || !L.resident) continue;
-        for (int k = 0; k < spsync && ok; k++) ok = gmunu_batch_step(L.b, cfl, nullptr, 1, cs) == GMUNU_OK;
-        stepped = true;
-        std::lock_guard<std::mutex> lk(mu);
-        info.replays += spsync;
-      }
-      if (ok && stepped) {
-        ok = hipEventRecord(ev_step, cs) == hipSuccess && finish_unloads() &&
-             hipEventSynchronize(ev_step) == hipSuccess && check_lanes();
-        std::lock_guard<std::mutex> lk(mu);
-        info.busy_s += now_s() - t0;
-      } else if (ok && (!loading.empty() || !unloading.empty())) {
-        // nothing to step: wait for the oldest copy instead of spinning
-        Req *r = !loading.empty() ? loading.front() : unloading.front();
-        ok = hipEventSynchronize(r->ev) == hipSuccess;
-      }
-      ok = ok && finish_unloads();
+      ok = ok && finish_loads(progress) && poll_lanes(progress) && launch_lanes(progress) &&
+           finish_unloads(progress);
       if (!ok) {
         fail_all();
         break;
       }
       publish();
+      if (!progress) {
+        if (any_inflight() || !loading.empty() || !unloading.empty())
+          std::this_thread::sleep_for(std::chrono::microseconds(20));
+      }
     }
-    (void)hipStreamSynchronize(cs);
+    for (Lane &L : lane) (void)hipStreamSynchronize(L.st);
     (void)hipStreamSynchronize(xs);
   }
 };
@@ -355,10 +408,10 @@ int gmunu_server_create(size_t hbm_bytes, int max_slots, double cfl, int steps_p
   gmunu_server *s = new (std::nothrow) gmunu_server();
   if (!s) return GMUNU_ENOMEM;
   s->cfl = cfl;
-  s->spsync = steps_per_sync;
+  s->spsync = std::min(steps_per_sync, kMaxRound);
   s->max_slots = max_slots;
-  // list capacity: a solve needs at most ~4 tiles of 256 cells per 256 of
-  // its cells (ragged tiles), plus one per block for the remainders
+  // list capacity: a solve needs at most ~4 tiles per 256 of its cells
+  // (ragged tiles), plus one per block for the remainders
   const long max_cells = (long)(hbm_bytes / 232);
   s->maxi = std::min(1L << 30, 4 * (max_cells / 256) + 64L * max_slots + 1024);
   bool ok = hipGetDevice(&s->device) == hipSuccess;
@@ -368,12 +421,13 @@ int gmunu_server_create(size_t hbm_bytes, int max_slots, double cfl, int steps_p
     return GMUNU_ENOMEM;
   }
   s->pool.reset(hbm_bytes);
-  ok = hipStreamCreateWithFlags(&s->cs, hipStreamNonBlocking) == hipSuccess &&
-       hipStreamCreateWithFlags(&s->xs, hipStreamNonBlocking) == hipSuccess &&
-       hipEventCreateWithFlags(&s->ev_step, hipEventDisableTiming) == hipSuccess;
+  ok = hipStreamCreateWithFlags(&s->xs, hipStreamNonBlocking) == hipSuccess;
   for (Lane &L : s->lane) {
     if (!ok) break;
-    ok = gmunu_batch_create(max_slots, max_slots, s->maxi, &L.b) == GMUNU_OK;
+    ok = hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) == hipSuccess &&
+         gmunu_batch_create(max_slots, max_slots, s->maxi, &L.b) == GMUNU_OK;
+    L.round = s->spsync;
     L.slot.assign(max_slots, nullptr);
     for (int k = max_slots - 1; k >= 0; k--) L.free_slots.push_back(k);
     L.t.assign(max_slots, 0.0);
@@ -382,10 +436,11 @@ int gmunu_server_create(size_t hbm_bytes, int max_slots, double cfl, int steps_p
     L.nf.assign(max_slots, 0u);
   }
   if (!ok) {
-    for (Lane &L : s->lane)
+    for (Lane &L : s->lane) {
       if (L.b) gmunu_batch_destroy(L.b);
-    if (s->ev_step) (void)hipEventDestroy(s->ev_step);
-    if (s->cs) (void)hipStreamDestroy(s->cs);
+      if (L.ev) (void)hipEventDestroy(L.ev);
+      if (L.st) (void)hipStreamDestroy(L.st);
+    }
     if (s->xs) (void)hipStreamDestroy(s->xs);
     (void)hipFree(s->arena);
     delete s;
@@ -411,7 +466,7 @@ int gmunu_server_submit(gmunu_server *s, const gmunu_request *req, unsigned long
   r->arr8 = RangePool::round_up(sizeof(double) * 8 * r->nv, kAlign);
   r->arr5 = RangePool::round_up(sizeof(double) * 5 * r->nv, kAlign);
   r->bytes = 3 * r->arr8 + r->arr5;
-  r->lane = req->desc.rk == 2 ? 0 : 1;
+  r->lane = gmunu_server::lane_index(req->desc);
   r->items = batch_items_for(s->lane[r->lane].b, req->desc);
   if (r->bytes > s->pool.capacity() || r->items.stage > s->maxi || r->items.cells > s->maxi ||
       r->items.ghosts > s->maxi) {
@@ -476,10 +531,11 @@ int gmunu_server_destroy(gmunu_server *s) {
     if (r->ev) (void)hipEventDestroy(r->ev);
     delete r;
   }
-  for (Lane &L : s->lane)
+  for (Lane &L : s->lane) {
     if (L.b) gmunu_batch_destroy(L.b);
-  (void)hipEventDestroy(s->ev_step);
-  (void)hipStreamDestroy(s->cs);
+    (void)hipEventDestroy(L.ev);
+    (void)hipStreamDestroy(L.st);
+  }
   (void)hipStreamDestroy(s->xs);
   const int rc = hipFree(s->arena) == hipSuccess ? GMUNU_OK : GMUNU_EHIP;
   delete s;
