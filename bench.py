@@ -233,8 +233,12 @@ def _drive_server(S, reqs, dev, offsets=None, concurrency=None):
         S.submit(p, pr, met, te, ms, prim_out=torch.empty_like(pr), tag=k)
         arrival[k] = at
 
+    last_note = clock()
     while len(recs) < len(reqs):
         now = clock()
+        if now - last_note > 20.0:
+            log(f"[serve]   {len(recs)} of {len(reqs)} done")
+            last_note = now
         if concurrency is None:
             while i < len(reqs) and t0 + offsets[i] <= now:
                 submit(i, t0 + offsets[i])
@@ -266,7 +270,11 @@ def _drive_plain(reqs, offsets, dev, cfl):
     clock = gmu.Server.clock
     t0 = clock() + 0.02
     recs, busy = [], 0.0
+    last_note = clock()
     for k, r in enumerate(reqs):
+        if clock() - last_note > 20.0:
+            log(f"[serve]   plain: {k} of {len(reqs)} done")
+            last_note = clock()
         arr = t0 + offsets[k]
         while clock() < arr:
             time.sleep(min(0.01, max(0.0, arr - clock())))
