@@ -98,7 +98,19 @@ typedef struct gmunu_grid_desc {
   int c2p_maxit;             /* root-finder iteration limit */
   double c2p_tol;            /* relative tolerance of the recovered root */
   int rk;                    /* 3: SSPRK3, 2: SSPRK2 */
+  int recon;                 /* GMUNU_RECON_* (reconstruction of the face states) */
+  int riemann;               /* GMUNU_RIEMANN_* (approximate Riemann solver) */
+  int pp_limiter;            /* 1: positivity-preserving flux limiter (section 2.4) */
+  int c2p;                   /* GMUNU_C2P_* (primitive recovery scheme, section 2.5) */
 } gmunu_grid_desc;
+
+enum {
+  GMUNU_RECON_MC = 0,        /* monotonised-central slopes (2 ghost layers) */
+  GMUNU_RIEMANN_HLLE = 0,    /* HLL with the two-speed bounds of section 2.3 */
+  GMUNU_RIEMANN_TVDLF = 1,   /* local Lax-Friedrichs (Rusanov) */
+  GMUNU_C2P_GRMHD = 0,       /* master-function recovery of section 2.5.2 (any B) */
+  GMUNU_C2P_GRHD_Z = 1       /* z-scheme recovery of section 2.5.1 (B = 0 only; B passed through) */
+};
 
 typedef struct gmunu_ctx gmunu_ctx;
 

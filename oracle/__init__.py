@@ -45,6 +45,7 @@ class _Desc(ctypes.Structure):
         ("rho_max", ctypes.c_double), ("eps_max", ctypes.c_double), ("w_max", ctypes.c_double),
         ("c2p_maxit", ctypes.c_int), ("c2p_tol", ctypes.c_double),
         ("rk", ctypes.c_int),
+        ("recon", ctypes.c_int), ("riemann", ctypes.c_int), ("pp", ctypes.c_int), ("c2p", ctypes.c_int),
     ]
 
 
@@ -85,6 +86,7 @@ def lib():
         L.og_cell_volumes.argtypes = [P, P]
         L.og_mc_faces.argtypes = [ctypes.c_int, P, P, P]
         L.og_point_hlle.argtypes = [ctypes.c_double, P, P, P, P, ctypes.c_int, P]
+        L.og_point_tvdlf.argtypes = [ctypes.c_double, P, P, P, P, ctypes.c_int, P]
         if L.og_desc_size() != ctypes.sizeof(_Desc):
             raise RuntimeError("oracle descriptor layout mismatch")
         _lib = L
@@ -93,7 +95,7 @@ def lib():
 
 DEFAULTS = dict(ng=2, gamma=5.0 / 3.0, rho_atmo=1e-12, k_atmo=100.0, gamma_atmo=2.0,
                 rho_low_factor=100.0, alpha_bh=1e-2, rho_max=float("inf"), eps_max=float("inf"),
-                w_max=1e3, c2p_maxit=200, c2p_tol=1e-15, rk=3)
+                w_max=1e3, c2p_maxit=200, c2p_tol=1e-15, rk=3, recon=0, riemann=0, pp_limiter=0, c2p=0)
 
 
 def make_desc(p: dict) -> _Desc:
@@ -112,6 +114,7 @@ def make_desc(p: dict) -> _Desc:
               "eps_max", "w_max", "c2p_tol"):
         setattr(d, k, float(q[k]))
     d.c2p_maxit, d.rk = int(q["c2p_maxit"]), int(q["rk"])
+    d.recon, d.riemann, d.pp, d.c2p = int(q["recon"]), int(q["riemann"]), int(q["pp_limiter"]), int(q["c2p"])
     return d
 
 
@@ -279,4 +282,11 @@ def point_hlle(gamma, pl, pr, met5, ref3, axis):
     a = [np.ascontiguousarray(x, dtype=np.float64) for x in (pl, pr, met5, ref3)]
     f = np.zeros(8)
     lib().og_point_hlle(gamma, _p(a[0]), _p(a[1]), _p(a[2]), _p(a[3]), axis, _p(f))
+    return f
+
+
+def point_tvdlf(gamma, pl, pr, met5, ref3, axis):
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (pl, pr, met5, ref3)]
+    f = np.zeros(8)
+    lib().og_point_tvdlf(gamma, _p(a[0]), _p(a[1]), _p(a[2]), _p(a[3]), axis, _p(f))
     return f

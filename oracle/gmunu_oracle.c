@@ -54,6 +54,7 @@ typedef struct {
   int c2p_maxit;
   double c2p_tol;
   int rk;
+  int recon, riemann, pp, c2p;  /* scheme options: 0 = MC, HLLE, off, GRMHD recovery */
 } og_desc;
 
 /* ------------------------------------------------------------------ grid */
@@ -298,11 +299,11 @@ static double c2p_fa(const c2p_consts *c, double mu, double *dfa) {
 
 /* Illinois (modified regula falsi) root of g on the bracket [a, b] with
  * g(a) < 0 < g(b) (Dowell & Jarratt 1971, as used in section 2.5). */
-typedef double (*scalar_fn)(const c2p_consts *, double);
-static double fa_only(const c2p_consts *c, double mu) { return c2p_fa(c, mu, NULL); }
-static double f_only(const c2p_consts *c, double mu) { return c2p_f(c, mu, NULL); }
+typedef double (*scalar_fn)(const void *, double);
+static double fa_only(const void *c, double mu) { return c2p_fa((const c2p_consts *)c, mu, NULL); }
+static double f_only(const void *c, double mu) { return c2p_f((const c2p_consts *)c, mu, NULL); }
 
-static double illinois(const c2p_consts *c, scalar_fn g, double a, double b, double tol, int maxit, int *iters, int *ok) {
+static double illinois(const void *c, scalar_fn g, double a, double b, double tol, int maxit, int *iters, int *ok) {
   double fa = g(c, a), fb = g(c, b);
   *ok = 1;
   *iters = 0;
@@ -335,12 +336,141 @@ static void atmosphere_prim(const og_desc *d, double B[3], double pr[NV]) {
   for (int i = 0; i < 3; i++) pr[BB1 + i] = B[i];
 }
 
+/* Error handling after a recovery (section 2.5.3), shared by both schemes:
+ * atmosphere below rho_min, EOS limits, the velocity limit W_max (rescaled
+ * only in the low-density or black-hole region, else fatal).  capped: the
+ * recovery already had to cap the velocity (z-scheme, reading of the
+ * bracket when S >= tau + D), treated like W > W_max. */
+static int finish_recovery(const og_desc *d, double D, double rho, double eps, double W, double vu[3],
+                           const double gd[3], double alpha, double Bu[3], double pr[NV], int flags, int capped) {
+  double rho_min = d->rho_atmo;
+  double rho_low = d->rho_low_factor * d->rho_atmo;
+  if (rho < rho_min) {
+    atmosphere_prim(d, Bu, pr);
+    return flags | F_ATMO;
+  }
+  if (rho > d->rho_max) {
+    flags |= F_FATAL_RHO;
+    rho = d->rho_max;
+  }
+  int soft = (rho < rho_low) || (alpha < d->alpha_bh);
+  if (eps < 0.0) {
+    eps = 0.0;
+    flags |= F_EPS_CLAMP;
+  }
+  if (eps > d->eps_max) {
+    eps = d->eps_max;
+    flags |= soft ? F_EPS_CLAMP : F_FATAL_EPS;
+  }
+  if (capped) flags |= soft ? F_V_CLAMP : F_FATAL_V;
+  if (W > d->w_max) {
+    if (soft) {
+      /* rescale v to v_max keeping D: rho = D / W_max, then re-limit */
+      double vmax2 = 1.0 - 1.0 / (d->w_max * d->w_max);
+      double v2 = 0.0;
+      for (int i = 0; i < 3; i++) v2 += vu[i] * gd[i] * vu[i];
+      double sc = sqrt(vmax2 / v2);
+      for (int i = 0; i < 3; i++) vu[i] *= sc;
+      W = d->w_max;
+      rho = D / W;
+      if (rho < rho_min) rho = rho_min;
+      if (rho > d->rho_max) rho = d->rho_max;
+      if (eps < 0.0) eps = 0.0;
+      if (eps > d->eps_max) eps = d->eps_max;
+      flags |= F_V_CLAMP;
+    } else {
+      flags |= F_FATAL_V;
+    }
+  }
+  pr[RHO] = rho;
+  for (int i = 0; i < 3; i++) pr[WV1 + i] = W * vu[i];
+  pr[PRS] = (d->gamma - 1.0) * rho * eps;
+  for (int i = 0; i < 3; i++) pr[BB1 + i] = Bu[i];
+  return flags;
+}
+
+/* --- GRHD recovery (section 2.5.1): the z = W v root on [z_-, z_+] --- */
+
+typedef struct {
+  double D, r, q, rho_min, rho_max, eps_min, eps_max, gam;
+} z_consts;
+
+/* f(z) = z - r / h(z) with rho(z) = D / W(z), eps(z) = W q - z r +
+ * z^2 / (1 + W), both limited to the EOS range inside every evaluation,
+ * W(z) = sqrt(1 + z^2).  On request: W, the raw rho and eps, and the h used. */
+static double z_f(const z_consts *c, double z, double *W_out, double *rho_out, double *eps_out, double *h_out) {
+  double W = sqrt(1.0 + z * z);
+  double rho = c->D / W;
+  double eps = W * c->q - z * c->r + z * z / (1.0 + W);
+  if (W_out) { *W_out = W; *rho_out = rho; *eps_out = eps; }
+  rho = fmax(fmin(c->rho_max, rho), c->rho_min);
+  eps = fmax(fmin(c->eps_max, eps), c->eps_min);
+  double p = (c->gam - 1.0) * rho * eps;
+  double a = p / (rho * (1.0 + eps));
+  double h = (1.0 + eps) * (1.0 + a);
+  if (h_out) *h_out = h;
+  return z - c->r / h;
+}
+static double zf_only(const void *c, double z) { return z_f((const z_consts *)c, z, NULL, NULL, NULL, NULL); }
+
+static int c2p_point_z(const og_desc *d, const double qc[NV], double psi, double alpha, const double ref[3],
+                       double pr[NV], int *iters_out) {
+  double psi2 = psi * psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
+  double gd[3], gu[3];
+  for (int i = 0; i < 3; i++) { gd[i] = psi4 * ref[i]; gu[i] = 1.0 / gd[i]; }
+  double D = qc[QD] / psi6, tau = qc[QTAU] / psi6;
+  double Sd[3], Bu[3];
+  for (int i = 0; i < 3; i++) { Sd[i] = qc[QS1 + i] / psi6; Bu[i] = qc[QB1 + i] / psi6; }
+  if (iters_out) *iters_out = 0;
+  if (!(D >= d->rho_atmo)) {
+    atmosphere_prim(d, Bu, pr);
+    return F_ATMO;
+  }
+  /* step 1 */
+  double S2 = 0.0;
+  for (int i = 0; i < 3; i++) S2 += gu[i] * Sd[i] * Sd[i];
+  double S = sqrt(S2);
+  z_consts c;
+  c.D = D;
+  c.r = S / D;
+  c.q = tau / D;
+  c.rho_min = d->rho_atmo;
+  c.rho_max = d->rho_max;
+  c.eps_min = 0.0;
+  c.eps_max = d->eps_max;
+  c.gam = d->gamma;
+  double k = S / (tau + D);
+  /* a state with k beyond the one of W = W_max (or k >= 1, no finite W)
+   * is recovered with k at that limit and flagged like W > W_max */
+  double kmax = sqrt(1.0 - 1.0 / (d->w_max * d->w_max));
+  int capped = 0;
+  if (!(k <= kmax)) {
+    k = kmax;
+    capped = 1;
+  }
+  /* step 2 */
+  double zm = 0.5 * k / sqrt(1.0 - 0.25 * k * k);
+  double zp = k / sqrt(1.0 - k * k);
+  /* step 3 */
+  int iters = 0, ok = 1, flags = 0;
+  double z = illinois(&c, zf_only, zm, zp, d->c2p_tol, d->c2p_maxit, &iters, &ok);
+  if (iters_out) *iters_out = iters;
+  if (!ok) flags |= F_NOCONV;
+  /* step 4 */
+  double W, rho, eps, h;
+  z_f(&c, z, &W, &rho, &eps, &h);
+  double vu[3];
+  for (int i = 0; i < 3; i++) vu[i] = (gu[i] * Sd[i] / D) / (h * W);
+  return finish_recovery(d, D, rho, eps, W, vu, gd, alpha, Bu, pr, flags, capped);
+}
+
 /* Recovery of the primitives from the densitised conserved variables at one
- * cell (section 2.5.2 steps 1-4) followed by the error handling of section
- * 2.5.3.  Returns the flag bits; *iters receives the master-function
- * iteration count. */
+ * cell (section 2.5.2 steps 1-4; with c2p = 1 the GRHD z-scheme of section
+ * 2.5.1) followed by the error handling of section 2.5.3.  Returns the flag
+ * bits; *iters receives the root-finder iteration count. */
 int og_c2p_point(const og_desc *d, const double qc[NV], double psi, double alpha,
                  const double ref[3], double pr[NV], int *iters_out) {
+  if (d->c2p == 1) return c2p_point_z(d, qc, psi, alpha, ref, pr, iters_out);
   double psi2 = psi * psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
   double gd[3], gu[3];
   for (int i = 0; i < 3; i++) { gd[i] = psi4 * ref[i]; gu[i] = 1.0 / gd[i]; }
@@ -426,49 +556,7 @@ int og_c2p_point(const og_desc *d, const double qc[NV], double psi, double alpha
   double vu[3];
   for (int i = 0; i < 3; i++) vu[i] = mu * e.chi * (ru[i] + mu * c.rB * Bcu[i]);
 
-  /* error handling, section 2.5.3 */
-  double rho_low = d->rho_low_factor * d->rho_atmo;
-  if (rho < rho_min) {
-    atmosphere_prim(d, Bu, pr);
-    return flags | F_ATMO;
-  }
-  if (rho > d->rho_max) {
-    flags |= F_FATAL_RHO;
-    rho = d->rho_max;
-  }
-  int soft = (rho < rho_low) || (alpha < d->alpha_bh);
-  if (eps < 0.0) {
-    eps = 0.0;
-    flags |= F_EPS_CLAMP;
-  }
-  if (eps > d->eps_max) {
-    eps = d->eps_max;
-    flags |= soft ? F_EPS_CLAMP : F_FATAL_EPS;
-  }
-  if (W > d->w_max) {
-    if (soft) {
-      /* rescale v to v_max keeping D: rho = D / W_max, then re-limit */
-      double vmax2 = 1.0 - 1.0 / (d->w_max * d->w_max);
-      double v2 = 0.0;
-      for (int i = 0; i < 3; i++) v2 += vu[i] * gd[i] * vu[i];
-      double sc = sqrt(vmax2 / v2);
-      for (int i = 0; i < 3; i++) vu[i] *= sc;
-      W = d->w_max;
-      rho = D / W;
-      if (rho < rho_min) rho = rho_min;
-      if (rho > d->rho_max) rho = d->rho_max;
-      if (eps < 0.0) eps = 0.0;
-      if (eps > d->eps_max) eps = d->eps_max;
-      flags |= F_V_CLAMP;
-    } else {
-      flags |= F_FATAL_V;
-    }
-  }
-  pr[RHO] = rho;
-  for (int i = 0; i < 3; i++) pr[WV1 + i] = W * vu[i];
-  pr[PRS] = (d->gamma - 1.0) * rho * eps;
-  for (int i = 0; i < 3; i++) pr[BB1 + i] = Bu[i];
-  return flags;
+  return finish_recovery(d, D, rho, eps, W, vu, gd, alpha, Bu, pr, flags, 0);
 }
 
 /* --------------------------------------------------- exported point calls */
@@ -521,6 +609,14 @@ static void load_metric(const og_desc *d, const double *met, long c, double m[5]
  * (i,j,k): MC-reconstructed left/right primitives, face metric as the mean
  * of the two neighbouring centres, then HLLE (section 2.1 discretised
  * equation; section 3 solver settings). */
+/* Local Lax-Friedrichs (Rusanov) flux, the solver named TVDLF in section 3:
+ * the mean of the two fluxes minus the largest speed magnitude c times half
+ * the jump of the conserved variables. */
+static void tvdlf(const double fl[NV], const double fr[NV], const double ql[NV], const double qr[NV], double c,
+                  double f[NV]) {
+  for (int v = 0; v < NV; v++) f[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * c * (qr[v] - ql[v]);
+}
+
 static void face_flux_x(const og_desc *d, const double *prim, const double *met, int a, int f,
                         int i, int j, int k, double out[NV], double *absterms) {
   int cell[3] = {i, j, k};
@@ -564,7 +660,11 @@ static void face_flux_x(const og_desc *d, const double *prim, const double *met,
   speeds_from_state(d->gamma, &sl, a, &lml, &lpl);
   speeds_from_state(d->gamma, &sr, a, &lmr, &lpr);
   double fh[NV];
-  hlle(fl, fr, ql, qr, fmin(lml, lmr), fmax(lpl, lpr), fh);
+  if (d->riemann == 1) {
+    tvdlf(fl, fr, ql, qr, fmax(fmax(fabs(lml), fabs(lpl)), fmax(fabs(lmr), fabs(lpr))), fh);
+  } else {
+    hlle(fl, fr, ql, qr, fmin(lml, lmr), fmax(lpl, lpr), fh);
+  }
   for (int v = 0; v < NV; v++) out[v] = fh[v] * area;
   if (absterms) {
     /* magnitude of the terms summed by the HLLE formula, with the states'
@@ -573,9 +673,14 @@ static void face_flux_x(const og_desc *d, const double *prim, const double *met,
     abs_terms_from_state(&sl, a, ual, fal);
     abs_terms_from_state(&sr, a, uar, far_);
     double ap = fmax(0.0, fmax(lpl, lpr)), am = fmin(0.0, fmin(lml, lmr)), den = ap - am;
+    double cmax = fmax(fmax(fabs(lml), fabs(lpl)), fmax(fabs(lmr), fabs(lpr)));
     for (int v = 0; v < NV; v++) {
-      double t = den < 1e-300 ? 0.5 * (fal[v] + far_[v])
-                              : (ap * fal[v] - am * far_[v] - ap * am * (uar[v] + ual[v])) / den;
+      double t;
+      if (d->riemann == 1)
+        t = 0.5 * (fal[v] + far_[v]) + 0.5 * cmax * (uar[v] + ual[v]);
+      else
+        t = den < 1e-300 ? 0.5 * (fal[v] + far_[v])
+                         : (ap * fal[v] - am * far_[v] - ap * am * (uar[v] + ual[v])) / den;
       absterms[v] = t * area;
     }
   }
@@ -1084,4 +1189,20 @@ void og_point_hlle(double gam, const double pl[NV], const double pr[NV], const d
   speeds_from_state(gam, &sl, a, &lml, &lpl);
   speeds_from_state(gam, &sr, a, &lmr, &lpr);
   hlle(fl, fr, ql, qr, fmin(lml, lmr), fmax(lpl, lpr), f);
+}
+
+/* The local Lax-Friedrichs flux between two primitive states at one point. */
+void og_point_tvdlf(double gam, const double pl[NV], const double pr[NV], const double met[5], const double ref[3],
+                    int a, double f[NV]) {
+  pstate sl, sr;
+  point_state(gam, pl, met[0], met[1], met + 2, ref, &sl);
+  point_state(gam, pr, met[0], met[1], met + 2, ref, &sr);
+  double ql[NV], qr[NV], fl[NV], fr[NV], lml, lpl, lmr, lpr;
+  cons_from_state(&sl, ql);
+  cons_from_state(&sr, qr);
+  flux_from_state(&sl, a, fl);
+  flux_from_state(&sr, a, fr);
+  speeds_from_state(gam, &sl, a, &lml, &lpl);
+  speeds_from_state(gam, &sr, a, &lmr, &lpr);
+  tvdlf(fl, fr, ql, qr, fmax(fmax(fabs(lml), fabs(lpl)), fmax(fabs(lmr), fabs(lpr))), f);
 }

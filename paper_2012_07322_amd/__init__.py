@@ -37,12 +37,13 @@ class GridDesc(ctypes.Structure):
         ("rho_max", ctypes.c_double), ("eps_max", ctypes.c_double), ("w_max", ctypes.c_double),
         ("c2p_maxit", ctypes.c_int), ("c2p_tol", ctypes.c_double),
         ("rk", ctypes.c_int),
+        ("recon", ctypes.c_int), ("riemann", ctypes.c_int), ("pp_limiter", ctypes.c_int), ("c2p", ctypes.c_int),
     ]
 
 
 DEFAULTS = dict(ng=2, gamma=5.0 / 3.0, rho_atmo=1e-12, k_atmo=100.0, gamma_atmo=2.0,
                 rho_low_factor=100.0, alpha_bh=1e-2, rho_max=math.inf, eps_max=math.inf,
-                w_max=1e3, c2p_maxit=200, c2p_tol=1e-15, rk=3)
+                w_max=1e3, c2p_maxit=200, c2p_tol=1e-15, rk=3, recon=0, riemann=0, pp_limiter=0, c2p=0)
 
 _lib = None
 _P = ctypes.c_void_p
@@ -93,6 +94,8 @@ def make_desc(p: dict) -> GridDesc:
               "w_max", "c2p_tol"):
         setattr(d, k, float(q[k]))
     d.c2p_maxit, d.rk = int(q["c2p_maxit"]), int(q["rk"])
+    d.recon, d.riemann, d.pp_limiter, d.c2p = (int(q["recon"]), int(q["riemann"]), int(q["pp_limiter"]),
+                                               int(q["c2p"]))
     return d
 
 

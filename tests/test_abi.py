@@ -37,7 +37,7 @@ def test_descriptor_layout_matches_header():
     off = {f[0]: getattr(gmu.GridDesc, f[0]).offset for f in gmu.GridDesc._fields_}
     assert off["ndim"] == 0 and off["coord"] == 4 and off["n"] == 8 and off["ng"] == 20
     assert off["xmin"] == 24 and off["dx"] == 48 and off["bc"] == 72 and off["gamma"] == 96
-    assert ctypes.sizeof(gmu.GridDesc) == off["rk"] + 8
+    assert off["recon"] == off["rk"] + 4 and ctypes.sizeof(gmu.GridDesc) == off["c2p"] + 8
 
 
 @pytest.mark.parametrize("mutate", [

@@ -497,3 +497,125 @@ def test_tov_fixture_matches_printed_star_numbers():
     assert su["R_iso"] == pytest.approx(4.267, abs=1e-3)
     st = W.tov_isotropic(1.346e-3)
     assert st["Mb"] == pytest.approx(su["Mb"], rel=3e-4)
+
+
+# ------------------------------------------ GRHD z-scheme recovery (2.5.1)
+
+def _hydro_states(n, seed):
+    pr, psi, al, ref = W.random_states(n, seed=seed)
+    pr[5:8] = 0.0
+    return pr, psi, al, ref
+
+
+def test_z_scheme_round_trip_and_agreement_with_the_grmhd_recovery():
+    """With B = 0 both recoveries invert the same prim -> con map: the
+    z-scheme returns the primitives it started from, and the same answer as
+    the master-function recovery of section 2.5.2, to the round-off of the
+    inversion (rho, W v^i to 1e-12; eps to 1e-12 of max(eps, tau/D))."""
+    pr, psi, al, ref = _hydro_states(1500, seed=11)
+    pz = _c2p_desc(c2p=1)
+    pm = _c2p_desc(c2p=0)
+    checked = 0
+    for c in range(pr.shape[1]):
+        met = np.array([psi[c], al[c], 0, 0, 0])
+        q = oracle.point_prim2con(5 / 3, pr[:, c], met, ref[:, c])
+        eps = pr[4, c] / (2 / 3 * pr[0, c])
+        tD = q[4] / q[0]
+        if tD > 1e3 * eps:
+            continue
+        gd = psi[c] ** 4 * ref[:, c]
+        rz, fz, _ = oracle.c2p_point(pz, q, psi[c], al[c], ref[:, c])
+        rm, fm, _ = oracle.c2p_point(pm, q, psi[c], al[c], ref[:, c])
+        assert fz == 0 and fm == 0
+        checked += 1
+        u = np.sqrt((gd * pr[1:4, c] ** 2).sum())
+        for r in (rz, rm):
+            assert abs(r[0] - pr[0, c]) <= 1e-12 * pr[0, c]
+            assert np.all(np.abs(r[1:4] - pr[1:4, c]) * np.sqrt(gd) <= 1e-12 * max(u, 1e-3))
+            assert abs(r[4] / (2 / 3 * r[0]) - eps) <= 1e-12 * max(eps, tD)
+        assert abs(rz[0] - rm[0]) <= 2e-12 * rm[0]
+        assert np.array_equal(rz[5:8], np.zeros(3))
+    assert checked > 500
+
+
+def test_z_scheme_static_state_and_error_branches():
+    p = _c2p_desc(c2p=1, rho_atmo=1e-10, k_atmo=100.0, gamma_atmo=2.0, w_max=10.0)
+    # S = 0: the bracket is [0, 0], z = 0, no iteration, v exactly 0
+    q = oracle.point_prim2con(5 / 3, [2.0, 0, 0, 0, 0.3, 0, 0, 0], [1, 1, 0, 0, 0], [1, 1, 1])
+    r, fl, it = oracle.c2p_point(p, q, 1.0, 1.0, [1, 1, 1])
+    assert fl == 0 and it == 0
+    assert np.array_equal(r[1:4], np.zeros(3))
+    np.testing.assert_allclose(r[[0, 4]], [2.0, 0.3], rtol=1e-15)
+    # D below rho_min: atmosphere
+    q = oracle.point_prim2con(5 / 3, [1e-12, 0.1, 0, 0, 1e-14, 0, 0, 0], [1, 1, 0, 0, 0], [1, 1, 1])
+    r, fl, _ = oracle.c2p_point(p, q, 1.0, 1.0, [1, 1, 1])
+    assert fl & oracle.FLAG_ATMO
+    # S >= tau + D has no finite W: capped at W_max, fatal at high density,
+    # a velocity clamp at low density
+    for rho, want in ((1.0, oracle.FLAG_FATAL_V), (5e-9, oracle.FLAG_V_CLAMP)):
+        q = oracle.point_prim2con(5 / 3, [rho, 3.0, 0, 0, 0.1 * rho, 0, 0, 0], [1, 1, 0, 0, 0], [1, 1, 1])
+        q[1] = 1.01 * (q[4] + q[0])
+        r, fl, _ = oracle.c2p_point(p, q, 1.0, 1.0, [1, 1, 1])
+        assert fl & want
+        assert math.sqrt(1 + r[1] ** 2) <= 10.0 * (1 + 1e-12)
+
+
+def test_z_scheme_tube_agrees_with_the_grmhd_recovery():
+    """A full evolution of the relativistic shock tube with either recovery:
+    the two agree to far below the scheme's error, and the z-scheme run
+    converges to the exact solution like the other."""
+    rs = RiemannSRHD((10, 40 / 3, 0), (1, 0, 0), 5 / 3)
+    out = {}
+    for c2p in (0, 1):
+        p, pr, met = W.srhd_shock_tube(200)
+        p["c2p"] = c2p
+        oracle.fill_ghosts(p, pr)
+        q = oracle.prim2con(p, pr, met)
+        s, t, nf = oracle.evolve(p, q, pr, met, 0.4, 0.0, 0.4)
+        assert nf == 0 and abs(t - 0.4) < 1e-14
+        out[c2p] = oracle.interior(p, pr)[:, 0, 0]
+    d = np.abs(out[1] - out[0]).max(axis=1) / (np.abs(out[0]).max(axis=1) + 1e-300)
+    assert d.max() < 1e-8
+    dx = p["dx"][0]
+    ex = np.array([rs.cell_average(i * dx, (i + 1) * dx, 0.4, 0.5)[0] for i in range(200)])
+    assert np.sum(np.abs(out[1][0] - ex)) * dx < 0.06
+
+
+# ----------------------------------------------------- TVDLF flux (section 3)
+
+def test_tvdlf_consistency_and_diffusion():
+    """F(U, U) = f(U) for the local Lax-Friedrichs flux; on the shock tube it
+    converges at first order and is at least as diffusive as HLLE."""
+    pr, psi, al, ref = W.random_states(100, seed=8)
+    for c in range(100):
+        met = [psi[c], al[c], 0, 0, 0]
+        for ax in range(3):
+            f, _ = oracle.point_flux(5 / 3, pr[:, c], met, ref[:, c], ax)
+            fl = oracle.point_tvdlf(5 / 3, pr[:, c], pr[:, c], met, ref[:, c], ax)
+            np.testing.assert_allclose(fl, f, rtol=0, atol=1e-13 * (np.abs(f).max() + 1e-300))
+    rs = RiemannSRHD((10, 40 / 3, 0), (1, 0, 0), 5 / 3)
+    err = {}
+    for riemann in (0, 1):
+        for n in (100, 400):
+            p, pr, met = W.srhd_shock_tube(n)
+            p["riemann"] = riemann
+            oracle.fill_ghosts(p, pr)
+            q = oracle.prim2con(p, pr, met)
+            oracle.evolve(p, q, pr, met, 0.4, 0.0, 0.4)
+            dx = p["dx"][0]
+            ex = np.array([rs.cell_average(i * dx, (i + 1) * dx, 0.4, 0.5)[0] for i in range(n)])
+            err[riemann, n] = np.sum(np.abs(oracle.interior(p, pr)[0, 0, 0] - ex)) * dx
+    assert err[1, 100] / err[1, 400] > 2.5
+    assert err[1, 400] >= err[0, 400] and err[1, 400] < 0.05
+
+
+@pytest.mark.parametrize("coord", [W.CYL, W.SPH])
+def test_tvdlf_keeps_a_uniform_static_state(coord):
+    """F(U, U) = f(U) makes the uniform static state static with TVDLF too."""
+    p, pr, met = W.uniform_state(coord, ndim=3, n=(8, 8, 4), pres=0.7)
+    p["riemann"] = 1
+    oracle.fill_ghosts(p, pr)
+    L = oracle.interior(p, oracle.rhs(p, pr, met))
+    g = oracle.cell_geometry(p, 0, 0, 0)
+    scale = 0.7 * (abs(g[2]) + abs(g[1])) / g[0]
+    assert np.abs(L).max() <= 8e-16 * max(scale, 1.0)
