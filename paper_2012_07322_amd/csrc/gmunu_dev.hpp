@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/gmunu.h"
+
 namespace gm {
 
 constexpr int NV = 8;
@@ -53,6 +55,8 @@ struct Grid {
   double rho_atmo, p_atmo, rho_low, alpha_bh, rho_max, eps_max, w_max;
   int maxit;
   double tol;
+  int riemann;  // GMUNU_RIEMANN_*
+  int c2p;      // GMUNU_C2P_*
   int bc[3][2];
   Geo geo;
 };
@@ -309,6 +313,56 @@ __device__ __forceinline__ double illinois_root(Fn f, double lo, double hi, doub
   return xb;
 }
 
+// Error handling after a recovery (section 2.5.3), shared by both schemes:
+// atmosphere below rho_min, EOS limits, the velocity limit W_max (rescaled
+// only in the low-density or black-hole region, else fatal).  capped: the
+// recovery already had to cap the velocity, treated like W > W_max.  Writes
+// pr[0..4] (pr[5..7] hold B already).
+__device__ __forceinline__ int c2p_finish(const Grid &G, double D, double rho, double eps, double W, double *v,
+                                          const double *gd, double alpha, int flags, bool capped, double *pr) {
+  if (rho < G.rho_atmo) {
+    pr[0] = G.rho_atmo;
+    pr[1] = pr[2] = pr[3] = 0.0;
+    pr[4] = G.p_atmo;
+    return flags | FL_ATMO;
+  }
+  if (rho > G.rho_max) {
+    flags |= FL_FRHO;
+    rho = G.rho_max;
+  }
+  const bool soft = (rho < G.rho_low) || (alpha < G.alpha_bh);
+  if (eps < 0.0) {
+    eps = 0.0;
+    flags |= FL_EPS;
+  }
+  if (eps > G.eps_max) {
+    eps = G.eps_max;
+    flags |= soft ? FL_EPS : FL_FEPS;
+  }
+  if (capped) flags |= soft ? FL_V : FL_FV;
+  if (W > G.w_max) {
+    if (soft) {
+      const double vmax2 = 1.0 - rcp(G.w_max * G.w_max);
+      const double v2 = gd[0] * v[0] * v[0] + gd[1] * v[1] * v[1] + gd[2] * v[2] * v[2];
+      const double sc = sqrt(vmax2 * rcp(v2));
+#pragma unroll
+      for (int a = 0; a < 3; a++) v[a] *= sc;
+      W = G.w_max;
+      rho = fmax(fmin(D / W, G.rho_max), G.rho_atmo);
+      eps = fmax(fmin(eps, G.eps_max), 0.0);
+      flags |= FL_V;
+    } else {
+      flags |= FL_FV;
+    }
+  }
+  pr[0] = rho;
+  pr[1] = W * v[0];
+  pr[2] = W * v[1];
+  pr[3] = W * v[2];
+  pr[4] = G.gm1 * rho * eps;
+  return flags;
+}
+
 // Primitive recovery of one cell from densitised q (section 2.5.2) and the
 // error handling of section 2.5.3.  Returns flag bits; pr receives the
 // primitives (atmosphere / limited values where flagged).
@@ -405,48 +459,94 @@ __device__ __forceinline__ int c2p_cell(const Grid &G, const double *qc, double 
   double v[3];
 #pragma unroll
   for (int a = 0; a < 3; a++) v[a] = mu * chi * (ru[a] + mu * c.rb * Bc[a]);
+  return c2p_finish(G, D, rho, eps, W, v, gd, alpha, flags, false, pr);
+}
 
-  // error handling, section 2.5.3
-  if (rho < G.rho_atmo) {
+// GRHD recovery (section 2.5.1): f(z) = z - r / h(z) with z = W v,
+// W = sqrt(1 + z^2), rho = D / W, eps = W q - z r + z^2 / (1 + W) limited
+// to the EOS range inside each evaluation; for the ideal gas
+// h = (1 + eps)(1 + a) = 1 + Gamma eps.
+__device__ __forceinline__ double z_master(const Grid &G, double D, double r, double q, double z, double *Wout,
+                                           double *rho_raw, double *eps_raw, double *h_out) {
+  const double z2 = z * z;
+  const double iW = rsq(1.0 + z2);
+  const double W = (1.0 + z2) * iW;
+  const double eps_r = W * q - z * r + z2 * rcp(1.0 + W);
+  const double eps = fmax(fmin(G.eps_max, eps_r), 0.0);
+  const double h = 1.0 + G.gam * eps;
+  if (Wout) {
+    *Wout = W;
+    *rho_raw = D * iW;
+    *eps_raw = eps_r;
+    *h_out = h;
+  }
+  return z - r * rcp(h);
+}
+
+// Primitive recovery of one cell by the z-scheme (B is passed through: the
+// scheme is for B = 0) and the error handling of section 2.5.3.
+__device__ __forceinline__ int c2p_cell_z(const Grid &G, const double *qc, double psi, double alpha, double g1,
+                                          double g2, double *pr) {
+  const double psi2 = psi * psi, psi4 = psi2 * psi2;
+  const double ipsi6 = rcp(psi4 * psi2);
+  const double gd[3] = {psi4, psi4 * g1, psi4 * g2};
+  const double D = qc[0] * ipsi6;
+#pragma unroll
+  for (int a = 0; a < 3; a++) pr[5 + a] = qc[5 + a] * ipsi6;
+  if (!(D >= G.rho_atmo)) {
     pr[0] = G.rho_atmo;
     pr[1] = pr[2] = pr[3] = 0.0;
     pr[4] = G.p_atmo;
-    return flags | FL_ATMO;
+    return FL_ATMO;
   }
-  if (rho > G.rho_max) {
-    flags |= FL_FRHO;
-    rho = G.rho_max;
-  }
-  const bool soft = (rho < G.rho_low) || (alpha < G.alpha_bh);
-  if (eps < 0.0) {
-    eps = 0.0;
-    flags |= FL_EPS;
-  }
-  if (eps > G.eps_max) {
-    eps = G.eps_max;
-    flags |= soft ? FL_EPS : FL_FEPS;
-  }
-  if (W > G.w_max) {
-    if (soft) {
-      const double vmax2 = 1.0 - rcp(G.w_max * G.w_max);
-      const double v2 = gd[0] * v[0] * v[0] + gd[1] * v[1] * v[1] + gd[2] * v[2] * v[2];
-      const double sc = sqrt(vmax2 * rcp(v2));
+  const double tau = qc[4] * ipsi6;
+  double Su[3], S2 = 0.0;
 #pragma unroll
-      for (int a = 0; a < 3; a++) v[a] *= sc;
-      W = G.w_max;
-      rho = fmax(fmin(D / W, G.rho_max), G.rho_atmo);
-      eps = fmax(fmin(eps, G.eps_max), 0.0);
-      flags |= FL_V;
-    } else {
-      flags |= FL_FV;
-    }
+  for (int a = 0; a < 3; a++) {
+    const double Sd = qc[1 + a] * ipsi6;
+    Su[a] = Sd * rcp(gd[a]);
+    S2 += Su[a] * Sd;
   }
-  pr[0] = rho;
-  pr[1] = W * v[0];
-  pr[2] = W * v[1];
-  pr[3] = W * v[2];
-  pr[4] = G.gm1 * rho * eps;
-  return flags;
+  const double S = sqrt_pos(S2);
+  const double iD = rcp(D);
+  const double r = S * iD, q = tau * iD;
+  double k = S * rcp(tau + D);
+  // beyond the k of W = W_max (or k >= 1: no finite W) the state is taken at
+  // that limit and flagged like W > W_max
+  const double kmax = sqrt_pos(1.0 - rcp(G.w_max * G.w_max));
+  const bool capped = !(k <= kmax);
+  if (capped) k = kmax;
+  const double zm = 0.5 * k * rsq(1.0 - 0.25 * k * k);
+  const double zp = k * rsq(1.0 - k * k);
+  auto f = [&](double z) { return z_master(G, D, r, q, z, nullptr, nullptr, nullptr, nullptr); };
+  int flags = 0;
+  double z;
+  const double fm = f(zm), fp = f(zp);
+  if (fp == 0.0) {
+    z = zp;
+  } else if (fm == 0.0) {
+    z = zm;
+  } else if ((fm < 0.0) == (fp < 0.0)) {
+    flags |= FL_NOCONV;
+    z = fabs(fm) < fabs(fp) ? zm : zp;
+  } else {
+    int its;
+    bool ok;
+    z = illinois_root(f, zm, zp, fm, fp, G.tol, G.maxit, its, ok);
+    if (!ok) flags |= FL_NOCONV;
+  }
+  double W, rho, eps, h;
+  z_master(G, D, r, q, z, &W, &rho, &eps, &h);
+  const double s = iD * rcp(h * W);
+  double v[3] = {Su[0] * s, Su[1] * s, Su[2] * s};
+  return c2p_finish(G, D, rho, eps, W, v, gd, alpha, flags, capped, pr);
+}
+
+// Recovery by the scheme the grid selects.
+__device__ __forceinline__ int c2p_any(const Grid &G, const double *qc, double psi, double alpha, double g1,
+                                       double g2, double *pr) {
+  return G.c2p == GMUNU_C2P_GRHD_Z ? c2p_cell_z(G, qc, psi, alpha, g1, g2, pr)
+                                   : c2p_cell(G, qc, psi, alpha, g1, g2, pr);
 }
 
 }  // namespace gm

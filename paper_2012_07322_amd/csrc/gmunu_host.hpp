@@ -89,6 +89,8 @@ inline GeoOffsets setup_grid(const gmunu_grid_desc &d, Grid &G, std::vector<doub
   G.w_max = d.w_max;
   G.maxit = d.c2p_maxit;
   G.tol = d.c2p_tol;
+  G.riemann = d.riemann;
+  G.c2p = d.c2p;
 
   auto put = [&](const std::vector<double> &v) {
     size_t off = tab.size();

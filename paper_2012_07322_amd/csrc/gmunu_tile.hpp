@@ -60,6 +60,16 @@ __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC
   double UL[NV], FL[NV], UR[NV], FR[NV], lmL, lpL, lmR, lpR;
   state_flux<D>(G.gam, G.gfac, pl, psi4, psi6, alpha, beta, g1, g2, gud, UL, FL, lmL, lpL);
   state_flux<D>(G.gam, G.gfac, pr, psi4, psi6, alpha, beta, g1, g2, gud, UR, FR, lmR, lpR);
+  if (G.riemann == GMUNU_RIEMANN_TVDLF) {
+    // local Lax-Friedrichs: the largest speed magnitude of both states
+    const double c = fmax(fmax(fabs(lmL), fabs(lpL)), fmax(fabs(lmR), fabs(lpR)));
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      const double f = (0.5 * (FL[v] + FR[v]) - 0.5 * c * (UR[v] - UL[v])) * fa;
+      Fo[v] = fa == 0.0 ? 0.0 : f;
+    }
+    return;
+  }
   const double ap = fmax(0.0, fmax(lpL, lpR));
   const double am = fmin(0.0, fmin(lmL, lmR));
   const double den = ap - am;
@@ -389,7 +399,7 @@ __device__ __forceinline__ void c2p_one(const Grid &G, double *q, const double *
   double g1 = 1.0, g2 = 1.0;
   if (G.coord != CART) ref_diag(G.coord, G.geo.r2c[i + G.g[0]], G.geo.s2c[j + G.g[1]], g1, g2);
   const double psi = met[c], alpha = met[G.nv + c];
-  const int fl = c2p_cell(G, qc, psi, alpha, g1, g2, pr);
+  const int fl = c2p_any(G, qc, psi, alpha, g1, g2, pr);
 #pragma unroll
   for (int v = 0; v < NV; v++) prim[v * G.nv + c] = pr[v];
   if (fl & FL_REWRITE) {

@@ -116,14 +116,19 @@ def test_prim2con_parity():
     assert err < 1e-13
 
 
-@pytest.mark.parametrize("coord", [W.CART, W.SPH])
-def test_c2p_parity(coord):
+@pytest.mark.parametrize("coord,scheme", [(W.CART, 0), (W.SPH, 0), (W.CART, 1), (W.SPH, 1)])
+def test_c2p_parity(coord, scheme):
+    """scheme 0: the GRMHD master-function recovery (section 2.5.2); 1: the
+    GRHD z-scheme (section 2.5.1) on states with B = 0."""
     n = 4096
     pr, psi, al, _ = W.random_states(n, seed=5, rho=(1e-6, 10), eps=(1e-6, 10), bmax=1.0)
+    if scheme == 1:
+        pr[5:8] = 0.0
     if coord == W.SPH:
         p = W.grid(2, W.SPH, [64, 64], [0.5, 0.2, 0], [3.0, math.pi - 0.2, 2 * math.pi], [[1, 1], [1, 1]])
     else:
         p = W.grid(3, W.CART, [16, 16, 16], [0, 0, 0], [1, 1, 1], [[1, 1]] * 3)
+    p["c2p"] = scheme
     P = W.empty_prim(p)
     met = W.flat_metric(p)
     I = W.interior(p, P)
