@@ -85,6 +85,7 @@ def lib():
         L.og_cell_geometry.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
         L.og_cell_volumes.argtypes = [P, P]
         L.og_mc_faces.argtypes = [ctypes.c_int, P, P, P]
+        L.og_mp5_faces.argtypes = [ctypes.c_int, P, P, P]
         L.og_point_hlle.argtypes = [ctypes.c_double, P, P, P, P, ctypes.c_int, P]
         L.og_point_tvdlf.argtypes = [ctypes.c_double, P, P, P, P, ctypes.c_int, P]
         if L.og_desc_size() != ctypes.sizeof(_Desc):
@@ -115,6 +116,8 @@ def make_desc(p: dict) -> _Desc:
         setattr(d, k, float(q[k]))
     d.c2p_maxit, d.rk = int(q["c2p_maxit"]), int(q["rk"])
     d.recon, d.riemann, d.pp, d.c2p = int(q["recon"]), int(q["riemann"]), int(q["pp_limiter"]), int(q["c2p"])
+    if d.recon == 1 and d.ng < 3:
+        raise ValueError("MP5 needs three ghost layers (ng = 3)")
     return d
 
 
@@ -266,6 +269,16 @@ def interior(p, a):
     g = [d.ng if ax < d.ndim else 0 for ax in range(3)]
     sl = (slice(g[2], g[2] + d.n[2]), slice(g[1], g[1] + d.n[1]), slice(g[0], g[0] + d.n[0]))
     return a[(Ellipsis,) + sl]
+
+
+def mp5_faces(u):
+    """MP5 face values on a line: (left, right) states at the n-5 faces
+    between cells f and f+1, f = 2..n-4."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    n = u.shape[0]
+    lo, hi = np.zeros(n - 5), np.zeros(n - 5)
+    lib().og_mp5_faces(n, _p(u), _p(lo), _p(hi))
+    return lo, hi
 
 
 def mc_faces(u):

@@ -587,6 +587,38 @@ static double mc_slope(double um, double u0, double up) {
   return dl > 0.0 ? m : -m;
 }
 
+/* MP5 (Suresh & Huynh 1997), the fifth-order monotonicity-preserving
+ * reconstruction named in section 3: the interface value at i+1/2 from the
+ * cell values u_{i-2..i+2} (a..e), left-biased.  The fifth-order value is
+ * kept when it lies between u_i and the monotonicity bound u_mp (alpha = 4);
+ * otherwise it is brought into [u_min, u_max] built from the curvature
+ * (M4 minmod of second differences). */
+static double minmod2(double x, double y) {
+  if (x * y <= 0.0) return 0.0;
+  return fabs(x) < fabs(y) ? x : y;
+}
+static double minmod4(double w, double x, double y, double z) {
+  if (w > 0.0 && x > 0.0 && y > 0.0 && z > 0.0) return fmin(fmin(w, x), fmin(y, z));
+  if (w < 0.0 && x < 0.0 && y < 0.0 && z < 0.0) return fmax(fmax(w, x), fmax(y, z));
+  return 0.0;
+}
+static double mp5_face(double a, double b, double c, double d, double e) {
+  const double alpha = 4.0;
+  double uor = (2.0 * a - 13.0 * b + 47.0 * c + 27.0 * d - 3.0 * e) / 60.0;
+  double ump = c + minmod2(d - c, alpha * (c - b));
+  if ((uor - c) * (uor - ump) <= 0.0) return uor;
+  double dm = a - 2.0 * b + c, d0 = b - 2.0 * c + d, dp = c - 2.0 * d + e;
+  double dm4p = minmod4(4.0 * d0 - dp, 4.0 * dp - d0, d0, dp);
+  double dm4m = minmod4(4.0 * dm - d0, 4.0 * d0 - dm, dm, d0);
+  double uul = c + alpha * (c - b);
+  double uav = 0.5 * (c + d);
+  double umd = uav - 0.5 * dm4p;
+  double ulc = c + 0.5 * (c - b) + (4.0 / 3.0) * dm4m;
+  double umin = fmax(fmin(fmin(c, d), umd), fmin(fmin(c, uul), ulc));
+  double umax = fmin(fmax(fmax(c, d), umd), fmax(fmax(c, uul), ulc));
+  return uor + minmod2(umin - uor, umax - uor);
+}
+
 /* HLLE flux (Harten, Lax & van Leer 1983; Einfeldt 1988), with the signal
  * speeds bounded by zero.  If both bounds vanish the average is used. */
 static void hlle(const double fl[NV], const double fr[NV], const double ql[NV], const double qr[NV],
@@ -628,22 +660,36 @@ static void face_flux_x(const og_desc *d, const double *prim, const double *met,
     return;
   }
   long nt = ntot(d);
-  long idx[4];
-  for (int s = 0; s < 4; s++) {
+  /* stencil cells f-3 .. f+2 along a (MC uses f-2 .. f+1) */
+  long idx[6];
+  for (int s = 0; s < 6; s++) {
     int c[3] = {cell[0], cell[1], cell[2]};
-    c[a] = f - 2 + s;
-    idx[s] = at(d, c[0], c[1], c[2]);
+    c[a] = f - 3 + s;
+    idx[s] = (s == 0 || s == 5) && d->recon != 1 ? -1 : at(d, c[0], c[1], c[2]);
   }
   double pl[NV], pr[NV];
   for (int v = 0; v < NV; v++) {
-    double u0 = prim[v * nt + idx[0]], u1 = prim[v * nt + idx[1]];
-    double u2 = prim[v * nt + idx[2]], u3 = prim[v * nt + idx[3]];
-    pl[v] = u1 + 0.5 * mc_slope(u0, u1, u2);
-    pr[v] = u2 - 0.5 * mc_slope(u1, u2, u3);
+    double u[6];
+    for (int s = 0; s < 6; s++) u[s] = idx[s] < 0 ? 0.0 : prim[v * nt + idx[s]];
+    if (d->recon == 1) {
+      pl[v] = mp5_face(u[0], u[1], u[2], u[3], u[4]);
+      pr[v] = mp5_face(u[5], u[4], u[3], u[2], u[1]);
+    } else {
+      pl[v] = u[2] + 0.5 * mc_slope(u[1], u[2], u[3]);
+      pr[v] = u[3] - 0.5 * mc_slope(u[2], u[3], u[4]);
+    }
+  }
+  if (d->recon == 1 && !(pl[RHO] > 0.0 && pl[PRS] > 0.0 && pr[RHO] > 0.0 && pr[PRS] > 0.0)) {
+    /* a reconstructed state without positive density and pressure: both
+     * sides of this face fall back to the adjacent cell values */
+    for (int v = 0; v < NV; v++) {
+      pl[v] = prim[v * nt + idx[2]];
+      pr[v] = prim[v * nt + idx[3]];
+    }
   }
   double m1[5], m2[5], mf[5];
-  load_metric(d, met, idx[1], m1);
-  load_metric(d, met, idx[2], m2);
+  load_metric(d, met, idx[2], m1);
+  load_metric(d, met, idx[3], m2);
   for (int v = 0; v < 5; v++) mf[v] = 0.5 * (m1[v] + m2[v]);
   double x[3] = {centre(d, 0, i), centre(d, 1, j), centre(d, 2, k)};
   x[a] = face_pos(d, a, f);
@@ -1168,6 +1214,15 @@ int og_desc_size(void) { return (int)sizeof(og_desc); }
 /* MC-reconstructed face values of one variable on a line: for each face
  * f = 1..n-3 between cells f and f+1 of u[0..n-1], left value from cell f,
  * right value from cell f+1.  out_l/out_r have n-3 entries. */
+/* MP5 face values of a 1D sequence: out_l[f - 2], out_r[f - 2] are the left
+ * and right states at the face between u[f] and u[f + 1], f = 2 .. n-4. */
+void og_mp5_faces(int n, const double *u, double *out_l, double *out_r) {
+  for (int f = 2; f + 3 < n; f++) {
+    out_l[f - 2] = mp5_face(u[f - 2], u[f - 1], u[f], u[f + 1], u[f + 2]);
+    out_r[f - 2] = mp5_face(u[f + 3], u[f + 2], u[f + 1], u[f], u[f - 1]);
+  }
+}
+
 void og_mc_faces(int n, const double *u, double *out_l, double *out_r) {
   for (int f = 1; f + 2 < n; f++) {
     out_l[f - 1] = u[f] + 0.5 * mc_slope(u[f - 1], u[f], u[f + 1]);
