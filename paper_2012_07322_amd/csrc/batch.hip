@@ -41,16 +41,23 @@ struct BlockRec {
   int active;
 };
 
-// Compiled tile shapes (256 threads; each pass has at most 256 faces).
+// Compiled tile shapes (256 threads; each pass has at most 256 faces) and
+// reconstruction halo (2: MC, 3: MP5).
 struct Variant {
-  int tx, ty, tz, nd;
+  int tx, ty, tz, nd, h;
 };
-constexpr int NVAR = 8;
-constexpr Variant kVar[NVAR] = {{8, 8, 3, 3},   {8, 5, 5, 3},  {16, 4, 3, 3}, {8, 6, 4, 3},
-                                {16, 15, 1, 2}, {32, 7, 1, 2}, {8, 28, 1, 2}, {255, 1, 1, 1}};
+constexpr int NVAR = 11;
+constexpr Variant kVar[NVAR] = {{8, 8, 3, 3, 2},   {8, 5, 5, 3, 2},  {16, 4, 3, 3, 2}, {8, 6, 4, 3, 2},
+                                {16, 15, 1, 2, 2}, {32, 7, 1, 2, 2}, {8, 28, 1, 2, 2}, {255, 1, 1, 1, 2},
+                                {8, 5, 5, 3, 3},   {16, 15, 1, 2, 3}, {255, 1, 1, 1, 3}};
 // Work lists: one per tile variant, then recovery, ghosts, CFL (entries
 // ordered by group), and the recovery / ghost lists of an init.
-enum { L_C2P = NVAR, L_GH, L_CFL, L_IC2P, L_IGH, NLIST };
+// Stage lists: one per (tile variant, Riemann solver), list = variant +
+// NVAR * riemann; then recovery, ghosts, CFL (entries ordered by group), and
+// the recovery / ghost lists of an init.
+constexpr int NSL = 2 * NVAR;
+enum { L_C2P = NSL, L_GH, L_CFL, L_IC2P, L_IGH, NLIST };
+static_assert(NSL <= kMaxVariants && NSL <= 32, "stage lists are counted in 32-bit masks and server counters");
 
 // Entry table of one list on the device: blk[e] is the slot of entry e,
 // start[e] the index of its first item (start[nent] = total), meta = {nent,
@@ -92,10 +99,10 @@ __device__ __forceinline__ int find_entry(const int *start, int nent, int it, in
   return lo;
 }
 
-template <int TX, int TY, int TZ, int ND, int MODE>
+template <int TX, int TY, int TZ, int ND, int MODE, int H, int R>
 __global__ __launch_bounds__(NT, 3) void k_bstage(const BlockRec *__restrict__ B, DList L,
                                                           const double *dts, double ca, double cb, int out_qn) {
-  __shared__ double sF[stage_lds<TX, TY, TZ, ND>()];
+  __shared__ double sF[stage_lds<TX, TY, TZ, ND, H>()];
   const int nent = L.meta[0];
   int it, end, stride;
   xcd_range(L.meta[1], it, end, stride);
@@ -109,7 +116,7 @@ __global__ __launch_bounds__(NT, 3) void k_bstage(const BlockRec *__restrict__ B
     const int gx = (b.G.n[0] + TX - 1) / TX, gy = (b.G.n[1] + TY - 1) / TY;
     const int i0 = (l % gx) * TX, j0 = ((l / gx) % gy) * TY, k0 = (l / (gx * gy)) * TZ;
     double *out = (MODE == 0 || !out_qn) ? b.qs : b.qn;
-    stage_tile<TX, TY, TZ, ND, MODE>(b.G, i0, j0, k0, b.prim, b.met, b.qn, b.qs, out, dtp, ca, cb, sF);
+    stage_tile<TX, TY, TZ, ND, MODE, H, R>(b.G, i0, j0, k0, b.prim, b.met, b.qn, b.qs, out, dtp, ca, cb, sF);
   }
 }
 
@@ -196,37 +203,42 @@ __global__ void k_badvance(double *t, int *nstep, const double *dt, int ngroups)
   }
 }
 
-template <int V, int MODE>
-void launch_variant(const BlockRec *B, DList L, const double *dts, double ca, double cb, int out_qn, int grid,
-                    hipStream_t st) {
-  constexpr Variant v = kVar[V];
-  hipLaunchKernelGGL((k_bstage<v.tx, v.ty, v.tz, v.nd, MODE>), dim3(grid), dim3(NT), 0, st, B, L, dts, ca, cb,
-                     out_qn);
+// Launch the stage kernel of list LI (variant LI % NVAR, Riemann solver
+// LI / NVAR), or of the run-time list li by recursion over the lists.
+template <int LI, int MODE>
+void launch_list(const BlockRec *B, DList L, const double *dts, double ca, double cb, int out_qn, int grid,
+                 hipStream_t st) {
+  constexpr Variant v = kVar[LI % NVAR];
+  hipLaunchKernelGGL((k_bstage<v.tx, v.ty, v.tz, v.nd, MODE, v.h, LI / NVAR>), dim3(grid), dim3(NT), 0, st, B, L,
+                     dts, ca, cb, out_qn);
 }
 
-template <int MODE>
-void launch_variant_any(int v, const BlockRec *B, DList L, const double *dts, double ca, double cb, int out_qn,
-                        int grid, hipStream_t st) {
-  switch (v) {
-    case 0: launch_variant<0, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
-    case 1: launch_variant<1, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
-    case 2: launch_variant<2, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
-    case 3: launch_variant<3, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
-    case 4: launch_variant<4, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
-    case 5: launch_variant<5, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
-    case 6: launch_variant<6, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
-    default: launch_variant<7, MODE>(B, L, dts, ca, cb, out_qn, grid, st); break;
+template <int MODE, int LI = 0>
+void launch_list_any(int li, const BlockRec *B, DList L, const double *dts, double ca, double cb, int out_qn,
+                     int grid, hipStream_t st) {
+  if constexpr (LI < NSL) {
+    if (li == LI)
+      launch_list<LI, MODE>(B, L, dts, ca, cb, out_qn, grid, st);
+    else
+      launch_list_any<MODE, LI + 1>(li, B, L, dts, ca, cb, out_qn, grid, st);
   }
 }
 
 // Default tile for a block before (or without) tuning.
 int default_variant(const gmunu_grid_desc &d) {
+  if (d.recon == GMUNU_RECON_MP5) return d.ndim == 1 ? 10 : d.ndim == 2 ? 9 : 8;
   if (d.ndim == 1) return 7;
   if (d.ndim == 2) return 4;
   return d.n[0] <= 8 ? 0 : 1;
 }
 
-std::tuple<int, int, int, int> bucket_of(const gmunu_grid_desc &d) { return {d.ndim, d.n[0], d.n[1], d.n[2]}; }
+int halo_of(const gmunu_grid_desc &d) { return d.recon == GMUNU_RECON_MP5 ? 3 : 2; }
+
+std::tuple<int, int, int, int, int, int> bucket_of(const gmunu_grid_desc &d) {
+  return {d.ndim, d.n[0], d.n[1], d.n[2], d.recon, d.riemann};
+}
+
+int list_of(int variant, const gmunu_grid_desc &d) { return variant + NVAR * (d.riemann == GMUNU_RIEMANN_TVDLF); }
 
 long ceil_div(long a, long b) { return (a + b - 1) / b; }
 
@@ -267,7 +279,7 @@ struct gmunu_batch {
   std::vector<double *> geo;  // per-slot geometry tables, grown, never shrunk
   std::vector<size_t> geo_cap;
   std::vector<int> var;
-  std::map<std::tuple<int, int, int, int>, int> tuned;
+  std::map<std::tuple<int, int, int, int, int, int>, int> tuned;
   struct TimeSet {
     int group;
     double t, t_end;
@@ -393,8 +405,8 @@ int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, unsigned mask
       }
     }
     const int last = s == nst - 1;
-    for (int v = 0; v < NVAR; v++)
-      if (mask & (1u << v)) launch_variant_any<1>(v, b->d_rec, b->list(v), b->d_dt, ca, cb, last, gst, st);
+    for (int l = 0; l < NSL; l++)
+      if (mask & (1u << l)) launch_list_any<1>(l, b->d_rec, b->list(l), b->d_dt, ca, cb, last, gst, st);
     hipLaunchKernelGGL(k_bc2p, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_C2P), b->d_dt, last, 0, nfatal,
                        b->d_gfatal);
     hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_GH), b->d_dt, 0);
@@ -411,8 +423,9 @@ namespace gm {
 BatchItems batch_items_for(const gmunu_batch *b, const gmunu_grid_desc &d) {
   BatchItems r;
   auto it = b->tuned.find(bucket_of(d));
-  r.variant = it != b->tuned.end() ? it->second : default_variant(d);
-  r.stage = stage_items(d, r.variant);
+  const int v = it != b->tuned.end() ? it->second : default_variant(d);
+  r.variant = list_of(v, d);
+  r.stage = stage_items(d, v);
   r.cells = cell_items(d);
   r.ghosts = ghost_items(d);
   return r;
@@ -580,7 +593,7 @@ int gmunu_batch_commit(gmunu_batch *b, void *stream) {
   for (int s = 0; s < b->maxb; s++) {
     if (!b->used[s]) continue;
     const gmunu_grid_desc &d = b->blk[s].desc;
-    h[b->var[s]].add(s, stage_items(d, b->var[s]));
+    h[list_of(b->var[s], d)].add(s, stage_items(d, b->var[s]));
     h[L_C2P].add(s, cell_items(d));
     h[L_GH].add(s, ghost_items(d));
     by_group[b->rec[s].group].push_back(s);
@@ -594,8 +607,8 @@ int gmunu_batch_commit(gmunu_batch *b, void *stream) {
   unsigned mask = 0;
   for (int l = 0; l < L_IC2P; l++)
     if (h[l].total > b->maxi) return GMUNU_EINVAL;
-  for (int v = 0; v < NVAR; v++)
-    if (h[v].total) mask |= 1u << v;
+  for (int l = 0; l < NSL; l++)
+    if (h[l].total) mask |= 1u << l;
   int meta[2 * L_IC2P];
   bool ok = upload_records(b, st);
   for (int l = 0; l < L_IC2P; l++) ok = ok && upload_list(b, l, h[l], meta + 2 * l, st);
@@ -653,7 +666,7 @@ int gmunu_batch_init(gmunu_batch *b, const int *slots, int nslots, void *stream)
 int gmunu_batch_autotune(gmunu_batch *b, void *stream) {
   if (!b) return GMUNU_ENULL;
   hipStream_t st = as_stream(stream);
-  std::map<std::tuple<int, int, int, int>, std::vector<int>> buckets;
+  std::map<std::tuple<int, int, int, int, int, int>, std::vector<int>> buckets;
   for (int s = 0; s < b->maxb; s++)
     if (b->used[s]) buckets[bucket_of(b->blk[s].desc)].push_back(s);
   hipEvent_t e0, e1;
@@ -667,23 +680,25 @@ int gmunu_batch_autotune(gmunu_batch *b, void *stream) {
   for (auto &bk : buckets) {
     if (rc) break;
     const int nd = std::get<0>(bk.first);
+    const int h = halo_of(b->blk[bk.second[0]].desc);
     int best = -1;
     float best_ms = 0.f;
     for (int v = 0; v < NVAR; v++) {
-      if (kVar[v].nd != nd) continue;
-      // only this bucket's blocks, all on variant v, in list v (MODE 0
-      // writes the right-hand side into q_s, which is scratch)
+      if (kVar[v].nd != nd || kVar[v].h != h) continue;
+      // only this bucket's blocks, all on variant v, in their stage list
+      // (MODE 0 writes the right-hand side into q_s, which is scratch)
+      const int li = list_of(v, b->blk[bk.second[0]].desc);
       HList h;
       for (int s : bk.second) h.add(s, stage_items(b->blk[s].desc, v));
       if (h.total > b->maxi) continue;
       int meta[2];
-      if (!upload_list(b, v, h, meta, st) || hipStreamSynchronize(st) != hipSuccess) {
+      if (!upload_list(b, li, h, meta, st) || hipStreamSynchronize(st) != hipSuccess) {
         rc = GMUNU_EHIP;
         break;
       }
-      launch_variant_any<0>(v, b->d_rec, b->list(v), b->d_dt, 0.0, 1.0, 0, gst, st);  // warm-up
+      launch_list_any<0>(li, b->d_rec, b->list(li), b->d_dt, 0.0, 1.0, 0, gst, st);  // warm-up
       (void)hipEventRecord(e0, st);
-      for (int r = 0; r < 3; r++) launch_variant_any<0>(v, b->d_rec, b->list(v), b->d_dt, 0.0, 1.0, 0, gst, st);
+      for (int r = 0; r < 3; r++) launch_list_any<0>(li, b->d_rec, b->list(li), b->d_dt, 0.0, 1.0, 0, gst, st);
       (void)hipEventRecord(e1, st);
       if (hipEventSynchronize(e1) != hipSuccess) {
         rc = GMUNU_EHIP;
@@ -768,7 +783,7 @@ int gmunu_batch_info(gmunu_batch *b, long *items_out, int *out_variant) {
   if (!b) return GMUNU_ENULL;
   if (items_out) {
     long st = 0;
-    for (int v = 0; v < NVAR; v++) st += b->counts[v];
+    for (int l = 0; l < NSL; l++) st += b->counts[l];
     items_out[0] = st;
     items_out[1] = b->counts[L_C2P];
     items_out[2] = b->counts[L_GH];

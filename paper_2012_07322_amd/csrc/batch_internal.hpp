@@ -7,9 +7,11 @@
 
 namespace gm {
 
+constexpr int kMaxVariants = 32;  // bound on the number of stage work lists
+
 struct BatchItems {
-  int variant;  // tile variant the block would get (tuned or default)
-  long stage;   // items in that variant's stage list
+  int variant;  // stage list the block would join (tile variant and Riemann solver)
+  long stage;   // items in that stage list
   long cells;   // items in the recovery and CFL lists (256 interior cells each)
   long ghosts;  // items in the ghost list
 };

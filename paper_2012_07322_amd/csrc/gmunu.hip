@@ -76,17 +76,17 @@ __device__ __forceinline__ void xcd_tile(const Grid &G, int TX, int TY, int TZ, 
 
 // MODE 0: dqdt = L(prim).  MODE 1: q_out = ca q_n + cb (q_s + dt L(prim)).
 // skipp (nullable): nothing is done when *skipp == 0 (a step past t_end).
-template <int TX, int TY, int TZ, int ND, int MODE>
+template <int TX, int TY, int TZ, int ND, int MODE, int H, int R>
 __global__ __launch_bounds__(NT, 3) void k_stage(const Grid G, const double *__restrict__ prim,
                                                          const double *__restrict__ met, const double *qn,
                                                          const double *qs, double *out,
                                                          const double *__restrict__ dtp, double ca, double cb,
                                                          const double *__restrict__ skipp) {
-  __shared__ double sF[stage_lds<TX, TY, TZ, ND>()];
+  __shared__ double sF[stage_lds<TX, TY, TZ, ND, H>()];
   if (skipp && *skipp == 0.0) return;
   int bx, by, bz;
   xcd_tile(G, TX, TY, TZ, bx, by, bz);
-  stage_tile<TX, TY, TZ, ND, MODE>(G, bx * TX, by * TY, bz * TZ, prim, met, qn, qs, out, dtp, ca, cb, sF);
+  stage_tile<TX, TY, TZ, ND, MODE, H, R>(G, bx * TX, by * TY, bz * TZ, prim, met, qn, qs, out, dtp, ca, cb, sF);
 }
 
 __global__ __launch_bounds__(NT) void k_c2p(const Grid G, double *q, const double *__restrict__ met, double *prim,
@@ -132,13 +132,13 @@ __global__ __launch_bounds__(NT) void k_cfl_finish(const double *part, int npart
 
 __global__ void k_advance(double *tp, const double *dtp) { *tp += *dtp; }
 
-template <int TX, int TY, int TZ, int ND, int MODE>
+template <int TX, int TY, int TZ, int ND, int MODE, int H, int R>
 void launch_stage_t(const gmunu_ctx *ctx, const double *prim, const double *met, const double *qn,
                     const double *qs, double *out, const double *dtp, double ca, double cb, const double *skipp,
                     hipStream_t st) {
   const Grid &G = ctx->G;
   dim3 grid(((G.n[0] + TX - 1) / TX) * ((G.n[1] + TY - 1) / TY) * ((G.n[2] + TZ - 1) / TZ));
-  hipLaunchKernelGGL((k_stage<TX, TY, TZ, ND, MODE>), grid, dim3(NT), 0, st, G, prim, met, qn, qs, out,
+  hipLaunchKernelGGL((k_stage<TX, TY, TZ, ND, MODE, H, R>), grid, dim3(NT), 0, st, G, prim, met, qn, qs, out,
                      dtp, ca, cb, skipp);
 }
 
@@ -146,12 +146,28 @@ template <int MODE>
 void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, const double *qn,
                   const double *qs, double *out, const double *dtp, double ca, double cb, const double *skipp,
                   hipStream_t st) {
-  if (ctx->G.ndim == 1)
-    launch_stage_t<255, 1, 1, 1, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);
-  else if (ctx->G.ndim == 2)
-    launch_stage_t<16, 15, 1, 2, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);
-  else
-    launch_stage_t<8, 5, 5, 3, MODE>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);
+  const int mp5 = ctx->G.recon == GMUNU_RECON_MP5, lf = ctx->G.riemann == GMUNU_RIEMANN_TVDLF;
+  switch (ctx->G.ndim * 4 + mp5 * 2 + lf) {
+#define GM_CASE(NDIM, TX, TY, TZ, M, L)                                                                         \
+  case NDIM * 4 + M * 2 + L:                                                                                     \
+    launch_stage_t<TX, TY, TZ, NDIM, MODE, 2 + M, L>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);       \
+    break;
+    GM_CASE(1, 255, 1, 1, 0, 0)
+    GM_CASE(1, 255, 1, 1, 0, 1)
+    GM_CASE(1, 255, 1, 1, 1, 0)
+    GM_CASE(1, 255, 1, 1, 1, 1)
+    GM_CASE(2, 16, 15, 1, 0, 0)
+    GM_CASE(2, 16, 15, 1, 0, 1)
+    GM_CASE(2, 16, 15, 1, 1, 0)
+    GM_CASE(2, 16, 15, 1, 1, 1)
+    GM_CASE(3, 8, 5, 5, 0, 0)
+    GM_CASE(3, 8, 5, 5, 0, 1)
+    GM_CASE(3, 8, 5, 5, 1, 0)
+    GM_CASE(3, 8, 5, 5, 1, 1)
+#undef GM_CASE
+    default:
+      break;
+  }
 }
 
 int launch_c2p(gmunu_ctx *ctx, double *q, const double *metric, double *prim, uint8_t *flags,

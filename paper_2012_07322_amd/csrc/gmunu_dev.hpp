@@ -55,6 +55,7 @@ struct Grid {
   double rho_atmo, p_atmo, rho_low, alpha_bh, rho_max, eps_max, w_max;
   int maxit;
   double tol;
+  int recon;    // GMUNU_RECON_*
   int riemann;  // GMUNU_RIEMANN_*
   int c2p;      // GMUNU_C2P_*
   int bc[3][2];
@@ -109,6 +110,36 @@ __device__ __forceinline__ double mc_slope(double a, double b, double c) {
   double cen = 0.5 * (dl + dr);
   double m = fmin(fmin(fabs(2.0 * dl), fabs(cen)), fabs(2.0 * dr));
   return (dl * dr > 0.0) ? copysign(m, cen) : 0.0;
+}
+
+// MP5 (Suresh & Huynh 1997; the default reconstruction of section 3): the
+// left-biased interface value at i+1/2 from u_{i-2..i+2} = a..e.  The
+// fifth-order value is kept when it lies between u_i and the monotonicity
+// bound (alpha = 4), else it is brought into [u_min, u_max] built from the
+// M4 minmod of second differences.
+__device__ __forceinline__ double minmod2(double x, double y) {
+  return x * y <= 0.0 ? 0.0 : (fabs(x) < fabs(y) ? x : y);
+}
+__device__ __forceinline__ double minmod4(double w, double x, double y, double z) {
+  if (w > 0.0 && x > 0.0 && y > 0.0 && z > 0.0) return fmin(fmin(w, x), fmin(y, z));
+  if (w < 0.0 && x < 0.0 && y < 0.0 && z < 0.0) return fmax(fmax(w, x), fmax(y, z));
+  return 0.0;
+}
+__device__ __forceinline__ double mp5_face(double a, double b, double c, double d, double e) {
+  constexpr double alpha = 4.0;
+  const double uor = (2.0 * a - 13.0 * b + 47.0 * c + 27.0 * d - 3.0 * e) * (1.0 / 60.0);
+  const double ump = c + minmod2(d - c, alpha * (c - b));
+  if ((uor - c) * (uor - ump) <= 0.0) return uor;
+  const double dm = a - 2.0 * b + c, d0 = b - 2.0 * c + d, dp = c - 2.0 * d + e;
+  const double dm4p = minmod4(4.0 * d0 - dp, 4.0 * dp - d0, d0, dp);
+  const double dm4m = minmod4(4.0 * dm - d0, 4.0 * d0 - dm, dm, d0);
+  const double uul = c + alpha * (c - b);
+  const double uav = 0.5 * (c + d);
+  const double umd = uav - 0.5 * dm4p;
+  const double ulc = c + 0.5 * (c - b) + (4.0 / 3.0) * dm4m;
+  const double umin = fmax(fmin(fmin(c, d), umd), fmin(fmin(c, uul), ulc));
+  const double umax = fmin(fmax(fmax(c, d), umd), fmax(fmax(c, uul), ulc));
+  return uor + minmod2(umin - uor, umax - uor);
 }
 
 // Conserved vector U, flux F along direction D and the two wave-speed bounds

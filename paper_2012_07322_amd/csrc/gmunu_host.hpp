@@ -45,7 +45,8 @@ inline int validate_desc(const gmunu_grid_desc &d) {
   if (!(d.gamma > 1.0) || !(d.rho_atmo > 0.0) || !(d.w_max > 1.0) || d.c2p_maxit < 1 || !(d.c2p_tol > 0.0))
     return GMUNU_EINVAL;
   if (d.rk != 2 && d.rk != 3) return GMUNU_EINVAL;
-  if (d.recon != GMUNU_RECON_MC) return GMUNU_EINVAL;
+  if (d.recon != GMUNU_RECON_MC && d.recon != GMUNU_RECON_MP5) return GMUNU_EINVAL;
+  if (d.recon == GMUNU_RECON_MP5 && d.ng < 3) return GMUNU_EINVAL;
   if (d.riemann != GMUNU_RIEMANN_HLLE && d.riemann != GMUNU_RIEMANN_TVDLF) return GMUNU_EINVAL;
   if (d.pp_limiter != 0) return GMUNU_EINVAL;
   if (d.c2p != GMUNU_C2P_GRMHD && d.c2p != GMUNU_C2P_GRHD_Z) return GMUNU_EINVAL;
@@ -89,6 +90,7 @@ inline GeoOffsets setup_grid(const gmunu_grid_desc &d, Grid &G, std::vector<doub
   G.w_max = d.w_max;
   G.maxit = d.c2p_maxit;
   G.tol = d.c2p_tol;
+  G.recon = d.recon;
   G.riemann = d.riemann;
   G.c2p = d.c2p;
 

@@ -21,26 +21,49 @@ __device__ __forceinline__ double ld(const double *__restrict__ base, long nv, i
 }
 
 // Face flux times face factor through the lower face (along D) of cell
-// (i,j,k): MC reconstruction from the four cells across the face, metric as
-// the mean of the two adjacent centres, HLLE.  The stencil comes from the
+// (i,j,k): reconstruction from the cells across the face (H = 2: MC from
+// four cells; H = 3: MP5 from six), metric as the mean of the two adjacent
+// centres, HLLE (R = 0) or TVDLF (R = 1).  The stencil comes from the
 // workgroup's staged region S (RC cells per variable, prim variables 0-7,
-// metric 8-12): r0 is the region index of the cell two below the face, rs
-// the region stride along D.
-template <int D>
+// metric 8-12): r0 is the region index of the cell H below the face, rs the
+// region stride along D.
+template <int D, int H, int R>
 __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC, int r0, int rs, int i, int j,
                                           int k, double *Fo) {
   const int cd = (D == 0 ? i : D == 1 ? j : k) + G.g[D];
   // zero-area faces (r = 0, theta = 0 or pi) are evaluated like any other
   // and their flux replaced by 0 at the end; no load-dependent branch here
   const double fa = G.geo.fa[D][cd];
-  const int r1 = r0 + rs, r2 = r1 + rs, r3 = r2 + rs;
+  // the two cells adjacent to the face
+  const int r1 = r0 + (H - 1) * rs, r2 = r1 + rs;
   double pl[NV], pr[NV];
+  if constexpr (H == 2) {
+    const int r3 = r2 + rs;
 #pragma unroll
-  for (int v = 0; v < NV; v++) {
-    const double *Sv = S + v * RC;
-    const double a = Sv[r0], b = Sv[r1], e = Sv[r2], f = Sv[r3];
-    pl[v] = b + 0.5 * mc_slope(a, b, e);
-    pr[v] = e - 0.5 * mc_slope(b, e, f);
+    for (int v = 0; v < NV; v++) {
+      const double *Sv = S + v * RC;
+      const double a = Sv[r0], b = Sv[r1], e = Sv[r2], f = Sv[r3];
+      pl[v] = b + 0.5 * mc_slope(a, b, e);
+      pr[v] = e - 0.5 * mc_slope(b, e, f);
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      const double *Sv = S + v * RC;
+      const double u0 = Sv[r0], u1 = Sv[r0 + rs], u2 = Sv[r1], u3 = Sv[r2], u4 = Sv[r2 + rs],
+                   u5 = Sv[r2 + 2 * rs];
+      pl[v] = mp5_face(u0, u1, u2, u3, u4);
+      pr[v] = mp5_face(u5, u4, u3, u2, u1);
+    }
+    // a reconstructed state without positive density and pressure: both
+    // sides fall back to the adjacent cell values
+    if (!(pl[0] > 0.0 && pl[4] > 0.0 && pr[0] > 0.0 && pr[4] > 0.0)) {
+#pragma unroll
+      for (int v = 0; v < NV; v++) {
+        pl[v] = S[v * RC + r1];
+        pr[v] = S[v * RC + r2];
+      }
+    }
   }
   const double *Sm = S + NV * RC;
   const double psi = 0.5 * (Sm[r1] + Sm[r2]);
@@ -60,7 +83,7 @@ __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC
   double UL[NV], FL[NV], UR[NV], FR[NV], lmL, lpL, lmR, lpR;
   state_flux<D>(G.gam, G.gfac, pl, psi4, psi6, alpha, beta, g1, g2, gud, UL, FL, lmL, lpL);
   state_flux<D>(G.gam, G.gfac, pr, psi4, psi6, alpha, beta, g1, g2, gud, UR, FR, lmR, lpR);
-  if (G.riemann == GMUNU_RIEMANN_TVDLF) {
+  if constexpr (R == GMUNU_RIEMANN_TVDLF) {
     // local Lax-Friedrichs: the largest speed magnitude of both states
     const double c = fmax(fmax(fabs(lmL), fabs(lpL)), fmax(fabs(lmR), fabs(lpR)));
 #pragma unroll
@@ -246,10 +269,10 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
 }
 
 // Staged region of the face pass along D of a TX x TY x TZ tile: the tile's
-// cells plus two on each side along D.
-template <int TX, int TY, int TZ, int D>
+// cells plus H on each side along D (H = 2 for MC, 3 for MP5).
+template <int TX, int TY, int TZ, int D, int H>
 constexpr int region_cells() {
-  return (TX + 4 * (D == 0)) * (TY + 4 * (D == 1)) * (TZ + 4 * (D == 2));
+  return (TX + 2 * H * (D == 0)) * (TY + 2 * H * (D == 1)) * (TZ + 2 * H * (D == 2));
 }
 
 // Faces of the pass along D (the tile's lower faces plus the upper layer).
@@ -260,10 +283,10 @@ constexpr int pass_faces() {
 
 // LDS doubles per workgroup: the staged region (prim and metric) of the
 // largest pass, reused for the face fluxes.
-template <int TX, int TY, int TZ, int ND>
+template <int TX, int TY, int TZ, int ND, int H = 2>
 constexpr int stage_lds() {
-  constexpr int r0 = region_cells<TX, TY, TZ, 0>(), r1 = ND > 1 ? region_cells<TX, TY, TZ, 1>() : 0,
-                r2 = ND > 2 ? region_cells<TX, TY, TZ, 2>() : 0;
+  constexpr int r0 = region_cells<TX, TY, TZ, 0, H>(), r1 = ND > 1 ? region_cells<TX, TY, TZ, 1, H>() : 0,
+                r2 = ND > 2 ? region_cells<TX, TY, TZ, 2, H>() : 0;
   constexpr int r = r0 > r1 ? (r0 > r2 ? r0 : r2) : (r1 > r2 ? r1 : r2);
   return (NV + 5) * r;
 }
@@ -279,15 +302,16 @@ constexpr bool tile_fits() {
 // (1) stage prim and metric of the pass's region into LDS (coalesced, each
 // value read once from memory), (2) one face per thread from LDS, (3) the
 // fluxes through LDS to the cells on both sides of each face.
-template <int TX, int TY, int TZ, int D>
+template <int TX, int TY, int TZ, int D, int H, int R>
 __device__ __forceinline__ void face_pass(const Grid &G, const double *__restrict__ prim,
                                           const double *__restrict__ met, double *S, int i0, int j0, int k0,
                                           int tx, int ty, int tz, bool valid, double *acc) {
-  constexpr int RX = TX + 4 * (D == 0), RY = TY + 4 * (D == 1), RZ = TZ + 4 * (D == 2), RC = RX * RY * RZ;
+  constexpr int RX = TX + 2 * H * (D == 0), RY = TY + 2 * H * (D == 1), RZ = TZ + 2 * H * (D == 2),
+                RC = RX * RY * RZ;
   constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2), NF = FX * FY * FZ;
   const int tid = threadIdx.x;
-  // (1) region origin: the tile origin moved two cells down along D
-  const int ai = i0 - 2 * (D == 0), aj = j0 - 2 * (D == 1), ak = k0 - 2 * (D == 2);
+  // (1) region origin: the tile origin moved H cells down along D
+  const int ai = i0 - H * (D == 0), aj = j0 - H * (D == 1), ak = k0 - H * (D == 2);
   for (int c = tid; c < RC; c += NT) {
     const int ri = c % RX, rj = (c / RX) % RY, rk = c / (RX * RY);
     const int gi = ai + ri, gj = aj + rj, gk = ak + rk;
@@ -301,7 +325,7 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *__restric
     }
   }
   __syncthreads();
-  // (2) face tid: region index of the cell two below it along D
+  // (2) face tid: region index of the cell H below it along D
   double Fo[NV];
   const int f = tid;
   const int fx = f % FX, fy = (f / FX) % FY, fz = f / (FX * FY);
@@ -310,8 +334,8 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *__restric
                   (D == 2 ? ck <= G.n[2] : ck < G.n[2]);
   if (ok) {
     constexpr int rs = D == 0 ? 1 : D == 1 ? RX : RX * RY;
-    const int r0 = fx + RX * (fy + RY * fz);  // region coordinate = face coordinate - 2 + 2 along D
-    face_flux<D>(G, S, RC, r0, rs, ci, cj, ck, Fo);
+    const int r0 = fx + RX * (fy + RY * fz);  // region coordinate = face coordinate - H + H along D
+    face_flux<D, H, R>(G, S, RC, r0, rs, ci, cj, ck, Fo);
   } else {
 #pragma unroll
     for (int v = 0; v < NV; v++) Fo[v] = 0.0;
@@ -337,8 +361,8 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *__restric
 // One RK stage (MODE 1: q_out = ca q_n + cb (q_s + dt L)) or the RHS alone
 // (MODE 0: out = L) on the tile of TX x TY x TZ cells with origin (i0,j0,k0).
 // Every thread of the workgroup (NT threads) must call it (it synchronises);
-// sF is the workgroup's LDS buffer of stage_lds<TX,TY,TZ,ND>() doubles.
-template <int TX, int TY, int TZ, int ND, int MODE>
+// sF is the workgroup's LDS buffer of stage_lds<TX,TY,TZ,ND,H>() doubles.
+template <int TX, int TY, int TZ, int ND, int MODE, int H = 2, int R = 0>
 __device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0, const double *__restrict__ prim,
                                            const double *__restrict__ met, const double *qn, const double *qs,
                                            double *out, const double *__restrict__ dtp, double ca, double cb,
@@ -356,9 +380,9 @@ __device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; v++) acc[v] = 0.0;
-  face_pass<TX, TY, TZ, 0>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
-  if constexpr (ND > 1) face_pass<TX, TY, TZ, 1>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
-  if constexpr (ND > 2) face_pass<TX, TY, TZ, 2>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
+  face_pass<TX, TY, TZ, 0, H, R>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
+  if constexpr (ND > 1) face_pass<TX, TY, TZ, 1, H, R>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
+  if constexpr (ND > 2) face_pass<TX, TY, TZ, 2, H, R>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
   if (!valid) return;
   const unsigned rel = (unsigned)((tz + G.g[2]) * G.s[2] + (ty + G.g[1]) * G.s[1] + (tx + G.g[0]));
   cell_sources(G, pb, mb, i, j, k, rel, acc);

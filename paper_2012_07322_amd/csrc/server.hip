@@ -75,7 +75,7 @@ struct Lane {
   double t_launch = 0.0;
   std::vector<Req *> slot;  // resident or uploading, by slot
   std::vector<int> free_slots;
-  long stage[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long stage[kMaxVariants] = {};
   long cells = 0, ghosts = 0;
   std::vector<Req *> joining;  // uploaded, to be added when the lane is idle
   std::vector<int> newly;

@@ -107,11 +107,11 @@ def empty_prim(p):
 
 # --------------------------------------------------------------- 1D problems
 
-def mhd_shock_tube(n=400, gamma=5.0 / 3.0, rk=3):
+def mhd_shock_tube(n=400, gamma=5.0 / 3.0, rk=3, **kw):
     """Balsara-type relativistic MHD shock tube on [-0.5, 0.5] (section
     3.2.2): left (rho, p, By) = (1, 1, 1), right (0.125, 0.1, -1), Bx = 0.5."""
     p = grid(1, CART, [n], [-0.5, 0, 0], [0.5, 1, 1], [[OUTFLOW, OUTFLOW]], gamma=gamma, rk=rk,
-             rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=gamma)
+             rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=gamma, **kw)
     x1, _, _ = centres(p)
     left = x1 < 0.0
     pr = empty_prim(p)
@@ -122,12 +122,12 @@ def mhd_shock_tube(n=400, gamma=5.0 / 3.0, rk=3):
     return p, pr, flat_metric(p)
 
 
-def srhd_shock_tube(n=400, gamma=5.0 / 3.0, rk=3, bx=0.0):
+def srhd_shock_tube(n=400, gamma=5.0 / 3.0, rk=3, bx=0.0, **kw):
     """Relativistic hydro shock tube on [0, 1] (section 3.1.2): left
     (rho, p, v) = (10, 40/3, 0), right (1, 0, 0), jump at x = 0.5.  A uniform
     field parallel to the flow (bx) leaves the hydrodynamics unchanged."""
     p = grid(1, CART, [n], [0, 0, 0], [1, 1, 1], [[OUTFLOW, OUTFLOW]], gamma=gamma, rk=rk,
-             rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=gamma)
+             rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=gamma, **kw)
     x1, _, _ = centres(p)
     left = x1 < 0.5
     pr = empty_prim(p)
@@ -145,12 +145,12 @@ def alfven_speed2(rho=1.0, pres=0.5, gamma=5.0 / 3.0, B0=1.0, A0=1.0):
     return a / (1.0 + math.sqrt(1.0 - (A0 * A0 * a) ** 2))
 
 
-def alfven_wave(n=128, t=0.0, rk=2, gamma=5.0 / 3.0):
+def alfven_wave(n=128, t=0.0, rk=2, gamma=5.0 / 3.0, **kw):
     """Large-amplitude circularly polarised Alfven wave on periodic [0, 1]
     (section 3.2.1), at time t (exact solution: the initial profile moved by
     v_A t along +x)."""
     p = grid(1, CART, [n], [0, 0, 0], [1, 1, 1], [[PERIODIC, PERIODIC]], gamma=gamma, rk=rk,
-             rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=gamma)
+             rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=gamma, **kw)
     x1, _, _ = centres(p)
     vA = math.sqrt(alfven_speed2(gamma=gamma))
     k = 2.0 * math.pi
@@ -208,13 +208,13 @@ def periodic_wave_3d(n=16, gamma=5.0 / 3.0, rk=3, bfield=(0.3, 0.2, 0.1), vel=(0
 
 # ------------------------------------------------------------------ blast
 
-def blast_wave_3d(n=256, seed=0, gamma=4.0 / 3.0, rk=3):
+def blast_wave_3d(n=256, seed=0, gamma=4.0 / 3.0, rk=3, **kw):
     """Relativistic magnetised blast wave in [-0.5, 0.5]^3: p = 1 inside
     r <= 0.1 and 0.01 outside, rho = 0.01 (1 + 1e-4 u) with u in [-1, 1) from
     the counter-based generator, v = 0, B = (0.1, 0, 0), Gamma = 4/3
     (a 3D variant of the cylindrical blast wave of section 3.2.3)."""
     p = grid(3, CART, [n, n, n], [-0.5] * 3, [0.5] * 3, [[OUTFLOW, OUTFLOW]] * 3, gamma=gamma, rk=rk,
-             rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=gamma)
+             rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=gamma, **kw)
     return p, blast_prim(p, seed), flat_metric(p)
 
 
@@ -229,10 +229,10 @@ def blast_prim(p, seed=0, r_in=0.1, p_in=1.0, p_out=0.01, rho0=0.01, bx=0.1):
     return pr
 
 
-def blast_wave_2d(n=128, seed=0, gamma=4.0 / 3.0, rk=3):
+def blast_wave_2d(n=128, seed=0, gamma=4.0 / 3.0, rk=3, **kw):
     """2D Cartesian blast wave of the same kind as blast_wave_3d."""
     p = grid(2, CART, [n, n], [-0.5, -0.5, 0], [0.5, 0.5, 1], [[OUTFLOW, OUTFLOW]] * 2, gamma=gamma, rk=rk,
-             rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=gamma)
+             rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=gamma, **kw)
     return p, blast_prim(p, seed), flat_metric(p)
 
 
