@@ -649,8 +649,36 @@ static void tvdlf(const double fl[NV], const double fr[NV], const double ql[NV],
   for (int v = 0; v < NV; v++) f[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * c * (qr[v] - ql[v]);
 }
 
+/* What the positivity-preserving limiter needs besides the states: the
+ * stage's time step and the state the stage's Euler step starts from. */
+typedef struct {
+  double dt;
+  const double *qbase;
+} pp_ctx;
+
+/* theta of one conserved component and one side of a face (section 2.4):
+ * the largest blend weight of the high-order flux that keeps the one-sided
+ * Euler update u -/+ 2 dt/dV (f dA) above eps; 1 when the high-order flux
+ * already does.  sgn = -1 for the cell below the face (u^-), +1 above (u^+);
+ * fho, flf are flux times face area. */
+static double pp_theta(double u, double dV, double dt, double fho, double flf, double sgn) {
+  const double eps = 1e-16;
+  if (u + sgn * 2.0 * dt / dV * fho > eps) return 1.0;
+  double den = sgn * (flf - fho);
+  if (den == 0.0) return 1.0;
+  return (dV / (2.0 * dt) * (u - eps) + sgn * flf) / den;
+}
+
+static void face_flux_pp(const og_desc *d, const double *prim, const double *met, int a, int f,
+                         int i, int j, int k, double out[NV], double *absterms, const pp_ctx *pp);
+
 static void face_flux_x(const og_desc *d, const double *prim, const double *met, int a, int f,
                         int i, int j, int k, double out[NV], double *absterms) {
+  face_flux_pp(d, prim, met, a, f, i, j, k, out, absterms, NULL);
+}
+
+static void face_flux_pp(const og_desc *d, const double *prim, const double *met, int a, int f,
+                         int i, int j, int k, double out[NV], double *absterms, const pp_ctx *pp) {
   int cell[3] = {i, j, k};
   double area = face_area(d, a, f, i, j, k);
   if (area == 0.0) {
@@ -712,6 +740,44 @@ static void face_flux_x(const og_desc *d, const double *prim, const double *met,
     hlle(fl, fr, ql, qr, fmin(lml, lmr), fmax(lpl, lpr), fh);
   }
   for (int v = 0; v < NV; v++) out[v] = fh[v] * area;
+  if (pp && d->pp) {
+    /* positivity-preserving limiter (section 2.4): blend with the
+     * first-order Lax-Friedrichs flux of the two adjacent cell states (face
+     * metric), theta from D and tau on both sides, the smaller one kept
+     * (the largest theta for which both stay positive) */
+    double p0[NV], p1[NV];
+    for (int v = 0; v < NV; v++) {
+      p0[v] = prim[v * nt + idx[2]];
+      p1[v] = prim[v * nt + idx[3]];
+    }
+    pstate s0, s1;
+    point_state(d->gamma, p0, mf[0], mf[1], mf + 2, ref, &s0);
+    point_state(d->gamma, p1, mf[0], mf[1], mf + 2, ref, &s1);
+    double q0[NV], q1[NV], f0[NV], f1[NV], lm0, lp0, lm1, lp1, flf[NV];
+    cons_from_state(&s0, q0);
+    cons_from_state(&s1, q1);
+    flux_from_state(&s0, a, f0);
+    flux_from_state(&s1, a, f1);
+    speeds_from_state(d->gamma, &s0, a, &lm0, &lp0);
+    speeds_from_state(d->gamma, &s1, a, &lm1, &lp1);
+    tvdlf(f0, f1, q0, q1, fmax(fmax(fabs(lm0), fabs(lp0)), fmax(fabs(lm1), fabs(lp1))), flf);
+    int c0[3] = {cell[0], cell[1], cell[2]}, c1[3] = {cell[0], cell[1], cell[2]};
+    c0[a] = f - 1;
+    c1[a] = f;
+    double dV0 = cell_volume(d, c0[0], c0[1], c0[2]), dV1 = cell_volume(d, c1[0], c1[1], c1[2]);
+    double theta = 1.0;
+    const int comp[2] = {QD, QTAU};
+    for (int m = 0; m < 2; m++) {
+      int v = comp[m];
+      double fho = out[v], fl = flf[v] * area;
+      double tm = pp_theta(pp->qbase[v * nt + idx[2]], dV0, pp->dt, fho, fl, -1.0);
+      double tp = pp_theta(pp->qbase[v * nt + idx[3]], dV1, pp->dt, fho, fl, +1.0);
+      theta = fmin(theta, fmin(tm, tp));
+    }
+    theta = fmin(fmax(theta, 0.0), 1.0);
+    if (theta < 1.0)
+      for (int v = 0; v < NV; v++) out[v] = theta * out[v] + (1.0 - theta) * flf[v] * area;
+  }
   if (absterms) {
     /* magnitude of the terms summed by the HLLE formula, with the states'
      * and fluxes' own term magnitudes (error scale) */
@@ -730,11 +796,6 @@ static void face_flux_x(const og_desc *d, const double *prim, const double *met,
       absterms[v] = t * area;
     }
   }
-}
-
-static void face_flux(const og_desc *d, const double *prim, const double *met, int a, int f, int i, int j, int k,
-                      double out[NV]) {
-  face_flux_x(d, prim, met, a, f, i, j, k, out, NULL);
 }
 
 /* -------------------------------------------------------------- sources */
@@ -901,14 +962,24 @@ static void geom_sources(const og_desc *d, const pstate *st, int i, int j, int k
  * cell volume plus the gravitational and geometric sources (section 2.1,
  * the discretised equation; the minus sign on the flux bracket follows from
  * the conservation law and the positivity-limiter form of section 2.4). */
+static void rhs_cell_pp(const og_desc *d, const double *prim, const double *met, int i, int j, int k, double dq[NV],
+                        const pp_ctx *pp);
+
 void og_rhs_cell(const og_desc *d, const double *prim, const double *met, int i, int j, int k, double dq[NV]) {
+  rhs_cell_pp(d, prim, met, i, j, k, dq, NULL);
+}
+
+/* The same with the positivity-preserving limiter on the face fluxes when
+ * the descriptor asks for it and pp is given. */
+static void rhs_cell_pp(const og_desc *d, const double *prim, const double *met, int i, int j, int k, double dq[NV],
+                        const pp_ctx *pp) {
   int cell[3] = {i, j, k};
   for (int v = 0; v < NV; v++) dq[v] = 0.0;
   double dV = cell_volume(d, i, j, k);
   for (int a = 0; a < d->ndim; a++) {
     double fm[NV], fp[NV];
-    face_flux(d, prim, met, a, cell[a], i, j, k, fm);
-    face_flux(d, prim, met, a, cell[a] + 1, i, j, k, fp);
+    face_flux_pp(d, prim, met, a, cell[a], i, j, k, fm, NULL, pp);
+    face_flux_pp(d, prim, met, a, cell[a] + 1, i, j, k, fp, NULL, pp);
     for (int v = 0; v < NV; v++) dq[v] -= (fp[v] - fm[v]) / dV;
   }
   long nt = ntot(d), c = at(d, i, j, k);
@@ -1131,7 +1202,16 @@ long og_rk_stage(const og_desc *d, int stage, double dt, const double *qn, doubl
   else if (stage == 1) { a = 0.75; b = 0.25; }
   else { a = 1.0 / 3.0; b = 2.0 / 3.0; }
   double *L = (double *)malloc(sizeof(double) * NV * nt);
-  og_rhs(d, prim, met, L);
+  /* the stage's Euler step starts from q_n in stage 0, from q_s after */
+  pp_ctx pp = {dt, stage == 0 ? qn : qs};
+  for (int k = 0; k < d->n[2]; k++)
+    for (int j = 0; j < d->n[1]; j++)
+      for (int i = 0; i < d->n[0]; i++) {
+        double dq[NV];
+        rhs_cell_pp(d, prim, met, i, j, k, dq, &pp);
+        long c = at(d, i, j, k);
+        for (int v = 0; v < NV; v++) L[v * nt + c] = dq[v];
+      }
   for (int k = 0; k < d->n[2]; k++)
     for (int j = 0; j < d->n[1]; j++)
       for (int i = 0; i < d->n[0]; i++) {
