@@ -76,6 +76,7 @@ def lib():
         L.og_cfl_dt.restype = ctypes.c_double
         L.og_rk_stage.argtypes = [P, ctypes.c_int, ctypes.c_double, P, P, P, P, P]
         L.og_rk_stage.restype = ctypes.c_long
+        L.og_rk_update.argtypes = [P, ctypes.c_int, ctypes.c_double, P, P, P, P]
         L.og_evolve.argtypes = [P, P, P, P, ctypes.c_double, P, ctypes.c_double, ctypes.c_long, P]
         L.og_evolve.restype = ctypes.c_long
         L.og_point_prim2con.argtypes = [ctypes.c_double, P, P, P, P]
@@ -204,6 +205,15 @@ def rk_stage(p, stage, dt, qn, qs, prim, metric, flags=None):
     metric = _chk(metric)
     fp = _p(flags) if flags is not None else None
     return int(lib().og_rk_stage(_ref(d), stage, dt, _p(qn), _p(qs), _p(prim), _p(metric), fp))
+
+
+def rk_update(p, stage, dt, qn, qs, prim, metric):
+    """The stage's new conserved state in qs before the recovery."""
+    d = make_desc(p)
+    for a in (qn, qs, prim):
+        assert a.flags.c_contiguous and a.dtype == np.float64
+    metric = _chk(metric)
+    lib().og_rk_update(_ref(d), stage, dt, _p(qn), _p(qs), _p(prim), _p(metric))
 
 
 def evolve(p, q, prim, metric, cfl, t=0.0, t_end=float("inf"), nsteps=1 << 60):

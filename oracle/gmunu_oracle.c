@@ -765,14 +765,17 @@ static void face_flux_pp(const og_desc *d, const double *prim, const double *met
     c0[a] = f - 1;
     c1[a] = f;
     double dV0 = cell_volume(d, c0[0], c0[1], c0[2]), dV1 = cell_volume(d, c1[0], c1[1], c1[2]);
+    /* only the sides that are interior cells count: a ghost cell is not
+     * advanced by the step, so its positivity is not at stake (and its
+     * conserved state is not maintained) */
+    int in0 = c0[a] >= 0, in1 = c1[a] < d->n[a];
     double theta = 1.0;
     const int comp[2] = {QD, QTAU};
     for (int m = 0; m < 2; m++) {
       int v = comp[m];
       double fho = out[v], fl = flf[v] * area;
-      double tm = pp_theta(pp->qbase[v * nt + idx[2]], dV0, pp->dt, fho, fl, -1.0);
-      double tp = pp_theta(pp->qbase[v * nt + idx[3]], dV1, pp->dt, fho, fl, +1.0);
-      theta = fmin(theta, fmin(tm, tp));
+      if (in0) theta = fmin(theta, pp_theta(pp->qbase[v * nt + idx[2]], dV0, pp->dt, fho, fl, -1.0));
+      if (in1) theta = fmin(theta, pp_theta(pp->qbase[v * nt + idx[3]], dV1, pp->dt, fho, fl, +1.0));
     }
     theta = fmin(fmax(theta, 0.0), 1.0);
     if (theta < 1.0)
@@ -1191,10 +1194,12 @@ double og_cfl_dt(const og_desc *d, const double *prim, const double *met, double
  *           un+1 = 1/3 un + 2/3 (u2 + dt L(u2))
  *   SSPRK2: u1 = un + dt L(un); un+1 = 1/2 un + 1/2 (u1 + dt L(u1)).
  * prim must hold the primitives of the current stage state with ghosts.
- * On return qs holds the new stage state and prim its primitives (c2p, then
- * ghost fill).  Returns the number of fatal c2p cells. */
-long og_rk_stage(const og_desc *d, int stage, double dt, const double *qn, double *qs, double *prim,
-                 const double *met, uint8_t *flags) {
+ * og_rk_update leaves the new stage state in qs (interior cells) before any
+ * recovery; og_rk_stage then recovers prim (c2p, which may rewrite q of
+ * corrected cells) and fills its ghosts, and returns the number of fatal c2p
+ * cells. */
+void og_rk_update(const og_desc *d, int stage, double dt, const double *qn, double *qs, const double *prim,
+                  const double *met) {
   long nt = ntot(d);
   double a, b;
   if (stage == 0) { a = 0.0; b = 1.0; }
@@ -1223,6 +1228,11 @@ long og_rk_stage(const og_desc *d, int stage, double dt, const double *qn, doubl
         }
       }
   free(L);
+}
+
+long og_rk_stage(const og_desc *d, int stage, double dt, const double *qn, double *qs, double *prim,
+                 const double *met, uint8_t *flags) {
+  og_rk_update(d, stage, dt, qn, qs, prim, met);
   long nf = og_c2p(d, qs, met, prim, flags);
   og_fill_ghosts(d, prim);
   return nf;

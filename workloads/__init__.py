@@ -236,6 +236,52 @@ def blast_wave_2d(n=128, seed=0, gamma=4.0 / 3.0, rk=3, **kw):
     return p, blast_prim(p, seed), flat_metric(p)
 
 
+# ------------------------------------------------------ near-vacuum flows
+
+def receding_flow(coord=CART, ndim=1, n=(16, 1, 1), axis=0, centre=None, width=1, rho_low=1e-8, u=2.0,
+                  gamma=5.0 / 3.0, rk=3, **kw):
+    """Dense fluid (rho = p = 1) moving away along `axis` with W v = u from a
+    slab of `width` near-empty static cells (rho = p = rho_low) starting at
+    interior index `centre` (default the middle): the flow that opens a near
+    vacuum, where the high-order Euler update of the slab goes negative.
+    Domains as in uniform_state; outflow boundaries, ghosts not filled."""
+    if coord == CYL:
+        xmin, xmax = [0.5, -1.0, 0.0], [2.5, 1.0, 2 * math.pi]
+    elif coord == SPH:
+        xmin, xmax = [0.5, 0.3, 0.0], [2.5, math.pi - 0.3, 2 * math.pi]
+    else:
+        xmin, xmax = [0, 0, 0], [1, 1, 1]
+    nn = list(n[:ndim]) + [1] * (3 - ndim)
+    p = grid(ndim, coord, nn, xmin, xmax, [[OUTFLOW, OUTFLOW]] * ndim, gamma=gamma, rk=rk,
+             rho_atmo=1e-20, k_atmo=1.0, gamma_atmo=gamma, **kw)
+    pr = empty_prim(p)
+    c0 = nn[axis] // 2 if centre is None else centre
+    gi = np.arange(pr.shape[3 - axis]) - ghosts(p)[axis]
+    shape_ = [1, 1, 1]
+    shape_[2 - axis] = -1
+    gi = gi.reshape(shape_)
+    slab = (gi >= c0) & (gi < c0 + width)
+    pr[0] = np.where(slab, rho_low, 1.0)
+    pr[4] = np.where(slab, rho_low, 1.0)
+    pr[1 + axis] = np.where(gi < c0, -u, np.where(slab, 0.0, u))
+    return p, pr, flat_metric(p)
+
+
+def two_streams(n=200, v=0.99, gamma=5.0 / 3.0, rk=3, **kw):
+    """Periodic 1D flow on [-1/2, 1/2]: the middle half moves outwards at v
+    and the outer half inwards, so a near vacuum opens at x = 0 and the
+    streams collide at the periodic seam (rho = 1, p = 1e-3)."""
+    p = grid(1, CART, [n], [-0.5, 0, 0], [0.5, 1, 1], [[PERIODIC, PERIODIC]], gamma=gamma, rk=rk,
+             rho_atmo=1e-20, k_atmo=1.0, gamma_atmo=gamma, **kw)
+    x1, _, _ = centres(p)
+    pr = empty_prim(p)
+    Wl = 1 / math.sqrt(1 - v * v)
+    pr[0] = 1.0
+    pr[4] = 1e-3
+    pr[1] = Wl * v * np.sign(x1) * (np.abs(x1) < 0.25) - Wl * v * np.sign(x1) * (np.abs(x1) >= 0.25)
+    return p, pr, flat_metric(p)
+
+
 # ------------------------------------------------------------ uniform state
 
 def uniform_state(coord, ndim=2, n=(16, 16, 8), rho=1.0, pres=0.3, gamma=5.0 / 3.0, bfield=(0, 0, 0)):
