@@ -100,7 +100,9 @@ typedef struct gmunu_grid_desc {
   int rk;                    /* 3: SSPRK3, 2: SSPRK2 */
   int recon;                 /* GMUNU_RECON_* (reconstruction of the face states) */
   int riemann;               /* GMUNU_RIEMANN_* (approximate Riemann solver) */
-  int pp_limiter;            /* 1: positivity-preserving flux limiter (section 2.4) */
+  int pp_limiter;            /* 1: positivity-preserving flux limiter (section 2.4);
+                                single grids only (gmunu_batch_set_block and
+                                gmunu_server_submit reject it) */
   int c2p;                   /* GMUNU_C2P_* (primitive recovery scheme, section 2.5) */
 } gmunu_grid_desc;
 
@@ -145,7 +147,8 @@ int gmunu_fill_ghosts(gmunu_ctx *ctx, double *prim, void *stream);
 /* dq/dt on the interior cells: minus the flux-area divergence over the cell
  * volume plus gravitational and geometric sources (section 2.1, the
  * discretised equation), from primitives whose ghosts are filled.  Ghost
- * entries of dqdt are untouched. */
+ * entries of dqdt are untouched.  The positivity-preserving limiter acts on
+ * a stage's Euler step and is not applied here. */
 int gmunu_rhs(gmunu_ctx *ctx, const double *prim, const double *metric, double *dqdt, void *stream);
 
 /* Time step by the maxsum rule (section 2.9): dt = cfl / max over interior
@@ -158,8 +161,12 @@ int gmunu_cfl_dt(gmunu_ctx *ctx, const double *prim, const double *metric, doubl
  *   q_out = a q_n + b (q_s + dt L(prim_in)),  (a,b) = (0,1) for stage 0,
  *   SSPRK3 stage 1 (3/4, 1/4), stage 2 (1/3, 2/3); SSPRK2 stage 1 (1/2, 1/2);
  * then q_out -> prim_out by gmunu_c2p and the ghost fill.  q_s is not read in
- * stage 0.  q_out may alias q_n or q_s (each cell reads only its own q).
- * prim_out may alias prim_in.  dt is read from dt_dev. */
+ * stage 0.  q_out may alias q_n or q_s (each cell reads only its own q),
+ * except that with the positivity-preserving limiter (section 2.4) the stage
+ * also reads the base state of the neighbouring cells (q_n in stage 0, q_s
+ * after): then q_out must not overlap the base, and GMUNU_EINVAL is returned
+ * when it is the same pointer.  prim_out may alias prim_in.  dt is read from
+ * dt_dev. */
 int gmunu_rk_stage(gmunu_ctx *ctx, int stage, const double *dt_dev, const double *q_n, const double *q_s,
                    double *q_out, const double *prim_in, double *prim_out, const double *metric,
                    uint8_t *flags, unsigned int *nfatal_dev, void *stream);
@@ -169,7 +176,9 @@ int gmunu_rk_stage(gmunu_ctx *ctx, int stage, const double *dt_dev, const double
  * consistent with q^{n+1} with ghosts filled, and *t_dev += dt.  Device-side
  * time keeps the call graph-capturable.  Once *t_dev has reached t_end the
  * computed dt is 0 and the step changes nothing (q_n, q_s, prim and flags
- * are left as they are), so a caller may issue steps past the end. */
+ * are left as they are), so a caller may issue steps past the end.  With the
+ * limiter and SSPRK3 the middle stage writes a third state that the context
+ * holds (allocated by gmunu_create). */
 int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, double cfl,
                double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
                void *stream);
@@ -207,6 +216,9 @@ typedef struct gmunu_block {
  * geometry table is rewritten in place by set_block). */
 int gmunu_batch_create(int max_blocks, int max_groups, long max_items, gmunu_batch **out);
 int gmunu_batch_destroy(gmunu_batch *b);
+/* GMUNU_EINVAL for an invalid descriptor or one with pp_limiter set (the
+ * batched stage updates q_s in place, which the limiter's reads of
+ * neighbouring base states rule out). */
 int gmunu_batch_set_block(gmunu_batch *b, int slot, const gmunu_block *blk);
 int gmunu_batch_clear_block(gmunu_batch *b, int slot);
 /* Time, end time and step limit of a group (applied at the next commit,
@@ -314,7 +326,8 @@ double gmunu_server_clock(void);
  * current device. */
 int gmunu_server_create(size_t hbm_bytes, int max_slots, double cfl, int steps_per_sync, gmunu_server **out);
 /* Queue a solve (non-blocking).  GMUNU_EINVAL if the descriptor is invalid
- * or the solve can never fit the arena; GMUNU_ESTOP after a worker error. */
+ * or asks for the limiter (solves run in a batch), or the solve can never fit
+ * the arena; GMUNU_ESTOP after a worker error. */
 int gmunu_server_submit(gmunu_server *s, const gmunu_request *req, unsigned long long *id_out);
 /* Move up to `max` finished results into out; waits up to timeout_ms for the
  * first one if none is ready.  Returns the number moved (>= 0) or an error. */

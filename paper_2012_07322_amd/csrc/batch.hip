@@ -527,6 +527,9 @@ int gmunu_batch_set_block(gmunu_batch *b, int slot, const gmunu_block *blk) {
   if (slot < 0 || slot >= b->maxb || blk->group < 0 || blk->group >= b->maxg) return GMUNU_EINVAL;
   const int rc = validate_desc(blk->desc);
   if (rc) return rc;
+  // the batched stage updates q_s in place, which the limiter (reading the
+  // base state of neighbouring cells) does not allow
+  if (blk->desc.pp_limiter) return GMUNU_EINVAL;
   if (!blk->q_n || !blk->q_s || !blk->prim || !blk->metric) return GMUNU_ENULL;
   if (!aligned8(blk->q_n) || !aligned8(blk->q_s) || !aligned8(blk->prim) || !aligned8(blk->metric))
     return GMUNU_EALIGN;

@@ -34,6 +34,7 @@ struct gmunu_ctx {
   int device;
   double *geo;                 // packed 1D geometry tables (device)
   double *acc;                 // CFL partial maxima (device, kCflParts words)
+  double *qt;                  // limiter only: third conserved state for the middle SSPRK3 stage
   // launch timing (measurement only)
   int prof;
   std::vector<hipEvent_t> ev;  // pairs
@@ -74,9 +75,10 @@ __device__ __forceinline__ void xcd_tile(const Grid &G, int TX, int TY, int TZ, 
   bz = L / (gx * gy);
 }
 
-// MODE 0: dqdt = L(prim).  MODE 1: q_out = ca q_n + cb (q_s + dt L(prim)).
+// MODE 0: dqdt = L(prim).  MODE 1: q_out = ca q_n + cb (q_s + dt L(prim)),
+// with the positivity-preserving flux limiter when P = 1.
 // skipp (nullable): nothing is done when *skipp == 0 (a step past t_end).
-template <int TX, int TY, int TZ, int ND, int MODE, int H, int R>
+template <int TX, int TY, int TZ, int ND, int MODE, int H, int R, int P>
 __global__ __launch_bounds__(NT, 3) void k_stage(const Grid G, const double *__restrict__ prim,
                                                          const double *__restrict__ met, const double *qn,
                                                          const double *qs, double *out,
@@ -86,7 +88,8 @@ __global__ __launch_bounds__(NT, 3) void k_stage(const Grid G, const double *__r
   if (skipp && *skipp == 0.0) return;
   int bx, by, bz;
   xcd_tile(G, TX, TY, TZ, bx, by, bz);
-  stage_tile<TX, TY, TZ, ND, MODE, H, R>(G, bx * TX, by * TY, bz * TZ, prim, met, qn, qs, out, dtp, ca, cb, sF);
+  stage_tile<TX, TY, TZ, ND, MODE, H, R, P>(G, bx * TX, by * TY, bz * TZ, prim, met, qn, qs, out, dtp, ca, cb,
+                                            sF);
 }
 
 __global__ __launch_bounds__(NT) void k_c2p(const Grid G, double *q, const double *__restrict__ met, double *prim,
@@ -132,13 +135,13 @@ __global__ __launch_bounds__(NT) void k_cfl_finish(const double *part, int npart
 
 __global__ void k_advance(double *tp, const double *dtp) { *tp += *dtp; }
 
-template <int TX, int TY, int TZ, int ND, int MODE, int H, int R>
+template <int TX, int TY, int TZ, int ND, int MODE, int H, int R, int P>
 void launch_stage_t(const gmunu_ctx *ctx, const double *prim, const double *met, const double *qn,
                     const double *qs, double *out, const double *dtp, double ca, double cb, const double *skipp,
                     hipStream_t st) {
   const Grid &G = ctx->G;
   dim3 grid(((G.n[0] + TX - 1) / TX) * ((G.n[1] + TY - 1) / TY) * ((G.n[2] + TZ - 1) / TZ));
-  hipLaunchKernelGGL((k_stage<TX, TY, TZ, ND, MODE, H, R>), grid, dim3(NT), 0, st, G, prim, met, qn, qs, out,
+  hipLaunchKernelGGL((k_stage<TX, TY, TZ, ND, MODE, H, R, P>), grid, dim3(NT), 0, st, G, prim, met, qn, qs, out,
                      dtp, ca, cb, skipp);
 }
 
@@ -147,23 +150,27 @@ void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, c
                   const double *qs, double *out, const double *dtp, double ca, double cb, const double *skipp,
                   hipStream_t st) {
   const int mp5 = ctx->G.recon == GMUNU_RECON_MP5, lf = ctx->G.riemann == GMUNU_RIEMANN_TVDLF;
-  switch (ctx->G.ndim * 4 + mp5 * 2 + lf) {
-#define GM_CASE(NDIM, TX, TY, TZ, M, L)                                                                         \
-  case NDIM * 4 + M * 2 + L:                                                                                     \
-    launch_stage_t<TX, TY, TZ, NDIM, MODE, 2 + M, L>(ctx, prim, met, qn, qs, out, dtp, ca, cb, skipp, st);       \
+  // the limiter acts on the stage's Euler step, so the RHS alone (MODE 0) is unlimited
+  const int pp = MODE == 1 && ctx->G.pp;
+  switch (ctx->G.ndim * 8 + mp5 * 4 + lf * 2 + pp) {
+#define GM_CASE(NDIM, TX, TY, TZ, M, L, P)                                                                      \
+  case NDIM * 8 + M * 4 + L * 2 + P:                                                                             \
+    launch_stage_t<TX, TY, TZ, NDIM, MODE, 2 + M, L, MODE == 1 && P>(ctx, prim, met, qn, qs, out, dtp, ca, cb,   \
+                                                                     skipp, st);                                  \
     break;
-    GM_CASE(1, 255, 1, 1, 0, 0)
-    GM_CASE(1, 255, 1, 1, 0, 1)
-    GM_CASE(1, 255, 1, 1, 1, 0)
-    GM_CASE(1, 255, 1, 1, 1, 1)
-    GM_CASE(2, 16, 15, 1, 0, 0)
-    GM_CASE(2, 16, 15, 1, 0, 1)
-    GM_CASE(2, 16, 15, 1, 1, 0)
-    GM_CASE(2, 16, 15, 1, 1, 1)
-    GM_CASE(3, 8, 5, 5, 0, 0)
-    GM_CASE(3, 8, 5, 5, 0, 1)
-    GM_CASE(3, 8, 5, 5, 1, 0)
-    GM_CASE(3, 8, 5, 5, 1, 1)
+#define GM_CASES(NDIM, TX, TY, TZ) \
+  GM_CASE(NDIM, TX, TY, TZ, 0, 0, 0) \
+  GM_CASE(NDIM, TX, TY, TZ, 0, 0, 1) \
+  GM_CASE(NDIM, TX, TY, TZ, 0, 1, 0) \
+  GM_CASE(NDIM, TX, TY, TZ, 0, 1, 1) \
+  GM_CASE(NDIM, TX, TY, TZ, 1, 0, 0) \
+  GM_CASE(NDIM, TX, TY, TZ, 1, 0, 1) \
+  GM_CASE(NDIM, TX, TY, TZ, 1, 1, 0) \
+  GM_CASE(NDIM, TX, TY, TZ, 1, 1, 1)
+    GM_CASES(1, 255, 1, 1)
+    GM_CASES(2, 16, 15, 1)
+    GM_CASES(3, 8, 5, 5)
+#undef GM_CASES
 #undef GM_CASE
     default:
       break;
@@ -245,10 +252,21 @@ int gmunu_create(const gmunu_grid_desc *desc, gmunu_ctx **out) {
     delete ctx;
     return GMUNU_ENOMEM;
   }
+  // with the limiter a stage reads the base state of neighbouring cells, so
+  // its output may not overwrite its base: the step needs a third state
+  ctx->qt = nullptr;
+  if (desc->pp_limiter && desc->rk == 3 &&
+      hipMalloc(&ctx->qt, (size_t)NV * ctx->G.nv * sizeof(double)) != hipSuccess) {
+    (void)hipFree(ctx->geo);
+    (void)hipFree(ctx->acc);
+    delete ctx;
+    return GMUNU_ENOMEM;
+  }
   if (hipMemcpy(ctx->geo, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(ctx->acc, 0, kCflParts * sizeof(double)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(ctx->geo);
     (void)hipFree(ctx->acc);
+    if (ctx->qt) (void)hipFree(ctx->qt);
     delete ctx;
     return GMUNU_EHIP;
   }
@@ -263,6 +281,7 @@ int gmunu_destroy(gmunu_ctx *ctx) {
   for (auto e : ctx->ev) (void)hipEventDestroy(e);
   if (hipFree(ctx->geo) != hipSuccess) rc = GMUNU_EHIP;
   if (hipFree(ctx->acc) != hipSuccess) rc = GMUNU_EHIP;
+  if (ctx->qt && hipFree(ctx->qt) != hipSuccess) rc = GMUNU_EHIP;
   delete ctx;
   return rc;
 }
@@ -324,6 +343,7 @@ int gmunu_rk_stage(gmunu_ctx *ctx, int stage, const double *dt_dev, const double
   if (!ctx || !dt_dev || !q_n || !q_out || !prim_in || !prim_out || !metric) return GMUNU_ENULL;
   if (stage > 0 && !q_s) return GMUNU_ENULL;
   if (stage < 0 || stage >= ctx->d.rk) return GMUNU_EINVAL;
+  if (ctx->d.pp_limiter && q_out == (stage == 0 ? q_n : q_s)) return GMUNU_EINVAL;
   return rk_stage_impl(ctx, stage, dt_dev, q_n, q_s, q_out, prim_in, prim_out, metric, flags, nfatal_dev, nullptr,
                        as_stream(stream));
 }
@@ -335,9 +355,14 @@ int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const dou
   int rc = gmunu_cfl_dt(ctx, prim, metric, cfl, t_end, t_dev, dt_dev, stream);
   if (rc) return rc;
   const int nst = ctx->d.rk;
+  // stage s reads base[s] and writes base[s + 1] (q_n last); without the
+  // limiter a stage reads only its own cell's base, so the middle SSPRK3
+  // stage may update q_s in place
+  double *base[4] = {q_n, q_s, q_s, q_n};
+  if (nst == 2) base[2] = q_n;
+  if (nst == 3 && ctx->qt) base[2] = ctx->qt;
   for (int s = 0; s < nst; s++) {
-    double *out = (s == nst - 1) ? q_n : q_s;
-    rc = rk_stage_impl(ctx, s, dt_dev, q_n, q_s, out, prim, prim, metric, flags, nfatal_dev, dt_dev,
+    rc = rk_stage_impl(ctx, s, dt_dev, q_n, base[s], base[s + 1], prim, prim, metric, flags, nfatal_dev, dt_dev,
                        as_stream(stream));
     if (rc) return rc;
   }

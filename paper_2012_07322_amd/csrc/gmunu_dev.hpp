@@ -58,6 +58,7 @@ struct Grid {
   int recon;    // GMUNU_RECON_*
   int riemann;  // GMUNU_RIEMANN_*
   int c2p;      // GMUNU_C2P_*
+  int pp;       // positivity-preserving flux limiter on (single grids)
   int bc[3][2];
   Geo geo;
 };

@@ -48,7 +48,7 @@ inline int validate_desc(const gmunu_grid_desc &d) {
   if (d.recon != GMUNU_RECON_MC && d.recon != GMUNU_RECON_MP5) return GMUNU_EINVAL;
   if (d.recon == GMUNU_RECON_MP5 && d.ng < 3) return GMUNU_EINVAL;
   if (d.riemann != GMUNU_RIEMANN_HLLE && d.riemann != GMUNU_RIEMANN_TVDLF) return GMUNU_EINVAL;
-  if (d.pp_limiter != 0) return GMUNU_EINVAL;
+  if (d.pp_limiter != 0 && d.pp_limiter != 1) return GMUNU_EINVAL;
   if (d.c2p != GMUNU_C2P_GRMHD && d.c2p != GMUNU_C2P_GRHD_Z) return GMUNU_EINVAL;
   return GMUNU_OK;
 }
@@ -93,6 +93,7 @@ inline GeoOffsets setup_grid(const gmunu_grid_desc &d, Grid &G, std::vector<doub
   G.recon = d.recon;
   G.riemann = d.riemann;
   G.c2p = d.c2p;
+  G.pp = d.pp_limiter;
 
   auto put = [&](const std::vector<double> &v) {
     size_t off = tab.size();

@@ -20,6 +20,26 @@ __device__ __forceinline__ double ld(const double *__restrict__ base, long nv, i
   return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base + v * nv) + ob);
 }
 
+// What the positivity-preserving limiter needs besides the staged states:
+// the conserved state the stage's Euler step starts from and the step.
+struct PPBase {
+  const double *q;  // base conserved state (q_n in the first stage, q_s after)
+  double dt;
+};
+
+// theta of one conserved component on one side of a face (section 2.4): the
+// largest weight of the high-order flux for which the one-sided Euler update
+// u + sgn w F stays above eps, 1 when the high-order flux already keeps it
+// there.  w = 2 dt / cv_D of the cell, sgn = -1 below the face, +1 above; fho,
+// flf are the high-order and Lax-Friedrichs fluxes times the face factor.
+__device__ __forceinline__ double pp_side(double u, double w, double fho, double flf, double sgn) {
+  constexpr double eps = 1e-16;
+  if (u + sgn * w * fho > eps) return 1.0;
+  const double den = sgn * w * (flf - fho);
+  if (den == 0.0) return 1.0;
+  return ((u - eps) + sgn * w * flf) / den;
+}
+
 // Face flux times face factor through the lower face (along D) of cell
 // (i,j,k): reconstruction from the cells across the face (H = 2: MC from
 // four cells; H = 3: MP5 from six), metric as the mean of the two adjacent
@@ -27,9 +47,15 @@ __device__ __forceinline__ double ld(const double *__restrict__ base, long nv, i
 // workgroup's staged region S (RC cells per variable, prim variables 0-7,
 // metric 8-12): r0 is the region index of the cell H below the face, rs the
 // region stride along D.
-template <int D, int H, int R>
+//
+// P = 1 applies the positivity-preserving limiter (section 2.4): the flux is
+// blended with the first-order Lax-Friedrichs flux of the two adjacent cell
+// states, with the largest theta that keeps D and tau of the Euler update of
+// both adjacent interior cells above eps (ghost cells are not advanced and do
+// not take part).
+template <int D, int H, int R, int P = 0>
 __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC, int r0, int rs, int i, int j,
-                                          int k, double *Fo) {
+                                          int k, double *Fo, const PPBase &pb = PPBase{nullptr, 0.0}) {
   const int cd = (D == 0 ? i : D == 1 ? j : k) + G.g[D];
   // zero-area faces (r = 0, theta = 0 or pi) are evaluated like any other
   // and their flux replaced by 0 at the end; no load-dependent branch here
@@ -91,17 +117,53 @@ __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC
       const double f = (0.5 * (FL[v] + FR[v]) - 0.5 * c * (UR[v] - UL[v])) * fa;
       Fo[v] = fa == 0.0 ? 0.0 : f;
     }
-    return;
-  }
-  const double ap = fmax(0.0, fmax(lpL, lpR));
-  const double am = fmin(0.0, fmin(lmL, lmR));
-  const double den = ap - am;
-  const bool avg = den < kTiny;
-  const double s = fa * rcp(avg ? 1.0 : den);
+  } else {
+    const double ap = fmax(0.0, fmax(lpL, lpR));
+    const double am = fmin(0.0, fmin(lmL, lmR));
+    const double den = ap - am;
+    const bool avg = den < kTiny;
+    const double s = fa * rcp(avg ? 1.0 : den);
 #pragma unroll
-  for (int v = 0; v < NV; v++) {
-    const double f = avg ? 0.5 * (FL[v] + FR[v]) * fa : (ap * FL[v] - am * FR[v] + ap * am * (UR[v] - UL[v])) * s;
-    Fo[v] = fa == 0.0 ? 0.0 : f;
+    for (int v = 0; v < NV; v++) {
+      const double f =
+          avg ? 0.5 * (FL[v] + FR[v]) * fa : (ap * FL[v] - am * FR[v] + ap * am * (UR[v] - UL[v])) * s;
+      Fo[v] = fa == 0.0 ? 0.0 : f;
+    }
+  }
+  if constexpr (P) {
+    // zero-area faces carry no flux either way
+    if (fa == 0.0) return;
+    double p0[NV], p1[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      p0[v] = S[v * RC + r1];
+      p1[v] = S[v * RC + r2];
+    }
+    double U0[NV], F0[NV], U1[NV], F1[NV], lm0, lp0, lm1, lp1;
+    state_flux<D>(G.gam, G.gfac, p0, psi4, psi6, alpha, beta, g1, g2, gud, U0, F0, lm0, lp0);
+    state_flux<D>(G.gam, G.gfac, p1, psi4, psi6, alpha, beta, g1, g2, gud, U1, F1, lm1, lp1);
+    const double c = fmax(fmax(fabs(lm0), fabs(lp0)), fmax(fabs(lm1), fabs(lp1)));
+    double Fl[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) Fl[v] = (0.5 * (F0[v] + F1[v]) - 0.5 * c * (U1[v] - U0[v])) * fa;
+    // the cells below (interior index cd - 1) and above (cd) the face
+    const int cd = D == 0 ? i : D == 1 ? j : k;
+    const bool in0 = cd >= 1, in1 = cd < G.n[D];
+    const long o1 = cell_offset(G, i, j, k), o0 = o1 - G.s[D];
+    const double w0 = in0 ? 2.0 * pb.dt * G.geo.icv[D][cd - 1 + G.g[D]] : 0.0;
+    const double w1 = in1 ? 2.0 * pb.dt * G.geo.icv[D][cd + G.g[D]] : 0.0;
+    double theta = 1.0;
+#pragma unroll
+    for (int m = 0; m < 2; m++) {
+      const int v = m == 0 ? 0 : 4;  // D and tau
+      if (in0) theta = fmin(theta, pp_side(pb.q[v * G.nv + o0], w0, Fo[v], Fl[v], -1.0));
+      if (in1) theta = fmin(theta, pp_side(pb.q[v * G.nv + o1], w1, Fo[v], Fl[v], 1.0));
+    }
+    theta = fmin(fmax(theta, 0.0), 1.0);
+    if (theta < 1.0) {
+#pragma unroll
+      for (int v = 0; v < NV; v++) Fo[v] = theta * Fo[v] + (1.0 - theta) * Fl[v];
+    }
   }
 }
 
@@ -302,10 +364,11 @@ constexpr bool tile_fits() {
 // (1) stage prim and metric of the pass's region into LDS (coalesced, each
 // value read once from memory), (2) one face per thread from LDS, (3) the
 // fluxes through LDS to the cells on both sides of each face.
-template <int TX, int TY, int TZ, int D, int H, int R>
+template <int TX, int TY, int TZ, int D, int H, int R, int P = 0>
 __device__ __forceinline__ void face_pass(const Grid &G, const double *__restrict__ prim,
                                           const double *__restrict__ met, double *S, int i0, int j0, int k0,
-                                          int tx, int ty, int tz, bool valid, double *acc) {
+                                          int tx, int ty, int tz, bool valid, double *acc,
+                                          const PPBase &pb = PPBase{nullptr, 0.0}) {
   constexpr int RX = TX + 2 * H * (D == 0), RY = TY + 2 * H * (D == 1), RZ = TZ + 2 * H * (D == 2),
                 RC = RX * RY * RZ;
   constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2), NF = FX * FY * FZ;
@@ -335,7 +398,7 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *__restric
   if (ok) {
     constexpr int rs = D == 0 ? 1 : D == 1 ? RX : RX * RY;
     const int r0 = fx + RX * (fy + RY * fz);  // region coordinate = face coordinate - H + H along D
-    face_flux<D, H, R>(G, S, RC, r0, rs, ci, cj, ck, Fo);
+    face_flux<D, H, R, P>(G, S, RC, r0, rs, ci, cj, ck, Fo, pb);
   } else {
 #pragma unroll
     for (int v = 0; v < NV; v++) Fo[v] = 0.0;
@@ -362,7 +425,7 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *__restric
 // (MODE 0: out = L) on the tile of TX x TY x TZ cells with origin (i0,j0,k0).
 // Every thread of the workgroup (NT threads) must call it (it synchronises);
 // sF is the workgroup's LDS buffer of stage_lds<TX,TY,TZ,ND,H>() doubles.
-template <int TX, int TY, int TZ, int ND, int MODE, int H = 2, int R = 0>
+template <int TX, int TY, int TZ, int ND, int MODE, int H = 2, int R = 0, int P = 0>
 __device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0, const double *__restrict__ prim,
                                            const double *__restrict__ met, const double *qn, const double *qs,
                                            double *out, const double *__restrict__ dtp, double ca, double cb,
@@ -380,9 +443,14 @@ __device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; v++) acc[v] = 0.0;
-  face_pass<TX, TY, TZ, 0, H, R>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
-  if constexpr (ND > 1) face_pass<TX, TY, TZ, 1, H, R>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
-  if constexpr (ND > 2) face_pass<TX, TY, TZ, 2, H, R>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc);
+  static_assert(P == 0 || MODE == 1, "the limiter needs the stage's Euler step");
+  PPBase pp{nullptr, 0.0};
+  if constexpr (P) pp = PPBase{ca == 0.0 ? qn : qs, *dtp};
+  face_pass<TX, TY, TZ, 0, H, R, P>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
+  if constexpr (ND > 1)
+    face_pass<TX, TY, TZ, 1, H, R, P>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
+  if constexpr (ND > 2)
+    face_pass<TX, TY, TZ, 2, H, R, P>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
   if (!valid) return;
   const unsigned rel = (unsigned)((tz + G.g[2]) * G.s[2] + (ty + G.g[1]) * G.s[1] + (tx + G.g[0]));
   cell_sources(G, pb, mb, i, j, k, rel, acc);

@@ -456,6 +456,7 @@ int gmunu_server_submit(gmunu_server *s, const gmunu_request *req, unsigned long
   if (!req->prim || !req->metric) return GMUNU_ENULL;
   const int rc = validate_desc(req->desc);
   if (rc) return rc;
+  if (req->desc.pp_limiter) return GMUNU_EINVAL;  // solves run in a batch
   if (!(req->t_end >= 0.0) && req->max_steps <= 0) return GMUNU_EINVAL;
   Req *r = new (std::nothrow) Req();
   if (!r) return GMUNU_ENOMEM;

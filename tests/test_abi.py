@@ -52,6 +52,7 @@ def test_descriptor_layout_matches_header():
     lambda p: p.update(recon=2),
     lambda p: p.update(riemann=2),
     lambda p: p.update(c2p=2),
+    lambda p: p.update(pp_limiter=2),
 ])
 def test_create_rejects_invalid_descriptors(mutate):
     p, _, _ = W.mhd_shock_tube(400)
