@@ -343,14 +343,36 @@ constexpr int pass_faces() {
   return (TX + (D == 0)) * (TY + (D == 1)) * (TZ + (D == 2));
 }
 
-// LDS doubles per workgroup: the staged region (prim and metric) of the
-// largest pass, reused for the face fluxes.
-template <int TX, int TY, int TZ, int ND, int H = 2>
-constexpr int stage_lds() {
+template <int TX, int TY, int TZ, int ND, int H>
+constexpr int max_region() {
   constexpr int r0 = region_cells<TX, TY, TZ, 0, H>(), r1 = ND > 1 ? region_cells<TX, TY, TZ, 1, H>() : 0,
                 r2 = ND > 2 ? region_cells<TX, TY, TZ, 2, H>() : 0;
-  constexpr int r = r0 > r1 ? (r0 > r2 ? r0 : r2) : (r1 > r2 ? r1 : r2);
-  return (NV + 5) * r;
+  return r0 > r1 ? (r0 > r2 ? r0 : r2) : (r1 > r2 ? r1 : r2);
+}
+
+template <int TX, int TY, int TZ, int ND>
+constexpr int max_faces() {
+  constexpr int f0 = pass_faces<TX, TY, TZ, 0>(), f1 = ND > 1 ? pass_faces<TX, TY, TZ, 1>() : 0,
+                f2 = ND > 2 ? pass_faces<TX, TY, TZ, 2>() : 0;
+  return f0 > f1 ? (f0 > f2 ? f0 : f2) : (f1 > f2 ? f1 : f2);
+}
+
+// Separate flux buffer: when the staged region and the face fluxes both fit
+// in LDS for three workgroups per CU (160 KB), the fluxes get their own
+// buffer, so that one pass's fluxes are summed while the next pass's region
+// is staged (two barriers per pass instead of four).
+template <int TX, int TY, int TZ, int ND, int H>
+constexpr bool split_lds() {
+  return ((NV + 5) * max_region<TX, TY, TZ, ND, H>() + NV * max_faces<TX, TY, TZ, ND>()) * 8 * 3 <= 160 * 1024;
+}
+
+// LDS doubles per workgroup: the staged region (prim and metric) of the
+// largest pass, and the face fluxes (in a buffer of their own, or over the
+// region once it has been used).
+template <int TX, int TY, int TZ, int ND, int H = 2>
+constexpr int stage_lds() {
+  return (NV + 5) * max_region<TX, TY, TZ, ND, H>() +
+         (split_lds<TX, TY, TZ, ND, H>() ? NV * max_faces<TX, TY, TZ, ND>() : 0);
 }
 
 // Tile shapes whose passes have at most one face per thread.
@@ -360,22 +382,16 @@ constexpr bool tile_fits() {
          (ND < 3 || pass_faces<TX, TY, TZ, 2>() <= NT) && TX * TY * TZ <= NT;
 }
 
-// Flux divergence along D, accumulated into acc of the thread's cell:
-// (1) stage prim and metric of the pass's region into LDS (coalesced, each
-// value read once from memory), (2) one face per thread from LDS, (3) the
-// fluxes through LDS to the cells on both sides of each face.
-template <int TX, int TY, int TZ, int D, int H, int R, int P = 0>
-__device__ __forceinline__ void face_pass(const Grid &G, const double *__restrict__ prim,
-                                          const double *__restrict__ met, double *S, int i0, int j0, int k0,
-                                          int tx, int ty, int tz, bool valid, double *acc,
-                                          const PPBase &pb = PPBase{nullptr, 0.0}) {
+// Stage prim and metric of the pass's region (the tile plus H cells each
+// side along D) into S, coalesced, each value read once from memory.
+template <int TX, int TY, int TZ, int D, int H>
+__device__ __forceinline__ void stage_region(const Grid &G, const double *__restrict__ prim,
+                                             const double *__restrict__ met, double *S, int i0, int j0, int k0) {
   constexpr int RX = TX + 2 * H * (D == 0), RY = TY + 2 * H * (D == 1), RZ = TZ + 2 * H * (D == 2),
                 RC = RX * RY * RZ;
-  constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2), NF = FX * FY * FZ;
-  const int tid = threadIdx.x;
-  // (1) region origin: the tile origin moved H cells down along D
+  // region origin: the tile origin moved H cells down along D
   const int ai = i0 - H * (D == 0), aj = j0 - H * (D == 1), ak = k0 - H * (D == 2);
-  for (int c = tid; c < RC; c += NT) {
+  for (int c = threadIdx.x; c < RC; c += NT) {
     const int ri = c % RX, rj = (c / RX) % RY, rk = c / (RX * RY);
     const int gi = ai + ri, gj = aj + rj, gk = ak + rk;
     // cells outside the array (ragged tiles) are not needed by any valid face
@@ -387,8 +403,21 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *__restric
       for (int w = 0; w < 5; w++) S[(NV + w) * RC + c] = met[w * G.nv + o];
     }
   }
-  __syncthreads();
-  // (2) face tid: region index of the cell H below it along D
+}
+
+// Flux divergence along D accumulated into acc of the thread's cell, from
+// the pass's region staged in S: (1) one face per thread, (2) the fluxes
+// through LDS (SF; SF == S reuses the region once every face is done) to the
+// cells on both sides of each face.  Begins after a barrier that follows the
+// staging; on return other threads may still read SF.
+template <int TX, int TY, int TZ, int D, int H, int R, int P>
+__device__ __forceinline__ void face_pass(const Grid &G, const double *S, double *SF, int i0, int j0, int k0,
+                                          int tx, int ty, int tz, bool valid, double *acc, const PPBase &pb) {
+  constexpr int RX = TX + 2 * H * (D == 0), RY = TY + 2 * H * (D == 1), RZ = TZ + 2 * H * (D == 2),
+                RC = RX * RY * RZ;
+  constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2), NF = FX * FY * FZ;
+  const int tid = threadIdx.x;
+  // (1) face tid: region index of the cell H below it along D
   double Fo[NV];
   const int f = tid;
   const int fx = f % FX, fy = (f / FX) % FY, fz = f / (FX * FY);
@@ -403,11 +432,11 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *__restric
 #pragma unroll
     for (int v = 0; v < NV; v++) Fo[v] = 0.0;
   }
-  __syncthreads();
-  // (3) fluxes through LDS (over the staged region, no longer needed)
+  if (SF == S) __syncthreads();  // every face has read the region
+  // (2) fluxes through LDS
   if (f < NF) {
 #pragma unroll
-    for (int v = 0; v < NV; v++) S[v * NF + f] = Fo[v];
+    for (int v = 0; v < NV; v++) SF[v * NF + f] = Fo[v];
   }
   __syncthreads();
   if (valid) {
@@ -416,9 +445,8 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *__restric
     const int cd = (D == 0 ? i0 + tx : D == 1 ? j0 + ty : k0 + tz) + G.g[D];
     const double icv = G.geo.icv[D][cd];
 #pragma unroll
-    for (int v = 0; v < NV; v++) acc[v] -= (S[v * NF + fu] - S[v * NF + fl]) * icv;
+    for (int v = 0; v < NV; v++) acc[v] -= (SF[v * NF + fu] - SF[v * NF + fl]) * icv;
   }
-  __syncthreads();
 }
 
 // One RK stage (MODE 1: q_out = ca q_n + cb (q_s + dt L)) or the RHS alone
@@ -446,11 +474,29 @@ __device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0
   static_assert(P == 0 || MODE == 1, "the limiter needs the stage's Euler step");
   PPBase pp{nullptr, 0.0};
   if constexpr (P) pp = PPBase{ca == 0.0 ? qn : qs, *dtp};
-  face_pass<TX, TY, TZ, 0, H, R, P>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
-  if constexpr (ND > 1)
-    face_pass<TX, TY, TZ, 1, H, R, P>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
-  if constexpr (ND > 2)
-    face_pass<TX, TY, TZ, 2, H, R, P>(G, prim, met, sF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
+  // with a separate flux buffer a pass's fluxes are summed while the next
+  // region is staged; with a shared one the summation must end first
+  constexpr bool split = split_lds<TX, TY, TZ, ND, H>();
+  double *SF = split ? sF + (NV + 5) * max_region<TX, TY, TZ, ND, H>() : sF;
+  stage_region<TX, TY, TZ, 0, H>(G, prim, met, sF, i0, j0, k0);
+  __syncthreads();
+  face_pass<TX, TY, TZ, 0, H, R, P>(G, sF, SF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
+  if constexpr (ND > 1) {
+    if constexpr (!split) __syncthreads();
+    stage_region<TX, TY, TZ, 1, H>(G, prim, met, sF, i0, j0, k0);
+    __syncthreads();
+    face_pass<TX, TY, TZ, 1, H, R, P>(G, sF, SF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
+  }
+  if constexpr (ND > 2) {
+    if constexpr (!split) __syncthreads();
+    stage_region<TX, TY, TZ, 2, H>(G, prim, met, sF, i0, j0, k0);
+    __syncthreads();
+    face_pass<TX, TY, TZ, 2, H, R, P>(G, sF, SF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
+  }
+  // a workgroup that takes another tile next restages sF: with a shared
+  // buffer the summation must end first (with a separate one the next
+  // tile's first barrier orders the flux buffer)
+  if constexpr (!split) __syncthreads();
   if (!valid) return;
   const unsigned rel = (unsigned)((tz + G.g[2]) * G.s[2] + (ty + G.g[1]) * G.s[1] + (tx + G.g[0]));
   cell_sources(G, pb, mb, i, j, k, rel, acc);
