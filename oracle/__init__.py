@@ -87,6 +87,7 @@ def lib():
         L.og_cell_volumes.argtypes = [P, P]
         L.og_mc_faces.argtypes = [ctypes.c_int, P, P, P]
         L.og_mp5_faces.argtypes = [ctypes.c_int, P, P, P]
+        L.og_ppm_faces.argtypes = [ctypes.c_int, P, P, P]
         L.og_point_hlle.argtypes = [ctypes.c_double, P, P, P, P, ctypes.c_int, P]
         L.og_point_tvdlf.argtypes = [ctypes.c_double, P, P, P, P, ctypes.c_int, P]
         if L.og_desc_size() != ctypes.sizeof(_Desc):
@@ -117,8 +118,8 @@ def make_desc(p: dict) -> _Desc:
         setattr(d, k, float(q[k]))
     d.c2p_maxit, d.rk = int(q["c2p_maxit"]), int(q["rk"])
     d.recon, d.riemann, d.pp, d.c2p = int(q["recon"]), int(q["riemann"]), int(q["pp_limiter"]), int(q["c2p"])
-    if d.recon == 1 and d.ng < 3:
-        raise ValueError("MP5 needs three ghost layers (ng = 3)")
+    if d.recon in (1, 2) and d.ng < 3:
+        raise ValueError("MP5 and PPM need three ghost layers (ng = 3)")
     return d
 
 
@@ -288,6 +289,16 @@ def mp5_faces(u):
     n = u.shape[0]
     lo, hi = np.zeros(n - 5), np.zeros(n - 5)
     lib().og_mp5_faces(n, _p(u), _p(lo), _p(hi))
+    return lo, hi
+
+
+def ppm_faces(u):
+    """PPM face values on a line: (left, right) states at the n-5 faces
+    between cells f and f+1, f = 2..n-4."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    n = u.shape[0]
+    lo, hi = np.zeros(n - 5), np.zeros(n - 5)
+    lib().og_ppm_faces(n, _p(u), _p(lo), _p(hi))
     return lo, hi
 
 

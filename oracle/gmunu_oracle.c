@@ -54,7 +54,8 @@ typedef struct {
   int c2p_maxit;
   double c2p_tol;
   int rk;
-  int recon, riemann, pp, c2p;  /* scheme options: 0 = MC, HLLE, off, GRMHD recovery */
+  int recon, riemann, pp, c2p;  /* scheme options: recon 0 MC, 1 MP5, 2 PPM; riemann 0 HLLE, 1 TVDLF;
+                                 pp 0 off, 1 on; c2p 0 GRMHD, 1 GRHD z-scheme */
 } og_desc;
 
 /* ------------------------------------------------------------------ grid */
@@ -619,6 +620,25 @@ static double mp5_face(double a, double b, double c, double d, double e) {
   return uor + minmod2(umin - uor, umax - uor);
 }
 
+/* PPM (Colella & Woodward 1984), the third-order reconstruction named in
+ * section 3, on a uniform grid without steepening or flattening: the value
+ * of cell c (neighbours a, b | d, e) at its face toward d.  The interface
+ * values between b, c and between c, d are the fourth-order interpolants
+ * corrected by the difference of the limited (MC) slopes of the two cells;
+ * the parabola through them is then made monotone: flat at a local extremum,
+ * and the value at the far face (toward b) moved so that the parabola does
+ * not overshoot, which changes the value toward d only when the overshoot is
+ * on that side. */
+static double ppm_face(double a, double b, double c, double d, double e) {
+  double sb = mc_slope(a, b, c), sc = mc_slope(b, c, d), sd = mc_slope(c, d, e);
+  double al = b + 0.5 * (c - b) - (sc - sb) / 6.0;
+  double ar = c + 0.5 * (d - c) - (sd - sc) / 6.0;
+  if ((ar - c) * (c - al) <= 0.0) return c;
+  double dq = ar - al, m = c - 0.5 * (al + ar);
+  if (-dq * dq / 6.0 > dq * m) return 3.0 * c - 2.0 * al;
+  return ar;
+}
+
 /* HLLE flux (Harten, Lax & van Leer 1983; Einfeldt 1988), with the signal
  * speeds bounded by zero.  If both bounds vanish the average is used. */
 static void hlle(const double fl[NV], const double fr[NV], const double ql[NV], const double qr[NV],
@@ -693,7 +713,7 @@ static void face_flux_pp(const og_desc *d, const double *prim, const double *met
   for (int s = 0; s < 6; s++) {
     int c[3] = {cell[0], cell[1], cell[2]};
     c[a] = f - 3 + s;
-    idx[s] = (s == 0 || s == 5) && d->recon != 1 ? -1 : at(d, c[0], c[1], c[2]);
+    idx[s] = (s == 0 || s == 5) && d->recon == 0 ? -1 : at(d, c[0], c[1], c[2]);
   }
   double pl[NV], pr[NV];
   for (int v = 0; v < NV; v++) {
@@ -702,12 +722,15 @@ static void face_flux_pp(const og_desc *d, const double *prim, const double *met
     if (d->recon == 1) {
       pl[v] = mp5_face(u[0], u[1], u[2], u[3], u[4]);
       pr[v] = mp5_face(u[5], u[4], u[3], u[2], u[1]);
+    } else if (d->recon == 2) {
+      pl[v] = ppm_face(u[0], u[1], u[2], u[3], u[4]);
+      pr[v] = ppm_face(u[5], u[4], u[3], u[2], u[1]);
     } else {
       pl[v] = u[2] + 0.5 * mc_slope(u[1], u[2], u[3]);
       pr[v] = u[3] - 0.5 * mc_slope(u[2], u[3], u[4]);
     }
   }
-  if (d->recon == 1 && !(pl[RHO] > 0.0 && pl[PRS] > 0.0 && pr[RHO] > 0.0 && pr[PRS] > 0.0)) {
+  if (d->recon != 0 && !(pl[RHO] > 0.0 && pl[PRS] > 0.0 && pr[RHO] > 0.0 && pr[PRS] > 0.0)) {
     /* a reconstructed state without positive density and pressure: both
      * sides of this face fall back to the adjacent cell values */
     for (int v = 0; v < NV; v++) {
@@ -1310,6 +1333,13 @@ void og_mp5_faces(int n, const double *u, double *out_l, double *out_r) {
   for (int f = 2; f + 3 < n; f++) {
     out_l[f - 2] = mp5_face(u[f - 2], u[f - 1], u[f], u[f + 1], u[f + 2]);
     out_r[f - 2] = mp5_face(u[f + 3], u[f + 2], u[f + 1], u[f], u[f - 1]);
+  }
+}
+
+void og_ppm_faces(int n, const double *u, double *out_l, double *out_r) {
+  for (int f = 2; f + 3 < n; f++) {
+    out_l[f - 2] = ppm_face(u[f - 2], u[f - 1], u[f], u[f + 1], u[f + 2]);
+    out_r[f - 2] = ppm_face(u[f + 3], u[f + 2], u[f + 1], u[f], u[f - 1]);
   }
 }
 

@@ -714,6 +714,103 @@ def test_mp5_shock_tube_converges_to_exact_solution():
     assert err[1, 400] < err[0, 400]
 
 
+# ---------------------------------------------------- PPM reconstruction
+
+def test_ppm_is_exact_for_cubic_cell_averages():
+    """The interface interpolant of PPM is exact for the cell averages of any
+    cubic, and on smooth monotone data neither the slope limiter nor the
+    monotonicity constraints of the parabolae change it."""
+    dx = 0.05
+    x = np.arange(-3, 23) * dx
+    c = [0.3, 1.1, -0.4, 0.2]
+
+    def prim_(t):
+        return sum(ck * t ** (k + 1) / (k + 1) for k, ck in enumerate(c))
+
+    def val(t):
+        return sum(ck * t ** k for k, ck in enumerate(c))
+
+    avg = (prim_(x + dx) - prim_(x)) / dx
+    assert np.all(np.diff(avg) > 0)
+    lo, hi = oracle.ppm_faces(avg)
+    faces = x[2:len(x) - 3] + dx
+    np.testing.assert_allclose(lo, val(faces), rtol=0, atol=2e-14)
+    np.testing.assert_allclose(hi, val(faces), rtol=0, atol=2e-14)
+
+
+def test_ppm_adds_no_new_extrema_and_flattens_extrema():
+    """At a step the face values stay within the two states; at a local
+    maximum the cell is flat (both its face values equal its average); a
+    parabola that would overshoot has its far face value moved so that it
+    does not (the face value toward the steep side stays within the cell's
+    neighbours)."""
+    for lo_v, hi_v in ((0.0, 1.0), (2.0, -1.0)):
+        u = np.array([lo_v] * 8 + [hi_v] * 8)
+        lo, hi = oracle.ppm_faces(u)
+        a, b = min(lo_v, hi_v), max(lo_v, hi_v)
+        assert np.all((lo >= a - 1e-15) & (lo <= b + 1e-15))
+        assert np.all((hi >= a - 1e-15) & (hi <= b + 1e-15))
+    u = np.array([0.0, 0.2, 0.5, 1.0, 0.6, 0.3, 0.1, 0.0, 0.0, 0.0])
+    lo, hi = oracle.ppm_faces(u)
+    # faces after cells 2..5: the maximum (cell 3) is flat on both sides
+    assert lo[1] == 1.0 and hi[0] == 1.0
+    # a monotone ramp followed by a plateau: no face value leaves the range
+    # of the two cells it separates
+    u = np.array([0.0, 0.0, 0.0, 0.05, 0.9, 1.0, 1.0, 1.0, 1.0, 1.0])
+    lo, hi = oracle.ppm_faces(u)
+    for f in range(len(lo)):
+        a, b = sorted((u[f + 2], u[f + 3]))
+        assert a - 1e-15 <= lo[f] <= b + 1e-15 and a - 1e-15 <= hi[f] <= b + 1e-15
+
+
+def test_ppm_converges_on_a_smooth_wave():
+    """Smooth data: the face values of a sine's cell averages converge at
+    third order in L1 (second in the maximum, at the flattened extrema) and
+    are several times closer than MC's; the advected density wave converges
+    faster than with MC (the flattened extrema cost PPM its third order
+    there, as they cost MC its second)."""
+    fl = []
+    for n in (64, 128):
+        dx = 1.0 / n
+        x = np.arange(-3, n + 3) * dx
+        avg = 1 + 0.2 * (np.cos(2 * math.pi * x) - np.cos(2 * math.pi * (x + dx))) / (2 * math.pi * dx)
+        lo, hi = oracle.ppm_faces(avg)
+        f = x[2:len(x) - 3] + dx
+        fl.append(np.abs(lo - (1 + 0.2 * np.sin(2 * math.pi * f))).mean())
+        mlo, _ = oracle.mc_faces(avg)
+        fm = x[1:len(x) - 2] + dx
+        assert fl[-1] < np.abs(mlo - (1 + 0.2 * np.sin(2 * math.pi * fm))).mean() / 3
+    assert fl[0] / fl[1] > 2 ** 2.8
+    p64, p128 = _advected_density_error(64, 2), _advected_density_error(128, 2)
+    m64, m128 = _advected_density_error(64, 0), _advected_density_error(128, 0)
+    assert p64 / p128 > 2 ** 2.2 and p64 / p128 > m64 / m128
+
+
+def test_ppm_shock_tube_converges_to_exact_solution():
+    """The relativistic shock tube with PPM converges to the exact solution
+    at first order (as at any discontinuity), with a smaller error than MC."""
+    rs = RiemannSRHD((10, 40 / 3, 0), (1, 0, 0), 5 / 3)
+    err = {}
+    for recon in (0, 2):
+        for n in (100, 400):
+            p, pr, met = W.srhd_shock_tube(n)
+            p.update(ng=3, recon=recon)
+            pr = np.zeros((8,) + W.shape(p))
+            x1, _, _ = W.centres(p)
+            pr[0] = np.where(x1 < 0.5, 10.0, 1.0)
+            pr[4] = np.where(x1 < 0.5, 40.0 / 3.0, 0.0)
+            met = W.flat_metric(p)
+            oracle.fill_ghosts(p, pr)
+            q = oracle.prim2con(p, pr, met)
+            s, t, nf = oracle.evolve(p, q, pr, met, 0.4, 0.0, 0.4)
+            assert nf == 0 and np.all(np.isfinite(pr))
+            dx = p["dx"][0]
+            ex = np.array([rs.cell_average(i * dx, (i + 1) * dx, 0.4, 0.5)[0] for i in range(n)])
+            err[recon, n] = np.sum(np.abs(oracle.interior(p, pr)[0, 0, 0] - ex)) * dx
+    assert err[2, 100] / err[2, 400] > 2.5
+    assert err[2, 400] < err[0, 400]
+
+
 # ------------------------------------- positivity-preserving limiter (2.4)
 
 def _evacuating_cell(pp, rho_low=1e-8, v=0.9, n=16, riemann=0, at=None):
