@@ -109,6 +109,7 @@ typedef struct gmunu_grid_desc {
 enum {
   GMUNU_RECON_MC = 0,        /* monotonised-central slopes (2 ghost layers) */
   GMUNU_RECON_MP5 = 1,       /* MP5, fifth order (3 ghost layers) */
+  GMUNU_RECON_PPM = 2,       /* PPM, third order (3 ghost layers) */
   GMUNU_RIEMANN_HLLE = 0,    /* HLL with the two-speed bounds of section 2.3 */
   GMUNU_RIEMANN_TVDLF = 1,   /* local Lax-Friedrichs (Rusanov) */
   GMUNU_C2P_GRMHD = 0,       /* master-function recovery of section 2.5.2 (any B) */

@@ -42,14 +42,15 @@ struct BlockRec {
 };
 
 // Compiled tile shapes (256 threads; each pass has at most 256 faces) and
-// reconstruction halo (2: MC, 3: MP5).
+// reconstruction (GMUNU_RECON_*).
 struct Variant {
-  int tx, ty, tz, nd, h;
+  int tx, ty, tz, nd, rec;
 };
-constexpr int NVAR = 11;
-constexpr Variant kVar[NVAR] = {{8, 8, 3, 3, 2},   {8, 5, 5, 3, 2},  {16, 4, 3, 3, 2}, {8, 6, 4, 3, 2},
-                                {16, 15, 1, 2, 2}, {32, 7, 1, 2, 2}, {8, 28, 1, 2, 2}, {255, 1, 1, 1, 2},
-                                {8, 5, 5, 3, 3},   {16, 15, 1, 2, 3}, {255, 1, 1, 1, 3}};
+constexpr int NVAR = 14;
+constexpr Variant kVar[NVAR] = {{8, 8, 3, 3, 0},   {8, 5, 5, 3, 0},   {16, 4, 3, 3, 0}, {8, 6, 4, 3, 0},
+                                {16, 15, 1, 2, 0}, {32, 7, 1, 2, 0},  {8, 28, 1, 2, 0}, {255, 1, 1, 1, 0},
+                                {8, 5, 5, 3, 1},   {16, 15, 1, 2, 1}, {255, 1, 1, 1, 1}, {8, 5, 5, 3, 2},
+                                {16, 15, 1, 2, 2}, {255, 1, 1, 1, 2}};
 // Work lists: one per tile variant, then recovery, ghosts, CFL (entries
 // ordered by group), and the recovery / ghost lists of an init.
 // Stage lists: one per (tile variant, Riemann solver), list = variant +
@@ -99,10 +100,10 @@ __device__ __forceinline__ int find_entry(const int *start, int nent, int it, in
   return lo;
 }
 
-template <int TX, int TY, int TZ, int ND, int MODE, int H, int R>
+template <int TX, int TY, int TZ, int ND, int MODE, int REC, int R>
 __global__ __launch_bounds__(NT, 3) void k_bstage(const BlockRec *__restrict__ B, DList L,
                                                           const double *dts, double ca, double cb, int out_qn) {
-  __shared__ double sF[stage_lds<TX, TY, TZ, ND, H>()];
+  __shared__ double sF[stage_lds<TX, TY, TZ, ND, recon_halo(REC)>()];
   const int nent = L.meta[0];
   int it, end, stride;
   xcd_range(L.meta[1], it, end, stride);
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(NT, 3) void k_bstage(const BlockRec *__restrict__ B
     const int gx = (b.G.n[0] + TX - 1) / TX, gy = (b.G.n[1] + TY - 1) / TY;
     const int i0 = (l % gx) * TX, j0 = ((l / gx) % gy) * TY, k0 = (l / (gx * gy)) * TZ;
     double *out = (MODE == 0 || !out_qn) ? b.qs : b.qn;
-    stage_tile<TX, TY, TZ, ND, MODE, H, R>(b.G, i0, j0, k0, b.prim, b.met, b.qn, b.qs, out, dtp, ca, cb, sF);
+    stage_tile<TX, TY, TZ, ND, MODE, REC, R>(b.G, i0, j0, k0, b.prim, b.met, b.qn, b.qs, out, dtp, ca, cb, sF);
   }
 }
 
@@ -209,7 +210,7 @@ template <int LI, int MODE>
 void launch_list(const BlockRec *B, DList L, const double *dts, double ca, double cb, int out_qn, int grid,
                  hipStream_t st) {
   constexpr Variant v = kVar[LI % NVAR];
-  hipLaunchKernelGGL((k_bstage<v.tx, v.ty, v.tz, v.nd, MODE, v.h, LI / NVAR>), dim3(grid), dim3(NT), 0, st, B, L,
+  hipLaunchKernelGGL((k_bstage<v.tx, v.ty, v.tz, v.nd, MODE, v.rec, LI / NVAR>), dim3(grid), dim3(NT), 0, st, B, L,
                      dts, ca, cb, out_qn);
 }
 
@@ -227,12 +228,12 @@ void launch_list_any(int li, const BlockRec *B, DList L, const double *dts, doub
 // Default tile for a block before (or without) tuning.
 int default_variant(const gmunu_grid_desc &d) {
   if (d.recon == GMUNU_RECON_MP5) return d.ndim == 1 ? 10 : d.ndim == 2 ? 9 : 8;
+  if (d.recon == GMUNU_RECON_PPM) return d.ndim == 1 ? 13 : d.ndim == 2 ? 12 : 11;
   if (d.ndim == 1) return 7;
   if (d.ndim == 2) return 4;
   return d.n[0] <= 8 ? 0 : 1;
 }
 
-int halo_of(const gmunu_grid_desc &d) { return d.recon == GMUNU_RECON_MP5 ? 3 : 2; }
 
 std::tuple<int, int, int, int, int, int> bucket_of(const gmunu_grid_desc &d) {
   return {d.ndim, d.n[0], d.n[1], d.n[2], d.recon, d.riemann};
@@ -683,11 +684,11 @@ int gmunu_batch_autotune(gmunu_batch *b, void *stream) {
   for (auto &bk : buckets) {
     if (rc) break;
     const int nd = std::get<0>(bk.first);
-    const int h = halo_of(b->blk[bk.second[0]].desc);
+    const int rec = b->blk[bk.second[0]].desc.recon;
     int best = -1;
     float best_ms = 0.f;
     for (int v = 0; v < NVAR; v++) {
-      if (kVar[v].nd != nd || kVar[v].h != h) continue;
+      if (kVar[v].nd != nd || kVar[v].rec != rec) continue;
       // only this bucket's blocks, all on variant v, in their stage list
       // (MODE 0 writes the right-hand side into q_s, which is scratch)
       const int li = list_of(v, b->blk[bk.second[0]].desc);

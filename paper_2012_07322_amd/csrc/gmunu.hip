@@ -78,17 +78,17 @@ __device__ __forceinline__ void xcd_tile(const Grid &G, int TX, int TY, int TZ, 
 // MODE 0: dqdt = L(prim).  MODE 1: q_out = ca q_n + cb (q_s + dt L(prim)),
 // with the positivity-preserving flux limiter when P = 1.
 // skipp (nullable): nothing is done when *skipp == 0 (a step past t_end).
-template <int TX, int TY, int TZ, int ND, int MODE, int H, int R, int P>
+template <int TX, int TY, int TZ, int ND, int MODE, int REC, int R, int P>
 __global__ __launch_bounds__(NT, 3) void k_stage(const Grid G, const double *__restrict__ prim,
                                                          const double *__restrict__ met, const double *qn,
                                                          const double *qs, double *out,
                                                          const double *__restrict__ dtp, double ca, double cb,
                                                          const double *__restrict__ skipp) {
-  __shared__ double sF[stage_lds<TX, TY, TZ, ND, H>()];
+  __shared__ double sF[stage_lds<TX, TY, TZ, ND, recon_halo(REC)>()];
   if (skipp && *skipp == 0.0) return;
   int bx, by, bz;
   xcd_tile(G, TX, TY, TZ, bx, by, bz);
-  stage_tile<TX, TY, TZ, ND, MODE, H, R, P>(G, bx * TX, by * TY, bz * TZ, prim, met, qn, qs, out, dtp, ca, cb,
+  stage_tile<TX, TY, TZ, ND, MODE, REC, R, P>(G, bx * TX, by * TY, bz * TZ, prim, met, qn, qs, out, dtp, ca, cb,
                                             sF);
 }
 
@@ -135,13 +135,13 @@ __global__ __launch_bounds__(NT) void k_cfl_finish(const double *part, int npart
 
 __global__ void k_advance(double *tp, const double *dtp) { *tp += *dtp; }
 
-template <int TX, int TY, int TZ, int ND, int MODE, int H, int R, int P>
+template <int TX, int TY, int TZ, int ND, int MODE, int REC, int R, int P>
 void launch_stage_t(const gmunu_ctx *ctx, const double *prim, const double *met, const double *qn,
                     const double *qs, double *out, const double *dtp, double ca, double cb, const double *skipp,
                     hipStream_t st) {
   const Grid &G = ctx->G;
   dim3 grid(((G.n[0] + TX - 1) / TX) * ((G.n[1] + TY - 1) / TY) * ((G.n[2] + TZ - 1) / TZ));
-  hipLaunchKernelGGL((k_stage<TX, TY, TZ, ND, MODE, H, R, P>), grid, dim3(NT), 0, st, G, prim, met, qn, qs, out,
+  hipLaunchKernelGGL((k_stage<TX, TY, TZ, ND, MODE, REC, R, P>), grid, dim3(NT), 0, st, G, prim, met, qn, qs, out,
                      dtp, ca, cb, skipp);
 }
 
@@ -149,28 +149,29 @@ template <int MODE>
 void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, const double *qn,
                   const double *qs, double *out, const double *dtp, double ca, double cb, const double *skipp,
                   hipStream_t st) {
-  const int mp5 = ctx->G.recon == GMUNU_RECON_MP5, lf = ctx->G.riemann == GMUNU_RIEMANN_TVDLF;
+  const int rec = ctx->G.recon, lf = ctx->G.riemann == GMUNU_RIEMANN_TVDLF;
   // the limiter acts on the stage's Euler step, so the RHS alone (MODE 0) is unlimited
   const int pp = MODE == 1 && ctx->G.pp;
-  switch (ctx->G.ndim * 8 + mp5 * 4 + lf * 2 + pp) {
+  switch (ctx->G.ndim * 16 + rec * 4 + lf * 2 + pp) {
 #define GM_CASE(NDIM, TX, TY, TZ, M, L, P)                                                                      \
-  case NDIM * 8 + M * 4 + L * 2 + P:                                                                             \
-    launch_stage_t<TX, TY, TZ, NDIM, MODE, 2 + M, L, MODE == 1 && P>(ctx, prim, met, qn, qs, out, dtp, ca, cb,   \
-                                                                     skipp, st);                                  \
+  case NDIM * 16 + M * 4 + L * 2 + P:                                                                            \
+    launch_stage_t<TX, TY, TZ, NDIM, MODE, M, L, MODE == 1 && P>(ctx, prim, met, qn, qs, out, dtp, ca, cb,       \
+                                                                 skipp, st);                                      \
     break;
-#define GM_CASES(NDIM, TX, TY, TZ) \
-  GM_CASE(NDIM, TX, TY, TZ, 0, 0, 0) \
-  GM_CASE(NDIM, TX, TY, TZ, 0, 0, 1) \
-  GM_CASE(NDIM, TX, TY, TZ, 0, 1, 0) \
-  GM_CASE(NDIM, TX, TY, TZ, 0, 1, 1) \
-  GM_CASE(NDIM, TX, TY, TZ, 1, 0, 0) \
-  GM_CASE(NDIM, TX, TY, TZ, 1, 0, 1) \
-  GM_CASE(NDIM, TX, TY, TZ, 1, 1, 0) \
-  GM_CASE(NDIM, TX, TY, TZ, 1, 1, 1)
+#define GM_CASES_R(NDIM, TX, TY, TZ, M) \
+  GM_CASE(NDIM, TX, TY, TZ, M, 0, 0)    \
+  GM_CASE(NDIM, TX, TY, TZ, M, 0, 1)    \
+  GM_CASE(NDIM, TX, TY, TZ, M, 1, 0)    \
+  GM_CASE(NDIM, TX, TY, TZ, M, 1, 1)
+#define GM_CASES(NDIM, TX, TY, TZ)  \
+  GM_CASES_R(NDIM, TX, TY, TZ, 0) \
+  GM_CASES_R(NDIM, TX, TY, TZ, 1) \
+  GM_CASES_R(NDIM, TX, TY, TZ, 2)
     GM_CASES(1, 255, 1, 1)
     GM_CASES(2, 16, 15, 1)
     GM_CASES(3, 8, 5, 5)
 #undef GM_CASES
+#undef GM_CASES_R
 #undef GM_CASE
     default:
       break;

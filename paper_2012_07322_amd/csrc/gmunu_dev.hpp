@@ -143,6 +143,21 @@ __device__ __forceinline__ double mp5_face(double a, double b, double c, double 
   return uor + minmod2(umin - uor, umax - uor);
 }
 
+// PPM (Colella & Woodward 1984; named in section 3), uniform grid, no
+// steepening or flattening: the value of cell c (neighbours a, b and d, e)
+// at its face toward d.  Interfaces b|c and c|d from the fourth-order
+// interpolant with MC slopes; the parabola is flat at a local extremum, and
+// where it would overshoot on the d side its b-side value is what moves the
+// d-side value (to 3c - 2 a_L).
+__device__ __forceinline__ double ppm_face(double a, double b, double c, double d, double e) {
+  const double sb = mc_slope(a, b, c), sc = mc_slope(b, c, d), sd = mc_slope(c, d, e);
+  const double aL = 0.5 * (b + c) - (sc - sb) * (1.0 / 6.0);
+  const double aR = 0.5 * (c + d) - (sd - sc) * (1.0 / 6.0);
+  const double dq = aR - aL, m = c - 0.5 * (aL + aR);
+  const double r = (dq * dq * (-1.0 / 6.0) > dq * m) ? 3.0 * c - 2.0 * aL : aR;
+  return ((aR - c) * (c - aL) <= 0.0) ? c : r;
+}
+
 // Conserved vector U, flux F along direction D and the two wave-speed bounds
 // of one primitive state at one point (section 2.1 and 2.3).  g1, g2: the
 // reference metric diagonal (the first entry is 1 in every coordinate

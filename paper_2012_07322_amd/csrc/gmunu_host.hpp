@@ -45,8 +45,8 @@ inline int validate_desc(const gmunu_grid_desc &d) {
   if (!(d.gamma > 1.0) || !(d.rho_atmo > 0.0) || !(d.w_max > 1.0) || d.c2p_maxit < 1 || !(d.c2p_tol > 0.0))
     return GMUNU_EINVAL;
   if (d.rk != 2 && d.rk != 3) return GMUNU_EINVAL;
-  if (d.recon != GMUNU_RECON_MC && d.recon != GMUNU_RECON_MP5) return GMUNU_EINVAL;
-  if (d.recon == GMUNU_RECON_MP5 && d.ng < 3) return GMUNU_EINVAL;
+  if (d.recon != GMUNU_RECON_MC && d.recon != GMUNU_RECON_MP5 && d.recon != GMUNU_RECON_PPM) return GMUNU_EINVAL;
+  if (d.recon != GMUNU_RECON_MC && d.ng < 3) return GMUNU_EINVAL;
   if (d.riemann != GMUNU_RIEMANN_HLLE && d.riemann != GMUNU_RIEMANN_TVDLF) return GMUNU_EINVAL;
   if (d.pp_limiter != 0 && d.pp_limiter != 1) return GMUNU_EINVAL;
   if (d.c2p != GMUNU_C2P_GRMHD && d.c2p != GMUNU_C2P_GRHD_Z) return GMUNU_EINVAL;

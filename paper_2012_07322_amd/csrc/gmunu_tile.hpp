@@ -14,6 +14,10 @@ namespace gm {
 constexpr double kTiny = 1e-300;
 constexpr int kCflParts = 2048;  // workgroups of the CFL reduction
 
+// Stencil halo of a reconstruction: cells on each side of a face that its
+// states depend on (MC 2; MP5 and PPM 3).
+constexpr int recon_halo(int rec) { return rec == GMUNU_RECON_MC ? 2 : 3; }
+
 // Load variable v at byte offset ob from a tile base (scalar base, 32-bit
 // per-lane offset).
 __device__ __forceinline__ double ld(const double *__restrict__ base, long nv, int v, unsigned ob) {
@@ -41,8 +45,8 @@ __device__ __forceinline__ double pp_side(double u, double w, double fho, double
 }
 
 // Face flux times face factor through the lower face (along D) of cell
-// (i,j,k): reconstruction from the cells across the face (H = 2: MC from
-// four cells; H = 3: MP5 from six), metric as the mean of the two adjacent
+// (i,j,k): reconstruction REC from the cells across the face (MC from four
+// cells, halo H = 2; MP5 or PPM from six, H = 3), metric as the mean of the two adjacent
 // centres, HLLE (R = 0) or TVDLF (R = 1).  The stencil comes from the
 // workgroup's staged region S (RC cells per variable, prim variables 0-7,
 // metric 8-12): r0 is the region index of the cell H below the face, rs the
@@ -53,9 +57,10 @@ __device__ __forceinline__ double pp_side(double u, double w, double fho, double
 // states, with the largest theta that keeps D and tau of the Euler update of
 // both adjacent interior cells above eps (ghost cells are not advanced and do
 // not take part).
-template <int D, int H, int R, int P = 0>
+template <int D, int REC, int R, int P = 0>
 __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC, int r0, int rs, int i, int j,
                                           int k, double *Fo, const PPBase &pb = PPBase{nullptr, 0.0}) {
+  constexpr int H = recon_halo(REC);
   const int cd = (D == 0 ? i : D == 1 ? j : k) + G.g[D];
   // zero-area faces (r = 0, theta = 0 or pi) are evaluated like any other
   // and their flux replaced by 0 at the end; no load-dependent branch here
@@ -63,7 +68,7 @@ __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC
   // the two cells adjacent to the face
   const int r1 = r0 + (H - 1) * rs, r2 = r1 + rs;
   double pl[NV], pr[NV];
-  if constexpr (H == 2) {
+  if constexpr (REC == GMUNU_RECON_MC) {
     const int r3 = r2 + rs;
 #pragma unroll
     for (int v = 0; v < NV; v++) {
@@ -78,8 +83,13 @@ __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC
       const double *Sv = S + v * RC;
       const double u0 = Sv[r0], u1 = Sv[r0 + rs], u2 = Sv[r1], u3 = Sv[r2], u4 = Sv[r2 + rs],
                    u5 = Sv[r2 + 2 * rs];
-      pl[v] = mp5_face(u0, u1, u2, u3, u4);
-      pr[v] = mp5_face(u5, u4, u3, u2, u1);
+      if constexpr (REC == GMUNU_RECON_MP5) {
+        pl[v] = mp5_face(u0, u1, u2, u3, u4);
+        pr[v] = mp5_face(u5, u4, u3, u2, u1);
+      } else {
+        pl[v] = ppm_face(u0, u1, u2, u3, u4);
+        pr[v] = ppm_face(u5, u4, u3, u2, u1);
+      }
     }
     // a reconstructed state without positive density and pressure: both
     // sides fall back to the adjacent cell values
@@ -410,9 +420,10 @@ __device__ __forceinline__ void stage_region(const Grid &G, const double *__rest
 // through LDS (SF; SF == S reuses the region once every face is done) to the
 // cells on both sides of each face.  Begins after a barrier that follows the
 // staging; on return other threads may still read SF.
-template <int TX, int TY, int TZ, int D, int H, int R, int P>
+template <int TX, int TY, int TZ, int D, int REC, int R, int P>
 __device__ __forceinline__ void face_pass(const Grid &G, const double *S, double *SF, int i0, int j0, int k0,
                                           int tx, int ty, int tz, bool valid, double *acc, const PPBase &pb) {
+  constexpr int H = recon_halo(REC);
   constexpr int RX = TX + 2 * H * (D == 0), RY = TY + 2 * H * (D == 1), RZ = TZ + 2 * H * (D == 2),
                 RC = RX * RY * RZ;
   constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2), NF = FX * FY * FZ;
@@ -427,7 +438,7 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *S, double
   if (ok) {
     constexpr int rs = D == 0 ? 1 : D == 1 ? RX : RX * RY;
     const int r0 = fx + RX * (fy + RY * fz);  // region coordinate = face coordinate - H + H along D
-    face_flux<D, H, R, P>(G, S, RC, r0, rs, ci, cj, ck, Fo, pb);
+    face_flux<D, REC, R, P>(G, S, RC, r0, rs, ci, cj, ck, Fo, pb);
   } else {
 #pragma unroll
     for (int v = 0; v < NV; v++) Fo[v] = 0.0;
@@ -452,8 +463,9 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *S, double
 // One RK stage (MODE 1: q_out = ca q_n + cb (q_s + dt L)) or the RHS alone
 // (MODE 0: out = L) on the tile of TX x TY x TZ cells with origin (i0,j0,k0).
 // Every thread of the workgroup (NT threads) must call it (it synchronises);
-// sF is the workgroup's LDS buffer of stage_lds<TX,TY,TZ,ND,H>() doubles.
-template <int TX, int TY, int TZ, int ND, int MODE, int H = 2, int R = 0, int P = 0>
+// sF is the workgroup's LDS buffer of stage_lds<TX,TY,TZ,ND,recon_halo(REC)>()
+// doubles.
+template <int TX, int TY, int TZ, int ND, int MODE, int REC = 0, int R = 0, int P = 0>
 __device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0, const double *__restrict__ prim,
                                            const double *__restrict__ met, const double *qn, const double *qs,
                                            double *out, const double *__restrict__ dtp, double ca, double cb,
@@ -476,22 +488,23 @@ __device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0
   if constexpr (P) pp = PPBase{ca == 0.0 ? qn : qs, *dtp};
   // with a separate flux buffer a pass's fluxes are summed while the next
   // region is staged; with a shared one the summation must end first
+  constexpr int H = recon_halo(REC);
   constexpr bool split = split_lds<TX, TY, TZ, ND, H>();
   double *SF = split ? sF + (NV + 5) * max_region<TX, TY, TZ, ND, H>() : sF;
   stage_region<TX, TY, TZ, 0, H>(G, prim, met, sF, i0, j0, k0);
   __syncthreads();
-  face_pass<TX, TY, TZ, 0, H, R, P>(G, sF, SF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
+  face_pass<TX, TY, TZ, 0, REC, R, P>(G, sF, SF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
   if constexpr (ND > 1) {
     if constexpr (!split) __syncthreads();
     stage_region<TX, TY, TZ, 1, H>(G, prim, met, sF, i0, j0, k0);
     __syncthreads();
-    face_pass<TX, TY, TZ, 1, H, R, P>(G, sF, SF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
+    face_pass<TX, TY, TZ, 1, REC, R, P>(G, sF, SF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
   }
   if constexpr (ND > 2) {
     if constexpr (!split) __syncthreads();
     stage_region<TX, TY, TZ, 2, H>(G, prim, met, sF, i0, j0, k0);
     __syncthreads();
-    face_pass<TX, TY, TZ, 2, H, R, P>(G, sF, SF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
+    face_pass<TX, TY, TZ, 2, REC, R, P>(G, sF, SF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
   }
   // a workgroup that takes another tile next restages sF: with a shared
   // buffer the summation must end first (with a separate one the next

@@ -49,7 +49,8 @@ def test_descriptor_layout_matches_header():
     lambda p: p.update(bc=[[W.PERIODIC, W.OUTFLOW], [5, 5], [5, 5]]),
     lambda p: p.update(dx=[0.0, 1.0, 1.0]),
     lambda p: p.update(recon=1),  # MP5 needs three ghost layers
-    lambda p: p.update(recon=2),
+    lambda p: p.update(recon=2),  # so does PPM
+    lambda p: p.update(recon=3, ng=3),
     lambda p: p.update(riemann=2),
     lambda p: p.update(c2p=2),
     lambda p: p.update(pp_limiter=2),
