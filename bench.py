@@ -25,20 +25,30 @@ HBM_PEAK_GBS = 8000.0
 STAGE_BYTES = {0: 29 * 8, 1: 37 * 8, 2: 37 * 8}
 
 
+STAGE_SOURCES = ("paper_2012_07322_amd/csrc/gmunu.hip", "paper_2012_07322_amd/csrc/gmunu_tile.hpp",
+                 "paper_2012_07322_amd/csrc/gmunu_dev.hpp", "paper_2012_07322_amd/csrc/gmunu_host.hpp",
+                 "include/gmunu.h")
+
+
+def stage_source_hash():
+    """SHA-256 over the sources the single-grid stage kernel is built from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in STAGE_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
 def kernel_traffic():
     """HBM bytes per stage launch from the committed rocprofv3 counters, if
     the kernel sources are unchanged since they were taken (else None)."""
-    import glob
-    import hashlib
 
     path = os.path.join(ROOT, "profiles", "k_stage_blast3d_256_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2012_07322_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
-    if h.hexdigest() != rec.get("source_sha256"):
+    if stage_source_hash() != rec.get("source_sha256"):
         return None
     return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
