@@ -1,0 +1,197 @@
+"""CPU oracle of the cell-centred multigrid solver (test infrastructure only).
+
+Plain C, FP64 (``mg_oracle.c``), loaded through ctypes; only the tests, the
+smoke check and the benchmark's CPU-baseline leg use it.  A problem is a
+dict: ndim, coord (0 Cartesian, 1 cylindrical, 2 spherical), n, xmin, dx,
+bc (per axis a pair of 0 Dirichlet, 1 Neumann, 2 periodic, 3 Robin
+d(r u)/dr = 0), levels (0: as many as the grid allows down to two cells on
+the shortest axis), pre, post, coarse (sweeps), power p and offset c of
+L(u) = Lap(u) - a (u + c)^p.  Arrays are numpy float64 with one ghost layer
+on each active axis, shape (n2 + 2 g2, n1 + 2 g1, n0 + 2 g0); vector fields
+have a leading axis of 3.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mg_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "libmgoracle.so")
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c99", "-fPIC", "-shared"]
+
+CART, CYL, SPH = 0, 1, 2
+DIRICHLET, NEUMANN, PERIODIC, ROBIN = 0, 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int), ("coord", ctypes.c_int), ("n", ctypes.c_int * 3),
+        ("xmin", ctypes.c_double * 3), ("dx", ctypes.c_double * 3), ("bc", (ctypes.c_int * 2) * 3),
+        ("levels", ctypes.c_int), ("pre", ctypes.c_int), ("post", ctypes.c_int), ("coarse", ctypes.c_int),
+        ("power", ctypes.c_int), ("offset", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.om_desc_size.restype = I
+        L.om_apply.argtypes = [P, P, P, P]
+        L.om_fill_ghosts.argtypes = [P, I, P]
+        L.om_smooth.argtypes = [P, P, P, P, I]
+        L.om_restrict.argtypes = [P, I, P, P]
+        L.om_prolong.argtypes = [P, I, P, P]
+        L.om_solve.argtypes = [P, P, P, P, D, I, I, P]
+        L.om_solve.restype = I
+        L.om_divergence.argtypes = [P, P, P]
+        L.om_subtract_gradient.argtypes = [P, P, P]
+        if L.om_desc_size() != ctypes.sizeof(_Desc):
+            raise RuntimeError("multigrid oracle descriptor layout mismatch")
+        _lib = L
+    return _lib
+
+
+DEFAULTS = dict(levels=0, pre=2, post=2, coarse=50, power=0, offset=0.0)
+
+
+def max_levels(p):
+    """Levels down to at least two cells on every active axis."""
+    L = 1
+    while all(p["n"][a] % (1 << L) == 0 and (p["n"][a] >> L) >= 2 for a in range(p["ndim"])):
+        L += 1
+    return L
+
+
+def make_desc(p):
+    q = dict(DEFAULTS)
+    q.update(p)
+    d = _Desc()
+    d.ndim, d.coord = int(q["ndim"]), int(q["coord"])
+    for a in range(3):
+        d.n[a] = int(q["n"][a])
+        d.xmin[a] = float(q["xmin"][a])
+        d.dx[a] = float(q["dx"][a])
+        d.bc[a][0], d.bc[a][1] = int(q["bc"][a][0]), int(q["bc"][a][1])
+    d.levels = int(q["levels"]) or max_levels(q)
+    d.pre, d.post, d.coarse, d.power = int(q["pre"]), int(q["post"]), int(q["coarse"]), int(q["power"])
+    d.offset = float(q["offset"])
+    for a in range(d.ndim):
+        if d.n[a] % (1 << (d.levels - 1)):
+            raise ValueError("grid not divisible for the requested levels")
+        for s in (0, 1):
+            if d.bc[a][s] == ROBIN and (a != 0 or d.coord == CART):
+                raise ValueError("the Robin condition is for the radial axis")
+    return d
+
+
+def shape(p, level=None):
+    d = make_desc(p)
+    s = d.levels - 1 - (d.levels - 1 if level is None else level)
+    return tuple((d.n[a] >> s) + 2 if a < d.ndim else 1 for a in (2, 1, 0))
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a):
+    assert a.flags.c_contiguous and a.dtype == np.float64
+    return a
+
+
+def apply(p, u, a=None):
+    """L(u) on the interior of the finest level; u's ghosts are used as given
+    (fill_ghosts applies the boundary conditions)."""
+    d = make_desc(p)
+    out = np.zeros_like(u)
+    lib().om_apply(ctypes.byref(d), _p(_c(u)), _p(_c(a)) if a is not None else None, _p(out))
+    return out
+
+
+def fill_ghosts(p, u, level=None):
+    d = make_desc(p)
+    lib().om_fill_ghosts(ctypes.byref(d), d.levels - 1 if level is None else level, _p(_c(u)))
+    return u
+
+
+def smooth(p, u, f, a=None, sweeps=1):
+    d = make_desc(p)
+    lib().om_smooth(ctypes.byref(d), _p(_c(u)), _p(_c(f)), _p(_c(a)) if a is not None else None, sweeps)
+    return u
+
+
+def restrict(p, level, fine):
+    d = make_desc(p)
+    out = np.zeros(shape(p, level - 1))
+    lib().om_restrict(ctypes.byref(d), level, _p(_c(fine)), _p(out))
+    return out
+
+
+def prolong(p, level, coarse):
+    """Kwak prolongation; the coarse ghosts are used as given."""
+    d = make_desc(p)
+    out = np.zeros(shape(p, level))
+    lib().om_prolong(ctypes.byref(d), level, _p(_c(coarse)), _p(out))
+    return out
+
+
+def solve(p, u, f, a=None, tol=1e-12, max_cycles=30, fmg=True):
+    """Solve in place; returns the residual history (max norms)."""
+    d = make_desc(p)
+    res = np.zeros(max_cycles + 1)
+    c = lib().om_solve(ctypes.byref(d), _p(_c(u)), _p(_c(f)), _p(_c(a)) if a is not None else None, tol,
+                       max_cycles, 1 if fmg else 0, _p(res))
+    return res[:c + 1]
+
+
+def divergence(p, q):
+    d = make_desc(p)
+    out = np.zeros(q.shape[1:])
+    lib().om_divergence(ctypes.byref(d), _p(_c(q)), _p(out))
+    return out
+
+
+def subtract_gradient(p, u, q):
+    d = make_desc(p)
+    lib().om_subtract_gradient(ctypes.byref(d), _p(_c(u)), _p(_c(q)))
+    return q
+
+
+def interior(p, a):
+    g = [1 if ax < p["ndim"] else 0 for ax in range(3)]
+    sl = tuple(slice(g[ax], a.shape[-3 + (2 - ax)] - g[ax]) for ax in (2, 1, 0))
+    return a[(Ellipsis,) + sl]
+
+
+def centres(p, level=None):
+    d = make_desc(p)
+    s = d.levels - 1 - (d.levels - 1 if level is None else level)
+    ax = []
+    for a in range(3):
+        g = 1 if a < d.ndim else 0
+        n = (d.n[a] >> s) if a < d.ndim else 1
+        h = d.dx[a] * (1 << s) if a < d.ndim else d.dx[a]
+        ax.append(d.xmin[a] + (np.arange(-g, n + g) + 0.5) * h)
+    x3, x2, x1 = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return x1, x2, x3
