@@ -1,0 +1,106 @@
+/* Cell-centred multigrid solver and elliptic divergence cleaning for
+ * MI355X (gfx950): C ABI.
+ *
+ * Cheong et al., "Gmunu" (arXiv 2012.07322), section 2.7 (non-linear
+ * cell-centred multigrid: 3/5/7-point second-order operators, red-black
+ * Newton-Gauss-Seidel smoothing, the same relaxation as the coarsest-level
+ * solver, piecewise-constant restriction, Kwak prolongation) and section 2.2
+ * (elliptic divergence cleaning).  The equation solved is
+ *     L(u) = Lap(u) - a (u + c)^p = f,   p in {-1, 0, 1},
+ * where Lap is the Laplacian of the flat reference metric in Cartesian,
+ * cylindrical (R, z, phi) or spherical (r, theta, phi) coordinates.  The
+ * scalar metric equations of section 2.6 in deviation form have this form
+ * (conformal factor: p = -1, c = 1, a = -2 pi U, f = 0 without the
+ * extrinsic-curvature term; lapse: p = 1 for u = alpha psi - 1), and so has
+ * the Poisson equation of the cleaning (a = 0).
+ *
+ * Arrays: FP64 device memory, one ghost layer on each active axis, layout
+ * [k][j][i] with i fastest: n[a] + 2 entries along an active axis, 1 along
+ * an inactive one.  Vector fields are three such arrays back to back.  Ghost
+ * entries of inputs are ignored; those of a solution are written from the
+ * boundary conditions.  All calls are asynchronous on `stream` (NULL: the
+ * default stream) unless stated; errors as in gmunu.h (GMUNU_E*).
+ */
+#ifndef GMUNU_MG_H
+#define GMUNU_MG_H
+
+#include "gmunu.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GMUNU_MG_DIRICHLET = 0, /* u = 0 on the face */
+  GMUNU_MG_NEUMANN = 1,   /* zero normal derivative (also: faces of zero area) */
+  GMUNU_MG_PERIODIC = 2,
+  GMUNU_MG_ROBIN = 3      /* d(r u)/dr = 0 on the outer radial face (section 2.6); axis 0, curvilinear */
+};
+
+typedef struct {
+  int ndim;          /* 1..3 */
+  int coord;         /* GMUNU_CART, GMUNU_CYL, GMUNU_SPH */
+  int n[3];          /* interior cells of the finest level; inactive axes 1 */
+  double xmin[3];    /* lower face coordinate per axis */
+  double dx[3];      /* finest spacing per axis */
+  int bc[3][2];      /* GMUNU_MG_* per axis and side */
+  int levels;        /* levels in the hierarchy; 0: down to 2 cells on the shortest active axis */
+  int pre, post;     /* red-black sweeps before and after the coarse correction (>= 0) */
+  int coarse;        /* sweeps on the coarsest level (>= 1) */
+  int power;         /* p: -1, 0 or 1 */
+  double offset;     /* c */
+} gmunu_mg_desc;
+
+typedef struct gmunu_mg gmunu_mg;
+
+/* Validate (each active n divisible by 2^(levels-1), at least 2 cells per
+ * axis on the coarsest level, Robin only on axis 0 of curvilinear grids),
+ * build the level hierarchy on the current device and allocate its arrays
+ * (5 arrays per coarse level, 2 on the finest).  Synchronous. */
+int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out);
+int gmunu_mg_destroy(gmunu_mg *mg);
+/* Levels actually used. */
+int gmunu_mg_levels(const gmunu_mg *mg);
+/* Entries of one array of level l (l = levels - 1 is the finest). */
+long gmunu_mg_size(const gmunu_mg *mg, int level);
+
+/* Solve L(u) = f on the finest level in place: an FAS full-multigrid cycle
+ * from the current u first when fmg != 0, then FAS V-cycles until
+ * max |f - L(u)| <= tol or max_cycles cycles were done (the FMG cycle
+ * counts as one).  a may be NULL (a = 0).  res_host (max_cycles + 1 doubles,
+ * nullable) receives the residual norm before and after each cycle;
+ * *cycles_out the cycles done.  Synchronises `stream` once per cycle to
+ * read the norm. */
+int gmunu_mg_solve(gmunu_mg *mg, double *u, const double *f, const double *a, double tol, int max_cycles, int fmg,
+                   double *res_host, int *cycles_out, void *stream);
+/* max |f - L(u)| on the finest level (u's ghosts filled first).  Synchronous. */
+int gmunu_mg_residual_norm(gmunu_mg *mg, double *u, const double *f, const double *a, double *norm_out,
+                           void *stream);
+
+/* Building blocks (finest level unless a level is given), for checking:
+ * out = L(u) on the interior with u's ghosts as given; ghost fill; `sweeps`
+ * red-black sweeps; restriction of level l into level l - 1 (volume-weighted
+ * mean of children); Kwak prolongation of level l - 1 (ghosts as given)
+ * into level l. */
+int gmunu_mg_apply(gmunu_mg *mg, const double *u, const double *a, double *out, void *stream);
+int gmunu_mg_fill_ghosts(gmunu_mg *mg, int level, double *u, void *stream);
+int gmunu_mg_smooth(gmunu_mg *mg, double *u, const double *f, const double *a, int sweeps, void *stream);
+int gmunu_mg_restrict(gmunu_mg *mg, int level, const double *fine, double *coarse, void *stream);
+int gmunu_mg_prolong(gmunu_mg *mg, int level, const double *coarse, double *fine, void *stream);
+
+/* Divergence cleaning (section 2.2) of a vector field q (three arrays):
+ * div = (1/sqrt g) d_i (sqrt g q^i) by centred differences (q's ghosts must
+ * be set), then Lap(Phi) = div solved like gmunu_mg_solve (phi: initial
+ * guess in, solution out; the descriptor's power must be 0 and a = 0), then
+ * q^i -= g^ii d_i Phi (centred) on the interior.  div (nullable) receives
+ * the divergence before cleaning.  Needs p = 0. */
+int gmunu_mg_divergence(gmunu_mg *mg, const double *q, double *div, void *stream);
+int gmunu_mg_subtract_gradient(gmunu_mg *mg, const double *phi, double *q, void *stream);
+int gmunu_mg_clean(gmunu_mg *mg, double *q, double *phi, double *div, double tol, int max_cycles, double *res_host,
+                   int *cycles_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

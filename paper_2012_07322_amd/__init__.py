@@ -512,3 +512,165 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------- multigrid
+
+MG_DIRICHLET, MG_NEUMANN, MG_PERIODIC, MG_ROBIN = 0, 1, 2, 3
+
+
+class MgDesc(ctypes.Structure):
+    """Mirror of gmunu_mg_desc."""
+    _fields_ = [
+        ("ndim", ctypes.c_int), ("coord", ctypes.c_int), ("n", ctypes.c_int * 3),
+        ("xmin", ctypes.c_double * 3), ("dx", ctypes.c_double * 3), ("bc", (ctypes.c_int * 2) * 3),
+        ("levels", ctypes.c_int), ("pre", ctypes.c_int), ("post", ctypes.c_int), ("coarse", ctypes.c_int),
+        ("power", ctypes.c_int), ("offset", ctypes.c_double),
+    ]
+
+
+MG_DEFAULTS = dict(levels=0, pre=2, post=2, coarse=50, power=0, offset=0.0)
+
+
+def _mg_sigs(L):
+    I, D = ctypes.c_int, ctypes.c_double
+    L.gmunu_mg_create.argtypes = [_P, ctypes.POINTER(_P)]
+    L.gmunu_mg_destroy.argtypes = [_P]
+    L.gmunu_mg_levels.argtypes = [_P]
+    L.gmunu_mg_size.argtypes = [_P, I]
+    L.gmunu_mg_size.restype = ctypes.c_long
+    L.gmunu_mg_solve.argtypes = [_P, _P, _P, _P, D, I, I, _P, _P, _P]
+    L.gmunu_mg_residual_norm.argtypes = [_P, _P, _P, _P, _P, _P]
+    L.gmunu_mg_apply.argtypes = [_P, _P, _P, _P, _P]
+    L.gmunu_mg_fill_ghosts.argtypes = [_P, I, _P, _P]
+    L.gmunu_mg_smooth.argtypes = [_P, _P, _P, _P, I, _P]
+    L.gmunu_mg_restrict.argtypes = [_P, I, _P, _P, _P]
+    L.gmunu_mg_prolong.argtypes = [_P, I, _P, _P, _P]
+    L.gmunu_mg_divergence.argtypes = [_P, _P, _P, _P]
+    L.gmunu_mg_subtract_gradient.argtypes = [_P, _P, _P, _P]
+    L.gmunu_mg_clean.argtypes = [_P, _P, _P, _P, D, I, _P, _P, _P]
+
+
+def make_mg_desc(p: dict) -> MgDesc:
+    q = dict(MG_DEFAULTS)
+    q.update(p)
+    d = MgDesc()
+    d.ndim, d.coord = int(q["ndim"]), int(q["coord"])
+    for a in range(3):
+        d.n[a] = int(q["n"][a])
+        d.xmin[a] = float(q["xmin"][a])
+        d.dx[a] = float(q["dx"][a])
+        d.bc[a][0], d.bc[a][1] = int(q["bc"][a][0]), int(q["bc"][a][1])
+    d.levels, d.pre, d.post, d.coarse = int(q["levels"]), int(q["pre"]), int(q["post"]), int(q["coarse"])
+    d.power, d.offset = int(q["power"]), float(q["offset"])
+    return d
+
+
+class Multigrid:
+    """Cell-centred multigrid hierarchy on the current device (gmunu_mg_*).
+    Arrays are contiguous float64 device tensors of shape(level) (one ghost
+    layer on each active axis); vector fields have a leading axis of 3."""
+
+    def __init__(self, params: dict):
+        L = lib()
+        if not hasattr(L, "_mg_sigs_set"):
+            _mg_sigs(L)
+            L._mg_sigs_set = True
+        self.desc = make_mg_desc(params)
+        h = _P()
+        _check(L.gmunu_mg_create(ctypes.byref(self.desc), ctypes.byref(h)), "gmunu_mg_create")
+        self._h = h
+        self.levels = int(L.gmunu_mg_levels(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gmunu_mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shape(self, level=None):
+        d = self.desc
+        s = 0 if level is None else self.levels - 1 - level
+        return tuple((d.n[a] >> s) + 2 if a < d.ndim else 1 for a in (2, 1, 0))
+
+    def empty(self, level=None, vector=False):
+        shp = ((3,) if vector else ()) + self.shape(level)
+        return torch.zeros(shp, dtype=torch.float64, device="cuda")
+
+    def _chk(self, t, what, level=None, vector=False, none_ok=False):
+        if t is None:
+            if none_ok:
+                return None
+            raise ValueError(f"{what} is required")
+        shp = ((3,) if vector else ()) + self.shape(level)
+        if tuple(t.shape) != shp:
+            raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {shp}")
+        return _ptr(t, what)
+
+    def solve(self, u, f, a=None, tol=1e-12, max_cycles=30, fmg=True):
+        """Solve in place; returns the residual history (list of max norms)."""
+        res = (ctypes.c_double * (max_cycles + 1))()
+        cyc = ctypes.c_int(0)
+        _check(lib().gmunu_mg_solve(self._h, self._chk(u, "u"), self._chk(f, "f"),
+                                    self._chk(a, "a", none_ok=True), float(tol), int(max_cycles), 1 if fmg else 0,
+                                    res, ctypes.byref(cyc), _stream()), "gmunu_mg_solve")
+        return [res[i] for i in range(cyc.value + 1)]
+
+    def residual_norm(self, u, f, a=None):
+        out = ctypes.c_double(0.0)
+        _check(lib().gmunu_mg_residual_norm(self._h, self._chk(u, "u"), self._chk(f, "f"),
+                                            self._chk(a, "a", none_ok=True), ctypes.byref(out), _stream()),
+               "gmunu_mg_residual_norm")
+        return out.value
+
+    def apply(self, u, a=None, out=None):
+        out = self.empty() if out is None else out
+        _check(lib().gmunu_mg_apply(self._h, self._chk(u, "u"), self._chk(a, "a", none_ok=True),
+                                    self._chk(out, "out"), _stream()), "gmunu_mg_apply")
+        return out
+
+    def fill_ghosts(self, u, level=None):
+        lv = self.levels - 1 if level is None else level
+        _check(lib().gmunu_mg_fill_ghosts(self._h, lv, self._chk(u, "u", lv), _stream()), "gmunu_mg_fill_ghosts")
+        return u
+
+    def smooth(self, u, f, a=None, sweeps=1):
+        _check(lib().gmunu_mg_smooth(self._h, self._chk(u, "u"), self._chk(f, "f"), self._chk(a, "a", none_ok=True),
+                                     int(sweeps), _stream()), "gmunu_mg_smooth")
+        return u
+
+    def restrict(self, level, fine, coarse=None):
+        coarse = self.empty(level - 1) if coarse is None else coarse
+        _check(lib().gmunu_mg_restrict(self._h, level, self._chk(fine, "fine", level),
+                                       self._chk(coarse, "coarse", level - 1), _stream()), "gmunu_mg_restrict")
+        return coarse
+
+    def prolong(self, level, coarse, fine=None):
+        fine = self.empty(level) if fine is None else fine
+        _check(lib().gmunu_mg_prolong(self._h, level, self._chk(coarse, "coarse", level - 1),
+                                      self._chk(fine, "fine", level), _stream()), "gmunu_mg_prolong")
+        return fine
+
+    def divergence(self, q, out=None):
+        out = self.empty() if out is None else out
+        _check(lib().gmunu_mg_divergence(self._h, self._chk(q, "q", vector=True), self._chk(out, "div"),
+                                         _stream()), "gmunu_mg_divergence")
+        return out
+
+    def subtract_gradient(self, phi, q):
+        _check(lib().gmunu_mg_subtract_gradient(self._h, self._chk(phi, "phi"), self._chk(q, "q", vector=True),
+                                                _stream()), "gmunu_mg_subtract_gradient")
+        return q
+
+    def clean(self, q, phi, div=None, tol=1e-12, max_cycles=30):
+        res = (ctypes.c_double * (max_cycles + 1))()
+        cyc = ctypes.c_int(0)
+        _check(lib().gmunu_mg_clean(self._h, self._chk(q, "q", vector=True), self._chk(phi, "phi"),
+                                    self._chk(div, "div", none_ok=True), float(tol), int(max_cycles), res,
+                                    ctypes.byref(cyc), _stream()), "gmunu_mg_clean")
+        return [res[i] for i in range(cyc.value + 1)]

@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("gmunu.hip", "batch.hip", "server.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("gmunu.hip", "batch.hip", "server.hip", "mg.hip")]
 OUT = os.path.join(HERE, "_build", "libgmunu.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -1,0 +1,695 @@
+// Cell-centred multigrid solver and elliptic divergence cleaning for MI355X
+// (gfx950): level hierarchy, kernels and the C ABI of include/gmunu_mg.h.
+//
+// Cheong et al., "Gmunu" (arXiv 2012.07322), section 2.7 and section 2.2.
+// Every operation of a cycle is one launch over the cells (or ghosts) of one
+// level, one thread per cell: the smoother updates one colour of the
+// red-black ordering per launch (i + j + k even first), the residual, the
+// restriction (volume-weighted mean of the children), the FAS coarse
+// right-hand side and the Kwak prolongation of the coarse correction.  The
+// geometry of the reference-metric Laplacian factorises into per-axis 1D
+// tables per level (weights toward the lower and upper neighbour, the
+// metric factors of the transverse terms, cell volumes), so a cell's
+// operator is a handful of table reads and FMAs.  The residual norm is a
+// grid-stride maximum with wavefront shuffles, one partial per workgroup and
+// one finishing workgroup: no atomics, no memset.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "../../include/gmunu.h"
+#include "../../include/gmunu_mg.h"
+#include "gmunu_dev.hpp"
+#include "gmunu_host.hpp"
+#include "gmunu_tile.hpp"
+
+using namespace gm;
+
+namespace {
+
+constexpr int kMaxLevels = 16;
+constexpr int kNormParts = 1024;
+
+// One level as the kernels see it.
+struct MgGeo {
+  int ndim, coord;
+  int n[3], g[3];
+  long s1, s2, nt;  // strides of axes 1 and 2, entries
+  double ih2_2;     // 1 / h^2 along axis 2
+  double h[3];
+  // per axis-0 index (ghosts included)
+  const double *a0m, *a0p, *g1, *g2, *vol0, *sg0;
+  // per axis-1 index
+  const double *a1m, *a1p, *s2t, *vol1, *sg1;
+  int bc[3][2];
+  double rob_lo, rob_hi;  // Robin ghost factors on axis 0 (centre inside / centre of the ghost)
+  int power;
+  double offset;
+};
+
+__device__ __forceinline__ long mg_off(const MgGeo &G, int i, int j, int k) {
+  return (long)(k + G.g[2]) * G.s2 + (long)(j + G.g[1]) * G.s1 + (i + G.g[0]);
+}
+
+__device__ __forceinline__ double mg_nl(const MgGeo &G, double a, double u) {
+  return G.power == 0 ? a : G.power == 1 ? a * (u + G.offset) : a / (u + G.offset);
+}
+__device__ __forceinline__ double mg_nl_du(const MgGeo &G, double a, double u) {
+  if (G.power == 0) return 0.0;
+  if (G.power == 1) return a;
+  const double w = u + G.offset;
+  return -a / (w * w);
+}
+
+// L(u) at interior cell (i,j,k) (linear offset o) and dL/du there.
+__device__ __forceinline__ double mg_L(const MgGeo &G, const double *__restrict__ u, const double *__restrict__ a,
+                                       int i, int j, int k, long o, double *dg) {
+  const int I = i + G.g[0], J = j + G.g[1];
+  const double uc = u[o];
+  double wm = G.a0m[I], wp = G.a0p[I];
+  double lap = wp * (u[o + 1] - uc) - wm * (uc - u[o - 1]);
+  double d = -(wm + wp);
+  if (G.ndim > 1) {
+    const double gi = G.g1[I];
+    wm = gi * G.a1m[J];
+    wp = gi * G.a1p[J];
+    lap += wp * (u[o + G.s1] - uc) - wm * (uc - u[o - G.s1]);
+    d -= wm + wp;
+  }
+  if (G.ndim > 2) {
+    const double w = G.g2[I] * G.s2t[J] * G.ih2_2;
+    lap += w * (u[o + G.s2] - uc) - w * (uc - u[o - G.s2]);
+    d -= 2.0 * w;
+  }
+  const double av = a ? a[o] : 0.0;
+  if (dg) *dg = d - mg_nl_du(G, av, uc);
+  return lap - mg_nl(G, av, uc);
+}
+
+__device__ __forceinline__ void mg_cell(const MgGeo &G, long t, int &i, int &j, int &k) {
+  i = (int)(t % G.n[0]);
+  j = (int)((t / G.n[0]) % G.n[1]);
+  k = (int)(t / ((long)G.n[0] * G.n[1]));
+}
+
+__device__ __forceinline__ long mg_cells(const MgGeo &G) { return (long)G.n[0] * G.n[1] * G.n[2]; }
+
+// Face-adjacent ghosts: thread t -> axis, side, transverse cell.
+__global__ __launch_bounds__(NT) void k_mg_ghosts(const MgGeo G, double *u) {
+  long t = (long)blockIdx.x * NT + threadIdx.x;
+  for (int a = 0; a < G.ndim; a++) {
+    const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    const long per = 2L * G.n[b1] * G.n[b2];
+    if (t >= per) {
+      t -= per;
+      continue;
+    }
+    const int side = (int)(t & 1);
+    const long tr = t >> 1;
+    int gc[3], sc[3];
+    gc[b1] = sc[b1] = (int)(tr % G.n[b1]);
+    gc[b2] = sc[b2] = (int)(tr / G.n[b1]);
+    gc[a] = side == 0 ? -1 : G.n[a];
+    const int kind = G.bc[a][side];
+    double v;
+    if (kind == GMUNU_MG_PERIODIC) {
+      sc[a] = side == 0 ? G.n[a] - 1 : 0;
+      v = u[mg_off(G, sc[0], sc[1], sc[2])];
+    } else {
+      sc[a] = side == 0 ? 0 : G.n[a] - 1;
+      const double ui = u[mg_off(G, sc[0], sc[1], sc[2])];
+      v = kind == GMUNU_MG_DIRICHLET ? -ui : kind == GMUNU_MG_NEUMANN ? ui : ui * (side == 0 ? G.rob_lo : G.rob_hi);
+    }
+    u[mg_off(G, gc[0], gc[1], gc[2])] = v;
+    return;
+  }
+}
+
+// One colour of red-black Newton-Gauss-Seidel: thread t -> the t-th cell of
+// that colour (every other cell of a row).
+__global__ __launch_bounds__(NT) void k_mg_smooth(const MgGeo G, double *u, const double *__restrict__ f,
+                                                  const double *__restrict__ a, int colour) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  const int hrow = (G.n[0] + 1) >> 1;
+  const long row = t / hrow;
+  if (row >= (long)G.n[1] * G.n[2]) return;
+  const int j = (int)(row % G.n[1]), k = (int)(row / G.n[1]);
+  const int i = (int)(t % hrow) * 2 + ((j + k + colour) & 1);
+  if (i >= G.n[0]) return;
+  const long o = mg_off(G, i, j, k);
+  double dg;
+  const double Lu = mg_L(G, u, a, i, j, k, o, &dg);
+  u[o] -= (Lu - f[o]) / dg;
+}
+
+// r = f - L(u) on the interior.
+__global__ __launch_bounds__(NT) void k_mg_residual(const MgGeo G, const double *__restrict__ u,
+                                                    const double *__restrict__ f, const double *__restrict__ a,
+                                                    double *__restrict__ r) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(G)) return;
+  int i, j, k;
+  mg_cell(G, t, i, j, k);
+  const long o = mg_off(G, i, j, k);
+  r[o] = f[o] - mg_L(G, u, a, i, j, k, o, nullptr);
+}
+
+// out = L(u) on the interior.
+__global__ __launch_bounds__(NT) void k_mg_apply(const MgGeo G, const double *__restrict__ u,
+                                                 const double *__restrict__ a, double *__restrict__ out) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(G)) return;
+  int i, j, k;
+  mg_cell(G, t, i, j, k);
+  const long o = mg_off(G, i, j, k);
+  out[o] = mg_L(G, u, a, i, j, k, o, nullptr);
+}
+
+// Per-workgroup maxima of |f - L(u)| over a grid-stride range of cells.
+__global__ __launch_bounds__(NT) void k_mg_norm(const MgGeo G, const double *__restrict__ u,
+                                                const double *__restrict__ f, const double *__restrict__ a,
+                                                double *part) {
+  double m = 0.0;
+  for (long t = (long)blockIdx.x * NT + threadIdx.x; t < mg_cells(G); t += (long)gridDim.x * NT) {
+    int i, j, k;
+    mg_cell(G, t, i, j, k);
+    const long o = mg_off(G, i, j, k);
+    m = fmax(m, fabs(f[o] - mg_L(G, u, a, i, j, k, o, nullptr)));
+  }
+  m = block_max(m);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(NT) void k_mg_norm_finish(double *part, int nparts) {
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += NT) m = fmax(m, part[b]);
+  m = block_max(m);
+  if (threadIdx.x == 0) part[kNormParts] = m;
+}
+
+// coarse = volume-weighted mean of the children (F: fine level, C: coarse).
+__global__ __launch_bounds__(NT) void k_mg_restrict(const MgGeo F, const MgGeo C, const double *__restrict__ fine,
+                                                    double *__restrict__ coarse) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(C)) return;
+  int i, j, k;
+  mg_cell(C, t, i, j, k);
+  double s = 0.0, w = 0.0;
+  const int nch = 1 << F.ndim;
+  for (int ch = 0; ch < nch; ch++) {
+    const int fi = 2 * i + (ch & 1);
+    const int fj = F.ndim > 1 ? 2 * j + ((ch >> 1) & 1) : j;
+    const int fk = F.ndim > 2 ? 2 * k + ((ch >> 2) & 1) : k;
+    const double v = F.vol0[fi + F.g[0]] * F.vol1[fj + F.g[1]];
+    s += v * fine[mg_off(F, fi, fj, fk)];
+    w += v;
+  }
+  coarse[mg_off(C, i, j, k)] = s / w;
+}
+
+// FAS coarse problem: f_c = L_c(u_c) + r_c, and uo_c = u_c (u_c's ghosts set).
+__global__ __launch_bounds__(NT) void k_mg_fas_rhs(const MgGeo C, const double *__restrict__ u,
+                                                   const double *__restrict__ a, const double *__restrict__ r,
+                                                   double *__restrict__ f, double *__restrict__ uo) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(C)) return;
+  int i, j, k;
+  mg_cell(C, t, i, j, k);
+  const long o = mg_off(C, i, j, k);
+  f[o] = mg_L(C, u, a, i, j, k, o, nullptr) + r[o];
+  uo[o] = u[o];
+}
+
+// e = u - uo into uo on the interior (the coarse correction).
+__global__ __launch_bounds__(NT) void k_mg_diff(const MgGeo C, const double *__restrict__ u, double *__restrict__ uo) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(C)) return;
+  int i, j, k;
+  mg_cell(C, t, i, j, k);
+  const long o = mg_off(C, i, j, k);
+  uo[o] = u[o] - uo[o];
+}
+
+// Kwak prolongation of v (coarse, ghosts set) into the fine interior:
+// fine = P v (add = 0) or fine += P v (add = 1).
+__global__ __launch_bounds__(NT) void k_mg_prolong(const MgGeo C, const MgGeo F, const double *__restrict__ v,
+                                                   double *__restrict__ fine, int add) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(F)) return;
+  int fc[3];
+  mg_cell(F, t, fc[0], fc[1], fc[2]);
+  int cc[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) cc[a] = a < F.ndim ? fc[a] >> 1 : fc[a];
+  const double w0 = F.ndim == 1 ? 0.75 : F.ndim == 2 ? 0.5 : 0.25;
+  const long oc = mg_off(C, cc[0], cc[1], cc[2]);
+  double s = w0 * v[oc];
+  s += 0.25 * v[oc + ((fc[0] & 1) ? 1 : -1)];
+  if (F.ndim > 1) s += 0.25 * v[oc + ((fc[1] & 1) ? C.s1 : -C.s1)];
+  if (F.ndim > 2) s += 0.25 * v[oc + ((fc[2] & 1) ? C.s2 : -C.s2)];
+  const long of = mg_off(F, fc[0], fc[1], fc[2]);
+  fine[of] = add ? fine[of] + s : s;
+}
+
+// (1/sqrt g) d_i (sqrt g q^i), centred.
+__global__ __launch_bounds__(NT) void k_mg_div(const MgGeo G, const double *__restrict__ q, double *__restrict__ out) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(G)) return;
+  int i, j, k;
+  mg_cell(G, t, i, j, k);
+  const int I = i + G.g[0], J = j + G.g[1];
+  const long o = mg_off(G, i, j, k);
+  const double sgc = G.sg0[I] * G.sg1[J];
+  double s = (G.sg0[I + 1] * q[o + 1] - G.sg0[I - 1] * q[o - 1]) * G.sg1[J] / (2.0 * G.h[0]);
+  if (G.ndim > 1)
+    s += (G.sg1[J + 1] * q[G.nt + o + G.s1] - G.sg1[J - 1] * q[G.nt + o - G.s1]) * G.sg0[I] / (2.0 * G.h[1]);
+  if (G.ndim > 2) s += (q[2 * G.nt + o + G.s2] - q[2 * G.nt + o - G.s2]) * sgc / (2.0 * G.h[2]);
+  out[o] = s / sgc;
+}
+
+// q^i -= g^ii d_i phi, centred, on the interior.
+__global__ __launch_bounds__(NT) void k_mg_subgrad(const MgGeo G, const double *__restrict__ phi,
+                                                   double *__restrict__ q) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(G)) return;
+  int i, j, k;
+  mg_cell(G, t, i, j, k);
+  const int I = i + G.g[0], J = j + G.g[1];
+  const long o = mg_off(G, i, j, k);
+  q[o] -= (phi[o + 1] - phi[o - 1]) / (2.0 * G.h[0]);
+  if (G.ndim > 1) q[G.nt + o] -= G.g1[I] * (phi[o + G.s1] - phi[o - G.s1]) / (2.0 * G.h[1]);
+  if (G.ndim > 2) q[2 * G.nt + o] -= G.g2[I] * G.s2t[J] * (phi[o + G.s2] - phi[o - G.s2]) / (2.0 * G.h[2]);
+}
+
+}  // namespace
+
+struct gmunu_mg {
+  gmunu_mg_desc d;
+  int levels;
+  MgGeo geo[kMaxLevels];
+  double *tab;  // geometry tables of all levels (device)
+  // per level: u, f, a, r, uo (the finest level's u, f, a are the caller's;
+  // a[l] is NULL when the equation has no a)
+  double *u[kMaxLevels], *f[kMaxLevels], *a[kMaxLevels], *r[kMaxLevels], *uo[kMaxLevels];
+  double *aown[kMaxLevels];  // coarse-level storage of a
+  double *part;  // norm partials + result
+  std::vector<double *> owned;
+};
+
+namespace {
+
+int auto_levels(const gmunu_mg_desc &d) {
+  int L = 1;
+  for (;;) {
+    bool ok = L < kMaxLevels;
+    for (int a = 0; a < d.ndim && ok; a++) ok = d.n[a] % (1 << L) == 0 && (d.n[a] >> L) >= 2;
+    if (!ok) return L;
+    L++;
+  }
+}
+
+int validate(const gmunu_mg_desc &d, int levels) {
+  if (d.ndim < 1 || d.ndim > 3 || d.coord < GMUNU_CART || d.coord > GMUNU_SPH) return GMUNU_EINVAL;
+  if (levels < 1 || levels > kMaxLevels) return GMUNU_EINVAL;
+  for (int a = 0; a < 3; a++) {
+    if (a >= d.ndim) {
+      if (d.n[a] != 1) return GMUNU_EINVAL;
+      continue;
+    }
+    if (d.n[a] < 1 || !(d.dx[a] > 0.0) || d.n[a] % (1 << (levels - 1)) != 0 || (d.n[a] >> (levels - 1)) < 2)
+      return GMUNU_EINVAL;
+    for (int s = 0; s < 2; s++) {
+      const int b = d.bc[a][s];
+      if (b < GMUNU_MG_DIRICHLET || b > GMUNU_MG_ROBIN) return GMUNU_EINVAL;
+      if (b == GMUNU_MG_ROBIN && (a != 0 || d.coord == GMUNU_CART)) return GMUNU_EINVAL;
+      if ((b == GMUNU_MG_PERIODIC) != (d.bc[a][1 - s] == GMUNU_MG_PERIODIC)) return GMUNU_EINVAL;
+    }
+  }
+  if (d.coord != GMUNU_CART && d.xmin[0] < 0.0) return GMUNU_EINVAL;
+  if (d.coord == GMUNU_SPH && d.ndim > 1 && (d.xmin[1] < 0.0 || d.xmin[1] + d.n[1] * d.dx[1] > M_PI + 1e-12))
+    return GMUNU_EINVAL;
+  if (d.power < -1 || d.power > 1 || d.pre < 0 || d.post < 0 || d.coarse < 1) return GMUNU_EINVAL;
+  return GMUNU_OK;
+}
+
+// Host tables of one level: 6 per axis-0 index, 5 per axis-1 index.
+void level_tables(const gmunu_mg_desc &d, int s, std::vector<double> &tab, size_t off[11], MgGeo &G) {
+  for (int a = 0; a < 3; a++) {
+    G.g[a] = a < d.ndim ? 1 : 0;
+    G.n[a] = a < d.ndim ? d.n[a] >> s : 1;
+    G.h[a] = a < d.ndim ? d.dx[a] * (double)(1 << s) : d.dx[a];
+  }
+  const int t0 = G.n[0] + 2 * G.g[0], t1 = G.n[1] + 2 * G.g[1], t2 = G.n[2] + 2 * G.g[2];
+  G.s1 = t0;
+  G.s2 = (long)t0 * t1;
+  G.nt = G.s2 * t2;
+  G.ndim = d.ndim;
+  G.coord = d.coord;
+  G.ih2_2 = 1.0 / (G.h[2] * G.h[2]);
+  const bool cyl = d.coord == GMUNU_CYL, sph = d.coord == GMUNU_SPH;
+  std::vector<double> a0m(t0), a0p(t0), g1(t0), g2(t0), vol0(t0), sg0(t0);
+  const double h0 = G.h[0], h02 = h0 * h0;
+  for (int I = 0; I < t0; I++) {
+    const double x = d.xmin[0] + (I - G.g[0] + 0.5) * h0;
+    const double fm = d.xmin[0] + (I - G.g[0]) * h0, fp = fm + h0;
+    a0m[I] = a0p[I] = 1.0 / h02;
+    g1[I] = g2[I] = vol0[I] = sg0[I] = 1.0;
+    if (cyl) {
+      a0m[I] = fm / (x * h02);
+      a0p[I] = fp / (x * h02);
+      g2[I] = 1.0 / (x * x);
+      vol0[I] = sg0[I] = x;
+    } else if (sph) {
+      a0m[I] = fm * fm / (x * x * h02);
+      a0p[I] = fp * fp / (x * x * h02);
+      g1[I] = g2[I] = 1.0 / (x * x);
+      vol0[I] = x * x + h02 / 12.0;
+      sg0[I] = x * x;
+    }
+  }
+  std::vector<double> a1m(t1), a1p(t1), s2t(t1), vol1(t1), sg1(t1);
+  const double h1 = G.h[1], h12 = h1 * h1;
+  for (int J = 0; J < t1; J++) {
+    const double y = d.xmin[1] + (J - G.g[1] + 0.5) * h1;
+    const double fm = d.xmin[1] + (J - G.g[1]) * h1, fp = fm + h1;
+    a1m[J] = a1p[J] = 1.0 / h12;
+    s2t[J] = vol1[J] = sg1[J] = 1.0;
+    if (sph) {
+      const double sy = std::sin(y);
+      a1m[J] = std::sin(fm) / (sy * h12);
+      a1p[J] = std::sin(fp) / (sy * h12);
+      s2t[J] = 1.0 / (sy * sy);
+      vol1[J] = d.ndim > 1 ? sy : 1.0;
+      sg1[J] = sy;
+    }
+  }
+  const std::vector<double> *all[11] = {&a0m, &a0p, &g1, &g2, &vol0, &sg0, &a1m, &a1p, &s2t, &vol1, &sg1};
+  for (int q = 0; q < 11; q++) {
+    while (tab.size() % 32) tab.push_back(0.0);
+    off[q] = tab.size();
+    tab.insert(tab.end(), all[q]->begin(), all[q]->end());
+  }
+  for (int a = 0; a < 3; a++)
+    for (int sd = 0; sd < 2; sd++) G.bc[a][sd] = d.bc[a][sd];
+  // Robin ghost factors: centre of the boundary cell / centre of its ghost
+  const double xin_lo = d.xmin[0] + 0.5 * h0, xg_lo = d.xmin[0] - 0.5 * h0;
+  const double xin_hi = d.xmin[0] + (G.n[0] - 0.5) * h0, xg_hi = d.xmin[0] + (G.n[0] + 0.5) * h0;
+  G.rob_lo = xin_lo / xg_lo;
+  G.rob_hi = xin_hi / xg_hi;
+  G.power = d.power;
+  G.offset = d.offset;
+}
+
+long ghost_count(const MgGeo &G) {
+  long s = 0;
+  for (int a = 0; a < G.ndim; a++) {
+    const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    s += 2L * G.n[b1] * G.n[b2];
+  }
+  return s;
+}
+
+long cells(const MgGeo &G) { return (long)G.n[0] * G.n[1] * G.n[2]; }
+
+void ghosts(const MgGeo &G, double *u, hipStream_t st) {
+  const long gc = ghost_count(G);
+  if (gc) hipLaunchKernelGGL(k_mg_ghosts, dim3(nblocks(gc)), dim3(NT), 0, st, G, u);
+}
+
+void smooth(const MgGeo &G, double *u, const double *f, const double *a, int sweeps, hipStream_t st) {
+  const long threads = (long)((G.n[0] + 1) / 2) * G.n[1] * G.n[2];
+  for (int s = 0; s < sweeps; s++)
+    for (int c = 0; c < 2; c++) {
+      ghosts(G, u, st);
+      hipLaunchKernelGGL(k_mg_smooth, dim3(nblocks(threads)), dim3(NT), 0, st, G, u, f, a, c);
+    }
+  ghosts(G, u, st);
+}
+
+void coarse_problem(gmunu_mg *m, int l, hipStream_t st) {
+  const MgGeo &F = m->geo[l], &C = m->geo[l - 1];
+  ghosts(F, m->u[l], st);
+  hipLaunchKernelGGL(k_mg_residual, dim3(nblocks(cells(F))), dim3(NT), 0, st, F, m->u[l], m->f[l], m->a[l], m->r[l]);
+  hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(cells(C))), dim3(NT), 0, st, F, C, m->u[l], m->u[l - 1]);
+  hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(cells(C))), dim3(NT), 0, st, F, C, m->r[l], m->r[l - 1]);
+  ghosts(C, m->u[l - 1], st);
+  hipLaunchKernelGGL(k_mg_fas_rhs, dim3(nblocks(cells(C))), dim3(NT), 0, st, C, m->u[l - 1], m->a[l - 1],
+                     m->r[l - 1], m->f[l - 1], m->uo[l - 1]);
+}
+
+void correct(gmunu_mg *m, int l, hipStream_t st) {
+  const MgGeo &F = m->geo[l], &C = m->geo[l - 1];
+  hipLaunchKernelGGL(k_mg_diff, dim3(nblocks(cells(C))), dim3(NT), 0, st, C, m->u[l - 1], m->uo[l - 1]);
+  ghosts(C, m->uo[l - 1], st);
+  hipLaunchKernelGGL(k_mg_prolong, dim3(nblocks(cells(F))), dim3(NT), 0, st, C, F, m->uo[l - 1], m->u[l], 1);
+}
+
+void vcycle(gmunu_mg *m, int l, hipStream_t st) {
+  if (l == 0) {
+    smooth(m->geo[0], m->u[0], m->f[0], m->a[0], m->d.coarse, st);
+    return;
+  }
+  smooth(m->geo[l], m->u[l], m->f[l], m->a[l], m->d.pre, st);
+  coarse_problem(m, l, st);
+  vcycle(m, l - 1, st);
+  correct(m, l, st);
+  smooth(m->geo[l], m->u[l], m->f[l], m->a[l], m->d.post, st);
+}
+
+void fmg(gmunu_mg *m, hipStream_t st) {
+  const int top = m->levels - 1;
+  for (int l = top; l > 0; l--) coarse_problem(m, l, st);
+  smooth(m->geo[0], m->u[0], m->f[0], m->a[0], m->d.coarse, st);
+  for (int l = 1; l <= top; l++) {
+    correct(m, l, st);
+    vcycle(m, l, st);
+  }
+}
+
+int norm(gmunu_mg *m, double *out, hipStream_t st) {
+  const int top = m->levels - 1;
+  const MgGeo &G = m->geo[top];
+  ghosts(G, m->u[top], st);
+  const long nb = nblocks(cells(G));
+  const int np = (int)(nb < kNormParts ? nb : kNormParts);
+  hipLaunchKernelGGL(k_mg_norm, dim3(np), dim3(NT), 0, st, G, m->u[top], m->f[top], m->a[top], m->part);
+  hipLaunchKernelGGL(k_mg_norm_finish, dim3(1), dim3(NT), 0, st, m->part, np);
+  if (hipMemcpyAsync(out, m->part + kNormParts, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return GMUNU_EHIP;
+  return launch_status();
+}
+
+// Bind the caller's finest-level arrays and restrict a to the coarse levels.
+void bind(gmunu_mg *m, double *u, const double *f, const double *a, hipStream_t st) {
+  const int top = m->levels - 1;
+  m->u[top] = u;
+  m->f[top] = const_cast<double *>(f);
+  m->a[top] = const_cast<double *>(a);
+  for (int l = top; l > 0; l--) {
+    m->a[l - 1] = a ? m->aown[l - 1] : nullptr;
+    if (a)
+      hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(cells(m->geo[l - 1]))), dim3(NT), 0, st, m->geo[l],
+                         m->geo[l - 1], m->a[l], m->a[l - 1]);
+  }
+}
+
+bool ok_ptr(const void *p) { return p && aligned8(p); }
+
+}  // namespace
+
+// --------------------------------------------------------------------- API
+
+extern "C" {
+
+int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out) {
+  if (!desc || !out) return GMUNU_ENULL;
+  const int levels = desc->levels > 0 ? desc->levels : auto_levels(*desc);
+  int rc = validate(*desc, levels);
+  if (rc) return rc;
+  gmunu_mg *m = new (std::nothrow) gmunu_mg();
+  if (!m) return GMUNU_ENOMEM;
+  m->d = *desc;
+  m->levels = levels;
+  std::vector<double> tab;
+  size_t off[kMaxLevels][11];
+  for (int l = 0; l < levels; l++) level_tables(*desc, levels - 1 - l, tab, off[l], m->geo[l]);
+  auto alloc = [&](size_t n) -> double * {
+    double *p = nullptr;
+    if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) return nullptr;
+    m->owned.push_back(p);
+    return p;
+  };
+  bool ok = (m->tab = alloc(tab.size())) != nullptr && (m->part = alloc(kNormParts + 1)) != nullptr;
+  for (int l = 0; l < levels && ok; l++) {
+    const size_t nt = (size_t)m->geo[l].nt;
+    ok = (m->r[l] = alloc(nt)) && (m->uo[l] = alloc(nt));
+    if (ok && l < levels - 1) ok = (m->u[l] = alloc(nt)) && (m->f[l] = alloc(nt)) && (m->aown[l] = alloc(nt));
+  }
+  ok = ok && hipMemcpy(m->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+  // zero every owned level array (ghosts of coarse arrays are then defined)
+  for (int l = 0; l < levels && ok; l++) {
+    const size_t b = (size_t)m->geo[l].nt * sizeof(double);
+    ok = hipMemset(m->r[l], 0, b) == hipSuccess && hipMemset(m->uo[l], 0, b) == hipSuccess;
+    if (ok && l < levels - 1)
+      ok = hipMemset(m->u[l], 0, b) == hipSuccess && hipMemset(m->f[l], 0, b) == hipSuccess &&
+           hipMemset(m->aown[l], 0, b) == hipSuccess;
+  }
+  ok = ok && hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    for (double *p : m->owned) (void)hipFree(p);
+    delete m;
+    return GMUNU_ENOMEM;
+  }
+  for (int l = 0; l < levels; l++) {
+    MgGeo &G = m->geo[l];
+    const double *b = m->tab;
+    G.a0m = b + off[l][0];
+    G.a0p = b + off[l][1];
+    G.g1 = b + off[l][2];
+    G.g2 = b + off[l][3];
+    G.vol0 = b + off[l][4];
+    G.sg0 = b + off[l][5];
+    G.a1m = b + off[l][6];
+    G.a1p = b + off[l][7];
+    G.s2t = b + off[l][8];
+    G.vol1 = b + off[l][9];
+    G.sg1 = b + off[l][10];
+  }
+  *out = m;
+  return GMUNU_OK;
+}
+
+int gmunu_mg_destroy(gmunu_mg *m) {
+  if (!m) return GMUNU_ENULL;
+  int rc = GMUNU_OK;
+  for (double *p : m->owned)
+    if (hipFree(p) != hipSuccess) rc = GMUNU_EHIP;
+  delete m;
+  return rc;
+}
+
+int gmunu_mg_levels(const gmunu_mg *m) { return m ? m->levels : GMUNU_ENULL; }
+
+long gmunu_mg_size(const gmunu_mg *m, int level) {
+  if (!m || level < 0 || level >= m->levels) return -1;
+  return m->geo[level].nt;
+}
+
+int gmunu_mg_solve(gmunu_mg *m, double *u, const double *f, const double *a, double tol, int max_cycles, int use_fmg,
+                   double *res_host, int *cycles_out, void *stream) {
+  if (!m || !u || !f) return GMUNU_ENULL;
+  if (!ok_ptr(u) || !ok_ptr(f) || (a && !aligned8(a))) return GMUNU_EALIGN;
+  if (max_cycles < 0 || !(tol >= 0.0)) return GMUNU_EINVAL;
+  hipStream_t st = as_stream(stream);
+  bind(m, u, f, a, st);
+  double r;
+  int rc = norm(m, &r, st);
+  if (rc) return rc;
+  if (res_host) res_host[0] = r;
+  int c = 0;
+  while (c < max_cycles && r > tol) {
+    if (c == 0 && use_fmg)
+      fmg(m, st);
+    else
+      vcycle(m, m->levels - 1, st);
+    c++;
+    rc = norm(m, &r, st);
+    if (rc) return rc;
+    if (res_host) res_host[c] = r;
+  }
+  if (cycles_out) *cycles_out = c;
+  return launch_status();
+}
+
+int gmunu_mg_residual_norm(gmunu_mg *m, double *u, const double *f, const double *a, double *norm_out,
+                           void *stream) {
+  if (!m || !u || !f || !norm_out) return GMUNU_ENULL;
+  if (!ok_ptr(u) || !ok_ptr(f) || (a && !aligned8(a))) return GMUNU_EALIGN;
+  hipStream_t st = as_stream(stream);
+  const int top = m->levels - 1;
+  m->u[top] = u;
+  m->f[top] = const_cast<double *>(f);
+  m->a[top] = const_cast<double *>(a);
+  return norm(m, norm_out, st);
+}
+
+int gmunu_mg_apply(gmunu_mg *m, const double *u, const double *a, double *out, void *stream) {
+  if (!m || !u || !out) return GMUNU_ENULL;
+  if (!ok_ptr(u) || !ok_ptr(out) || (a && !aligned8(a))) return GMUNU_EALIGN;
+  const MgGeo &G = m->geo[m->levels - 1];
+  hipLaunchKernelGGL(k_mg_apply, dim3(nblocks(cells(G))), dim3(NT), 0, as_stream(stream), G, u, a, out);
+  return launch_status();
+}
+
+int gmunu_mg_fill_ghosts(gmunu_mg *m, int level, double *u, void *stream) {
+  if (!m || !u) return GMUNU_ENULL;
+  if (!aligned8(u)) return GMUNU_EALIGN;
+  if (level < 0 || level >= m->levels) return GMUNU_EINVAL;
+  ghosts(m->geo[level], u, as_stream(stream));
+  return launch_status();
+}
+
+int gmunu_mg_smooth(gmunu_mg *m, double *u, const double *f, const double *a, int sweeps, void *stream) {
+  if (!m || !u || !f) return GMUNU_ENULL;
+  if (!ok_ptr(u) || !ok_ptr(f) || (a && !aligned8(a))) return GMUNU_EALIGN;
+  if (sweeps < 0) return GMUNU_EINVAL;
+  smooth(m->geo[m->levels - 1], u, f, a, sweeps, as_stream(stream));
+  return launch_status();
+}
+
+int gmunu_mg_restrict(gmunu_mg *m, int level, const double *fine, double *coarse, void *stream) {
+  if (!m || !fine || !coarse) return GMUNU_ENULL;
+  if (!ok_ptr(fine) || !ok_ptr(coarse)) return GMUNU_EALIGN;
+  if (level < 1 || level >= m->levels) return GMUNU_EINVAL;
+  const MgGeo &C = m->geo[level - 1];
+  hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(cells(C))), dim3(NT), 0, as_stream(stream), m->geo[level], C, fine,
+                     coarse);
+  return launch_status();
+}
+
+int gmunu_mg_prolong(gmunu_mg *m, int level, const double *coarse, double *fine, void *stream) {
+  if (!m || !fine || !coarse) return GMUNU_ENULL;
+  if (!ok_ptr(fine) || !ok_ptr(coarse)) return GMUNU_EALIGN;
+  if (level < 1 || level >= m->levels) return GMUNU_EINVAL;
+  const MgGeo &F = m->geo[level];
+  hipLaunchKernelGGL(k_mg_prolong, dim3(nblocks(cells(F))), dim3(NT), 0, as_stream(stream), m->geo[level - 1], F,
+                     coarse, fine, 0);
+  return launch_status();
+}
+
+int gmunu_mg_divergence(gmunu_mg *m, const double *q, double *div, void *stream) {
+  if (!m || !q || !div) return GMUNU_ENULL;
+  if (!ok_ptr(q) || !ok_ptr(div)) return GMUNU_EALIGN;
+  const MgGeo &G = m->geo[m->levels - 1];
+  hipLaunchKernelGGL(k_mg_div, dim3(nblocks(cells(G))), dim3(NT), 0, as_stream(stream), G, q, div);
+  return launch_status();
+}
+
+int gmunu_mg_subtract_gradient(gmunu_mg *m, const double *phi, double *q, void *stream) {
+  if (!m || !q || !phi) return GMUNU_ENULL;
+  if (!ok_ptr(q) || !ok_ptr(phi)) return GMUNU_EALIGN;
+  const MgGeo &G = m->geo[m->levels - 1];
+  hipLaunchKernelGGL(k_mg_subgrad, dim3(nblocks(cells(G))), dim3(NT), 0, as_stream(stream), G, phi, q);
+  return launch_status();
+}
+
+int gmunu_mg_clean(gmunu_mg *m, double *q, double *phi, double *div, double tol, int max_cycles, double *res_host,
+                   int *cycles_out, void *stream) {
+  if (!m || !q || !phi) return GMUNU_ENULL;
+  if (m->d.power != 0) return GMUNU_EINVAL;
+  if (!ok_ptr(q) || !ok_ptr(phi) || (div && !aligned8(div))) return GMUNU_EALIGN;
+  const int top = m->levels - 1;
+  // the divergence goes into the caller's div, else into the finest uo buffer
+  double *f = div ? div : m->uo[top];
+  int rc = gmunu_mg_divergence(m, q, f, stream);
+  if (rc) return rc;
+  rc = gmunu_mg_solve(m, phi, f, nullptr, tol, max_cycles, 1, res_host, cycles_out, stream);
+  if (rc) return rc;
+  ghosts(m->geo[top], phi, as_stream(stream));
+  return gmunu_mg_subtract_gradient(m, phi, q, stream);
+}
+
+}  // extern "C"
