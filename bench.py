@@ -382,6 +382,62 @@ def bench_serve(nreq=1000, probe=300, plain_n=300, plain_open=100, concurrency=6
     }
 
 
+def bench_mg(n=256, half=200.0, vcycles=8, sweeps=10):
+    """The metric-solver measurement of section 4: the lapse equation of a
+    static TOV star on a Cartesian n^3 box [-half, half]^3, solved from the
+    flat initial guess (alpha psi = 1) with V(2,2) red-black cycles.  Times
+    one FAS full-multigrid cycle, V-cycles (each with its residual norm and
+    host read-back), and smoothing sweeps of the finest level alone (the
+    dominant kernel: algorithmic bytes per sweep 40 per cell = u read by
+    both colours, f and a once, each cell written once)."""
+    import torch
+
+    import paper_2012_07322_amd as gmu
+    import workloads as W
+
+    log(f"[bench] multigrid: lapse equation on {n}^3")
+    p, a_np = W.lapse_equation(n, half)
+    M = gmu.Multigrid(p)
+    a = torch.from_numpy(a_np).cuda()
+    del a_np
+    f = torch.zeros_like(a)
+    u = torch.zeros_like(a)
+    M.solve(u, f, a, tol=0.0, max_cycles=2)  # warm-up (code objects, caches)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    u.zero_()
+    torch.cuda.synchronize()
+    ev[0].record()
+    h_fmg = M.solve(u, f, a, tol=0.0, max_cycles=1, fmg=True)
+    ev[1].record()
+    h_v = M.solve(u, f, a, tol=0.0, max_cycles=vcycles, fmg=False)
+    ev[2].record()
+    torch.cuda.synchronize()
+    u.zero_()
+    hist = M.solve(u, f, a, tol=1e-13, max_cycles=30, fmg=True)
+    torch.cuda.synchronize()
+    ev[3].record()
+    M.smooth(u, f, a, sweeps=sweeps)
+    ev[4].record()
+    torch.cuda.synchronize()
+    ms_fmg = ev[0].elapsed_time(ev[1])
+    ms_v = ev[1].elapsed_time(ev[2]) / vcycles
+    ms_sweep = ev[3].elapsed_time(ev[4]) / sweeps
+    cells = n ** 3
+    gbs = 40.0 * cells / (ms_sweep * 1e-3) / 1e9
+    cyc = next((i for i, r in enumerate(hist) if r <= 1e-10 * hist[0]), None)
+    out = {"workload": f"lapse equation of a static TOV star (K=100, Gamma=2, rho_c=1.28e-3), Cartesian {n}^3 on "
+                       f"[-{half:g},{half:g}]^3, Dirichlet faces, flat initial guess",
+           "levels": M.levels, "ms_per_fmg_cycle": ms_fmg, "ms_per_vcycle": ms_v,
+           "residual_after_fmg": h_fmg[-1] / h_fmg[0], "vcycle_rate": (h_v[-1] / h_v[0]) ** (1.0 / vcycles),
+           "residual_history": hist, "cycles_to_1e-10_relative": cyc,
+           "smoother": {"ms_per_sweep": ms_sweep, "bytes_per_cell_sweep": 40, "achieved_GBps": gbs,
+                        "peak_GBps": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}}
+    log(f"[bench] multigrid: FMG {ms_fmg:.2f} ms, V-cycle {ms_v:.2f} ms, sweep {ms_sweep:.3f} ms ({gbs:.0f} GB/s), "
+        f"{len(hist) - 1} cycles to {hist[-1]:.1e}")
+    M.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -400,6 +456,7 @@ def main():
     ap.add_argument("--serve-probe", type=int, default=300)
     ap.add_argument("--serve-plain", type=int, default=300)
     ap.add_argument("--serve-plain-open", type=int, default=100)
+    ap.add_argument("--mg", type=int, default=256, help="multigrid grid size (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -497,6 +554,9 @@ def main():
     torch.cuda.empty_cache()
     if args.blocks > 0:
         out["blocks"] = bench_blocks(args.blocks, steps=args.block_steps, cfl=args.cfl, seed=args.seed)
+        torch.cuda.empty_cache()
+    if args.mg > 0:
+        out["multigrid"] = bench_mg(args.mg)
         torch.cuda.empty_cache()
     if args.serve_requests > 0:
         out["serving"] = bench_serve(args.serve_requests, probe=args.serve_probe, plain_n=args.serve_plain,

@@ -434,6 +434,28 @@ def tov_fields(star, r):
     return rho, psi, alpha
 
 
+def lapse_equation(n=256, half=200.0, rho_c=1.28e-3, K=100.0, Gamma=2.0):
+    """The lapse equation of a static TOV star in deviation form on a
+    Cartesian n^3 box [-half, half]^3 (the paper's metric-solver test
+    domain), as an elliptic problem L(u) = Lap(u) - a (u + 1) = 0 for
+    u = alpha psi - 1 with a = 2 pi psi^4 (e + 6 p) (e = rho + p / (Gamma - 1),
+    p = K rho^Gamma; U + 2S of a static fluid, with the conformal factor of
+    the TOV solution).  Returns the multigrid problem dict (Dirichlet faces,
+    u = 0 there) and a (one ghost layer on each axis)."""
+    star = tov_isotropic(rho_c, K, Gamma)
+    h = 2.0 * half / n
+    x = -half + (np.arange(-1, n + 1) + 0.5) * h
+    p = dict(ndim=3, coord=CART, n=[n, n, n], xmin=[-half] * 3, dx=[h] * 3, bc=[[0, 0]] * 3, power=1,
+             offset=1.0)
+    a = np.empty((n + 2,) * 3)
+    for k in range(n + 2):  # slab by slab to bound the temporaries
+        r = np.sqrt(x[k] ** 2 + x[:, None] ** 2 + x[None, :] ** 2)
+        rho, psi, _ = tov_fields(star, r)
+        pres = K * rho ** Gamma
+        a[k] = 2.0 * math.pi * psi ** 4 * (rho + pres / (Gamma - 1.0) + 6.0 * pres)
+    return p, a
+
+
 def magnetised_star_2d(nr=256, nth=128, rmax=20.0, rho_c=1.28e-3, K=100.0, Gamma=2.0, b_peak=1e-4,
                        rho_atmo=1e-10, star=None):
     """Static magnetised polytropic star on a frozen CFC metric in 2D
