@@ -99,6 +99,34 @@ int gmunu_mg_subtract_gradient(gmunu_mg *mg, const double *phi, double *q, void 
 int gmunu_mg_clean(gmunu_mg *mg, double *q, double *phi, double *div, double tol, int max_cycles, double *res_host,
                    int *cycles_out, void *stream);
 
+/* The same cleaning applied to a GRMHD state (layout of include/gmunu.h)
+ * whose descriptor `hydro` has the multigrid's finest grid as its interior:
+ * q_B = q[5..7] (interior; the ghost layer from psi^6 times the primitive
+ * field, so prim's ghosts must be filled) is cleaned and written back to the
+ * interior of q.  The caller then recovers the primitives (gmunu_c2p) and
+ * fills their ghosts, as after any update of q.  Scratch of six finest-level
+ * arrays is allocated on the first call.  Needs p = 0. */
+int gmunu_mg_clean_state(gmunu_mg *mg, const gmunu_grid_desc *hydro, double *q, const double *prim,
+                         const double *metric, double tol, int max_cycles, double *res_host, int *cycles_out,
+                         void *stream);
+
+/* The scalar CFC metric equations of section 2.6 solved for a GRMHD state
+ * (steps 3 and 5 of the xCFC sequence, with the vector potential X and the
+ * shift left as they are, i.e. A^ij = 0: exact for static configurations):
+ *   Lap(psi - 1) = -2 pi U~ / psi,          U~ = q_tau + q_D,
+ *   Lap(alpha psi - 1) = alpha psi 2 pi (U~ + 2 S~) / psi^2,
+ *   S~ = psi^6 (rho h W^2 v^2 + 3 p) (fluid part, from prim and the new psi).
+ * mpsi must have p = -1, c = 1 and malpha p = 1, c = 1, both on the
+ * interior grid of `hydro` (boundary conditions: Robin on the outer radial
+ * face, as section 2.6 prescribes, for spherical grids).  Starts from the
+ * metric's psi and alpha; writes psi and alpha (metric variables 0 and 1) to
+ * every cell of the GRMHD layout, ghost layers extended by the multigrid
+ * boundary rule applied per layer.  cycles_out (2 ints, nullable): cycles of
+ * each solve. */
+int gmunu_mg_cfc_solve(gmunu_mg *mpsi, gmunu_mg *malpha, const gmunu_grid_desc *hydro, const double *q,
+                       const double *prim, double *metric, double tol, int max_cycles, int *cycles_out,
+                       void *stream);
+
 #ifdef __cplusplus
 }
 #endif

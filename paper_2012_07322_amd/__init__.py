@@ -549,6 +549,8 @@ def _mg_sigs(L):
     L.gmunu_mg_divergence.argtypes = [_P, _P, _P, _P]
     L.gmunu_mg_subtract_gradient.argtypes = [_P, _P, _P, _P]
     L.gmunu_mg_clean.argtypes = [_P, _P, _P, _P, D, I, _P, _P, _P]
+    L.gmunu_mg_clean_state.argtypes = [_P, _P, _P, _P, _P, D, I, _P, _P, _P]
+    L.gmunu_mg_cfc_solve.argtypes = [_P, _P, _P, _P, _P, _P, D, I, _P, _P]
 
 
 def make_mg_desc(p: dict) -> MgDesc:
@@ -674,3 +676,25 @@ class Multigrid:
                                     self._chk(div, "div", none_ok=True), float(tol), int(max_cycles), res,
                                     ctypes.byref(cyc), _stream()), "gmunu_mg_clean")
         return [res[i] for i in range(cyc.value + 1)]
+
+    def clean_state(self, grid_params, q, prim, metric, tol=1e-12, max_cycles=30):
+        """Clean q_B of a GRMHD state (q, prim, metric: the layout of
+        Grid(grid_params)) in place; returns the residual history."""
+        hd = make_desc(grid_params)
+        res = (ctypes.c_double * (max_cycles + 1))()
+        cyc = ctypes.c_int(0)
+        _check(lib().gmunu_mg_clean_state(self._h, ctypes.byref(hd), _ptr(q, "q"), _ptr(prim, "prim"),
+                                          _ptr(metric, "metric"), float(tol), int(max_cycles), res,
+                                          ctypes.byref(cyc), _stream()), "gmunu_mg_clean_state")
+        return [res[i] for i in range(cyc.value + 1)]
+
+
+def cfc_solve(mpsi, malpha, grid_params, q, prim, metric, tol=1e-12, max_cycles=60):
+    """Scalar CFC metric solve (psi, then alpha) for a GRMHD state; metric is
+    updated in place.  Returns the cycles of the two solves."""
+    hd = make_desc(grid_params)
+    cyc = (ctypes.c_int * 2)()
+    _check(lib().gmunu_mg_cfc_solve(mpsi._h, malpha._h, ctypes.byref(hd), _ptr(q, "q"), _ptr(prim, "prim"),
+                                    _ptr(metric, "metric"), float(tol), int(max_cycles), cyc, _stream()),
+           "gmunu_mg_cfc_solve")
+    return cyc[0], cyc[1]

@@ -283,6 +283,119 @@ __global__ __launch_bounds__(NT) void k_mg_subgrad(const MgGeo G, const double *
   if (G.ndim > 2) q[2 * G.nt + o] -= G.g2[I] * G.s2t[J] * (phi[o + G.s2] - phi[o - G.s2]) / (2.0 * G.h[2]);
 }
 
+// ------------------------------------------------- bridge to the GRMHD state
+
+// Layout of a GRMHD state array (include/gmunu.h: [var][k][j][i], ng ghost
+// layers on active axes) on the multigrid grid's interior.
+struct Hydro {
+  int ng[3];
+  long T0, T1, nv;  // cells per row, per plane, per variable
+  double gam;
+};
+
+__device__ __forceinline__ long hy_off(const Hydro &H, int i, int j, int k) {
+  return (long)(k + H.ng[2]) * H.T1 + (long)(j + H.ng[1]) * H.T0 + (i + H.ng[0]);
+}
+
+// q_B of every entry of the multigrid vector layout (interior from q, the
+// ghost layer from psi^6 times the primitive field, which the GRMHD ghost
+// fill maintains).
+__global__ __launch_bounds__(NT) void k_br_gather_qb(const MgGeo G, const Hydro H, const double *__restrict__ q,
+                                                     const double *__restrict__ prim, const double *__restrict__ met,
+                                                     double *__restrict__ qb) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= G.nt) return;
+  const int I = (int)(t % G.s1), J = (int)((t / G.s1) % (G.s2 / G.s1)), K = (int)(t / G.s2);
+  const int i = I - G.g[0], j = J - G.g[1], k = K - G.g[2];
+  const long o = hy_off(H, i, j, k);
+  const bool inside = i >= 0 && i < G.n[0] && j >= 0 && j < G.n[1] && k >= 0 && k < G.n[2];
+  const double psi = met[o], psi2 = psi * psi, psi6 = psi2 * psi2 * psi2;
+#pragma unroll
+  for (int c = 0; c < 3; c++) qb[c * G.nt + t] = inside ? q[(5 + c) * H.nv + o] : psi6 * prim[(5 + c) * H.nv + o];
+}
+
+__global__ __launch_bounds__(NT) void k_br_scatter_qb(const MgGeo G, const Hydro H, const double *__restrict__ qb,
+                                                      double *__restrict__ q) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(G)) return;
+  int i, j, k;
+  mg_cell(G, t, i, j, k);
+  const long o = hy_off(H, i, j, k), m = mg_off(G, i, j, k);
+#pragma unroll
+  for (int c = 0; c < 3; c++) q[(5 + c) * H.nv + o] = qb[c * G.nt + m];
+}
+
+// Coefficient of the scalar CFC equations (section 2.6) on the interior:
+// which 0 (conformal factor): a = -2 pi U~ with U~ = q_tau + q_D;
+// which 1 (lapse): a = 2 pi (U~ + 2 S~) / psi^2 with S~ = psi^6 (rho h W^2 v^2
+// + 3 p) from the primitives (fluid part) and psi from the metric.  u: the
+// initial guess u = psi - 1, or alpha psi - 1, from the metric.
+__global__ __launch_bounds__(NT) void k_br_cfc_coef(const MgGeo G, const Hydro H, const double *__restrict__ q,
+                                                    const double *__restrict__ prim, const double *__restrict__ met,
+                                                    int which, double *__restrict__ a, double *__restrict__ u) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(G)) return;
+  int i, j, k;
+  mg_cell(G, t, i, j, k);
+  const long o = hy_off(H, i, j, k), m = mg_off(G, i, j, k);
+  const double Ut = q[4 * H.nv + o] + q[o];
+  const double psi = met[o];
+  if (which == 0) {
+    a[m] = -2.0 * M_PI * Ut;
+    u[m] = psi - 1.0;
+    return;
+  }
+  const double psi2 = psi * psi, psi4 = psi2 * psi2;
+  // gamma_ij = psi^4 gamma^_ij with the reference metric of the grid
+  const int I = i + G.g[0], J = j + G.g[1];
+  double g1 = 1.0, g2 = 1.0;
+  if (G.coord == GMUNU_CYL) g2 = 1.0 / G.g2[I];
+  if (G.coord == GMUNU_SPH) {
+    g1 = 1.0 / G.g1[I];
+    g2 = g1 / G.s2t[J];
+  }
+  const double u1 = prim[H.nv + o], u2 = prim[2 * H.nv + o], u3 = prim[3 * H.nv + o];
+  const double w2v2 = psi4 * (u1 * u1 + g1 * u2 * u2 + g2 * u3 * u3);
+  const double rho = prim[o], p = prim[4 * H.nv + o];
+  const double rhoh = rho + H.gam / (H.gam - 1.0) * p;
+  const double St = psi4 * psi2 * (rhoh * w2v2 + 3.0 * p);
+  a[m] = 2.0 * M_PI * (Ut + 2.0 * St) / psi2;
+  u[m] = met[H.nv + o] * psi - 1.0;
+}
+
+// Metric of every GRMHD cell (ng ghost layers included) from the solution u
+// of level G, ghost layers extended by the multigrid boundary rule applied
+// per layer (mirror about the face times -1, +1 or r_in / r_ghost; periodic
+// wrap): which 0 writes psi = 1 + u, which 1 alpha = (1 + u) / psi.
+__global__ __launch_bounds__(NT) void k_br_store(const MgGeo G, const Hydro H, const double *__restrict__ u,
+                                                 double xmin0, int which, double *__restrict__ met) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= H.nv) return;
+  int c[3] = {(int)(t % H.T0) - H.ng[0], (int)((t / H.T0) % (H.T1 / H.T0)) - H.ng[1], (int)(t / H.T1) - H.ng[2]};
+  double fac = 1.0;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    if (a >= G.ndim) continue;
+    const int n = G.n[a];
+    if (c[a] >= 0 && c[a] < n) continue;
+    const int side = c[a] < 0 ? 0 : 1;
+    const int kind = G.bc[a][side];
+    if (kind == GMUNU_MG_PERIODIC) {
+      c[a] = side == 0 ? c[a] + n : c[a] - n;
+      continue;
+    }
+    const int in = side == 0 ? -1 - c[a] : 2 * n - 1 - c[a];
+    if (kind == GMUNU_MG_DIRICHLET) fac = -fac;
+    if (kind == GMUNU_MG_ROBIN) fac *= (xmin0 + (in + 0.5) * G.h[0]) / (xmin0 + (c[a] + 0.5) * G.h[0]);
+    c[a] = in;
+  }
+  const double v = 1.0 + fac * u[mg_off(G, c[0], c[1], c[2])];
+  if (which == 0)
+    met[t] = v;
+  else
+    met[H.nv + t] = v / met[t];
+}
+
 }  // namespace
 
 struct gmunu_mg {
@@ -295,6 +408,7 @@ struct gmunu_mg {
   double *u[kMaxLevels], *f[kMaxLevels], *a[kMaxLevels], *r[kMaxLevels], *uo[kMaxLevels];
   double *aown[kMaxLevels];  // coarse-level storage of a
   double *part;  // norm partials + result
+  double *br;    // state bridge scratch (6 arrays of the finest level), allocated on first use
   std::vector<double *> owned;
 };
 
@@ -522,6 +636,7 @@ int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out) {
     m->owned.push_back(p);
     return p;
   };
+  m->br = nullptr;
   bool ok = (m->tab = alloc(tab.size())) != nullptr && (m->part = alloc(kNormParts + 1)) != nullptr;
   for (int l = 0; l < levels && ok; l++) {
     const size_t nt = (size_t)m->geo[l].nt;
@@ -690,6 +805,102 @@ int gmunu_mg_clean(gmunu_mg *m, double *q, double *phi, double *div, double tol,
   if (rc) return rc;
   ghosts(m->geo[top], phi, as_stream(stream));
   return gmunu_mg_subtract_gradient(m, phi, q, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The GRMHD layout of a descriptor whose interior is the multigrid's finest
+// grid (same dimensions, coordinates, spacing and origin), else EINVAL.
+int hydro_of(const gmunu_mg *m, const gmunu_grid_desc *hd, Hydro &H) {
+  const gmunu_mg_desc &d = m->d;
+  if (hd->ndim != d.ndim || hd->coord != d.coord || hd->ng < 1) return GMUNU_EINVAL;
+  long T[3];
+  for (int a = 0; a < 3; a++) {
+    if (hd->n[a] != d.n[a]) return GMUNU_EINVAL;
+    if (a < d.ndim && (std::fabs(hd->dx[a] - d.dx[a]) > 1e-12 * d.dx[a] ||
+                       std::fabs(hd->xmin[a] - d.xmin[a]) > 1e-12 * (std::fabs(d.xmin[a]) + d.dx[a])))
+      return GMUNU_EINVAL;
+    H.ng[a] = a < d.ndim ? hd->ng : 0;
+    T[a] = d.n[a] + 2 * H.ng[a];
+  }
+  H.T0 = T[0];
+  H.T1 = T[0] * T[1];
+  H.nv = H.T1 * T[2];
+  H.gam = hd->gamma;
+  return GMUNU_OK;
+}
+
+bool bridge_scratch(gmunu_mg *m) {
+  if (m->br) return true;
+  double *p = nullptr;
+  if (hipMalloc(&p, 6 * (size_t)m->geo[m->levels - 1].nt * sizeof(double)) != hipSuccess) return false;
+  if (hipMemset(p, 0, 6 * (size_t)m->geo[m->levels - 1].nt * sizeof(double)) != hipSuccess) {
+    (void)hipFree(p);
+    return false;
+  }
+  m->owned.push_back(p);
+  m->br = p;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gmunu_mg_clean_state(gmunu_mg *m, const gmunu_grid_desc *hydro, double *q, const double *prim,
+                         const double *metric, double tol, int max_cycles, double *res_host, int *cycles_out,
+                         void *stream) {
+  if (!m || !hydro || !q || !prim || !metric) return GMUNU_ENULL;
+  if (!aligned8(q) || !aligned8(prim) || !aligned8(metric)) return GMUNU_EALIGN;
+  Hydro H;
+  int rc = hydro_of(m, hydro, H);
+  if (rc) return rc;
+  if (m->d.power != 0) return GMUNU_EINVAL;
+  if (!bridge_scratch(m)) return GMUNU_ENOMEM;
+  const MgGeo &G = m->geo[m->levels - 1];
+  hipStream_t st = as_stream(stream);
+  double *qb = m->br, *phi = m->br + 3 * G.nt, *div = m->br + 4 * G.nt;
+  hipLaunchKernelGGL(k_br_gather_qb, dim3(nblocks(G.nt)), dim3(NT), 0, st, G, H, q, prim, metric, qb);
+  if (hipMemsetAsync(phi, 0, (size_t)G.nt * sizeof(double), st) != hipSuccess) return GMUNU_EHIP;
+  rc = gmunu_mg_clean(m, qb, phi, div, tol, max_cycles, res_host, cycles_out, stream);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_br_scatter_qb, dim3(nblocks(cells(G))), dim3(NT), 0, st, G, H, qb, q);
+  return launch_status();
+}
+
+int gmunu_mg_cfc_solve(gmunu_mg *mpsi, gmunu_mg *malpha, const gmunu_grid_desc *hydro, const double *q,
+                       const double *prim, double *metric, double tol, int max_cycles, int *cycles_out,
+                       void *stream) {
+  if (!mpsi || !malpha || !hydro || !q || !prim || !metric) return GMUNU_ENULL;
+  if (!aligned8(q) || !aligned8(prim) || !aligned8(metric)) return GMUNU_EALIGN;
+  Hydro H, H2;
+  int rc = hydro_of(mpsi, hydro, H);
+  if (!rc) rc = hydro_of(malpha, hydro, H2);
+  if (rc) return rc;
+  if (mpsi->d.power != -1 || mpsi->d.offset != 1.0 || malpha->d.power != 1 || malpha->d.offset != 1.0)
+    return GMUNU_EINVAL;
+  if (!bridge_scratch(mpsi)) return GMUNU_ENOMEM;
+  hipStream_t st = as_stream(stream);
+  int cyc[2] = {0, 0};
+  gmunu_mg *ms[2] = {mpsi, malpha};
+  for (int w = 0; w < 2; w++) {
+    gmunu_mg *m = ms[w];
+    const MgGeo &G = m->geo[m->levels - 1];
+    const MgGeo &G0 = mpsi->geo[mpsi->levels - 1];
+    double *u = mpsi->br, *a = mpsi->br + G0.nt, *f = mpsi->br + 2 * G0.nt;
+    if (hipMemsetAsync(f, 0, (size_t)G0.nt * sizeof(double), st) != hipSuccess) return GMUNU_EHIP;
+    hipLaunchKernelGGL(k_br_cfc_coef, dim3(nblocks(cells(G))), dim3(NT), 0, st, G, H, q, prim, metric, w, a, u);
+    rc = gmunu_mg_solve(m, u, f, a, tol, max_cycles, 1, nullptr, &cyc[w], stream);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_br_store, dim3(nblocks(H.nv)), dim3(NT), 0, st, G, H, u, m->d.xmin[0], w, metric);
+  }
+  if (cycles_out) {
+    cycles_out[0] = cyc[0];
+    cycles_out[1] = cyc[1];
+  }
+  return launch_status();
 }
 
 }  // extern "C"

@@ -220,3 +220,92 @@ def test_invalid_descriptors_are_rejected():
     for p in bad:
         with pytest.raises(RuntimeError):
             gmu.Multigrid(p)
+
+
+# ------------------------------------------- bridge to the GRMHD state
+
+def test_clean_state_matches_the_oracle():
+    """Cleaning of q_B of a GRMHD state (q from the GPU's prim2con with a
+    non-trivial conformal factor): the cleaned interior q_B equals the
+    oracle's cleaning of the same field (interior q_B, ghost layer psi^6 B)."""
+    import workloads as W
+    n = 32
+    hp = W.grid(3, W.CART, [n] * 3, [0, 0, 0], [1, 1, 1], [[W.OUTFLOW, W.OUTFLOW]] * 3, gamma=5 / 3)
+    x, y, z = W.centres(hp)
+    s, c, pi = np.sin, np.cos, math.pi
+    pr = W.empty_prim(hp)
+    pr[0] = 1.0
+    pr[4] = 1.0
+    pr[5] = pi * c(pi * x) * s(pi * y) * s(pi * z) + 2 * pi * s(2 * pi * x) * c(2 * pi * y)
+    pr[6] = pi * s(pi * x) * c(pi * y) * s(pi * z) - 2 * pi * c(2 * pi * x) * s(2 * pi * y)
+    pr[7] = pi * s(pi * x) * s(pi * y) * c(pi * z)
+    met = W.flat_metric(hp)
+    met[0] = 1.0 + 0.1 * s(2 * pi * x) * c(pi * y)
+    g = gmu.Grid(hp)
+    prd, metd = dev(pr), dev(met)
+    q = g.prim2con(prd, metd)
+    q0 = host(q).copy()
+    mp = prob(3, CART, (n, n, n), (0, 0, 0), (1, 1, 1), [[D, D]] * 3)
+    M = gmu.Multigrid(mp)
+    hist = M.clean_state(hp, q, prd, metd, tol=1e-12, max_cycles=40)
+    assert hist[-1] <= 1e-12
+    qg = host(q)
+    # oracle: the same field on the multigrid layout
+    gh = 2
+    sl = (slice(gh - 1, gh + n + 1),) * 3
+    psi6 = met[0][sl] ** 6
+    qb = np.stack([psi6 * pr[5 + i][sl] for i in range(3)])
+    inner = (slice(1, -1),) * 3
+    for i in range(3):
+        qb[i][inner] = q0[5 + i][(slice(gh, gh + n),) * 3]
+    qb = np.ascontiguousarray(qb)
+    div = mg.divergence(mp, qb)
+    u = np.zeros(mg.shape(mp))
+    mg.solve(mp, u, np.ascontiguousarray(div), tol=1e-12, max_cycles=40)
+    mg.fill_ghosts(mp, u)
+    mg.subtract_gradient(mp, u, qb)
+    for i in range(3):
+        got = qg[5 + i][(slice(gh, gh + n),) * 3]
+        assert np.abs(got - qb[i][inner]).max() <= 1e-10 * np.abs(qb).max()
+    # the rest of q is untouched
+    assert np.array_equal(qg[:5], q0[:5])
+
+
+def test_cfc_solve_recovers_the_tov_metric():
+    """The scalar CFC equations solved from the conserved variables of a
+    static TOV star (built with its own metric) from a flat initial guess
+    return the TOV conformal factor and lapse (TOV in isotropic coordinates
+    is conformally flat), with the error falling at about second order; the
+    conformal factor agrees with the oracle's solve of the same equation."""
+    import workloads as W
+    errs = []
+    for nr, nth in ((64, 16), (128, 32)):
+        hp, pr, met = W.magnetised_star_2d(nr, nth, b_peak=1e-12)
+        g = gmu.Grid(hp)
+        prd, metd = dev(pr), dev(met)
+        g.fill_ghosts(prd)
+        q = g.prim2con(prd, metd)
+        exact = met.copy()
+        metd[0].fill_(1.0)
+        metd[1].fill_(1.0)
+        mp = prob(2, SPH, (nr, nth), (0.0, 0.0), (hp["dx"][0] * nr, math.pi), [[N, ROB], [N, N]], pre=4, post=4)
+        Mp = gmu.Multigrid(dict(mp, power=-1, offset=1.0))
+        Ma = gmu.Multigrid(dict(mp, power=1, offset=1.0))
+        cyc = gmu.cfc_solve(Mp, Ma, hp, q, prd, metd, tol=1e-12, max_cycles=200)
+        m = host(metd)
+        gh = hp.get("ng", 2)
+        sl = (Ellipsis, slice(gh, gh + nth), slice(gh, gh + nr))
+        e_psi = np.abs(m[0][sl] - exact[0][sl]).max()
+        e_al = np.abs(m[1][sl] - exact[1][sl]).max()
+        note(f"  TOV {nr}x{nth}: cycles {cyc}, |psi err| {e_psi:.2e}, |alpha err| {e_al:.2e}")
+        errs.append((e_psi, e_al))
+        # parity of the psi solve with the oracle on the same coefficient
+        qh = host(q)
+        a = np.zeros(mg.shape(dict(mp)))
+        a[0, 1:-1, 1:-1] = -2 * math.pi * (qh[4] + qh[0])[0, gh:gh + nth, gh:gh + nr]
+        uo = np.zeros(mg.shape(dict(mp)))
+        po = dict(mp, power=-1, offset=1.0)
+        mg.solve(po, uo, np.zeros_like(uo), np.ascontiguousarray(a), tol=1e-12, max_cycles=200)
+        assert np.abs(1.0 + mg.interior(po, uo)[0] - m[0][sl][0]).max() <= 1e-9
+    assert errs[1][0] < 2e-4 and errs[1][1] < 4e-4
+    assert errs[0][0] / errs[1][0] > 2.5 and errs[0][1] / errs[1][1] > 2.5
