@@ -78,11 +78,12 @@ def test_binding_raises_without_device_tensors():
 
 def _c_layout(structs):
     """sizeof and field offsets of header structs, from a C program built
-    with the host compiler against include/gmunu.h."""
+    with the host compiler against include/gmunu.h and gmunu_mg.h."""
     import subprocess
     import tempfile
 
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gmunu.h"', "int main(void) {"]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gmunu.h"', '#include "gmunu_mg.h"',
+             "int main(void) {"]
     for st, fields in structs.items():
         lines.append(f'  printf("{st} size %zu\\n", sizeof({st}));')
         for f in fields:
@@ -102,7 +103,7 @@ def _c_layout(structs):
 
 def test_struct_mirrors_match_the_header():
     mirrors = {"gmunu_grid_desc": gmu.GridDesc, "gmunu_block": gmu.BlockSpec, "gmunu_request": gmu.RequestSpec,
-               "gmunu_result": gmu.Result, "gmunu_server_info": gmu.ServerInfo}
+               "gmunu_result": gmu.Result, "gmunu_server_info": gmu.ServerInfo, "gmunu_mg_desc": gmu.MgDesc}
     lay = _c_layout({k: [f for f, _ in v._fields_] for k, v in mirrors.items()})
     for st, cls in mirrors.items():
         assert lay[(st, "size")] == ctypes.sizeof(cls), st
@@ -138,3 +139,19 @@ def test_range_pool_host_logic():
                                src, "-o", exe])
         out = subprocess.check_output([exe], text=True)
     assert out.strip().endswith("ok"), out
+
+
+def test_multigrid_create_rejects_invalid_descriptors():
+    """Validation happens before any device call."""
+    L = gmu.lib()
+    if not hasattr(L, "_mg_sigs_set"):
+        gmu._mg_sigs(L)
+        L._mg_sigs_set = True
+    base = dict(ndim=2, coord=0, n=[16, 16, 1], xmin=[0, 0, 0], dx=[1 / 16, 1 / 16, 1], bc=[[0, 0]] * 3)
+    bad = [dict(base, n=[12, 16, 1], levels=4), dict(base, bc=[[3, 0], [0, 0], [0, 0]]),
+           dict(base, coord=2, bc=[[1, 1], [3, 1], [1, 1]]), dict(base, bc=[[2, 0], [0, 0], [0, 0]]),
+           dict(base, power=2), dict(base, coarse=0), dict(base, n=[16, 16, 2]), dict(base, ndim=4)]
+    for p in bad:
+        h = ctypes.c_void_p()
+        assert L.gmunu_mg_create(ctypes.byref(gmu.make_mg_desc(p)), ctypes.byref(h)) == -1, p
+        assert not h.value
