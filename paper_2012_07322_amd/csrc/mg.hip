@@ -63,24 +63,45 @@ __device__ __forceinline__ double mg_nl_du(const MgGeo &G, double a, double u) {
   return -a / (w * w);
 }
 
-// L(u) at interior cell (i,j,k) (linear offset o) and dL/du there.
+// Neighbour of interior cell index c (0..n-1) along an axis of stride S on
+// the side `up`: the stored value inside, else the boundary rule applied to
+// the cell itself (the value a ghost fill would store there).
+__device__ __forceinline__ double mg_nb(const MgGeo &G, const double *__restrict__ u, long o, int c, int a, long S,
+                                        bool up) {
+  const int n = G.n[a];
+  if (up ? c < n - 1 : c > 0) return u[up ? o + S : o - S];
+  const int kind = G.bc[a][up ? 1 : 0];
+  if (kind == GMUNU_MG_PERIODIC) return u[up ? o - (long)(n - 1) * S : o + (long)(n - 1) * S];
+  const double ui = u[o];
+  return kind == GMUNU_MG_DIRICHLET ? -ui : kind == GMUNU_MG_NEUMANN ? ui : ui * (up ? G.rob_hi : G.rob_lo);
+}
+
+// L(u) at interior cell (i,j,k) (linear offset o) and dL/du there.  GH:
+// neighbours across the boundary from u's ghost entries as stored; else
+// from the boundary rule (mg_nb), so that no ghost fill is needed.
+template <bool GH>
 __device__ __forceinline__ double mg_L(const MgGeo &G, const double *__restrict__ u, const double *__restrict__ a,
                                        int i, int j, int k, long o, double *dg) {
   const int I = i + G.g[0], J = j + G.g[1];
   const double uc = u[o];
   double wm = G.a0m[I], wp = G.a0p[I];
-  double lap = wp * (u[o + 1] - uc) - wm * (uc - u[o - 1]);
+  double um = GH ? u[o - 1] : mg_nb(G, u, o, i, 0, 1, false), up = GH ? u[o + 1] : mg_nb(G, u, o, i, 0, 1, true);
+  double lap = wp * (up - uc) - wm * (uc - um);
   double d = -(wm + wp);
   if (G.ndim > 1) {
     const double gi = G.g1[I];
     wm = gi * G.a1m[J];
     wp = gi * G.a1p[J];
-    lap += wp * (u[o + G.s1] - uc) - wm * (uc - u[o - G.s1]);
+    um = GH ? u[o - G.s1] : mg_nb(G, u, o, j, 1, G.s1, false);
+    up = GH ? u[o + G.s1] : mg_nb(G, u, o, j, 1, G.s1, true);
+    lap += wp * (up - uc) - wm * (uc - um);
     d -= wm + wp;
   }
   if (G.ndim > 2) {
     const double w = G.g2[I] * G.s2t[J] * G.ih2_2;
-    lap += w * (u[o + G.s2] - uc) - w * (uc - u[o - G.s2]);
+    um = GH ? u[o - G.s2] : mg_nb(G, u, o, k, 2, G.s2, false);
+    up = GH ? u[o + G.s2] : mg_nb(G, u, o, k, 2, G.s2, true);
+    lap += w * (up - uc) - w * (uc - um);
     d -= 2.0 * w;
   }
   const double av = a ? a[o] : 0.0;
@@ -96,9 +117,8 @@ __device__ __forceinline__ void mg_cell(const MgGeo &G, long t, int &i, int &j, 
 
 __device__ __forceinline__ long mg_cells(const MgGeo &G) { return (long)G.n[0] * G.n[1] * G.n[2]; }
 
-// Face-adjacent ghosts: thread t -> axis, side, transverse cell.
-__global__ __launch_bounds__(NT) void k_mg_ghosts(const MgGeo G, double *u) {
-  long t = (long)blockIdx.x * NT + threadIdx.x;
+// Face-adjacent ghost number t: axis, side, transverse cell.
+__device__ __forceinline__ void mg_ghost_one(const MgGeo &G, double *u, long t) {
   for (int a = 0; a < G.ndim; a++) {
     const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
     const long per = 2L * G.n[b1] * G.n[b2];
@@ -127,11 +147,23 @@ __global__ __launch_bounds__(NT) void k_mg_ghosts(const MgGeo G, double *u) {
   }
 }
 
+__device__ __forceinline__ long mg_ghost_count(const MgGeo &G) {
+  long s = 0;
+  for (int a = 0; a < G.ndim; a++) {
+    const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    s += 2L * G.n[b1] * G.n[b2];
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(NT) void k_mg_ghosts(const MgGeo G, double *u) {
+  mg_ghost_one(G, u, (long)blockIdx.x * NT + threadIdx.x);
+}
+
 // One colour of red-black Newton-Gauss-Seidel: thread t -> the t-th cell of
 // that colour (every other cell of a row).
-__global__ __launch_bounds__(NT) void k_mg_smooth(const MgGeo G, double *u, const double *__restrict__ f,
-                                                  const double *__restrict__ a, int colour) {
-  const long t = (long)blockIdx.x * NT + threadIdx.x;
+__device__ __forceinline__ void mg_smooth_one(const MgGeo &G, double *u, const double *__restrict__ f,
+                                              const double *__restrict__ a, int colour, long t) {
   const int hrow = (G.n[0] + 1) >> 1;
   const long row = t / hrow;
   if (row >= (long)G.n[1] * G.n[2]) return;
@@ -140,20 +172,25 @@ __global__ __launch_bounds__(NT) void k_mg_smooth(const MgGeo G, double *u, cons
   if (i >= G.n[0]) return;
   const long o = mg_off(G, i, j, k);
   double dg;
-  const double Lu = mg_L(G, u, a, i, j, k, o, &dg);
+  const double Lu = mg_L<false>(G, u, a, i, j, k, o, &dg);
   u[o] -= (Lu - f[o]) / dg;
 }
 
-// r = f - L(u) on the interior.
-__global__ __launch_bounds__(NT) void k_mg_residual(const MgGeo G, const double *__restrict__ u,
-                                                    const double *__restrict__ f, const double *__restrict__ a,
-                                                    double *__restrict__ r) {
-  const long t = (long)blockIdx.x * NT + threadIdx.x;
-  if (t >= mg_cells(G)) return;
-  int i, j, k;
-  mg_cell(G, t, i, j, k);
-  const long o = mg_off(G, i, j, k);
-  r[o] = f[o] - mg_L(G, u, a, i, j, k, o, nullptr);
+__global__ __launch_bounds__(NT) void k_mg_smooth(const MgGeo G, double *u, const double *__restrict__ f,
+                                                  const double *__restrict__ a, int colour) {
+  mg_smooth_one(G, u, f, a, colour, (long)blockIdx.x * NT + threadIdx.x);
+}
+
+// The coarsest-level solver: `sweeps` red-black sweeps by one workgroup,
+// the colours separated by workgroup barriers instead of launches.
+__global__ __launch_bounds__(NT) void k_mg_coarse(const MgGeo G, double *u, const double *__restrict__ f,
+                                                  const double *__restrict__ a, int sweeps) {
+  const long nc = (long)((G.n[0] + 1) >> 1) * G.n[1] * G.n[2];
+  for (int s = 0; s < sweeps; s++)
+    for (int c = 0; c < 2; c++) {
+      for (long t = threadIdx.x; t < nc; t += NT) mg_smooth_one(G, u, f, a, c, t);
+      __syncthreads();
+    }
 }
 
 // out = L(u) on the interior.
@@ -164,7 +201,7 @@ __global__ __launch_bounds__(NT) void k_mg_apply(const MgGeo G, const double *__
   int i, j, k;
   mg_cell(G, t, i, j, k);
   const long o = mg_off(G, i, j, k);
-  out[o] = mg_L(G, u, a, i, j, k, o, nullptr);
+  out[o] = mg_L<true>(G, u, a, i, j, k, o, nullptr);
 }
 
 // Per-workgroup maxima of |f - L(u)| over a grid-stride range of cells.
@@ -176,7 +213,7 @@ __global__ __launch_bounds__(NT) void k_mg_norm(const MgGeo G, const double *__r
     int i, j, k;
     mg_cell(G, t, i, j, k);
     const long o = mg_off(G, i, j, k);
-    m = fmax(m, fabs(f[o] - mg_L(G, u, a, i, j, k, o, nullptr)));
+    m = fmax(m, fabs(f[o] - mg_L<false>(G, u, a, i, j, k, o, nullptr)));
   }
   m = block_max(m);
   if (threadIdx.x == 0) part[blockIdx.x] = m;
@@ -218,18 +255,77 @@ __global__ __launch_bounds__(NT) void k_mg_fas_rhs(const MgGeo C, const double *
   int i, j, k;
   mg_cell(C, t, i, j, k);
   const long o = mg_off(C, i, j, k);
-  f[o] = mg_L(C, u, a, i, j, k, o, nullptr) + r[o];
+  f[o] = mg_L<false>(C, u, a, i, j, k, o, nullptr) + r[o];
   uo[o] = u[o];
 }
 
-// e = u - uo into uo on the interior (the coarse correction).
-__global__ __launch_bounds__(NT) void k_mg_diff(const MgGeo C, const double *__restrict__ u, double *__restrict__ uo) {
+// Coarse problem of a fine level in one pass over the coarse cells: the
+// residual f - L(u) of each child (boundary rule inline) and the
+// volume-weighted means of u and of the residual into the coarse u and r.
+__global__ __launch_bounds__(NT) void k_mg_restrict_res(const MgGeo F, const MgGeo C, const double *__restrict__ u,
+                                                        const double *__restrict__ f, const double *__restrict__ a,
+                                                        double *__restrict__ uc, double *__restrict__ rc) {
   const long t = (long)blockIdx.x * NT + threadIdx.x;
   if (t >= mg_cells(C)) return;
   int i, j, k;
   mg_cell(C, t, i, j, k);
-  const long o = mg_off(C, i, j, k);
-  uo[o] = u[o] - uo[o];
+  double su = 0.0, sr = 0.0, w = 0.0;
+  const int nch = 1 << F.ndim;
+  for (int ch = 0; ch < nch; ch++) {
+    const int fi = 2 * i + (ch & 1);
+    const int fj = F.ndim > 1 ? 2 * j + ((ch >> 1) & 1) : j;
+    const int fk = F.ndim > 2 ? 2 * k + ((ch >> 2) & 1) : k;
+    const double v = F.vol0[fi + F.g[0]] * F.vol1[fj + F.g[1]];
+    const long o = mg_off(F, fi, fj, fk);
+    su += v * u[o];
+    sr += v * (f[o] - mg_L<false>(F, u, a, fi, fj, fk, o, nullptr));
+    w += v;
+  }
+  const long oc = mg_off(C, i, j, k);
+  uc[oc] = su / w;
+  rc[oc] = sr / w;
+}
+
+// u_F += P (u_C - uo_C): Kwak prolongation of the coarse correction, whose
+// values across the boundary follow the boundary rule (it is homogeneous,
+// so the correction obeys it too).
+__device__ __forceinline__ double mg_corr(const MgGeo &C, const double *__restrict__ u,
+                                          const double *__restrict__ uo, long o) {
+  return u[o] - uo[o];
+}
+
+__global__ __launch_bounds__(NT) void k_mg_correct(const MgGeo C, const MgGeo F, const double *__restrict__ uc,
+                                                   const double *__restrict__ uoc, double *__restrict__ fine) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(F)) return;
+  int fc[3];
+  mg_cell(F, t, fc[0], fc[1], fc[2]);
+  int cc[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) cc[a] = a < F.ndim ? fc[a] >> 1 : fc[a];
+  const double w0 = F.ndim == 1 ? 0.75 : F.ndim == 2 ? 0.5 : 0.25;
+  const long oc = mg_off(C, cc[0], cc[1], cc[2]);
+  const double e0 = mg_corr(C, uc, uoc, oc);
+  double s = w0 * e0;
+  const long S[3] = {1, C.s1, C.s2};
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    if (a >= F.ndim) continue;
+    const bool up = fc[a] & 1;
+    const int c = cc[a], n = C.n[a];
+    double e;
+    if (up ? c < n - 1 : c > 0) {
+      e = mg_corr(C, uc, uoc, up ? oc + S[a] : oc - S[a]);
+    } else {
+      const int kind = C.bc[a][up ? 1 : 0];
+      if (kind == GMUNU_MG_PERIODIC)
+        e = mg_corr(C, uc, uoc, up ? oc - (long)(n - 1) * S[a] : oc + (long)(n - 1) * S[a]);
+      else
+        e = kind == GMUNU_MG_DIRICHLET ? -e0 : kind == GMUNU_MG_NEUMANN ? e0 : e0 * (up ? C.rob_hi : C.rob_lo);
+    }
+    s += 0.25 * e;
+  }
+  fine[mg_off(F, fc[0], fc[1], fc[2])] += s;
 }
 
 // Kwak prolongation of v (coarse, ghosts set) into the fine interior:
@@ -410,6 +506,12 @@ struct gmunu_mg {
   double *part;  // norm partials + result
   double *br;    // state bridge scratch (6 arrays of the finest level), allocated on first use
   std::vector<double *> owned;
+  // V-cycles are replayed from a graph captured on a private stream for the
+  // finest arrays (u, f, a) they were captured with
+  hipStream_t gs;
+  hipEvent_t ev;
+  hipGraphExec_t vexec;
+  const double *gu, *gf, *ga;
 };
 
 namespace {
@@ -532,50 +634,62 @@ void ghosts(const MgGeo &G, double *u, hipStream_t st) {
   if (gc) hipLaunchKernelGGL(k_mg_ghosts, dim3(nblocks(gc)), dim3(NT), 0, st, G, u);
 }
 
-void smooth(const MgGeo &G, double *u, const double *f, const double *a, int sweeps, hipStream_t st) {
+// Red-black sweeps (boundary rule inline: no ghost fill between colours).
+void sweeps_raw(const MgGeo &G, double *u, const double *f, const double *a, int sweeps, hipStream_t st) {
   const long threads = (long)((G.n[0] + 1) / 2) * G.n[1] * G.n[2];
   for (int s = 0; s < sweeps; s++)
-    for (int c = 0; c < 2; c++) {
-      ghosts(G, u, st);
+    for (int c = 0; c < 2; c++)
       hipLaunchKernelGGL(k_mg_smooth, dim3(nblocks(threads)), dim3(NT), 0, st, G, u, f, a, c);
-    }
+}
+
+// The same, then u's ghost entries from the boundary rule.
+void smooth(const MgGeo &G, double *u, const double *f, const double *a, int sweeps, hipStream_t st) {
+  sweeps_raw(G, u, f, a, sweeps, st);
   ghosts(G, u, st);
 }
 
+// Coarse problem of level l: u_{l-1} = R u_l (kept in uo_{l-1}),
+// f_{l-1} = L_{l-1}(R u_l) + R (f_l - L_l(u_l)).
 void coarse_problem(gmunu_mg *m, int l, hipStream_t st) {
   const MgGeo &F = m->geo[l], &C = m->geo[l - 1];
-  ghosts(F, m->u[l], st);
-  hipLaunchKernelGGL(k_mg_residual, dim3(nblocks(cells(F))), dim3(NT), 0, st, F, m->u[l], m->f[l], m->a[l], m->r[l]);
-  hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(cells(C))), dim3(NT), 0, st, F, C, m->u[l], m->u[l - 1]);
-  hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(cells(C))), dim3(NT), 0, st, F, C, m->r[l], m->r[l - 1]);
-  ghosts(C, m->u[l - 1], st);
+  hipLaunchKernelGGL(k_mg_restrict_res, dim3(nblocks(cells(C))), dim3(NT), 0, st, F, C, m->u[l], m->f[l], m->a[l],
+                     m->u[l - 1], m->r[l - 1]);
   hipLaunchKernelGGL(k_mg_fas_rhs, dim3(nblocks(cells(C))), dim3(NT), 0, st, C, m->u[l - 1], m->a[l - 1],
                      m->r[l - 1], m->f[l - 1], m->uo[l - 1]);
 }
 
+// u_l += P(u_{l-1} - uo_{l-1})
 void correct(gmunu_mg *m, int l, hipStream_t st) {
   const MgGeo &F = m->geo[l], &C = m->geo[l - 1];
-  hipLaunchKernelGGL(k_mg_diff, dim3(nblocks(cells(C))), dim3(NT), 0, st, C, m->u[l - 1], m->uo[l - 1]);
-  ghosts(C, m->uo[l - 1], st);
-  hipLaunchKernelGGL(k_mg_prolong, dim3(nblocks(cells(F))), dim3(NT), 0, st, C, F, m->uo[l - 1], m->u[l], 1);
+  hipLaunchKernelGGL(k_mg_correct, dim3(nblocks(cells(F))), dim3(NT), 0, st, C, F, m->u[l - 1], m->uo[l - 1],
+                     m->u[l]);
+}
+
+// The coarsest level: one workgroup when it is small, else launches.
+void coarse_solve(gmunu_mg *m, hipStream_t st) {
+  const MgGeo &G = m->geo[0];
+  if (cells(G) <= 64L * NT)
+    hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(NT), 0, st, G, m->u[0], m->f[0], m->a[0], m->d.coarse);
+  else
+    sweeps_raw(G, m->u[0], m->f[0], m->a[0], m->d.coarse, st);
 }
 
 void vcycle(gmunu_mg *m, int l, hipStream_t st) {
   if (l == 0) {
-    smooth(m->geo[0], m->u[0], m->f[0], m->a[0], m->d.coarse, st);
+    coarse_solve(m, st);
     return;
   }
-  smooth(m->geo[l], m->u[l], m->f[l], m->a[l], m->d.pre, st);
+  sweeps_raw(m->geo[l], m->u[l], m->f[l], m->a[l], m->d.pre, st);
   coarse_problem(m, l, st);
   vcycle(m, l - 1, st);
   correct(m, l, st);
-  smooth(m->geo[l], m->u[l], m->f[l], m->a[l], m->d.post, st);
+  sweeps_raw(m->geo[l], m->u[l], m->f[l], m->a[l], m->d.post, st);
 }
 
 void fmg(gmunu_mg *m, hipStream_t st) {
   const int top = m->levels - 1;
   for (int l = top; l > 0; l--) coarse_problem(m, l, st);
-  smooth(m->geo[0], m->u[0], m->f[0], m->a[0], m->d.coarse, st);
+  coarse_solve(m, st);
   for (int l = 1; l <= top; l++) {
     correct(m, l, st);
     vcycle(m, l, st);
@@ -585,7 +699,6 @@ void fmg(gmunu_mg *m, hipStream_t st) {
 int norm(gmunu_mg *m, double *out, hipStream_t st) {
   const int top = m->levels - 1;
   const MgGeo &G = m->geo[top];
-  ghosts(G, m->u[top], st);
   const long nb = nblocks(cells(G));
   const int np = (int)(nb < kNormParts ? nb : kNormParts);
   hipLaunchKernelGGL(k_mg_norm, dim3(np), dim3(NT), 0, st, G, m->u[top], m->f[top], m->a[top], m->part);
@@ -637,6 +750,10 @@ int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out) {
     return p;
   };
   m->br = nullptr;
+  m->gs = nullptr;
+  m->ev = nullptr;
+  m->vexec = nullptr;
+  m->gu = m->gf = m->ga = nullptr;
   bool ok = (m->tab = alloc(tab.size())) != nullptr && (m->part = alloc(kNormParts + 1)) != nullptr;
   for (int l = 0; l < levels && ok; l++) {
     const size_t nt = (size_t)m->geo[l].nt;
@@ -680,6 +797,9 @@ int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out) {
 int gmunu_mg_destroy(gmunu_mg *m) {
   if (!m) return GMUNU_ENULL;
   int rc = GMUNU_OK;
+  if (m->vexec && hipGraphExecDestroy(m->vexec) != hipSuccess) rc = GMUNU_EHIP;
+  if (m->ev && hipEventDestroy(m->ev) != hipSuccess) rc = GMUNU_EHIP;
+  if (m->gs && hipStreamDestroy(m->gs) != hipSuccess) rc = GMUNU_EHIP;
   for (double *p : m->owned)
     if (hipFree(p) != hipSuccess) rc = GMUNU_EHIP;
   delete m;
@@ -698,8 +818,34 @@ int gmunu_mg_solve(gmunu_mg *m, double *u, const double *f, const double *a, dou
   if (!m || !u || !f) return GMUNU_ENULL;
   if (!ok_ptr(u) || !ok_ptr(f) || (a && !aligned8(a))) return GMUNU_EALIGN;
   if (max_cycles < 0 || !(tol >= 0.0)) return GMUNU_EINVAL;
-  hipStream_t st = as_stream(stream);
+  // the cycles run on the context's stream, ordered after the caller's work
+  hipStream_t cst = as_stream(stream);
+  if (!m->gs && hipStreamCreateWithFlags(&m->gs, hipStreamNonBlocking) != hipSuccess) return GMUNU_EHIP;
+  if (!m->ev && hipEventCreateWithFlags(&m->ev, hipEventDisableTiming) != hipSuccess) return GMUNU_EHIP;
+  hipStream_t st = m->gs;
+  if (hipEventRecord(m->ev, cst) != hipSuccess || hipStreamWaitEvent(st, m->ev, 0) != hipSuccess) return GMUNU_EHIP;
   bind(m, u, f, a, st);
+  if (!m->vexec || m->gu != u || m->gf != f || m->ga != a) {
+    // capture one V-cycle over the arrays just bound (launches only: no
+    // memset, no host synchronisation inside)
+    if (m->vexec) {
+      (void)hipGraphExecDestroy(m->vexec);
+      m->vexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return GMUNU_EHIP;
+    vcycle(m, m->levels - 1, st);
+    if (hipStreamEndCapture(st, &g) != hipSuccess) return GMUNU_EHIP;
+    const bool ok = hipGraphInstantiate(&m->vexec, g, nullptr, nullptr, 0) == hipSuccess;
+    (void)hipGraphDestroy(g);
+    if (!ok) {
+      m->vexec = nullptr;
+      return GMUNU_EHIP;
+    }
+    m->gu = u;
+    m->gf = f;
+    m->ga = a;
+  }
   double r;
   int rc = norm(m, &r, st);
   if (rc) return rc;
@@ -708,14 +854,16 @@ int gmunu_mg_solve(gmunu_mg *m, double *u, const double *f, const double *a, dou
   while (c < max_cycles && r > tol) {
     if (c == 0 && use_fmg)
       fmg(m, st);
-    else
-      vcycle(m, m->levels - 1, st);
+    else if (hipGraphLaunch(m->vexec, st) != hipSuccess)
+      return GMUNU_EHIP;
     c++;
     rc = norm(m, &r, st);
     if (rc) return rc;
     if (res_host) res_host[c] = r;
   }
   if (cycles_out) *cycles_out = c;
+  ghosts(m->geo[m->levels - 1], u, st);
+  if (hipEventRecord(m->ev, st) != hipSuccess || hipStreamWaitEvent(cst, m->ev, 0) != hipSuccess) return GMUNU_EHIP;
   return launch_status();
 }
 
