@@ -54,7 +54,8 @@ typedef struct {
 typedef struct gmunu_mg gmunu_mg;
 
 /* Validate (each active n divisible by 2^(levels-1), at least 2 cells per
- * axis on the coarsest level, Robin only on axis 0 of curvilinear grids),
+ * axis on the coarsest level, Robin only on axis 0 of curvilinear grids,
+ * fewer than 2^31 entries per array),
  * build the level hierarchy on the current device and allocate its arrays
  * (5 arrays per coarse level, 2 on the finest).  Synchronous. */
 int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out);

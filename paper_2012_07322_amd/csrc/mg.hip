@@ -30,7 +30,7 @@ using namespace gm;
 namespace {
 
 constexpr int kMaxLevels = 16;
-constexpr int kNormParts = 1024;
+constexpr int kNormParts = 16384;
 
 // One level as the kernels see it.
 struct MgGeo {
@@ -109,10 +109,14 @@ __device__ __forceinline__ double mg_L(const MgGeo &G, const double *__restrict_
   return lap - mg_nl(G, av, uc);
 }
 
+// Interior cell number t (x fastest); 32-bit arithmetic (a level has fewer
+// than 2^32 cells, which validation ensures).
 __device__ __forceinline__ void mg_cell(const MgGeo &G, long t, int &i, int &j, int &k) {
-  i = (int)(t % G.n[0]);
-  j = (int)((t / G.n[0]) % G.n[1]);
-  k = (int)(t / ((long)G.n[0] * G.n[1]));
+  const unsigned u = (unsigned)t, n0 = (unsigned)G.n[0], n1 = (unsigned)G.n[1];
+  const unsigned r = u / n0;
+  i = (int)(u - r * n0);
+  k = (int)(r / n1);
+  j = (int)(r - (unsigned)k * n1);
 }
 
 __device__ __forceinline__ long mg_cells(const MgGeo &G) { return (long)G.n[0] * G.n[1] * G.n[2]; }
@@ -164,11 +168,11 @@ __global__ __launch_bounds__(NT) void k_mg_ghosts(const MgGeo G, double *u) {
 // that colour (every other cell of a row).
 __device__ __forceinline__ void mg_smooth_one(const MgGeo &G, double *u, const double *__restrict__ f,
                                               const double *__restrict__ a, int colour, long t) {
-  const int hrow = (G.n[0] + 1) >> 1;
-  const long row = t / hrow;
-  if (row >= (long)G.n[1] * G.n[2]) return;
-  const int j = (int)(row % G.n[1]), k = (int)(row / G.n[1]);
-  const int i = (int)(t % hrow) * 2 + ((j + k + colour) & 1);
+  const unsigned hrow = (unsigned)(G.n[0] + 1) >> 1, n1 = (unsigned)G.n[1];
+  if (t >= (long)hrow * G.n[1] * G.n[2]) return;
+  const unsigned row = (unsigned)t / hrow;
+  const int k = (int)(row / n1), j = (int)(row - (unsigned)k * n1);
+  const int i = (int)((unsigned)t - row * hrow) * 2 + ((j + k + colour) & 1);
   if (i >= G.n[0]) return;
   const long o = mg_off(G, i, j, k);
   double dg;
@@ -547,6 +551,8 @@ int validate(const gmunu_mg_desc &d, int levels) {
   if (d.coord == GMUNU_SPH && d.ndim > 1 && (d.xmin[1] < 0.0 || d.xmin[1] + d.n[1] * d.dx[1] > M_PI + 1e-12))
     return GMUNU_EINVAL;
   if (d.power < -1 || d.power > 1 || d.pre < 0 || d.post < 0 || d.coarse < 1) return GMUNU_EINVAL;
+  // cell numbers of a level fit 32-bit kernel arithmetic
+  if ((double)(d.n[0] + 2) * (d.n[1] + 2) * (d.n[2] + 2) >= 2147483647.0) return GMUNU_EINVAL;
   return GMUNU_OK;
 }
 
