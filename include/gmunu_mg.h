@@ -57,7 +57,7 @@ typedef struct gmunu_mg gmunu_mg;
  * axis on the coarsest level, Robin only on axis 0 of curvilinear grids,
  * fewer than 2^31 entries per array),
  * build the level hierarchy on the current device and allocate its arrays
- * (5 arrays per coarse level, 2 on the finest).  Synchronous. */
+ * (5 arrays per coarse level, 1 on the finest).  Synchronous. */
 int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out);
 int gmunu_mg_destroy(gmunu_mg *mg);
 /* Levels actually used. */

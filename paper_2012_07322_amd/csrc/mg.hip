@@ -761,19 +761,24 @@ int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out) {
   m->vexec = nullptr;
   m->gu = m->gf = m->ga = nullptr;
   bool ok = (m->tab = alloc(tab.size())) != nullptr && (m->part = alloc(kNormParts + 1)) != nullptr;
+  // coarse levels: u, f, a, r (restricted residual) and uo (restricted u);
+  // the finest level only uo (the cleaning's divergence when the caller
+  // passes none)
   for (int l = 0; l < levels && ok; l++) {
     const size_t nt = (size_t)m->geo[l].nt;
-    ok = (m->r[l] = alloc(nt)) && (m->uo[l] = alloc(nt));
-    if (ok && l < levels - 1) ok = (m->u[l] = alloc(nt)) && (m->f[l] = alloc(nt)) && (m->aown[l] = alloc(nt));
+    ok = (m->uo[l] = alloc(nt)) != nullptr;
+    m->r[l] = nullptr;
+    if (ok && l < levels - 1)
+      ok = (m->r[l] = alloc(nt)) && (m->u[l] = alloc(nt)) && (m->f[l] = alloc(nt)) && (m->aown[l] = alloc(nt));
   }
   ok = ok && hipMemcpy(m->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
   // zero every owned level array (ghosts of coarse arrays are then defined)
   for (int l = 0; l < levels && ok; l++) {
     const size_t b = (size_t)m->geo[l].nt * sizeof(double);
-    ok = hipMemset(m->r[l], 0, b) == hipSuccess && hipMemset(m->uo[l], 0, b) == hipSuccess;
+    ok = hipMemset(m->uo[l], 0, b) == hipSuccess;
     if (ok && l < levels - 1)
-      ok = hipMemset(m->u[l], 0, b) == hipSuccess && hipMemset(m->f[l], 0, b) == hipSuccess &&
-           hipMemset(m->aown[l], 0, b) == hipSuccess;
+      ok = hipMemset(m->r[l], 0, b) == hipSuccess && hipMemset(m->u[l], 0, b) == hipSuccess &&
+           hipMemset(m->f[l], 0, b) == hipSuccess && hipMemset(m->aown[l], 0, b) == hipSuccess;
   }
   ok = ok && hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
