@@ -31,12 +31,17 @@ STAGE_SOURCES = ("paper_2012_07322_amd/csrc/gmunu.hip", "paper_2012_07322_amd/cs
 
 
 def stage_source_hash():
-    """SHA-256 over the sources the single-grid stage kernel is built from."""
+    """SHA-256 over the code (comments and blank space removed) of the
+    sources the single-grid stage kernel is built from."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in STAGE_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        txt = open(os.path.join(ROOT, f)).read()
+        txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", " ", txt)
+        h.update(" ".join(txt.split()).encode())
     return h.hexdigest()
 
 

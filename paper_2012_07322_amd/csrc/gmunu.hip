@@ -5,7 +5,8 @@
 //   k_stage   per tile of cells (8x5x5 in 3D, 16x15 in 2D, 255 in 1D, so
 //             that each direction's faces fit one per thread): per direction
 //             the tile's stencil region of prim and metric is staged in LDS,
-//             each face is reconstructed (MC) and its HLLE flux computed once,
+//             each face is reconstructed (MC, MP5 or PPM) and its HLLE or
+//             TVDLF flux (optionally positivity-limited) computed once,
 //             fluxes are exchanged through LDS into the flux-area divergence;
 //             then gravitational + geometric sources and the RK combination;
 //   k_c2p     per interior cell: primitive recovery with error handling;

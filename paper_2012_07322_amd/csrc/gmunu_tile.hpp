@@ -1,8 +1,10 @@
 // Tile-level device routines shared by the single-grid and batched kernels:
-// face fluxes (MC + HLLE), sources, the fused stage on one tile, and the
-// per-cell recovery, ghost fill and CFL rate.  Cheong et al., "Gmunu"
+// face fluxes (MC, MP5 or PPM reconstruction; HLLE or TVDLF; the
+// positivity-preserving limiter), sources, the fused stage on one tile, and
+// the per-cell recovery, ghost fill and CFL rate.  Cheong et al., "Gmunu"
 // (arXiv 2012.07322): section 2.1 (fluxes, sources, update), section 2.3,
-// section 2.5, section 2.9, Appendix A.
+// section 2.4, section 2.5, section 2.9, section 3 (solver settings),
+// Appendix A.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -46,11 +48,11 @@ __device__ __forceinline__ double pp_side(double u, double w, double fho, double
 
 // Face flux times face factor through the lower face (along D) of cell
 // (i,j,k): reconstruction REC from the cells across the face (MC from four
-// cells, halo H = 2; MP5 or PPM from six, H = 3), metric as the mean of the two adjacent
-// centres, HLLE (R = 0) or TVDLF (R = 1).  The stencil comes from the
-// workgroup's staged region S (RC cells per variable, prim variables 0-7,
-// metric 8-12): r0 is the region index of the cell H below the face, rs the
-// region stride along D.
+// cells, halo H = 2; MP5 or PPM from six, H = 3), metric as the mean of the
+// two adjacent centres, HLLE (R = 0) or TVDLF (R = 1).  The stencil comes
+// from the workgroup's staged region S (RC cells per variable, prim
+// variables 0-7, metric 8-12): r0 is the region index of the cell H below
+// the face, rs the region stride along D.
 //
 // P = 1 applies the positivity-preserving limiter (section 2.4): the flux is
 // blended with the first-order Lax-Friedrichs flux of the two adjacent cell
@@ -341,7 +343,7 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
 }
 
 // Staged region of the face pass along D of a TX x TY x TZ tile: the tile's
-// cells plus H on each side along D (H = 2 for MC, 3 for MP5).
+// cells plus H on each side along D (H = 2 for MC, 3 for MP5 and PPM).
 template <int TX, int TY, int TZ, int D, int H>
 constexpr int region_cells() {
   return (TX + 2 * H * (D == 0)) * (TY + 2 * H * (D == 1)) * (TZ + 2 * H * (D == 2));
