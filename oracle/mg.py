@@ -5,8 +5,11 @@ smoke check and the benchmark's CPU-baseline leg use it.  A problem is a
 dict: ndim, coord (0 Cartesian, 1 cylindrical, 2 spherical), n, xmin, dx,
 bc (per axis a pair of 0 Dirichlet, 1 Neumann, 2 periodic, 3 Robin
 d(r u)/dr = 0), levels (0: as many as the grid allows down to two cells on
-the shortest axis), pre, post, coarse (sweeps), power p and offset c of
-L(u) = Lap(u) - a (u + c)^p.  Arrays are numpy float64 with one ghost layer
+the shortest axis), pre, post, coarse (sweeps), power p, offset c and
+power2 q of L(u) = Lap(u) - a (u + c)^p - a2 (u + c)^q (a, a2 optional
+arrays).  The vector operator Lap X^i + (1/3) d_i d_j X^j of the xCFC shift
+and vector-potential equations (Cartesian grids) has its own calls
+(vapply, vsmooth, vsolve).  Arrays are numpy float64 with one ghost layer
 on each active axis, shape (n2 + 2 g2, n1 + 2 g1, n0 + 2 g0); vector fields
 have a leading axis of 3.
 """
@@ -42,7 +45,7 @@ class _Desc(ctypes.Structure):
         ("ndim", ctypes.c_int), ("coord", ctypes.c_int), ("n", ctypes.c_int * 3),
         ("xmin", ctypes.c_double * 3), ("dx", ctypes.c_double * 3), ("bc", (ctypes.c_int * 2) * 3),
         ("levels", ctypes.c_int), ("pre", ctypes.c_int), ("post", ctypes.c_int), ("coarse", ctypes.c_int),
-        ("power", ctypes.c_int), ("offset", ctypes.c_double),
+        ("power", ctypes.c_int), ("offset", ctypes.c_double), ("power2", ctypes.c_int),
     ]
 
 
@@ -57,13 +60,19 @@ def lib():
         L = ctypes.CDLL(_LIB)
         P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         L.om_desc_size.restype = I
-        L.om_apply.argtypes = [P, P, P, P]
+        L.om_apply.argtypes = [P, P, P, P, P]
         L.om_fill_ghosts.argtypes = [P, I, P]
-        L.om_smooth.argtypes = [P, P, P, P, I]
+        L.om_smooth.argtypes = [P, P, P, P, P, I]
         L.om_restrict.argtypes = [P, I, P, P]
         L.om_prolong.argtypes = [P, I, P, P]
-        L.om_solve.argtypes = [P, P, P, P, D, I, I, P]
+        L.om_solve.argtypes = [P, P, P, P, P, D, I, I, P]
         L.om_solve.restype = I
+        L.om_vapply.argtypes = [P, P, P]
+        L.om_vsmooth.argtypes = [P, P, P, I]
+        L.om_vsolve.argtypes = [P, P, P, D, I, I, P]
+        L.om_vsolve.restype = I
+        L.om_xcfc_aij.argtypes = [P, P, P, P]
+        L.om_xcfc_beta_rhs.argtypes = [P, P, P, P, P]
         L.om_divergence.argtypes = [P, P, P]
         L.om_subtract_gradient.argtypes = [P, P, P]
         if L.om_desc_size() != ctypes.sizeof(_Desc):
@@ -72,7 +81,7 @@ def lib():
     return _lib
 
 
-DEFAULTS = dict(levels=0, pre=2, post=2, coarse=50, power=0, offset=0.0)
+DEFAULTS = dict(levels=0, pre=2, post=2, coarse=50, power=0, offset=0.0, power2=0)
 
 
 def max_levels(p):
@@ -96,6 +105,7 @@ def make_desc(p):
     d.levels = int(q["levels"]) or max_levels(q)
     d.pre, d.post, d.coarse, d.power = int(q["pre"]), int(q["post"]), int(q["coarse"]), int(q["power"])
     d.offset = float(q["offset"])
+    d.power2 = int(q["power2"])
     for a in range(d.ndim):
         if d.n[a] % (1 << (d.levels - 1)):
             raise ValueError("grid not divisible for the requested levels")
@@ -120,12 +130,16 @@ def _c(a):
     return a
 
 
-def apply(p, u, a=None):
+def _o(a):
+    return _p(_c(a)) if a is not None else None
+
+
+def apply(p, u, a=None, a2=None):
     """L(u) on the interior of the finest level; u's ghosts are used as given
     (fill_ghosts applies the boundary conditions)."""
     d = make_desc(p)
     out = np.zeros_like(u)
-    lib().om_apply(ctypes.byref(d), _p(_c(u)), _p(_c(a)) if a is not None else None, _p(out))
+    lib().om_apply(ctypes.byref(d), _p(_c(u)), _o(a), _o(a2), _p(out))
     return out
 
 
@@ -135,9 +149,9 @@ def fill_ghosts(p, u, level=None):
     return u
 
 
-def smooth(p, u, f, a=None, sweeps=1):
+def smooth(p, u, f, a=None, sweeps=1, a2=None):
     d = make_desc(p)
-    lib().om_smooth(ctypes.byref(d), _p(_c(u)), _p(_c(f)), _p(_c(a)) if a is not None else None, sweeps)
+    lib().om_smooth(ctypes.byref(d), _p(_c(u)), _p(_c(f)), _o(a), _o(a2), sweeps)
     return u
 
 
@@ -156,13 +170,58 @@ def prolong(p, level, coarse):
     return out
 
 
-def solve(p, u, f, a=None, tol=1e-12, max_cycles=30, fmg=True):
+def solve(p, u, f, a=None, tol=1e-12, max_cycles=30, fmg=True, a2=None):
     """Solve in place; returns the residual history (max norms)."""
     d = make_desc(p)
     res = np.zeros(max_cycles + 1)
-    c = lib().om_solve(ctypes.byref(d), _p(_c(u)), _p(_c(f)), _p(_c(a)) if a is not None else None, tol,
-                       max_cycles, 1 if fmg else 0, _p(res))
+    c = lib().om_solve(ctypes.byref(d), _p(_c(u)), _p(_c(f)), _o(a), _o(a2), tol, max_cycles, 1 if fmg else 0,
+                       _p(res))
     return res[:c + 1]
+
+
+def _cart(d):
+    if d.coord != CART:
+        raise ValueError("the vector operator is for Cartesian grids")
+    return d
+
+
+def vapply(p, X):
+    """Lap X^i + (1/3) d_i d_j X^j on the interior (X: shape (3, ...), ghosts
+    ignored: values across the boundary come from the boundary rule)."""
+    d = _cart(make_desc(p))
+    out = np.zeros_like(X)
+    lib().om_vapply(ctypes.byref(d), _p(_c(X)), _p(out))
+    return out
+
+
+def vsmooth(p, X, f, sweeps=1):
+    d = _cart(make_desc(p))
+    lib().om_vsmooth(ctypes.byref(d), _p(_c(X)), _p(_c(f)), sweeps)
+    return X
+
+
+def vsolve(p, X, f, tol=1e-12, max_cycles=30, fmg=True):
+    d = _cart(make_desc(p))
+    res = np.zeros(max_cycles + 1)
+    c = lib().om_vsolve(ctypes.byref(d), _p(_c(X)), _p(_c(f)), tol, max_cycles, 1 if fmg else 0, _p(res))
+    return res[:c + 1]
+
+
+def xcfc_aij(p, X):
+    """A~^ij from X (six components xx, yy, zz, xy, xz, yz) and A~_ij A~^ij."""
+    d = _cart(make_desc(p))
+    A6 = np.zeros((6,) + X.shape[1:])
+    a2 = np.zeros(X.shape[1:])
+    lib().om_xcfc_aij(ctypes.byref(d), _p(_c(X)), _p(A6), _p(a2))
+    return A6, a2
+
+
+def xcfc_beta_rhs(p, w, S, A6):
+    """16 pi w S_i + 2 A~^ij d_j w on the interior (w's ghosts as given)."""
+    d = _cart(make_desc(p))
+    out = np.zeros_like(S)
+    lib().om_xcfc_beta_rhs(ctypes.byref(d), _p(_c(w)), _p(_c(S)), _p(_c(A6)), _p(out))
+    return out
 
 
 def divergence(p, q):

@@ -5,9 +5,11 @@
  * Cheong et al., "Gmunu" (arXiv 2012.07322), section 2.7 (non-linear
  * cell-centred multigrid) and section 2.2 (elliptic divergence cleaning).
  * Plain C, FP64, one cell at a time, in the order the paper describes:
- *   - the equation L(u) = f with L(u) = Lap(u) - a (u + c)^p, p in {-1, 0, 1}
- *     (the scalar metric equations of section 2.6 in deviation form and the
- *     Poisson equation of the divergence cleaning are all of this form);
+ *   - the equation L(u) = f with L(u) = Lap(u) - a (u + c)^p - a2 (u + c)^q,
+ *     p in {-1, 0, 1}, q an integer (the scalar metric equations of section
+ *     2.6 in deviation form, with q = -7 for the extrinsic-curvature term of
+ *     the conformal-factor equation, and the Poisson equation of the
+ *     divergence cleaning are all of this form);
  *   - Lap: the standard 3/5/7-point second-order Laplacian of the reference
  *     metric in Cartesian, cylindrical (R, z, phi) or spherical
  *     (r, theta, phi) coordinates, exactly as the paper writes it (with the
@@ -15,7 +17,8 @@
  *   - smoother: Newton-Gauss-Seidel in red-black ordering (cells with
  *     i + j + k even first);
  *   - coarsest level: the same relaxation, repeated, as the solver;
- *   - restriction: piecewise constant (mean of the 2^ndim children);
+ *   - restriction: piecewise constant (weighted mean of the 2^ndim
+ *     children);
  *   - prolongation: Kwak's scheme (2D: (2 u_c + u_x + u_y) / 4 toward the
  *     child's side), generalised to 1D as (3 u_c + u_x) / 4 and to 3D as
  *     (u_c + u_x + u_y + u_z) / 4, the weights that keep the scheme's
@@ -31,15 +34,19 @@
  *     face the Robin condition d(r u)/dr = 0 of section 2.6 (ghost value
  *     u_in r_in / r_ghost, exact for a 1/r fall-off); faces of zero area
  *     (r = 0, R = 0, theta = 0 or pi) need none;
- *   - restriction is an unweighted mean of the children in every
- *     coordinate system (the paper gives the piecewise constant stencil
- *     only).
+ *   - restriction is the volume-weighted mean of the children (the paper
+ *     gives the piecewise constant stencil only; weighting by the cell
+ *     volumes of the reference metric keeps the coarse problem consistent
+ *     next to r = 0 and R = 0, and reduces to the plain mean on Cartesian
+ *     grids).
  *
  * Arrays: one ghost layer on each active axis, layout [k][j][i], i fastest.
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+
+#define OM_PI 3.14159265358979323846
 
 enum { OM_CART = 0, OM_CYL = 1, OM_SPH = 2 };
 enum { OM_DIRICHLET = 0, OM_NEUMANN = 1, OM_PERIODIC = 2, OM_ROBIN = 3 };
@@ -55,6 +62,7 @@ typedef struct {
   int coarse;        /* sweeps on the coarsest level */
   int power;         /* p */
   double offset;     /* c */
+  int power2;        /* q of the optional second term a2 (u + c)^q */
 } om_desc;
 
 /* one level of the hierarchy */
@@ -114,20 +122,31 @@ static void weights(const om_desc *d, const lvl *L, int a, int i, int j, int k, 
   }
 }
 
-static double nonlin(const om_desc *d, double a, double u) {
-  if (d->power == 0) return a;
-  if (d->power == 1) return a * (u + d->offset);
-  return a / (u + d->offset);
+static double ipow(double w, int q) {
+  double r = 1.0;
+  for (int e = q < 0 ? -q : q; e > 0; e--) r *= w;
+  return q < 0 ? 1.0 / r : r;
 }
-static double nonlin_du(const om_desc *d, double a, double u) {
-  if (d->power == 0) return 0.0;
-  if (d->power == 1) return a;
-  return -a / ((u + d->offset) * (u + d->offset));
+
+/* a (u + c)^p + a2 (u + c)^q and its derivative in u */
+static double nonlin(const om_desc *d, double a, double a2, double u) {
+  double w = u + d->offset, t;
+  if (d->power == 0) t = a;
+  else if (d->power == 1) t = a * w;
+  else t = a / w;
+  return a2 != 0.0 ? t + a2 * ipow(w, d->power2) : t;
+}
+static double nonlin_du(const om_desc *d, double a, double a2, double u) {
+  double w = u + d->offset, t;
+  if (d->power == 0) t = 0.0;
+  else if (d->power == 1) t = a;
+  else t = -a / (w * w);
+  return a2 != 0.0 ? t + a2 * d->power2 * ipow(w, d->power2 - 1) : t;
 }
 
 /* L(u) at interior cell (i,j,k) and its derivative with respect to u there. */
-static double apply_cell(const om_desc *d, const lvl *L, const double *u, const double *ac, int i, int j, int k,
-                         double *diag) {
+static double apply_cell(const om_desc *d, const lvl *L, const double *u, const double *ac, const double *a2c,
+                         int i, int j, int k, double *diag) {
   long c = idx(d, L, i, j, k);
   double lap = 0.0, dg = 0.0;
   int cell[3] = {i, j, k};
@@ -141,9 +160,9 @@ static double apply_cell(const om_desc *d, const lvl *L, const double *u, const 
     lap += wp * (up - u[c]) - wm * (u[c] - um);
     dg -= wp + wm;
   }
-  double av = ac ? ac[c] : 0.0;
-  if (diag) *diag = dg - nonlin_du(d, av, u[c]);
-  return lap - nonlin(d, av, u[c]);
+  double av = ac ? ac[c] : 0.0, a2v = a2c ? a2c[c] : 0.0;
+  if (diag) *diag = dg - nonlin_du(d, av, a2v, u[c]);
+  return lap - nonlin(d, av, a2v, u[c]);
 }
 
 /* Ghost values of u on level L from its boundary conditions (face-adjacent
@@ -181,7 +200,8 @@ static void fill_ghosts(const om_desc *d, const lvl *L, double *u) {
 
 /* Red-black Newton-Gauss-Seidel: colour 0 (i + j + k even), then colour 1,
  * ghosts refreshed before each colour. */
-static void smooth(const om_desc *d, const lvl *L, double *u, const double *f, const double *ac, int sweeps) {
+static void smooth(const om_desc *d, const lvl *L, double *u, const double *f, const double *ac, const double *a2c,
+                   int sweeps) {
   for (int s = 0; s < sweeps; s++)
     for (int col = 0; col < 2; col++) {
       fill_ghosts(d, L, u);
@@ -190,7 +210,7 @@ static void smooth(const om_desc *d, const lvl *L, double *u, const double *f, c
           for (int i = 0; i < L->n[0]; i++) {
             if (((i + j + k) & 1) != col) continue;
             double dg;
-            double Lu = apply_cell(d, L, u, ac, i, j, k, &dg);
+            double Lu = apply_cell(d, L, u, ac, a2c, i, j, k, &dg);
             long c = idx(d, L, i, j, k);
             u[c] -= (Lu - f[c]) / dg;
           }
@@ -199,12 +219,13 @@ static void smooth(const om_desc *d, const lvl *L, double *u, const double *f, c
 }
 
 /* r = f - L(u) on the interior (u's ghosts must be current). */
-static void residual(const om_desc *d, const lvl *L, const double *u, const double *f, const double *ac, double *r) {
+static void residual(const om_desc *d, const lvl *L, const double *u, const double *f, const double *ac,
+                     const double *a2c, double *r) {
   for (int k = 0; k < L->n[2]; k++)
     for (int j = 0; j < L->n[1]; j++)
       for (int i = 0; i < L->n[0]; i++) {
         long c = idx(d, L, i, j, k);
-        r[c] = f[c] - apply_cell(d, L, u, ac, i, j, k, NULL);
+        r[c] = f[c] - apply_cell(d, L, u, ac, a2c, i, j, k, NULL);
       }
 }
 
@@ -264,10 +285,11 @@ static void prolong(const om_desc *d, const lvl *C, const lvl *F, const double *
 
 typedef struct {
   lvl L[16];
-  double *u[16], *f[16], *a[16], *r[16], *uo[16];
+  double *u[16], *f[16], *a[16], *a2[16], *r[16], *uo[16];
 } hier;
 
-static void hier_init(const om_desc *d, hier *H, double *u_fine, const double *f_fine, const double *a_fine) {
+static void hier_init(const om_desc *d, hier *H, double *u_fine, const double *f_fine, const double *a_fine,
+                      const double *a2_fine) {
   int top = d->levels - 1;
   for (int l = 0; l < d->levels; l++) {
     H->L[l] = level_of(d, l);
@@ -278,14 +300,18 @@ static void hier_init(const om_desc *d, hier *H, double *u_fine, const double *f
       H->u[l] = u_fine;
       H->f[l] = (double *)f_fine;
       H->a[l] = (double *)a_fine;
+      H->a2[l] = (double *)a2_fine;
     } else {
       H->u[l] = (double *)calloc(nt, sizeof(double));
       H->f[l] = (double *)calloc(nt, sizeof(double));
       H->a[l] = a_fine ? (double *)calloc(nt, sizeof(double)) : NULL;
+      H->a2[l] = a2_fine ? (double *)calloc(nt, sizeof(double)) : NULL;
     }
   }
-  for (int l = top; l > 0; l--)
+  for (int l = top; l > 0; l--) {
     if (a_fine) restrict_pc(d, &H->L[l - 1], &H->L[l], H->a[l], H->a[l - 1]);
+    if (a2_fine) restrict_pc(d, &H->L[l - 1], &H->L[l], H->a2[l], H->a2[l - 1]);
+  }
 }
 
 static void hier_free(const om_desc *d, hier *H) {
@@ -297,6 +323,7 @@ static void hier_free(const om_desc *d, hier *H) {
       free(H->u[l]);
       free(H->f[l]);
       free(H->a[l]);
+      free(H->a2[l]);
     }
   }
 }
@@ -306,7 +333,7 @@ static void hier_free(const om_desc *d, hier *H) {
 static void coarse_problem(const om_desc *d, hier *H, int l) {
   const lvl *F = &H->L[l], *C = &H->L[l - 1];
   fill_ghosts(d, F, H->u[l]);
-  residual(d, F, H->u[l], H->f[l], H->a[l], H->r[l]);
+  residual(d, F, H->u[l], H->f[l], H->a[l], H->a2[l], H->r[l]);
   restrict_pc(d, C, F, H->u[l], H->u[l - 1]);
   restrict_pc(d, C, F, H->r[l], H->r[l - 1]);
   fill_ghosts(d, C, H->u[l - 1]);
@@ -315,7 +342,7 @@ static void coarse_problem(const om_desc *d, hier *H, int l) {
     for (int j = 0; j < C->n[1]; j++)
       for (int i = 0; i < C->n[0]; i++) {
         long c = idx(d, C, i, j, k);
-        H->f[l - 1][c] = apply_cell(d, C, H->u[l - 1], H->a[l - 1], i, j, k, NULL) + H->r[l - 1][c];
+        H->f[l - 1][c] = apply_cell(d, C, H->u[l - 1], H->a[l - 1], H->a2[l - 1], i, j, k, NULL) + H->r[l - 1][c];
       }
 }
 
@@ -329,14 +356,14 @@ static void correct(const om_desc *d, hier *H, int l) {
 
 static void vcycle(const om_desc *d, hier *H, int l) {
   if (l == 0) {
-    smooth(d, &H->L[0], H->u[0], H->f[0], H->a[0], d->coarse);
+    smooth(d, &H->L[0], H->u[0], H->f[0], H->a[0], H->a2[0], d->coarse);
     return;
   }
-  smooth(d, &H->L[l], H->u[l], H->f[l], H->a[l], d->pre);
+  smooth(d, &H->L[l], H->u[l], H->f[l], H->a[l], H->a2[l], d->pre);
   coarse_problem(d, H, l);
   vcycle(d, H, l - 1);
   correct(d, H, l);
-  smooth(d, &H->L[l], H->u[l], H->f[l], H->a[l], d->post);
+  smooth(d, &H->L[l], H->u[l], H->f[l], H->a[l], H->a2[l], d->post);
 }
 
 /* FAS full multigrid from the current solution: coarse problems down to
@@ -345,7 +372,7 @@ static void vcycle(const om_desc *d, hier *H, int l) {
 static void fmg(const om_desc *d, hier *H) {
   int top = d->levels - 1;
   for (int l = top; l > 0; l--) coarse_problem(d, H, l);
-  smooth(d, &H->L[0], H->u[0], H->f[0], H->a[0], d->coarse);
+  smooth(d, &H->L[0], H->u[0], H->f[0], H->a[0], H->a2[0], d->coarse);
   for (int l = 1; l <= top; l++) {
     correct(d, H, l);
     vcycle(d, H, l);
@@ -356,7 +383,7 @@ static double max_residual(const om_desc *d, hier *H) {
   int top = d->levels - 1;
   const lvl *L = &H->L[top];
   fill_ghosts(d, L, H->u[top]);
-  residual(d, L, H->u[top], H->f[top], H->a[top], H->r[top]);
+  residual(d, L, H->u[top], H->f[top], H->a[top], H->a2[top], H->r[top]);
   double m = 0.0;
   for (int k = 0; k < L->n[2]; k++)
     for (int j = 0; j < L->n[1]; j++)
@@ -369,13 +396,13 @@ static double max_residual(const om_desc *d, hier *H) {
 int om_desc_size(void) { return (int)sizeof(om_desc); }
 
 /* L(u) on the finest level's interior; u's ghosts as the caller set them. */
-void om_apply(const om_desc *d, const double *u, const double *a, double *out) {
+void om_apply(const om_desc *d, const double *u, const double *a, const double *a2, double *out) {
   lvl L = level_of(d, d->levels - 1);
   for (int k = 0; k < L.n[2]; k++)
     for (int j = 0; j < L.n[1]; j++)
       for (int i = 0; i < L.n[0]; i++) {
         long c = idx(d, &L, i, j, k);
-        out[c] = apply_cell(d, &L, u, a, i, j, k, NULL);
+        out[c] = apply_cell(d, &L, u, a, a2, i, j, k, NULL);
       }
 }
 
@@ -384,9 +411,9 @@ void om_fill_ghosts(const om_desc *d, int level, double *u) {
   fill_ghosts(d, &L, u);
 }
 
-void om_smooth(const om_desc *d, double *u, const double *f, const double *a, int sweeps) {
+void om_smooth(const om_desc *d, double *u, const double *f, const double *a, const double *a2, int sweeps) {
   lvl L = level_of(d, d->levels - 1);
-  smooth(d, &L, u, f, a, sweeps);
+  smooth(d, &L, u, f, a, a2, sweeps);
 }
 
 /* fine level l, coarse level l - 1 */
@@ -406,10 +433,10 @@ void om_prolong(const om_desc *d, int l, const double *coarse, double *fine) {
  * set, then FAS V-cycles until max |f - L(u)| <= tol or max_cycles cycles
  * (the FMG cycle counts as one).  res[] (max_cycles + 1 entries) receives
  * the residual norm before and after each cycle.  Returns the cycles done. */
-int om_solve(const om_desc *d, double *u, const double *f, const double *a, double tol, int max_cycles, int use_fmg,
-             double *res) {
+int om_solve(const om_desc *d, double *u, const double *f, const double *a, const double *a2, double tol,
+             int max_cycles, int use_fmg, double *res) {
   hier H;
-  hier_init(d, &H, u, f, a);
+  hier_init(d, &H, u, f, a, a2);
   int top = d->levels - 1, c = 0;
   res[0] = max_residual(d, &H);
   while (c < max_cycles && res[c] > tol) {
@@ -477,6 +504,291 @@ void om_subtract_gradient(const om_desc *d, const double *u, double *q) {
           p[a]++;
           double g = (u[idx(d, &L, p[0], p[1], p[2])] - u[idx(d, &L, m[0], m[1], m[2])]) / (2.0 * L.dx[a]);
           q[a * L.nt + idx(d, &L, i, j, k)] -= gi[a] * g;
+        }
+      }
+}
+
+/* ------------------------------------------------------------------------
+ * Vector equations of the xCFC scheme (section 2.6) on Cartesian grids:
+ *     L(X)^i = Lap X^i + (1/3) d_i (d_j X^j) = f^i,
+ * second derivatives by the standard second-order differences, the mixed
+ * ones d_i d_j (i != j) by the four-point corner formula of section 2.7.
+ * Its stencil couples diagonal neighbours, which share a colour in the
+ * red-black ordering, so the Gauss-Seidel sweep here visits the 2^ndim
+ * colours (i mod 2, j mod 2, k mod 2) in turn (cells of one colour are
+ * never neighbours, so a sweep does not depend on the order within a
+ * colour).  Values across the boundary, edges and corners included, come
+ * from the boundary rule applied per axis (mirror, times -1 for Dirichlet,
+ * +1 for Neumann; periodic wrap).  Same level hierarchy, restriction,
+ * Kwak prolongation and FAS cycles as the scalar solver, per component.
+ * Vector arrays: three component arrays back to back. */
+
+static double vval(const om_desc *d, const lvl *L, const double *u, int i, int j, int k) {
+  int c[3] = {i, j, k};
+  double fac = 1.0;
+  for (int a = 0; a < d->ndim; a++) {
+    int n = L->n[a];
+    if (c[a] >= 0 && c[a] < n) continue;
+    int side = c[a] < 0 ? 0 : 1;
+    int kind = d->bc[a][side];
+    if (kind == OM_PERIODIC) {
+      c[a] = side == 0 ? c[a] + n : c[a] - n;
+      continue;
+    }
+    if (kind == OM_DIRICHLET) fac = -fac;
+    c[a] = side == 0 ? -1 - c[a] : 2 * n - 1 - c[a];
+  }
+  return fac * u[idx(d, L, c[0], c[1], c[2])];
+}
+
+static double vapply_cell(const om_desc *d, const lvl *L, const double *u, int comp, int i, int j, int k,
+                          double *diag) {
+  const long nt = L->nt;
+  const double *uc = u + comp * nt;
+  const double u0 = uc[idx(d, L, i, j, k)];
+  double lap = 0.0, dg = 0.0;
+  for (int a = 0; a < d->ndim; a++) {
+    int m[3] = {i, j, k}, p[3] = {i, j, k};
+    m[a]--;
+    p[a]++;
+    double h2 = L->dx[a] * L->dx[a];
+    lap += (vval(d, L, uc, p[0], p[1], p[2]) - 2.0 * u0 + vval(d, L, uc, m[0], m[1], m[2])) / h2;
+    dg -= 2.0 / h2;
+  }
+  double gd = 0.0;
+  if (comp < d->ndim) {
+    for (int b = 0; b < d->ndim; b++) {
+      const double *ub = u + b * nt;
+      if (b == comp) {
+        int m[3] = {i, j, k}, p[3] = {i, j, k};
+        m[b]--;
+        p[b]++;
+        double h2 = L->dx[b] * L->dx[b];
+        gd += (vval(d, L, ub, p[0], p[1], p[2]) - 2.0 * u0 + vval(d, L, ub, m[0], m[1], m[2])) / h2;
+        dg -= (2.0 / 3.0) / h2;
+      } else {
+        int pp[3] = {i, j, k}, pm[3] = {i, j, k}, mp[3] = {i, j, k}, mm[3] = {i, j, k};
+        pp[comp]++; pp[b]++;
+        pm[comp]++; pm[b]--;
+        mp[comp]--; mp[b]++;
+        mm[comp]--; mm[b]--;
+        gd += (vval(d, L, ub, pp[0], pp[1], pp[2]) - vval(d, L, ub, pm[0], pm[1], pm[2]) -
+               vval(d, L, ub, mp[0], mp[1], mp[2]) + vval(d, L, ub, mm[0], mm[1], mm[2])) /
+              (4.0 * L->dx[comp] * L->dx[b]);
+      }
+    }
+  }
+  if (diag) *diag = dg;
+  return lap + gd / 3.0;
+}
+
+static void vsmooth(const om_desc *d, const lvl *L, double *u, const double *f, int sweeps) {
+  const int ncol = 1 << d->ndim;
+  for (int s = 0; s < sweeps; s++)
+    for (int col = 0; col < ncol; col++)
+      for (int k = 0; k < L->n[2]; k++)
+        for (int j = 0; j < L->n[1]; j++)
+          for (int i = 0; i < L->n[0]; i++) {
+            int cc = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
+            if (cc != col) continue;
+            long c = idx(d, L, i, j, k);
+            for (int comp = 0; comp < 3; comp++) {
+              double dg;
+              double Lu = vapply_cell(d, L, u, comp, i, j, k, &dg);
+              u[comp * L->nt + c] -= (Lu - f[comp * L->nt + c]) / dg;
+            }
+          }
+}
+
+static void vresidual(const om_desc *d, const lvl *L, const double *u, const double *f, double *r) {
+  for (int k = 0; k < L->n[2]; k++)
+    for (int j = 0; j < L->n[1]; j++)
+      for (int i = 0; i < L->n[0]; i++) {
+        long c = idx(d, L, i, j, k);
+        for (int comp = 0; comp < 3; comp++)
+          r[comp * L->nt + c] = f[comp * L->nt + c] - vapply_cell(d, L, u, comp, i, j, k, NULL);
+      }
+}
+
+typedef struct {
+  lvl L[16];
+  double *u[16], *f[16], *r[16], *uo[16];
+} vhier;
+
+static void vhier_init(const om_desc *d, vhier *H, double *u, const double *f) {
+  int top = d->levels - 1;
+  for (int l = 0; l < d->levels; l++) {
+    H->L[l] = level_of(d, l);
+    long nt = 3 * H->L[l].nt;
+    H->r[l] = (double *)calloc(nt, sizeof(double));
+    H->uo[l] = (double *)calloc(nt, sizeof(double));
+    H->u[l] = l == top ? u : (double *)calloc(nt, sizeof(double));
+    H->f[l] = l == top ? (double *)f : (double *)calloc(nt, sizeof(double));
+  }
+}
+
+static void vhier_free(const om_desc *d, vhier *H) {
+  int top = d->levels - 1;
+  for (int l = 0; l < d->levels; l++) {
+    free(H->r[l]);
+    free(H->uo[l]);
+    if (l != top) {
+      free(H->u[l]);
+      free(H->f[l]);
+    }
+  }
+}
+
+static void vcoarse_problem(const om_desc *d, vhier *H, int l) {
+  const lvl *F = &H->L[l], *C = &H->L[l - 1];
+  vresidual(d, F, H->u[l], H->f[l], H->r[l]);
+  for (int comp = 0; comp < 3; comp++) {
+    restrict_pc(d, C, F, H->u[l] + comp * F->nt, H->u[l - 1] + comp * C->nt);
+    restrict_pc(d, C, F, H->r[l] + comp * F->nt, H->r[l - 1] + comp * C->nt);
+  }
+  memcpy(H->uo[l - 1], H->u[l - 1], sizeof(double) * 3 * C->nt);
+  for (int k = 0; k < C->n[2]; k++)
+    for (int j = 0; j < C->n[1]; j++)
+      for (int i = 0; i < C->n[0]; i++) {
+        long c = idx(d, C, i, j, k);
+        for (int comp = 0; comp < 3; comp++)
+          H->f[l - 1][comp * C->nt + c] = vapply_cell(d, C, H->u[l - 1], comp, i, j, k, NULL) +
+                                          H->r[l - 1][comp * C->nt + c];
+      }
+}
+
+static void vcorrect(const om_desc *d, vhier *H, int l) {
+  const lvl *C = &H->L[l - 1], *F = &H->L[l];
+  for (long c = 0; c < 3 * C->nt; c++) H->uo[l - 1][c] = H->u[l - 1][c] - H->uo[l - 1][c];
+  for (int comp = 0; comp < 3; comp++) {
+    fill_ghosts(d, C, H->uo[l - 1] + comp * C->nt);
+    prolong(d, C, F, H->uo[l - 1] + comp * C->nt, H->u[l] + comp * F->nt, 1);
+  }
+}
+
+static void vvcycle(const om_desc *d, vhier *H, int l) {
+  if (l == 0) {
+    vsmooth(d, &H->L[0], H->u[0], H->f[0], d->coarse);
+    return;
+  }
+  vsmooth(d, &H->L[l], H->u[l], H->f[l], d->pre);
+  vcoarse_problem(d, H, l);
+  vvcycle(d, H, l - 1);
+  vcorrect(d, H, l);
+  vsmooth(d, &H->L[l], H->u[l], H->f[l], d->post);
+}
+
+static void vfmg(const om_desc *d, vhier *H) {
+  int top = d->levels - 1;
+  for (int l = top; l > 0; l--) vcoarse_problem(d, H, l);
+  vsmooth(d, &H->L[0], H->u[0], H->f[0], d->coarse);
+  for (int l = 1; l <= top; l++) {
+    vcorrect(d, H, l);
+    vvcycle(d, H, l);
+  }
+}
+
+static double vmax_residual(const om_desc *d, vhier *H) {
+  int top = d->levels - 1;
+  const lvl *L = &H->L[top];
+  vresidual(d, L, H->u[top], H->f[top], H->r[top]);
+  double m = 0.0;
+  for (int comp = 0; comp < 3; comp++)
+    for (int k = 0; k < L->n[2]; k++)
+      for (int j = 0; j < L->n[1]; j++)
+        for (int i = 0; i < L->n[0]; i++) m = fmax(m, fabs(H->r[top][comp * L->nt + idx(d, L, i, j, k)]));
+  return m;
+}
+
+/* L(X) on the interior of the finest level (Cartesian). */
+void om_vapply(const om_desc *d, const double *u, double *out) {
+  lvl L = level_of(d, d->levels - 1);
+  for (int k = 0; k < L.n[2]; k++)
+    for (int j = 0; j < L.n[1]; j++)
+      for (int i = 0; i < L.n[0]; i++)
+        for (int comp = 0; comp < 3; comp++)
+          out[comp * L.nt + idx(d, &L, i, j, k)] = vapply_cell(d, &L, u, comp, i, j, k, NULL);
+}
+
+void om_vsmooth(const om_desc *d, double *u, const double *f, int sweeps) {
+  lvl L = level_of(d, d->levels - 1);
+  vsmooth(d, &L, u, f, sweeps);
+}
+
+/* Solve L(X) = f like om_solve; the ghost entries of X are left zero. */
+int om_vsolve(const om_desc *d, double *u, const double *f, double tol, int max_cycles, int use_fmg, double *res) {
+  vhier H;
+  vhier_init(d, &H, u, f);
+  int top = d->levels - 1, c = 0;
+  res[0] = vmax_residual(d, &H);
+  while (c < max_cycles && res[c] > tol) {
+    if (c == 0 && use_fmg)
+      vfmg(d, &H);
+    else
+      vvcycle(d, &H, top);
+    c++;
+    res[c] = vmax_residual(d, &H);
+  }
+  vhier_free(d, &H);
+  return c;
+}
+
+/* A~^ij = d_i X^j + d_j X^i - (2/3) delta^ij d_k X^k (section 2.6, Cartesian,
+ * centred first derivatives, boundary rule across the boundary) on the
+ * interior: the six components (xx, yy, zz, xy, xz, yz) into A6 and
+ * A~_ij A~^ij into a2. */
+void om_xcfc_aij(const om_desc *d, const double *X, double *A6, double *a2) {
+  lvl L = level_of(d, d->levels - 1);
+  for (int k = 0; k < L.n[2]; k++)
+    for (int j = 0; j < L.n[1]; j++)
+      for (int i = 0; i < L.n[0]; i++) {
+        double g[3][3];  /* g[a][b] = d_a X^b */
+        for (int a = 0; a < 3; a++)
+          for (int b = 0; b < 3; b++) {
+            g[a][b] = 0.0;
+            if (a >= d->ndim) continue;
+            int m[3] = {i, j, k}, p[3] = {i, j, k};
+            m[a]--;
+            p[a]++;
+            const double *xb = X + b * L.nt;
+            g[a][b] = (vval(d, &L, xb, p[0], p[1], p[2]) - vval(d, &L, xb, m[0], m[1], m[2])) / (2.0 * L.dx[a]);
+          }
+        double dv = g[0][0] + g[1][1] + g[2][2];
+        double A[3][3];
+        for (int a = 0; a < 3; a++)
+          for (int b = 0; b < 3; b++) A[a][b] = g[a][b] + g[b][a] - (a == b ? 2.0 / 3.0 * dv : 0.0);
+        long c = idx(d, &L, i, j, k);
+        const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+        for (int q = 0; q < 6; q++) A6[q * L.nt + c] = A[pa[q]][pb[q]];
+        double s = 0.0;
+        for (int a = 0; a < 3; a++)
+          for (int b = 0; b < 3; b++) s += A[a][b] * A[a][b];
+        a2[c] = s;
+      }
+}
+
+/* Right-hand side of the shift equation (section 2.6, Cartesian):
+ * 16 pi w S_i + 2 A~^ij d_j w with w = alpha psi^-6 (its ghosts set by the
+ * caller), S = psi^6 S_i the rescaled momentum density and A6 from
+ * om_xcfc_aij, on the interior. */
+void om_xcfc_beta_rhs(const om_desc *d, const double *w, const double *S, const double *A6, double *out) {
+  lvl L = level_of(d, d->levels - 1);
+  const int qi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+  for (int k = 0; k < L.n[2]; k++)
+    for (int j = 0; j < L.n[1]; j++)
+      for (int i = 0; i < L.n[0]; i++) {
+        long c = idx(d, &L, i, j, k);
+        double gw[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < d->ndim; a++) {
+          int m[3] = {i, j, k}, p[3] = {i, j, k};
+          m[a]--;
+          p[a]++;
+          gw[a] = (w[idx(d, &L, p[0], p[1], p[2])] - w[idx(d, &L, m[0], m[1], m[2])]) / (2.0 * L.dx[a]);
+        }
+        for (int a = 0; a < 3; a++) {
+          double t = 0.0;
+          for (int b = 0; b < 3; b++) t += A6[qi[a][b] * L.nt + c] * gw[b];
+          out[a * L.nt + c] = 16.0 * OM_PI * w[c] * S[a * L.nt + c] + 2.0 * t;
         }
       }
 }

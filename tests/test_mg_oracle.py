@@ -248,3 +248,210 @@ def test_cleaning_removes_a_gradient_and_keeps_a_curl():
     assert out[0][0] / out[1][0] > 3.5       # the gradient part is removed at second order
     assert out[1][2] < 0.05 * out[1][1]       # divergence reduced well below the initial one
     assert out[0][2] / out[1][2] > 3.5       # and what remains is a second-order truncation error
+
+
+# ----------------------------------------- xCFC vector and A^2 equations
+
+def test_vector_operator_exact_on_quadratics():
+    """Lap X^i + (1/3) d_i d_j X^j of quadratic X equals its exact value
+    (second differences and the four-point mixed difference are exact on
+    quadratics) away from the boundary layer: here (4 + 7/3, 4 + 8/3, 2/3)."""
+    p = prob(3, CART, (8, 6, 6), (0, 0, 0), (1, 1.5, 1), [[D, D]] * 3)
+    x, y, z = mg.centres(p)
+    X = np.ascontiguousarray(np.stack([x * x + 3 * x * y - y * z + z * z,
+                                       2 * y * y - x * z + x * y,
+                                       z * z + 4 * x * z - x * x + y * z]))
+    L = mg.vapply(p, X)
+    inner = (slice(2, -2),) * 3
+    for i, v in enumerate((4 + 7 / 3, 4 + 8 / 3, 2 / 3)):
+        np.testing.assert_allclose(L[i][inner], v, rtol=0, atol=1e-10)
+
+
+def test_vector_operator_discrete_symbol_on_periodic_modes():
+    """On a periodic box every cell, corners and edges across the wrap
+    included, gives the discrete symbol of the operator: a second
+    difference multiplies a mode by -4 sin^2(k h / 2) / h^2 and the
+    four-point mixed difference is the product of two centred first
+    differences (factor sin(k h) / h each)."""
+    p = prob(3, CART, (8, 12, 8), (0, 0, 0), (1, 1, 1), [[PER, PER]] * 3)
+    x, y, z = mg.centres(p)
+    hx, hy, hz = p["dx"][:3]
+    kx, ky, kz = 2 * math.pi, 4 * math.pi, 2 * math.pi
+    sx, sy, sz = (4 * math.sin(k * h / 2) ** 2 / h ** 2 for k, h in ((kx, hx), (ky, hy), (kz, hz)))
+    cx, cy, cz = (math.sin(k * h) / h for k, h in ((kx, hx), (ky, hy), (kz, hz)))
+    S, C = np.sin, np.cos
+    X0 = S(kx * x) * S(ky * y)
+    X1 = C(kx * x) * C(ky * y) * C(kz * z)
+    X2 = C(kx * x) * S(kz * z)
+    L0 = -(sx + sy) * X0 + (-sx * X0 + cx * cy * S(kx * x) * S(ky * y) * C(kz * z)
+                            - cx * cz * S(kx * x) * C(kz * z)) / 3
+    L1 = -(sx + sy + sz) * X1 + (cx * cy * C(kx * x) * C(ky * y) - sy * X1) / 3
+    L2 = -(sx + sz) * X2 + (cy * cz * C(kx * x) * S(ky * y) * S(kz * z) - sz * X2) / 3
+    L = mg.vapply(p, np.ascontiguousarray(np.stack([X0, X1, X2])))
+    for i, ex in enumerate((L0, L1, L2)):
+        np.testing.assert_allclose(mg.interior(p, L[i]), mg.interior(p, ex), rtol=0, atol=1e-9)
+
+
+def vector_operator_matrix(p):
+    shp = (3,) + mg.shape(p)
+    inner = np.stack([mg.interior(p, c) for c in np.arange(np.prod(shp)).reshape(shp)]).ravel()
+    cols = []
+    for k in inner:
+        e = np.zeros(np.prod(shp))
+        e[k] = 1.0
+        L = mg.vapply(p, np.ascontiguousarray(e.reshape(shp)))
+        cols.append(np.stack([mg.interior(p, c) for c in L]).ravel())
+    return sp.csc_matrix(np.array(cols).T)
+
+
+def test_vector_multigrid_reaches_the_discrete_solution():
+    """The four-colour Newton-Gauss-Seidel FAS cycles reach the exact
+    solution of the discrete vector system (direct sparse solve) on a 2D
+    grid with Dirichlet x faces and periodic y faces."""
+    p = prob(2, CART, (16, 16), (0, 0), (1, 1), [[D, D], [PER, PER]])
+    x, y, _ = mg.centres(p)
+    f = np.ascontiguousarray(np.stack([np.exp(-((x - 0.4) ** 2 + (y - 0.5) ** 2) * 20),
+                                       np.cos(2 * math.pi * y) * x * (1 - x), 0.3 + 0 * x]))
+    X = np.zeros((3,) + mg.shape(p))
+    res = mg.vsolve(p, X, f, tol=1e-12, max_cycles=60)
+    assert res[-1] <= 1e-12
+    ex = spla.spsolve(vector_operator_matrix(p), np.stack([mg.interior(p, c) for c in f]).ravel())
+    got = np.stack([mg.interior(p, c) for c in X]).ravel()
+    np.testing.assert_allclose(got, ex, rtol=0, atol=1e-10 * np.abs(ex).max())
+    assert (res[2:] / res[1:-1]).max() < 0.3
+
+
+def test_vector_equation_second_order_3d():
+    """X = phi (1, 2, -1), phi = sin(pi x) sin(pi y) sin(pi z) vanishing on
+    the faces of the unit box: L(X)^i = -3 pi^2 X^i + (1/3) d_i (sum_b c_b
+    d_b phi) in closed form; the multigrid solution converges to X at
+    second order and each V-cycle cuts the residual by > 4."""
+    errs = []
+    c = (1.0, 2.0, -1.0)
+    for n in (8, 16):
+        p = prob(3, CART, (n, n, n), (0, 0, 0), (1, 1, 1), [[D, D]] * 3)
+        x, y, z = mg.centres(p)
+        S, C, pi = np.sin, np.cos, math.pi
+        phi = S(pi * x) * S(pi * y) * S(pi * z)
+        # second derivatives d_i d_b phi
+        H = [[-pi * pi * phi, pi * pi * C(pi * x) * C(pi * y) * S(pi * z), pi * pi * C(pi * x) * S(pi * y) * C(pi * z)],
+             [None, -pi * pi * phi, pi * pi * S(pi * x) * C(pi * y) * C(pi * z)],
+             [None, None, -pi * pi * phi]]
+        for i in range(3):
+            for b in range(i):
+                H[i][b] = H[b][i]
+        f = np.ascontiguousarray(np.stack([-3 * pi * pi * c[i] * phi + sum(c[b] * H[i][b] for b in range(3)) / 3
+                                           for i in range(3)]))
+        X = np.zeros((3,) + mg.shape(p))
+        res = mg.vsolve(p, X, f, tol=1e-11, max_cycles=40)
+        assert res[-1] <= 1e-11
+        assert (res[2:] / res[1:-1]).max() < 0.25
+        errs.append(max(np.abs(mg.interior(p, X[i]) - c[i] * mg.interior(p, phi)).max() for i in range(3)))
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_xcfc_aij_of_a_linear_field():
+    """For X^b = sum_a M_ba x^a + const, A~^ab = M_ab + M_ba - (2/3) tr(M)
+    delta^ab exactly (centred differences), traceless, and A~_ij A~^ij is
+    the sum of its squares; six components in the order xx yy zz xy xz yz."""
+    p = prob(3, CART, (6, 6, 6), (0, 0, 0), (1, 1, 1), [[D, D]] * 3)
+    x, y, z = mg.centres(p)
+    M = np.array([[0.3, -1.0, 2.0], [0.5, 1.2, -0.7], [0.1, 0.4, -0.9]])
+    xs = (x, y, z)
+    X = np.ascontiguousarray(np.stack([sum(M[b, a] * xs[a] for a in range(3)) + b for b in range(3)]))
+    A6, a2 = mg.xcfc_aij(p, X)
+    A = M + M.T - 2.0 / 3.0 * np.trace(M) * np.eye(3)
+    inner = (slice(2, -2),) * 3
+    for q, (i, j) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+        np.testing.assert_allclose(A6[q][inner], A[i, j], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(A6[0][inner] + A6[1][inner] + A6[2][inner], 0.0, atol=1e-12)
+    np.testing.assert_allclose(a2[inner], (A * A).sum(), rtol=1e-13)
+
+
+def test_xcfc_shift_source_closed_form():
+    """16 pi w S_i + 2 A~^ij d_j w for w linear (exact centred gradient),
+    a uniform S and arbitrary symmetric A~ per cell."""
+    p = prob(3, CART, (6, 4, 4), (0, 0, 0), (1.5, 1, 1), [[D, D]] * 3)
+    x, y, z = mg.centres(p)
+    g = np.array([0.7, -0.2, 0.4])
+    w = np.ascontiguousarray(0.9 + g[0] * x + g[1] * y + g[2] * z)
+    S = np.ascontiguousarray(np.stack([0.1 + 0 * x, -0.3 + 0 * x, 0.05 + 0 * x]))
+    rng = np.random.default_rng(3)
+    A6 = np.ascontiguousarray(rng.standard_normal((6,) + x.shape))
+    full = [[0, 3, 4], [3, 1, 5], [4, 5, 2]]
+    out = mg.xcfc_beta_rhs(p, w, S, A6)
+    for i in range(3):
+        ex = 16 * math.pi * w * S[i] + 2 * sum(A6[full[i][j]] * g[j] for j in range(3))
+        np.testing.assert_allclose(mg.interior(p, out[i]), mg.interior(p, ex), rtol=1e-13, atol=1e-13)
+
+
+def test_conformal_factor_equation_with_the_aij_term():
+    """The conformal-factor equation with both source terms of section 2.6
+    in deviation form, Lap(d) = -2 pi U / (1 + d) - (1/8) A2 (1 + d)^-7
+    (p = -1, q = -7, c = 1): for a manufactured d (zero on the faces) the
+    multigrid solution converges to it at second order, so both non-linear
+    terms and their Newton derivatives enter with the right sign and power."""
+    errs = []
+    for n in (16, 32):
+        p = prob(2, CART, (n, n), (0, 0), (1, 1), [[D, D]] * 2, power=-1, power2=-7, offset=1.0)
+        x, y, _ = mg.centres(p)
+        pi = math.pi
+        d = 0.4 * np.sin(pi * x) * np.sin(pi * y)
+        U = 0.3 * (1 + x * y)
+        A2 = 2.0 + np.cos(3 * x) * np.sin(2 * y)
+        a = np.ascontiguousarray(-2 * pi * U)
+        a2 = np.ascontiguousarray(-A2 / 8)
+        f = np.ascontiguousarray(-2 * pi * pi * d - a / (1 + d) - a2 * (1 + d) ** -7)
+        u = np.zeros(mg.shape(p))
+        res = mg.solve(p, u, f, a, tol=1e-12, max_cycles=40, a2=a2)
+        assert res[-1] <= 1e-12
+        errs.append(np.abs(mg.interior(p, u) - mg.interior(p, d)).max())
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_vector_sweep_is_jacobi_within_each_of_four_colours():
+    """One vector smoothing sweep equals, colour by colour in the order
+    (i mod 2, j mod 2) = (0,0), (1,0), (0,1), (1,1), a simultaneous Newton
+    update of that colour's cells, X -= (L(X) - f) / diag, with the operator's
+    analytic diagonal -2 sum_a 1/h_a^2 - (2/3)/h_i^2 (component i active): the
+    mixed stencil couples diagonal neighbours, so two colours do not
+    suffice."""
+    p = prob(2, CART, (8, 6), (0, 0), (1, 1.5), [[PER, PER], [D, N]])
+    rng = np.random.default_rng(5)
+    shp = (3,) + mg.shape(p)
+    X = np.ascontiguousarray(rng.standard_normal(shp))
+    f = np.ascontiguousarray(rng.standard_normal(shp))
+    got = mg.vsmooth(p, X.copy(), f, sweeps=1)
+    h = p["dx"]
+    diag = [-2 * (1 / h[0] ** 2 + 1 / h[1] ** 2) - (2 / 3) / h[i] ** 2 if i < 2 else -2 * (1 / h[0] ** 2 + 1 / h[1] ** 2)
+            for i in range(3)]
+    ref = X.copy()
+    jj, ii = np.meshgrid(np.arange(shp[2]) - 1, np.arange(shp[3]) - 1, indexing="ij")
+    for col in range(4):
+        mask = ((ii % 2) == (col & 1)) & ((jj % 2) == (col >> 1))
+        mask[0, :] = mask[-1, :] = False
+        mask[:, 0] = mask[:, -1] = False
+        L = mg.vapply(p, np.ascontiguousarray(ref))
+        for i in range(3):
+            ref[i, 0][mask] -= (L[i, 0][mask] - f[i, 0][mask]) / diag[i]
+    for i in range(3):
+        np.testing.assert_allclose(mg.interior(p, got[i]), mg.interior(p, ref[i]), rtol=1e-12, atol=1e-12)
+
+
+def test_smoother_takes_a_newton_step_on_both_nonlinear_terms():
+    """With a negligible Laplacian (huge cells) each cell's equation is
+    -a (u+1)^-1 - a2 (u+1)^-7 = f, and one sweep is exactly one Newton step
+    on it, derivative a (u+1)^-2 + 7 a2 (u+1)^-8 included."""
+    p = prob(2, CART, (4, 4), (0, 0), (4e6, 4e6), [[N, N], [N, N]], power=-1, power2=-7, offset=1.0)
+    rng = np.random.default_rng(9)
+    shp = mg.shape(p)
+    u = np.ascontiguousarray(0.2 + 0.1 * rng.random(shp))
+    a = np.ascontiguousarray(-1.0 - rng.random(shp))
+    a2 = np.ascontiguousarray(-0.5 - rng.random(shp))
+    f = np.ascontiguousarray(rng.random(shp))
+    w = 1 + u
+    g = -a / w - a2 * w ** -7 - f
+    dg = a / w ** 2 + 7 * a2 * w ** -8
+    ex = u - g / dg
+    got = mg.smooth(p, u.copy(), f, a, sweeps=1, a2=a2)
+    np.testing.assert_allclose(mg.interior(p, got), mg.interior(p, ex), rtol=1e-9)
