@@ -16,6 +16,7 @@ have a leading axis of 3.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -254,3 +255,46 @@ def centres(p, level=None):
         ax.append(d.xmin[a] + (np.arange(-g, n + g) + 0.5) * h)
     x3, x2, x1 = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
     return x1, x2, x3
+
+
+def fluid_stilde(psi, rho, wv, p, gamma):
+    """S~ = psi^6 (rho h W^2 v^2 + 3 p) of an ideal-gas fluid on a Cartesian
+    grid (section 2.6): W^2 v^2 = psi^4 sum_i (W v^i)^2, rho h = rho +
+    gamma / (gamma - 1) p."""
+    rhoh = rho + gamma / (gamma - 1.0) * p
+    w2v2 = psi ** 4 * (wv[0] ** 2 + wv[1] ** 2 + wv[2] ** 2)
+    return psi ** 6 * (rhoh * w2v2 + 3.0 * p)
+
+
+def xcfc_solve(pv, ps, pa, U, S, stilde, X, u_psi, u_ap, beta, tol=1e-12, max_cycles=60):
+    """The xCFC metric solve of section 2.6 on a Cartesian grid, steps 1 to 6
+    in the paper's order, on multigrid-layout arrays:
+      1. L(X)^i = 8 pi S~_i                          (vector problem pv)
+      2. A~^ij from X, A2 = A~_ij A~^ij
+      3. Lap(psi - 1) = -2 pi U~ / psi - (1/8) A2 psi^-7
+                                 (ps: power -1, power2 -7, offset 1)
+      4. S~ = stilde(psi) with the new psi
+      5. Lap(alpha psi - 1) = (alpha psi) [2 pi (U~ + 2 S~) psi^-2
+                                           + (7/8) A2 psi^-8]  (pa: power 1, offset 1)
+      6. L(beta)^i = 16 pi w S~_i + 2 A~^ij d_j w,  w = alpha psi^-6
+    U: U~; S: S~_i (shape (3, ...)); X, beta: initial guesses in, solutions
+    out; u_psi = psi - 1 and u_ap = alpha psi - 1: initial guesses in,
+    solutions out (ghosts filled).  Returns psi, alpha (ghosts from the
+    boundary rules) and the cycles of the four solves."""
+    cyc = []
+    zero = np.zeros_like(U)
+    cyc.append(len(vsolve(pv, X, np.ascontiguousarray(8.0 * math.pi * S), tol, max_cycles)) - 1)
+    A6, A2 = xcfc_aij(pv, X)
+    a = np.ascontiguousarray(-2.0 * math.pi * U)
+    a2 = np.ascontiguousarray(-A2 / 8.0)
+    cyc.append(len(solve(ps, u_psi, zero, a, tol, max_cycles, a2=a2)) - 1)
+    fill_ghosts(ps, u_psi)
+    psi = 1.0 + u_psi
+    St = stilde(psi)
+    a = np.ascontiguousarray(2.0 * math.pi * (U + 2.0 * St) / psi ** 2 + 7.0 / 8.0 * A2 * psi ** -8)
+    cyc.append(len(solve(pa, u_ap, zero, a, tol, max_cycles)) - 1)
+    fill_ghosts(pa, u_ap)
+    alpha = (1.0 + u_ap) / psi
+    w = np.ascontiguousarray(alpha * psi ** -6)
+    cyc.append(len(vsolve(pv, beta, xcfc_beta_rhs(pv, w, S, A6), tol, max_cycles)) - 1)
+    return psi, alpha, cyc

@@ -455,3 +455,67 @@ def test_smoother_takes_a_newton_step_on_both_nonlinear_terms():
     ex = u - g / dg
     got = mg.smooth(p, u.copy(), f, a, sweeps=1, a2=a2)
     np.testing.assert_allclose(mg.interior(p, got), mg.interior(p, ex), rtol=1e-9)
+
+
+def _xcfc_manufactured():
+    """Closed forms of a smooth xCFC configuration on [-1, 1]^3 (all fields
+    vanish, or psi and alpha psi equal 1, on the faces): X, psi and
+    alpha psi chosen; S~_i, U~ and S~ follow from the X, psi and alpha
+    equations of section 2.6; the shift source in closed form too."""
+    import sympy as sy
+    x, y, z = sy.symbols("x y z")
+    c = (x, y, z)
+    b = sy.cos(sy.pi * x / 2) * sy.cos(sy.pi * y / 2) * sy.cos(sy.pi * z / 2)
+    psi = 1 + sy.Rational(1, 10) * b
+    ap = 1 - sy.Rational(3, 20) * b
+    X = [sy.Rational(1, 20) * b * (1 + x / 2), -sy.Rational(3, 100) * b * (1 - 2 * y / 5 + z / 5),
+         sy.Rational(1, 50) * b * (1 + 3 * x * y / 10)]
+    lap = lambda f: sum(sy.diff(f, v, 2) for v in c)  # noqa: E731
+    div = sum(sy.diff(X[i], c[i]) for i in range(3))
+    S = [(lap(X[i]) + sy.diff(div, c[i]) / 3) / (8 * sy.pi) for i in range(3)]
+    A = [[sy.diff(X[j], c[i]) + sy.diff(X[i], c[j]) - (sy.Rational(2, 3) * div if i == j else 0) for j in range(3)]
+         for i in range(3)]
+    A2 = sum(A[i][j] ** 2 for i in range(3) for j in range(3))
+    U = -(lap(psi) + A2 / 8 * psi ** -7) * psi / (2 * sy.pi)
+    St = ((lap(ap) / ap - sy.Rational(7, 8) * A2 * psi ** -8) * psi ** 2 / (2 * sy.pi) - U) / 2
+    w = ap / psi * psi ** -6
+    fb = [16 * sy.pi * w * S[i] + 2 * sum(A[i][j] * sy.diff(w, c[j]) for j in range(3)) for i in range(3)]
+    f = lambda e: sy.lambdify(c, e, "numpy")  # noqa: E731
+    return dict(psi=f(psi), alpha=f(ap / psi), X=[f(e) for e in X], S=[f(e) for e in S], U=f(U),
+                P=f(St / psi ** 6), fb=[f(e) for e in fb])
+
+
+def test_xcfc_sequence_converges_to_a_manufactured_metric():
+    """The oracle's xCFC sequence (steps 1 to 6 of section 2.6) with sources
+    manufactured from a chosen X, psi and alpha psi returns them at second
+    order; the shift converges at second order to the discrete solution of
+    its equation with the closed-form source, so every coefficient of the
+    sequence (8 pi S~, A~^ij, the A2 terms of both scalar equations, the
+    16 pi w S~ and A~ grad w terms) enters with the right sign and factor."""
+    M = _xcfc_manufactured()
+    errs = []
+    for n in (16, 32):
+        base = dict(ndim=3, coord=CART, n=[n] * 3, xmin=[-1.0] * 3, dx=[2.0 / n] * 3, bc=[[D, D]] * 3)
+        pv = dict(base)
+        ps = dict(base, power=-1, power2=-7, offset=1.0)
+        pa = dict(base, power=1, offset=1.0)
+        x, y, z = mg.centres(pv)
+        ev = lambda fn: np.ascontiguousarray(np.broadcast_to(fn(x, y, z), x.shape), dtype=np.float64)  # noqa: E731
+        U = ev(M["U"])
+        S = np.ascontiguousarray(np.stack([ev(e) for e in M["S"]]))
+        P = ev(M["P"])
+        X = np.zeros((3,) + x.shape)
+        beta = np.zeros((3,) + x.shape)
+        up, ua = np.zeros(x.shape), np.zeros(x.shape)
+        psi, alpha, cyc = mg.xcfc_solve(pv, ps, pa, U, S, lambda ps_: ps_ ** 6 * P, X, up, ua, beta, tol=1e-12)
+        assert max(cyc) < 60
+        bref = np.zeros((3,) + x.shape)
+        mg.vsolve(pv, bref, np.ascontiguousarray(np.stack([ev(e) for e in M["fb"]])), tol=1e-12, max_cycles=60)
+        I = lambda a: mg.interior(pv, a)  # noqa: E731
+        errs.append((max(np.abs(I(X[i]) - I(ev(M["X"][i]))).max() for i in range(3)),
+                     np.abs(I(psi) - I(ev(M["psi"]))).max(), np.abs(I(alpha) - I(ev(M["alpha"]))).max(),
+                     max(np.abs(I(beta[i]) - I(bref[i])).max() for i in range(3)),
+                     max(np.abs(I(bref[i])).max() for i in range(3))))
+    for q in range(4):
+        assert 3.3 < errs[0][q] / errs[1][q] < 4.7, (q, errs)
+    assert errs[1][3] < 0.05 * errs[1][4]  # the shift itself is not small
