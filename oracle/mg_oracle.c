@@ -519,7 +519,11 @@ void om_subtract_gradient(const om_desc *d, const double *u, double *q) {
  * never neighbours, so a sweep does not depend on the order within a
  * colour).  Values across the boundary, edges and corners included, come
  * from the boundary rule applied per axis (mirror, times -1 for Dirichlet,
- * +1 for Neumann; periodic wrap).  Same level hierarchy, restriction,
+ * +1 for Neumann; periodic wrap).  A cell's three components are updated
+ * together from the values before its update: where two axes mirror (a
+ * corner of the domain) the mixed difference of one component reads the
+ * cell's own other component, and this keeps a colour's update independent
+ * of any ordering.  Same level hierarchy, restriction,
  * Kwak prolongation and FAS cycles as the scalar solver, per component.
  * Vector arrays: three component arrays back to back. */
 
@@ -592,11 +596,9 @@ static void vsmooth(const om_desc *d, const lvl *L, double *u, const double *f, 
             int cc = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
             if (cc != col) continue;
             long c = idx(d, L, i, j, k);
-            for (int comp = 0; comp < 3; comp++) {
-              double dg;
-              double Lu = vapply_cell(d, L, u, comp, i, j, k, &dg);
-              u[comp * L->nt + c] -= (Lu - f[comp * L->nt + c]) / dg;
-            }
+            double Lu[3], dg[3];
+            for (int comp = 0; comp < 3; comp++) Lu[comp] = vapply_cell(d, L, u, comp, i, j, k, &dg[comp]);
+            for (int comp = 0; comp < 3; comp++) u[comp * L->nt + c] -= (Lu[comp] - f[comp * L->nt + c]) / dg[comp];
           }
 }
 

@@ -415,8 +415,10 @@ def test_vector_sweep_is_jacobi_within_each_of_four_colours():
     update of that colour's cells, X -= (L(X) - f) / diag, with the operator's
     analytic diagonal -2 sum_a 1/h_a^2 - (2/3)/h_i^2 (component i active): the
     mixed stencil couples diagonal neighbours, so two colours do not
-    suffice."""
-    p = prob(2, CART, (8, 6), (0, 0), (1, 1.5), [[PER, PER], [D, N]])
+    suffice.  Both axes mirror here, so at the corners the mixed difference
+    of one component reads the cell's own other component, which the
+    simultaneous update takes from before the cell's update."""
+    p = prob(2, CART, (8, 6), (0, 0), (1, 1.5), [[D, N], [D, N]])
     rng = np.random.default_rng(5)
     shp = (3,) + mg.shape(p)
     X = np.ascontiguousarray(rng.standard_normal(shp))
