@@ -85,10 +85,20 @@ def lib():
 DEFAULTS = dict(levels=0, pre=2, post=2, coarse=50, power=0, offset=0.0, power2=0)
 
 
+def _coarsens(p, a, L):
+    """Axis a still has a valid level after L halvings: divisible, at least
+    two cells, and an even count on a periodic axis (with an odd count the
+    cells on either side of the wrap share a colour of the red-black and
+    multi-colour orderings, which then no longer separate neighbours)."""
+    n = p["n"][a] >> L
+    return p["n"][a] % (1 << L) == 0 and n >= 2 and (p["bc"][a][0] != PERIODIC or n % 2 == 0)
+
+
 def max_levels(p):
-    """Levels down to at least two cells on every active axis."""
+    """Levels down to at least two cells on every active axis (an even
+    number on periodic axes)."""
     L = 1
-    while all(p["n"][a] % (1 << L) == 0 and (p["n"][a] >> L) >= 2 for a in range(p["ndim"])):
+    while all(_coarsens(p, a, L) for a in range(p["ndim"])):
         L += 1
     return L
 
@@ -108,8 +118,8 @@ def make_desc(p):
     d.offset = float(q["offset"])
     d.power2 = int(q["power2"])
     for a in range(d.ndim):
-        if d.n[a] % (1 << (d.levels - 1)):
-            raise ValueError("grid not divisible for the requested levels")
+        if not _coarsens(q, a, d.levels - 1):
+            raise ValueError("grid not divisible for the requested levels (even counts on periodic axes)")
         for s in (0, 1):
             if d.bc[a][s] == ROBIN and (a != 0 or d.coord == CART):
                 raise ValueError("the Robin condition is for the radial axis")

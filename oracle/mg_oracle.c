@@ -34,6 +34,10 @@
  *     face the Robin condition d(r u)/dr = 0 of section 2.6 (ghost value
  *     u_in r_in / r_ghost, exact for a 1/r fall-off); faces of zero area
  *     (r = 0, R = 0, theta = 0 or pi) need none;
+ *   - on a periodic axis every level keeps an even number of cells (the
+ *     caller chooses the levels so): with an odd count the cells on either
+ *     side of the wrap share a colour, and the red-black and multi-colour
+ *     orderings would no longer separate neighbours;
  *   - restriction is the volume-weighted mean of the children (the paper
  *     gives the piecewise constant stencil only; weighting by the cell
  *     volumes of the reference metric keeps the coarse problem consistent

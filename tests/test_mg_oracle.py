@@ -521,3 +521,14 @@ def test_xcfc_sequence_converges_to_a_manufactured_metric():
     for q in range(4):
         assert 3.3 < errs[0][q] / errs[1][q] < 4.7, (q, errs)
     assert errs[1][3] < 0.05 * errs[1][4]  # the shift itself is not small
+
+
+def test_periodic_axes_keep_an_even_count_on_every_level():
+    """With an odd number of cells on a periodic axis the two cells beside
+    the wrap would share a colour: the hierarchy stops before that level
+    (12 periodic cells: 12, 6; not 3) and refuses it when asked for."""
+    p = prob(2, CART, (12, 16), (0, 0), (1, 1), [[PER, PER], [D, D]])
+    assert mg.make_desc(p).levels == 2
+    assert mg.make_desc(dict(p, bc=[[D, D], [D, D], [N, N]])).levels == 3
+    with pytest.raises(ValueError):
+        mg.make_desc(dict(p, levels=3))
