@@ -5,14 +5,18 @@
  * cell-centred multigrid: 3/5/7-point second-order operators, red-black
  * Newton-Gauss-Seidel smoothing, the same relaxation as the coarsest-level
  * solver, piecewise-constant restriction, Kwak prolongation) and section 2.2
- * (elliptic divergence cleaning).  The equation solved is
- *     L(u) = Lap(u) - a (u + c)^p = f,   p in {-1, 0, 1},
+ * (elliptic divergence cleaning).  The scalar equation solved is
+ *     L(u) = Lap(u) - a (u + c)^p - a2 (u + c)^q = f,   p in {-1, 0, 1},
  * where Lap is the Laplacian of the flat reference metric in Cartesian,
  * cylindrical (R, z, phi) or spherical (r, theta, phi) coordinates.  The
  * scalar metric equations of section 2.6 in deviation form have this form
- * (conformal factor: p = -1, c = 1, a = -2 pi U, f = 0 without the
- * extrinsic-curvature term; lapse: p = 1 for u = alpha psi - 1), and so has
- * the Poisson equation of the cleaning (a = 0).
+ * (conformal factor: p = -1, q = -7, c = 1, a = -2 pi U~,
+ * a2 = -A~_ij A~^ij / 8, f = 0; lapse: p = 1 for u = alpha psi - 1), and so
+ * has the Poisson equation of the cleaning (a = a2 = 0).  The vector
+ * equation of the xCFC potential X and of the shift (section 2.6),
+ *     L(X)^i = Lap X^i + (1/3) d_i d_j X^j = f^i,
+ * is solved on Cartesian grids (second differences and the four-point mixed
+ * difference of section 2.7; Newton-Gauss-Seidel over 2^ndim colours).
  *
  * Arrays: FP64 device memory, one ghost layer on each active axis, layout
  * [k][j][i] with i fastest: n[a] + 2 entries along an active axis, 1 along
@@ -44,20 +48,24 @@ typedef struct {
   double xmin[3];    /* lower face coordinate per axis */
   double dx[3];      /* finest spacing per axis */
   int bc[3][2];      /* GMUNU_MG_* per axis and side */
-  int levels;        /* levels in the hierarchy; 0: down to 2 cells on the shortest active axis */
+  int levels;        /* levels in the hierarchy; 0: as many as the axes allow (see gmunu_mg_create) */
   int pre, post;     /* red-black sweeps before and after the coarse correction (>= 0) */
   int coarse;        /* sweeps on the coarsest level (>= 1) */
   int power;         /* p: -1, 0 or 1 */
   double offset;     /* c */
+  int power2;        /* q of the second term, -8..8; 0: no second term (a2 must be NULL) */
 } gmunu_mg_desc;
 
 typedef struct gmunu_mg gmunu_mg;
 
 /* Validate (each active n divisible by 2^(levels-1), at least 2 cells per
- * axis on the coarsest level, Robin only on axis 0 of curvilinear grids,
+ * axis on the coarsest level and an even number on periodic axes, Robin
+ * only on axis 0 of curvilinear grids,
  * fewer than 2^31 entries per array),
  * build the level hierarchy on the current device and allocate its arrays
- * (5 arrays per coarse level, 1 on the finest).  Synchronous. */
+ * (5 arrays per coarse level, 6 with power2 != 0; 1 on the finest; the
+ * vector equations add 12 per coarse level on their first use).
+ * Synchronous. */
 int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out);
 int gmunu_mg_destroy(gmunu_mg *mg);
 /* Levels actually used. */
@@ -68,24 +76,27 @@ long gmunu_mg_size(const gmunu_mg *mg, int level);
 /* Solve L(u) = f on the finest level in place: an FAS full-multigrid cycle
  * from the current u first when fmg != 0, then FAS V-cycles until
  * max |f - L(u)| <= tol or max_cycles cycles were done (the FMG cycle
- * counts as one).  a may be NULL (a = 0).  res_host (max_cycles + 1 doubles,
- * nullable) receives the residual norm before and after each cycle;
- * *cycles_out the cycles done.  Synchronises `stream` once per cycle to
- * read the norm. */
-int gmunu_mg_solve(gmunu_mg *mg, double *u, const double *f, const double *a, double tol, int max_cycles, int fmg,
-                   double *res_host, int *cycles_out, void *stream);
-/* max |f - L(u)| on the finest level (u's ghosts filled first).  Synchronous. */
-int gmunu_mg_residual_norm(gmunu_mg *mg, double *u, const double *f, const double *a, double *norm_out,
-                           void *stream);
+ * counts as one).  a and a2 may be NULL (zero); a2 needs power2 != 0
+ * (else EINVAL).  res_host (max_cycles + 1 doubles, nullable) receives the
+ * residual norm before and after each cycle; *cycles_out the cycles done.
+ * Synchronises `stream` once per cycle to read the norm.  The V-cycle is
+ * replayed from a graph captured for the arrays (u, f, a, a2) of the call;
+ * four such graphs are kept per hierarchy. */
+int gmunu_mg_solve(gmunu_mg *mg, double *u, const double *f, const double *a, const double *a2, double tol,
+                   int max_cycles, int fmg, double *res_host, int *cycles_out, void *stream);
+/* max |f - L(u)| on the finest level (boundary rule inline).  Synchronous. */
+int gmunu_mg_residual_norm(gmunu_mg *mg, double *u, const double *f, const double *a, const double *a2,
+                           double *norm_out, void *stream);
 
 /* Building blocks (finest level unless a level is given), for checking:
  * out = L(u) on the interior with u's ghosts as given; ghost fill; `sweeps`
  * red-black sweeps; restriction of level l into level l - 1 (volume-weighted
  * mean of children); Kwak prolongation of level l - 1 (ghosts as given)
  * into level l. */
-int gmunu_mg_apply(gmunu_mg *mg, const double *u, const double *a, double *out, void *stream);
+int gmunu_mg_apply(gmunu_mg *mg, const double *u, const double *a, const double *a2, double *out, void *stream);
 int gmunu_mg_fill_ghosts(gmunu_mg *mg, int level, double *u, void *stream);
-int gmunu_mg_smooth(gmunu_mg *mg, double *u, const double *f, const double *a, int sweeps, void *stream);
+int gmunu_mg_smooth(gmunu_mg *mg, double *u, const double *f, const double *a, const double *a2, int sweeps,
+                    void *stream);
 int gmunu_mg_restrict(gmunu_mg *mg, int level, const double *fine, double *coarse, void *stream);
 int gmunu_mg_prolong(gmunu_mg *mg, int level, const double *coarse, double *fine, void *stream);
 
@@ -127,6 +138,47 @@ int gmunu_mg_clean_state(gmunu_mg *mg, const gmunu_grid_desc *hydro, double *q, 
 int gmunu_mg_cfc_solve(gmunu_mg *mpsi, gmunu_mg *malpha, const gmunu_grid_desc *hydro, const double *q,
                        const double *prim, double *metric, double tol, int max_cycles, int *cycles_out,
                        void *stream);
+
+/* Vector equation L(X) = f of section 2.6 on Cartesian grids (EINVAL for
+ * other coordinates; the descriptor's power, offset and power2 are not
+ * used).  X and f: three arrays back to back (X^x, X^y, X^z); values across
+ * the boundary come from each axis's rule, so ghost entries of X are not
+ * read.  vapply: out = L(X) on the interior.  vsmooth: `sweeps` sweeps of
+ * the 2^ndim colours, then X's ghosts filled.  vsolve: as gmunu_mg_solve
+ * (per-component maximum norm); X's ghosts filled on return.  The first
+ * vector call allocates the coarse levels' vector arrays. */
+int gmunu_mg_vapply(gmunu_mg *mg, const double *X, double *out, void *stream);
+int gmunu_mg_vsmooth(gmunu_mg *mg, double *X, const double *f, int sweeps, void *stream);
+int gmunu_mg_vsolve(gmunu_mg *mg, double *X, const double *f, double tol, int max_cycles, int fmg, double *res_host,
+                    int *cycles_out, void *stream);
+
+/* Section 2.6, Cartesian: A~^ij = d_i X^j + d_j X^i - (2/3) delta^ij d_k X^k
+ * by centred differences (values across the boundary by the axis rules) on
+ * the interior, as six arrays (xx, yy, zz, xy, xz, yz) in A6, and
+ * A~_ij A~^ij in A2. */
+int gmunu_mg_xcfc_aij(gmunu_mg *mg, const double *X, double *A6, double *A2, void *stream);
+/* Source of the shift equation, 16 pi w S_i + 2 A~^ij d_j w with
+ * w = alpha psi^-6 (centred gradient from w's stored ghost entries),
+ * S = S~_i (three arrays), A6 as above; out: three arrays, interior. */
+int gmunu_mg_xcfc_beta_rhs(gmunu_mg *mg, const double *w, const double *S, const double *A6, double *out,
+                           void *stream);
+
+/* The xCFC metric solve of section 2.6 (steps 1 to 6) for a GRMHD state on a
+ * Cartesian grid: X from L(X) = 8 pi S~_i (S~_i = q_{S_i}; X in/out: initial
+ * guess and solution, three multigrid arrays of mvec), A~^ij from X, psi
+ * from its equation with both terms (mpsi: p = -1, q = -7, c = 1), S~ with
+ * the new psi as in gmunu_mg_cfc_solve, alpha psi (malpha: p = 1, c = 1,
+ * its coefficient with the (7/8) A~_ij A~^ij psi^-8 term), then the shift
+ * from L(beta) = 16 pi alpha psi^-6 S~_i + 2 A~^ij d_j(alpha psi^-6)
+ * starting from the metric's shift.  psi, alpha and beta^i (metric variables
+ * 0..4) are written to every cell of the GRMHD layout, ghost layers
+ * extended by the boundary rules.  mvec, mpsi and malpha: hierarchies on
+ * the interior grid of `hydro` (mvec Cartesian).  cycles_out (4 ints,
+ * nullable): cycles of the X, psi, alpha psi and beta solves.  Scratch of
+ * 17 finest arrays is allocated in mvec on the first call. */
+int gmunu_mg_xcfc_solve(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, const gmunu_grid_desc *hydro,
+                        const double *q, const double *prim, double *metric, double *X, double tol, int max_cycles,
+                        int *cycles_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -525,11 +525,11 @@ class MgDesc(ctypes.Structure):
         ("ndim", ctypes.c_int), ("coord", ctypes.c_int), ("n", ctypes.c_int * 3),
         ("xmin", ctypes.c_double * 3), ("dx", ctypes.c_double * 3), ("bc", (ctypes.c_int * 2) * 3),
         ("levels", ctypes.c_int), ("pre", ctypes.c_int), ("post", ctypes.c_int), ("coarse", ctypes.c_int),
-        ("power", ctypes.c_int), ("offset", ctypes.c_double),
+        ("power", ctypes.c_int), ("offset", ctypes.c_double), ("power2", ctypes.c_int),
     ]
 
 
-MG_DEFAULTS = dict(levels=0, pre=2, post=2, coarse=50, power=0, offset=0.0)
+MG_DEFAULTS = dict(levels=0, pre=2, post=2, coarse=50, power=0, offset=0.0, power2=0)
 
 
 def _mg_sigs(L):
@@ -539,11 +539,11 @@ def _mg_sigs(L):
     L.gmunu_mg_levels.argtypes = [_P]
     L.gmunu_mg_size.argtypes = [_P, I]
     L.gmunu_mg_size.restype = ctypes.c_long
-    L.gmunu_mg_solve.argtypes = [_P, _P, _P, _P, D, I, I, _P, _P, _P]
-    L.gmunu_mg_residual_norm.argtypes = [_P, _P, _P, _P, _P, _P]
-    L.gmunu_mg_apply.argtypes = [_P, _P, _P, _P, _P]
+    L.gmunu_mg_solve.argtypes = [_P, _P, _P, _P, _P, D, I, I, _P, _P, _P]
+    L.gmunu_mg_residual_norm.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+    L.gmunu_mg_apply.argtypes = [_P, _P, _P, _P, _P, _P]
     L.gmunu_mg_fill_ghosts.argtypes = [_P, I, _P, _P]
-    L.gmunu_mg_smooth.argtypes = [_P, _P, _P, _P, I, _P]
+    L.gmunu_mg_smooth.argtypes = [_P, _P, _P, _P, _P, I, _P]
     L.gmunu_mg_restrict.argtypes = [_P, I, _P, _P, _P]
     L.gmunu_mg_prolong.argtypes = [_P, I, _P, _P, _P]
     L.gmunu_mg_divergence.argtypes = [_P, _P, _P, _P]
@@ -551,6 +551,12 @@ def _mg_sigs(L):
     L.gmunu_mg_clean.argtypes = [_P, _P, _P, _P, D, I, _P, _P, _P]
     L.gmunu_mg_clean_state.argtypes = [_P, _P, _P, _P, _P, D, I, _P, _P, _P]
     L.gmunu_mg_cfc_solve.argtypes = [_P, _P, _P, _P, _P, _P, D, I, _P, _P]
+    L.gmunu_mg_vapply.argtypes = [_P, _P, _P, _P]
+    L.gmunu_mg_vsmooth.argtypes = [_P, _P, _P, I, _P]
+    L.gmunu_mg_vsolve.argtypes = [_P, _P, _P, D, I, I, _P, _P, _P]
+    L.gmunu_mg_xcfc_aij.argtypes = [_P, _P, _P, _P, _P]
+    L.gmunu_mg_xcfc_beta_rhs.argtypes = [_P, _P, _P, _P, _P, _P]
+    L.gmunu_mg_xcfc_solve.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, D, I, _P, _P]
 
 
 def make_mg_desc(p: dict) -> MgDesc:
@@ -564,7 +570,7 @@ def make_mg_desc(p: dict) -> MgDesc:
         d.dx[a] = float(q["dx"][a])
         d.bc[a][0], d.bc[a][1] = int(q["bc"][a][0]), int(q["bc"][a][1])
     d.levels, d.pre, d.post, d.coarse = int(q["levels"]), int(q["pre"]), int(q["post"]), int(q["coarse"])
-    d.power, d.offset = int(q["power"]), float(q["offset"])
+    d.power, d.offset, d.power2 = int(q["power"]), float(q["offset"]), int(q["power2"])
     return d
 
 
@@ -601,39 +607,42 @@ class Multigrid:
         return tuple((d.n[a] >> s) + 2 if a < d.ndim else 1 for a in (2, 1, 0))
 
     def empty(self, level=None, vector=False):
-        shp = ((3,) if vector else ()) + self.shape(level)
+        shp = ((int(vector) if vector > 1 else 3,) if vector else ()) + self.shape(level)
         return torch.zeros(shp, dtype=torch.float64, device="cuda")
 
     def _chk(self, t, what, level=None, vector=False, none_ok=False):
+        """vector: False (scalar), True (three components) or a component count."""
         if t is None:
             if none_ok:
                 return None
             raise ValueError(f"{what} is required")
-        shp = ((3,) if vector else ()) + self.shape(level)
+        shp = ((int(vector) if vector > 1 else 3,) if vector else ()) + self.shape(level)
         if tuple(t.shape) != shp:
             raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {shp}")
         return _ptr(t, what)
 
-    def solve(self, u, f, a=None, tol=1e-12, max_cycles=30, fmg=True):
+    def solve(self, u, f, a=None, tol=1e-12, max_cycles=30, fmg=True, a2=None):
         """Solve in place; returns the residual history (list of max norms)."""
         res = (ctypes.c_double * (max_cycles + 1))()
         cyc = ctypes.c_int(0)
         _check(lib().gmunu_mg_solve(self._h, self._chk(u, "u"), self._chk(f, "f"),
-                                    self._chk(a, "a", none_ok=True), float(tol), int(max_cycles), 1 if fmg else 0,
-                                    res, ctypes.byref(cyc), _stream()), "gmunu_mg_solve")
+                                    self._chk(a, "a", none_ok=True), self._chk(a2, "a2", none_ok=True), float(tol),
+                                    int(max_cycles), 1 if fmg else 0, res, ctypes.byref(cyc), _stream()),
+               "gmunu_mg_solve")
         return [res[i] for i in range(cyc.value + 1)]
 
-    def residual_norm(self, u, f, a=None):
+    def residual_norm(self, u, f, a=None, a2=None):
         out = ctypes.c_double(0.0)
         _check(lib().gmunu_mg_residual_norm(self._h, self._chk(u, "u"), self._chk(f, "f"),
-                                            self._chk(a, "a", none_ok=True), ctypes.byref(out), _stream()),
-               "gmunu_mg_residual_norm")
+                                            self._chk(a, "a", none_ok=True), self._chk(a2, "a2", none_ok=True),
+                                            ctypes.byref(out), _stream()), "gmunu_mg_residual_norm")
         return out.value
 
-    def apply(self, u, a=None, out=None):
+    def apply(self, u, a=None, out=None, a2=None):
         out = self.empty() if out is None else out
         _check(lib().gmunu_mg_apply(self._h, self._chk(u, "u"), self._chk(a, "a", none_ok=True),
-                                    self._chk(out, "out"), _stream()), "gmunu_mg_apply")
+                                    self._chk(a2, "a2", none_ok=True), self._chk(out, "out"), _stream()),
+               "gmunu_mg_apply")
         return out
 
     def fill_ghosts(self, u, level=None):
@@ -641,10 +650,44 @@ class Multigrid:
         _check(lib().gmunu_mg_fill_ghosts(self._h, lv, self._chk(u, "u", lv), _stream()), "gmunu_mg_fill_ghosts")
         return u
 
-    def smooth(self, u, f, a=None, sweeps=1):
+    def smooth(self, u, f, a=None, sweeps=1, a2=None):
         _check(lib().gmunu_mg_smooth(self._h, self._chk(u, "u"), self._chk(f, "f"), self._chk(a, "a", none_ok=True),
-                                     int(sweeps), _stream()), "gmunu_mg_smooth")
+                                     self._chk(a2, "a2", none_ok=True), int(sweeps), _stream()), "gmunu_mg_smooth")
         return u
+
+    # vector equation of xCFC (Cartesian): X, f of shape (3,) + shape()
+    def vapply(self, X, out=None):
+        out = self.empty(vector=True) if out is None else out
+        _check(lib().gmunu_mg_vapply(self._h, self._chk(X, "X", vector=True), self._chk(out, "out", vector=True),
+                                     _stream()), "gmunu_mg_vapply")
+        return out
+
+    def vsmooth(self, X, f, sweeps=1):
+        _check(lib().gmunu_mg_vsmooth(self._h, self._chk(X, "X", vector=True), self._chk(f, "f", vector=True),
+                                      int(sweeps), _stream()), "gmunu_mg_vsmooth")
+        return X
+
+    def vsolve(self, X, f, tol=1e-12, max_cycles=30, fmg=True):
+        res = (ctypes.c_double * (max_cycles + 1))()
+        cyc = ctypes.c_int(0)
+        _check(lib().gmunu_mg_vsolve(self._h, self._chk(X, "X", vector=True), self._chk(f, "f", vector=True),
+                                     float(tol), int(max_cycles), 1 if fmg else 0, res, ctypes.byref(cyc),
+                                     _stream()), "gmunu_mg_vsolve")
+        return [res[i] for i in range(cyc.value + 1)]
+
+    def xcfc_aij(self, X, A6=None, A2=None):
+        A6 = self.empty(vector=6) if A6 is None else A6
+        A2 = self.empty() if A2 is None else A2
+        _check(lib().gmunu_mg_xcfc_aij(self._h, self._chk(X, "X", vector=True), self._chk(A6, "A6", vector=6),
+                                       self._chk(A2, "A2"), _stream()), "gmunu_mg_xcfc_aij")
+        return A6, A2
+
+    def xcfc_beta_rhs(self, w, S, A6, out=None):
+        out = self.empty(vector=True) if out is None else out
+        _check(lib().gmunu_mg_xcfc_beta_rhs(self._h, self._chk(w, "w"), self._chk(S, "S", vector=True),
+                                            self._chk(A6, "A6", vector=6), self._chk(out, "out", vector=True),
+                                            _stream()), "gmunu_mg_xcfc_beta_rhs")
+        return out
 
     def restrict(self, level, fine, coarse=None):
         coarse = self.empty(level - 1) if coarse is None else coarse
@@ -698,3 +741,16 @@ def cfc_solve(mpsi, malpha, grid_params, q, prim, metric, tol=1e-12, max_cycles=
                                     _ptr(metric, "metric"), float(tol), int(max_cycles), cyc, _stream()),
            "gmunu_mg_cfc_solve")
     return cyc[0], cyc[1]
+
+
+def xcfc_solve(mvec, mpsi, malpha, grid_params, q, prim, metric, X, tol=1e-12, max_cycles=60):
+    """xCFC metric solve (X, psi, alpha, beta) for a GRMHD state on a
+    Cartesian grid; metric and X (mvec.empty(vector=True)) are updated in
+    place.  Returns the cycles of the four solves."""
+    hd = make_desc(grid_params)
+    cyc = (ctypes.c_int * 4)()
+    _check(lib().gmunu_mg_xcfc_solve(mvec._h, mpsi._h, malpha._h, ctypes.byref(hd), _ptr(q, "q"),
+                                     _ptr(prim, "prim"), _ptr(metric, "metric"),
+                                     mvec._chk(X, "X", vector=True), float(tol), int(max_cycles), cyc, _stream()),
+           "gmunu_mg_xcfc_solve")
+    return tuple(cyc[i] for i in range(4))

@@ -45,7 +45,7 @@ struct MgGeo {
   const double *a1m, *a1p, *s2t, *vol1, *sg1;
   int bc[3][2];
   double rob_lo, rob_hi;  // Robin ghost factors on axis 0 (centre inside / centre of the ghost)
-  int power;
+  int power, power2;
   double offset;
 };
 
@@ -53,14 +53,22 @@ __device__ __forceinline__ long mg_off(const MgGeo &G, int i, int j, int k) {
   return (long)(k + G.g[2]) * G.s2 + (long)(j + G.g[1]) * G.s1 + (i + G.g[0]);
 }
 
-__device__ __forceinline__ double mg_nl(const MgGeo &G, double a, double u) {
-  return G.power == 0 ? a : G.power == 1 ? a * (u + G.offset) : a / (u + G.offset);
+__device__ __forceinline__ double mg_ipow(double w, int q) {
+  double r = 1.0;
+  for (int e = q < 0 ? -q : q; e > 0; e--) r *= w;
+  return q < 0 ? 1.0 / r : r;
 }
-__device__ __forceinline__ double mg_nl_du(const MgGeo &G, double a, double u) {
-  if (G.power == 0) return 0.0;
-  if (G.power == 1) return a;
+
+// a (u + c)^p + a2 (u + c)^q and its derivative in u.
+__device__ __forceinline__ double mg_nl(const MgGeo &G, double a, double a2, double u) {
   const double w = u + G.offset;
-  return -a / (w * w);
+  const double t = G.power == 0 ? a : G.power == 1 ? a * w : a / w;
+  return a2 != 0.0 ? t + a2 * mg_ipow(w, G.power2) : t;
+}
+__device__ __forceinline__ double mg_nl_du(const MgGeo &G, double a, double a2, double u) {
+  const double w = u + G.offset;
+  const double t = G.power == 0 ? 0.0 : G.power == 1 ? a : -a / (w * w);
+  return a2 != 0.0 ? t + a2 * G.power2 * mg_ipow(w, G.power2 - 1) : t;
 }
 
 // Neighbour of interior cell index c (0..n-1) along an axis of stride S on
@@ -81,7 +89,7 @@ __device__ __forceinline__ double mg_nb(const MgGeo &G, const double *__restrict
 // from the boundary rule (mg_nb), so that no ghost fill is needed.
 template <bool GH>
 __device__ __forceinline__ double mg_L(const MgGeo &G, const double *__restrict__ u, const double *__restrict__ a,
-                                       int i, int j, int k, long o, double *dg) {
+                                       const double *__restrict__ a2, int i, int j, int k, long o, double *dg) {
   const int I = i + G.g[0], J = j + G.g[1];
   const double uc = u[o];
   double wm = G.a0m[I], wp = G.a0p[I];
@@ -104,9 +112,9 @@ __device__ __forceinline__ double mg_L(const MgGeo &G, const double *__restrict_
     lap += w * (up - uc) - w * (uc - um);
     d -= 2.0 * w;
   }
-  const double av = a ? a[o] : 0.0;
-  if (dg) *dg = d - mg_nl_du(G, av, uc);
-  return lap - mg_nl(G, av, uc);
+  const double av = a ? a[o] : 0.0, a2v = a2 ? a2[o] : 0.0;
+  if (dg) *dg = d - mg_nl_du(G, av, a2v, uc);
+  return lap - mg_nl(G, av, a2v, uc);
 }
 
 // Interior cell number t (x fastest); 32-bit arithmetic (a level has fewer
@@ -160,14 +168,17 @@ __device__ __forceinline__ long mg_ghost_count(const MgGeo &G) {
   return s;
 }
 
+template <int NC>
 __global__ __launch_bounds__(NT) void k_mg_ghosts(const MgGeo G, double *u) {
-  mg_ghost_one(G, u, (long)blockIdx.x * NT + threadIdx.x);
+#pragma unroll
+  for (int q = 0; q < NC; q++) mg_ghost_one(G, u + q * G.nt, (long)blockIdx.x * NT + threadIdx.x);
 }
 
 // One colour of red-black Newton-Gauss-Seidel: thread t -> the t-th cell of
 // that colour (every other cell of a row).
 __device__ __forceinline__ void mg_smooth_one(const MgGeo &G, double *u, const double *__restrict__ f,
-                                              const double *__restrict__ a, int colour, long t) {
+                                              const double *__restrict__ a, const double *__restrict__ a2, int colour,
+                                              long t) {
   const unsigned hrow = (unsigned)(G.n[0] + 1) >> 1, n1 = (unsigned)G.n[1];
   if (t >= (long)hrow * G.n[1] * G.n[2]) return;
   const unsigned row = (unsigned)t / hrow;
@@ -176,48 +187,51 @@ __device__ __forceinline__ void mg_smooth_one(const MgGeo &G, double *u, const d
   if (i >= G.n[0]) return;
   const long o = mg_off(G, i, j, k);
   double dg;
-  const double Lu = mg_L<false>(G, u, a, i, j, k, o, &dg);
+  const double Lu = mg_L<false>(G, u, a, a2, i, j, k, o, &dg);
   u[o] -= (Lu - f[o]) / dg;
 }
 
 __global__ __launch_bounds__(NT) void k_mg_smooth(const MgGeo G, double *u, const double *__restrict__ f,
-                                                  const double *__restrict__ a, int colour) {
-  mg_smooth_one(G, u, f, a, colour, (long)blockIdx.x * NT + threadIdx.x);
+                                                  const double *__restrict__ a, const double *__restrict__ a2,
+                                                  int colour) {
+  mg_smooth_one(G, u, f, a, a2, colour, (long)blockIdx.x * NT + threadIdx.x);
 }
 
 // The coarsest-level solver: `sweeps` red-black sweeps by one workgroup,
 // the colours separated by workgroup barriers instead of launches.
 __global__ __launch_bounds__(NT) void k_mg_coarse(const MgGeo G, double *u, const double *__restrict__ f,
-                                                  const double *__restrict__ a, int sweeps) {
+                                                  const double *__restrict__ a, const double *__restrict__ a2,
+                                                  int sweeps) {
   const long nc = (long)((G.n[0] + 1) >> 1) * G.n[1] * G.n[2];
   for (int s = 0; s < sweeps; s++)
     for (int c = 0; c < 2; c++) {
-      for (long t = threadIdx.x; t < nc; t += NT) mg_smooth_one(G, u, f, a, c, t);
+      for (long t = threadIdx.x; t < nc; t += NT) mg_smooth_one(G, u, f, a, a2, c, t);
       __syncthreads();
     }
 }
 
 // out = L(u) on the interior.
 __global__ __launch_bounds__(NT) void k_mg_apply(const MgGeo G, const double *__restrict__ u,
-                                                 const double *__restrict__ a, double *__restrict__ out) {
+                                                 const double *__restrict__ a, const double *__restrict__ a2,
+                                                 double *__restrict__ out) {
   const long t = (long)blockIdx.x * NT + threadIdx.x;
   if (t >= mg_cells(G)) return;
   int i, j, k;
   mg_cell(G, t, i, j, k);
   const long o = mg_off(G, i, j, k);
-  out[o] = mg_L<true>(G, u, a, i, j, k, o, nullptr);
+  out[o] = mg_L<true>(G, u, a, a2, i, j, k, o, nullptr);
 }
 
 // Per-workgroup maxima of |f - L(u)| over a grid-stride range of cells.
 __global__ __launch_bounds__(NT) void k_mg_norm(const MgGeo G, const double *__restrict__ u,
                                                 const double *__restrict__ f, const double *__restrict__ a,
-                                                double *part) {
+                                                const double *__restrict__ a2, double *part) {
   double m = 0.0;
   for (long t = (long)blockIdx.x * NT + threadIdx.x; t < mg_cells(G); t += (long)gridDim.x * NT) {
     int i, j, k;
     mg_cell(G, t, i, j, k);
     const long o = mg_off(G, i, j, k);
-    m = fmax(m, fabs(f[o] - mg_L<false>(G, u, a, i, j, k, o, nullptr)));
+    m = fmax(m, fabs(f[o] - mg_L<false>(G, u, a, a2, i, j, k, o, nullptr)));
   }
   m = block_max(m);
   if (threadIdx.x == 0) part[blockIdx.x] = m;
@@ -252,14 +266,15 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(const MgGeo F, const MgGeo C
 
 // FAS coarse problem: f_c = L_c(u_c) + r_c, and uo_c = u_c (u_c's ghosts set).
 __global__ __launch_bounds__(NT) void k_mg_fas_rhs(const MgGeo C, const double *__restrict__ u,
-                                                   const double *__restrict__ a, const double *__restrict__ r,
-                                                   double *__restrict__ f, double *__restrict__ uo) {
+                                                   const double *__restrict__ a, const double *__restrict__ a2,
+                                                   const double *__restrict__ r, double *__restrict__ f,
+                                                   double *__restrict__ uo) {
   const long t = (long)blockIdx.x * NT + threadIdx.x;
   if (t >= mg_cells(C)) return;
   int i, j, k;
   mg_cell(C, t, i, j, k);
   const long o = mg_off(C, i, j, k);
-  f[o] = mg_L<false>(C, u, a, i, j, k, o, nullptr) + r[o];
+  f[o] = mg_L<false>(C, u, a, a2, i, j, k, o, nullptr) + r[o];
   uo[o] = u[o];
 }
 
@@ -268,7 +283,8 @@ __global__ __launch_bounds__(NT) void k_mg_fas_rhs(const MgGeo C, const double *
 // volume-weighted means of u and of the residual into the coarse u and r.
 __global__ __launch_bounds__(NT) void k_mg_restrict_res(const MgGeo F, const MgGeo C, const double *__restrict__ u,
                                                         const double *__restrict__ f, const double *__restrict__ a,
-                                                        double *__restrict__ uc, double *__restrict__ rc) {
+                                                        const double *__restrict__ a2, double *__restrict__ uc,
+                                                        double *__restrict__ rc) {
   const long t = (long)blockIdx.x * NT + threadIdx.x;
   if (t >= mg_cells(C)) return;
   int i, j, k;
@@ -282,7 +298,7 @@ __global__ __launch_bounds__(NT) void k_mg_restrict_res(const MgGeo F, const MgG
     const double v = F.vol0[fi + F.g[0]] * F.vol1[fj + F.g[1]];
     const long o = mg_off(F, fi, fj, fk);
     su += v * u[o];
-    sr += v * (f[o] - mg_L<false>(F, u, a, fi, fj, fk, o, nullptr));
+    sr += v * (f[o] - mg_L<false>(F, u, a, a2, fi, fj, fk, o, nullptr));
     w += v;
   }
   const long oc = mg_off(C, i, j, k);
@@ -292,14 +308,15 @@ __global__ __launch_bounds__(NT) void k_mg_restrict_res(const MgGeo F, const MgG
 
 // u_F += P (u_C - uo_C): Kwak prolongation of the coarse correction, whose
 // values across the boundary follow the boundary rule (it is homogeneous,
-// so the correction obeys it too).
+// so the correction obeys it too); NC components back to back.
 __device__ __forceinline__ double mg_corr(const MgGeo &C, const double *__restrict__ u,
                                           const double *__restrict__ uo, long o) {
   return u[o] - uo[o];
 }
 
-__global__ __launch_bounds__(NT) void k_mg_correct(const MgGeo C, const MgGeo F, const double *__restrict__ uc,
-                                                   const double *__restrict__ uoc, double *__restrict__ fine) {
+template <int NC>
+__global__ __launch_bounds__(NT) void k_mg_correct(const MgGeo C, const MgGeo F, const double *__restrict__ uc0,
+                                                   const double *__restrict__ uoc0, double *__restrict__ fine0) {
   const long t = (long)blockIdx.x * NT + threadIdx.x;
   if (t >= mg_cells(F)) return;
   int fc[3];
@@ -309,27 +326,32 @@ __global__ __launch_bounds__(NT) void k_mg_correct(const MgGeo C, const MgGeo F,
   for (int a = 0; a < 3; a++) cc[a] = a < F.ndim ? fc[a] >> 1 : fc[a];
   const double w0 = F.ndim == 1 ? 0.75 : F.ndim == 2 ? 0.5 : 0.25;
   const long oc = mg_off(C, cc[0], cc[1], cc[2]);
-  const double e0 = mg_corr(C, uc, uoc, oc);
-  double s = w0 * e0;
   const long S[3] = {1, C.s1, C.s2};
 #pragma unroll
-  for (int a = 0; a < 3; a++) {
-    if (a >= F.ndim) continue;
-    const bool up = fc[a] & 1;
-    const int c = cc[a], n = C.n[a];
-    double e;
-    if (up ? c < n - 1 : c > 0) {
-      e = mg_corr(C, uc, uoc, up ? oc + S[a] : oc - S[a]);
-    } else {
-      const int kind = C.bc[a][up ? 1 : 0];
-      if (kind == GMUNU_MG_PERIODIC)
-        e = mg_corr(C, uc, uoc, up ? oc - (long)(n - 1) * S[a] : oc + (long)(n - 1) * S[a]);
-      else
-        e = kind == GMUNU_MG_DIRICHLET ? -e0 : kind == GMUNU_MG_NEUMANN ? e0 : e0 * (up ? C.rob_hi : C.rob_lo);
+  for (int q = 0; q < NC; q++) {
+    const double *uc = uc0 + q * C.nt, *uoc = uoc0 + q * C.nt;
+    double *fine = fine0 + q * F.nt;
+    const double e0 = mg_corr(C, uc, uoc, oc);
+    double s = w0 * e0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      if (a >= F.ndim) continue;
+      const bool up = fc[a] & 1;
+      const int c = cc[a], n = C.n[a];
+      double e;
+      if (up ? c < n - 1 : c > 0) {
+        e = mg_corr(C, uc, uoc, up ? oc + S[a] : oc - S[a]);
+      } else {
+        const int kind = C.bc[a][up ? 1 : 0];
+        if (kind == GMUNU_MG_PERIODIC)
+          e = mg_corr(C, uc, uoc, up ? oc - (long)(n - 1) * S[a] : oc + (long)(n - 1) * S[a]);
+        else
+          e = kind == GMUNU_MG_DIRICHLET ? -e0 : kind == GMUNU_MG_NEUMANN ? e0 : e0 * (up ? C.rob_hi : C.rob_lo);
+      }
+      s += 0.25 * e;
     }
-    s += 0.25 * e;
+    fine[mg_off(F, fc[0], fc[1], fc[2])] += s;
   }
-  fine[mg_off(F, fc[0], fc[1], fc[2])] += s;
 }
 
 // Kwak prolongation of v (coarse, ghosts set) into the fine interior:
@@ -383,6 +405,283 @@ __global__ __launch_bounds__(NT) void k_mg_subgrad(const MgGeo G, const double *
   if (G.ndim > 2) q[2 * G.nt + o] -= G.g2[I] * G.s2t[J] * (phi[o + G.s2] - phi[o - G.s2]) / (2.0 * G.h[2]);
 }
 
+// ------------------------------------------- vector equations of xCFC
+//
+// L(X)^i = Lap X^i + (1/3) d_i d_j X^j on Cartesian grids (section 2.6),
+// second differences and the four-point mixed difference of section 2.7.
+// The mixed stencil couples diagonal neighbours, so the Newton-Gauss-Seidel
+// smoother visits 2^ndim colours (i mod 2, j mod 2, k mod 2), one launch
+// each; cells of one colour are never neighbours, and the three components
+// of a cell do not enter each other's diagonal, so a colour updates all its
+// cells and components at once.  Across the boundary every axis applies its
+// own rule (mirror times -1 or +1, periodic wrap): a step from a cell along
+// an axis is an offset and a sign, and a diagonal neighbour takes the
+// product of the two steps' signs.
+
+struct VStep {
+  long dm[3], dp[3];
+  double fm[3], fp[3];
+};
+
+__device__ __forceinline__ void mgv_axis(const MgGeo &G, int c, int a, long S, bool up, long &d, double &f) {
+  const int n = G.n[a];
+  if (up ? c < n - 1 : c > 0) {
+    d = up ? S : -S;
+    f = 1.0;
+    return;
+  }
+  const int kind = G.bc[a][up ? 1 : 0];
+  if (kind == GMUNU_MG_PERIODIC) {
+    d = up ? -(long)(n - 1) * S : (long)(n - 1) * S;
+    f = 1.0;
+    return;
+  }
+  d = 0;
+  f = kind == GMUNU_MG_DIRICHLET ? -1.0 : 1.0;
+}
+
+__device__ __forceinline__ VStep mgv_steps(const MgGeo &G, int i, int j, int k) {
+  VStep s;
+  const int c[3] = {i, j, k};
+  const long S[3] = {1, G.s1, G.s2};
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    s.dm[a] = s.dp[a] = 0;
+    s.fm[a] = s.fp[a] = 0.0;
+    if (a >= G.ndim) continue;
+    mgv_axis(G, c[a], a, S[a], false, s.dm[a], s.fm[a]);
+    mgv_axis(G, c[a], a, S[a], true, s.dp[a], s.fp[a]);
+  }
+  return s;
+}
+
+// L(X) at interior cell offset o (all three components) and the diagonal
+// of each component's row.
+__device__ __forceinline__ void mgv_L(const MgGeo &G, const double *__restrict__ u, const VStep &s, long o,
+                                      double L[3], double dg[3]) {
+  const long nt = G.nt;
+  double d2[3][3];  // d2[q][a]: second difference of component q along axis a
+  double ih2[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) ih2[a] = 1.0 / (G.h[a] * G.h[a]);
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    const double *uq = u + q * nt;
+    const double u0 = uq[o];
+    double lap = 0.0, d = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      d2[q][a] = 0.0;
+      if (a >= G.ndim) continue;
+      d2[q][a] = (s.fp[a] * uq[o + s.dp[a]] - 2.0 * u0 + s.fm[a] * uq[o + s.dm[a]]) * ih2[a];
+      lap += d2[q][a];
+      d -= 2.0 * ih2[a];
+    }
+    L[q] = lap;
+    dg[q] = q < G.ndim ? d - (2.0 / 3.0) * ih2[q] : d;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    if (q >= G.ndim) continue;
+    double gd = d2[q][q];
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      if (b == q || b >= G.ndim) continue;
+      const double *ub = u + b * nt;
+      const double pp = s.fp[q] * s.fp[b] * ub[o + s.dp[q] + s.dp[b]];
+      const double pm = s.fp[q] * s.fm[b] * ub[o + s.dp[q] + s.dm[b]];
+      const double mp = s.fm[q] * s.fp[b] * ub[o + s.dm[q] + s.dp[b]];
+      const double mm = s.fm[q] * s.fm[b] * ub[o + s.dm[q] + s.dm[b]];
+      gd += (pp - pm - mp + mm) / (4.0 * G.h[q] * G.h[b]);
+    }
+    L[q] += gd / 3.0;
+  }
+}
+
+// Cells of colour `colour` (bit a: parity along axis a) on a level.
+__device__ __forceinline__ long mgv_colour_cells(const MgGeo &G, int colour) {
+  long n = 1;
+#pragma unroll
+  for (int a = 0; a < 3; a++) n *= a < G.ndim ? (G.n[a] - ((colour >> a) & 1) + 1) >> 1 : G.n[a];
+  return n;
+}
+
+__device__ __forceinline__ void mgv_smooth_one(const MgGeo &G, double *u, const double *__restrict__ f, int colour,
+                                               long t) {
+  const int ci = colour & 1, cj = (colour >> 1) & 1, ck = (colour >> 2) & 1;
+  const unsigned hx = (unsigned)(G.n[0] - ci + 1) >> 1;
+  const unsigned hy = G.ndim > 1 ? (unsigned)(G.n[1] - cj + 1) >> 1 : 1u;
+  const unsigned hz = G.ndim > 2 ? (unsigned)(G.n[2] - ck + 1) >> 1 : 1u;
+  if (t >= (long)hx * hy * hz) return;
+  const unsigned tt = (unsigned)t, r = tt / hx;
+  const int i = 2 * (int)(tt - r * hx) + ci;
+  const unsigned kk = r / hy;
+  const int j = G.ndim > 1 ? 2 * (int)(r - kk * hy) + cj : 0;
+  const int k = G.ndim > 2 ? 2 * (int)kk + ck : 0;
+  const long o = mg_off(G, i, j, k);
+  double L[3], dg[3];
+  mgv_L(G, u, mgv_steps(G, i, j, k), o, L, dg);
+#pragma unroll
+  for (int q = 0; q < 3; q++) u[q * G.nt + o] -= (L[q] - f[q * G.nt + o]) / dg[q];
+}
+
+__global__ __launch_bounds__(NT) void k_mgv_smooth(const MgGeo G, double *u, const double *__restrict__ f,
+                                                   int colour) {
+  mgv_smooth_one(G, u, f, colour, (long)blockIdx.x * NT + threadIdx.x);
+}
+
+// Coarsest level: all sweeps in one workgroup, colours separated by barriers.
+__global__ __launch_bounds__(NT) void k_mgv_coarse(const MgGeo G, double *u, const double *__restrict__ f,
+                                                   int sweeps) {
+  const int ncol = 1 << G.ndim;
+  for (int s = 0; s < sweeps; s++)
+    for (int c = 0; c < ncol; c++) {
+      const long nc = mgv_colour_cells(G, c);
+      for (long t = threadIdx.x; t < nc; t += NT) mgv_smooth_one(G, u, f, c, t);
+      __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_mgv_apply(const MgGeo G, const double *__restrict__ u,
+                                                  double *__restrict__ out) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(G)) return;
+  int i, j, k;
+  mg_cell(G, t, i, j, k);
+  const long o = mg_off(G, i, j, k);
+  double L[3], dg[3];
+  mgv_L(G, u, mgv_steps(G, i, j, k), o, L, dg);
+#pragma unroll
+  for (int q = 0; q < 3; q++) out[q * G.nt + o] = L[q];
+}
+
+__global__ __launch_bounds__(NT) void k_mgv_norm(const MgGeo G, const double *__restrict__ u,
+                                                 const double *__restrict__ f, double *part) {
+  double m = 0.0;
+  for (long t = (long)blockIdx.x * NT + threadIdx.x; t < mg_cells(G); t += (long)gridDim.x * NT) {
+    int i, j, k;
+    mg_cell(G, t, i, j, k);
+    const long o = mg_off(G, i, j, k);
+    double L[3], dg[3];
+    mgv_L(G, u, mgv_steps(G, i, j, k), o, L, dg);
+#pragma unroll
+    for (int q = 0; q < 3; q++) m = fmax(m, fabs(f[q * G.nt + o] - L[q]));
+  }
+  m = block_max(m);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+// Coarse problem of a fine level for the vector equation: the children's
+// residuals and values averaged into the coarse r and u (Cartesian cells
+// have equal volumes).
+__global__ __launch_bounds__(NT) void k_mgv_restrict_res(const MgGeo F, const MgGeo C, const double *__restrict__ u,
+                                                         const double *__restrict__ f, double *__restrict__ uc,
+                                                         double *__restrict__ rc) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(C)) return;
+  int i, j, k;
+  mg_cell(C, t, i, j, k);
+  double su[3] = {0.0, 0.0, 0.0}, sr[3] = {0.0, 0.0, 0.0};
+  const int nch = 1 << F.ndim;
+  for (int ch = 0; ch < nch; ch++) {
+    const int fi = 2 * i + (ch & 1);
+    const int fj = F.ndim > 1 ? 2 * j + ((ch >> 1) & 1) : j;
+    const int fk = F.ndim > 2 ? 2 * k + ((ch >> 2) & 1) : k;
+    const long o = mg_off(F, fi, fj, fk);
+    double L[3], dg[3];
+    mgv_L(F, u, mgv_steps(F, fi, fj, fk), o, L, dg);
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      su[q] += u[q * F.nt + o];
+      sr[q] += f[q * F.nt + o] - L[q];
+    }
+  }
+  const long oc = mg_off(C, i, j, k);
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    uc[q * C.nt + oc] = su[q] / nch;
+    rc[q * C.nt + oc] = sr[q] / nch;
+  }
+}
+
+// f_c = L_c(u_c) + r_c and uo_c = u_c.
+__global__ __launch_bounds__(NT) void k_mgv_fas_rhs(const MgGeo C, const double *__restrict__ u,
+                                                    const double *__restrict__ r, double *__restrict__ f,
+                                                    double *__restrict__ uo) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(C)) return;
+  int i, j, k;
+  mg_cell(C, t, i, j, k);
+  const long o = mg_off(C, i, j, k);
+  double L[3], dg[3];
+  mgv_L(C, u, mgv_steps(C, i, j, k), o, L, dg);
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    f[q * C.nt + o] = L[q] + r[q * C.nt + o];
+    uo[q * C.nt + o] = u[q * C.nt + o];
+  }
+}
+
+// A~^ij = d_i X^j + d_j X^i - (2/3) delta^ij d_k X^k (centred, boundary rule
+// across the boundary) as six components (xx yy zz xy xz yz), and
+// A~_ij A~^ij.
+__global__ __launch_bounds__(NT) void k_mgv_aij(const MgGeo G, const double *__restrict__ X, double *__restrict__ A6,
+                                                double *__restrict__ A2) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(G)) return;
+  int i, j, k;
+  mg_cell(G, t, i, j, k);
+  const long o = mg_off(G, i, j, k);
+  const VStep s = mgv_steps(G, i, j, k);
+  double g[3][3];  // g[a][b] = d_a X^b
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      const double *xb = X + b * G.nt;
+      g[a][b] = a < G.ndim ? (s.fp[a] * xb[o + s.dp[a]] - s.fm[a] * xb[o + s.dm[a]]) / (2.0 * G.h[a]) : 0.0;
+    }
+  const double dv = g[0][0] + g[1][1] + g[2][2];
+  double A[3][3], a2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      A[a][b] = g[a][b] + g[b][a] - (a == b ? 2.0 / 3.0 * dv : 0.0);
+      a2 += A[a][b] * A[a][b];
+    }
+  A6[o] = A[0][0];
+  A6[G.nt + o] = A[1][1];
+  A6[2 * G.nt + o] = A[2][2];
+  A6[3 * G.nt + o] = A[0][1];
+  A6[4 * G.nt + o] = A[0][2];
+  A6[5 * G.nt + o] = A[1][2];
+  A2[o] = a2;
+}
+
+// Source of the shift equation: 16 pi w S_i + 2 A~^ij d_j w, w = alpha
+// psi^-6 with its ghost entries as stored (centred gradient).
+__global__ __launch_bounds__(NT) void k_mgv_beta_rhs(const MgGeo G, const double *__restrict__ w,
+                                                     const double *__restrict__ S, const double *__restrict__ A6,
+                                                     double *__restrict__ out) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(G)) return;
+  int i, j, k;
+  mg_cell(G, t, i, j, k);
+  const long o = mg_off(G, i, j, k);
+  const long St[3] = {1, G.s1, G.s2};
+  double gw[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) gw[a] = a < G.ndim ? (w[o + St[a]] - w[o - St[a]]) / (2.0 * G.h[a]) : 0.0;
+  const long nt = G.nt;
+  const double axx = A6[o], ayy = A6[nt + o], azz = A6[2 * nt + o];
+  const double axy = A6[3 * nt + o], axz = A6[4 * nt + o], ayz = A6[5 * nt + o];
+  const double wc = 16.0 * M_PI * w[o];
+  out[o] = wc * S[o] + 2.0 * (axx * gw[0] + axy * gw[1] + axz * gw[2]);
+  out[nt + o] = wc * S[nt + o] + 2.0 * (axy * gw[0] + ayy * gw[1] + ayz * gw[2]);
+  out[2 * nt + o] = wc * S[2 * nt + o] + 2.0 * (axz * gw[0] + ayz * gw[1] + azz * gw[2]);
+}
+
 // ------------------------------------------------- bridge to the GRMHD state
 
 // Layout of a GRMHD state array (include/gmunu.h: [var][k][j][i], ng ghost
@@ -425,14 +724,17 @@ __global__ __launch_bounds__(NT) void k_br_scatter_qb(const MgGeo G, const Hydro
   for (int c = 0; c < 3; c++) q[(5 + c) * H.nv + o] = qb[c * G.nt + m];
 }
 
-// Coefficient of the scalar CFC equations (section 2.6) on the interior:
-// which 0 (conformal factor): a = -2 pi U~ with U~ = q_tau + q_D;
-// which 1 (lapse): a = 2 pi (U~ + 2 S~) / psi^2 with S~ = psi^6 (rho h W^2 v^2
-// + 3 p) from the primitives (fluid part) and psi from the metric.  u: the
-// initial guess u = psi - 1, or alpha psi - 1, from the metric.
+// Coefficients of the scalar CFC equations (section 2.6) on the interior:
+// which 0 (conformal factor): a = -2 pi U~ with U~ = q_tau + q_D, and with
+// A2 = A~_ij A~^ij given, a2 = -A2 / 8 (the term in psi^-7);
+// which 1 (lapse): a = 2 pi (U~ + 2 S~) / psi^2 (+ (7/8) A2 psi^-8) with
+// S~ = psi^6 (rho h W^2 v^2 + 3 p) from the primitives (fluid part) and psi
+// from the metric.  u: the initial guess u = psi - 1, or alpha psi - 1, from
+// the metric.
 __global__ __launch_bounds__(NT) void k_br_cfc_coef(const MgGeo G, const Hydro H, const double *__restrict__ q,
                                                     const double *__restrict__ prim, const double *__restrict__ met,
-                                                    int which, double *__restrict__ a, double *__restrict__ u) {
+                                                    int which, const double *__restrict__ A2, double *__restrict__ a,
+                                                    double *__restrict__ a2, double *__restrict__ u) {
   const long t = (long)blockIdx.x * NT + threadIdx.x;
   if (t >= mg_cells(G)) return;
   int i, j, k;
@@ -442,6 +744,7 @@ __global__ __launch_bounds__(NT) void k_br_cfc_coef(const MgGeo G, const Hydro H
   const double psi = met[o];
   if (which == 0) {
     a[m] = -2.0 * M_PI * Ut;
+    if (A2) a2[m] = -A2[m] / 8.0;
     u[m] = psi - 1.0;
     return;
   }
@@ -459,14 +762,59 @@ __global__ __launch_bounds__(NT) void k_br_cfc_coef(const MgGeo G, const Hydro H
   const double rho = prim[o], p = prim[4 * H.nv + o];
   const double rhoh = rho + H.gam / (H.gam - 1.0) * p;
   const double St = psi4 * psi2 * (rhoh * w2v2 + 3.0 * p);
-  a[m] = 2.0 * M_PI * (Ut + 2.0 * St) / psi2;
+  double av = 2.0 * M_PI * (Ut + 2.0 * St) / psi2;
+  if (A2) av += 7.0 / 8.0 * A2[m] / (psi4 * psi4);
+  a[m] = av;
   u[m] = met[H.nv + o] * psi - 1.0;
+}
+
+// Momentum source of the vector equations: S[c] = q_{S_c} (= psi^6 S_c, the
+// rescaled S~_c of section 2.6; Cartesian, so f^ij S~_j = S~_i) and
+// fX = 8 pi S on the interior.
+__global__ __launch_bounds__(NT) void k_bx_src(const MgGeo G, const Hydro H, const double *__restrict__ q,
+                                               double *__restrict__ S, double *__restrict__ fX) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(G)) return;
+  int i, j, k;
+  mg_cell(G, t, i, j, k);
+  const long o = hy_off(H, i, j, k), m = mg_off(G, i, j, k);
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    const double v = q[(1 + c) * H.nv + o];
+    S[c * G.nt + m] = v;
+    fX[c * G.nt + m] = 8.0 * M_PI * v;
+  }
+}
+
+// w = alpha psi^-6 on every entry of the multigrid layout (its ghost layer
+// from the metric's first ghost layer).
+__global__ __launch_bounds__(NT) void k_bx_w(const MgGeo G, const Hydro H, const double *__restrict__ met,
+                                             double *__restrict__ w) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= G.nt) return;
+  const int I = (int)(t % G.s1), J = (int)((t / G.s1) % (G.s2 / G.s1)), K = (int)(t / G.s2);
+  const long o = hy_off(H, I - G.g[0], J - G.g[1], K - G.g[2]);
+  const double psi = met[o], psi2 = psi * psi;
+  w[t] = met[H.nv + o] / (psi2 * psi2 * psi2);
+}
+
+// The metric's shift on the interior as the initial guess of its solve.
+__global__ __launch_bounds__(NT) void k_bx_beta_in(const MgGeo G, const Hydro H, const double *__restrict__ met,
+                                                   double *__restrict__ beta) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(G)) return;
+  int i, j, k;
+  mg_cell(G, t, i, j, k);
+  const long o = hy_off(H, i, j, k), m = mg_off(G, i, j, k);
+#pragma unroll
+  for (int c = 0; c < 3; c++) beta[c * G.nt + m] = met[(2 + c) * H.nv + o];
 }
 
 // Metric of every GRMHD cell (ng ghost layers included) from the solution u
 // of level G, ghost layers extended by the multigrid boundary rule applied
 // per layer (mirror about the face times -1, +1 or r_in / r_ghost; periodic
-// wrap): which 0 writes psi = 1 + u, which 1 alpha = (1 + u) / psi.
+// wrap): which 0 writes psi = 1 + u, which 1 alpha = (1 + u) / psi, which
+// 2..4 the shift component beta^(which - 2) = u.
 __global__ __launch_bounds__(NT) void k_br_store(const MgGeo G, const Hydro H, const double *__restrict__ u,
                                                  double xmin0, int which, double *__restrict__ met) {
   const long t = (long)blockIdx.x * NT + threadIdx.x;
@@ -489,11 +837,13 @@ __global__ __launch_bounds__(NT) void k_br_store(const MgGeo G, const Hydro H, c
     if (kind == GMUNU_MG_ROBIN) fac *= (xmin0 + (in + 0.5) * G.h[0]) / (xmin0 + (c[a] + 0.5) * G.h[0]);
     c[a] = in;
   }
-  const double v = 1.0 + fac * u[mg_off(G, c[0], c[1], c[2])];
+  const double v = fac * u[mg_off(G, c[0], c[1], c[2])];
   if (which == 0)
-    met[t] = v;
+    met[t] = 1.0 + v;
+  else if (which == 1)
+    met[H.nv + t] = (1.0 + v) / met[t];
   else
-    met[H.nv + t] = v / met[t];
+    met[which * H.nv + t] = v;
 }
 
 }  // namespace
@@ -507,24 +857,43 @@ struct gmunu_mg {
   // a[l] is NULL when the equation has no a)
   double *u[kMaxLevels], *f[kMaxLevels], *a[kMaxLevels], *r[kMaxLevels], *uo[kMaxLevels];
   double *aown[kMaxLevels];  // coarse-level storage of a
+  double *a2[kMaxLevels], *a2own[kMaxLevels];  // the same for a2 (allocated when power2 != 0)
   double *part;  // norm partials + result
   double *br;    // state bridge scratch (6 arrays of the finest level), allocated on first use
+  // vector equations (Cartesian): per coarse level u, f, r, uo of three
+  // components each, allocated on first use; xs: scratch of the xCFC
+  // sequence (17 finest arrays), allocated on first use
+  double *vu[kMaxLevels], *vf[kMaxLevels], *vr[kMaxLevels], *vuo[kMaxLevels];
+  bool vready;
+  double *xs;
   std::vector<double *> owned;
-  // V-cycles are replayed from a graph captured on a private stream for the
-  // finest arrays (u, f, a) they were captured with
+  // V-cycles are replayed from graphs captured on a private stream, each for
+  // the finest arrays it was captured with (two per kind of equation)
   hipStream_t gs;
   hipEvent_t ev;
-  hipGraphExec_t vexec;
-  const double *gu, *gf, *ga;
+  struct Slot {
+    hipGraphExec_t exec;
+    bool vec;
+    const double *u, *f, *a, *a2;
+  } slot[4];
+  int next_slot;
 };
 
 namespace {
+
+// Axis a after L halvings: divisible, at least two cells, and an even count
+// on a periodic axis (an odd count would give the cells on either side of
+// the wrap the same colour, and a colour's cells would not be independent).
+bool coarsens(const gmunu_mg_desc &d, int a, int L) {
+  const int n = d.n[a] >> L;
+  return d.n[a] % (1 << L) == 0 && n >= 2 && (d.bc[a][0] != GMUNU_MG_PERIODIC || n % 2 == 0);
+}
 
 int auto_levels(const gmunu_mg_desc &d) {
   int L = 1;
   for (;;) {
     bool ok = L < kMaxLevels;
-    for (int a = 0; a < d.ndim && ok; a++) ok = d.n[a] % (1 << L) == 0 && (d.n[a] >> L) >= 2;
+    for (int a = 0; a < d.ndim && ok; a++) ok = coarsens(d, a, L);
     if (!ok) return L;
     L++;
   }
@@ -538,8 +907,7 @@ int validate(const gmunu_mg_desc &d, int levels) {
       if (d.n[a] != 1) return GMUNU_EINVAL;
       continue;
     }
-    if (d.n[a] < 1 || !(d.dx[a] > 0.0) || d.n[a] % (1 << (levels - 1)) != 0 || (d.n[a] >> (levels - 1)) < 2)
-      return GMUNU_EINVAL;
+    if (d.n[a] < 1 || !(d.dx[a] > 0.0) || !coarsens(d, a, levels - 1)) return GMUNU_EINVAL;
     for (int s = 0; s < 2; s++) {
       const int b = d.bc[a][s];
       if (b < GMUNU_MG_DIRICHLET || b > GMUNU_MG_ROBIN) return GMUNU_EINVAL;
@@ -551,6 +919,7 @@ int validate(const gmunu_mg_desc &d, int levels) {
   if (d.coord == GMUNU_SPH && d.ndim > 1 && (d.xmin[1] < 0.0 || d.xmin[1] + d.n[1] * d.dx[1] > M_PI + 1e-12))
     return GMUNU_EINVAL;
   if (d.power < -1 || d.power > 1 || d.pre < 0 || d.post < 0 || d.coarse < 1) return GMUNU_EINVAL;
+  if (d.power2 < -8 || d.power2 > 8) return GMUNU_EINVAL;
   // cell numbers of a level fit 32-bit kernel arithmetic
   if ((double)(d.n[0] + 2) * (d.n[1] + 2) * (d.n[2] + 2) >= 2147483647.0) return GMUNU_EINVAL;
   return GMUNU_OK;
@@ -621,6 +990,7 @@ void level_tables(const gmunu_mg_desc &d, int s, std::vector<double> &tab, size_
   G.rob_lo = xin_lo / xg_lo;
   G.rob_hi = xin_hi / xg_hi;
   G.power = d.power;
+  G.power2 = d.power2;
   G.offset = d.offset;
 }
 
@@ -637,20 +1007,22 @@ long cells(const MgGeo &G) { return (long)G.n[0] * G.n[1] * G.n[2]; }
 
 void ghosts(const MgGeo &G, double *u, hipStream_t st) {
   const long gc = ghost_count(G);
-  if (gc) hipLaunchKernelGGL(k_mg_ghosts, dim3(nblocks(gc)), dim3(NT), 0, st, G, u);
+  if (gc) hipLaunchKernelGGL(k_mg_ghosts<1>, dim3(nblocks(gc)), dim3(NT), 0, st, G, u);
 }
 
 // Red-black sweeps (boundary rule inline: no ghost fill between colours).
-void sweeps_raw(const MgGeo &G, double *u, const double *f, const double *a, int sweeps, hipStream_t st) {
+void sweeps_raw(const MgGeo &G, double *u, const double *f, const double *a, const double *a2, int sweeps,
+                hipStream_t st) {
   const long threads = (long)((G.n[0] + 1) / 2) * G.n[1] * G.n[2];
   for (int s = 0; s < sweeps; s++)
     for (int c = 0; c < 2; c++)
-      hipLaunchKernelGGL(k_mg_smooth, dim3(nblocks(threads)), dim3(NT), 0, st, G, u, f, a, c);
+      hipLaunchKernelGGL(k_mg_smooth, dim3(nblocks(threads)), dim3(NT), 0, st, G, u, f, a, a2, c);
 }
 
 // The same, then u's ghost entries from the boundary rule.
-void smooth(const MgGeo &G, double *u, const double *f, const double *a, int sweeps, hipStream_t st) {
-  sweeps_raw(G, u, f, a, sweeps, st);
+void smooth(const MgGeo &G, double *u, const double *f, const double *a, const double *a2, int sweeps,
+            hipStream_t st) {
+  sweeps_raw(G, u, f, a, a2, sweeps, st);
   ghosts(G, u, st);
 }
 
@@ -659,15 +1031,15 @@ void smooth(const MgGeo &G, double *u, const double *f, const double *a, int swe
 void coarse_problem(gmunu_mg *m, int l, hipStream_t st) {
   const MgGeo &F = m->geo[l], &C = m->geo[l - 1];
   hipLaunchKernelGGL(k_mg_restrict_res, dim3(nblocks(cells(C))), dim3(NT), 0, st, F, C, m->u[l], m->f[l], m->a[l],
-                     m->u[l - 1], m->r[l - 1]);
+                     m->a2[l], m->u[l - 1], m->r[l - 1]);
   hipLaunchKernelGGL(k_mg_fas_rhs, dim3(nblocks(cells(C))), dim3(NT), 0, st, C, m->u[l - 1], m->a[l - 1],
-                     m->r[l - 1], m->f[l - 1], m->uo[l - 1]);
+                     m->a2[l - 1], m->r[l - 1], m->f[l - 1], m->uo[l - 1]);
 }
 
 // u_l += P(u_{l-1} - uo_{l-1})
 void correct(gmunu_mg *m, int l, hipStream_t st) {
   const MgGeo &F = m->geo[l], &C = m->geo[l - 1];
-  hipLaunchKernelGGL(k_mg_correct, dim3(nblocks(cells(F))), dim3(NT), 0, st, C, F, m->u[l - 1], m->uo[l - 1],
+  hipLaunchKernelGGL(k_mg_correct<1>, dim3(nblocks(cells(F))), dim3(NT), 0, st, C, F, m->u[l - 1], m->uo[l - 1],
                      m->u[l]);
 }
 
@@ -675,9 +1047,9 @@ void correct(gmunu_mg *m, int l, hipStream_t st) {
 void coarse_solve(gmunu_mg *m, hipStream_t st) {
   const MgGeo &G = m->geo[0];
   if (cells(G) <= 64L * NT)
-    hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(NT), 0, st, G, m->u[0], m->f[0], m->a[0], m->d.coarse);
+    hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(NT), 0, st, G, m->u[0], m->f[0], m->a[0], m->a2[0], m->d.coarse);
   else
-    sweeps_raw(G, m->u[0], m->f[0], m->a[0], m->d.coarse, st);
+    sweeps_raw(G, m->u[0], m->f[0], m->a[0], m->a2[0], m->d.coarse, st);
 }
 
 void vcycle(gmunu_mg *m, int l, hipStream_t st) {
@@ -685,11 +1057,11 @@ void vcycle(gmunu_mg *m, int l, hipStream_t st) {
     coarse_solve(m, st);
     return;
   }
-  sweeps_raw(m->geo[l], m->u[l], m->f[l], m->a[l], m->d.pre, st);
+  sweeps_raw(m->geo[l], m->u[l], m->f[l], m->a[l], m->a2[l], m->d.pre, st);
   coarse_problem(m, l, st);
   vcycle(m, l - 1, st);
   correct(m, l, st);
-  sweeps_raw(m->geo[l], m->u[l], m->f[l], m->a[l], m->d.post, st);
+  sweeps_raw(m->geo[l], m->u[l], m->f[l], m->a[l], m->a2[l], m->d.post, st);
 }
 
 void fmg(gmunu_mg *m, hipStream_t st) {
@@ -707,7 +1079,8 @@ int norm(gmunu_mg *m, double *out, hipStream_t st) {
   const MgGeo &G = m->geo[top];
   const long nb = nblocks(cells(G));
   const int np = (int)(nb < kNormParts ? nb : kNormParts);
-  hipLaunchKernelGGL(k_mg_norm, dim3(np), dim3(NT), 0, st, G, m->u[top], m->f[top], m->a[top], m->part);
+  hipLaunchKernelGGL(k_mg_norm, dim3(np), dim3(NT), 0, st, G, m->u[top], m->f[top], m->a[top], m->a2[top],
+                     m->part);
   hipLaunchKernelGGL(k_mg_norm_finish, dim3(1), dim3(NT), 0, st, m->part, np);
   if (hipMemcpyAsync(out, m->part + kNormParts, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
@@ -715,21 +1088,212 @@ int norm(gmunu_mg *m, double *out, hipStream_t st) {
   return launch_status();
 }
 
-// Bind the caller's finest-level arrays and restrict a to the coarse levels.
-void bind(gmunu_mg *m, double *u, const double *f, const double *a, hipStream_t st) {
+// Bind the caller's finest-level arrays and restrict a and a2 to the coarse
+// levels.
+void bind(gmunu_mg *m, double *u, const double *f, const double *a, const double *a2, hipStream_t st) {
   const int top = m->levels - 1;
   m->u[top] = u;
   m->f[top] = const_cast<double *>(f);
   m->a[top] = const_cast<double *>(a);
+  m->a2[top] = const_cast<double *>(a2);
   for (int l = top; l > 0; l--) {
     m->a[l - 1] = a ? m->aown[l - 1] : nullptr;
+    m->a2[l - 1] = a2 ? m->a2own[l - 1] : nullptr;
     if (a)
       hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(cells(m->geo[l - 1]))), dim3(NT), 0, st, m->geo[l],
                          m->geo[l - 1], m->a[l], m->a[l - 1]);
+    if (a2)
+      hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(cells(m->geo[l - 1]))), dim3(NT), 0, st, m->geo[l],
+                         m->geo[l - 1], m->a2[l], m->a2[l - 1]);
   }
 }
 
+// a2 is accepted only by a hierarchy whose equation has the second term.
+bool a2_ok(const gmunu_mg *m, const double *a2) { return !a2 || (m->d.power2 != 0 && aligned8(a2)); }
+
 bool ok_ptr(const void *p) { return p && aligned8(p); }
+
+// ----------------------------------------------- vector-equation cycles
+
+long colour_cells(const MgGeo &G, int c) {
+  long n = 1;
+  for (int a = 0; a < 3; a++) n *= a < G.ndim ? (G.n[a] - ((c >> a) & 1) + 1) >> 1 : G.n[a];
+  return n;
+}
+
+void vsweeps(const MgGeo &G, double *u, const double *f, int sweeps, hipStream_t st) {
+  const int ncol = 1 << G.ndim;
+  for (int s = 0; s < sweeps; s++)
+    for (int c = 0; c < ncol; c++)
+      hipLaunchKernelGGL(k_mgv_smooth, dim3(nblocks(colour_cells(G, c))), dim3(NT), 0, st, G, u, f, c);
+}
+
+void vghosts(const MgGeo &G, double *u, hipStream_t st) {
+  const long gc = ghost_count(G);
+  if (gc) hipLaunchKernelGGL(k_mg_ghosts<3>, dim3(nblocks(gc)), dim3(NT), 0, st, G, u);
+}
+
+void vcoarse_problem(gmunu_mg *m, int l, hipStream_t st) {
+  const MgGeo &F = m->geo[l], &C = m->geo[l - 1];
+  hipLaunchKernelGGL(k_mgv_restrict_res, dim3(nblocks(cells(C))), dim3(NT), 0, st, F, C, m->vu[l], m->vf[l],
+                     m->vu[l - 1], m->vr[l - 1]);
+  hipLaunchKernelGGL(k_mgv_fas_rhs, dim3(nblocks(cells(C))), dim3(NT), 0, st, C, m->vu[l - 1], m->vr[l - 1],
+                     m->vf[l - 1], m->vuo[l - 1]);
+}
+
+void vcorrect(gmunu_mg *m, int l, hipStream_t st) {
+  const MgGeo &F = m->geo[l], &C = m->geo[l - 1];
+  hipLaunchKernelGGL(k_mg_correct<3>, dim3(nblocks(cells(F))), dim3(NT), 0, st, C, F, m->vu[l - 1], m->vuo[l - 1],
+                     m->vu[l]);
+}
+
+void vcoarse_solve(gmunu_mg *m, hipStream_t st) {
+  const MgGeo &G = m->geo[0];
+  if (cells(G) <= 64L * NT)
+    hipLaunchKernelGGL(k_mgv_coarse, dim3(1), dim3(NT), 0, st, G, m->vu[0], m->vf[0], m->d.coarse);
+  else
+    vsweeps(G, m->vu[0], m->vf[0], m->d.coarse, st);
+}
+
+void vvcycle(gmunu_mg *m, int l, hipStream_t st) {
+  if (l == 0) {
+    vcoarse_solve(m, st);
+    return;
+  }
+  vsweeps(m->geo[l], m->vu[l], m->vf[l], m->d.pre, st);
+  vcoarse_problem(m, l, st);
+  vvcycle(m, l - 1, st);
+  vcorrect(m, l, st);
+  vsweeps(m->geo[l], m->vu[l], m->vf[l], m->d.post, st);
+}
+
+void vfmg(gmunu_mg *m, hipStream_t st) {
+  const int top = m->levels - 1;
+  for (int l = top; l > 0; l--) vcoarse_problem(m, l, st);
+  vcoarse_solve(m, st);
+  for (int l = 1; l <= top; l++) {
+    vcorrect(m, l, st);
+    vvcycle(m, l, st);
+  }
+}
+
+int vnorm(gmunu_mg *m, double *out, hipStream_t st) {
+  const int top = m->levels - 1;
+  const MgGeo &G = m->geo[top];
+  const long nb = nblocks(cells(G));
+  const int np = (int)(nb < kNormParts ? nb : kNormParts);
+  hipLaunchKernelGGL(k_mgv_norm, dim3(np), dim3(NT), 0, st, G, m->vu[top], m->vf[top], m->part);
+  hipLaunchKernelGGL(k_mg_norm_finish, dim3(1), dim3(NT), 0, st, m->part, np);
+  if (hipMemcpyAsync(out, m->part + kNormParts, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return GMUNU_EHIP;
+  return launch_status();
+}
+
+bool alloc_zeroed(gmunu_mg *m, size_t n, double **out) {
+  double *p = nullptr;
+  if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) return false;
+  if (hipMemset(p, 0, n * sizeof(double)) != hipSuccess) {
+    (void)hipFree(p);
+    return false;
+  }
+  m->owned.push_back(p);
+  *out = p;
+  return true;
+}
+
+bool vector_storage(gmunu_mg *m) {
+  if (m->vready) return true;
+  for (int l = 0; l < m->levels - 1; l++) {
+    const size_t n = 3 * (size_t)m->geo[l].nt;
+    if (!alloc_zeroed(m, n, &m->vu[l]) || !alloc_zeroed(m, n, &m->vf[l]) || !alloc_zeroed(m, n, &m->vr[l]) ||
+        !alloc_zeroed(m, n, &m->vuo[l]))
+      return false;
+  }
+  m->vready = true;
+  return true;
+}
+
+// ------------------------------------------------- solve driver
+
+// The private stream is ordered after the caller's work on entry and the
+// caller's stream after the private one on exit.
+int enter(gmunu_mg *m, hipStream_t cst) {
+  if (!m->gs && hipStreamCreateWithFlags(&m->gs, hipStreamNonBlocking) != hipSuccess) return GMUNU_EHIP;
+  if (!m->ev && hipEventCreateWithFlags(&m->ev, hipEventDisableTiming) != hipSuccess) return GMUNU_EHIP;
+  if (hipEventRecord(m->ev, cst) != hipSuccess || hipStreamWaitEvent(m->gs, m->ev, 0) != hipSuccess)
+    return GMUNU_EHIP;
+  return GMUNU_OK;
+}
+
+int leave(gmunu_mg *m, hipStream_t cst) {
+  if (hipEventRecord(m->ev, m->gs) != hipSuccess || hipStreamWaitEvent(cst, m->ev, 0) != hipSuccess)
+    return GMUNU_EHIP;
+  return launch_status();
+}
+
+// The graph of one V-cycle over the bound arrays: a cached one, else
+// captured now into the least recently made slot (launches only: no
+// memset, no host synchronisation inside).
+hipGraphExec_t cycle_graph(gmunu_mg *m, bool vec, const double *u, const double *f, const double *a,
+                           const double *a2) {
+  for (auto &sl : m->slot)
+    if (sl.exec && sl.vec == vec && sl.u == u && sl.f == f && sl.a == a && sl.a2 == a2) return sl.exec;
+  auto &sl = m->slot[m->next_slot];
+  m->next_slot = (m->next_slot + 1) % 4;
+  if (sl.exec) {
+    (void)hipGraphExecDestroy(sl.exec);
+    sl.exec = nullptr;
+  }
+  hipStream_t st = m->gs;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+  if (vec)
+    vvcycle(m, m->levels - 1, st);
+  else
+    vcycle(m, m->levels - 1, st);
+  if (hipStreamEndCapture(st, &g) != hipSuccess) return nullptr;
+  const bool ok = hipGraphInstantiate(&sl.exec, g, nullptr, nullptr, 0) == hipSuccess;
+  (void)hipGraphDestroy(g);
+  if (!ok) {
+    sl.exec = nullptr;
+    return nullptr;
+  }
+  sl.vec = vec;
+  sl.u = u;
+  sl.f = f;
+  sl.a = a;
+  sl.a2 = a2;
+  return sl.exec;
+}
+
+// Cycles until the norm is at most tol (arrays bound); the first one an FMG
+// cycle when use_fmg.
+int cycles(gmunu_mg *m, bool vec, hipGraphExec_t exec, double tol, int max_cycles, int use_fmg, double *res_host,
+           int *cycles_out) {
+  hipStream_t st = m->gs;
+  double r;
+  int rc = vec ? vnorm(m, &r, st) : norm(m, &r, st);
+  if (rc) return rc;
+  if (res_host) res_host[0] = r;
+  int c = 0;
+  while (c < max_cycles && r > tol) {
+    if (c == 0 && use_fmg) {
+      if (vec)
+        vfmg(m, st);
+      else
+        fmg(m, st);
+    } else if (hipGraphLaunch(exec, st) != hipSuccess) {
+      return GMUNU_EHIP;
+    }
+    c++;
+    rc = vec ? vnorm(m, &r, st) : norm(m, &r, st);
+    if (rc) return rc;
+    if (res_host) res_host[c] = r;
+  }
+  if (cycles_out) *cycles_out = c;
+  return GMUNU_OK;
+}
 
 }  // namespace
 
@@ -756,10 +1320,12 @@ int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out) {
     return p;
   };
   m->br = nullptr;
+  m->xs = nullptr;
+  m->vready = false;
   m->gs = nullptr;
   m->ev = nullptr;
-  m->vexec = nullptr;
-  m->gu = m->gf = m->ga = nullptr;
+  for (auto &sl : m->slot) sl = gmunu_mg::Slot{nullptr, false, nullptr, nullptr, nullptr, nullptr};
+  m->next_slot = 0;
   bool ok = (m->tab = alloc(tab.size())) != nullptr && (m->part = alloc(kNormParts + 1)) != nullptr;
   // coarse levels: u, f, a, r (restricted residual) and uo (restricted u);
   // the finest level only uo (the cleaning's divergence when the caller
@@ -768,8 +1334,10 @@ int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out) {
     const size_t nt = (size_t)m->geo[l].nt;
     ok = (m->uo[l] = alloc(nt)) != nullptr;
     m->r[l] = nullptr;
+    m->a2own[l] = nullptr;
     if (ok && l < levels - 1)
       ok = (m->r[l] = alloc(nt)) && (m->u[l] = alloc(nt)) && (m->f[l] = alloc(nt)) && (m->aown[l] = alloc(nt));
+    if (ok && l < levels - 1 && desc->power2 != 0) ok = (m->a2own[l] = alloc(nt)) != nullptr;
   }
   ok = ok && hipMemcpy(m->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
   // zero every owned level array (ghosts of coarse arrays are then defined)
@@ -778,7 +1346,8 @@ int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out) {
     ok = hipMemset(m->uo[l], 0, b) == hipSuccess;
     if (ok && l < levels - 1)
       ok = hipMemset(m->r[l], 0, b) == hipSuccess && hipMemset(m->u[l], 0, b) == hipSuccess &&
-           hipMemset(m->f[l], 0, b) == hipSuccess && hipMemset(m->aown[l], 0, b) == hipSuccess;
+           hipMemset(m->f[l], 0, b) == hipSuccess && hipMemset(m->aown[l], 0, b) == hipSuccess &&
+           (!m->a2own[l] || hipMemset(m->a2own[l], 0, b) == hipSuccess);
   }
   ok = ok && hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
@@ -808,7 +1377,8 @@ int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out) {
 int gmunu_mg_destroy(gmunu_mg *m) {
   if (!m) return GMUNU_ENULL;
   int rc = GMUNU_OK;
-  if (m->vexec && hipGraphExecDestroy(m->vexec) != hipSuccess) rc = GMUNU_EHIP;
+  for (auto &sl : m->slot)
+    if (sl.exec && hipGraphExecDestroy(sl.exec) != hipSuccess) rc = GMUNU_EHIP;
   if (m->ev && hipEventDestroy(m->ev) != hipSuccess) rc = GMUNU_EHIP;
   if (m->gs && hipStreamDestroy(m->gs) != hipSuccess) rc = GMUNU_EHIP;
   for (double *p : m->owned)
@@ -824,77 +1394,44 @@ long gmunu_mg_size(const gmunu_mg *m, int level) {
   return m->geo[level].nt;
 }
 
-int gmunu_mg_solve(gmunu_mg *m, double *u, const double *f, const double *a, double tol, int max_cycles, int use_fmg,
-                   double *res_host, int *cycles_out, void *stream) {
+int gmunu_mg_solve(gmunu_mg *m, double *u, const double *f, const double *a, const double *a2, double tol,
+                   int max_cycles, int use_fmg, double *res_host, int *cycles_out, void *stream) {
   if (!m || !u || !f) return GMUNU_ENULL;
   if (!ok_ptr(u) || !ok_ptr(f) || (a && !aligned8(a))) return GMUNU_EALIGN;
-  if (max_cycles < 0 || !(tol >= 0.0)) return GMUNU_EINVAL;
+  if (max_cycles < 0 || !(tol >= 0.0) || !a2_ok(m, a2)) return GMUNU_EINVAL;
   // the cycles run on the context's stream, ordered after the caller's work
   hipStream_t cst = as_stream(stream);
-  if (!m->gs && hipStreamCreateWithFlags(&m->gs, hipStreamNonBlocking) != hipSuccess) return GMUNU_EHIP;
-  if (!m->ev && hipEventCreateWithFlags(&m->ev, hipEventDisableTiming) != hipSuccess) return GMUNU_EHIP;
-  hipStream_t st = m->gs;
-  if (hipEventRecord(m->ev, cst) != hipSuccess || hipStreamWaitEvent(st, m->ev, 0) != hipSuccess) return GMUNU_EHIP;
-  bind(m, u, f, a, st);
-  if (!m->vexec || m->gu != u || m->gf != f || m->ga != a) {
-    // capture one V-cycle over the arrays just bound (launches only: no
-    // memset, no host synchronisation inside)
-    if (m->vexec) {
-      (void)hipGraphExecDestroy(m->vexec);
-      m->vexec = nullptr;
-    }
-    hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return GMUNU_EHIP;
-    vcycle(m, m->levels - 1, st);
-    if (hipStreamEndCapture(st, &g) != hipSuccess) return GMUNU_EHIP;
-    const bool ok = hipGraphInstantiate(&m->vexec, g, nullptr, nullptr, 0) == hipSuccess;
-    (void)hipGraphDestroy(g);
-    if (!ok) {
-      m->vexec = nullptr;
-      return GMUNU_EHIP;
-    }
-    m->gu = u;
-    m->gf = f;
-    m->ga = a;
-  }
-  double r;
-  int rc = norm(m, &r, st);
+  int rc = enter(m, cst);
   if (rc) return rc;
-  if (res_host) res_host[0] = r;
-  int c = 0;
-  while (c < max_cycles && r > tol) {
-    if (c == 0 && use_fmg)
-      fmg(m, st);
-    else if (hipGraphLaunch(m->vexec, st) != hipSuccess)
-      return GMUNU_EHIP;
-    c++;
-    rc = norm(m, &r, st);
-    if (rc) return rc;
-    if (res_host) res_host[c] = r;
-  }
-  if (cycles_out) *cycles_out = c;
-  ghosts(m->geo[m->levels - 1], u, st);
-  if (hipEventRecord(m->ev, st) != hipSuccess || hipStreamWaitEvent(cst, m->ev, 0) != hipSuccess) return GMUNU_EHIP;
-  return launch_status();
+  bind(m, u, f, a, a2, m->gs);
+  hipGraphExec_t exec = cycle_graph(m, false, u, f, a, a2);
+  if (!exec) return GMUNU_EHIP;
+  rc = cycles(m, false, exec, tol, max_cycles, use_fmg, res_host, cycles_out);
+  if (rc) return rc;
+  ghosts(m->geo[m->levels - 1], u, m->gs);
+  return leave(m, cst);
 }
 
-int gmunu_mg_residual_norm(gmunu_mg *m, double *u, const double *f, const double *a, double *norm_out,
-                           void *stream) {
+int gmunu_mg_residual_norm(gmunu_mg *m, double *u, const double *f, const double *a, const double *a2,
+                           double *norm_out, void *stream) {
   if (!m || !u || !f || !norm_out) return GMUNU_ENULL;
   if (!ok_ptr(u) || !ok_ptr(f) || (a && !aligned8(a))) return GMUNU_EALIGN;
+  if (!a2_ok(m, a2)) return GMUNU_EINVAL;
   hipStream_t st = as_stream(stream);
   const int top = m->levels - 1;
   m->u[top] = u;
   m->f[top] = const_cast<double *>(f);
   m->a[top] = const_cast<double *>(a);
+  m->a2[top] = const_cast<double *>(a2);
   return norm(m, norm_out, st);
 }
 
-int gmunu_mg_apply(gmunu_mg *m, const double *u, const double *a, double *out, void *stream) {
+int gmunu_mg_apply(gmunu_mg *m, const double *u, const double *a, const double *a2, double *out, void *stream) {
   if (!m || !u || !out) return GMUNU_ENULL;
   if (!ok_ptr(u) || !ok_ptr(out) || (a && !aligned8(a))) return GMUNU_EALIGN;
+  if (!a2_ok(m, a2)) return GMUNU_EINVAL;
   const MgGeo &G = m->geo[m->levels - 1];
-  hipLaunchKernelGGL(k_mg_apply, dim3(nblocks(cells(G))), dim3(NT), 0, as_stream(stream), G, u, a, out);
+  hipLaunchKernelGGL(k_mg_apply, dim3(nblocks(cells(G))), dim3(NT), 0, as_stream(stream), G, u, a, a2, out);
   return launch_status();
 }
 
@@ -906,11 +1443,12 @@ int gmunu_mg_fill_ghosts(gmunu_mg *m, int level, double *u, void *stream) {
   return launch_status();
 }
 
-int gmunu_mg_smooth(gmunu_mg *m, double *u, const double *f, const double *a, int sweeps, void *stream) {
+int gmunu_mg_smooth(gmunu_mg *m, double *u, const double *f, const double *a, const double *a2, int sweeps,
+                    void *stream) {
   if (!m || !u || !f) return GMUNU_ENULL;
   if (!ok_ptr(u) || !ok_ptr(f) || (a && !aligned8(a))) return GMUNU_EALIGN;
-  if (sweeps < 0) return GMUNU_EINVAL;
-  smooth(m->geo[m->levels - 1], u, f, a, sweeps, as_stream(stream));
+  if (sweeps < 0 || !a2_ok(m, a2)) return GMUNU_EINVAL;
+  smooth(m->geo[m->levels - 1], u, f, a, a2, sweeps, as_stream(stream));
   return launch_status();
 }
 
@@ -960,10 +1498,71 @@ int gmunu_mg_clean(gmunu_mg *m, double *q, double *phi, double *div, double tol,
   double *f = div ? div : m->uo[top];
   int rc = gmunu_mg_divergence(m, q, f, stream);
   if (rc) return rc;
-  rc = gmunu_mg_solve(m, phi, f, nullptr, tol, max_cycles, 1, res_host, cycles_out, stream);
+  rc = gmunu_mg_solve(m, phi, f, nullptr, nullptr, tol, max_cycles, 1, res_host, cycles_out, stream);
   if (rc) return rc;
   ghosts(m->geo[top], phi, as_stream(stream));
   return gmunu_mg_subtract_gradient(m, phi, q, stream);
+}
+
+// ------------------------------------------------ vector equations (xCFC)
+
+int gmunu_mg_vapply(gmunu_mg *m, const double *X, double *out, void *stream) {
+  if (!m || !X || !out) return GMUNU_ENULL;
+  if (!ok_ptr(X) || !ok_ptr(out)) return GMUNU_EALIGN;
+  if (m->d.coord != GMUNU_CART) return GMUNU_EINVAL;
+  const MgGeo &G = m->geo[m->levels - 1];
+  hipLaunchKernelGGL(k_mgv_apply, dim3(nblocks(cells(G))), dim3(NT), 0, as_stream(stream), G, X, out);
+  return launch_status();
+}
+
+int gmunu_mg_vsmooth(gmunu_mg *m, double *X, const double *f, int sweeps, void *stream) {
+  if (!m || !X || !f) return GMUNU_ENULL;
+  if (!ok_ptr(X) || !ok_ptr(f)) return GMUNU_EALIGN;
+  if (m->d.coord != GMUNU_CART || sweeps < 0) return GMUNU_EINVAL;
+  const MgGeo &G = m->geo[m->levels - 1];
+  hipStream_t st = as_stream(stream);
+  vsweeps(G, X, f, sweeps, st);
+  vghosts(G, X, st);
+  return launch_status();
+}
+
+int gmunu_mg_vsolve(gmunu_mg *m, double *X, const double *f, double tol, int max_cycles, int use_fmg,
+                    double *res_host, int *cycles_out, void *stream) {
+  if (!m || !X || !f) return GMUNU_ENULL;
+  if (!ok_ptr(X) || !ok_ptr(f)) return GMUNU_EALIGN;
+  if (m->d.coord != GMUNU_CART || max_cycles < 0 || !(tol >= 0.0)) return GMUNU_EINVAL;
+  if (!vector_storage(m)) return GMUNU_ENOMEM;
+  hipStream_t cst = as_stream(stream);
+  int rc = enter(m, cst);
+  if (rc) return rc;
+  const int top = m->levels - 1;
+  m->vu[top] = X;
+  m->vf[top] = const_cast<double *>(f);
+  hipGraphExec_t exec = cycle_graph(m, true, X, f, nullptr, nullptr);
+  if (!exec) return GMUNU_EHIP;
+  rc = cycles(m, true, exec, tol, max_cycles, use_fmg, res_host, cycles_out);
+  if (rc) return rc;
+  vghosts(m->geo[top], X, m->gs);
+  return leave(m, cst);
+}
+
+int gmunu_mg_xcfc_aij(gmunu_mg *m, const double *X, double *A6, double *A2, void *stream) {
+  if (!m || !X || !A6 || !A2) return GMUNU_ENULL;
+  if (!ok_ptr(X) || !ok_ptr(A6) || !ok_ptr(A2)) return GMUNU_EALIGN;
+  if (m->d.coord != GMUNU_CART) return GMUNU_EINVAL;
+  const MgGeo &G = m->geo[m->levels - 1];
+  hipLaunchKernelGGL(k_mgv_aij, dim3(nblocks(cells(G))), dim3(NT), 0, as_stream(stream), G, X, A6, A2);
+  return launch_status();
+}
+
+int gmunu_mg_xcfc_beta_rhs(gmunu_mg *m, const double *w, const double *S, const double *A6, double *out,
+                           void *stream) {
+  if (!m || !w || !S || !A6 || !out) return GMUNU_ENULL;
+  if (!ok_ptr(w) || !ok_ptr(S) || !ok_ptr(A6) || !ok_ptr(out)) return GMUNU_EALIGN;
+  if (m->d.coord != GMUNU_CART) return GMUNU_EINVAL;
+  const MgGeo &G = m->geo[m->levels - 1];
+  hipLaunchKernelGGL(k_mgv_beta_rhs, dim3(nblocks(cells(G))), dim3(NT), 0, as_stream(stream), G, w, S, A6, out);
+  return launch_status();
 }
 
 }  // extern "C"
@@ -989,6 +1588,30 @@ int hydro_of(const gmunu_mg *m, const gmunu_grid_desc *hd, Hydro &H) {
   H.nv = H.T1 * T[2];
   H.gam = hd->gamma;
   return GMUNU_OK;
+}
+
+bool bridge_scratch(gmunu_mg *m);
+
+// Steps 3 to 5 of the xCFC sequence (A2 = A~_ij A~^ij, or NULL for the
+// scalar CFC equations alone): psi from its equation, S~ with the new psi,
+// then alpha psi; psi and alpha written to the metric.  cyc: 2 ints.
+int scalar_cfc(gmunu_mg *mpsi, gmunu_mg *malpha, const Hydro &H, const double *q, const double *prim,
+               double *metric, const double *A2, double tol, int max_cycles, int *cyc, hipStream_t st) {
+  gmunu_mg *ms[2] = {mpsi, malpha};
+  const MgGeo &G0 = mpsi->geo[mpsi->levels - 1];
+  double *u = mpsi->br, *a = mpsi->br + G0.nt, *f = mpsi->br + 2 * G0.nt, *a2 = mpsi->br + 3 * G0.nt;
+  for (int w = 0; w < 2; w++) {
+    gmunu_mg *m = ms[w];
+    const MgGeo &G = m->geo[m->levels - 1];
+    if (hipMemsetAsync(f, 0, (size_t)G0.nt * sizeof(double), st) != hipSuccess) return GMUNU_EHIP;
+    hipLaunchKernelGGL(k_br_cfc_coef, dim3(nblocks(cells(G))), dim3(NT), 0, st, G, H, q, prim, metric, w, A2, a, a2,
+                       u);
+    const int rc = gmunu_mg_solve(m, u, f, a, w == 0 && A2 ? a2 : nullptr, tol, max_cycles, 1, nullptr, &cyc[w],
+                                  (void *)st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_br_store, dim3(nblocks(H.nv)), dim3(NT), 0, st, G, H, u, m->d.xmin[0], w, metric);
+  }
+  return launch_status();
 }
 
 bool bridge_scratch(gmunu_mg *m) {
@@ -1041,24 +1664,55 @@ int gmunu_mg_cfc_solve(gmunu_mg *mpsi, gmunu_mg *malpha, const gmunu_grid_desc *
   if (mpsi->d.power != -1 || mpsi->d.offset != 1.0 || malpha->d.power != 1 || malpha->d.offset != 1.0)
     return GMUNU_EINVAL;
   if (!bridge_scratch(mpsi)) return GMUNU_ENOMEM;
-  hipStream_t st = as_stream(stream);
   int cyc[2] = {0, 0};
-  gmunu_mg *ms[2] = {mpsi, malpha};
-  for (int w = 0; w < 2; w++) {
-    gmunu_mg *m = ms[w];
-    const MgGeo &G = m->geo[m->levels - 1];
-    const MgGeo &G0 = mpsi->geo[mpsi->levels - 1];
-    double *u = mpsi->br, *a = mpsi->br + G0.nt, *f = mpsi->br + 2 * G0.nt;
-    if (hipMemsetAsync(f, 0, (size_t)G0.nt * sizeof(double), st) != hipSuccess) return GMUNU_EHIP;
-    hipLaunchKernelGGL(k_br_cfc_coef, dim3(nblocks(cells(G))), dim3(NT), 0, st, G, H, q, prim, metric, w, a, u);
-    rc = gmunu_mg_solve(m, u, f, a, tol, max_cycles, 1, nullptr, &cyc[w], stream);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_br_store, dim3(nblocks(H.nv)), dim3(NT), 0, st, G, H, u, m->d.xmin[0], w, metric);
-  }
-  if (cycles_out) {
+  rc = scalar_cfc(mpsi, malpha, H, q, prim, metric, nullptr, tol, max_cycles, cyc, as_stream(stream));
+  if (!rc && cycles_out) {
     cycles_out[0] = cyc[0];
     cycles_out[1] = cyc[1];
   }
+  return rc;
+}
+
+int gmunu_mg_xcfc_solve(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, const gmunu_grid_desc *hydro,
+                        const double *q, const double *prim, double *metric, double *X, double tol, int max_cycles,
+                        int *cycles_out, void *stream) {
+  if (!mvec || !mpsi || !malpha || !hydro || !q || !prim || !metric || !X) return GMUNU_ENULL;
+  if (!aligned8(q) || !aligned8(prim) || !aligned8(metric) || !aligned8(X)) return GMUNU_EALIGN;
+  Hydro H, H2, H3;
+  int rc = hydro_of(mpsi, hydro, H);
+  if (!rc) rc = hydro_of(malpha, hydro, H2);
+  if (!rc) rc = hydro_of(mvec, hydro, H3);
+  if (rc) return rc;
+  if (mvec->d.coord != GMUNU_CART || mpsi->d.power != -1 || mpsi->d.offset != 1.0 || mpsi->d.power2 != -7 ||
+      malpha->d.power != 1 || malpha->d.offset != 1.0)
+    return GMUNU_EINVAL;
+  if (!bridge_scratch(mpsi) || !vector_storage(mvec)) return GMUNU_ENOMEM;
+  const MgGeo &G = mvec->geo[mvec->levels - 1];
+  if (!mvec->xs && !alloc_zeroed(mvec, 17 * (size_t)G.nt, &mvec->xs)) return GMUNU_ENOMEM;
+  hipStream_t st = as_stream(stream);
+  double *S = mvec->xs, *fv = S + 3 * G.nt, *beta = S + 6 * G.nt, *A6 = S + 9 * G.nt, *A2 = S + 15 * G.nt,
+         *w = S + 16 * G.nt;
+  int cyc[4] = {0, 0, 0, 0};
+  // step 1: the vector potential
+  hipLaunchKernelGGL(k_bx_src, dim3(nblocks(cells(G))), dim3(NT), 0, st, G, H, q, S, fv);
+  rc = gmunu_mg_vsolve(mvec, X, fv, tol, max_cycles, 1, nullptr, &cyc[0], stream);
+  if (rc) return rc;
+  // step 2: A~^ij
+  hipLaunchKernelGGL(k_mgv_aij, dim3(nblocks(cells(G))), dim3(NT), 0, st, G, X, A6, A2);
+  // steps 3 to 5: conformal factor and lapse
+  rc = scalar_cfc(mpsi, malpha, H, q, prim, metric, A2, tol, max_cycles, &cyc[1], st);
+  if (rc) return rc;
+  // step 6: the shift
+  hipLaunchKernelGGL(k_bx_w, dim3(nblocks(G.nt)), dim3(NT), 0, st, G, H, metric, w);
+  hipLaunchKernelGGL(k_mgv_beta_rhs, dim3(nblocks(cells(G))), dim3(NT), 0, st, G, w, S, A6, fv);
+  hipLaunchKernelGGL(k_bx_beta_in, dim3(nblocks(cells(G))), dim3(NT), 0, st, G, H, metric, beta);
+  rc = gmunu_mg_vsolve(mvec, beta, fv, tol, max_cycles, 1, nullptr, &cyc[3], stream);
+  if (rc) return rc;
+  for (int c = 0; c < 3; c++)
+    hipLaunchKernelGGL(k_br_store, dim3(nblocks(H.nv)), dim3(NT), 0, st, G, H, beta + c * G.nt, mvec->d.xmin[0],
+                       2 + c, metric);
+  if (cycles_out)
+    for (int c = 0; c < 4; c++) cycles_out[c] = cyc[c];
   return launch_status();
 }
 

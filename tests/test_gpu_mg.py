@@ -20,6 +20,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_2012_07322_amd as gmu
 from oracle import mg
 
@@ -216,7 +217,8 @@ def test_invalid_descriptors_are_rejected():
            prob(2, CART, (16, 16), (0, 0), (1, 1), [[ROB, D], [D, D]]),            # Robin in Cartesian
            prob(2, SPH, (16, 16), (0, 0), (1, 1), [[N, D], [ROB, D]]),             # Robin off axis 0
            prob(2, CART, (16, 16), (0, 0), (1, 1), [[PER, D], [D, D]]),            # one-sided periodic
-           prob(2, CART, (16, 16), (0, 0), (1, 1), [[D, D], [D, D]], power=2)]
+           prob(2, CART, (16, 16), (0, 0), (1, 1), [[D, D], [D, D]], power=2),
+           prob(2, CART, (12, 16), (0, 0), (1, 1), [[PER, PER], [D, D]], levels=3)]  # 3 periodic cells
     for p in bad:
         with pytest.raises(RuntimeError):
             gmu.Multigrid(p)
@@ -241,10 +243,9 @@ def test_clean_state_matches_the_oracle():
     pr[7] = pi * s(pi * x) * s(pi * y) * c(pi * z)
     met = W.flat_metric(hp)
     met[0] = 1.0 + 0.1 * s(2 * pi * x) * c(pi * y)
-    g = gmu.Grid(hp)
     prd, metd = dev(pr), dev(met)
-    q = g.prim2con(prd, metd)
-    q0 = host(q).copy()
+    q0 = oracle.prim2con(hp, pr, met)  # the state's conserved variables, from the oracle
+    q = dev(q0)
     mp = prob(3, CART, (n, n, n), (0, 0, 0), (1, 1, 1), [[D, D]] * 3)
     M = gmu.Multigrid(mp)
     hist = M.clean_state(hp, q, prd, metd, tol=1e-12, max_cycles=40)
@@ -281,10 +282,10 @@ def test_cfc_solve_recovers_the_tov_metric():
     errs = []
     for nr, nth in ((64, 16), (128, 32)):
         hp, pr, met = W.magnetised_star_2d(nr, nth, b_peak=1e-12)
-        g = gmu.Grid(hp)
+        pr = oracle.fill_ghosts(hp, np.ascontiguousarray(pr))
         prd, metd = dev(pr), dev(met)
-        g.fill_ghosts(prd)
-        q = g.prim2con(prd, metd)
+        qh = oracle.prim2con(hp, pr, met)
+        q = dev(qh)
         exact = met.copy()
         metd[0].fill_(1.0)
         metd[1].fill_(1.0)
@@ -300,7 +301,6 @@ def test_cfc_solve_recovers_the_tov_metric():
         note(f"  TOV {nr}x{nth}: cycles {cyc}, |psi err| {e_psi:.2e}, |alpha err| {e_al:.2e}")
         errs.append((e_psi, e_al))
         # parity of the psi solve with the oracle on the same coefficient
-        qh = host(q)
         a = np.zeros(mg.shape(dict(mp)))
         a[0, 1:-1, 1:-1] = -2 * math.pi * (qh[4] + qh[0])[0, gh:gh + nth, gh:gh + nr]
         uo = np.zeros(mg.shape(dict(mp)))
@@ -309,3 +309,205 @@ def test_cfc_solve_recovers_the_tov_metric():
         assert np.abs(1.0 + mg.interior(po, uo)[0] - m[0][sl][0]).max() <= 1e-9
     assert errs[1][0] < 2e-4 and errs[1][1] < 4e-4
     assert errs[0][0] / errs[1][0] > 2.5 and errs[0][1] / errs[1][1] > 2.5
+
+
+# ------------------------------------- second non-linear term (power2)
+
+@pytest.mark.parametrize("case", ["cart3d", "sph2d"])
+def test_second_term_operator_sweep_and_solve_parity(case):
+    """L(u) = Lap(u) - a (u + c)^-1 - a2 (u + c)^-7 (the conformal-factor
+    equation with its extrinsic-curvature term): operator, two sweeps and a
+    solve against the oracle."""
+    p = dict(CASES[case], power=-1, power2=-7, offset=2.0)
+    M = gmu.Multigrid(p)
+    u, f = random_field(p, 11), random_field(p, 12)
+    a, a2 = random_field(p, 13) * 0.1, random_field(p, 14) * 0.1
+    uo = mg.fill_ghosts(p, u.copy())
+    Lg = mg.interior(p, host(M.apply(dev(uo), dev(a), a2=dev(a2))))
+    Lo = mg.interior(p, mg.apply(p, uo, a, a2))
+    assert np.abs(Lg - Lo).max() <= 1e-12 * np.abs(Lo).max()
+    ug = dev(u)
+    M.smooth(ug, dev(f), dev(a), sweeps=2, a2=dev(a2))
+    so = mg.smooth(p, u.copy(), f, a, sweeps=2, a2=a2)
+    assert np.abs(host(ug) - so).max() <= 1e-12 * np.abs(so).max()
+    x, y, z = mg.centres(p)
+    f = np.ascontiguousarray(np.exp(-x * x - y * y) - 0.3)
+    ug = torch.zeros(M.shape(), dtype=torch.float64, device="cuda")
+    hg = M.solve(ug, dev(f), dev(a), tol=1e-11, max_cycles=100, a2=dev(a2))
+    uo = np.zeros(mg.shape(p))
+    ho = mg.solve(p, uo, f, a, tol=1e-11, max_cycles=100, a2=a2)
+    note(f"  {case}: cycles gpu {len(hg) - 1} oracle {len(ho) - 1}")
+    assert hg[-1] <= 1e-11 and ho[-1] <= 1e-11
+    scale = np.abs(mg.interior(p, uo)).max()
+    assert np.abs(mg.interior(p, host(ug)) - mg.interior(p, uo)).max() <= 1e-10 * scale
+
+
+# ------------------------------------------ vector equations of xCFC
+
+VCASES = {
+    "cart3d": prob(3, CART, (16, 8, 8), (0, 0, 0), (1, 0.5, 0.5), [[D, N], [PER, PER], [D, D]]),
+    "cart3d_ragged": prob(3, CART, (12, 20, 6), (0, 0, 0), (1.2, 2.0, 0.6), [[PER, PER], [N, D], [D, D]]),
+    "cart2d": prob(2, CART, (16, 16), (0, 0), (1, 1), [[D, D], [PER, PER]]),
+    "cart1d": prob(1, CART, (32,), (0,), (1,), [[D, N]]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(VCASES))
+def test_vector_operator_and_sweep_parity(case):
+    """L(X) and two four-/eight-colour sweeps against the oracle (values
+    across the boundary by the axis rules on both sides)."""
+    p = VCASES[case]
+    M = gmu.Multigrid(p)
+    X, f = random_field(p, 21, True), random_field(p, 22, True)
+    Lg = host(M.vapply(dev(X)))
+    Lo = mg.vapply(p, np.ascontiguousarray(X))
+    for i in range(3):
+        assert np.abs(mg.interior(p, Lg[i]) - mg.interior(p, Lo[i])).max() <= 1e-12 * np.abs(Lo).max(), i
+    Xg = dev(X)
+    M.vsmooth(Xg, dev(f), sweeps=2)
+    Xo = mg.vsmooth(p, X.copy(), f, sweeps=2)
+    g = host(Xg)
+    for i in range(3):
+        assert np.abs(mg.interior(p, g[i]) - mg.interior(p, Xo[i])).max() <= 1e-12 * np.abs(Xo).max(), i
+
+
+@pytest.mark.parametrize("case", sorted(VCASES))
+def test_vector_solve_parity(case):
+    p = VCASES[case]
+    M = gmu.Multigrid(p)
+    x, y, z = mg.centres(p)
+    f = np.ascontiguousarray(np.stack([np.exp(-((x - 0.4) ** 2 + (y - 0.2) ** 2) * 10), np.sin(3 * x) * np.cos(2 * y),
+                                       0.5 + 0.0 * x]))
+    Xg = M.empty(vector=True)
+    hg = M.vsolve(Xg, dev(f), tol=1e-11, max_cycles=60)
+    Xo = np.zeros((3,) + mg.shape(p))
+    ho = mg.vsolve(p, Xo, f, tol=1e-11, max_cycles=60)
+    note(f"  {case}: cycles gpu {len(hg) - 1} oracle {len(ho) - 1}, final {hg[-1]:.2e}")
+    assert hg[-1] <= 1e-11 and ho[-1] <= 1e-11
+    g = host(Xg)
+    scale = np.abs(Xo).max()
+    for i in range(3):
+        assert np.abs(mg.interior(p, g[i]) - mg.interior(p, Xo[i])).max() <= 1e-10 * scale, i
+        # ghosts written from the boundary rule
+        assert np.array_equal(g[i], mg.fill_ghosts(p, g[i].copy())), i
+    for a, b in zip(hg, ho):
+        if b < 1e-5:
+            break
+        assert abs(a - b) <= 1e-6 * b, (a, b)
+
+
+def test_xcfc_aij_and_shift_source_parity():
+    p = VCASES["cart3d_ragged"]
+    M = gmu.Multigrid(p)
+    X = random_field(p, 31, True)
+    A6g, A2g = M.xcfc_aij(dev(X))
+    A6o, A2o = mg.xcfc_aij(p, np.ascontiguousarray(X))
+    A6g, A2g = host(A6g), host(A2g)
+    for q in range(6):
+        assert np.abs(mg.interior(p, A6g[q]) - mg.interior(p, A6o[q])).max() <= 1e-13 * np.abs(A6o).max(), q
+    assert np.abs(mg.interior(p, A2g) - mg.interior(p, A2o)).max() <= 1e-13 * np.abs(A2o).max()
+    w = 1.0 + 0.3 * random_field(p, 32)
+    S = random_field(p, 33, True)
+    og = host(M.xcfc_beta_rhs(dev(w), dev(S), dev(A6o)))
+    oo = mg.xcfc_beta_rhs(p, np.ascontiguousarray(w), np.ascontiguousarray(S), A6o)
+    for i in range(3):
+        assert np.abs(mg.interior(p, og[i]) - mg.interior(p, oo[i])).max() <= 1e-13 * np.abs(oo).max(), i
+
+
+def test_vector_large_grid_cycle_rate():
+    """256^3 vector problem (Dirichlet box): the residual falls by a steady
+    factor per V(2,2)-cycle (< 0.3 asserted) down to 1e-9 of the source."""
+    n = 256
+    p = prob(3, CART, (n, n, n), (-1, -1, -1), (1, 1, 1), [[D, D]] * 3)
+    M = gmu.Multigrid(p)
+    sh = M.shape()
+    ax = [(torch.arange(sh[2 - a], dtype=torch.float64, device="cuda") - 0.5) * p["dx"][a] - 1 for a in range(3)]
+    X, Y, Z = ax[0].view(1, 1, -1), ax[1].view(1, -1, 1), ax[2].view(-1, 1, 1)
+    e = torch.exp(-8 * (X * X + Y * Y + Z * Z))
+    f = torch.stack([e * X, e * Y, e * (1 + Z)]).contiguous()
+    Xg = M.empty(vector=True)
+    hist = M.vsolve(Xg, f, tol=1e-9, max_cycles=30)
+    rates = [hist[i + 1] / hist[i] for i in range(1, len(hist) - 1)]
+    note(f"  vector 256^3: {len(hist) - 1} cycles, rates {['%.3f' % r for r in rates]}")
+    assert hist[-1] <= 1e-9
+    assert max(rates) < 0.3
+
+
+def test_vector_and_second_term_misuse_is_rejected():
+    M = gmu.Multigrid(CASES["sph2d"])
+    with pytest.raises(RuntimeError):
+        M.vapply(M.empty(vector=True))
+    M2 = gmu.Multigrid(CASES["cart3d"])  # power2 = 0: no second term
+    u = M2.empty()
+    with pytest.raises(RuntimeError):
+        M2.apply(u, None, a2=u)
+    with pytest.raises(RuntimeError):
+        gmu.Multigrid(dict(CASES["cart3d"], power2=9))
+
+
+def test_xcfc_solve_matches_the_oracle():
+    """The full xCFC metric solve of a rotating, self-gravitating blob on a
+    Cartesian grid (conserved variables from the oracle's prim2con on a flat
+    initial metric): X, psi, alpha and beta^i against the oracle's
+    sequence, interior and the first ghost layer; a second call from the
+    converged metric and X needs at most one cycle per equation and leaves
+    the metric unchanged."""
+    import workloads as W
+    n = 32
+    hp = W.grid(3, W.CART, [n] * 3, [-1, -1, -1], [1, 1, 1], [[W.OUTFLOW, W.OUTFLOW]] * 3, gamma=2.0)
+    x, y, z = W.centres(hp)
+    r2 = x * x + y * y + z * z
+    e = np.exp(-r2 / 0.15)
+    pr = W.empty_prim(hp)
+    pr[0] = 1e-4 + 0.02 * e
+    pr[4] = 100.0 * pr[0] ** 2
+    env = np.exp(-r2 / 0.3)
+    pr[1], pr[2], pr[3] = -0.3 * y * env, 0.3 * x * env, 0.05 * x * env
+    met = W.flat_metric(hp)
+    q = oracle.prim2con(hp, pr, met)
+    base = dict(ndim=3, coord=CART, n=[n] * 3, xmin=[-1.0] * 3, dx=[2.0 / n] * 3, bc=[[D, D]] * 3)
+    pv, ps, pa = dict(base), dict(base, power=-1, power2=-7, offset=1.0), dict(base, power=1, offset=1.0)
+    Mv, Mp, Ma = gmu.Multigrid(pv), gmu.Multigrid(ps), gmu.Multigrid(pa)
+    Xg = Mv.empty(vector=True)
+    metd = dev(met)
+    cyc = gmu.xcfc_solve(Mv, Mp, Ma, hp, dev(q), dev(pr), metd, Xg, tol=1e-12, max_cycles=60)
+    note(f"  xCFC 32^3: cycles (X, psi, alpha psi, beta) {cyc}")
+    mg_g = host(metd).copy()
+    # oracle: the same sources on the multigrid layout
+    gh = hp["ng"]
+    inner = (slice(gh, gh + n),) * 3
+
+    def to_mg(a):
+        out = np.zeros(mg.shape(pv))
+        out[1:-1, 1:-1, 1:-1] = a[inner]
+        return out
+
+    U = to_mg(q[4] + q[0])
+    S = np.ascontiguousarray(np.stack([to_mg(q[1 + i]) for i in range(3)]))
+    rho, P = to_mg(pr[0]), to_mg(pr[4])
+    wv = [to_mg(pr[1 + i]) for i in range(3)]
+    Xo, beta = np.zeros((3,) + mg.shape(pv)), np.zeros((3,) + mg.shape(pv))
+    up, ua = np.zeros(mg.shape(pv)), np.zeros(mg.shape(pv))
+    psi, alpha, cyc_o = mg.xcfc_solve(pv, ps, pa, U, S, lambda ps_: mg.fluid_stilde(ps_, rho, wv, P, 2.0), Xo, up, ua,
+                                      beta, tol=1e-12, max_cycles=60)
+    note(f"  oracle cycles {cyc_o}")
+    Xh = host(Xg)
+    I = lambda a: mg.interior(pv, a)  # noqa: E731
+    assert max(np.abs(I(Xh[i]) - I(Xo[i])).max() for i in range(3)) <= 1e-10 * np.abs(Xo).max()
+    one = (slice(gh - 1, gh + n + 1),) * 3  # interior plus the first ghost layer
+    face = np.zeros(psi.shape, bool)
+    face[1:-1, 1:-1, :] = face[1:-1, :, 1:-1] = face[:, 1:-1, 1:-1] = True  # no edges or corners
+    err_psi = np.abs(mg_g[0][one] - psi)[face].max()
+    err_al = np.abs(mg_g[1][one] - alpha)[face].max()
+    assert err_psi <= 1e-10 * np.abs(psi - 1).max(), err_psi
+    assert err_al <= 1e-10 * np.abs(alpha - 1).max(), err_al
+    bscale = np.abs(beta).max()
+    assert bscale > 1e-4  # the rotation drives a shift
+    for i in range(3):
+        bo = mg.fill_ghosts(pv, beta[i].copy())
+        assert np.abs(mg_g[2 + i][one] - bo)[face].max() <= 1e-10 * bscale, i
+    assert I(psi).min() > 1.0 and I(alpha).max() < 1.0
+    # warm start: converged input
+    cyc2 = gmu.xcfc_solve(Mv, Mp, Ma, hp, dev(q), dev(pr), metd, Xg, tol=1e-11, max_cycles=60)
+    assert max(cyc2) <= 1, cyc2
+    assert np.abs(host(metd) - mg_g).max() <= 1e-9 * max(bscale, np.abs(psi - 1).max())
