@@ -443,6 +443,70 @@ def bench_mg(n=256, half=200.0, vcycles=8, sweeps=10):
     return out
 
 
+def bench_xcfc(n=256, half=24.0, omega=0.01, sweeps=10):
+    """The xCFC metric solve of section 2.6 (steps 1 to 6: X, psi, alpha psi,
+    beta) for a uniformly rotating polytropic star on a Cartesian n^3 box,
+    from the flat initial guess (psi = alpha = 1, beta = X = 0) to a residual
+    of 1e-10 per equation; the conserved variables are those of the star on
+    its TOV metric.  Also times sweeps of the vector smoother on the finest
+    level (eight colour launches per sweep; algorithmic bytes 72 per cell:
+    X read and written, f read, three components)."""
+    import torch
+
+    import paper_2012_07322_amd as gmu
+    import workloads as W
+
+    log(f"[bench] xCFC: rotating star on {n}^3")
+    hp, pr, met = W.rotating_star_3d(n, half, omega)
+    g = gmu.Grid(hp)
+    prd = torch.from_numpy(pr).cuda()
+    metd = torch.from_numpy(met).cuda()
+    del pr
+    q = g.prim2con(prd, metd)
+    base = dict(ndim=3, coord=0, n=[n] * 3, xmin=[-half] * 3, dx=[2.0 * half / n] * 3, bc=[[0, 0]] * 3)
+    Mv = gmu.Multigrid(base)
+    Mp = gmu.Multigrid(dict(base, power=-1, power2=-7, offset=1.0))
+    Ma = gmu.Multigrid(dict(base, power=1, offset=1.0))
+    X = Mv.empty(vector=True)
+    flat = torch.from_numpy(W.flat_metric(hp)).cuda()
+    tol = 1e-10
+    metd.copy_(flat)
+    gmu.xcfc_solve(Mv, Mp, Ma, hp, q, prd, metd, X, tol=tol, max_cycles=60)  # warm-up: code objects, graphs
+    metd.copy_(flat)
+    X.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cyc = gmu.xcfc_solve(Mv, Mp, Ma, hp, q, prd, metd, X, tol=tol, max_cycles=60)
+    torch.cuda.synchronize()
+    ms_solve = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    cyc_warm = gmu.xcfc_solve(Mv, Mp, Ma, hp, q, prd, metd, X, tol=tol, max_cycles=60)
+    torch.cuda.synchronize()
+    ms_warm = (time.perf_counter() - t0) * 1e3
+    m = metd[:, 2:-2, 2:-2, 2:-2]
+    shift = float(m[2:5].abs().max())
+    f = torch.zeros_like(X)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    Mv.vsmooth(X, f, sweeps=sweeps)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms_sweep = ev[0].elapsed_time(ev[1]) / sweeps
+    gbs = 72.0 * n ** 3 / (ms_sweep * 1e-3) / 1e9
+    out = {"workload": f"rotating polytropic star (K=100, Gamma=2, rho_c=1.28e-3, omega={omega:g}), Cartesian {n}^3 "
+                       f"on [-{half:g},{half:g}]^3, Dirichlet faces, flat initial guess",
+           "tolerance": tol, "ms_per_solve": ms_solve, "cycles_X_psi_alphapsi_beta": list(cyc),
+           "ms_per_warm_solve": ms_warm, "warm_cycles": list(cyc_warm),
+           "psi_centre": float(m[0].max()), "alpha_centre": float(m[1].min()), "max_shift": shift,
+           "vector_smoother": {"ms_per_sweep": ms_sweep, "bytes_per_cell_sweep": 72, "achieved_GBps": gbs,
+                               "peak_GBps": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS}}
+    log(f"[bench] xCFC: solve {ms_solve:.1f} ms, cycles {cyc}, warm {ms_warm:.1f} ms {cyc_warm}, vector sweep "
+        f"{ms_sweep:.3f} ms ({gbs:.0f} GB/s), max |beta| {shift:.2e}")
+    for M in (Mv, Mp, Ma):
+        M.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -462,6 +526,7 @@ def main():
     ap.add_argument("--serve-plain", type=int, default=300)
     ap.add_argument("--serve-plain-open", type=int, default=100)
     ap.add_argument("--mg", type=int, default=256, help="multigrid grid size (0: skip)")
+    ap.add_argument("--xcfc", type=int, default=256, help="xCFC metric-solve grid size (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -562,6 +627,9 @@ def main():
         torch.cuda.empty_cache()
     if args.mg > 0:
         out["multigrid"] = bench_mg(args.mg)
+        torch.cuda.empty_cache()
+    if args.xcfc > 0:
+        out["xcfc"] = bench_xcfc(args.xcfc)
         torch.cuda.empty_cache()
     if args.serve_requests > 0:
         out["serving"] = bench_serve(args.serve_requests, probe=args.serve_probe, plain_n=args.serve_plain,

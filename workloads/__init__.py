@@ -456,6 +456,41 @@ def lapse_equation(n=256, half=200.0, rho_c=1.28e-3, K=100.0, Gamma=2.0):
     return p, a
 
 
+def rotating_star_3d(n=256, half=24.0, omega=0.01, rho_c=1.28e-3, K=100.0, Gamma=2.0, rho_atmo=1e-10, star=None):
+    """Uniformly rotating polytropic star on a Cartesian n^3 box
+    [-half, half]^3 for the xCFC metric solve: the TOV profile (isotropic
+    coordinates) with angular velocity omega about z inside the star
+    (v^x = -omega y, v^y = omega x in the Eulerian frame, W from the TOV
+    conformal factor), atmosphere outside, no field.  Returns the grid
+    parameters, the primitives and the TOV metric (psi, alpha; zero shift),
+    built slab by slab to bound the temporaries."""
+    if star is None:
+        star = tov_isotropic(rho_c, K, Gamma)
+    p = grid(3, CART, [n] * 3, [-half] * 3, [half] * 3, [[OUTFLOW, OUTFLOW]] * 3, gamma=Gamma, rk=3,
+             rho_atmo=rho_atmo, k_atmo=K, gamma_atmo=Gamma)
+    g = ghosts(p)[0]
+    h = 2.0 * half / n
+    x = -half + (np.arange(-g, n + g) + 0.5) * h
+    shp = shape(p)
+    prim = np.zeros((8,) + shp)
+    met = np.zeros((5,) + shp)
+    X, Y = np.meshgrid(x, x, indexing="xy")  # [j][i]
+    for k in range(shp[0]):
+        r = np.sqrt(X * X + Y * Y + x[k] ** 2)
+        rho, psi, alpha = tov_fields(star, r)
+        inside = rho > rho_atmo
+        vx, vy = np.where(inside, -omega * Y, 0.0), np.where(inside, omega * X, 0.0)
+        W = 1.0 / np.sqrt(1.0 - psi ** 4 * (vx * vx + vy * vy))
+        rho = np.maximum(rho, rho_atmo)
+        prim[0, k] = rho
+        prim[1, k] = W * vx
+        prim[2, k] = W * vy
+        prim[4, k] = K * rho ** Gamma
+        met[0, k] = psi
+        met[1, k] = alpha
+    return p, prim, met
+
+
 def magnetised_star_2d(nr=256, nth=128, rmax=20.0, rho_c=1.28e-3, K=100.0, Gamma=2.0, b_peak=1e-4,
                        rho_atmo=1e-10, star=None):
     """Static magnetised polytropic star on a frozen CFC metric in 2D
