@@ -47,6 +47,9 @@ struct MgGeo {
   double rob_lo, rob_hi;  // Robin ghost factors on axis 0 (centre inside / centre of the ghost)
   int power, power2;
   double offset;
+  // vector operator (Cartesian): 1/h_a^2, 1/(4 h_a h_b) for the axis pairs
+  // (0,1), (0,2), (1,2), and the inverse diagonal of each component's row
+  double vih2[3], vmix[3], vidg[3];
 };
 
 __device__ __forceinline__ long mg_off(const MgGeo &G, int i, int j, int k) {
@@ -198,16 +201,43 @@ __global__ __launch_bounds__(NT) void k_mg_smooth(const MgGeo G, double *u, cons
 }
 
 // The coarsest-level solver: `sweeps` red-black sweeps by one workgroup,
-// the colours separated by workgroup barriers instead of launches.
+// the colours separated by workgroup barriers instead of launches.  With
+// lds != 0 the level's arrays (u, f and the given a, a2) are first copied
+// into dynamic LDS, relaxed there and u copied back: the sweeps are then
+// bound by LDS rather than global-memory latency.
 __global__ __launch_bounds__(NT) void k_mg_coarse(const MgGeo G, double *u, const double *__restrict__ f,
                                                   const double *__restrict__ a, const double *__restrict__ a2,
-                                                  int sweeps) {
+                                                  int sweeps, int lds) {
+  extern __shared__ double sm[];
+  double *uu = u;
+  const double *ff = f, *aa = a, *aa2 = a2;
+  if (lds) {
+    double *p = sm;
+    for (long e = threadIdx.x; e < G.nt; e += NT) p[e] = u[e];
+    uu = p;
+    p += G.nt;
+    for (long e = threadIdx.x; e < G.nt; e += NT) p[e] = f[e];
+    ff = p;
+    p += G.nt;
+    if (a) {
+      for (long e = threadIdx.x; e < G.nt; e += NT) p[e] = a[e];
+      aa = p;
+      p += G.nt;
+    }
+    if (a2) {
+      for (long e = threadIdx.x; e < G.nt; e += NT) p[e] = a2[e];
+      aa2 = p;
+    }
+    __syncthreads();
+  }
   const long nc = (long)((G.n[0] + 1) >> 1) * G.n[1] * G.n[2];
   for (int s = 0; s < sweeps; s++)
     for (int c = 0; c < 2; c++) {
-      for (long t = threadIdx.x; t < nc; t += NT) mg_smooth_one(G, u, f, a, a2, c, t);
+      for (long t = threadIdx.x; t < nc; t += NT) mg_smooth_one(G, uu, ff, aa, aa2, c, t);
       __syncthreads();
     }
+  if (lds)
+    for (long e = threadIdx.x; e < G.nt; e += NT) u[e] = uu[e];
 }
 
 // out = L(u) on the interior.
@@ -419,82 +449,76 @@ __global__ __launch_bounds__(NT) void k_mg_subgrad(const MgGeo G, const double *
 // product of the two steps' signs.
 
 struct VStep {
-  long dm[3], dp[3];
-  double fm[3], fp[3];
+  int dm[3], dp[3];  // offsets of the minus / plus neighbour along each axis
+  unsigned neg;      // bit a: the minus step negates; bit 3 + a: the plus step
 };
 
-__device__ __forceinline__ void mgv_axis(const MgGeo &G, int c, int a, long S, bool up, long &d, double &f) {
+__device__ __forceinline__ void mgv_axis(const MgGeo &G, int c, int a, int S, bool up, int &d, unsigned &neg) {
   const int n = G.n[a];
+  const int bit = up ? 3 + a : a;
   if (up ? c < n - 1 : c > 0) {
     d = up ? S : -S;
-    f = 1.0;
     return;
   }
   const int kind = G.bc[a][up ? 1 : 0];
   if (kind == GMUNU_MG_PERIODIC) {
-    d = up ? -(long)(n - 1) * S : (long)(n - 1) * S;
-    f = 1.0;
+    d = up ? -(n - 1) * S : (n - 1) * S;
     return;
   }
   d = 0;
-  f = kind == GMUNU_MG_DIRICHLET ? -1.0 : 1.0;
+  if (kind == GMUNU_MG_DIRICHLET) neg |= 1u << bit;
 }
 
 __device__ __forceinline__ VStep mgv_steps(const MgGeo &G, int i, int j, int k) {
   VStep s;
+  s.neg = 0;
   const int c[3] = {i, j, k};
-  const long S[3] = {1, G.s1, G.s2};
+  const int S[3] = {1, (int)G.s1, (int)G.s2};
 #pragma unroll
   for (int a = 0; a < 3; a++) {
     s.dm[a] = s.dp[a] = 0;
-    s.fm[a] = s.fp[a] = 0.0;
     if (a >= G.ndim) continue;
-    mgv_axis(G, c[a], a, S[a], false, s.dm[a], s.fm[a]);
-    mgv_axis(G, c[a], a, S[a], true, s.dp[a], s.fp[a]);
+    mgv_axis(G, c[a], a, S[a], false, s.dm[a], s.neg);
+    mgv_axis(G, c[a], a, S[a], true, s.dp[a], s.neg);
   }
   return s;
 }
 
-// L(X) at interior cell offset o (all three components) and the diagonal
-// of each component's row.
+__device__ __forceinline__ double mgv_sgn(unsigned neg, int bits, double v) { return (neg >> bits) & 1 ? -v : v; }
+
+// L(X) at interior cell offset o, all three components.  The level's
+// constants 1/h_a^2, 1/(4 h_a h_b) and the inverse diagonals are
+// precomputed (MgGeo.vih2, vmix, vidg).
 __device__ __forceinline__ void mgv_L(const MgGeo &G, const double *__restrict__ u, const VStep &s, long o,
-                                      double L[3], double dg[3]) {
+                                      double L[3]) {
   const long nt = G.nt;
-  double d2[3][3];  // d2[q][a]: second difference of component q along axis a
-  double ih2[3];
-#pragma unroll
-  for (int a = 0; a < 3; a++) ih2[a] = 1.0 / (G.h[a] * G.h[a]);
 #pragma unroll
   for (int q = 0; q < 3; q++) {
     const double *uq = u + q * nt;
     const double u0 = uq[o];
-    double lap = 0.0, d = 0.0;
+    double lap = 0.0, self = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-      d2[q][a] = 0.0;
       if (a >= G.ndim) continue;
-      d2[q][a] = (s.fp[a] * uq[o + s.dp[a]] - 2.0 * u0 + s.fm[a] * uq[o + s.dm[a]]) * ih2[a];
-      lap += d2[q][a];
-      d -= 2.0 * ih2[a];
+      const double up = mgv_sgn(s.neg, 3 + a, uq[o + s.dp[a]]), um = mgv_sgn(s.neg, a, uq[o + s.dm[a]]);
+      const double d2 = (up - 2.0 * u0 + um) * G.vih2[a];
+      lap += d2;
+      if (a == q) self = d2;
     }
-    L[q] = lap;
-    dg[q] = q < G.ndim ? d - (2.0 / 3.0) * ih2[q] : d;
-  }
-#pragma unroll
-  for (int q = 0; q < 3; q++) {
-    if (q >= G.ndim) continue;
-    double gd = d2[q][q];
+    double gd = self;
 #pragma unroll
     for (int b = 0; b < 3; b++) {
-      if (b == q || b >= G.ndim) continue;
+      if (q >= G.ndim || b == q || b >= G.ndim) continue;
       const double *ub = u + b * nt;
-      const double pp = s.fp[q] * s.fp[b] * ub[o + s.dp[q] + s.dp[b]];
-      const double pm = s.fp[q] * s.fm[b] * ub[o + s.dp[q] + s.dm[b]];
-      const double mp = s.fm[q] * s.fp[b] * ub[o + s.dm[q] + s.dp[b]];
-      const double mm = s.fm[q] * s.fm[b] * ub[o + s.dm[q] + s.dm[b]];
-      gd += (pp - pm - mp + mm) / (4.0 * G.h[q] * G.h[b]);
+      // sign of a diagonal neighbour: product of its two steps' signs
+      const unsigned pq = s.neg >> (3 + q), mq = s.neg >> q, pb = s.neg >> (3 + b), mb = s.neg >> b;
+      const double pp = mgv_sgn(pq ^ pb, 0, ub[o + s.dp[q] + s.dp[b]]);
+      const double pm = mgv_sgn(pq ^ mb, 0, ub[o + s.dp[q] + s.dm[b]]);
+      const double mp = mgv_sgn(mq ^ pb, 0, ub[o + s.dm[q] + s.dp[b]]);
+      const double mm = mgv_sgn(mq ^ mb, 0, ub[o + s.dm[q] + s.dm[b]]);
+      gd += (pp - pm - mp + mm) * G.vmix[q + b - 1];
     }
-    L[q] += gd / 3.0;
+    L[q] = lap + gd * (1.0 / 3.0);
   }
 }
 
@@ -519,10 +543,10 @@ __device__ __forceinline__ void mgv_smooth_one(const MgGeo &G, double *u, const 
   const int j = G.ndim > 1 ? 2 * (int)(r - kk * hy) + cj : 0;
   const int k = G.ndim > 2 ? 2 * (int)kk + ck : 0;
   const long o = mg_off(G, i, j, k);
-  double L[3], dg[3];
-  mgv_L(G, u, mgv_steps(G, i, j, k), o, L, dg);
+  double L[3];
+  mgv_L(G, u, mgv_steps(G, i, j, k), o, L);
 #pragma unroll
-  for (int q = 0; q < 3; q++) u[q * G.nt + o] -= (L[q] - f[q * G.nt + o]) / dg[q];
+  for (int q = 0; q < 3; q++) u[q * G.nt + o] -= (L[q] - f[q * G.nt + o]) * G.vidg[q];
 }
 
 __global__ __launch_bounds__(NT) void k_mgv_smooth(const MgGeo G, double *u, const double *__restrict__ f,
@@ -530,16 +554,63 @@ __global__ __launch_bounds__(NT) void k_mgv_smooth(const MgGeo G, double *u, con
   mgv_smooth_one(G, u, f, colour, (long)blockIdx.x * NT + threadIdx.x);
 }
 
-// Coarsest level: all sweeps in one workgroup, colours separated by barriers.
+// Two consecutive colours in one launch: (i even, j, k parities of `pair`)
+// then (i odd, same j, k parities).  Within such a pair a cell depends only
+// on its x-neighbours in the same row (the other rows it reads have other
+// j or k parities), so a workgroup owns whole rows (rpw of them) and
+// separates the halves by a barrier.  Same order and arithmetic as two
+// single-colour launches.
+__global__ __launch_bounds__(NT) void k_mgv_smooth2(const MgGeo G, double *u, const double *__restrict__ f,
+                                                    int pair, int rpw) {
+  const int cj = pair & 1, ck = (pair >> 1) & 1;
+  const unsigned hy = G.ndim > 1 ? (unsigned)(G.n[1] - cj + 1) >> 1 : 1u;
+  const unsigned hz = G.ndim > 2 ? (unsigned)(G.n[2] - ck + 1) >> 1 : 1u;
+  const unsigned rows = hy * hz, row0 = blockIdx.x * (unsigned)rpw;
+  for (int ci = 0; ci < 2; ci++) {
+    const unsigned hx = (unsigned)(G.n[0] - ci + 1) >> 1;
+    for (unsigned idx = threadIdx.x; idx < (unsigned)rpw * hx; idx += NT) {
+      const unsigned rr = idx / hx, row = row0 + rr;
+      if (row >= rows) break;
+      const int i = 2 * (int)(idx - rr * hx) + ci;
+      const unsigned kk = row / hy;
+      const int j = G.ndim > 1 ? 2 * (int)(row - kk * hy) + cj : 0;
+      const int k = G.ndim > 2 ? 2 * (int)kk + ck : 0;
+      const long o = mg_off(G, i, j, k);
+      double L[3];
+      mgv_L(G, u, mgv_steps(G, i, j, k), o, L);
+#pragma unroll
+      for (int q = 0; q < 3; q++) u[q * G.nt + o] -= (L[q] - f[q * G.nt + o]) * G.vidg[q];
+    }
+    __syncthreads();
+  }
+}
+
+// Coarsest level: all sweeps in one workgroup, colours separated by
+// barriers; with lds != 0 on copies of X and f in dynamic LDS.
 __global__ __launch_bounds__(NT) void k_mgv_coarse(const MgGeo G, double *u, const double *__restrict__ f,
-                                                   int sweeps) {
+                                                   int sweeps, int lds) {
+  extern __shared__ double sm[];
+  double *uu = u;
+  const double *ff = f;
+  const long n3 = 3 * G.nt;
+  if (lds) {
+    for (long e = threadIdx.x; e < n3; e += NT) {
+      sm[e] = u[e];
+      sm[n3 + e] = f[e];
+    }
+    __syncthreads();
+    uu = sm;
+    ff = sm + n3;
+  }
   const int ncol = 1 << G.ndim;
   for (int s = 0; s < sweeps; s++)
     for (int c = 0; c < ncol; c++) {
       const long nc = mgv_colour_cells(G, c);
-      for (long t = threadIdx.x; t < nc; t += NT) mgv_smooth_one(G, u, f, c, t);
+      for (long t = threadIdx.x; t < nc; t += NT) mgv_smooth_one(G, uu, ff, c, t);
       __syncthreads();
     }
+  if (lds)
+    for (long e = threadIdx.x; e < n3; e += NT) u[e] = uu[e];
 }
 
 __global__ __launch_bounds__(NT) void k_mgv_apply(const MgGeo G, const double *__restrict__ u,
@@ -549,8 +620,8 @@ __global__ __launch_bounds__(NT) void k_mgv_apply(const MgGeo G, const double *_
   int i, j, k;
   mg_cell(G, t, i, j, k);
   const long o = mg_off(G, i, j, k);
-  double L[3], dg[3];
-  mgv_L(G, u, mgv_steps(G, i, j, k), o, L, dg);
+  double L[3];
+  mgv_L(G, u, mgv_steps(G, i, j, k), o, L);
 #pragma unroll
   for (int q = 0; q < 3; q++) out[q * G.nt + o] = L[q];
 }
@@ -562,8 +633,8 @@ __global__ __launch_bounds__(NT) void k_mgv_norm(const MgGeo G, const double *__
     int i, j, k;
     mg_cell(G, t, i, j, k);
     const long o = mg_off(G, i, j, k);
-    double L[3], dg[3];
-    mgv_L(G, u, mgv_steps(G, i, j, k), o, L, dg);
+    double L[3];
+    mgv_L(G, u, mgv_steps(G, i, j, k), o, L);
 #pragma unroll
     for (int q = 0; q < 3; q++) m = fmax(m, fabs(f[q * G.nt + o] - L[q]));
   }
@@ -588,8 +659,8 @@ __global__ __launch_bounds__(NT) void k_mgv_restrict_res(const MgGeo F, const Mg
     const int fj = F.ndim > 1 ? 2 * j + ((ch >> 1) & 1) : j;
     const int fk = F.ndim > 2 ? 2 * k + ((ch >> 2) & 1) : k;
     const long o = mg_off(F, fi, fj, fk);
-    double L[3], dg[3];
-    mgv_L(F, u, mgv_steps(F, fi, fj, fk), o, L, dg);
+    double L[3];
+    mgv_L(F, u, mgv_steps(F, fi, fj, fk), o, L);
 #pragma unroll
     for (int q = 0; q < 3; q++) {
       su[q] += u[q * F.nt + o];
@@ -613,8 +684,8 @@ __global__ __launch_bounds__(NT) void k_mgv_fas_rhs(const MgGeo C, const double 
   int i, j, k;
   mg_cell(C, t, i, j, k);
   const long o = mg_off(C, i, j, k);
-  double L[3], dg[3];
-  mgv_L(C, u, mgv_steps(C, i, j, k), o, L, dg);
+  double L[3];
+  mgv_L(C, u, mgv_steps(C, i, j, k), o, L);
 #pragma unroll
   for (int q = 0; q < 3; q++) {
     f[q * C.nt + o] = L[q] + r[q * C.nt + o];
@@ -639,7 +710,9 @@ __global__ __launch_bounds__(NT) void k_mgv_aij(const MgGeo G, const double *__r
 #pragma unroll
     for (int b = 0; b < 3; b++) {
       const double *xb = X + b * G.nt;
-      g[a][b] = a < G.ndim ? (s.fp[a] * xb[o + s.dp[a]] - s.fm[a] * xb[o + s.dm[a]]) / (2.0 * G.h[a]) : 0.0;
+      g[a][b] = a < G.ndim ? (mgv_sgn(s.neg, 3 + a, xb[o + s.dp[a]]) - mgv_sgn(s.neg, a, xb[o + s.dm[a]])) /
+                                 (2.0 * G.h[a])
+                           : 0.0;
     }
   const double dv = g[0][0] + g[1][1] + g[2][2];
   double A[3][3], a2 = 0.0;
@@ -992,6 +1065,16 @@ void level_tables(const gmunu_mg_desc &d, int s, std::vector<double> &tab, size_
   G.power = d.power;
   G.power2 = d.power2;
   G.offset = d.offset;
+  double dsum = 0.0;
+  for (int a = 0; a < 3; a++) {
+    G.vih2[a] = a < d.ndim ? 1.0 / (G.h[a] * G.h[a]) : 0.0;
+    dsum -= 2.0 * G.vih2[a];
+  }
+  const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+  for (int q = 0; q < 3; q++) {
+    G.vmix[q] = pb[q] < d.ndim ? 1.0 / (4.0 * G.h[pa[q]] * G.h[pb[q]]) : 0.0;
+    G.vidg[q] = 1.0 / (q < d.ndim ? dsum - (2.0 / 3.0) * G.vih2[q] : dsum);
+  }
 }
 
 long ghost_count(const MgGeo &G) {
@@ -1044,11 +1127,17 @@ void correct(gmunu_mg *m, int l, hipStream_t st) {
 }
 
 // The coarsest level: one workgroup when it is small, else launches.
+// Dynamic LDS a one-workgroup coarsest solve may stage (bytes).
+constexpr long kCoarseLds = 64L * 1024;
+
 void coarse_solve(gmunu_mg *m, hipStream_t st) {
   const MgGeo &G = m->geo[0];
-  if (cells(G) <= 64L * NT)
-    hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(NT), 0, st, G, m->u[0], m->f[0], m->a[0], m->a2[0], m->d.coarse);
-  else
+  if (cells(G) <= 64L * NT) {
+    const long bytes = (2 + (m->a[0] ? 1 : 0) + (m->a2[0] ? 1 : 0)) * G.nt * (long)sizeof(double);
+    const int lds = bytes <= kCoarseLds;
+    hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(NT), lds ? bytes : 0, st, G, m->u[0], m->f[0], m->a[0], m->a2[0],
+                       m->d.coarse, lds);
+  } else
     sweeps_raw(G, m->u[0], m->f[0], m->a[0], m->a2[0], m->d.coarse, st);
 }
 
@@ -1121,11 +1210,22 @@ long colour_cells(const MgGeo &G, int c) {
   return n;
 }
 
+// Sweeps over the 2^ndim colours: two colours per launch (k_mgv_smooth2)
+// when a row's half fits in 4 passes of a workgroup, else one per launch.
 void vsweeps(const MgGeo &G, double *u, const double *f, int sweeps, hipStream_t st) {
   const int ncol = 1 << G.ndim;
+  const long hx0 = (G.n[0] + 1) >> 1;
+  const bool paired = hx0 <= 4L * NT;
+  const int rpw = hx0 >= NT ? 1 : (int)(NT / hx0);
   for (int s = 0; s < sweeps; s++)
-    for (int c = 0; c < ncol; c++)
-      hipLaunchKernelGGL(k_mgv_smooth, dim3(nblocks(colour_cells(G, c))), dim3(NT), 0, st, G, u, f, c);
+    for (int c = 0; c < ncol; c += paired ? 2 : 1) {
+      if (paired) {
+        const long rows = colour_cells(G, c) / ((G.n[0] + 1) >> 1);
+        hipLaunchKernelGGL(k_mgv_smooth2, dim3((rows + rpw - 1) / rpw), dim3(NT), 0, st, G, u, f, c >> 1, rpw);
+      } else {
+        hipLaunchKernelGGL(k_mgv_smooth, dim3(nblocks(colour_cells(G, c))), dim3(NT), 0, st, G, u, f, c);
+      }
+    }
 }
 
 void vghosts(const MgGeo &G, double *u, hipStream_t st) {
@@ -1149,9 +1249,12 @@ void vcorrect(gmunu_mg *m, int l, hipStream_t st) {
 
 void vcoarse_solve(gmunu_mg *m, hipStream_t st) {
   const MgGeo &G = m->geo[0];
-  if (cells(G) <= 64L * NT)
-    hipLaunchKernelGGL(k_mgv_coarse, dim3(1), dim3(NT), 0, st, G, m->vu[0], m->vf[0], m->d.coarse);
-  else
+  if (cells(G) <= 64L * NT) {
+    const long bytes = 6 * G.nt * (long)sizeof(double);
+    const int lds = bytes <= kCoarseLds;
+    hipLaunchKernelGGL(k_mgv_coarse, dim3(1), dim3(NT), lds ? bytes : 0, st, G, m->vu[0], m->vf[0], m->d.coarse,
+                       lds);
+  } else
     vsweeps(G, m->vu[0], m->vf[0], m->d.coarse, st);
 }
 
