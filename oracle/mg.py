@@ -308,3 +308,119 @@ def xcfc_solve(pv, ps, pa, U, S, stilde, X, u_psi, u_ap, beta, tol=1e-12, max_cy
     w = np.ascontiguousarray(alpha * psi ** -6)
     cyc.append(len(vsolve(pv, beta, xcfc_beta_rhs(pv, w, S, A6), tol, max_cycles)) - 1)
     return psi, alpha, cyc
+
+
+# ------------------------------------------- metric of a GRMHD state
+
+def _layout(hp):
+    """Interior slices of the GRMHD layout (ng ghost layers on active axes)."""
+    g = [hp.get("ng", 2) if a < hp["ndim"] else 0 for a in range(3)]
+    return tuple(slice(g[a], g[a] + hp["n"][a]) for a in (2, 1, 0))
+
+
+def _to_mg(p, hp, a):
+    out = np.zeros(shape(p))
+    out[interior_slices(p)] = a[_layout(hp)]
+    return out
+
+
+def interior_slices(p):
+    g = [1 if ax < p["ndim"] else 0 for ax in range(3)]
+    return tuple(slice(g[ax], g[ax] + p["n"][ax]) for ax in (2, 1, 0))
+
+
+def extend(hp, p, u):
+    """A multigrid solution u (interior used) on every cell of the GRMHD
+    layout of hp (ng ghost layers): each ghost layer from the boundary rule
+    applied per layer, axis by axis (mirror about the face times -1 for
+    Dirichlet, +1 for Neumann, r_in / r_ghost for Robin; periodic wrap)."""
+    ng = hp.get("ng", 2)
+    v = u[interior_slices(p)]
+    for a in range(p["ndim"]):
+        ax = 2 - a
+        n = p["n"][a]
+        idx = np.arange(-ng, n + ng)
+        src = idx.copy()
+        fac = np.ones(idx.size)
+        for side in (0, 1):
+            sel = idx < 0 if side == 0 else idx >= n
+            kind = p["bc"][a][side]
+            if kind == PERIODIC:
+                src[sel] = idx[sel] % n
+                continue
+            inn = -1 - idx[sel] if side == 0 else 2 * n - 1 - idx[sel]
+            src[sel] = inn
+            if kind == DIRICHLET:
+                fac[sel] = -1.0
+            elif kind == ROBIN:
+                x0, h = p["xmin"][0], p["dx"][0]
+                fac[sel] = (x0 + (inn + 0.5) * h) / (x0 + (idx[sel] + 0.5) * h)
+        shp = [1, 1, 1]
+        shp[ax] = -1
+        v = np.take(v, src, axis=ax) * fac.reshape(shp)
+    return v
+
+
+def fluid_stilde_curvilinear(hp, psi, prim):
+    """S~ = psi^6 (rho h W^2 v^2 + 3 p) on the GRMHD layout with
+    W^2 v^2 = psi^4 gamma^_ij (W v^i)(W v^j), gamma^ the reference metric
+    (Cartesian, cylindrical (R, z, phi) or spherical (r, theta, phi))."""
+    g = [hp.get("ng", 2) if a < hp["ndim"] else 0 for a in range(3)]
+    x = [hp["xmin"][a] + (np.arange(-g[a], hp["n"][a] + g[a]) + 0.5) * hp["dx"][a] for a in range(3)]
+    x3, x2, x1 = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+    one = np.ones_like(x1)
+    if hp["coord"] == CYL:
+        g11, g22, g33 = one, one, x1 * x1
+    elif hp["coord"] == SPH:
+        g11, g22, g33 = one, x1 * x1, (x1 * np.sin(x2)) ** 2
+    else:
+        g11, g22, g33 = one, one, one
+    gam = hp["gamma"]
+    rho, p = prim[0], prim[4]
+    w2v2 = psi ** 4 * (g11 * prim[1] ** 2 + g22 * prim[2] ** 2 + g33 * prim[3] ** 2)
+    return psi ** 6 * ((rho + gam / (gam - 1.0) * p) * w2v2 + 3.0 * p)
+
+
+def metric_update(hp, ppsi, palpha, q, prim, met, tol=1e-12, max_cycles=60, pvec=None, X=None):
+    """The metric of a GRMHD state re-solved from its conserved variables
+    (section 2.6), then the primitives recovered on the new metric (section
+    2.5): with pvec (Cartesian) the xCFC sequence (xcfc_solve; X in/out, the
+    shift from its equation), else the scalar CFC equations for psi and
+    alpha psi with the shift left as it is (U~ = q_tau + q_D, S~ from the
+    current primitives and the new psi).  met (psi, alpha, beta on every
+    cell of the layout) is updated in place, ghost layers by the boundary
+    rule of each equation applied per layer; q is corrected by the recovery.
+    Returns (q, prim with its ghosts filled, flags, nfatal, cycles)."""
+    import oracle as og
+    L = _layout(hp)
+    p0 = pvec if pvec is not None else ppsi
+    U = _to_mg(p0, hp, q[4] + q[0])
+    up = _to_mg(ppsi, hp, met[0] - 1.0)
+    cyc = [0, 0, 0, 0]
+    if pvec is not None:
+        S = np.ascontiguousarray(np.stack([_to_mg(pvec, hp, q[1 + c]) for c in range(3)]))
+        beta = np.ascontiguousarray(np.stack([_to_mg(pvec, hp, met[2 + c]) for c in range(3)]))
+        # initial guess of alpha psi from the metric as given (the converged
+        # solution does not depend on it beyond the tolerance)
+        ua = _to_mg(palpha, hp, met[1] * met[0] - 1.0)
+        rho, P = _to_mg(pvec, hp, prim[0]), _to_mg(pvec, hp, prim[4])
+        wv = [_to_mg(pvec, hp, prim[1 + c]) for c in range(3)]
+        _, _, cyc = xcfc_solve(pvec, ppsi, palpha, U, S, lambda ps_: fluid_stilde(ps_, rho, wv, P, hp["gamma"]),
+                               X, up, ua, beta, tol, max_cycles)
+        met[0] = 1.0 + extend(hp, ppsi, up)
+        met[1] = (1.0 + extend(hp, palpha, ua)) / met[0]
+        for c in range(3):
+            met[2 + c] = extend(hp, pvec, beta[c])
+    else:
+        zero = np.zeros_like(U)
+        cyc[1] = len(solve(ppsi, up, zero, np.ascontiguousarray(-2.0 * math.pi * U), tol, max_cycles)) - 1
+        met[0] = 1.0 + extend(hp, ppsi, up)
+        St = fluid_stilde_curvilinear(hp, met[0], prim)
+        a = np.zeros_like(U)
+        a[interior_slices(ppsi)] = (2.0 * math.pi * (q[4] + q[0] + 2.0 * St) / met[0] ** 2)[L]
+        ua = _to_mg(palpha, hp, met[1] * met[0] - 1.0)
+        cyc[2] = len(solve(palpha, ua, zero, a, tol, max_cycles)) - 1
+        met[1] = (1.0 + extend(hp, palpha, ua)) / met[0]
+    qc, pr, flags, nf = og.c2p(hp, q, met)
+    og.fill_ghosts(hp, pr)
+    return qc, pr, flags, nf, cyc

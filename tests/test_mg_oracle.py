@@ -532,3 +532,69 @@ def test_periodic_axes_keep_an_even_count_on_every_level():
     assert mg.make_desc(dict(p, bc=[[D, D], [D, D], [N, N]])).levels == 3
     with pytest.raises(ValueError):
         mg.make_desc(dict(p, levels=3))
+
+
+def test_metric_update_of_a_tov_star():
+    """Re-solving the metric of a static TOV star (2D spherical, Robin outer
+    face) from its conserved variables, starting from the flat metric:
+    psi and alpha approach the TOV metric at second order on the interior
+    and on both ghost layers (centre mirror, polar axis, Robin falloff), and
+    the primitives recovered on the new metric approach the star's."""
+    import oracle as og
+    import workloads as W
+    errs = []
+    for nr, nth in ((48, 8), (96, 16)):
+        hp, pr, met = W.magnetised_star_2d(nr, nth, b_peak=1e-12)
+        pr = og.fill_ghosts(hp, np.ascontiguousarray(pr))
+        q = og.prim2con(hp, pr, met)
+        m = met.copy()
+        m[0] = 1.0
+        m[1] = 1.0
+        base = dict(ndim=2, coord=SPH, n=[nr, nth, 1], xmin=[0.0, 0.0, 0.0], dx=[hp["dx"][0], math.pi / nth, 1.0],
+                    bc=[[N, ROB], [N, N], [N, N]], pre=4, post=4)
+        qc, prim, flags, nf, cyc = mg.metric_update(hp, dict(base, power=-1, offset=1.0),
+                                                    dict(base, power=1, offset=1.0), q, pr, m, tol=1e-12,
+                                                    max_cycles=300)
+        assert nf == 0 and max(cyc) < 300
+        g = hp["ng"]
+        inner = (0, slice(g, g + nth), slice(g, g + nr))
+        ghost = (0, slice(0, g + nth + g), slice(0, g + nr + g))
+        rho_i = np.abs(prim[0][inner] - pr[0][inner]).max() / pr[0].max()
+        errs.append((np.abs(m[0][ghost] - met[0][ghost]).max(), np.abs(m[1][ghost] - met[1][ghost]).max(), rho_i))
+    assert errs[1][0] < 4e-4 and errs[1][1] < 6e-4
+    for k in range(3):
+        assert errs[0][k] / errs[1][k] > 2.5, errs
+
+
+def test_stilde_is_the_same_scalar_in_every_coordinate_system():
+    """S~ = psi^6 (rho h W^2 v^2 + 3 p) is a scalar: one uniform flow
+    (W v = (0.3, -0.2, 0.4) in Cartesian components) written in cylindrical
+    (R, z, phi) and spherical (r, theta, phi) contravariant components by
+    the coordinate Jacobian gives the Cartesian value in every cell."""
+    import workloads as W
+    V = np.array([0.3, -0.2, 0.4])
+    psi0, rho0, p0, gam = 1.1, 0.7, 0.2, 5.0 / 3.0
+    ex = psi0 ** 6 * ((rho0 + gam / (gam - 1) * p0) * psi0 ** 4 * (V @ V) + 3 * p0)
+    for coord in (W.CYL, W.SPH):
+        if coord == W.CYL:
+            hp = W.grid(3, coord, [6, 5, 8], [0.5, -1.0, 0.0], [2.0, 1.0, 2 * math.pi], [[W.OUTFLOW] * 2] * 3,
+                        gamma=gam)
+        else:
+            hp = W.grid(3, coord, [6, 5, 8], [0.5, 0.3, 0.0], [2.0, math.pi - 0.3, 2 * math.pi],
+                        [[W.OUTFLOW] * 2] * 3, gamma=gam)
+        a, b, c = W.centres(hp)
+        pr = W.empty_prim(hp)
+        pr[0], pr[4] = rho0, p0
+        if coord == W.CYL:
+            R, phi = a, c
+            x, y = R * np.cos(phi), R * np.sin(phi)
+            pr[1] = (x * V[0] + y * V[1]) / R
+            pr[2] = V[2] + 0 * R
+            pr[3] = (x * V[1] - y * V[0]) / R ** 2
+        else:
+            r, th, phi = a, b, c
+            pr[1] = np.sin(th) * np.cos(phi) * V[0] + np.sin(th) * np.sin(phi) * V[1] + np.cos(th) * V[2]
+            pr[2] = (np.cos(th) * np.cos(phi) * V[0] + np.cos(th) * np.sin(phi) * V[1] - np.sin(th) * V[2]) / r
+            pr[3] = (-np.sin(phi) * V[0] + np.cos(phi) * V[1]) / (r * np.sin(th))
+        St = mg.fluid_stilde_curvilinear(hp, np.full(a.shape, psi0), pr)
+        np.testing.assert_allclose(St, ex, rtol=1e-13)
