@@ -180,6 +180,21 @@ int gmunu_mg_xcfc_solve(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, const 
                         const double *q, const double *prim, double *metric, double *X, double tol, int max_cycles,
                         int *cycles_out, void *stream);
 
+/* A metric update inside a GRMHD evolution (lifting the frozen-metric
+ * restriction, section 2.6 with the recovery of section 2.5): the metric
+ * re-solved from the state's conserved variables -- the xCFC sequence of
+ * gmunu_mg_xcfc_solve when mvec is given (X in/out, Cartesian grids), else
+ * the scalar equations of gmunu_mg_cfc_solve (shift unchanged) -- then
+ * gmunu_c2p of q on the new metric (q corrected where the recovery says so,
+ * flags and nfatal_dev as there) and gmunu_fill_ghosts of prim.  ctx and
+ * hydro describe the same grid (the context's and the descriptor it was
+ * created from).  cycles_out (4 ints, nullable): cycles of the X, psi,
+ * alpha psi and beta solves (0 for those not run). */
+int gmunu_mg_metric_update(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, gmunu_ctx *ctx,
+                           const gmunu_grid_desc *hydro, double *q, double *prim, double *metric, double *X,
+                           uint8_t *flags, unsigned int *nfatal_dev, double tol, int max_cycles, int *cycles_out,
+                           void *stream);
+
 #ifdef __cplusplus
 }
 #endif

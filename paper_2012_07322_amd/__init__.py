@@ -557,6 +557,7 @@ def _mg_sigs(L):
     L.gmunu_mg_xcfc_aij.argtypes = [_P, _P, _P, _P, _P]
     L.gmunu_mg_xcfc_beta_rhs.argtypes = [_P, _P, _P, _P, _P, _P]
     L.gmunu_mg_xcfc_solve.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, D, I, _P, _P]
+    L.gmunu_mg_metric_update.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, D, I, _P, _P]
 
 
 def make_mg_desc(p: dict) -> MgDesc:
@@ -741,6 +742,23 @@ def cfc_solve(mpsi, malpha, grid_params, q, prim, metric, tol=1e-12, max_cycles=
                                     _ptr(metric, "metric"), float(tol), int(max_cycles), cyc, _stream()),
            "gmunu_mg_cfc_solve")
     return cyc[0], cyc[1]
+
+
+def metric_update(grid, mpsi, malpha, q, prim, metric, mvec=None, X=None, flags=None, nfatal=None, tol=1e-12,
+                  max_cycles=60):
+    """Re-solve the metric of a GRMHD state from its conserved variables
+    (xCFC when mvec and X are given, else the scalar CFC equations), then
+    recover prim on the new metric and fill its ghosts (gmunu_mg_metric_update).
+    grid: the Grid of the state.  Returns the cycles of the four solves."""
+    fp = _ptr(flags, "flags", torch.uint8) if flags is not None else None
+    npn = _ptr(nfatal, "nfatal", torch.int32) if nfatal is not None else None
+    cyc = (ctypes.c_int * 4)()
+    _check(lib().gmunu_mg_metric_update(mvec._h if mvec is not None else None, mpsi._h, malpha._h, grid._h,
+                                        ctypes.byref(grid.desc), grid._chk(q, 8, "q"), grid._chk(prim, 8, "prim"),
+                                        grid._chk(metric, 5, "metric"),
+                                        mvec._chk(X, "X", vector=True) if mvec is not None else None, fp, npn,
+                                        float(tol), int(max_cycles), cyc, _stream()), "gmunu_mg_metric_update")
+    return tuple(cyc[i] for i in range(4))
 
 
 def xcfc_solve(mvec, mpsi, malpha, grid_params, q, prim, metric, X, tol=1e-12, max_cycles=60):

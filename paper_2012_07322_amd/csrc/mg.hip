@@ -1819,4 +1819,22 @@ int gmunu_mg_xcfc_solve(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, const 
   return launch_status();
 }
 
+int gmunu_mg_metric_update(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, gmunu_ctx *ctx,
+                           const gmunu_grid_desc *hydro, double *q, double *prim, double *metric, double *X,
+                           uint8_t *flags, unsigned int *nfatal_dev, double tol, int max_cycles, int *cycles_out,
+                           void *stream) {
+  if (!ctx || (mvec && !X)) return GMUNU_ENULL;
+  int cyc[4] = {0, 0, 0, 0};
+  int rc = mvec ? gmunu_mg_xcfc_solve(mvec, mpsi, malpha, hydro, q, prim, metric, X, tol, max_cycles, cyc, stream)
+                : gmunu_mg_cfc_solve(mpsi, malpha, hydro, q, prim, metric, tol, max_cycles, cyc + 1, stream);
+  if (rc) return rc;
+  rc = gmunu_c2p(ctx, q, metric, prim, flags, nfatal_dev, stream);
+  if (rc) return rc;
+  rc = gmunu_fill_ghosts(ctx, prim, stream);
+  if (rc) return rc;
+  if (cycles_out)
+    for (int c = 0; c < 4; c++) cycles_out[c] = cyc[c];
+  return GMUNU_OK;
+}
+
 }  // extern "C"
