@@ -121,8 +121,8 @@ def make_desc(p):
         if not _coarsens(q, a, d.levels - 1):
             raise ValueError("grid not divisible for the requested levels (even counts on periodic axes)")
         for s in (0, 1):
-            if d.bc[a][s] == ROBIN and (a != 0 or d.coord == CART):
-                raise ValueError("the Robin condition is for the radial axis")
+            if d.bc[a][s] == ROBIN and a != 0 and d.coord != CART:
+                raise ValueError("the Robin condition is for the radial axis (any face of a Cartesian grid)")
     return d
 
 
@@ -191,8 +191,8 @@ def solve(p, u, f, a=None, tol=1e-12, max_cycles=30, fmg=True, a2=None):
 
 
 def _cart(d):
-    if d.coord != CART:
-        raise ValueError("the vector operator is for Cartesian grids")
+    if d.coord != CART or any(d.bc[a][s] == ROBIN for a in range(3) for s in (0, 1)):
+        raise ValueError("the vector operator is for Cartesian grids without Robin faces")
     return d
 
 
@@ -335,13 +335,17 @@ def extend(hp, p, u):
     applied per layer, axis by axis (mirror about the face times -1 for
     Dirichlet, +1 for Neumann, r_in / r_ghost for Robin; periodic wrap)."""
     ng = hp.get("ng", 2)
+    nd = p["ndim"]
     v = u[interior_slices(p)]
-    for a in range(p["ndim"]):
+    # cell-centre coordinates along each axis of the array as it grows
+    xs = [p["xmin"][a] + (np.arange(p["n"][a]) + 0.5) * p["dx"][a] if a < nd else np.zeros(1) for a in range(3)]
+    for a in range(nd):
         ax = 2 - a
         n = p["n"][a]
         idx = np.arange(-ng, n + ng)
         src = idx.copy()
         fac = np.ones(idx.size)
+        sel_r = np.zeros(idx.size, bool)
         for side in (0, 1):
             sel = idx < 0 if side == 0 else idx >= n
             kind = p["bc"][a][side]
@@ -352,12 +356,25 @@ def extend(hp, p, u):
             src[sel] = inn
             if kind == DIRICHLET:
                 fac[sel] = -1.0
-            elif kind == ROBIN:
+            elif kind == ROBIN and p["coord"] != CART:
                 x0, h = p["xmin"][0], p["dx"][0]
                 fac[sel] = (x0 + (inn + 0.5) * h) / (x0 + (idx[sel] + 0.5) * h)
+            elif kind == ROBIN:
+                sel_r |= sel
         shp = [1, 1, 1]
         shp[ax] = -1
         v = np.take(v, src, axis=ax) * fac.reshape(shp)
+        xa = p["xmin"][a] + (idx + 0.5) * p["dx"][a]
+        if sel_r.any():
+            # Cartesian Robin: r_in / r_ghost with the other coordinates of
+            # the cell as the array holds them at this stage
+            X = np.meshgrid(*[xa[src + ng] if b == a else xs[b] for b in (2, 1, 0)], indexing="ij")
+            G = np.meshgrid(*[xa if b == a else xs[b] for b in (2, 1, 0)], indexing="ij")
+            rin = np.sqrt(sum(X[2 - b] ** 2 for b in range(nd)))
+            rg = np.sqrt(sum(G[2 - b] ** 2 for b in range(nd)))
+            f = np.where(sel_r.reshape(shp), rin / rg, 1.0)
+            v = v * f
+        xs[a] = xa
     return v
 
 
