@@ -464,9 +464,10 @@ def bench_xcfc(n=256, half=24.0, omega=0.01, sweeps=10):
     del pr
     q = g.prim2con(prd, metd)
     base = dict(ndim=3, coord=0, n=[n] * 3, xmin=[-half] * 3, dx=[2.0 * half / n] * 3, bc=[[0, 0]] * 3)
+    rob = dict(base, bc=[[3, 3]] * 3)  # psi, alpha psi: u + x.grad u = 0 on the faces; X, beta: 0
     Mv = gmu.Multigrid(base)
-    Mp = gmu.Multigrid(dict(base, power=-1, power2=-7, offset=1.0))
-    Ma = gmu.Multigrid(dict(base, power=1, offset=1.0))
+    Mp = gmu.Multigrid(dict(rob, power=-1, power2=-7, offset=1.0))
+    Ma = gmu.Multigrid(dict(rob, power=1, offset=1.0))
     X = Mv.empty(vector=True)
     flat = torch.from_numpy(W.flat_metric(hp)).cuda()
     tol = 1e-10
@@ -494,7 +495,7 @@ def bench_xcfc(n=256, half=24.0, omega=0.01, sweeps=10):
     ms_sweep = ev[0].elapsed_time(ev[1]) / sweeps
     gbs = 72.0 * n ** 3 / (ms_sweep * 1e-3) / 1e9
     out = {"workload": f"rotating polytropic star (K=100, Gamma=2, rho_c=1.28e-3, omega={omega:g}), Cartesian {n}^3 "
-                       f"on [-{half:g},{half:g}]^3, Dirichlet faces, flat initial guess",
+                       f"on [-{half:g},{half:g}]^3, Robin faces (psi, alpha psi) and Dirichlet faces (X, beta), flat initial guess",
            "tolerance": tol, "ms_per_solve": ms_solve, "cycles_X_psi_alphapsi_beta": list(cyc),
            "ms_per_warm_solve": ms_warm, "warm_cycles": list(cyc_warm),
            "psi_centre": float(m[0].max()), "alpha_centre": float(m[1].min()), "max_shift": shift,

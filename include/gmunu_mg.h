@@ -38,7 +38,9 @@ enum {
   GMUNU_MG_DIRICHLET = 0, /* u = 0 on the face */
   GMUNU_MG_NEUMANN = 1,   /* zero normal derivative (also: faces of zero area) */
   GMUNU_MG_PERIODIC = 2,
-  GMUNU_MG_ROBIN = 3      /* d(r u)/dr = 0 on the outer radial face (section 2.6); axis 0, curvilinear */
+  GMUNU_MG_ROBIN = 3      /* d(r u)/dr = 0 (section 2.6): outer radial face (axis 0) of curvilinear grids, any
+                             face of Cartesian grids (u + x.grad u = 0, r the distance from the origin);
+                             ghost value u_in r_in / r_ghost, exact for a 1/r fall-off */
 };
 
 typedef struct {
@@ -60,7 +62,7 @@ typedef struct gmunu_mg gmunu_mg;
 
 /* Validate (each active n divisible by 2^(levels-1), at least 2 cells per
  * axis on the coarsest level and an even number on periodic axes, Robin
- * only on axis 0 of curvilinear grids,
+ * only on axis 0 of curvilinear grids (any axis of Cartesian ones),
  * fewer than 2^31 entries per array),
  * build the level hierarchy on the current device and allocate its arrays
  * (5 arrays per coarse level, 6 with power2 != 0; 1 on the finest; the
@@ -140,8 +142,8 @@ int gmunu_mg_cfc_solve(gmunu_mg *mpsi, gmunu_mg *malpha, const gmunu_grid_desc *
                        void *stream);
 
 /* Vector equation L(X) = f of section 2.6 on Cartesian grids (EINVAL for
- * other coordinates; the descriptor's power, offset and power2 are not
- * used).  X and f: three arrays back to back (X^x, X^y, X^z); values across
+ * other coordinates or Robin faces; the descriptor's power, offset and
+ * power2 are not used).  X and f: three arrays back to back (X^x, X^y, X^z); values across
  * the boundary come from each axis's rule, so ghost entries of X are not
  * read.  vapply: out = L(X) on the interior.  vsmooth: `sweeps` sweeps of
  * the 2^ndim colours, then X's ghosts filled.  vsolve: as gmunu_mg_solve

@@ -45,6 +45,7 @@ struct MgGeo {
   const double *a1m, *a1p, *s2t, *vol1, *sg1;
   int bc[3][2];
   double rob_lo, rob_hi;  // Robin ghost factors on axis 0 (centre inside / centre of the ghost)
+  double x0[3];           // lower face coordinate per axis (Cartesian Robin factors)
   int power, power2;
   double offset;
   // vector operator (Cartesian): 1/h_a^2, 1/(4 h_a h_b) for the axis pairs
@@ -74,17 +75,37 @@ __device__ __forceinline__ double mg_nl_du(const MgGeo &G, double a, double a2, 
   return a2 != 0.0 ? t + a2 * G.power2 * mg_ipow(w, G.power2 - 1) : t;
 }
 
-// Neighbour of interior cell index c (0..n-1) along an axis of stride S on
-// the side `up`: the stored value inside, else the boundary rule applied to
-// the cell itself (the value a ghost fill would store there).
-__device__ __forceinline__ double mg_nb(const MgGeo &G, const double *__restrict__ u, long o, int c, int a, long S,
-                                        bool up) {
-  const int n = G.n[a];
+// Robin ghost factor r_in / r_ghost for the ghost of boundary cell c across
+// face (a, up): on curvilinear grids (axis 0) the level's constants; on
+// Cartesian grids r is the distance of the cell centres from the origin
+// (the condition u + x.grad u = 0 of section 2.6 as a 1/r fall-off between
+// the cell and its ghost).
+__device__ __forceinline__ double mg_rob(const MgGeo &G, int i, int j, int k, int a, bool up) {
+  if (G.coord != GMUNU_CART) return up ? G.rob_hi : G.rob_lo;
+  const int c[3] = {i, j, k};
+  double ri = 0.0, rg = 0.0;
+#pragma unroll
+  for (int b = 0; b < 3; b++) {
+    if (b >= G.ndim) continue;
+    const double xi = G.x0[b] + (c[b] + 0.5) * G.h[b];
+    const double xg = b == a ? G.x0[b] + (c[b] + (up ? 1 : -1) + 0.5) * G.h[b] : xi;
+    ri += xi * xi;
+    rg += xg * xg;
+  }
+  return sqrt(ri) / sqrt(rg);
+}
+
+// Neighbour of interior cell (i, j, k) along axis a (stride S) on the side
+// `up`: the stored value inside, else the boundary rule applied to the cell
+// itself (the value a ghost fill would store there).
+__device__ __forceinline__ double mg_nb(const MgGeo &G, const double *__restrict__ u, long o, int i, int j, int k,
+                                        int a, long S, bool up) {
+  const int n = G.n[a], c = a == 0 ? i : a == 1 ? j : k;
   if (up ? c < n - 1 : c > 0) return u[up ? o + S : o - S];
   const int kind = G.bc[a][up ? 1 : 0];
   if (kind == GMUNU_MG_PERIODIC) return u[up ? o - (long)(n - 1) * S : o + (long)(n - 1) * S];
   const double ui = u[o];
-  return kind == GMUNU_MG_DIRICHLET ? -ui : kind == GMUNU_MG_NEUMANN ? ui : ui * (up ? G.rob_hi : G.rob_lo);
+  return kind == GMUNU_MG_DIRICHLET ? -ui : kind == GMUNU_MG_NEUMANN ? ui : ui * mg_rob(G, i, j, k, a, up);
 }
 
 // L(u) at interior cell (i,j,k) (linear offset o) and dL/du there.  GH:
@@ -96,22 +117,23 @@ __device__ __forceinline__ double mg_L(const MgGeo &G, const double *__restrict_
   const int I = i + G.g[0], J = j + G.g[1];
   const double uc = u[o];
   double wm = G.a0m[I], wp = G.a0p[I];
-  double um = GH ? u[o - 1] : mg_nb(G, u, o, i, 0, 1, false), up = GH ? u[o + 1] : mg_nb(G, u, o, i, 0, 1, true);
+  double um = GH ? u[o - 1] : mg_nb(G, u, o, i, j, k, 0, 1, false);
+  double up = GH ? u[o + 1] : mg_nb(G, u, o, i, j, k, 0, 1, true);
   double lap = wp * (up - uc) - wm * (uc - um);
   double d = -(wm + wp);
   if (G.ndim > 1) {
     const double gi = G.g1[I];
     wm = gi * G.a1m[J];
     wp = gi * G.a1p[J];
-    um = GH ? u[o - G.s1] : mg_nb(G, u, o, j, 1, G.s1, false);
-    up = GH ? u[o + G.s1] : mg_nb(G, u, o, j, 1, G.s1, true);
+    um = GH ? u[o - G.s1] : mg_nb(G, u, o, i, j, k, 1, G.s1, false);
+    up = GH ? u[o + G.s1] : mg_nb(G, u, o, i, j, k, 1, G.s1, true);
     lap += wp * (up - uc) - wm * (uc - um);
     d -= wm + wp;
   }
   if (G.ndim > 2) {
     const double w = G.g2[I] * G.s2t[J] * G.ih2_2;
-    um = GH ? u[o - G.s2] : mg_nb(G, u, o, k, 2, G.s2, false);
-    up = GH ? u[o + G.s2] : mg_nb(G, u, o, k, 2, G.s2, true);
+    um = GH ? u[o - G.s2] : mg_nb(G, u, o, i, j, k, 2, G.s2, false);
+    up = GH ? u[o + G.s2] : mg_nb(G, u, o, i, j, k, 2, G.s2, true);
     lap += w * (up - uc) - w * (uc - um);
     d -= 2.0 * w;
   }
@@ -155,7 +177,9 @@ __device__ __forceinline__ void mg_ghost_one(const MgGeo &G, double *u, long t) 
     } else {
       sc[a] = side == 0 ? 0 : G.n[a] - 1;
       const double ui = u[mg_off(G, sc[0], sc[1], sc[2])];
-      v = kind == GMUNU_MG_DIRICHLET ? -ui : kind == GMUNU_MG_NEUMANN ? ui : ui * (side == 0 ? G.rob_lo : G.rob_hi);
+      v = kind == GMUNU_MG_DIRICHLET ? -ui
+          : kind == GMUNU_MG_NEUMANN ? ui
+                                     : ui * mg_rob(G, sc[0], sc[1], sc[2], a, side == 1);
     }
     u[mg_off(G, gc[0], gc[1], gc[2])] = v;
     return;
@@ -376,7 +400,9 @@ __global__ __launch_bounds__(NT) void k_mg_correct(const MgGeo C, const MgGeo F,
         if (kind == GMUNU_MG_PERIODIC)
           e = mg_corr(C, uc, uoc, up ? oc - (long)(n - 1) * S[a] : oc + (long)(n - 1) * S[a]);
         else
-          e = kind == GMUNU_MG_DIRICHLET ? -e0 : kind == GMUNU_MG_NEUMANN ? e0 : e0 * (up ? C.rob_hi : C.rob_lo);
+          e = kind == GMUNU_MG_DIRICHLET ? -e0
+            : kind == GMUNU_MG_NEUMANN ? e0
+                                       : e0 * mg_rob(C, cc[0], cc[1], cc[2], a, up);
       }
       s += 0.25 * e;
     }
@@ -894,8 +920,10 @@ __global__ __launch_bounds__(NT) void k_br_store(const MgGeo G, const Hydro H, c
   if (t >= H.nv) return;
   int c[3] = {(int)(t % H.T0) - H.ng[0], (int)((t / H.T0) % (H.T1 / H.T0)) - H.ng[1], (int)(t / H.T1) - H.ng[2]};
   double fac = 1.0;
+  // axes from the last to the first: an edge or corner ghost takes the
+  // factor of each axis at the other coordinates not yet mapped inside
 #pragma unroll
-  for (int a = 0; a < 3; a++) {
+  for (int a = 2; a >= 0; a--) {
     if (a >= G.ndim) continue;
     const int n = G.n[a];
     if (c[a] >= 0 && c[a] < n) continue;
@@ -907,7 +935,22 @@ __global__ __launch_bounds__(NT) void k_br_store(const MgGeo G, const Hydro H, c
     }
     const int in = side == 0 ? -1 - c[a] : 2 * n - 1 - c[a];
     if (kind == GMUNU_MG_DIRICHLET) fac = -fac;
-    if (kind == GMUNU_MG_ROBIN) fac *= (xmin0 + (in + 0.5) * G.h[0]) / (xmin0 + (c[a] + 0.5) * G.h[0]);
+    if (kind == GMUNU_MG_ROBIN) {
+      if (G.coord != GMUNU_CART) {
+        fac *= (xmin0 + (in + 0.5) * G.h[0]) / (xmin0 + (c[a] + 0.5) * G.h[0]);
+      } else {
+        double ri = 0.0, rg = 0.0;
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+          if (b >= G.ndim) continue;
+          const double xg = G.x0[b] + (c[b] + 0.5) * G.h[b];
+          const double xi = b == a ? G.x0[b] + (in + 0.5) * G.h[b] : xg;
+          ri += xi * xi;
+          rg += xg * xg;
+        }
+        fac *= sqrt(ri) / sqrt(rg);
+      }
+    }
     c[a] = in;
   }
   const double v = fac * u[mg_off(G, c[0], c[1], c[2])];
@@ -984,7 +1027,7 @@ int validate(const gmunu_mg_desc &d, int levels) {
     for (int s = 0; s < 2; s++) {
       const int b = d.bc[a][s];
       if (b < GMUNU_MG_DIRICHLET || b > GMUNU_MG_ROBIN) return GMUNU_EINVAL;
-      if (b == GMUNU_MG_ROBIN && (a != 0 || d.coord == GMUNU_CART)) return GMUNU_EINVAL;
+      if (b == GMUNU_MG_ROBIN && a != 0 && d.coord != GMUNU_CART) return GMUNU_EINVAL;
       if ((b == GMUNU_MG_PERIODIC) != (d.bc[a][1 - s] == GMUNU_MG_PERIODIC)) return GMUNU_EINVAL;
     }
   }
@@ -1062,6 +1105,7 @@ void level_tables(const gmunu_mg_desc &d, int s, std::vector<double> &tab, size_
   const double xin_hi = d.xmin[0] + (G.n[0] - 0.5) * h0, xg_hi = d.xmin[0] + (G.n[0] + 0.5) * h0;
   G.rob_lo = xin_lo / xg_lo;
   G.rob_hi = xin_hi / xg_hi;
+  for (int a = 0; a < 3; a++) G.x0[a] = d.xmin[a];
   G.power = d.power;
   G.power2 = d.power2;
   G.offset = d.offset;
@@ -1201,6 +1245,16 @@ void bind(gmunu_mg *m, double *u, const double *f, const double *a, const double
 bool a2_ok(const gmunu_mg *m, const double *a2) { return !a2 || (m->d.power2 != 0 && aligned8(a2)); }
 
 bool ok_ptr(const void *p) { return p && aligned8(p); }
+
+// The vector equations: Cartesian grids whose faces are Dirichlet, Neumann
+// or periodic.
+bool vector_ok(const gmunu_mg *m) {
+  if (m->d.coord != GMUNU_CART) return false;
+  for (int a = 0; a < 3; a++)
+    for (int sd = 0; sd < 2; sd++)
+      if (m->d.bc[a][sd] == GMUNU_MG_ROBIN) return false;
+  return true;
+}
 
 // ----------------------------------------------- vector-equation cycles
 
@@ -1612,7 +1666,7 @@ int gmunu_mg_clean(gmunu_mg *m, double *q, double *phi, double *div, double tol,
 int gmunu_mg_vapply(gmunu_mg *m, const double *X, double *out, void *stream) {
   if (!m || !X || !out) return GMUNU_ENULL;
   if (!ok_ptr(X) || !ok_ptr(out)) return GMUNU_EALIGN;
-  if (m->d.coord != GMUNU_CART) return GMUNU_EINVAL;
+  if (!vector_ok(m)) return GMUNU_EINVAL;
   const MgGeo &G = m->geo[m->levels - 1];
   hipLaunchKernelGGL(k_mgv_apply, dim3(nblocks(cells(G))), dim3(NT), 0, as_stream(stream), G, X, out);
   return launch_status();
@@ -1621,7 +1675,7 @@ int gmunu_mg_vapply(gmunu_mg *m, const double *X, double *out, void *stream) {
 int gmunu_mg_vsmooth(gmunu_mg *m, double *X, const double *f, int sweeps, void *stream) {
   if (!m || !X || !f) return GMUNU_ENULL;
   if (!ok_ptr(X) || !ok_ptr(f)) return GMUNU_EALIGN;
-  if (m->d.coord != GMUNU_CART || sweeps < 0) return GMUNU_EINVAL;
+  if (!vector_ok(m) || sweeps < 0) return GMUNU_EINVAL;
   const MgGeo &G = m->geo[m->levels - 1];
   hipStream_t st = as_stream(stream);
   vsweeps(G, X, f, sweeps, st);
@@ -1633,7 +1687,7 @@ int gmunu_mg_vsolve(gmunu_mg *m, double *X, const double *f, double tol, int max
                     double *res_host, int *cycles_out, void *stream) {
   if (!m || !X || !f) return GMUNU_ENULL;
   if (!ok_ptr(X) || !ok_ptr(f)) return GMUNU_EALIGN;
-  if (m->d.coord != GMUNU_CART || max_cycles < 0 || !(tol >= 0.0)) return GMUNU_EINVAL;
+  if (!vector_ok(m) || max_cycles < 0 || !(tol >= 0.0)) return GMUNU_EINVAL;
   if (!vector_storage(m)) return GMUNU_ENOMEM;
   hipStream_t cst = as_stream(stream);
   int rc = enter(m, cst);
@@ -1652,7 +1706,7 @@ int gmunu_mg_vsolve(gmunu_mg *m, double *X, const double *f, double tol, int max
 int gmunu_mg_xcfc_aij(gmunu_mg *m, const double *X, double *A6, double *A2, void *stream) {
   if (!m || !X || !A6 || !A2) return GMUNU_ENULL;
   if (!ok_ptr(X) || !ok_ptr(A6) || !ok_ptr(A2)) return GMUNU_EALIGN;
-  if (m->d.coord != GMUNU_CART) return GMUNU_EINVAL;
+  if (!vector_ok(m)) return GMUNU_EINVAL;
   const MgGeo &G = m->geo[m->levels - 1];
   hipLaunchKernelGGL(k_mgv_aij, dim3(nblocks(cells(G))), dim3(NT), 0, as_stream(stream), G, X, A6, A2);
   return launch_status();
@@ -1662,7 +1716,7 @@ int gmunu_mg_xcfc_beta_rhs(gmunu_mg *m, const double *w, const double *S, const 
                            void *stream) {
   if (!m || !w || !S || !A6 || !out) return GMUNU_ENULL;
   if (!ok_ptr(w) || !ok_ptr(S) || !ok_ptr(A6) || !ok_ptr(out)) return GMUNU_EALIGN;
-  if (m->d.coord != GMUNU_CART) return GMUNU_EINVAL;
+  if (!vector_ok(m)) return GMUNU_EINVAL;
   const MgGeo &G = m->geo[m->levels - 1];
   hipLaunchKernelGGL(k_mgv_beta_rhs, dim3(nblocks(cells(G))), dim3(NT), 0, as_stream(stream), G, w, S, A6, out);
   return launch_status();
@@ -1786,7 +1840,7 @@ int gmunu_mg_xcfc_solve(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, const 
   if (!rc) rc = hydro_of(malpha, hydro, H2);
   if (!rc) rc = hydro_of(mvec, hydro, H3);
   if (rc) return rc;
-  if (mvec->d.coord != GMUNU_CART || mpsi->d.power != -1 || mpsi->d.offset != 1.0 || mpsi->d.power2 != -7 ||
+  if (!vector_ok(mvec) || mpsi->d.power != -1 || mpsi->d.offset != 1.0 || mpsi->d.power2 != -7 ||
       malpha->d.power != 1 || malpha->d.offset != 1.0)
     return GMUNU_EINVAL;
   if (!bridge_scratch(mpsi) || !vector_storage(mvec)) return GMUNU_ENOMEM;

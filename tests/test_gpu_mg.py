@@ -62,6 +62,7 @@ CASES = {
     "sph3d": prob(3, SPH, (8, 8, 8), (0.5, 0.3, 0.0), (2.5, math.pi - 0.3, 2 * math.pi),
                   [[D, ROB], [N, D], [PER, PER]]),
     "sph1d": prob(1, SPH, (32,), (0.0,), (4.0,), [[N, ROB]]),
+    "cart3d_robin": prob(3, CART, (16, 8, 8), (-1.0, 0.2, -0.6), (1.0, 1.2, 0.4), [[ROB, ROB], [N, ROB], [ROB, D]]),
 }
 
 
@@ -95,7 +96,7 @@ def test_ghost_fill_and_operator_parity(case):
         assert np.abs(Lg - Lo).max() <= 1e-12 * np.abs(Lo).max(), (power, np.abs(Lg - Lo).max())
 
 
-@pytest.mark.parametrize("case", ["cart3d", "sph2d", "cyl3d"])
+@pytest.mark.parametrize("case", ["cart3d", "sph2d", "cyl3d", "cart3d_robin"])
 def test_smoothing_sweep_parity(case):
     p = dict(CASES[case], power=-1, offset=2.0)
     M = gmu.Multigrid(p)
@@ -131,6 +132,8 @@ SOLVES = {
                        pre=4, post=4), {"a": True}),
     "alpha_cart3d": (prob(3, CART, (32, 32, 32), (-1, -1, -1), (1, 1, 1), [[D, D]] * 3, power=1, offset=1.0),
                      {"a": True}),
+    "psi_cart3d_robin": (prob(3, CART, (32, 32, 32), (-2, -2, -2), (2, 2, 2), [[ROB, ROB]] * 3, power=-1,
+                              offset=1.0), {"a": True}),
 }
 
 
@@ -214,7 +217,7 @@ def test_large_grid_cycle_rate_and_residual():
 
 def test_invalid_descriptors_are_rejected():
     bad = [prob(2, CART, (12, 16), (0, 0), (1, 1), [[D, D], [D, D]], levels=4),   # 12 not divisible by 8
-           prob(2, CART, (16, 16), (0, 0), (1, 1), [[ROB, D], [D, D]]),            # Robin in Cartesian
+           prob(2, CYL, (16, 16), (0.5, 0), (1, 1), [[N, D], [ROB, D]]),           # Robin off axis 0 (cylindrical)
            prob(2, SPH, (16, 16), (0, 0), (1, 1), [[N, D], [ROB, D]]),             # Robin off axis 0
            prob(2, CART, (16, 16), (0, 0), (1, 1), [[PER, D], [D, D]]),            # one-sided periodic
            prob(2, CART, (16, 16), (0, 0), (1, 1), [[D, D], [D, D]], power=2),
@@ -437,6 +440,9 @@ def test_vector_and_second_term_misuse_is_rejected():
     M = gmu.Multigrid(CASES["sph2d"])
     with pytest.raises(RuntimeError):
         M.vapply(M.empty(vector=True))
+    Mr = gmu.Multigrid(CASES["cart3d_robin"])  # the vector equations take no Robin faces
+    with pytest.raises(RuntimeError):
+        Mr.vapply(Mr.empty(vector=True))
     M2 = gmu.Multigrid(CASES["cart3d"])  # power2 = 0: no second term
     u = M2.empty()
     with pytest.raises(RuntimeError):
@@ -466,7 +472,8 @@ def test_xcfc_solve_matches_the_oracle():
     met = W.flat_metric(hp)
     q = oracle.prim2con(hp, pr, met)
     base = dict(ndim=3, coord=CART, n=[n] * 3, xmin=[-1.0] * 3, dx=[2.0 / n] * 3, bc=[[D, D]] * 3)
-    pv, ps, pa = dict(base), dict(base, power=-1, power2=-7, offset=1.0), dict(base, power=1, offset=1.0)
+    rob = dict(base, bc=[[ROB, ROB]] * 3)  # u + x.grad u = 0 on the faces for psi and alpha psi
+    pv, ps, pa = dict(base), dict(rob, power=-1, power2=-7, offset=1.0), dict(rob, power=1, offset=1.0)
     Mv, Mp, Ma = gmu.Multigrid(pv), gmu.Multigrid(ps), gmu.Multigrid(pa)
     Xg = Mv.empty(vector=True)
     metd = dev(met)
@@ -573,7 +580,8 @@ def test_evolution_with_metric_updates_matches_the_oracle(kind):
         pr = oracle.fill_ghosts(hp, np.ascontiguousarray(pr))
         q = oracle.prim2con(hp, pr, met)
         base = dict(ndim=3, coord=CART, n=[16] * 3, xmin=[-12.0] * 3, dx=[1.5] * 3, bc=[[D, D]] * 3)
-        pv, ps, pa = dict(base), dict(base, power=-1, power2=-7, offset=1.0), dict(base, power=1, offset=1.0)
+        rob = dict(base, bc=[[ROB, ROB]] * 3)
+        pv, ps, pa = dict(base), dict(rob, power=-1, power2=-7, offset=1.0), dict(rob, power=1, offset=1.0)
         steps, every = 4, 2
     cfl = 0.4
     g = gmu.Grid(hp)
