@@ -121,8 +121,9 @@ def make_desc(p):
         if not _coarsens(q, a, d.levels - 1):
             raise ValueError("grid not divisible for the requested levels (even counts on periodic axes)")
         for s in (0, 1):
-            if d.bc[a][s] == ROBIN and a != 0 and d.coord != CART:
-                raise ValueError("the Robin condition is for the radial axis (any face of a Cartesian grid)")
+            if d.bc[a][s] == ROBIN and ((d.coord == SPH and a != 0) or (d.coord == CYL and a == 2)):
+                raise ValueError("the Robin condition is for the outer faces in r (spherical), R and z "
+                                 "(cylindrical) or x, y, z (Cartesian)")
     return d
 
 
@@ -356,7 +357,7 @@ def extend(hp, p, u):
             src[sel] = inn
             if kind == DIRICHLET:
                 fac[sel] = -1.0
-            elif kind == ROBIN and p["coord"] != CART:
+            elif kind == ROBIN and p["coord"] == SPH:
                 x0, h = p["xmin"][0], p["dx"][0]
                 fac[sel] = (x0 + (inn + 0.5) * h) / (x0 + (idx[sel] + 0.5) * h)
             elif kind == ROBIN:
@@ -366,12 +367,14 @@ def extend(hp, p, u):
         v = np.take(v, src, axis=ax) * fac.reshape(shp)
         xa = p["xmin"][a] + (idx + 0.5) * p["dx"][a]
         if sel_r.any():
-            # Cartesian Robin: r_in / r_ghost with the other coordinates of
-            # the cell as the array holds them at this stage
+            # Cartesian / cylindrical Robin: r_in / r_ghost with the other
+            # coordinates of the cell as the array holds them at this stage
+            # (cylindrical distance from R and z)
             X = np.meshgrid(*[xa[src + ng] if b == a else xs[b] for b in (2, 1, 0)], indexing="ij")
             G = np.meshgrid(*[xa if b == a else xs[b] for b in (2, 1, 0)], indexing="ij")
-            rin = np.sqrt(sum(X[2 - b] ** 2 for b in range(nd)))
-            rg = np.sqrt(sum(G[2 - b] ** 2 for b in range(nd)))
+            nb = min(nd, 2) if p["coord"] == CYL else nd
+            rin = np.sqrt(sum(X[2 - b] ** 2 for b in range(nb)))
+            rg = np.sqrt(sum(G[2 - b] ** 2 for b in range(nb)))
             f = np.where(sel_r.reshape(shp), rin / rg, 1.0)
             v = v * f
         xs[a] = xa

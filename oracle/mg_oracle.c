@@ -32,13 +32,14 @@
  *   - boundary conditions by ghost values: Dirichlet (u = 0 on the face),
  *     Neumann (zero normal derivative), periodic, and on the outer radial
  *     face the Robin condition d(r u)/dr = 0 of section 2.6 (ghost value
- *     u_in r_in / r_ghost, exact for a 1/r fall-off); on Cartesian grids the
- *     same condition, u + x.grad u = 0, on any face, through the same ghost
- *     rule with r the distance of the cell centres from the origin (the
- *     paper imposes it at the outermost cell centres; the ghost form holds
- *     the 1/r fall-off the condition expresses between each boundary cell
- *     and its ghost); faces of zero area (r = 0, R = 0, theta = 0 or pi)
- *     need none;
+ *     u_in r_in / r_ghost, exact for a 1/r fall-off); on Cartesian and
+ *     cylindrical grids the same condition (u + x.grad u = 0, and
+ *     u + R du/dR + z du/dz = 0) on any face (cylindrical: the R and z
+ *     faces), through the same ghost rule with r the distance of the cell
+ *     centres from the origin (the paper imposes it at the outermost cell
+ *     centres; the ghost form holds the 1/r fall-off the condition
+ *     expresses between each boundary cell and its ghost); faces of zero
+ *     area (r = 0, R = 0, theta = 0 or pi) need none;
  *   - on a periodic axis every level keeps an even number of cells (the
  *     caller chooses the levels so): with an odd count the cells on either
  *     side of the wrap share a colour, and the red-black and multi-colour
@@ -198,11 +199,12 @@ static void fill_ghosts(const om_desc *d, const lvl *L, double *u) {
               v = -ui;
             } else if (kind == OM_NEUMANN) {
               v = ui;
-            } else if (d->coord == OM_CART) {
+            } else if (d->coord != OM_SPH) {
               /* 1/r falloff between the boundary cell and its ghost, r the
-               * distance of the cell centres from the origin (active axes) */
+               * distance of the cell centres from the origin (Cartesian:
+               * the active axes; cylindrical: R and z) */
               double ri = 0.0, rg = 0.0;
-              for (int b = 0; b < d->ndim; b++) {
+              for (int b = 0; b < d->ndim && b < (d->coord == OM_CYL ? 2 : 3); b++) {
                 double xi = centre(d, L, b, s[b]), xg = centre(d, L, b, g[b]);
                 ri += xi * xi;
                 rg += xg * xg;
