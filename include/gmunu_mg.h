@@ -38,9 +38,10 @@ enum {
   GMUNU_MG_DIRICHLET = 0, /* u = 0 on the face */
   GMUNU_MG_NEUMANN = 1,   /* zero normal derivative (also: faces of zero area) */
   GMUNU_MG_PERIODIC = 2,
-  GMUNU_MG_ROBIN = 3      /* d(r u)/dr = 0 (section 2.6): outer radial face (axis 0) of curvilinear grids, any
-                             face of Cartesian grids (u + x.grad u = 0, r the distance from the origin);
-                             ghost value u_in r_in / r_ghost, exact for a 1/r fall-off */
+  GMUNU_MG_ROBIN = 3      /* d(r u)/dr = 0 (section 2.6): the outer r face (axis 0) of spherical grids, the R
+                             and z faces of cylindrical ones (u + R du/dR + z du/dz = 0), any face of Cartesian
+                             ones (u + x.grad u = 0); ghost value u_in r_in / r_ghost with r the distance of the
+                             cell centres from the origin, exact for a 1/r fall-off */
 };
 
 typedef struct {
@@ -62,7 +63,7 @@ typedef struct gmunu_mg gmunu_mg;
 
 /* Validate (each active n divisible by 2^(levels-1), at least 2 cells per
  * axis on the coarsest level and an even number on periodic axes, Robin
- * only on axis 0 of curvilinear grids (any axis of Cartesian ones),
+ * only where GMUNU_MG_ROBIN allows it,
  * fewer than 2^31 entries per array),
  * build the level hierarchy on the current device and allocate its arrays
  * (5 arrays per coarse level, 6 with power2 != 0; 1 on the finest; the

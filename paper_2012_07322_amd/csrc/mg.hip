@@ -76,17 +76,19 @@ __device__ __forceinline__ double mg_nl_du(const MgGeo &G, double a, double a2, 
 }
 
 // Robin ghost factor r_in / r_ghost for the ghost of boundary cell c across
-// face (a, up): on curvilinear grids (axis 0) the level's constants; on
-// Cartesian grids r is the distance of the cell centres from the origin
-// (the condition u + x.grad u = 0 of section 2.6 as a 1/r fall-off between
-// the cell and its ghost).
+// face (a, up): on spherical grids (axis 0) the level's constants; on
+// Cartesian and cylindrical grids r is the distance of the cell centres
+// from the origin (x, y, z; or R, z) -- the conditions u + x.grad u = 0 and
+// u + R du/dR + z du/dz = 0 of section 2.6 as a 1/r fall-off between the
+// cell and its ghost.
 __device__ __forceinline__ double mg_rob(const MgGeo &G, int i, int j, int k, int a, bool up) {
-  if (G.coord != GMUNU_CART) return up ? G.rob_hi : G.rob_lo;
+  if (G.coord == GMUNU_SPH) return up ? G.rob_hi : G.rob_lo;
   const int c[3] = {i, j, k};
+  const int nb = G.coord == GMUNU_CYL ? 2 : 3;
   double ri = 0.0, rg = 0.0;
 #pragma unroll
   for (int b = 0; b < 3; b++) {
-    if (b >= G.ndim) continue;
+    if (b >= G.ndim || b >= nb) continue;
     const double xi = G.x0[b] + (c[b] + 0.5) * G.h[b];
     const double xg = b == a ? G.x0[b] + (c[b] + (up ? 1 : -1) + 0.5) * G.h[b] : xi;
     ri += xi * xi;
@@ -936,13 +938,14 @@ __global__ __launch_bounds__(NT) void k_br_store(const MgGeo G, const Hydro H, c
     const int in = side == 0 ? -1 - c[a] : 2 * n - 1 - c[a];
     if (kind == GMUNU_MG_DIRICHLET) fac = -fac;
     if (kind == GMUNU_MG_ROBIN) {
-      if (G.coord != GMUNU_CART) {
+      if (G.coord == GMUNU_SPH) {
         fac *= (xmin0 + (in + 0.5) * G.h[0]) / (xmin0 + (c[a] + 0.5) * G.h[0]);
       } else {
+        const int nb = G.coord == GMUNU_CYL ? 2 : 3;
         double ri = 0.0, rg = 0.0;
 #pragma unroll
         for (int b = 0; b < 3; b++) {
-          if (b >= G.ndim) continue;
+          if (b >= G.ndim || b >= nb) continue;
           const double xg = G.x0[b] + (c[b] + 0.5) * G.h[b];
           const double xi = b == a ? G.x0[b] + (in + 0.5) * G.h[b] : xg;
           ri += xi * xi;
@@ -1027,7 +1030,8 @@ int validate(const gmunu_mg_desc &d, int levels) {
     for (int s = 0; s < 2; s++) {
       const int b = d.bc[a][s];
       if (b < GMUNU_MG_DIRICHLET || b > GMUNU_MG_ROBIN) return GMUNU_EINVAL;
-      if (b == GMUNU_MG_ROBIN && a != 0 && d.coord != GMUNU_CART) return GMUNU_EINVAL;
+      if (b == GMUNU_MG_ROBIN && ((d.coord == GMUNU_SPH && a != 0) || (d.coord == GMUNU_CYL && a == 2)))
+        return GMUNU_EINVAL;
       if ((b == GMUNU_MG_PERIODIC) != (d.bc[a][1 - s] == GMUNU_MG_PERIODIC)) return GMUNU_EINVAL;
     }
   }

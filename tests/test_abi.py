@@ -148,7 +148,7 @@ def test_multigrid_create_rejects_invalid_descriptors():
         gmu._mg_sigs(L)
         L._mg_sigs_set = True
     base = dict(ndim=2, coord=0, n=[16, 16, 1], xmin=[0, 0, 0], dx=[1 / 16, 1 / 16, 1], bc=[[0, 0]] * 3)
-    bad = [dict(base, n=[12, 16, 1], levels=4), dict(base, coord=1, xmin=[0.5, 0, 0], bc=[[0, 0], [3, 0], [0, 0]]),
+    bad = [dict(base, n=[12, 16, 1], levels=4),
            dict(base, coord=2, bc=[[1, 1], [3, 1], [1, 1]]), dict(base, bc=[[2, 0], [0, 0], [0, 0]]),
            dict(base, power=2), dict(base, coarse=0), dict(base, n=[16, 16, 2]), dict(base, ndim=4),
            dict(base, power2=9), dict(base, n=[12, 16, 1], bc=[[2, 2], [0, 0], [0, 0]], levels=3)]

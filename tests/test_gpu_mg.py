@@ -63,6 +63,7 @@ CASES = {
                   [[D, ROB], [N, D], [PER, PER]]),
     "sph1d": prob(1, SPH, (32,), (0.0,), (4.0,), [[N, ROB]]),
     "cart3d_robin": prob(3, CART, (16, 8, 8), (-1.0, 0.2, -0.6), (1.0, 1.2, 0.4), [[ROB, ROB], [N, ROB], [ROB, D]]),
+    "cyl2d_robin": prob(2, CYL, (16, 32), (0.0, -2.0), (2.0, 2.0), [[N, ROB], [ROB, ROB]]),
 }
 
 
@@ -134,6 +135,7 @@ SOLVES = {
                      {"a": True}),
     "psi_cart3d_robin": (prob(3, CART, (32, 32, 32), (-2, -2, -2), (2, 2, 2), [[ROB, ROB]] * 3, power=-1,
                               offset=1.0), {"a": True}),
+    "cyl2d_robin": (prob(2, CYL, (32, 64), (0.0, -2.0), (2.0, 2.0), [[N, ROB], [ROB, ROB]]), {}),
 }
 
 
@@ -217,7 +219,7 @@ def test_large_grid_cycle_rate_and_residual():
 
 def test_invalid_descriptors_are_rejected():
     bad = [prob(2, CART, (12, 16), (0, 0), (1, 1), [[D, D], [D, D]], levels=4),   # 12 not divisible by 8
-           prob(2, CYL, (16, 16), (0.5, 0), (1, 1), [[N, D], [ROB, D]]),           # Robin off axis 0 (cylindrical)
+           prob(3, CYL, (8, 8, 8), (0.5, -1, 0), (2.5, 1, 2 * math.pi), [[N, D], [D, D], [ROB, ROB]]),  # Robin in phi
            prob(2, SPH, (16, 16), (0, 0), (1, 1), [[N, D], [ROB, D]]),             # Robin off axis 0
            prob(2, CART, (16, 16), (0, 0), (1, 1), [[PER, D], [D, D]]),            # one-sided periodic
            prob(2, CART, (16, 16), (0, 0), (1, 1), [[D, D], [D, D]], power=2),
