@@ -183,6 +183,15 @@ int gmunu_mg_xcfc_solve(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, const 
                         const double *q, const double *prim, double *metric, double *X, double tol, int max_cycles,
                         int *cycles_out, void *stream);
 
+/* max |L(psi - 1)| of the conformal-factor equation of section 2.6 with the
+ * current metric and the state's conserved variables (U~ = q_tau + q_D;
+ * with mvec and X, Cartesian, the A~_ij A~^ij psi^-7 term from X as well):
+ * the constraint residual that decides when the metric is re-solved during
+ * an evolution (section 2.6, frequency of solving the metric).  mpsi: p =
+ * -1, c = 1 (q = -7 with mvec).  Synchronous. */
+int gmunu_mg_psi_residual(gmunu_mg *mvec, gmunu_mg *mpsi, const gmunu_grid_desc *hydro, const double *q,
+                          const double *metric, const double *X, double *norm_out, void *stream);
+
 /* A metric update inside a GRMHD evolution (lifting the frozen-metric
  * restriction, section 2.6 with the recovery of section 2.5): the metric
  * re-solved from the state's conserved variables -- the xCFC sequence of

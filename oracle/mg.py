@@ -444,3 +444,17 @@ def metric_update(hp, ppsi, palpha, q, prim, met, tol=1e-12, max_cycles=60, pvec
     qc, pr, flags, nf = og.c2p(hp, q, met)
     og.fill_ghosts(hp, pr)
     return qc, pr, flags, nf, cyc
+
+
+def psi_residual(hp, ppsi, q, met, pvec=None, X=None):
+    """max |L(psi - 1)| of the conformal-factor equation of section 2.6 with
+    the metric as given (its interior) and U~ = q_tau + q_D; with pvec and X
+    (Cartesian) the A2 psi^-7 term from X."""
+    U = _to_mg(ppsi, hp, q[4] + q[0])
+    u = _to_mg(ppsi, hp, met[0] - 1.0)
+    fill_ghosts(ppsi, u)
+    a2 = None
+    if pvec is not None:
+        a2 = np.ascontiguousarray(-xcfc_aij(pvec, X)[1] / 8.0)
+    L = apply(ppsi, u, np.ascontiguousarray(-2.0 * math.pi * U), a2)
+    return float(np.abs(L[interior_slices(ppsi)]).max())

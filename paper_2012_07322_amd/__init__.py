@@ -558,6 +558,7 @@ def _mg_sigs(L):
     L.gmunu_mg_xcfc_beta_rhs.argtypes = [_P, _P, _P, _P, _P, _P]
     L.gmunu_mg_xcfc_solve.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, D, I, _P, _P]
     L.gmunu_mg_metric_update.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, D, I, _P, _P]
+    L.gmunu_mg_psi_residual.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P]
 
 
 def make_mg_desc(p: dict) -> MgDesc:
@@ -759,6 +760,38 @@ def metric_update(grid, mpsi, malpha, q, prim, metric, mvec=None, X=None, flags=
                                         mvec._chk(X, "X", vector=True) if mvec is not None else None, fp, npn,
                                         float(tol), int(max_cycles), cyc, _stream()), "gmunu_mg_metric_update")
     return tuple(cyc[i] for i in range(4))
+
+
+def psi_residual(grid, mpsi, q, metric, mvec=None, X=None):
+    """max |L(psi - 1)| of the conformal-factor equation with the current
+    metric and matter (gmunu_mg_psi_residual)."""
+    out = ctypes.c_double(0.0)
+    _check(lib().gmunu_mg_psi_residual(mvec._h if mvec is not None else None, mpsi._h, ctypes.byref(grid.desc),
+                                       grid._chk(q, 8, "q"), grid._chk(metric, 5, "metric"),
+                                       mvec._chk(X, "X", vector=True) if mvec is not None else None,
+                                       ctypes.byref(out), _stream()), "gmunu_mg_psi_residual")
+    return out.value
+
+
+def evolve_dynamical(grid, q_n, q_s, prim, metric, mpsi, malpha, cfl, steps, every=50, eps=1e-3, mvec=None, X=None,
+                     t_dev=None, dt_dev=None, flags=None, nfatal=None, tol=1e-6, max_cycles=60):
+    """GRMHD steps on a metric re-solved from the evolved matter (section
+    2.6): after each step the metric is updated when `every` steps have
+    passed since the last update or when the conformal-factor residual
+    exceeds eps.  Returns the step numbers (1-based) after which it was
+    updated."""
+    dev = q_n.device
+    t_dev = torch.zeros(1, dtype=torch.float64, device=dev) if t_dev is None else t_dev
+    dt_dev = torch.zeros(1, dtype=torch.float64, device=dev) if dt_dev is None else dt_dev
+    updates, since = [], 0
+    for s in range(1, steps + 1):
+        grid.step(q_n, q_s, prim, metric, cfl, 1e30, t_dev, dt_dev, flags, nfatal)
+        since += 1
+        if since >= every or psi_residual(grid, mpsi, q_n, metric, mvec, X) > eps:
+            metric_update(grid, mpsi, malpha, q_n, prim, metric, mvec, X, flags, nfatal, tol, max_cycles)
+            updates.append(s)
+            since = 0
+    return updates
 
 
 def xcfc_solve(mvec, mpsi, malpha, grid_params, q, prim, metric, X, tol=1e-12, max_cycles=60):

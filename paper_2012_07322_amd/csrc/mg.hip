@@ -1877,6 +1877,35 @@ int gmunu_mg_xcfc_solve(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, const 
   return launch_status();
 }
 
+int gmunu_mg_psi_residual(gmunu_mg *mvec, gmunu_mg *mpsi, const gmunu_grid_desc *hydro, const double *q,
+                          const double *metric, const double *X, double *norm_out, void *stream) {
+  if (!mpsi || !hydro || !q || !metric || !norm_out || (mvec && !X)) return GMUNU_ENULL;
+  if (!aligned8(q) || !aligned8(metric) || (X && !aligned8(X))) return GMUNU_EALIGN;
+  Hydro H;
+  int rc = hydro_of(mpsi, hydro, H);
+  if (!rc && mvec) rc = hydro_of(mvec, hydro, H);
+  if (rc) return rc;
+  if (mpsi->d.power != -1 || mpsi->d.offset != 1.0 || (mvec && (!vector_ok(mvec) || mpsi->d.power2 != -7)))
+    return GMUNU_EINVAL;
+  if (!bridge_scratch(mpsi)) return GMUNU_ENOMEM;
+  if (mvec && !mvec->xs && !alloc_zeroed(mvec, 17 * (size_t)mvec->geo[mvec->levels - 1].nt, &mvec->xs))
+    return GMUNU_ENOMEM;
+  hipStream_t st = as_stream(stream);
+  const MgGeo &G = mpsi->geo[mpsi->levels - 1];
+  double *u = mpsi->br, *a = mpsi->br + G.nt, *f = mpsi->br + 2 * G.nt, *a2 = mpsi->br + 3 * G.nt;
+  const double *A2 = nullptr;
+  if (mvec) {
+    const MgGeo &V = mvec->geo[mvec->levels - 1];
+    double *A6 = mvec->xs + 9 * V.nt, *A2v = mvec->xs + 15 * V.nt;
+    hipLaunchKernelGGL(k_mgv_aij, dim3(nblocks(cells(V))), dim3(NT), 0, st, V, X, A6, A2v);
+    A2 = A2v;
+  }
+  if (hipMemsetAsync(f, 0, (size_t)G.nt * sizeof(double), st) != hipSuccess) return GMUNU_EHIP;
+  hipLaunchKernelGGL(k_br_cfc_coef, dim3(nblocks(cells(G))), dim3(NT), 0, st, G, H, q, metric, metric, 0, A2, a, a2,
+                     u);
+  return gmunu_mg_residual_norm(mpsi, u, f, a, A2 ? a2 : nullptr, norm_out, stream);
+}
+
 int gmunu_mg_metric_update(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, gmunu_ctx *ctx,
                            const gmunu_grid_desc *hydro, double *q, double *prim, double *metric, double *X,
                            uint8_t *flags, unsigned int *nfatal_dev, double tol, int max_cycles, int *cycles_out,

@@ -652,3 +652,63 @@ def test_tov_star_stays_in_equilibrium_with_a_dynamical_metric():
          f"max |psi_c/psi_c0 - 1| {drift_psi:.2e}")
     assert int(nf.item()) == 0
     assert drift_rho < 2e-2 and drift_psi < 2e-3
+
+
+def test_psi_residual_matches_the_oracle():
+    """The conformal-factor residual (the re-solve trigger of section 2.6)
+    against the oracle: on a TOV star with the flat metric (large) and
+    with its own metric (small), and with the A2 term of an xCFC state."""
+    hp, pr, met, q, ps, pa = _tov_state(32, 8)
+    g = gmu.Grid(hp)
+    Mp = gmu.Multigrid(ps)
+    flat = met.copy()
+    flat[0] = 1.0
+    flat[1] = 1.0
+    vals = []
+    for m in (flat, met):
+        rg = gmu.psi_residual(g, Mp, dev(q), dev(m))
+        ro = mg.psi_residual(hp, ps, q, m)
+        vals.append(ro)
+        assert abs(rg - ro) <= 1e-12 * ro, (rg, ro)
+    assert vals[1] < 0.5 * vals[0]  # the star's own metric nearly satisfies the constraint
+    import workloads as W
+    hp, pr, met = W.rotating_star_3d(16, 12.0, 0.02)
+    pr = oracle.fill_ghosts(hp, np.ascontiguousarray(pr))
+    q = oracle.prim2con(hp, pr, met)
+    base = dict(ndim=3, coord=CART, n=[16] * 3, xmin=[-12.0] * 3, dx=[1.5] * 3, bc=[[D, D]] * 3)
+    pv, ps = dict(base), dict(base, bc=[[ROB, ROB]] * 3, power=-1, power2=-7, offset=1.0)
+    X = np.ascontiguousarray(random_field(pv, 41, True) * 0.01)
+    rg = gmu.psi_residual(gmu.Grid(hp), gmu.Multigrid(ps), dev(q), dev(met), gmu.Multigrid(pv), dev(X))
+    ro = mg.psi_residual(hp, ps, q, met, pv, X)
+    assert abs(rg - ro) <= 1e-12 * ro, (rg, ro)
+
+
+def test_adaptive_metric_updates_follow_the_residual():
+    """evolve_dynamical on a pulsating TOV star with Delta n = 1000 and a
+    residual threshold: the metric is re-solved exactly after the steps at
+    which the oracle's loop (oracle evolution, oracle residual, oracle
+    update) re-solves it, and the states agree."""
+    hp, pr, met, q, ps, pa = _tov_state(32, 8, vpert=2e-2)
+    g = gmu.Grid(hp)
+    Mp, Ma = gmu.Multigrid(ps), gmu.Multigrid(pa)
+    qd, prd, md = dev(q), dev(pr), dev(met)
+    qs = torch.zeros_like(qd)
+    r0 = mg.psi_residual(hp, ps, q, met)
+    eps = 1.05 * r0  # the pulsation moves matter: the residual grows above it within a few steps
+    upd = gmu.evolve_dynamical(g, qd, qs, prd, md, Mp, Ma, 0.4, 30, every=1000, eps=eps, tol=1e-12, max_cycles=300)
+    qo, pro, mo = q.copy(), pr.copy(), met.copy()
+    to, upd_o = 0.0, []
+    for s in range(1, 31):
+        _, to, nfo = oracle.evolve(hp, qo, pro, mo, 0.4, to, nsteps=1)
+        if mg.psi_residual(hp, ps, qo, mo) > eps:
+            qc, pc, _, _, _ = mg.metric_update(hp, ps, pa, qo, pro, mo, tol=1e-12, max_cycles=300)
+            qo[...] = qc
+            pro[...] = pc
+            upd_o.append(s)
+    note(f"  adaptive updates after steps gpu {upd} oracle {upd_o} (eps {eps:.3e})")
+    assert upd == upd_o and len(upd) >= 1
+    L = (Ellipsis,) + tuple(slice(hp["ng"], hp["ng"] + hp["n"][a]) if a < 2 else slice(None) for a in (2, 1, 0))
+    A, B = host(qd)[L], qo[L]
+    smom = max(np.abs(B[v]).max() for v in (1, 2, 3))
+    diffs = [np.abs(A[v] - B[v]).max() / (smom if v in (1, 2, 3) else np.abs(B[v]).max()) for v in range(5)]
+    assert max(diffs) <= 1e-9, diffs
