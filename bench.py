@@ -394,7 +394,8 @@ def bench_mg(n=256, half=200.0, vcycles=8, sweeps=10):
     one FAS full-multigrid cycle, V-cycles (each with its residual norm and
     host read-back), and smoothing sweeps of the finest level alone (the
     dominant kernel: algorithmic bytes per sweep 40 per cell = u read by
-    both colours, f and a once, each cell written once)."""
+    both colours, f and a once, each cell written once; the timed call
+    includes its one refresh of the colour-split copies of f and a)."""
     import torch
 
     import paper_2012_07322_amd as gmu

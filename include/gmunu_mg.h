@@ -76,7 +76,9 @@ int gmunu_mg_levels(const gmunu_mg *mg);
 /* Entries of one array of level l (l = levels - 1 is the finest). */
 long gmunu_mg_size(const gmunu_mg *mg, int level);
 
-/* Solve L(u) = f on the finest level in place: an FAS full-multigrid cycle
+/* Solve L(u) = f on the finest level in place (on a large finest level the
+ * first call allocates colour-split copies of f, a and a2 that the
+ * red-black sweeps read): an FAS full-multigrid cycle
  * from the current u first when fmg != 0, then FAS V-cycles until
  * max |f - L(u)| <= tol or max_cycles cycles were done (the FMG cycle
  * counts as one).  a and a2 may be NULL (zero); a2 needs power2 != 0
@@ -93,9 +95,10 @@ int gmunu_mg_residual_norm(gmunu_mg *mg, double *u, const double *f, const doubl
 
 /* Building blocks (finest level unless a level is given), for checking:
  * out = L(u) on the interior with u's ghosts as given; ghost fill; `sweeps`
- * red-black sweeps; restriction of level l into level l - 1 (volume-weighted
- * mean of children); Kwak prolongation of level l - 1 (ghosts as given)
- * into level l. */
+ * red-black sweeps (on a large finest level f, a and a2 are first copied
+ * into colour-split buffers of the hierarchy, as in the solve); restriction
+ * of level l into level l - 1 (volume-weighted mean of children); Kwak
+ * prolongation of level l - 1 (ghosts as given) into level l. */
 int gmunu_mg_apply(gmunu_mg *mg, const double *u, const double *a, const double *a2, double *out, void *stream);
 int gmunu_mg_fill_ghosts(gmunu_mg *mg, int level, double *u, void *stream);
 int gmunu_mg_smooth(gmunu_mg *mg, double *u, const double *f, const double *a, const double *a2, int sweeps,

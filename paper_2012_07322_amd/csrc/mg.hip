@@ -114,8 +114,8 @@ __device__ __forceinline__ double mg_nb(const MgGeo &G, const double *__restrict
 // neighbours across the boundary from u's ghost entries as stored; else
 // from the boundary rule (mg_nb), so that no ghost fill is needed.
 template <bool GH>
-__device__ __forceinline__ double mg_L(const MgGeo &G, const double *__restrict__ u, const double *__restrict__ a,
-                                       const double *__restrict__ a2, int i, int j, int k, long o, double *dg) {
+__device__ __forceinline__ double mg_L(const MgGeo &G, const double *__restrict__ u, double av, double a2v, int i,
+                                       int j, int k, long o, double *dg) {
   const int I = i + G.g[0], J = j + G.g[1];
   const double uc = u[o];
   double wm = G.a0m[I], wp = G.a0p[I];
@@ -139,7 +139,6 @@ __device__ __forceinline__ double mg_L(const MgGeo &G, const double *__restrict_
     lap += w * (up - uc) - w * (uc - um);
     d -= 2.0 * w;
   }
-  const double av = a ? a[o] : 0.0, a2v = a2 ? a2[o] : 0.0;
   if (dg) *dg = d - mg_nl_du(G, av, a2v, uc);
   return lap - mg_nl(G, av, a2v, uc);
 }
@@ -204,10 +203,14 @@ __global__ __launch_bounds__(NT) void k_mg_ghosts(const MgGeo G, double *u) {
 }
 
 // One colour of red-black Newton-Gauss-Seidel: thread t -> the t-th cell of
-// that colour (every other cell of a row).
+// that colour (every other cell of a row).  With fs non-null, f, a and a2
+// are read from colour-split copies (per row the even-i cells, then the odd
+// ones), so that a colour reads them contiguously.
 __device__ __forceinline__ void mg_smooth_one(const MgGeo &G, double *u, const double *__restrict__ f,
                                               const double *__restrict__ a, const double *__restrict__ a2, int colour,
-                                              long t) {
+                                              long t, const double *__restrict__ fs = nullptr,
+                                              const double *__restrict__ as = nullptr,
+                                              const double *__restrict__ a2s = nullptr) {
   const unsigned hrow = (unsigned)(G.n[0] + 1) >> 1, n1 = (unsigned)G.n[1];
   if (t >= (long)hrow * G.n[1] * G.n[2]) return;
   const unsigned row = (unsigned)t / hrow;
@@ -215,15 +218,39 @@ __device__ __forceinline__ void mg_smooth_one(const MgGeo &G, double *u, const d
   const int i = (int)((unsigned)t - row * hrow) * 2 + ((j + k + colour) & 1);
   if (i >= G.n[0]) return;
   const long o = mg_off(G, i, j, k);
+  double fv, av, a2v;
+  if (fs) {
+    const long si = (long)row * G.n[0] + (long)(i & 1) * hrow + (i >> 1);
+    fv = fs[si];
+    av = as ? as[si] : 0.0;
+    a2v = a2s ? a2s[si] : 0.0;
+  } else {
+    fv = f[o];
+    av = a ? a[o] : 0.0;
+    a2v = a2 ? a2[o] : 0.0;
+  }
   double dg;
-  const double Lu = mg_L<false>(G, u, a, a2, i, j, k, o, &dg);
-  u[o] -= (Lu - f[o]) / dg;
+  const double Lu = mg_L<false>(G, u, av, a2v, i, j, k, o, &dg);
+  u[o] -= (Lu - fv) / dg;
 }
 
 __global__ __launch_bounds__(NT) void k_mg_smooth(const MgGeo G, double *u, const double *__restrict__ f,
                                                   const double *__restrict__ a, const double *__restrict__ a2,
-                                                  int colour) {
-  mg_smooth_one(G, u, f, a, a2, colour, (long)blockIdx.x * NT + threadIdx.x);
+                                                  int colour, const double *__restrict__ fs,
+                                                  const double *__restrict__ as, const double *__restrict__ a2s) {
+  mg_smooth_one(G, u, f, a, a2, colour, (long)blockIdx.x * NT + threadIdx.x, fs, as, a2s);
+}
+
+// Colour-split copy of an interior array: per row the even-i cells, then
+// the odd-i cells (the layout mg_smooth_one reads with fs).
+__global__ __launch_bounds__(NT) void k_mg_split(const MgGeo G, const double *__restrict__ src,
+                                                 double *__restrict__ dst) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  if (t >= mg_cells(G)) return;
+  int i, j, k;
+  mg_cell(G, t, i, j, k);
+  const long row = (long)k * G.n[1] + j, hrow = (G.n[0] + 1) >> 1;
+  dst[row * G.n[0] + (i & 1) * hrow + (i >> 1)] = src[mg_off(G, i, j, k)];
 }
 
 // The coarsest-level solver: `sweeps` red-black sweeps by one workgroup,
@@ -275,7 +302,7 @@ __global__ __launch_bounds__(NT) void k_mg_apply(const MgGeo G, const double *__
   int i, j, k;
   mg_cell(G, t, i, j, k);
   const long o = mg_off(G, i, j, k);
-  out[o] = mg_L<true>(G, u, a, a2, i, j, k, o, nullptr);
+  out[o] = mg_L<true>(G, u, a ? a[o] : 0.0, a2 ? a2[o] : 0.0, i, j, k, o, nullptr);
 }
 
 // Per-workgroup maxima of |f - L(u)| over a grid-stride range of cells.
@@ -287,7 +314,7 @@ __global__ __launch_bounds__(NT) void k_mg_norm(const MgGeo G, const double *__r
     int i, j, k;
     mg_cell(G, t, i, j, k);
     const long o = mg_off(G, i, j, k);
-    m = fmax(m, fabs(f[o] - mg_L<false>(G, u, a, a2, i, j, k, o, nullptr)));
+    m = fmax(m, fabs(f[o] - mg_L<false>(G, u, a ? a[o] : 0.0, a2 ? a2[o] : 0.0, i, j, k, o, nullptr)));
   }
   m = block_max(m);
   if (threadIdx.x == 0) part[blockIdx.x] = m;
@@ -330,7 +357,7 @@ __global__ __launch_bounds__(NT) void k_mg_fas_rhs(const MgGeo C, const double *
   int i, j, k;
   mg_cell(C, t, i, j, k);
   const long o = mg_off(C, i, j, k);
-  f[o] = mg_L<false>(C, u, a, a2, i, j, k, o, nullptr) + r[o];
+  f[o] = mg_L<false>(C, u, a ? a[o] : 0.0, a2 ? a2[o] : 0.0, i, j, k, o, nullptr) + r[o];
   uo[o] = u[o];
 }
 
@@ -354,7 +381,7 @@ __global__ __launch_bounds__(NT) void k_mg_restrict_res(const MgGeo F, const MgG
     const double v = F.vol0[fi + F.g[0]] * F.vol1[fj + F.g[1]];
     const long o = mg_off(F, fi, fj, fk);
     su += v * u[o];
-    sr += v * (f[o] - mg_L<false>(F, u, a, a2, fi, fj, fk, o, nullptr));
+    sr += v * (f[o] - mg_L<false>(F, u, a ? a[o] : 0.0, a2 ? a2[o] : 0.0, fi, fj, fk, o, nullptr));
     w += v;
   }
   const long oc = mg_off(C, i, j, k);
@@ -977,6 +1004,10 @@ struct gmunu_mg {
   double *u[kMaxLevels], *f[kMaxLevels], *a[kMaxLevels], *r[kMaxLevels], *uo[kMaxLevels];
   double *aown[kMaxLevels];  // coarse-level storage of a
   double *a2[kMaxLevels], *a2own[kMaxLevels];  // the same for a2 (allocated when power2 != 0)
+  // colour-split copies of the finest f, a, a2 for the red-black sweeps
+  // (allocated by the first solve of a large enough level; fs == NULL: none)
+  double *fs, *as, *a2s;
+  const double *sf, *sa, *sa2;  // the split copies' sources in the cycles being run
   double *part;  // norm partials + result
   double *br;    // state bridge scratch (6 arrays of the finest level), allocated on first use
   // vector equations (Cartesian): per coarse level u, f, r, uo of three
@@ -1143,11 +1174,11 @@ void ghosts(const MgGeo &G, double *u, hipStream_t st) {
 
 // Red-black sweeps (boundary rule inline: no ghost fill between colours).
 void sweeps_raw(const MgGeo &G, double *u, const double *f, const double *a, const double *a2, int sweeps,
-                hipStream_t st) {
+                hipStream_t st, const double *fs = nullptr, const double *as = nullptr, const double *a2s = nullptr) {
   const long threads = (long)((G.n[0] + 1) / 2) * G.n[1] * G.n[2];
   for (int s = 0; s < sweeps; s++)
     for (int c = 0; c < 2; c++)
-      hipLaunchKernelGGL(k_mg_smooth, dim3(nblocks(threads)), dim3(NT), 0, st, G, u, f, a, a2, c);
+      hipLaunchKernelGGL(k_mg_smooth, dim3(nblocks(threads)), dim3(NT), 0, st, G, u, f, a, a2, c, fs, as, a2s);
 }
 
 // The same, then u's ghost entries from the boundary rule.
@@ -1194,11 +1225,14 @@ void vcycle(gmunu_mg *m, int l, hipStream_t st) {
     coarse_solve(m, st);
     return;
   }
-  sweeps_raw(m->geo[l], m->u[l], m->f[l], m->a[l], m->a2[l], m->d.pre, st);
+  const bool sp = l == m->levels - 1 && m->sf;  // finest level: colour-split f, a, a2
+  sweeps_raw(m->geo[l], m->u[l], m->f[l], m->a[l], m->a2[l], m->d.pre, st, sp ? m->fs : nullptr,
+             sp && m->sa ? m->as : nullptr, sp && m->sa2 ? m->a2s : nullptr);
   coarse_problem(m, l, st);
   vcycle(m, l - 1, st);
   correct(m, l, st);
-  sweeps_raw(m->geo[l], m->u[l], m->f[l], m->a[l], m->a2[l], m->d.post, st);
+  sweeps_raw(m->geo[l], m->u[l], m->f[l], m->a[l], m->a2[l], m->d.post, st, sp ? m->fs : nullptr,
+             sp && m->sa ? m->as : nullptr, sp && m->sa2 ? m->a2s : nullptr);
 }
 
 void fmg(gmunu_mg *m, hipStream_t st) {
@@ -1225,8 +1259,10 @@ int norm(gmunu_mg *m, double *out, hipStream_t st) {
   return launch_status();
 }
 
-// Bind the caller's finest-level arrays and restrict a and a2 to the coarse
-// levels.
+void split_copies(gmunu_mg *m, const double *f, const double *a, const double *a2, hipStream_t st);
+
+// Bind the caller's finest-level arrays, restrict a and a2 to the coarse
+// levels and refresh the colour-split copies.
 void bind(gmunu_mg *m, double *u, const double *f, const double *a, const double *a2, hipStream_t st) {
   const int top = m->levels - 1;
   m->u[top] = u;
@@ -1243,6 +1279,28 @@ void bind(gmunu_mg *m, double *u, const double *f, const double *a, const double
       hipLaunchKernelGGL(k_mg_restrict, dim3(nblocks(cells(m->geo[l - 1]))), dim3(NT), 0, st, m->geo[l],
                          m->geo[l - 1], m->a2[l], m->a2[l - 1]);
   }
+  split_copies(m, f, a, a2, st);
+}
+
+// Colour-split copies of the finest f, a, a2 for the red-black sweeps
+// (large levels only: the copies cost one pass and save one per sweep).
+void split_copies(gmunu_mg *m, const double *f, const double *a, const double *a2, hipStream_t st) {
+  const MgGeo &G = m->geo[m->levels - 1];
+  m->sf = m->sa = m->sa2 = nullptr;
+  if (cells(G) < 32768 || G.n[0] < 16) return;
+  const size_t bytes = (size_t)cells(G) * sizeof(double);
+  auto get = [&](double *&p) {
+    if (!p && hipMalloc(&p, bytes) == hipSuccess) m->owned.push_back(p);
+    return p != nullptr;
+  };
+  if (!get(m->fs) || (a && !get(m->as)) || (a2 && !get(m->a2s))) return;
+  const dim3 gr(nblocks(cells(G)));
+  hipLaunchKernelGGL(k_mg_split, gr, dim3(NT), 0, st, G, f, m->fs);
+  if (a) hipLaunchKernelGGL(k_mg_split, gr, dim3(NT), 0, st, G, a, m->as);
+  if (a2) hipLaunchKernelGGL(k_mg_split, gr, dim3(NT), 0, st, G, a2, m->a2s);
+  m->sf = f;
+  m->sa = a;
+  m->sa2 = a2;
 }
 
 // a2 is accepted only by a hierarchy whose equation has the second term.
@@ -1482,6 +1540,8 @@ int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out) {
   };
   m->br = nullptr;
   m->xs = nullptr;
+  m->fs = m->as = m->a2s = nullptr;
+  m->sf = m->sa = m->sa2 = nullptr;
   m->vready = false;
   m->gs = nullptr;
   m->ev = nullptr;
@@ -1609,7 +1669,13 @@ int gmunu_mg_smooth(gmunu_mg *m, double *u, const double *f, const double *a, co
   if (!m || !u || !f) return GMUNU_ENULL;
   if (!ok_ptr(u) || !ok_ptr(f) || (a && !aligned8(a))) return GMUNU_EALIGN;
   if (sweeps < 0 || !a2_ok(m, a2)) return GMUNU_EINVAL;
-  smooth(m->geo[m->levels - 1], u, f, a, a2, sweeps, as_stream(stream));
+  hipStream_t st = as_stream(stream);
+  const MgGeo &G = m->geo[m->levels - 1];
+  split_copies(m, f, a, a2, st);
+  const bool sp = m->sf != nullptr;
+  sweeps_raw(G, u, f, a, a2, sweeps, st, sp ? m->fs : nullptr, sp && a ? m->as : nullptr,
+             sp && a2 ? m->a2s : nullptr);
+  ghosts(G, u, st);
   return launch_status();
 }
 

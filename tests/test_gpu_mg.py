@@ -97,9 +97,13 @@ def test_ghost_fill_and_operator_parity(case):
         assert np.abs(Lg - Lo).max() <= 1e-12 * np.abs(Lo).max(), (power, np.abs(Lg - Lo).max())
 
 
-@pytest.mark.parametrize("case", ["cart3d", "sph2d", "cyl3d", "cart3d_robin"])
+# large enough for the colour-split copies of f, a, a2 (>= 32768 cells)
+SPLIT = prob(3, CART, (64, 32, 16), (0, 0, 0), (1, 0.5, 0.25), [[D, N], [PER, PER], [ROB, D]])
+
+
+@pytest.mark.parametrize("case", ["cart3d", "sph2d", "cyl3d", "cart3d_robin", "split"])
 def test_smoothing_sweep_parity(case):
-    p = dict(CASES[case], power=-1, offset=2.0)
+    p = dict(CASES[case] if case != "split" else SPLIT, power=-1, offset=2.0)
     M = gmu.Multigrid(p)
     u, f, a = random_field(p, 3), random_field(p, 4), random_field(p, 5) * 0.1
     ug = dev(u)
@@ -318,12 +322,12 @@ def test_cfc_solve_recovers_the_tov_metric():
 
 # ------------------------------------- second non-linear term (power2)
 
-@pytest.mark.parametrize("case", ["cart3d", "sph2d"])
+@pytest.mark.parametrize("case", ["cart3d", "sph2d", "split"])
 def test_second_term_operator_sweep_and_solve_parity(case):
     """L(u) = Lap(u) - a (u + c)^-1 - a2 (u + c)^-7 (the conformal-factor
     equation with its extrinsic-curvature term): operator, two sweeps and a
     solve against the oracle."""
-    p = dict(CASES[case], power=-1, power2=-7, offset=2.0)
+    p = dict(CASES[case] if case != "split" else SPLIT, power=-1, power2=-7, offset=2.0)
     M = gmu.Multigrid(p)
     u, f = random_field(p, 11), random_field(p, 12)
     a, a2 = random_field(p, 13) * 0.1, random_field(p, 14) * 0.1
