@@ -192,14 +192,24 @@ def solve(p, u, f, a=None, tol=1e-12, max_cycles=30, fmg=True, a2=None):
 
 
 def _cart(d):
-    if d.coord != CART or any(d.bc[a][s] == ROBIN for a in range(3) for s in (0, 1)):
-        raise ValueError("the vector operator is for Cartesian grids without Robin faces")
+    """Grids the vector equations take: Cartesian, or axisymmetric
+    cylindrical / spherical (at most two active axes), no Robin faces; a
+    spherical grid reaching r = 0 must end at theta = pi/2 (equatorial
+    symmetry: the mirror of the centre is then the cell itself)."""
+    if any(d.bc[a][s] == ROBIN for a in range(3) for s in (0, 1)):
+        raise ValueError("the vector equations take no Robin faces")
+    if d.coord != CART and d.ndim > 2:
+        raise ValueError("curvilinear vector equations are axisymmetric (at most two active axes)")
+    if d.coord == SPH and abs(d.xmin[0]) < 1e-12:
+        if d.ndim < 2 or abs(d.xmin[1] + d.n[1] * d.dx[1] - math.pi / 2) > 1e-12:
+            raise ValueError("a spherical vector grid reaching r = 0 must end at theta = pi/2")
     return d
 
 
 def vapply(p, X):
-    """Lap X^i + (1/3) d_i d_j X^j on the interior (X: shape (3, ...), ghosts
-    ignored: values across the boundary come from the boundary rule)."""
+    """L(X) = Lap X + (1/3) grad div X in orthonormal components on the
+    interior (X: shape (3, ...), ghosts ignored: values across the boundary
+    come from the boundary rule)."""
     d = _cart(make_desc(p))
     out = np.zeros_like(X)
     lib().om_vapply(ctypes.byref(d), _p(_c(X)), _p(out))

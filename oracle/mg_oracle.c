@@ -530,66 +530,141 @@ void om_subtract_gradient(const om_desc *d, const double *u, double *q) {
 }
 
 /* ------------------------------------------------------------------------
- * Vector equations of the xCFC scheme (section 2.6) on Cartesian grids:
- *     L(X)^i = Lap X^i + (1/3) d_i (d_j X^j) = f^i,
- * second derivatives by the standard second-order differences, the mixed
- * ones d_i d_j (i != j) by the four-point corner formula of section 2.7.
- * Its stencil couples diagonal neighbours, which share a colour in the
- * red-black ordering, so the Gauss-Seidel sweep here visits the 2^ndim
- * colours (i mod 2, j mod 2, k mod 2) in turn (cells of one colour are
- * never neighbours, so a sweep does not depend on the order within a
- * colour).  Values across the boundary, edges and corners included, come
- * from the boundary rule applied per axis (mirror, times -1 for Dirichlet,
- * +1 for Neumann; periodic wrap).  A cell's three components are updated
- * together from the values before its update: where two axes mirror (a
- * corner of the domain) the mixed difference of one component reads the
- * cell's own other component, and this keeps a colour's update independent
- * of any ordering.  Same level hierarchy, restriction,
- * Kwak prolongation and FAS cycles as the scalar solver, per component.
- * Vector arrays: three component arrays back to back. */
+ * Vector equations of the xCFC scheme (section 2.6):
+ *     L(X)^i = Lap X^i + (1/3) grad_i (div X) = f^i,
+ * in orthonormal components (Cartesian x, y, z; cylindrical R, z, phi;
+ * spherical r, theta, phi; curvilinear grids axisymmetric, d/dphi = 0, at
+ * most two active axes).  Second derivatives by the standard second-order
+ * differences (the flux form of the scalar Laplacian of each system), the
+ * mixed ones by the four-point corner formula of section 2.7, first ones
+ * centred.  In curvilinear coordinates the vector Laplacian and grad div of
+ * orthonormal components carry the connection terms:
+ *   cylindrical: L_R = Lap A_R - A_R/R^2 + (1/3) d_R D,
+ *                L_z = Lap A_z + (1/3) d_z D,  L_phi = Lap A_phi - A_phi/R^2,
+ *                D = (1/R) d_R (R A_R) + d_z A_z,
+ *                d_R D = (1/R) d_R (R d_R A_R) - A_R/R^2 + d_R d_z A_z,
+ *                d_z D = (1/R) d_R d_z (R A_R) + d_z^2 A_z;
+ *   spherical:   L_r = Lap A_r - 2 A_r/r^2 - 2/(r^2 sin) d_th (sin A_th)
+ *                      + (1/3) d_r D,
+ *                L_th = Lap A_th - A_th/(r^2 sin^2) + (2/r^2) d_th A_r
+ *                      + (1/3) (1/r) d_th D,
+ *                L_phi = Lap A_phi - A_phi/(r^2 sin^2),
+ *                D = (1/r^2) d_r (r^2 A_r) + 1/(r sin) d_th (sin A_th),
+ *                d_r D = (1/r^2) d_r (r^2 d_r A_r) - 2 A_r/r^2
+ *                        + (1/sin) d_r d_th (sin A_th / r),
+ *                (1/r) d_th D = (1/r^3) d_r d_th (r^2 A_r)
+ *                        + 1/(r^2 sin) d_th (sin d_th A_th) - A_th/(r^2 sin^2).
+ * The mixed stencil couples diagonal neighbours, which share a colour in
+ * the red-black ordering, so the Gauss-Seidel sweep visits the 2^ndim
+ * colours (i mod 2, j mod 2, k mod 2) in turn; a colour's cells, and the
+ * three components of each cell, are updated together from the values
+ * before the colour's update.  Values across the boundary, edges and
+ * corners included, come from each axis's rule applied to each component:
+ * periodic wrap, or a mirror with a sign per component -- Dirichlet: all
+ * odd; Neumann (a symmetry face): the normal component odd, and also the
+ * phi component at the cylindrical axis and at the polar axis, and every
+ * component at the spherical centre (whose mirror image at theta -> pi -
+ * theta is the cell itself on equatorially symmetric grids, which the
+ * centre therefore requires).  Coordinates enter the corner weights with
+ * their signs, so across a mirror they extend the field's parity.  Same
+ * level hierarchy, volume-weighted restriction, Kwak prolongation and FAS
+ * cycles as the scalar solver, per component.  Vector arrays: three
+ * component arrays back to back. */
 
-static double vval(const om_desc *d, const lvl *L, const double *u, int i, int j, int k) {
+static double vsign(const om_desc *d, const lvl *L, int a, int side, int comp) {
+  if (d->bc[a][side] == OM_DIRICHLET) return -1.0;
+  int odd = comp == a;
+  double fpos = side == 0 ? d->xmin[a] : d->xmin[a] + L->n[a] * L->dx[a];
+  if (d->coord == OM_CYL && a == 0 && fabs(fpos) < 1e-12 && comp == 2) odd = 1;
+  if (d->coord == OM_SPH && a == 0 && fabs(fpos) < 1e-12) odd = 1;
+  if (d->coord == OM_SPH && a == 1 && (fabs(fpos) < 1e-12 || fabs(fpos - OM_PI) < 1e-12) && comp == 2) odd = 1;
+  return odd ? -1.0 : 1.0;
+}
+
+/* component comp of u at cell (i,j,k), inside or across the boundary */
+static double vval(const om_desc *d, const lvl *L, const double *u, int comp, int i, int j, int k) {
   int c[3] = {i, j, k};
   double fac = 1.0;
   for (int a = 0; a < d->ndim; a++) {
     int n = L->n[a];
     if (c[a] >= 0 && c[a] < n) continue;
     int side = c[a] < 0 ? 0 : 1;
-    int kind = d->bc[a][side];
-    if (kind == OM_PERIODIC) {
+    if (d->bc[a][side] == OM_PERIODIC) {
       c[a] = side == 0 ? c[a] + n : c[a] - n;
       continue;
     }
-    if (kind == OM_DIRICHLET) fac = -fac;
+    fac *= vsign(d, L, a, side, comp);
     c[a] = side == 0 ? -1 - c[a] : 2 * n - 1 - c[a];
   }
-  return fac * u[idx(d, L, c[0], c[1], c[2])];
+  return fac * u[comp * L->nt + idx(d, L, c[0], c[1], c[2])];
 }
 
-static double vapply_cell(const om_desc *d, const lvl *L, const double *u, int comp, int i, int j, int k,
+/* face ghosts of every component from the rule above */
+static void vfill_ghosts(const om_desc *d, const lvl *L, double *u) {
+  for (int comp = 0; comp < 3; comp++)
+    for (int a = 0; a < d->ndim; a++) {
+      int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+      for (int t2 = 0; t2 < L->n[b2]; t2++)
+        for (int t1 = 0; t1 < L->n[b1]; t1++)
+          for (int side = 0; side < 2; side++) {
+            int g[3];
+            g[b1] = t1;
+            g[b2] = t2;
+            g[a] = side == 0 ? -1 : L->n[a];
+            u[comp * L->nt + idx(d, L, g[0], g[1], g[2])] = vval(d, L, u, comp, g[0], g[1], g[2]);
+          }
+    }
+}
+
+/* axis-a term of the flux-form Laplacian of component comp, and its
+ * diagonal */
+static double vlap_axis(const om_desc *d, const lvl *L, const double *u, int comp, int a, int i, int j, int k,
+                        double *dg) {
+  int m[3] = {i, j, k}, p[3] = {i, j, k};
+  m[a]--;
+  p[a]++;
+  double wm, wp;
+  weights(d, L, a, i, j, k, &wm, &wp);
+  double u0 = u[comp * L->nt + idx(d, L, i, j, k)];
+  *dg = -(wm + wp);
+  return wp * (vval(d, L, u, comp, p[0], p[1], p[2]) - u0) - wm * (u0 - vval(d, L, u, comp, m[0], m[1], m[2]));
+}
+
+enum { W_ONE, W_R, W_SIN_OVER_R, W_R2 };
+
+/* four-point mixed difference d_0 d_1 of g = w(corner) * component b */
+static double vmix01(const om_desc *d, const lvl *L, const double *u, int b, int i, int j, int k, int wk) {
+  double s = 0.0;
+  for (int di = -1; di <= 1; di += 2)
+    for (int dj = -1; dj <= 1; dj += 2) {
+      double r = centre(d, L, 0, i + di), th = centre(d, L, 1, j + dj);
+      double w = wk == W_ONE ? 1.0 : wk == W_R ? r : wk == W_R2 ? r * r : sin(th) / r;
+      s += di * dj * w * vval(d, L, u, b, i + di, j + dj, k);
+    }
+  return s / (4.0 * L->dx[0] * L->dx[1]);
+}
+
+static double vapply_cart(const om_desc *d, const lvl *L, const double *u, int comp, int i, int j, int k,
                           double *diag) {
-  const long nt = L->nt;
-  const double *uc = u + comp * nt;
-  const double u0 = uc[idx(d, L, i, j, k)];
+  const double u0 = u[comp * L->nt + idx(d, L, i, j, k)];
   double lap = 0.0, dg = 0.0;
   for (int a = 0; a < d->ndim; a++) {
     int m[3] = {i, j, k}, p[3] = {i, j, k};
     m[a]--;
     p[a]++;
     double h2 = L->dx[a] * L->dx[a];
-    lap += (vval(d, L, uc, p[0], p[1], p[2]) - 2.0 * u0 + vval(d, L, uc, m[0], m[1], m[2])) / h2;
+    lap += (vval(d, L, u, comp, p[0], p[1], p[2]) - 2.0 * u0 + vval(d, L, u, comp, m[0], m[1], m[2])) / h2;
     dg -= 2.0 / h2;
   }
   double gd = 0.0;
   if (comp < d->ndim) {
     for (int b = 0; b < d->ndim; b++) {
-      const double *ub = u + b * nt;
       if (b == comp) {
         int m[3] = {i, j, k}, p[3] = {i, j, k};
         m[b]--;
         p[b]++;
         double h2 = L->dx[b] * L->dx[b];
-        gd += (vval(d, L, ub, p[0], p[1], p[2]) - 2.0 * u0 + vval(d, L, ub, m[0], m[1], m[2])) / h2;
+        gd += (vval(d, L, u, b, p[0], p[1], p[2]) - 2.0 * u0 + vval(d, L, u, b, m[0], m[1], m[2])) / h2;
         dg -= (2.0 / 3.0) / h2;
       } else {
         int pp[3] = {i, j, k}, pm[3] = {i, j, k}, mp[3] = {i, j, k}, mm[3] = {i, j, k};
@@ -597,14 +672,71 @@ static double vapply_cell(const om_desc *d, const lvl *L, const double *u, int c
         pm[comp]++; pm[b]--;
         mp[comp]--; mp[b]++;
         mm[comp]--; mm[b]--;
-        gd += (vval(d, L, ub, pp[0], pp[1], pp[2]) - vval(d, L, ub, pm[0], pm[1], pm[2]) -
-               vval(d, L, ub, mp[0], mp[1], mp[2]) + vval(d, L, ub, mm[0], mm[1], mm[2])) /
+        gd += (vval(d, L, u, b, pp[0], pp[1], pp[2]) - vval(d, L, u, b, pm[0], pm[1], pm[2]) -
+               vval(d, L, u, b, mp[0], mp[1], mp[2]) + vval(d, L, u, b, mm[0], mm[1], mm[2])) /
               (4.0 * L->dx[comp] * L->dx[b]);
       }
     }
   }
   if (diag) *diag = dg;
   return lap + gd / 3.0;
+}
+
+static double vapply_curv(const om_desc *d, const lvl *L, const double *u, int comp, int i, int j, int k,
+                          double *diag) {
+  const double u0 = u[comp * L->nt + idx(d, L, i, j, k)];
+  const int two = d->ndim > 1;
+  double dl0, dl1 = 0.0;
+  const double l0 = vlap_axis(d, L, u, comp, 0, i, j, k, &dl0);
+  const double l1 = two ? vlap_axis(d, L, u, comp, 1, i, j, k, &dl1) : 0.0;
+  const double lap = l0 + l1, dlap = dl0 + dl1;
+  const double r = centre(d, L, 0, i), ir2 = 1.0 / (r * r);
+  double Lq, dg;
+  if (d->coord == OM_CYL) {
+    if (comp == 0) {
+      const double mix = two ? vmix01(d, L, u, 1, i, j, k, W_ONE) : 0.0;
+      Lq = lap - u0 * ir2 + (l0 - u0 * ir2 + mix) / 3.0;
+      dg = dlap - ir2 + (dl0 - ir2) / 3.0;
+    } else if (comp == 1) {
+      const double mix = two ? vmix01(d, L, u, 0, i, j, k, W_R) / r : 0.0;
+      Lq = lap + (mix + l1) / 3.0;
+      dg = dlap + dl1 / 3.0;
+    } else {
+      Lq = lap - u0 * ir2;
+      dg = dlap - ir2;
+    }
+  } else {
+    const double s = sin(centre(d, L, 1, j)), is2 = 1.0 / (s * s);
+    if (comp == 0) {
+      double dth = 0.0, mix = 0.0;
+      if (two) {
+        dth = (sin(centre(d, L, 1, j + 1)) * vval(d, L, u, 1, i, j + 1, k) -
+               sin(centre(d, L, 1, j - 1)) * vval(d, L, u, 1, i, j - 1, k)) /
+              (2.0 * L->dx[1]);
+        mix = vmix01(d, L, u, 1, i, j, k, W_SIN_OVER_R) / s;
+      }
+      Lq = lap - 2.0 * u0 * ir2 - 2.0 * ir2 / s * dth + (l0 - 2.0 * u0 * ir2 + mix) / 3.0;
+      dg = dlap - 2.0 * ir2 + (dl0 - 2.0 * ir2) / 3.0;
+    } else if (comp == 1) {
+      double dr = 0.0, mix = 0.0;
+      if (two) {
+        dr = (vval(d, L, u, 0, i, j + 1, k) - vval(d, L, u, 0, i, j - 1, k)) / (2.0 * L->dx[1]);
+        mix = vmix01(d, L, u, 0, i, j, k, W_R2) / (r * r * r);
+      }
+      Lq = lap - u0 * ir2 * is2 + 2.0 * ir2 * dr + (mix + l1 - u0 * ir2 * is2) / 3.0;
+      dg = dlap - ir2 * is2 + (dl1 - ir2 * is2) / 3.0;
+    } else {
+      Lq = lap - u0 * ir2 * is2;
+      dg = dlap - ir2 * is2;
+    }
+  }
+  if (diag) *diag = dg;
+  return Lq;
+}
+
+static double vapply_cell(const om_desc *d, const lvl *L, const double *u, int comp, int i, int j, int k,
+                          double *diag) {
+  return d->coord == OM_CART ? vapply_cart(d, L, u, comp, i, j, k, diag) : vapply_curv(d, L, u, comp, i, j, k, diag);
 }
 
 static void vsmooth(const om_desc *d, const lvl *L, double *u, const double *f, int sweeps) {
@@ -683,10 +815,8 @@ static void vcoarse_problem(const om_desc *d, vhier *H, int l) {
 static void vcorrect(const om_desc *d, vhier *H, int l) {
   const lvl *C = &H->L[l - 1], *F = &H->L[l];
   for (long c = 0; c < 3 * C->nt; c++) H->uo[l - 1][c] = H->u[l - 1][c] - H->uo[l - 1][c];
-  for (int comp = 0; comp < 3; comp++) {
-    fill_ghosts(d, C, H->uo[l - 1] + comp * C->nt);
-    prolong(d, C, F, H->uo[l - 1] + comp * C->nt, H->u[l] + comp * F->nt, 1);
-  }
+  vfill_ghosts(d, C, H->uo[l - 1]);
+  for (int comp = 0; comp < 3; comp++) prolong(d, C, F, H->uo[l - 1] + comp * C->nt, H->u[l] + comp * F->nt, 1);
 }
 
 static void vvcycle(const om_desc *d, vhier *H, int l) {
@@ -756,16 +886,22 @@ int om_vsolve(const om_desc *d, double *u, const double *f, double tol, int max_
   return c;
 }
 
-/* A~^ij = d_i X^j + d_j X^i - (2/3) delta^ij d_k X^k (section 2.6, Cartesian,
- * centred first derivatives, boundary rule across the boundary) on the
- * interior: the six components (xx, yy, zz, xy, xz, yz) into A6 and
- * A~_ij A~^ij into a2. */
+/* A~^ij = grad^i X^j + grad^j X^i - (2/3) delta^ij div X (section 2.6) in
+ * orthonormal components, centred first derivatives with the boundary rule
+ * across the boundary, and the connection terms of cylindrical and
+ * spherical coordinates (d/dphi = 0):
+ *   cylindrical: grad_phi X_R = -X_phi/R, grad_phi X_phi = X_R/R;
+ *   spherical:   grad_th X_r = (d_th X_r - X_th)/r, grad_th X_th = (d_th X_th + X_r)/r,
+ *                grad_th X_phi = d_th X_phi / r, grad_phi X_r = -X_phi/r,
+ *                grad_phi X_th = -cot X_phi / r, grad_phi X_phi = (X_r + cot X_th)/r.
+ * On the interior: the six components (xx, yy, zz, xy, xz, yz, in the
+ * order of the axes) into A6 and A~_ij A~^ij into a2. */
 void om_xcfc_aij(const om_desc *d, const double *X, double *A6, double *a2) {
   lvl L = level_of(d, d->levels - 1);
   for (int k = 0; k < L.n[2]; k++)
     for (int j = 0; j < L.n[1]; j++)
       for (int i = 0; i < L.n[0]; i++) {
-        double g[3][3];  /* g[a][b] = d_a X^b */
+        double g[3][3];  /* g[a][b] = d_a X^b (coordinate derivative of component b) */
         for (int a = 0; a < 3; a++)
           for (int b = 0; b < 3; b++) {
             g[a][b] = 0.0;
@@ -773,26 +909,44 @@ void om_xcfc_aij(const om_desc *d, const double *X, double *A6, double *a2) {
             int m[3] = {i, j, k}, p[3] = {i, j, k};
             m[a]--;
             p[a]++;
-            const double *xb = X + b * L.nt;
-            g[a][b] = (vval(d, &L, xb, p[0], p[1], p[2]) - vval(d, &L, xb, m[0], m[1], m[2])) / (2.0 * L.dx[a]);
+            g[a][b] = (vval(d, &L, X, b, p[0], p[1], p[2]) - vval(d, &L, X, b, m[0], m[1], m[2])) / (2.0 * L.dx[a]);
           }
-        double dv = g[0][0] + g[1][1] + g[2][2];
+        long c = idx(d, &L, i, j, k);
+        double x[3] = {X[c], X[L.nt + c], X[2 * L.nt + c]};
+        double G[3][3];  /* G[a][b] = grad_a X_b, orthonormal */
+        for (int a = 0; a < 3; a++)
+          for (int b = 0; b < 3; b++) G[a][b] = g[a][b];
+        if (d->coord == OM_CYL) {
+          double R = centre(d, &L, 0, i);
+          G[2][0] = -x[2] / R;
+          G[2][1] = 0.0;
+          G[2][2] = x[0] / R;
+        } else if (d->coord == OM_SPH) {
+          double r = centre(d, &L, 0, i), th = centre(d, &L, 1, j), ct = cos(th) / sin(th);
+          G[1][0] = (g[1][0] - x[1]) / r;
+          G[1][1] = (g[1][1] + x[0]) / r;
+          G[1][2] = g[1][2] / r;
+          G[2][0] = -x[2] / r;
+          G[2][1] = -ct * x[2] / r;
+          G[2][2] = (x[0] + ct * x[1]) / r;
+        }
+        double dv = G[0][0] + G[1][1] + G[2][2];
         double A[3][3];
         for (int a = 0; a < 3; a++)
-          for (int b = 0; b < 3; b++) A[a][b] = g[a][b] + g[b][a] - (a == b ? 2.0 / 3.0 * dv : 0.0);
-        long c = idx(d, &L, i, j, k);
+          for (int b = 0; b < 3; b++) A[a][b] = G[a][b] + G[b][a] - (a == b ? 2.0 / 3.0 * dv : 0.0);
         const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
         for (int q = 0; q < 6; q++) A6[q * L.nt + c] = A[pa[q]][pb[q]];
-        double s = 0.0;
+        double sum = 0.0;
         for (int a = 0; a < 3; a++)
-          for (int b = 0; b < 3; b++) s += A[a][b] * A[a][b];
-        a2[c] = s;
+          for (int b = 0; b < 3; b++) sum += A[a][b] * A[a][b];
+        a2[c] = sum;
       }
 }
 
-/* Right-hand side of the shift equation (section 2.6, Cartesian):
- * 16 pi w S_i + 2 A~^ij d_j w with w = alpha psi^-6 (its ghosts set by the
- * caller), S = psi^6 S_i the rescaled momentum density and A6 from
+/* Right-hand side of the shift equation (section 2.6), orthonormal
+ * components: 16 pi w S_i + 2 A~^ij grad_j w with w = alpha psi^-6 (its
+ * ghosts set by the caller; grad_theta w = d_theta w / r in spherical
+ * coordinates), S = psi^6 S_i the rescaled momentum density and A6 from
  * om_xcfc_aij, on the interior. */
 void om_xcfc_beta_rhs(const om_desc *d, const double *w, const double *S, const double *A6, double *out) {
   lvl L = level_of(d, d->levels - 1);
@@ -808,6 +962,7 @@ void om_xcfc_beta_rhs(const om_desc *d, const double *w, const double *S, const 
           p[a]++;
           gw[a] = (w[idx(d, &L, p[0], p[1], p[2])] - w[idx(d, &L, m[0], m[1], m[2])]) / (2.0 * L.dx[a]);
         }
+        if (d->coord == OM_SPH) gw[1] /= centre(d, &L, 0, i);
         for (int a = 0; a < 3; a++) {
           double t = 0.0;
           for (int b = 0; b < 3; b++) t += A6[qi[a][b] * L.nt + c] * gw[b];
