@@ -70,6 +70,7 @@ def lib():
         L.om_solve.restype = I
         L.om_vapply.argtypes = [P, P, P]
         L.om_vsmooth.argtypes = [P, P, P, I]
+        L.om_vfill_ghosts.argtypes = [P, P]
         L.om_vsolve.argtypes = [P, P, P, D, I, I, P]
         L.om_vsolve.restype = I
         L.om_xcfc_aij.argtypes = [P, P, P, P]
@@ -216,6 +217,14 @@ def vapply(p, X):
     return out
 
 
+def vfill_ghosts(p, X):
+    """Face ghosts of a vector field (three components) from the vector
+    boundary rule."""
+    d = _cart(make_desc(p))
+    lib().om_vfill_ghosts(ctypes.byref(d), _p(_c(X)))
+    return X
+
+
 def vsmooth(p, X, f, sweeps=1):
     d = _cart(make_desc(p))
     lib().om_vsmooth(ctypes.byref(d), _p(_c(X)), _p(_c(f)), sweeps)
@@ -279,8 +288,9 @@ def centres(p, level=None):
 
 
 def fluid_stilde(psi, rho, wv, p, gamma):
-    """S~ = psi^6 (rho h W^2 v^2 + 3 p) of an ideal-gas fluid on a Cartesian
-    grid (section 2.6): W^2 v^2 = psi^4 sum_i (W v^i)^2, rho h = rho +
+    """S~ = psi^6 (rho h W^2 v^2 + 3 p) of an ideal-gas fluid (section 2.6):
+    W^2 v^2 = psi^4 sum_i (W v^i)^2 with orthonormal components W v^i
+    (Cartesian ones, or h_i times the contravariant ones), rho h = rho +
     gamma / (gamma - 1) p."""
     rhoh = rho + gamma / (gamma - 1.0) * p
     w2v2 = psi ** 4 * (wv[0] ** 2 + wv[1] ** 2 + wv[2] ** 2)
@@ -340,11 +350,47 @@ def interior_slices(p):
     return tuple(slice(g[ax], g[ax] + p["n"][ax]) for ax in (2, 1, 0))
 
 
-def extend(hp, p, u):
+def vodd(p, a, side):
+    """Components (bit q) odd across the non-periodic face (a, side) for the
+    vector equations: Dirichlet all; Neumann the normal one, plus phi at the
+    cylindrical and polar axes and every component at the spherical centre."""
+    kind = p["bc"][a][side]
+    if kind == DIRICHLET:
+        return 7
+    odd = 1 << a
+    fpos = p["xmin"][a] if side == 0 else p["xmin"][a] + p["n"][a] * p["dx"][a]
+    if p["coord"] == CYL and a == 0 and abs(fpos) < 1e-12:
+        odd |= 4
+    if p["coord"] == SPH and a == 0 and abs(fpos) < 1e-12:
+        odd = 7
+    if p["coord"] == SPH and a == 1 and (abs(fpos) < 1e-12 or abs(fpos - math.pi) < 1e-12):
+        odd |= 4
+    return odd
+
+
+def hscale(hp, c):
+    """Scale factor h_c of the reference metric at the (signed) cell centres
+    of the GRMHD layout: orthonormal component = h_c times the
+    contravariant one, the covariant one divided by h_c."""
+    g = [hp.get("ng", 2) if a < hp["ndim"] else 0 for a in range(3)]
+    x = [hp["xmin"][a] + (np.arange(-g[a], hp["n"][a] + g[a]) + 0.5) * hp["dx"][a] for a in range(3)]
+    x3, x2, x1 = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+    if hp["coord"] == CYL and c == 2:
+        return x1
+    if hp["coord"] == SPH and c == 1:
+        return x1
+    if hp["coord"] == SPH and c == 2:
+        return x1 * np.sin(x2)
+    return np.ones_like(x1)
+
+
+def extend(hp, p, u, comp=None):
     """A multigrid solution u (interior used) on every cell of the GRMHD
     layout of hp (ng ghost layers): each ghost layer from the boundary rule
     applied per layer, axis by axis (mirror about the face times -1 for
-    Dirichlet, +1 for Neumann, r_in / r_ghost for Robin; periodic wrap)."""
+    Dirichlet, +1 for Neumann, r_in / r_ghost for Robin; periodic wrap).
+    With comp, u is that orthonormal component of a vector field and the
+    mirror takes the component's parity (vodd)."""
     ng = hp.get("ng", 2)
     nd = p["ndim"]
     v = u[interior_slices(p)]
@@ -365,7 +411,10 @@ def extend(hp, p, u):
                 continue
             inn = -1 - idx[sel] if side == 0 else 2 * n - 1 - idx[sel]
             src[sel] = inn
-            if kind == DIRICHLET:
+            if comp is not None:
+                if (vodd(p, a, side) >> comp) & 1:
+                    fac[sel] = -1.0
+            elif kind == DIRICHLET:
                 fac[sel] = -1.0
             elif kind == ROBIN and p["coord"] == SPH:
                 x0, h = p["xmin"][0], p["dx"][0]
@@ -414,8 +463,9 @@ def fluid_stilde_curvilinear(hp, psi, prim):
 def metric_update(hp, ppsi, palpha, q, prim, met, tol=1e-12, max_cycles=60, pvec=None, X=None):
     """The metric of a GRMHD state re-solved from its conserved variables
     (section 2.6), then the primitives recovered on the new metric (section
-    2.5): with pvec (Cartesian) the xCFC sequence (xcfc_solve; X in/out, the
-    shift from its equation), else the scalar CFC equations for psi and
+    2.5): with pvec the xCFC sequence (xcfc_solve in orthonormal components:
+    S~_i / h_i in, the shift's contravariant components beta / h_i out; X
+    in/out), else the scalar CFC equations for psi and
     alpha psi with the shift left as it is (U~ = q_tau + q_D, S~ from the
     current primitives and the new psi).  met (psi, alpha, beta on every
     cell of the layout) is updated in place, ghost layers by the boundary
@@ -428,19 +478,21 @@ def metric_update(hp, ppsi, palpha, q, prim, met, tol=1e-12, max_cycles=60, pvec
     up = _to_mg(ppsi, hp, met[0] - 1.0)
     cyc = [0, 0, 0, 0]
     if pvec is not None:
-        S = np.ascontiguousarray(np.stack([_to_mg(pvec, hp, q[1 + c]) for c in range(3)]))
-        beta = np.ascontiguousarray(np.stack([_to_mg(pvec, hp, met[2 + c]) for c in range(3)]))
+        hs = [hscale(hp, c) for c in range(3)]
+        S = np.ascontiguousarray(np.stack([_to_mg(pvec, hp, q[1 + c] / hs[c]) for c in range(3)]))
+        beta = np.ascontiguousarray(np.stack([_to_mg(pvec, hp, met[2 + c] * hs[c]) for c in range(3)]))
         # initial guess of alpha psi from the metric as given (the converged
         # solution does not depend on it beyond the tolerance)
         ua = _to_mg(palpha, hp, met[1] * met[0] - 1.0)
         rho, P = _to_mg(pvec, hp, prim[0]), _to_mg(pvec, hp, prim[4])
-        wv = [_to_mg(pvec, hp, prim[1 + c]) for c in range(3)]
+        # orthonormal components h_c W v^c, so that W^2 v^2 = psi^4 sum (W v)^2
+        wv = [_to_mg(pvec, hp, prim[1 + c] * hs[c]) for c in range(3)]
         _, _, cyc = xcfc_solve(pvec, ppsi, palpha, U, S, lambda ps_: fluid_stilde(ps_, rho, wv, P, hp["gamma"]),
                                X, up, ua, beta, tol, max_cycles)
         met[0] = 1.0 + extend(hp, ppsi, up)
         met[1] = (1.0 + extend(hp, palpha, ua)) / met[0]
         for c in range(3):
-            met[2 + c] = extend(hp, pvec, beta[c])
+            met[2 + c] = extend(hp, pvec, beta[c], comp=c) / hs[c]
     else:
         zero = np.zeros_like(U)
         cyc[1] = len(solve(ppsi, up, zero, np.ascontiguousarray(-2.0 * math.pi * U), tol, max_cycles)) - 1

@@ -132,6 +132,10 @@ static void weights(const om_desc *d, const lvl *L, int a, int i, int j, int k, 
   }
 }
 
+/* running maximum of |v|; a NaN counts as infinite, so that a solution
+ * gone NaN never reads as converged */
+static double om_absmax(double m, double v) { return v != v ? INFINITY : fmax(m, fabs(v)); }
+
 static double ipow(double w, int q) {
   double r = 1.0;
   for (int e = q < 0 ? -q : q; e > 0; e--) r *= w;
@@ -408,7 +412,7 @@ static double max_residual(const om_desc *d, hier *H) {
   double m = 0.0;
   for (int k = 0; k < L->n[2]; k++)
     for (int j = 0; j < L->n[1]; j++)
-      for (int i = 0; i < L->n[0]; i++) m = fmax(m, fabs(H->r[top][idx(d, L, i, j, k)]));
+      for (int i = 0; i < L->n[0]; i++) m = om_absmax(m, H->r[top][idx(d, L, i, j, k)]);
   return m;
 }
 
@@ -551,7 +555,9 @@ void om_subtract_gradient(const om_desc *d, const double *u, double *q) {
  *                L_phi = Lap A_phi - A_phi/(r^2 sin^2),
  *                D = (1/r^2) d_r (r^2 A_r) + 1/(r sin) d_th (sin A_th),
  *                d_r D = (1/r^2) d_r (r^2 d_r A_r) - 2 A_r/r^2
- *                        + (1/sin) d_r d_th (sin A_th / r),
+ *                        + (1/sin) [(1/r) d_r d_th (sin A_th) - d_th (sin A_th) / r^2]
+ *                (the last written so that no corner radius divides: a
+ *                coarse level's ghost centre can lie at r = 0),
  *                (1/r) d_th D = (1/r^3) d_r d_th (r^2 A_r)
  *                        + 1/(r^2 sin) d_th (sin d_th A_th) - A_th/(r^2 sin^2).
  * The mixed stencil couples diagonal neighbours, which share a colour in
@@ -630,7 +636,7 @@ static double vlap_axis(const om_desc *d, const lvl *L, const double *u, int com
   return wp * (vval(d, L, u, comp, p[0], p[1], p[2]) - u0) - wm * (u0 - vval(d, L, u, comp, m[0], m[1], m[2]));
 }
 
-enum { W_ONE, W_R, W_SIN_OVER_R, W_R2 };
+enum { W_ONE, W_R, W_SIN, W_R2 };
 
 /* four-point mixed difference d_0 d_1 of g = w(corner) * component b */
 static double vmix01(const om_desc *d, const lvl *L, const double *u, int b, int i, int j, int k, int wk) {
@@ -638,7 +644,7 @@ static double vmix01(const om_desc *d, const lvl *L, const double *u, int b, int
   for (int di = -1; di <= 1; di += 2)
     for (int dj = -1; dj <= 1; dj += 2) {
       double r = centre(d, L, 0, i + di), th = centre(d, L, 1, j + dj);
-      double w = wk == W_ONE ? 1.0 : wk == W_R ? r : wk == W_R2 ? r * r : sin(th) / r;
+      double w = wk == W_ONE ? 1.0 : wk == W_R ? r : wk == W_R2 ? r * r : sin(th);
       s += di * dj * w * vval(d, L, u, b, i + di, j + dj, k);
     }
   return s / (4.0 * L->dx[0] * L->dx[1]);
@@ -713,7 +719,7 @@ static double vapply_curv(const om_desc *d, const lvl *L, const double *u, int c
         dth = (sin(centre(d, L, 1, j + 1)) * vval(d, L, u, 1, i, j + 1, k) -
                sin(centre(d, L, 1, j - 1)) * vval(d, L, u, 1, i, j - 1, k)) /
               (2.0 * L->dx[1]);
-        mix = vmix01(d, L, u, 1, i, j, k, W_SIN_OVER_R) / s;
+        mix = (vmix01(d, L, u, 1, i, j, k, W_SIN) / r - dth * ir2) / s;
       }
       Lq = lap - 2.0 * u0 * ir2 - 2.0 * ir2 / s * dth + (l0 - 2.0 * u0 * ir2 + mix) / 3.0;
       dg = dlap - 2.0 * ir2 + (dl0 - 2.0 * ir2) / 3.0;
@@ -849,7 +855,7 @@ static double vmax_residual(const om_desc *d, vhier *H) {
   for (int comp = 0; comp < 3; comp++)
     for (int k = 0; k < L->n[2]; k++)
       for (int j = 0; j < L->n[1]; j++)
-        for (int i = 0; i < L->n[0]; i++) m = fmax(m, fabs(H->r[top][comp * L->nt + idx(d, L, i, j, k)]));
+        for (int i = 0; i < L->n[0]; i++) m = om_absmax(m, H->r[top][comp * L->nt + idx(d, L, i, j, k)]);
   return m;
 }
 
@@ -866,6 +872,13 @@ void om_vapply(const om_desc *d, const double *u, double *out) {
 void om_vsmooth(const om_desc *d, double *u, const double *f, int sweeps) {
   lvl L = level_of(d, d->levels - 1);
   vsmooth(d, &L, u, f, sweeps);
+}
+
+/* Face ghosts of the three components of X on the finest level from the
+ * vector boundary rule (per-component parity). */
+void om_vfill_ghosts(const om_desc *d, double *u) {
+  lvl L = level_of(d, d->levels - 1);
+  vfill_ghosts(d, &L, u);
 }
 
 /* Solve L(X) = f like om_solve; the ghost entries of X are left zero. */

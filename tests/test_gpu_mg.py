@@ -358,6 +358,12 @@ VCASES = {
     "cart3d_ragged": prob(3, CART, (12, 20, 6), (0, 0, 0), (1.2, 2.0, 0.6), [[PER, PER], [N, D], [D, D]]),
     "cart2d": prob(2, CART, (16, 16), (0, 0), (1, 1), [[D, D], [PER, PER]]),
     "cart1d": prob(1, CART, (32,), (0,), (1,), [[D, N]]),
+    # axisymmetric (R, z) with the axis, orthonormal components
+    "cyl2d": prob(2, CYL, (16, 32), (0.0, -2.0), (2.0, 2.0), [[N, D], [D, D]]),
+    # (r, theta) on [0, 2] x [0, pi/2]: centre, polar axis, equator
+    "sph2d_eq": prob(2, SPH, (16, 8), (0.0, 0.0), (2.0, math.pi / 2), [[N, D], [N, N]], pre=4, post=4),
+    # a spherical shell over the full theta range
+    "sph2d_shell": prob(2, SPH, (16, 16), (0.5, 0.0), (2.5, math.pi), [[D, D], [N, N]], pre=4, post=4),
 }
 
 
@@ -395,18 +401,20 @@ def test_vector_solve_parity(case):
     assert hg[-1] <= 1e-11 and ho[-1] <= 1e-11
     g = host(Xg)
     scale = np.abs(Xo).max()
+    gv = mg.vfill_ghosts(p, np.ascontiguousarray(g.copy()))
     for i in range(3):
         assert np.abs(mg.interior(p, g[i]) - mg.interior(p, Xo[i])).max() <= 1e-10 * scale, i
-        # ghosts written from the boundary rule
-        assert np.array_equal(g[i], mg.fill_ghosts(p, g[i].copy())), i
+        # ghosts written from the vector boundary rule (per-component parity)
+        assert np.array_equal(g[i], gv[i]), i
     for a, b in zip(hg, ho):
         if b < 1e-5:
             break
         assert abs(a - b) <= 1e-6 * b, (a, b)
 
 
-def test_xcfc_aij_and_shift_source_parity():
-    p = VCASES["cart3d_ragged"]
+@pytest.mark.parametrize("case", ["cart3d_ragged", "cyl2d", "sph2d_eq"])
+def test_xcfc_aij_and_shift_source_parity(case):
+    p = VCASES[case]
     M = gmu.Multigrid(p)
     X = random_field(p, 31, True)
     A6g, A2g = M.xcfc_aij(dev(X))
@@ -449,6 +457,9 @@ def test_vector_and_second_term_misuse_is_rejected():
     Mr = gmu.Multigrid(CASES["cart3d_robin"])  # the vector equations take no Robin faces
     with pytest.raises(RuntimeError):
         Mr.vapply(Mr.empty(vector=True))
+    Ms = gmu.Multigrid(prob(2, SPH, (16, 16), (0.0, 0.0), (2.0, math.pi), [[N, D], [N, N]]))
+    with pytest.raises(RuntimeError):  # the centre needs an equatorially symmetric grid
+        Ms.vapply(Ms.empty(vector=True))
     M2 = gmu.Multigrid(CASES["cart3d"])  # power2 = 0: no second term
     u = M2.empty()
     with pytest.raises(RuntimeError):
@@ -716,3 +727,58 @@ def test_adaptive_metric_updates_follow_the_residual():
     smom = max(np.abs(B[v]).max() for v in (1, 2, 3))
     diffs = [np.abs(A[v] - B[v]).max() / (smom if v in (1, 2, 3) else np.abs(B[v]).max()) for v in range(5)]
     assert max(diffs) <= 1e-9, diffs
+
+
+def test_xcfc_metric_update_in_spherical_coordinates():
+    """The xCFC metric update of a uniformly rotating polytropic star on a 2D
+    spherical grid (r, theta) in [0, 20] x [0, pi/2] (centre, polar axis,
+    equator; Robin falloff for psi and alpha psi): X, psi, alpha and the
+    shift's contravariant components on every cell equal the oracle's update
+    (orthonormal conversions, per-component parities of the shift's ghost
+    layers); frame dragging: beta^phi = -omega < 0 inside the star."""
+    import workloads as W
+    nr, nth = 32, 8
+    hp = W.grid(2, W.SPH, [nr, nth], [0.0, 0.0, 0.0], [20.0, math.pi / 2, 2 * math.pi],
+                [[W.REFLECT, W.OUTFLOW], [W.AXIS, W.REFLECT]], gamma=2.0, rho_atmo=1e-10, k_atmo=100.0,
+                gamma_atmo=2.0)
+    star = W.tov_isotropic()
+    r, th, _ = W.centres(hp)
+    rho, psi, alpha = W.tov_fields(star, r)
+    rho = np.maximum(rho, 1e-10)
+    om = 0.02
+    met = W.flat_metric(hp)
+    met[0], met[1] = psi, alpha
+    pr = W.empty_prim(hp)
+    pr[0], pr[4] = rho, 100.0 * rho ** 2
+    vphi = np.where(rho > 1e-9, om, 0.0)
+    Wl = 1.0 / np.sqrt(1.0 - psi ** 4 * (r * np.sin(th)) ** 2 * vphi ** 2)
+    pr[3] = Wl * vphi
+    q = oracle.prim2con(hp, np.ascontiguousarray(pr), met)
+    flat = W.flat_metric(hp)
+    base = dict(ndim=2, coord=SPH, n=[nr, nth, 1], xmin=[0.0, 0.0, 0.0], dx=[20.0 / nr, math.pi / 2 / nth, 1.0],
+                pre=4, post=4)
+    pv = dict(base, bc=[[N, D], [N, N], [N, N]])
+    ps = dict(base, bc=[[N, ROB], [N, N], [N, N]], power=-1, power2=-7, offset=1.0)
+    pa = dict(base, bc=[[N, ROB], [N, N], [N, N]], power=1, offset=1.0)
+    g = gmu.Grid(hp)
+    Mv, Mp, Ma = gmu.Multigrid(pv), gmu.Multigrid(ps), gmu.Multigrid(pa)
+    Xg = Mv.empty(vector=True)
+    qd, prd, md = dev(q), dev(pr), dev(flat)
+    cyc = gmu.metric_update(g, Mp, Ma, qd, prd, md, mvec=Mv, X=Xg, tol=1e-11, max_cycles=400)
+    mo = flat.copy()
+    Xo = np.zeros((3,) + mg.shape(pv))
+    _, _, _, _, cyco = mg.metric_update(hp, ps, pa, q.copy(), pr.copy(), mo, tol=1e-11, max_cycles=400, pvec=pv,
+                                        X=Xo)
+    note(f"  spherical xCFC update: cycles gpu {cyc} oracle {list(cyco)}")
+    mgd = host(md)
+    assert np.abs(mgd[0] - mo[0]).max() <= 1e-9 * np.abs(mo[0] - 1).max()
+    assert np.abs(mgd[1] - mo[1]).max() <= 1e-9 * np.abs(mo[1] - 1).max()
+    bscale = np.abs(mo[4]).max()
+    assert bscale > 1e-4
+    for c in range(3):
+        assert np.abs(mgd[2 + c] - mo[2 + c]).max() <= 1e-8 * bscale, c
+    Xh = host(Xg)
+    for c in range(3):
+        assert np.abs(mg.interior(pv, Xh[c]) - mg.interior(pv, Xo[c])).max() <= 1e-9 * np.abs(Xo).max(), c
+    inside = (slice(None),) + (slice(hp["ng"], hp["ng"] + nth), slice(hp["ng"], hp["ng"] + nr // 4))
+    assert (mo[4][inside] < 0).all()  # frame dragging: omega = -beta^phi > 0 for positive rotation
