@@ -46,12 +46,17 @@ struct MgGeo {
   int bc[3][2];
   double rob_lo, rob_hi;  // Robin ghost factors on axis 0 (centre inside / centre of the ghost)
   double x0[3];           // lower face coordinate per axis (Cartesian Robin factors)
+  unsigned vodd[3][2];    // vector equations: components odd across each mirror face (bit q)
   int power, power2;
   double offset;
   // vector operator (Cartesian): 1/h_a^2, 1/(4 h_a h_b) for the axis pairs
   // (0,1), (0,2), (1,2), and the inverse diagonal of each component's row
   double vih2[3], vmix[3], vidg[3];
 };
+
+// Running maximum of |v|; a NaN counts as infinite, so that a solution gone
+// NaN never reads as converged.
+__device__ __forceinline__ double mg_absmax(double m, double v) { return v != v ? INFINITY : fmax(m, fabs(v)); }
 
 __device__ __forceinline__ long mg_off(const MgGeo &G, int i, int j, int k) {
   return (long)(k + G.g[2]) * G.s2 + (long)(j + G.g[1]) * G.s1 + (i + G.g[0]);
@@ -196,10 +201,46 @@ __device__ __forceinline__ long mg_ghost_count(const MgGeo &G) {
   return s;
 }
 
+// Face ghost t of component q of a vector field: periodic wrap or mirror
+// with the component's parity across that face.
+__device__ __forceinline__ void mgv_ghost_one(const MgGeo &G, double *u, int q, long t) {
+  for (int a = 0; a < G.ndim; a++) {
+    const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    const long per = 2L * G.n[b1] * G.n[b2];
+    if (t >= per) {
+      t -= per;
+      continue;
+    }
+    const int side = (int)(t & 1);
+    const long tr = t >> 1;
+    int gc[3], sc[3];
+    gc[b1] = sc[b1] = (int)(tr % G.n[b1]);
+    gc[b2] = sc[b2] = (int)(tr / G.n[b1]);
+    gc[a] = side == 0 ? -1 : G.n[a];
+    double v;
+    if (G.bc[a][side] == GMUNU_MG_PERIODIC) {
+      sc[a] = side == 0 ? G.n[a] - 1 : 0;
+      v = u[mg_off(G, sc[0], sc[1], sc[2])];
+    } else {
+      sc[a] = side == 0 ? 0 : G.n[a] - 1;
+      const double ui = u[mg_off(G, sc[0], sc[1], sc[2])];
+      v = (G.vodd[a][side] >> q) & 1 ? -ui : ui;
+    }
+    u[mg_off(G, gc[0], gc[1], gc[2])] = v;
+    return;
+  }
+}
+
 template <int NC>
 __global__ __launch_bounds__(NT) void k_mg_ghosts(const MgGeo G, double *u) {
+  const long t = (long)blockIdx.x * NT + threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < NC; q++) mg_ghost_one(G, u + q * G.nt, (long)blockIdx.x * NT + threadIdx.x);
+  for (int q = 0; q < NC; q++) {
+    if (NC == 1)
+      mg_ghost_one(G, u, t);
+    else
+      mgv_ghost_one(G, u + q * G.nt, q, t);
+  }
 }
 
 // One colour of red-black Newton-Gauss-Seidel: thread t -> the t-th cell of
@@ -314,7 +355,7 @@ __global__ __launch_bounds__(NT) void k_mg_norm(const MgGeo G, const double *__r
     int i, j, k;
     mg_cell(G, t, i, j, k);
     const long o = mg_off(G, i, j, k);
-    m = fmax(m, fabs(f[o] - mg_L<false>(G, u, a ? a[o] : 0.0, a2 ? a2[o] : 0.0, i, j, k, o, nullptr)));
+    m = mg_absmax(m, f[o] - mg_L<false>(G, u, a ? a[o] : 0.0, a2 ? a2[o] : 0.0, i, j, k, o, nullptr));
   }
   m = block_max(m);
   if (threadIdx.x == 0) part[blockIdx.x] = m;
@@ -428,6 +469,8 @@ __global__ __launch_bounds__(NT) void k_mg_correct(const MgGeo C, const MgGeo F,
         const int kind = C.bc[a][up ? 1 : 0];
         if (kind == GMUNU_MG_PERIODIC)
           e = mg_corr(C, uc, uoc, up ? oc - (long)(n - 1) * S[a] : oc + (long)(n - 1) * S[a]);
+        else if (NC == 3)  // vector components: their parity across the face
+          e = (C.vodd[a][up ? 1 : 0] >> q) & 1 ? -e0 : e0;
         else
           e = kind == GMUNU_MG_DIRICHLET ? -e0
             : kind == GMUNU_MG_NEUMANN ? e0
@@ -505,23 +548,24 @@ __global__ __launch_bounds__(NT) void k_mg_subgrad(const MgGeo G, const double *
 
 struct VStep {
   int dm[3], dp[3];  // offsets of the minus / plus neighbour along each axis
-  unsigned neg;      // bit a: the minus step negates; bit 3 + a: the plus step
+  unsigned neg;      // bit 6 q + a: the minus step negates component q; 6 q + 3 + a: the plus step
 };
 
 __device__ __forceinline__ void mgv_axis(const MgGeo &G, int c, int a, int S, bool up, int &d, unsigned &neg) {
   const int n = G.n[a];
-  const int bit = up ? 3 + a : a;
   if (up ? c < n - 1 : c > 0) {
     d = up ? S : -S;
     return;
   }
-  const int kind = G.bc[a][up ? 1 : 0];
-  if (kind == GMUNU_MG_PERIODIC) {
+  if (G.bc[a][up ? 1 : 0] == GMUNU_MG_PERIODIC) {
     d = up ? -(n - 1) * S : (n - 1) * S;
     return;
   }
   d = 0;
-  if (kind == GMUNU_MG_DIRICHLET) neg |= 1u << bit;
+  const unsigned odd = G.vodd[a][up ? 1 : 0];
+#pragma unroll
+  for (int q = 0; q < 3; q++)
+    if ((odd >> q) & 1) neg |= 1u << (6 * q + (up ? 3 : 0) + a);
 }
 
 __device__ __forceinline__ VStep mgv_steps(const MgGeo &G, int i, int j, int k) {
@@ -541,11 +585,19 @@ __device__ __forceinline__ VStep mgv_steps(const MgGeo &G, int i, int j, int k) 
 
 __device__ __forceinline__ double mgv_sgn(unsigned neg, int bits, double v) { return (neg >> bits) & 1 ? -v : v; }
 
-// L(X) at interior cell offset o, all three components.  The level's
-// constants 1/h_a^2, 1/(4 h_a h_b) and the inverse diagonals are
-// precomputed (MgGeo.vih2, vmix, vidg).
-__device__ __forceinline__ void mgv_L(const MgGeo &G, const double *__restrict__ u, const VStep &s, long o,
-                                      double L[3]) {
+// Component b at the diagonal neighbour (sq along axis qa, sb along axis
+// ab; +1 or -1): the sign is the product of its two steps' signs.
+__device__ __forceinline__ double mgv_corner(const double *__restrict__ ub, const VStep &s, long o, int b, int qa,
+                                             int sq, int ab, int sb) {
+  const unsigned n1 = s.neg >> (6 * b + (sq > 0 ? 3 : 0) + qa), n2 = s.neg >> (6 * b + (sb > 0 ? 3 : 0) + ab);
+  return mgv_sgn(n1 ^ n2, 0, ub[o + (sq > 0 ? s.dp[qa] : s.dm[qa]) + (sb > 0 ? s.dp[ab] : s.dm[ab])]);
+}
+
+// L(X) at interior cell (i, j) (offset o) on a Cartesian level, all three
+// components, and the inverse diagonals (level constants: 1/h_a^2,
+// 1/(4 h_a h_b) and the inverse diagonals are precomputed in MgGeo).
+__device__ __forceinline__ void mgv_L_cart(const MgGeo &G, const double *__restrict__ u, const VStep &s, long o,
+                                           double L[3], double idg[3]) {
   const long nt = G.nt;
 #pragma unroll
   for (int q = 0; q < 3; q++) {
@@ -555,7 +607,8 @@ __device__ __forceinline__ void mgv_L(const MgGeo &G, const double *__restrict__
 #pragma unroll
     for (int a = 0; a < 3; a++) {
       if (a >= G.ndim) continue;
-      const double up = mgv_sgn(s.neg, 3 + a, uq[o + s.dp[a]]), um = mgv_sgn(s.neg, a, uq[o + s.dm[a]]);
+      const double up = mgv_sgn(s.neg, 6 * q + 3 + a, uq[o + s.dp[a]]);
+      const double um = mgv_sgn(s.neg, 6 * q + a, uq[o + s.dm[a]]);
       const double d2 = (up - 2.0 * u0 + um) * G.vih2[a];
       lap += d2;
       if (a == q) self = d2;
@@ -565,16 +618,99 @@ __device__ __forceinline__ void mgv_L(const MgGeo &G, const double *__restrict__
     for (int b = 0; b < 3; b++) {
       if (q >= G.ndim || b == q || b >= G.ndim) continue;
       const double *ub = u + b * nt;
-      // sign of a diagonal neighbour: product of its two steps' signs
-      const unsigned pq = s.neg >> (3 + q), mq = s.neg >> q, pb = s.neg >> (3 + b), mb = s.neg >> b;
-      const double pp = mgv_sgn(pq ^ pb, 0, ub[o + s.dp[q] + s.dp[b]]);
-      const double pm = mgv_sgn(pq ^ mb, 0, ub[o + s.dp[q] + s.dm[b]]);
-      const double mp = mgv_sgn(mq ^ pb, 0, ub[o + s.dm[q] + s.dp[b]]);
-      const double mm = mgv_sgn(mq ^ mb, 0, ub[o + s.dm[q] + s.dm[b]]);
+      const double pp = mgv_corner(ub, s, o, b, q, 1, b, 1), pm = mgv_corner(ub, s, o, b, q, 1, b, -1);
+      const double mp = mgv_corner(ub, s, o, b, q, -1, b, 1), mm = mgv_corner(ub, s, o, b, q, -1, b, -1);
       gd += (pp - pm - mp + mm) * G.vmix[q + b - 1];
     }
     L[q] = lap + gd * (1.0 / 3.0);
+    idg[q] = G.vidg[q];
   }
+}
+
+// The same on an axisymmetric cylindrical (R, z) or spherical (r, theta)
+// level in orthonormal components: the flux-form Laplacian of each
+// component (the scalar operator's tables), the connection terms of the
+// vector Laplacian and of grad div, mixed differences by the four-point
+// formula with signed corner coordinates; diagonals per cell.
+__device__ __forceinline__ void mgv_L_curv(const MgGeo &G, const double *__restrict__ u, const VStep &s, long o,
+                                           int i, int j, double L[3], double idg[3]) {
+  const long nt = G.nt;
+  const bool two = G.ndim > 1;
+  const int I = i + G.g[0], J = j + G.g[1];
+  const double h0 = G.h[0], h1 = G.h[1];
+  const double r = G.x0[0] + (i + 0.5) * h0, ir2 = 1.0 / (r * r);
+  const double wm0 = G.a0m[I], wp0 = G.a0p[I];
+  const double wm1 = two ? G.g1[I] * G.a1m[J] : 0.0, wp1 = two ? G.g1[I] * G.a1p[J] : 0.0;
+  const double i4h = two ? 1.0 / (4.0 * h0 * h1) : 0.0;
+  double l0[3], l1[3], u0[3];
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    const double *uq = u + q * nt;
+    u0[q] = uq[o];
+    l0[q] = wp0 * (mgv_sgn(s.neg, 6 * q + 3, uq[o + s.dp[0]]) - u0[q]) -
+            wm0 * (u0[q] - mgv_sgn(s.neg, 6 * q, uq[o + s.dm[0]]));
+    l1[q] = two ? wp1 * (mgv_sgn(s.neg, 6 * q + 4, uq[o + s.dp[1]]) - u0[q]) -
+                      wm1 * (u0[q] - mgv_sgn(s.neg, 6 * q + 1, uq[o + s.dm[1]]))
+                : 0.0;
+  }
+  const double dl0 = -(wm0 + wp0), dl1 = -(wm1 + wp1), dlap = dl0 + dl1;
+  const double *u0p = u, *u1p = u + nt;
+  if (G.coord == GMUNU_CYL) {
+    double mixz = 0.0, mixR = 0.0;
+    if (two) {
+#pragma unroll
+      for (int di = -1; di <= 1; di += 2)
+#pragma unroll
+        for (int dj = -1; dj <= 1; dj += 2) {
+          mixz += di * dj * mgv_corner(u1p, s, o, 1, 0, di, 1, dj);
+          mixR += di * dj * (r + di * h0) * mgv_corner(u0p, s, o, 0, 0, di, 1, dj);
+        }
+      mixz *= i4h;
+      mixR *= i4h / r;
+    }
+    L[0] = l0[0] + l1[0] - u0[0] * ir2 + (l0[0] - u0[0] * ir2 + mixz) * (1.0 / 3.0);
+    idg[0] = 1.0 / (dlap - ir2 + (dl0 - ir2) * (1.0 / 3.0));
+    L[1] = l0[1] + l1[1] + (mixR + l1[1]) * (1.0 / 3.0);
+    idg[1] = 1.0 / (dlap + dl1 * (1.0 / 3.0));
+    L[2] = l0[2] + l1[2] - u0[2] * ir2;
+    idg[2] = 1.0 / (dlap - ir2);
+  } else {
+    const double sn = G.sg1[J], is2 = 1.0 / (sn * sn);
+    double dth = 0.0, dr = 0.0, mixt = 0.0, mixr = 0.0;
+    if (two) {
+      dth = (G.sg1[J + 1] * mgv_sgn(s.neg, 6 + 4, u1p[o + s.dp[1]]) -
+             G.sg1[J - 1] * mgv_sgn(s.neg, 6 + 1, u1p[o + s.dm[1]])) /
+            (2.0 * h1);
+      dr = (mgv_sgn(s.neg, 4, u0p[o + s.dp[1]]) - mgv_sgn(s.neg, 1, u0p[o + s.dm[1]])) / (2.0 * h1);
+#pragma unroll
+      for (int di = -1; di <= 1; di += 2)
+#pragma unroll
+        for (int dj = -1; dj <= 1; dj += 2) {
+          const double rc = r + di * h0;
+          mixt += di * dj * G.sg1[J + dj] * mgv_corner(u1p, s, o, 1, 0, di, 1, dj);
+          mixr += di * dj * (rc * rc) * mgv_corner(u0p, s, o, 0, 0, di, 1, dj);
+        }
+      // (1/sin) d_r d_th (sin A_th / r) without dividing by a corner radius
+      mixt = (mixt * i4h / r - dth * ir2) / sn;
+      mixr *= i4h * ir2 / r;
+    }
+    L[0] = l0[0] + l1[0] - 2.0 * u0[0] * ir2 - 2.0 * ir2 / sn * dth +
+           (l0[0] - 2.0 * u0[0] * ir2 + mixt) * (1.0 / 3.0);
+    idg[0] = 1.0 / (dlap - 2.0 * ir2 + (dl0 - 2.0 * ir2) * (1.0 / 3.0));
+    L[1] = l0[1] + l1[1] - u0[1] * ir2 * is2 + 2.0 * ir2 * dr + (mixr + l1[1] - u0[1] * ir2 * is2) * (1.0 / 3.0);
+    idg[1] = 1.0 / (dlap - ir2 * is2 + (dl1 - ir2 * is2) * (1.0 / 3.0));
+    L[2] = l0[2] + l1[2] - u0[2] * ir2 * is2;
+    idg[2] = 1.0 / (dlap - ir2 * is2);
+  }
+}
+
+__device__ __forceinline__ void mgv_L(const MgGeo &G, const double *__restrict__ u, long o, int i, int j, int k,
+                                      double L[3], double idg[3]) {
+  const VStep s = mgv_steps(G, i, j, k);
+  if (G.coord == GMUNU_CART)
+    mgv_L_cart(G, u, s, o, L, idg);
+  else
+    mgv_L_curv(G, u, s, o, i, j, L, idg);
 }
 
 // Cells of colour `colour` (bit a: parity along axis a) on a level.
@@ -598,10 +734,10 @@ __device__ __forceinline__ void mgv_smooth_one(const MgGeo &G, double *u, const 
   const int j = G.ndim > 1 ? 2 * (int)(r - kk * hy) + cj : 0;
   const int k = G.ndim > 2 ? 2 * (int)kk + ck : 0;
   const long o = mg_off(G, i, j, k);
-  double L[3];
-  mgv_L(G, u, mgv_steps(G, i, j, k), o, L);
+  double L[3], idg[3];
+  mgv_L(G, u, o, i, j, k, L, idg);
 #pragma unroll
-  for (int q = 0; q < 3; q++) u[q * G.nt + o] -= (L[q] - f[q * G.nt + o]) * G.vidg[q];
+  for (int q = 0; q < 3; q++) u[q * G.nt + o] -= (L[q] - f[q * G.nt + o]) * idg[q];
 }
 
 __global__ __launch_bounds__(NT) void k_mgv_smooth(const MgGeo G, double *u, const double *__restrict__ f,
@@ -631,10 +767,10 @@ __global__ __launch_bounds__(NT) void k_mgv_smooth2(const MgGeo G, double *u, co
       const int j = G.ndim > 1 ? 2 * (int)(row - kk * hy) + cj : 0;
       const int k = G.ndim > 2 ? 2 * (int)kk + ck : 0;
       const long o = mg_off(G, i, j, k);
-      double L[3];
-      mgv_L(G, u, mgv_steps(G, i, j, k), o, L);
+      double L[3], idg[3];
+      mgv_L(G, u, o, i, j, k, L, idg);
 #pragma unroll
-      for (int q = 0; q < 3; q++) u[q * G.nt + o] -= (L[q] - f[q * G.nt + o]) * G.vidg[q];
+      for (int q = 0; q < 3; q++) u[q * G.nt + o] -= (L[q] - f[q * G.nt + o]) * idg[q];
     }
     __syncthreads();
   }
@@ -675,8 +811,8 @@ __global__ __launch_bounds__(NT) void k_mgv_apply(const MgGeo G, const double *_
   int i, j, k;
   mg_cell(G, t, i, j, k);
   const long o = mg_off(G, i, j, k);
-  double L[3];
-  mgv_L(G, u, mgv_steps(G, i, j, k), o, L);
+  double L[3], idg[3];
+  mgv_L(G, u, o, i, j, k, L, idg);
 #pragma unroll
   for (int q = 0; q < 3; q++) out[q * G.nt + o] = L[q];
 }
@@ -688,18 +824,17 @@ __global__ __launch_bounds__(NT) void k_mgv_norm(const MgGeo G, const double *__
     int i, j, k;
     mg_cell(G, t, i, j, k);
     const long o = mg_off(G, i, j, k);
-    double L[3];
-    mgv_L(G, u, mgv_steps(G, i, j, k), o, L);
+    double L[3], idg[3];
+    mgv_L(G, u, o, i, j, k, L, idg);
 #pragma unroll
-    for (int q = 0; q < 3; q++) m = fmax(m, fabs(f[q * G.nt + o] - L[q]));
+    for (int q = 0; q < 3; q++) m = mg_absmax(m, f[q * G.nt + o] - L[q]);
   }
   m = block_max(m);
   if (threadIdx.x == 0) part[blockIdx.x] = m;
 }
 
 // Coarse problem of a fine level for the vector equation: the children's
-// residuals and values averaged into the coarse r and u (Cartesian cells
-// have equal volumes).
+// residuals and values, volume-weighted means into the coarse r and u.
 __global__ __launch_bounds__(NT) void k_mgv_restrict_res(const MgGeo F, const MgGeo C, const double *__restrict__ u,
                                                          const double *__restrict__ f, double *__restrict__ uc,
                                                          double *__restrict__ rc) {
@@ -707,26 +842,28 @@ __global__ __launch_bounds__(NT) void k_mgv_restrict_res(const MgGeo F, const Mg
   if (t >= mg_cells(C)) return;
   int i, j, k;
   mg_cell(C, t, i, j, k);
-  double su[3] = {0.0, 0.0, 0.0}, sr[3] = {0.0, 0.0, 0.0};
+  double su[3] = {0.0, 0.0, 0.0}, sr[3] = {0.0, 0.0, 0.0}, w = 0.0;
   const int nch = 1 << F.ndim;
   for (int ch = 0; ch < nch; ch++) {
     const int fi = 2 * i + (ch & 1);
     const int fj = F.ndim > 1 ? 2 * j + ((ch >> 1) & 1) : j;
     const int fk = F.ndim > 2 ? 2 * k + ((ch >> 2) & 1) : k;
     const long o = mg_off(F, fi, fj, fk);
-    double L[3];
-    mgv_L(F, u, mgv_steps(F, fi, fj, fk), o, L);
+    const double v = F.vol0[fi + F.g[0]] * F.vol1[fj + F.g[1]];
+    double L[3], idg[3];
+    mgv_L(F, u, o, fi, fj, fk, L, idg);
 #pragma unroll
     for (int q = 0; q < 3; q++) {
-      su[q] += u[q * F.nt + o];
-      sr[q] += f[q * F.nt + o] - L[q];
+      su[q] += v * u[q * F.nt + o];
+      sr[q] += v * (f[q * F.nt + o] - L[q]);
     }
+    w += v;
   }
   const long oc = mg_off(C, i, j, k);
 #pragma unroll
   for (int q = 0; q < 3; q++) {
-    uc[q * C.nt + oc] = su[q] / nch;
-    rc[q * C.nt + oc] = sr[q] / nch;
+    uc[q * C.nt + oc] = su[q] / w;
+    rc[q * C.nt + oc] = sr[q] / w;
   }
 }
 
@@ -739,8 +876,8 @@ __global__ __launch_bounds__(NT) void k_mgv_fas_rhs(const MgGeo C, const double 
   int i, j, k;
   mg_cell(C, t, i, j, k);
   const long o = mg_off(C, i, j, k);
-  double L[3];
-  mgv_L(C, u, mgv_steps(C, i, j, k), o, L);
+  double L[3], idg[3];
+  mgv_L(C, u, o, i, j, k, L, idg);
 #pragma unroll
   for (int q = 0; q < 3; q++) {
     f[q * C.nt + o] = L[q] + r[q * C.nt + o];
@@ -748,9 +885,10 @@ __global__ __launch_bounds__(NT) void k_mgv_fas_rhs(const MgGeo C, const double 
   }
 }
 
-// A~^ij = d_i X^j + d_j X^i - (2/3) delta^ij d_k X^k (centred, boundary rule
-// across the boundary) as six components (xx yy zz xy xz yz), and
-// A~_ij A~^ij.
+// A~^ij = grad^i X^j + grad^j X^i - (2/3) delta^ij div X in orthonormal
+// components (centred, boundary rule across the boundary; the connection
+// terms of cylindrical and spherical coordinates, d/dphi = 0) as six
+// components (xx yy zz xy xz yz in the order of the axes), and A~_ij A~^ij.
 __global__ __launch_bounds__(NT) void k_mgv_aij(const MgGeo G, const double *__restrict__ X, double *__restrict__ A6,
                                                 double *__restrict__ A2) {
   const long t = (long)blockIdx.x * NT + threadIdx.x;
@@ -759,16 +897,34 @@ __global__ __launch_bounds__(NT) void k_mgv_aij(const MgGeo G, const double *__r
   mg_cell(G, t, i, j, k);
   const long o = mg_off(G, i, j, k);
   const VStep s = mgv_steps(G, i, j, k);
-  double g[3][3];  // g[a][b] = d_a X^b
+  double g[3][3];  // g[a][b] = grad_a X_b in orthonormal components
 #pragma unroll
   for (int a = 0; a < 3; a++)
 #pragma unroll
     for (int b = 0; b < 3; b++) {
       const double *xb = X + b * G.nt;
-      g[a][b] = a < G.ndim ? (mgv_sgn(s.neg, 3 + a, xb[o + s.dp[a]]) - mgv_sgn(s.neg, a, xb[o + s.dm[a]])) /
+      g[a][b] = a < G.ndim ? (mgv_sgn(s.neg, 6 * b + 3 + a, xb[o + s.dp[a]]) -
+                              mgv_sgn(s.neg, 6 * b + a, xb[o + s.dm[a]])) /
                                  (2.0 * G.h[a])
                            : 0.0;
     }
+  // connection terms (d/dphi = 0)
+  const double x0v = X[o], x1v = X[G.nt + o], x2v = X[2 * G.nt + o];
+  if (G.coord == GMUNU_CYL) {
+    const double R = G.x0[0] + (i + 0.5) * G.h[0];
+    g[2][0] = -x2v / R;
+    g[2][1] = 0.0;
+    g[2][2] = x0v / R;
+  } else if (G.coord == GMUNU_SPH) {
+    const double r = G.x0[0] + (i + 0.5) * G.h[0], th = G.x0[1] + (j + 0.5) * G.h[1];
+    const double ct = cos(th) / sin(th);
+    g[1][0] = (g[1][0] - x1v) / r;
+    g[1][1] = (g[1][1] + x0v) / r;
+    g[1][2] = g[1][2] / r;
+    g[2][0] = -x2v / r;
+    g[2][1] = -ct * x2v / r;
+    g[2][2] = (x0v + ct * x1v) / r;
+  }
   const double dv = g[0][0] + g[1][1] + g[2][2];
   double A[3][3], a2 = 0.0;
 #pragma unroll
@@ -787,8 +943,8 @@ __global__ __launch_bounds__(NT) void k_mgv_aij(const MgGeo G, const double *__r
   A2[o] = a2;
 }
 
-// Source of the shift equation: 16 pi w S_i + 2 A~^ij d_j w, w = alpha
-// psi^-6 with its ghost entries as stored (centred gradient).
+// Source of the shift equation: 16 pi w S_i + 2 A~^ij grad_j w, w = alpha
+// psi^-6 with its ghost entries as stored (centred orthonormal gradient).
 __global__ __launch_bounds__(NT) void k_mgv_beta_rhs(const MgGeo G, const double *__restrict__ w,
                                                      const double *__restrict__ S, const double *__restrict__ A6,
                                                      double *__restrict__ out) {
@@ -801,6 +957,7 @@ __global__ __launch_bounds__(NT) void k_mgv_beta_rhs(const MgGeo G, const double
   double gw[3];
 #pragma unroll
   for (int a = 0; a < 3; a++) gw[a] = a < G.ndim ? (w[o + St[a]] - w[o - St[a]]) / (2.0 * G.h[a]) : 0.0;
+  if (G.coord == GMUNU_SPH) gw[1] /= G.x0[0] + (i + 0.5) * G.h[0];  // orthonormal theta component
   const long nt = G.nt;
   const double axx = A6[o], ayy = A6[nt + o], azz = A6[2 * nt + o];
   const double axy = A6[3 * nt + o], axz = A6[4 * nt + o], ayz = A6[5 * nt + o];
@@ -896,9 +1053,18 @@ __global__ __launch_bounds__(NT) void k_br_cfc_coef(const MgGeo G, const Hydro H
   u[m] = met[H.nv + o] * psi - 1.0;
 }
 
-// Momentum source of the vector equations: S[c] = q_{S_c} (= psi^6 S_c, the
-// rescaled S~_c of section 2.6; Cartesian, so f^ij S~_j = S~_i) and
-// fX = 8 pi S on the interior.
+// Scale factors of the reference metric at signed cell-centre coordinates
+// (x0, x1): orthonormal component = h_c times the contravariant one, and
+// the covariant one divided by h_c.
+__device__ __forceinline__ double mg_hscale(int coord, int c, double x0, double x1) {
+  if (coord == GMUNU_CYL) return c == 2 ? x0 : 1.0;
+  if (coord == GMUNU_SPH) return c == 0 ? 1.0 : c == 1 ? x0 : x0 * sin(x1);
+  return 1.0;
+}
+
+// Momentum source of the vector equations in orthonormal components:
+// S[c] = q_{S_c} / h_c (q_S = psi^6 S_c covariant, the rescaled S~_c of
+// section 2.6) and fX = 8 pi S, on the interior.
 __global__ __launch_bounds__(NT) void k_bx_src(const MgGeo G, const Hydro H, const double *__restrict__ q,
                                                double *__restrict__ S, double *__restrict__ fX) {
   const long t = (long)blockIdx.x * NT + threadIdx.x;
@@ -906,9 +1072,10 @@ __global__ __launch_bounds__(NT) void k_bx_src(const MgGeo G, const Hydro H, con
   int i, j, k;
   mg_cell(G, t, i, j, k);
   const long o = hy_off(H, i, j, k), m = mg_off(G, i, j, k);
+  const double x0 = G.x0[0] + (i + 0.5) * G.h[0], x1 = G.x0[1] + (j + 0.5) * G.h[1];
 #pragma unroll
   for (int c = 0; c < 3; c++) {
-    const double v = q[(1 + c) * H.nv + o];
+    const double v = q[(1 + c) * H.nv + o] / mg_hscale(G.coord, c, x0, x1);
     S[c * G.nt + m] = v;
     fX[c * G.nt + m] = 8.0 * M_PI * v;
   }
@@ -926,7 +1093,8 @@ __global__ __launch_bounds__(NT) void k_bx_w(const MgGeo G, const Hydro H, const
   w[t] = met[H.nv + o] / (psi2 * psi2 * psi2);
 }
 
-// The metric's shift on the interior as the initial guess of its solve.
+// The metric's shift on the interior (orthonormal components) as the
+// initial guess of its solve.
 __global__ __launch_bounds__(NT) void k_bx_beta_in(const MgGeo G, const Hydro H, const double *__restrict__ met,
                                                    double *__restrict__ beta) {
   const long t = (long)blockIdx.x * NT + threadIdx.x;
@@ -934,20 +1102,24 @@ __global__ __launch_bounds__(NT) void k_bx_beta_in(const MgGeo G, const Hydro H,
   int i, j, k;
   mg_cell(G, t, i, j, k);
   const long o = hy_off(H, i, j, k), m = mg_off(G, i, j, k);
+  const double x0 = G.x0[0] + (i + 0.5) * G.h[0], x1 = G.x0[1] + (j + 0.5) * G.h[1];
 #pragma unroll
-  for (int c = 0; c < 3; c++) beta[c * G.nt + m] = met[(2 + c) * H.nv + o];
+  for (int c = 0; c < 3; c++) beta[c * G.nt + m] = met[(2 + c) * H.nv + o] * mg_hscale(G.coord, c, x0, x1);
 }
 
 // Metric of every GRMHD cell (ng ghost layers included) from the solution u
 // of level G, ghost layers extended by the multigrid boundary rule applied
 // per layer (mirror about the face times -1, +1 or r_in / r_ghost; periodic
 // wrap): which 0 writes psi = 1 + u, which 1 alpha = (1 + u) / psi, which
-// 2..4 the shift component beta^(which - 2) = u.
+// 2..4 the shift component c = which - 2 from its orthonormal value u
+// (mirrored with the component's parity, then divided by h_c at the
+// cell's signed coordinates).
 __global__ __launch_bounds__(NT) void k_br_store(const MgGeo G, const Hydro H, const double *__restrict__ u,
                                                  double xmin0, int which, double *__restrict__ met) {
   const long t = (long)blockIdx.x * NT + threadIdx.x;
   if (t >= H.nv) return;
   int c[3] = {(int)(t % H.T0) - H.ng[0], (int)((t / H.T0) % (H.T1 / H.T0)) - H.ng[1], (int)(t / H.T1) - H.ng[2]};
+  const double xc0 = G.x0[0] + (c[0] + 0.5) * G.h[0], xc1 = G.x0[1] + (c[1] + 0.5) * G.h[1];
   double fac = 1.0;
   // axes from the last to the first: an edge or corner ghost takes the
   // factor of each axis at the other coordinates not yet mapped inside
@@ -963,8 +1135,12 @@ __global__ __launch_bounds__(NT) void k_br_store(const MgGeo G, const Hydro H, c
       continue;
     }
     const int in = side == 0 ? -1 - c[a] : 2 * n - 1 - c[a];
-    if (kind == GMUNU_MG_DIRICHLET) fac = -fac;
-    if (kind == GMUNU_MG_ROBIN) {
+    if (which >= 2) {
+      if ((G.vodd[a][side] >> (which - 2)) & 1) fac = -fac;
+    } else if (kind == GMUNU_MG_DIRICHLET) {
+      fac = -fac;
+    }
+    if (which < 2 && kind == GMUNU_MG_ROBIN) {
       if (G.coord == GMUNU_SPH) {
         fac *= (xmin0 + (in + 0.5) * G.h[0]) / (xmin0 + (c[a] + 0.5) * G.h[0]);
       } else {
@@ -989,7 +1165,7 @@ __global__ __launch_bounds__(NT) void k_br_store(const MgGeo G, const Hydro H, c
   else if (which == 1)
     met[H.nv + t] = (1.0 + v) / met[t];
   else
-    met[which * H.nv + t] = v;
+    met[which * H.nv + t] = v / mg_hscale(G.coord, which - 2, xc0, xc1);
 }
 
 }  // namespace
@@ -1141,6 +1317,21 @@ void level_tables(const gmunu_mg_desc &d, int s, std::vector<double> &tab, size_
   G.rob_lo = xin_lo / xg_lo;
   G.rob_hi = xin_hi / xg_hi;
   for (int a = 0; a < 3; a++) G.x0[a] = d.xmin[a];
+  // per-component parity across each non-periodic face for the vector
+  // equations: Dirichlet all odd; Neumann a symmetry face (normal component
+  // odd), plus phi at the cylindrical and polar axes and every component at
+  // the spherical centre (equatorially symmetric grids)
+  for (int a = 0; a < 3; a++)
+    for (int sd = 0; sd < 2; sd++) {
+      const double fpos = sd == 0 ? d.xmin[a] : d.xmin[a] + d.n[a] * d.dx[a];
+      unsigned odd = d.bc[a][sd] == GMUNU_MG_DIRICHLET ? 7u : 1u << a;
+      if (d.bc[a][sd] == GMUNU_MG_NEUMANN) {
+        if (d.coord == GMUNU_CYL && a == 0 && std::fabs(fpos) < 1e-12) odd |= 4u;
+        if (d.coord == GMUNU_SPH && a == 0 && std::fabs(fpos) < 1e-12) odd = 7u;
+        if (d.coord == GMUNU_SPH && a == 1 && (std::fabs(fpos) < 1e-12 || std::fabs(fpos - M_PI) < 1e-12)) odd |= 4u;
+      }
+      G.vodd[a][sd] = odd;
+    }
   G.power = d.power;
   G.power2 = d.power2;
   G.offset = d.offset;
@@ -1308,13 +1499,18 @@ bool a2_ok(const gmunu_mg *m, const double *a2) { return !a2 || (m->d.power2 != 
 
 bool ok_ptr(const void *p) { return p && aligned8(p); }
 
-// The vector equations: Cartesian grids whose faces are Dirichlet, Neumann
-// or periodic.
+// The vector equations: Cartesian grids, or axisymmetric cylindrical and
+// spherical ones (at most two active axes), faces Dirichlet, Neumann or
+// periodic; a spherical grid reaching r = 0 must end at theta = pi/2.
 bool vector_ok(const gmunu_mg *m) {
-  if (m->d.coord != GMUNU_CART) return false;
+  const gmunu_mg_desc &d = m->d;
   for (int a = 0; a < 3; a++)
     for (int sd = 0; sd < 2; sd++)
-      if (m->d.bc[a][sd] == GMUNU_MG_ROBIN) return false;
+      if (d.bc[a][sd] == GMUNU_MG_ROBIN) return false;
+  if (d.coord != GMUNU_CART && d.ndim > 2) return false;
+  if (d.coord == GMUNU_SPH && std::fabs(d.xmin[0]) < 1e-12 &&
+      (d.ndim < 2 || std::fabs(d.xmin[1] + d.n[1] * d.dx[1] - M_PI / 2) > 1e-12))
+    return false;
   return true;
 }
 
