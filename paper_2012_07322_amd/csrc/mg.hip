@@ -2163,7 +2163,8 @@ int gmunu_mg_psi_residual(gmunu_mg *mvec, gmunu_mg *mpsi, const gmunu_grid_desc 
     A2 = A2v;
   }
   if (hipMemsetAsync(f, 0, (size_t)G.nt * sizeof(double), st) != hipSuccess) return GMUNU_EHIP;
-  hipLaunchKernelGGL(k_br_cfc_coef, dim3(nblocks(cells(G))), dim3(NT), 0, st, G, H, q, metric, metric, 0, A2, a, a2,
+  // which 0 (the conformal factor) reads no primitives
+  hipLaunchKernelGGL(k_br_cfc_coef, dim3(nblocks(cells(G))), dim3(NT), 0, st, G, H, q, nullptr, metric, 0, A2, a, a2,
                      u);
   return gmunu_mg_residual_norm(mpsi, u, f, a, A2 ? a2 : nullptr, norm_out, stream);
 }
