@@ -64,6 +64,8 @@ def lib():
         L.om_apply.argtypes = [P, P, P, P, P]
         L.om_fill_ghosts.argtypes = [P, I, P]
         L.om_smooth.argtypes = [P, P, P, P, P, I]
+        L.om_line_smooth.argtypes = [P, P, P, P, P, I]
+        L.om_vline_smooth.argtypes = [P, P, P, I]
         L.om_restrict.argtypes = [P, I, P, P]
         L.om_prolong.argtypes = [P, I, P, P]
         L.om_solve.argtypes = [P, P, P, P, P, D, I, I, P]
@@ -168,6 +170,14 @@ def smooth(p, u, f, a=None, sweeps=1, a2=None):
     return u
 
 
+def line_smooth(p, u, f, a=None, sweeps=1, a2=None):
+    """Alternating zebra line relaxation sweeps on the finest level (the
+    alternative smoother for anisotropic cells); ghosts refreshed."""
+    d = make_desc(p)
+    lib().om_line_smooth(ctypes.byref(d), _p(_c(u)), _p(_c(f)), _o(a), _o(a2), sweeps)
+    return u
+
+
 def restrict(p, level, fine):
     d = make_desc(p)
     out = np.zeros(shape(p, level - 1))
@@ -228,6 +238,14 @@ def vfill_ghosts(p, X):
 def vsmooth(p, X, f, sweeps=1):
     d = _cart(make_desc(p))
     lib().om_vsmooth(ctypes.byref(d), _p(_c(X)), _p(_c(f)), sweeps)
+    return X
+
+
+def vline_smooth(p, X, f, sweeps=1):
+    """Line relaxation sweeps of the vector equations (components of a line
+    one after the other)."""
+    d = _cart(make_desc(p))
+    lib().om_vline_smooth(ctypes.byref(d), _p(_c(X)), _p(_c(f)), sweeps)
     return X
 
 

@@ -24,7 +24,12 @@
  *     (u_c + u_x + u_y + u_z) / 4, the weights that keep the scheme's
  *     property of reproducing linear functions;
  *   - cycles: full-approximation-scheme V-cycles and an FAS full-multigrid
- *     cycle that starts from the current solution.
+ *     cycle that starts from the current solution;
+ *   - beside the paper's point smoother, alternating zebra line relaxation
+ *     (line_smooth, vline_smooth), the standard remedy for the anisotropic
+ *     cells on which the paper notes point smoothers converge slowly; it
+ *     is defined by its steps there and changes the iteration, not the
+ *     discrete solution.
  *
  * Readings where the paper is silent or garbled:
  *   - the cylindrical and spherical second differences are printed as
@@ -179,6 +184,27 @@ static double apply_cell(const om_desc *d, const lvl *L, const double *u, const 
   return lap - nonlin(d, av, a2v, u[c]);
 }
 
+/* Ratio ghost / boundary cell of the non-periodic face (a, side): cell s,
+ * ghost g (s with index -1 or n along a). */
+static double ghost_factor(const om_desc *d, const lvl *L, int a, int side, const int s[3], const int g[3]) {
+  int kind = d->bc[a][side];
+  if (kind == OM_DIRICHLET) return -1.0;
+  if (kind == OM_NEUMANN) return 1.0;
+  if (d->coord != OM_SPH) {
+    /* 1/r falloff between the boundary cell and its ghost, r the distance
+     * of the cell centres from the origin (Cartesian: the active axes;
+     * cylindrical: R and z) */
+    double ri = 0.0, rg = 0.0;
+    for (int b = 0; b < d->ndim && b < (d->coord == OM_CYL ? 2 : 3); b++) {
+      double xi = centre(d, L, b, s[b]), xg = centre(d, L, b, g[b]);
+      ri += xi * xi;
+      rg += xg * xg;
+    }
+    return sqrt(ri) / sqrt(rg);
+  }
+  return centre(d, L, a, s[a]) / centre(d, L, a, g[a]);
+}
+
 /* Ghost values of u on level L from its boundary conditions (face-adjacent
  * ghosts only: the stencils use no edge or corner ghost). */
 static void fill_ghosts(const om_desc *d, const lvl *L, double *u) {
@@ -199,24 +225,7 @@ static void fill_ghosts(const om_desc *d, const lvl *L, double *u) {
           } else {
             s[a] = side == 0 ? 0 : L->n[a] - 1;
             double ui = u[idx(d, L, s[0], s[1], s[2])];
-            if (kind == OM_DIRICHLET) {
-              v = -ui;
-            } else if (kind == OM_NEUMANN) {
-              v = ui;
-            } else if (d->coord != OM_SPH) {
-              /* 1/r falloff between the boundary cell and its ghost, r the
-               * distance of the cell centres from the origin (Cartesian:
-               * the active axes; cylindrical: R and z) */
-              double ri = 0.0, rg = 0.0;
-              for (int b = 0; b < d->ndim && b < (d->coord == OM_CYL ? 2 : 3); b++) {
-                double xi = centre(d, L, b, s[b]), xg = centre(d, L, b, g[b]);
-                ri += xi * xi;
-                rg += xg * xg;
-              }
-              v = ui * sqrt(ri) / sqrt(rg);
-            } else {
-              v = ui * centre(d, L, a, s[a]) / centre(d, L, a, g[a]);
-            }
+            v = kind == OM_DIRICHLET ? -ui : kind == OM_NEUMANN ? ui : ui * ghost_factor(d, L, a, side, s, g);
           }
           u[idx(d, L, g[0], g[1], g[2])] = v;
         }
@@ -240,6 +249,106 @@ static void smooth(const om_desc *d, const lvl *L, double *u, const double *f, c
             u[c] -= (Lu - f[c]) / dg;
           }
     }
+  fill_ghosts(d, L, u);
+}
+
+/* Solve the tridiagonal system lo[m] x[m-1] + dg[m] x[m] + up[m] x[m+1] =
+ * rhs[m] (m = 0..n-1; lo[0], up[n-1] unused) by Gaussian elimination
+ * without pivoting (the Thomas algorithm); x overwrites rhs, up is
+ * overwritten. */
+static void thomas(int n, const double *lo, const double *dg, double *up, double *rhs) {
+  double piv = dg[0];
+  up[0] /= piv;
+  rhs[0] /= piv;
+  for (int m = 1; m < n; m++) {
+    piv = dg[m] - lo[m] * up[m - 1];
+    if (m < n - 1) up[m] /= piv;
+    rhs[m] = (rhs[m] - lo[m] * rhs[m - 1]) / piv;
+  }
+  for (int m = n - 2; m >= 0; m--) rhs[m] -= up[m] * rhs[m + 1];
+}
+
+/* Lines of colour col along axis a: the transverse axes b1 < b2, colour
+ * bit 0 the parity of the index along b1, bit 1 along b2 (active axes
+ * only).  Calls back for each line's first cell. */
+static int line_colours(const om_desc *d) { return 1 << (d->ndim - 1); }
+static int on_line_colour(const om_desc *d, int a, int col, const int c[3]) {
+  int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+  int p1 = b1 < d->ndim ? c[b1] & 1 : 0, p2 = b2 < d->ndim ? c[b2] & 1 : 0;
+  return (p1 | (p2 << 1)) == col;
+}
+
+/* Alternating zebra line relaxation (an alternative to the paper's point
+ * smoother for strongly anisotropic cells): per sweep each active
+ * non-periodic axis in turn, per axis the line colours in order, per line
+ * one Newton step of the line's equations with their exact Jacobian with
+ * respect to the line's own cells -- the Laplacian weights toward the two
+ * neighbours along the line, and on the diagonal dL/du plus, for every
+ * face of the cell that is a non-periodic boundary, the weight toward that
+ * face's ghost times ghost_factor (the ghost follows the cell) -- while
+ * every other cell holds its current value.  For a linear L one sweep is
+ * block Gauss-Seidel over the lines.  With every active axis periodic,
+ * red-black point sweeps. */
+static void line_smooth(const om_desc *d, const lvl *L, double *u, const double *f, const double *ac,
+                        const double *a2c, int sweeps) {
+  int any = 0;
+  for (int a = 0; a < d->ndim; a++) any |= d->bc[a][0] != OM_PERIODIC;
+  if (!any) {
+    smooth(d, L, u, f, ac, a2c, sweeps);
+    return;
+  }
+  int nmax = L->n[0] > L->n[1] ? L->n[0] : L->n[1];
+  nmax = nmax > L->n[2] ? nmax : L->n[2];
+  double *lo = malloc(sizeof(double) * nmax), *dg = malloc(sizeof(double) * nmax);
+  double *up = malloc(sizeof(double) * nmax), *rhs = malloc(sizeof(double) * nmax);
+  for (int s = 0; s < sweeps; s++)
+    for (int a = 0; a < d->ndim; a++) {
+      if (d->bc[a][0] == OM_PERIODIC) continue;
+      int n = L->n[a];
+      for (int col = 0; col < line_colours(d); col++) {
+        fill_ghosts(d, L, u);
+        for (int k = 0; k < (a == 2 ? 1 : L->n[2]); k++)
+          for (int j = 0; j < (a == 1 ? 1 : L->n[1]); j++)
+            for (int i = 0; i < (a == 0 ? 1 : L->n[0]); i++) {
+              int c0[3] = {i, j, k};
+              if (!on_line_colour(d, a, col, c0)) continue;
+              for (int m = 0; m < n; m++) {
+                int c[3] = {i, j, k};
+                c[a] = m;
+                double dgm, wm, wp;
+                double Lu = apply_cell(d, L, u, ac, a2c, c[0], c[1], c[2], &dgm);
+                for (int b = 0; b < d->ndim; b++) {
+                  if (d->bc[b][0] == OM_PERIODIC) continue;
+                  weights(d, L, b, c[0], c[1], c[2], &wm, &wp);
+                  int g[3] = {c[0], c[1], c[2]};
+                  if (c[b] == 0) {
+                    g[b] = -1;
+                    dgm += wm * ghost_factor(d, L, b, 0, c, g);
+                  }
+                  if (c[b] == L->n[b] - 1) {
+                    g[b] = L->n[b];
+                    dgm += wp * ghost_factor(d, L, b, 1, c, g);
+                  }
+                }
+                weights(d, L, a, c[0], c[1], c[2], &wm, &wp);
+                lo[m] = wm;
+                up[m] = wp;
+                dg[m] = dgm;
+                rhs[m] = f[idx(d, L, c[0], c[1], c[2])] - Lu;
+              }
+              thomas(n, lo, dg, up, rhs);
+              for (int m = 0; m < n; m++) {
+                int c[3] = {i, j, k};
+                c[a] = m;
+                u[idx(d, L, c[0], c[1], c[2])] += rhs[m];
+              }
+            }
+      }
+    }
+  free(lo);
+  free(dg);
+  free(up);
+  free(rhs);
   fill_ghosts(d, L, u);
 }
 
@@ -439,6 +548,12 @@ void om_fill_ghosts(const om_desc *d, int level, double *u) {
 void om_smooth(const om_desc *d, double *u, const double *f, const double *a, const double *a2, int sweeps) {
   lvl L = level_of(d, d->levels - 1);
   smooth(d, &L, u, f, a, a2, sweeps);
+}
+
+/* `sweeps` line-relaxation sweeps on the finest level (line_smooth). */
+void om_line_smooth(const om_desc *d, double *u, const double *f, const double *a, const double *a2, int sweeps) {
+  lvl L = level_of(d, d->levels - 1);
+  line_smooth(d, &L, u, f, a, a2, sweeps);
 }
 
 /* fine level l, coarse level l - 1 */
@@ -761,6 +876,72 @@ static void vsmooth(const om_desc *d, const lvl *L, double *u, const double *f, 
           }
 }
 
+/* Line relaxation of the vector equations (as line_smooth): per line the
+ * components one after the other, each a Newton step of its own equation
+ * with its exact Jacobian with respect to that component on the line's
+ * cells -- the flux-form Laplacian weights along the line, times 4/3 for
+ * the component along the line's axis (the grad-div term adds (1/3)
+ * d^2/dx_a^2 of the a-th component); on the diagonal the point smoother's
+ * dL/du plus, for every non-periodic boundary face of the cell, the
+ * weight toward its mirror ghost (times 4/3 across a face normal to the
+ * component) times the component's sign there -- everything else at its
+ * current value (the other components included). */
+static void vline_smooth(const om_desc *d, const lvl *L, double *u, const double *f, int sweeps) {
+  int any = 0;
+  for (int a = 0; a < d->ndim; a++) any |= d->bc[a][0] != OM_PERIODIC;
+  if (!any) {
+    vsmooth(d, L, u, f, sweeps);
+    return;
+  }
+  int nmax = L->n[0] > L->n[1] ? L->n[0] : L->n[1];
+  nmax = nmax > L->n[2] ? nmax : L->n[2];
+  double *lo = malloc(sizeof(double) * nmax), *dg = malloc(sizeof(double) * nmax);
+  double *up = malloc(sizeof(double) * nmax), *rhs = malloc(sizeof(double) * nmax);
+  for (int s = 0; s < sweeps; s++)
+    for (int a = 0; a < d->ndim; a++) {
+      if (d->bc[a][0] == OM_PERIODIC) continue;
+      int n = L->n[a];
+      for (int col = 0; col < line_colours(d); col++)
+        for (int k = 0; k < (a == 2 ? 1 : L->n[2]); k++)
+          for (int j = 0; j < (a == 1 ? 1 : L->n[1]); j++)
+            for (int i = 0; i < (a == 0 ? 1 : L->n[0]); i++) {
+              int c0[3] = {i, j, k};
+              if (!on_line_colour(d, a, col, c0)) continue;
+              for (int comp = 0; comp < 3; comp++) {
+                double kap = comp == a ? 4.0 / 3.0 : 1.0;
+                for (int m = 0; m < n; m++) {
+                  int c[3] = {i, j, k};
+                  c[a] = m;
+                  double dgm, wm, wp;
+                  double Lu = vapply_cell(d, L, u, comp, c[0], c[1], c[2], &dgm);
+                  for (int b = 0; b < d->ndim; b++) {
+                    if (d->bc[b][0] == OM_PERIODIC) continue;
+                    double kb = comp == b ? 4.0 / 3.0 : 1.0;
+                    weights(d, L, b, c[0], c[1], c[2], &wm, &wp);
+                    if (c[b] == 0) dgm += kb * wm * vsign(d, L, b, 0, comp);
+                    if (c[b] == L->n[b] - 1) dgm += kb * wp * vsign(d, L, b, 1, comp);
+                  }
+                  weights(d, L, a, c[0], c[1], c[2], &wm, &wp);
+                  lo[m] = kap * wm;
+                  up[m] = kap * wp;
+                  dg[m] = dgm;
+                  rhs[m] = f[comp * L->nt + idx(d, L, c[0], c[1], c[2])] - Lu;
+                }
+                thomas(n, lo, dg, up, rhs);
+                for (int m = 0; m < n; m++) {
+                  int c[3] = {i, j, k};
+                  c[a] = m;
+                  u[comp * L->nt + idx(d, L, c[0], c[1], c[2])] += rhs[m];
+                }
+              }
+            }
+    }
+  free(lo);
+  free(dg);
+  free(up);
+  free(rhs);
+}
+
 static void vresidual(const om_desc *d, const lvl *L, const double *u, const double *f, double *r) {
   for (int k = 0; k < L->n[2]; k++)
     for (int j = 0; j < L->n[1]; j++)
@@ -872,6 +1053,11 @@ void om_vapply(const om_desc *d, const double *u, double *out) {
 void om_vsmooth(const om_desc *d, double *u, const double *f, int sweeps) {
   lvl L = level_of(d, d->levels - 1);
   vsmooth(d, &L, u, f, sweeps);
+}
+
+void om_vline_smooth(const om_desc *d, double *u, const double *f, int sweeps) {
+  lvl L = level_of(d, d->levels - 1);
+  vline_smooth(d, &L, u, f, sweeps);
 }
 
 /* Face ghosts of the three components of X on the finest level from the

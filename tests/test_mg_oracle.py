@@ -806,3 +806,145 @@ def test_shift_source_uses_the_orthonormal_gradient():
             e = max(e, np.abs(mg.interior(p, out[i]) - mg.interior(p, ex)).max())
         errs.append(e)
     assert 3.5 < errs[0] / errs[1] < 4.5, errs
+
+
+# ------------------------------------------------ line relaxation smoother
+
+def _lines(p, ax, col):
+    """Interior flat indices (k, j, i order) of each line of colour col
+    along axis ax: transverse axes coloured by index parity (bit 0 the
+    lower transverse axis, bit 1 the upper)."""
+    nd = p["ndim"]
+    shp = tuple(p["n"][a] for a in (2, 1, 0))
+    idx = np.arange(int(np.prod(shp))).reshape(shp)
+    b1, b2 = (1 if ax == 0 else 0), (1 if ax == 2 else 2)
+    lines = {}
+    for kk in range(shp[0]):
+        for jj in range(shp[1]):
+            for ii in range(shp[2]):
+                c = [ii, jj, kk]
+                p1 = c[b1] & 1 if b1 < nd else 0
+                p2 = c[b2] & 1 if b2 < nd else 0
+                if (p1 | (p2 << 1)) == col:
+                    lines.setdefault(tuple(c[b] for b in range(3) if b != ax), []).append(idx[kk, jj, ii])
+    return [np.array(sorted(v)) for v in lines.values()]
+
+
+def _block_gauss_seidel(p, residual, jacobian, u, sweeps, ncomp=1):
+    """Line sweeps from their definition: per active non-periodic axis, per
+    colour, per line (per component) one Newton step u_I += J_II^-1 r_I with
+    the full residual r and the Jacobian block of the line's unknowns."""
+    nd = p["ndim"]
+    nc = int(np.prod(p["n"]))
+    for _ in range(sweeps):
+        for ax in range(nd):
+            if p["bc"][ax][0] == PER:
+                continue
+            for col in range(1 << (nd - 1)):
+                for I0 in _lines(p, ax, col):
+                    for q in range(ncomp):
+                        I = I0 + q * nc
+                        r = residual(u)
+                        u[I] += np.linalg.solve(jacobian(u)[np.ix_(I, I)], r[I])
+    return u
+
+
+LINE_SCALAR = {
+    "sph2d_robin": prob(2, SPH, (8, 6), (0, 0), (30, math.pi / 2), [[N, ROB], [N, N]]),
+    "cyl2d_robin": prob(2, CYL, (6, 8), (0, -1), (2, 1), [[N, ROB], [ROB, D]]),
+    "cart3d_periodic": prob(3, CART, (4, 4, 6), (0, 0, 0), (1, 1, 1), [[D, N], [PER, PER], [ROB, D]]),
+    "sph3d_shell": prob(3, SPH, (4, 4, 4), (0.5, 0.3, 0), (2.5, math.pi - 0.3, 2 * math.pi),
+                        [[D, ROB], [N, D], [PER, PER]]),
+    "psi_sph2d": prob(2, SPH, (8, 6), (0, 0), (30, math.pi / 2), [[N, ROB], [N, N]], power=-1, power2=-7,
+                      offset=1.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(LINE_SCALAR))
+def test_line_smoother_is_block_gauss_seidel_over_lines(case):
+    """Two line-relaxation sweeps equal block Gauss-Seidel over the lines
+    of the assembled operator (its matrix built column by column from the
+    point operator with the boundary rule, the nonlinear terms' derivative
+    added on the diagonal): the Jacobian blocks, the line ordering and the
+    boundary folds all follow from the operator itself."""
+    p = LINE_SCALAR[case]
+    rng = np.random.default_rng(5)
+    sh = mg.shape(p)
+    u0 = rng.standard_normal(sh) * 0.1
+    f = rng.standard_normal(sh)
+    nl = p.get("power", 0) != 0
+    a = rng.random(sh) * 0.1 if nl else None
+    a2 = rng.random(sh) * 0.1 if nl else None
+    A = operator_matrix(p).toarray()
+    ai, a2i = (mg.interior(p, a).ravel(), mg.interior(p, a2).ravel()) if nl else (0.0, 0.0)
+    c, q = p.get("offset", 0.0), p.get("power2", 0)
+
+    def nonlin(v, deriv):
+        w = v + c
+        if not nl:
+            return 0.0 * v
+        return (-ai / (w * w) + a2i * q * w ** (q - 1)) if deriv else (ai / w + a2i * w ** q)
+
+    fi = mg.interior(p, f).ravel()
+    ref = _block_gauss_seidel(p, lambda v: fi - (A @ v - nonlin(v, False)),
+                              lambda v: A - np.diag(nonlin(v, True)), mg.interior(p, u0).ravel().copy(), 2)
+    got = mg.interior(p, mg.line_smooth(p, u0.copy(), f, a, sweeps=2, a2=a2)).ravel()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def vector_operator_matrix(p):
+    """The vector operator as a dense matrix over (component, interior
+    cell), column by column from the oracle's vapply on unit fields."""
+    shp = mg.shape(p)
+    nt = int(np.prod(shp))
+    inner = mg.interior(p, np.arange(nt).reshape(shp)).ravel()
+    cols = []
+    for q in range(3):
+        for k in inner:
+            e = np.zeros((3, nt))
+            e[q, k] = 1.0
+            L = mg.vapply(p, np.ascontiguousarray(e.reshape((3,) + shp)))
+            cols.append(np.concatenate([mg.interior(p, L[c]).ravel() for c in range(3)]))
+    return np.array(cols).T
+
+
+LINE_VECTOR = {
+    "sph2d_eq": prob(2, SPH, (8, 6), (0, 0), (2, math.pi / 2), [[N, D], [N, N]]),
+    "sph2d_shell": prob(2, SPH, (6, 8), (0.5, 0), (2.5, math.pi), [[D, D], [N, N]]),
+    "cyl2d": prob(2, CYL, (6, 8), (0, -2), (2, 2), [[N, D], [D, D]]),
+    "cart3d_ragged": prob(3, CART, (4, 6, 4), (0, 0, 0), (1.2, 2.0, 0.6), [[PER, PER], [N, D], [D, D]]),
+    "cart1d": prob(1, CART, (8,), (0,), (1,), [[D, N]]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(LINE_VECTOR))
+def test_vector_line_smoother_is_block_gauss_seidel(case):
+    """Two vector line sweeps equal block Gauss-Seidel over (line,
+    component) blocks of the assembled vector operator, components of a
+    line in order: the 4/3 weight of the component along the line, the
+    mirror signs folded at the boundaries and the orthonormal connection
+    terms on the diagonal all follow from the operator."""
+    p = LINE_VECTOR[case]
+    rng = np.random.default_rng(6)
+    sh = (3,) + mg.shape(p)
+    X0, f = rng.standard_normal(sh), rng.standard_normal(sh)
+    A = vector_operator_matrix(p)
+    fi = np.concatenate([mg.interior(p, f[q]).ravel() for q in range(3)])
+    x = np.concatenate([mg.interior(p, X0[q]).ravel() for q in range(3)])
+    ref = _block_gauss_seidel(p, lambda v: fi - A @ v, lambda v: A, x, 2, ncomp=3)
+    got = mg.vline_smooth(p, X0.copy(), f, sweeps=2)
+    g = np.concatenate([mg.interior(p, got[q]).ravel() for q in range(3)])
+    assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("coord", [CART, CYL, SPH])
+def test_one_line_sweep_solves_a_linear_1d_problem(coord):
+    """In 1D the only line is the whole grid: one sweep solves a linear
+    equation (p = 1 here) to rounding."""
+    p = prob(1, coord, (32,), (0.0,), (4.0,), [[N if coord != CART else D, ROB]], power=1, offset=1.0)
+    rng = np.random.default_rng(7)
+    sh = mg.shape(p)
+    u, f, a = rng.standard_normal(sh), rng.standard_normal(sh), rng.random(sh)
+    mg.line_smooth(p, u, f, a, sweeps=1)
+    L = mg.interior(p, mg.apply(p, u, a))
+    assert np.abs(mg.interior(p, f) - L).max() <= 1e-12 * np.abs(L).max()
