@@ -509,6 +509,63 @@ def bench_xcfc(n=256, half=24.0, omega=0.01, sweeps=10):
     return out
 
 
+def bench_xcfc_sph(nr=640, nth=64, rmax=30.0, omega=0.02, tol=1e-6, smoother=1, sweeps=2):
+    """The xCFC metric update (solve, then recovery on the new metric) of a
+    uniformly rotating polytropic star on the layout of the paper's 2D
+    rotating-star runs: spherical (r, theta) in [0, 30] x [0, pi/2] with
+    640 x 64 cells, centre, polar axis and equator symmetry faces, Robin
+    falloff for psi and alpha psi, X = beta = 0 at r = 30; from the flat
+    metric, and again warm, to the paper's typical metric-solver tolerance
+    (1e-6).  Smoother: line relaxation (1, V(2,2)) or the paper's point
+    smoother (0; V(4,4) recommended)."""
+    import torch
+
+    import paper_2012_07322_amd as gmu
+    import workloads as W
+
+    log(f"[bench] xCFC spherical: rotating star on {nr}x{nth}")
+    hp, pr, met = W.rotating_star_sph2d(nr, nth, rmax, omega)
+    g = gmu.Grid(hp)
+    prd = torch.from_numpy(pr).cuda()
+    metd = torch.from_numpy(met).cuda()
+    q = g.prim2con(prd, metd)
+    base = dict(ndim=2, coord=2, n=[nr, nth, 1], xmin=[0.0, 0.0, 0.0], dx=[rmax / nr, math.pi / 2 / nth, 1.0],
+                pre=sweeps, post=sweeps, coarse=8 if smoother else 50, smoother=smoother)
+    Mv = gmu.Multigrid(dict(base, bc=[[1, 0], [1, 1], [1, 1]]))
+    Mp = gmu.Multigrid(dict(base, bc=[[1, 3], [1, 1], [1, 1]], power=-1, power2=-7, offset=1.0))
+    Ma = gmu.Multigrid(dict(base, bc=[[1, 3], [1, 1], [1, 1]], power=1, offset=1.0))
+    X = Mv.empty(vector=True)
+    flat = torch.from_numpy(W.flat_metric(hp)).cuda()
+    metd.copy_(flat)
+    gmu.metric_update(g, Mp, Ma, q, prd, metd, mvec=Mv, X=X, tol=tol, max_cycles=2000)  # warm-up
+    metd.copy_(flat)
+    X.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cyc = gmu.metric_update(g, Mp, Ma, q, prd, metd, mvec=Mv, X=X, tol=tol, max_cycles=2000)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    cyc_w = gmu.metric_update(g, Mp, Ma, q, prd, metd, mvec=Mv, X=X, tol=tol, max_cycles=2000)
+    torch.cuda.synchronize()
+    ms_w = (time.perf_counter() - t0) * 1e3
+    ng = hp["ng"]
+    m = metd[:, 0, ng:ng + nth, ng:ng + nr]
+    out = {"workload": f"uniformly rotating polytropic star (K=100, Gamma=2, rho_c=1.28e-3, omega={omega:g}), spherical "
+                       f"{nr}x{nth} on [0,{rmax:g}]x[0,pi/2], centre/axis/equator symmetry, Robin falloff, flat "
+                       f"initial metric",
+           "smoother": "line" if smoother else "point", "sweeps": sweeps,
+           "tolerance": tol, "ms_per_update": ms, "cycles_X_psi_alphapsi_beta": list(cyc),
+           "ms_per_warm_update": ms_w, "warm_cycles": list(cyc_w),
+           "psi_centre": float(m[0].max()), "alpha_centre": float(m[1].min()),
+           "min_beta_phi": float(m[4].min())}
+    log(f"[bench] xCFC spherical: update {ms:.1f} ms, cycles {cyc}, warm {ms_w:.1f} ms {cyc_w}")
+    for M in (Mv, Mp, Ma):
+        M.close()
+    g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -529,6 +586,8 @@ def main():
     ap.add_argument("--serve-plain-open", type=int, default=100)
     ap.add_argument("--mg", type=int, default=256, help="multigrid grid size (0: skip)")
     ap.add_argument("--xcfc", type=int, default=256, help="xCFC metric-solve grid size (0: skip)")
+    ap.add_argument("--xcfc-sph", type=int, default=640,
+                    help="radial cells of the spherical xCFC update (theta cells: a tenth; 0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -632,6 +691,9 @@ def main():
         torch.cuda.empty_cache()
     if args.xcfc > 0:
         out["xcfc"] = bench_xcfc(args.xcfc)
+        torch.cuda.empty_cache()
+    if args.xcfc_sph > 0:
+        out["xcfc_spherical"] = bench_xcfc_sph(args.xcfc_sph, max(8, args.xcfc_sph // 10))
         torch.cuda.empty_cache()
     if args.serve_requests > 0:
         out["serving"] = bench_serve(args.serve_requests, probe=args.serve_probe, plain_n=args.serve_plain,

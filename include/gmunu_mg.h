@@ -52,12 +52,31 @@ typedef struct {
   double dx[3];      /* finest spacing per axis */
   int bc[3][2];      /* GMUNU_MG_* per axis and side */
   int levels;        /* levels in the hierarchy; 0: as many as the axes allow (see gmunu_mg_create) */
-  int pre, post;     /* red-black sweeps before and after the coarse correction (>= 0) */
+  int pre, post;     /* smoothing sweeps before and after the coarse correction (>= 0) */
   int coarse;        /* sweeps on the coarsest level (>= 1) */
   int power;         /* p: -1, 0 or 1 */
   double offset;     /* c */
   int power2;        /* q of the second term, -8..8; 0: no second term (a2 must be NULL) */
+  int smoother;      /* GMUNU_MG_POINT or GMUNU_MG_LINE */
 } gmunu_mg_desc;
+
+/* Smoothers.  POINT: red-black Newton-Gauss-Seidel, one cell at a time
+ * (section 2.7).  LINE: alternating zebra line relaxation, for the grids on
+ * which section 2.7 notes that point smoothers converge slowly (spherical
+ * polar cells, whose aspect r dtheta / dr runs from far below to far above
+ * one): a sweep takes each active non-periodic axis in turn and relaxes
+ * whole lines of cells along it, lines coloured by the parities of their
+ * transverse indices and one colour after the other; each line takes one
+ * Newton step of the equation with the couplings along the line solved
+ * exactly (a tridiagonal system, parallel cyclic reduction, the face ghosts
+ * at its two ends folded into the boundary cells through the boundary
+ * rule) and the transverse neighbours held at their current values.  The
+ * vector equations relax the components of a line one after the other.
+ * Lines may be at most 1024 cells long (longer non-periodic axes: EINVAL);
+ * with every active axis periodic LINE relaxes points.  The line systems
+ * must be non-singular: a problem with no Dirichlet or Robin face, a = 0
+ * and one active axis is not. */
+enum { GMUNU_MG_POINT = 0, GMUNU_MG_LINE = 1 };
 
 typedef struct gmunu_mg gmunu_mg;
 

@@ -526,10 +526,12 @@ class MgDesc(ctypes.Structure):
         ("xmin", ctypes.c_double * 3), ("dx", ctypes.c_double * 3), ("bc", (ctypes.c_int * 2) * 3),
         ("levels", ctypes.c_int), ("pre", ctypes.c_int), ("post", ctypes.c_int), ("coarse", ctypes.c_int),
         ("power", ctypes.c_int), ("offset", ctypes.c_double), ("power2", ctypes.c_int),
+        ("smoother", ctypes.c_int),
     ]
 
 
-MG_DEFAULTS = dict(levels=0, pre=2, post=2, coarse=50, power=0, offset=0.0, power2=0)
+MG_DEFAULTS = dict(levels=0, pre=2, post=2, coarse=50, power=0, offset=0.0, power2=0, smoother=0)
+MG_POINT, MG_LINE = 0, 1
 
 
 def _mg_sigs(L):
@@ -573,6 +575,7 @@ def make_mg_desc(p: dict) -> MgDesc:
         d.bc[a][0], d.bc[a][1] = int(q["bc"][a][0]), int(q["bc"][a][1])
     d.levels, d.pre, d.post, d.coarse = int(q["levels"]), int(q["pre"]), int(q["post"]), int(q["coarse"])
     d.power, d.offset, d.power2 = int(q["power"]), float(q["offset"]), int(q["power2"])
+    d.smoother = int(q["smoother"])
     return d
 
 

@@ -49,6 +49,7 @@ struct MgGeo {
   unsigned vodd[3][2];    // vector equations: components odd across each mirror face (bit q)
   int power, power2;
   double offset;
+  int line;  // smoother: alternating zebra line relaxation (else red-black points)
   // vector operator (Cartesian): 1/h_a^2, 1/(4 h_a h_b) for the axis pairs
   // (0,1), (0,2), (1,2), and the inverse diagonal of each component's row
   double vih2[3], vmix[3], vidg[3];
@@ -332,6 +333,173 @@ __global__ __launch_bounds__(NT) void k_mg_coarse(const MgGeo G, double *u, cons
     }
   if (lds)
     for (long e = threadIdx.x; e < G.nt; e += NT) u[e] = uu[e];
+}
+
+// ---- Line relaxation --------------------------------------------------------
+// One wavefront per line.  The line's tridiagonal system (couplings toward
+// the lower and upper neighbour along the line, diagonal, right-hand side)
+// is built in LDS by the lanes, cell by cell, and solved by parallel cyclic
+// reduction: at stride s every row eliminates its couplings to the rows s
+// below and s above, so after ceil(log2 n) doublings each row holds one
+// unknown.  Two copies of the four arrays alternate between doublings.
+
+constexpr int kLineWave = 64;
+constexpr int kMaxLine = 1024;
+
+// Weights of the flux-form Laplacian from cell (I, J) (ghost-inclusive
+// indices) toward its lower and upper neighbour along axis a: the terms
+// of mg_L.
+__device__ __forceinline__ void mg_w(const MgGeo &G, int I, int J, int a, double &wm, double &wp) {
+  if (a == 0) {
+    wm = G.a0m[I];
+    wp = G.a0p[I];
+  } else if (a == 1) {
+    wm = G.g1[I] * G.a1m[J];
+    wp = G.g1[I] * G.a1p[J];
+  } else {
+    wm = wp = G.g2[I] * G.s2t[J] * G.ih2_2;
+  }
+}
+
+// Factor s of the boundary rule ghost = s u_cell across the non-periodic
+// face (a, up) of boundary cell c.
+__device__ __forceinline__ double mg_fold(const MgGeo &G, const int c[3], int a, bool up) {
+  const int kind = G.bc[a][up ? 1 : 0];
+  return kind == GMUNU_MG_DIRICHLET ? -1.0 : kind == GMUNU_MG_NEUMANN ? 1.0 : mg_rob(G, c[0], c[1], c[2], a, up);
+}
+
+// First cell of line t of colour `colour` along axis a: the transverse
+// axes b1 < b2, each active one coloured by its index parity (bit 0: b1,
+// bit 1: b2).  False past the last line.
+__device__ __forceinline__ bool mg_line(const MgGeo &G, int a, int colour, long t, int c[3]) {
+  const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+  const int p1 = colour & 1, p2 = (colour >> 1) & 1;
+  const long h1 = b1 < G.ndim ? (G.n[b1] - p1 + 1) >> 1 : 1;
+  const long h2 = b2 < G.ndim ? (G.n[b2] - p2 + 1) >> 1 : 1;
+  if (t >= h1 * h2) return false;
+  c[a] = 0;
+  c[b1] = b1 < G.ndim ? 2 * (int)(t % h1) + p1 : 0;
+  c[b2] = b2 < G.ndim ? 2 * (int)(t / h1) + p2 : 0;
+  return true;
+}
+
+// Parallel cyclic reduction of the system in sm (A: lower couplings, B:
+// diagonal, C: upper couplings, D: right-hand side, n entries each, A[0] =
+// C[n-1] = 0) by the 64 lanes of one wavefront (lane `ln`); returns the
+// copy (0 or 1) holding the decoupled rows, whose solution is D / B.  The
+// doublings are separated by workgroup barriers, so every wavefront of the
+// workgroup calls this with the same n.
+__device__ __forceinline__ int mg_pcr(double *sm, int n, int ln) {
+  int p = 0;
+  for (int s = 1; s < n; s <<= 1) {
+    const double *A = sm + p * 4 * n, *B = A + n, *C = B + n, *D = C + n;
+    double *A2 = sm + (1 - p) * 4 * n, *B2 = A2 + n, *C2 = B2 + n, *D2 = C2 + n;
+    for (int m = ln; m < n; m += kLineWave) {
+      double b = B[m], d = D[m], na = 0.0, nc = 0.0;
+      if (m >= s) {
+        const double al = -A[m] / B[m - s];
+        na = al * A[m - s];
+        b += al * C[m - s];
+        d += al * D[m - s];
+      }
+      if (m + s < n) {
+        const double ga = -C[m] / B[m + s];
+        nc = ga * C[m + s];
+        b += ga * A[m + s];
+        d += ga * D[m + s];
+      }
+      A2[m] = na;
+      B2[m] = b;
+      C2[m] = nc;
+      D2[m] = d;
+    }
+    __syncthreads();
+    p ^= 1;
+  }
+  return p;
+}
+
+// One Newton step of the line from cell c along axis ax by one wavefront
+// (lane ln, LDS sm of 8 n doubles; live = false: a wavefront with no line
+// that only keeps the workgroup's barriers) with the exact Jacobian with
+// respect to the line's cells: the couplings along the line, on the
+// diagonal mg_L's dL/du plus, across each non-periodic boundary face of
+// the cell, the weight toward the ghost times its boundary-rule factor (the
+// ghost follows the cell); right-hand side f - L(u); u += the solution.
+__device__ __forceinline__ void mg_line_step(const MgGeo &G, double *u, const double *__restrict__ f,
+                                             const double *__restrict__ a, const double *__restrict__ a2, int ax,
+                                             const int c[3], bool live, double *sm, int ln) {
+  const int n = G.n[ax];
+  for (int m = ln; live && m < n; m += kLineWave) {
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[ax] = m;
+    const long o = mg_off(G, cc[0], cc[1], cc[2]);
+    double dg, wm, wp;
+    const double Lu = mg_L<false>(G, u, a ? a[o] : 0.0, a2 ? a2[o] : 0.0, cc[0], cc[1], cc[2], o, &dg);
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      if (b >= G.ndim || G.bc[b][0] == GMUNU_MG_PERIODIC || (cc[b] > 0 && cc[b] < G.n[b] - 1)) continue;
+      mg_w(G, cc[0] + G.g[0], cc[1] + G.g[1], b, wm, wp);
+      if (cc[b] == 0) dg += wm * mg_fold(G, cc, b, false);
+      if (cc[b] == G.n[b] - 1) dg += wp * mg_fold(G, cc, b, true);
+    }
+    mg_w(G, cc[0] + G.g[0], cc[1] + G.g[1], ax, wm, wp);
+    if (m == 0) wm = 0.0;
+    if (m == n - 1) wp = 0.0;
+    sm[m] = wm;
+    sm[n + m] = dg;
+    sm[2 * n + m] = wp;
+    sm[3 * n + m] = f[o] - Lu;
+  }
+  __syncthreads();
+  const double *R = sm + mg_pcr(sm, n, ln) * 4 * n;
+  for (int m = ln; live && m < n; m += kLineWave) {
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[ax] = m;
+    u[mg_off(G, cc[0], cc[1], cc[2])] += R[3 * n + m] / R[n + m];
+  }
+}
+
+// Lines of one colour along axis ax, one wavefront (workgroup) per line.
+__global__ __launch_bounds__(kLineWave) void k_mg_line(const MgGeo G, double *u, const double *__restrict__ f,
+                                                       const double *__restrict__ a, const double *__restrict__ a2,
+                                                       int ax, int colour) {
+  extern __shared__ double sm[];
+  int c[3];
+  if (!mg_line(G, ax, colour, blockIdx.x, c)) return;
+  mg_line_step(G, u, f, a, a2, ax, c, true, sm, threadIdx.x);
+}
+
+// Number of lines of colour `colour` along axis a.
+__host__ __device__ __forceinline__ long mg_line_count(const MgGeo &G, int a, int colour) {
+  const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+  const long h1 = b1 < G.ndim ? (G.n[b1] - (colour & 1) + 1) >> 1 : 1;
+  const long h2 = b2 < G.ndim ? (G.n[b2] - ((colour >> 1) & 1) + 1) >> 1 : 1;
+  return h1 * h2;
+}
+
+// The coarsest-level solver of the line smoother: `sweeps` line sweeps by
+// one workgroup of NT threads, its wavefronts taking a colour's lines in
+// rounds (LDS: 8 n doubles per wavefront and axis), colours and axes
+// separated by barriers.
+__global__ __launch_bounds__(NT) void k_mg_line_coarse(const MgGeo G, double *u, const double *__restrict__ f,
+                                                       const double *__restrict__ a, const double *__restrict__ a2,
+                                                       int sweeps) {
+  extern __shared__ double sm[];
+  const int w = threadIdx.x / kLineWave, ln = threadIdx.x % kLineWave, nw = NT / kLineWave;
+  for (int s = 0; s < sweeps; s++)
+    for (int ax = 0; ax < G.ndim; ax++) {
+      if (G.bc[ax][0] == GMUNU_MG_PERIODIC) continue;
+      for (int col = 0; col < 1 << (G.ndim - 1); col++) {
+        const long nl = mg_line_count(G, ax, col);
+        for (long t0 = 0; t0 < nl; t0 += nw) {
+          int c[3] = {0, 0, 0};
+          const bool live = mg_line(G, ax, col, t0 + w, c);
+          mg_line_step(G, u, f, a, a2, ax, c, live, sm + (long)w * 8 * G.n[ax], ln);
+          __syncthreads();
+        }
+      }
+    }
 }
 
 // out = L(u) on the interior.
@@ -804,6 +972,80 @@ __global__ __launch_bounds__(NT) void k_mgv_coarse(const MgGeo G, double *u, con
     for (long e = threadIdx.x; e < n3; e += NT) u[e] = uu[e];
 }
 
+// Line relaxation of the vector equations, the line from cell c along
+// axis ax by one wavefront (as mg_line_step): the components one after the
+// other, each a Newton step of its own equation with its exact Jacobian
+// with respect to that component on the line -- the couplings of the
+// component's flux-form Laplacian, times 4/3 along the component's own
+// axis through the grad-div term; on the diagonal the point smoother's
+// plus, across each non-periodic boundary face, the weight toward the
+// mirror ghost times the component's sign there -- and everything else
+// (the other components included) at its current value.
+__device__ __forceinline__ void mgv_line_step(const MgGeo &G, double *u, const double *__restrict__ f, int ax,
+                                              const int c[3], bool live, double *sm, int ln) {
+  const int n = G.n[ax];
+  for (int q = 0; q < 3; q++) {
+    const double kap = ax == q && q < G.ndim ? 4.0 / 3.0 : 1.0;
+    for (int m = ln; live && m < n; m += kLineWave) {
+      int cc[3] = {c[0], c[1], c[2]};
+      cc[ax] = m;
+      const long o = mg_off(G, cc[0], cc[1], cc[2]);
+      double L[3], idg[3], wm, wp;
+      mgv_L(G, u, o, cc[0], cc[1], cc[2], L, idg);
+      double dg = 1.0 / idg[q];
+#pragma unroll
+      for (int b = 0; b < 3; b++) {
+        if (b >= G.ndim || G.bc[b][0] == GMUNU_MG_PERIODIC || (cc[b] > 0 && cc[b] < G.n[b] - 1)) continue;
+        const double kb = b == q ? 4.0 / 3.0 : 1.0;
+        mg_w(G, cc[0] + G.g[0], cc[1] + G.g[1], b, wm, wp);
+        if (cc[b] == 0) dg += (G.vodd[b][0] >> q) & 1 ? -kb * wm : kb * wm;
+        if (cc[b] == G.n[b] - 1) dg += (G.vodd[b][1] >> q) & 1 ? -kb * wp : kb * wp;
+      }
+      mg_w(G, cc[0] + G.g[0], cc[1] + G.g[1], ax, wm, wp);
+      wm = m == 0 ? 0.0 : kap * wm;
+      wp = m == n - 1 ? 0.0 : kap * wp;
+      sm[m] = wm;
+      sm[n + m] = dg;
+      sm[2 * n + m] = wp;
+      sm[3 * n + m] = f[q * G.nt + o] - L[q];
+    }
+    __syncthreads();
+    const double *R = sm + mg_pcr(sm, n, ln) * 4 * n;
+    for (int m = ln; live && m < n; m += kLineWave) {
+      int cc[3] = {c[0], c[1], c[2]};
+      cc[ax] = m;
+      u[q * G.nt + mg_off(G, cc[0], cc[1], cc[2])] += R[3 * n + m] / R[n + m];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kLineWave) void k_mgv_line(const MgGeo G, double *u, const double *__restrict__ f,
+                                                        int ax, int colour) {
+  extern __shared__ double sm[];
+  int c[3];
+  if (!mg_line(G, ax, colour, blockIdx.x, c)) return;
+  mgv_line_step(G, u, f, ax, c, true, sm, threadIdx.x);
+}
+
+__global__ __launch_bounds__(NT) void k_mgv_line_coarse(const MgGeo G, double *u, const double *__restrict__ f,
+                                                        int sweeps) {
+  extern __shared__ double sm[];
+  const int w = threadIdx.x / kLineWave, ln = threadIdx.x % kLineWave, nw = NT / kLineWave;
+  for (int s = 0; s < sweeps; s++)
+    for (int ax = 0; ax < G.ndim; ax++) {
+      if (G.bc[ax][0] == GMUNU_MG_PERIODIC) continue;
+      for (int col = 0; col < 1 << (G.ndim - 1); col++) {
+        const long nl = mg_line_count(G, ax, col);
+        for (long t0 = 0; t0 < nl; t0 += nw) {
+          int c[3] = {0, 0, 0};
+          const bool live = mg_line(G, ax, col, t0 + w, c);
+          mgv_line_step(G, u, f, ax, c, live, sm + (long)w * 8 * G.n[ax], ln);
+        }
+      }
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_mgv_apply(const MgGeo G, const double *__restrict__ u,
                                                   double *__restrict__ out) {
   const long t = (long)blockIdx.x * NT + threadIdx.x;
@@ -1247,6 +1489,9 @@ int validate(const gmunu_mg_desc &d, int levels) {
     return GMUNU_EINVAL;
   if (d.power < -1 || d.power > 1 || d.pre < 0 || d.post < 0 || d.coarse < 1) return GMUNU_EINVAL;
   if (d.power2 < -8 || d.power2 > 8) return GMUNU_EINVAL;
+  if (d.smoother != GMUNU_MG_POINT && d.smoother != GMUNU_MG_LINE) return GMUNU_EINVAL;
+  for (int a = 0; a < d.ndim; a++)
+    if (d.smoother == GMUNU_MG_LINE && d.bc[a][0] != GMUNU_MG_PERIODIC && d.n[a] > kMaxLine) return GMUNU_EINVAL;
   // cell numbers of a level fit 32-bit kernel arithmetic
   if ((double)(d.n[0] + 2) * (d.n[1] + 2) * (d.n[2] + 2) >= 2147483647.0) return GMUNU_EINVAL;
   return GMUNU_OK;
@@ -1335,6 +1580,9 @@ void level_tables(const gmunu_mg_desc &d, int s, std::vector<double> &tab, size_
   G.power = d.power;
   G.power2 = d.power2;
   G.offset = d.offset;
+  G.line = 0;
+  for (int a = 0; a < d.ndim; a++)
+    if (d.smoother == GMUNU_MG_LINE && d.bc[a][0] != GMUNU_MG_PERIODIC) G.line = 1;
   double dsum = 0.0;
   for (int a = 0; a < 3; a++) {
     G.vih2[a] = a < d.ndim ? 1.0 / (G.h[a] * G.h[a]) : 0.0;
@@ -1363,9 +1611,36 @@ void ghosts(const MgGeo &G, double *u, hipStream_t st) {
   if (gc) hipLaunchKernelGGL(k_mg_ghosts<1>, dim3(nblocks(gc)), dim3(NT), 0, st, G, u);
 }
 
-// Red-black sweeps (boundary rule inline: no ghost fill between colours).
+// Line sweeps: per sweep every non-periodic axis, per axis its colours.
+void line_sweeps(const MgGeo &G, double *u, const double *f, const double *a, const double *a2, int sweeps,
+                 hipStream_t st) {
+  for (int s = 0; s < sweeps; s++)
+    for (int ax = 0; ax < G.ndim; ax++) {
+      if (G.bc[ax][0] == GMUNU_MG_PERIODIC) continue;
+      const size_t lds = 8 * (size_t)G.n[ax] * sizeof(double);
+      for (int c = 0; c < 1 << (G.ndim - 1); c++)
+        hipLaunchKernelGGL(k_mg_line, dim3(mg_line_count(G, ax, c)), dim3(kLineWave), lds, st, G, u, f, a, a2, ax,
+                           c);
+    }
+}
+
+// Dynamic LDS of a one-workgroup coarsest line solve (0: too long lines).
+size_t line_coarse_lds(const MgGeo &G) {
+  int nmax = 1;
+  for (int ax = 0; ax < G.ndim; ax++)
+    if (G.bc[ax][0] != GMUNU_MG_PERIODIC) nmax = G.n[ax] > nmax ? G.n[ax] : nmax;
+  const size_t b = (size_t)(NT / kLineWave) * 8 * nmax * sizeof(double);
+  return b <= 64 * 1024 ? b : 0;
+}
+
+// Smoothing sweeps (boundary rule inline: no ghost fill between colours):
+// line sweeps for the line smoother, else red-black.
 void sweeps_raw(const MgGeo &G, double *u, const double *f, const double *a, const double *a2, int sweeps,
                 hipStream_t st, const double *fs = nullptr, const double *as = nullptr, const double *a2s = nullptr) {
+  if (G.line) {
+    line_sweeps(G, u, f, a, a2, sweeps, st);
+    return;
+  }
   const long threads = (long)((G.n[0] + 1) / 2) * G.n[1] * G.n[2];
   for (int s = 0; s < sweeps; s++)
     for (int c = 0; c < 2; c++)
@@ -1402,6 +1677,15 @@ constexpr long kCoarseLds = 64L * 1024;
 
 void coarse_solve(gmunu_mg *m, hipStream_t st) {
   const MgGeo &G = m->geo[0];
+  if (G.line) {
+    const size_t lds = line_coarse_lds(G);
+    if (cells(G) <= 64L * NT && lds)
+      hipLaunchKernelGGL(k_mg_line_coarse, dim3(1), dim3(NT), lds, st, G, m->u[0], m->f[0], m->a[0], m->a2[0],
+                         m->d.coarse);
+    else
+      line_sweeps(G, m->u[0], m->f[0], m->a[0], m->a2[0], m->d.coarse, st);
+    return;
+  }
   if (cells(G) <= 64L * NT) {
     const long bytes = (2 + (m->a[0] ? 1 : 0) + (m->a2[0] ? 1 : 0)) * G.nt * (long)sizeof(double);
     const int lds = bytes <= kCoarseLds;
@@ -1478,7 +1762,7 @@ void bind(gmunu_mg *m, double *u, const double *f, const double *a, const double
 void split_copies(gmunu_mg *m, const double *f, const double *a, const double *a2, hipStream_t st) {
   const MgGeo &G = m->geo[m->levels - 1];
   m->sf = m->sa = m->sa2 = nullptr;
-  if (cells(G) < 32768 || G.n[0] < 16) return;
+  if (G.line || cells(G) < 32768 || G.n[0] < 16) return;
   const size_t bytes = (size_t)cells(G) * sizeof(double);
   auto get = [&](double *&p) {
     if (!p && hipMalloc(&p, bytes) == hipSuccess) m->owned.push_back(p);
@@ -1525,6 +1809,16 @@ long colour_cells(const MgGeo &G, int c) {
 // Sweeps over the 2^ndim colours: two colours per launch (k_mgv_smooth2)
 // when a row's half fits in 4 passes of a workgroup, else one per launch.
 void vsweeps(const MgGeo &G, double *u, const double *f, int sweeps, hipStream_t st) {
+  if (G.line) {
+    for (int s = 0; s < sweeps; s++)
+      for (int ax = 0; ax < G.ndim; ax++) {
+        if (G.bc[ax][0] == GMUNU_MG_PERIODIC) continue;
+        const size_t lds = 8 * (size_t)G.n[ax] * sizeof(double);
+        for (int c = 0; c < 1 << (G.ndim - 1); c++)
+          hipLaunchKernelGGL(k_mgv_line, dim3(mg_line_count(G, ax, c)), dim3(kLineWave), lds, st, G, u, f, ax, c);
+      }
+    return;
+  }
   const int ncol = 1 << G.ndim;
   const long hx0 = (G.n[0] + 1) >> 1;
   const bool paired = hx0 <= 4L * NT;
@@ -1561,6 +1855,14 @@ void vcorrect(gmunu_mg *m, int l, hipStream_t st) {
 
 void vcoarse_solve(gmunu_mg *m, hipStream_t st) {
   const MgGeo &G = m->geo[0];
+  if (G.line) {
+    const size_t lds = line_coarse_lds(G);
+    if (cells(G) <= 64L * NT && lds)
+      hipLaunchKernelGGL(k_mgv_line_coarse, dim3(1), dim3(NT), lds, st, G, m->vu[0], m->vf[0], m->d.coarse);
+    else
+      vsweeps(G, m->vu[0], m->vf[0], m->d.coarse, st);
+    return;
+  }
   if (cells(G) <= 64L * NT) {
     const long bytes = 6 * G.nt * (long)sizeof(double);
     const int lds = bytes <= kCoarseLds;

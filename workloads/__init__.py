@@ -491,6 +491,35 @@ def rotating_star_3d(n=256, half=24.0, omega=0.01, rho_c=1.28e-3, K=100.0, Gamma
     return p, prim, met
 
 
+def rotating_star_sph2d(nr=640, nth=64, rmax=30.0, omega=0.02, rho_c=1.28e-3, K=100.0, Gamma=2.0, rho_atmo=1e-10,
+                        star=None):
+    """Uniformly rotating polytropic star on an axisymmetric, equatorially
+    symmetric spherical grid (r, theta) in [0, rmax] x [0, pi/2] (the layout
+    of the paper's 2D rotating-star runs): TOV profile in isotropic
+    coordinates, v^phi = omega inside the star (coordinate angular
+    velocity, W from the TOV conformal factor), atmosphere outside, no
+    field.  Returns the grid parameters, the primitives and the TOV metric
+    (zero shift)."""
+    if star is None:
+        star = tov_isotropic(rho_c, K, Gamma)
+    p = grid(2, SPH, [nr, nth], [0.0, 0.0, 0.0], [rmax, math.pi / 2, 2 * math.pi],
+             [[REFLECT, OUTFLOW], [AXIS, REFLECT]], gamma=Gamma, rk=3, rho_atmo=rho_atmo, k_atmo=K,
+             gamma_atmo=Gamma)
+    r, th, _ = centres(p)
+    rho, psi, alpha = tov_fields(star, r)
+    inside = rho > rho_atmo
+    rho = np.maximum(rho, rho_atmo)
+    prim = np.zeros((8,) + shape(p))
+    met = np.zeros((5,) + shape(p))
+    vphi = np.where(inside, omega, 0.0)
+    W = 1.0 / np.sqrt(1.0 - psi ** 4 * (r * np.sin(th)) ** 2 * vphi ** 2)
+    prim[0] = rho
+    prim[3] = W * vphi
+    prim[4] = K * rho ** Gamma
+    met[0], met[1] = psi, alpha
+    return p, prim, met
+
+
 def magnetised_star_2d(nr=256, nth=128, rmax=20.0, rho_c=1.28e-3, K=100.0, Gamma=2.0, b_peak=1e-4,
                        rho_atmo=1e-10, star=None):
     """Static magnetised polytropic star on a frozen CFC metric in 2D
