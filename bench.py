@@ -509,15 +509,15 @@ def bench_xcfc(n=256, half=24.0, omega=0.01, sweeps=10):
     return out
 
 
-def bench_xcfc_sph(nr=640, nth=64, rmax=30.0, omega=0.02, tol=1e-6, smoother=1, sweeps=2):
+def bench_xcfc_sph(nr=640, nth=64, rmax=30.0, omega=0.02, tol=1e-6, smoother=1, sweeps=1, coarse=None):
     """The xCFC metric update (solve, then recovery on the new metric) of a
     uniformly rotating polytropic star on the layout of the paper's 2D
     rotating-star runs: spherical (r, theta) in [0, 30] x [0, pi/2] with
     640 x 64 cells, centre, polar axis and equator symmetry faces, Robin
     falloff for psi and alpha psi, X = beta = 0 at r = 30; from the flat
     metric, and again warm, to the paper's typical metric-solver tolerance
-    (1e-6).  Smoother: line relaxation (1, V(2,2)) or the paper's point
-    smoother (0; V(4,4) recommended)."""
+    (1e-6).  Smoother: line relaxation (1; V(1,1) cycles, 4 coarsest-level
+    sweeps) or the paper's point smoother (0; V(4,4) and 50 recommended)."""
     import torch
 
     import paper_2012_07322_amd as gmu
@@ -530,7 +530,7 @@ def bench_xcfc_sph(nr=640, nth=64, rmax=30.0, omega=0.02, tol=1e-6, smoother=1, 
     metd = torch.from_numpy(met).cuda()
     q = g.prim2con(prd, metd)
     base = dict(ndim=2, coord=2, n=[nr, nth, 1], xmin=[0.0, 0.0, 0.0], dx=[rmax / nr, math.pi / 2 / nth, 1.0],
-                pre=sweeps, post=sweeps, coarse=8 if smoother else 50, smoother=smoother)
+                pre=sweeps, post=sweeps, coarse=coarse or (4 if smoother else 50), smoother=smoother)
     Mv = gmu.Multigrid(dict(base, bc=[[1, 0], [1, 1], [1, 1]]))
     Mp = gmu.Multigrid(dict(base, bc=[[1, 3], [1, 1], [1, 1]], power=-1, power2=-7, offset=1.0))
     Ma = gmu.Multigrid(dict(base, bc=[[1, 3], [1, 1], [1, 1]], power=1, offset=1.0))
@@ -554,7 +554,7 @@ def bench_xcfc_sph(nr=640, nth=64, rmax=30.0, omega=0.02, tol=1e-6, smoother=1, 
     out = {"workload": f"uniformly rotating polytropic star (K=100, Gamma=2, rho_c=1.28e-3, omega={omega:g}), spherical "
                        f"{nr}x{nth} on [0,{rmax:g}]x[0,pi/2], centre/axis/equator symmetry, Robin falloff, flat "
                        f"initial metric",
-           "smoother": "line" if smoother else "point", "sweeps": sweeps,
+           "smoother": "line" if smoother else "point", "sweeps": sweeps, "coarse_sweeps": base["coarse"],
            "tolerance": tol, "ms_per_update": ms, "cycles_X_psi_alphapsi_beta": list(cyc),
            "ms_per_warm_update": ms_w, "warm_cycles": list(cyc_w),
            "psi_centre": float(m[0].max()), "alpha_centre": float(m[1].min()),

@@ -336,14 +336,16 @@ __global__ __launch_bounds__(NT) void k_mg_coarse(const MgGeo G, double *u, cons
 }
 
 // ---- Line relaxation --------------------------------------------------------
-// One wavefront per line.  The line's tridiagonal system (couplings toward
-// the lower and upper neighbour along the line, diagonal, right-hand side)
-// is built in LDS by the lanes, cell by cell, and solved by parallel cyclic
-// reduction: at stride s every row eliminates its couplings to the rows s
-// below and s above, so after ceil(log2 n) doublings each row holds one
-// unknown.  Two copies of the four arrays alternate between doublings.
+// One workgroup per line (up to kLineThreads lanes, one or more cells per
+// lane).  The line's tridiagonal system (couplings toward the lower and
+// upper neighbour along the line, diagonal, right-hand side) is built in
+// LDS by the lanes, cell by cell, and solved by parallel cyclic reduction:
+// at stride s every row eliminates its couplings to the rows s below and s
+// above, so after ceil(log2 n) doublings each row holds one unknown.  Two
+// copies of the four arrays alternate between doublings.
 
 constexpr int kLineWave = 64;
+constexpr int kLineThreads = 512;
 constexpr int kMaxLine = 1024;
 
 // Weights of the flux-form Laplacian from cell (I, J) (ghost-inclusive
@@ -385,16 +387,16 @@ __device__ __forceinline__ bool mg_line(const MgGeo &G, int a, int colour, long 
 
 // Parallel cyclic reduction of the system in sm (A: lower couplings, B:
 // diagonal, C: upper couplings, D: right-hand side, n entries each, A[0] =
-// C[n-1] = 0) by the 64 lanes of one wavefront (lane `ln`); returns the
-// copy (0 or 1) holding the decoupled rows, whose solution is D / B.  The
-// doublings are separated by workgroup barriers, so every wavefront of the
-// workgroup calls this with the same n.
-__device__ __forceinline__ int mg_pcr(double *sm, int n, int ln) {
+// C[n-1] = 0) by nl lanes (this one: ln); returns the copy (0 or 1)
+// holding the decoupled rows, whose solution is D / B.  The doublings are
+// separated by workgroup barriers, so every thread of the workgroup calls
+// this with the same n.
+__device__ __forceinline__ int mg_pcr(double *sm, int n, int ln, int nl) {
   int p = 0;
   for (int s = 1; s < n; s <<= 1) {
     const double *A = sm + p * 4 * n, *B = A + n, *C = B + n, *D = C + n;
     double *A2 = sm + (1 - p) * 4 * n, *B2 = A2 + n, *C2 = B2 + n, *D2 = C2 + n;
-    for (int m = ln; m < n; m += kLineWave) {
+    for (int m = ln; m < n; m += nl) {
       double b = B[m], d = D[m], na = 0.0, nc = 0.0;
       if (m >= s) {
         const double al = -A[m] / B[m - s];
@@ -419,18 +421,18 @@ __device__ __forceinline__ int mg_pcr(double *sm, int n, int ln) {
   return p;
 }
 
-// One Newton step of the line from cell c along axis ax by one wavefront
-// (lane ln, LDS sm of 8 n doubles; live = false: a wavefront with no line
-// that only keeps the workgroup's barriers) with the exact Jacobian with
+// One Newton step of the line from cell c along axis ax by nl lanes (this
+// one: ln; LDS sm of 8 n doubles; live = false: lanes with no line that
+// only keep the workgroup's barriers) with the exact Jacobian with
 // respect to the line's cells: the couplings along the line, on the
 // diagonal mg_L's dL/du plus, across each non-periodic boundary face of
 // the cell, the weight toward the ghost times its boundary-rule factor (the
 // ghost follows the cell); right-hand side f - L(u); u += the solution.
 __device__ __forceinline__ void mg_line_step(const MgGeo &G, double *u, const double *__restrict__ f,
                                              const double *__restrict__ a, const double *__restrict__ a2, int ax,
-                                             const int c[3], bool live, double *sm, int ln) {
+                                             const int c[3], bool live, double *sm, int ln, int nl) {
   const int n = G.n[ax];
-  for (int m = ln; live && m < n; m += kLineWave) {
+  for (int m = ln; live && m < n; m += nl) {
     int cc[3] = {c[0], c[1], c[2]};
     cc[ax] = m;
     const long o = mg_off(G, cc[0], cc[1], cc[2]);
@@ -452,22 +454,22 @@ __device__ __forceinline__ void mg_line_step(const MgGeo &G, double *u, const do
     sm[3 * n + m] = f[o] - Lu;
   }
   __syncthreads();
-  const double *R = sm + mg_pcr(sm, n, ln) * 4 * n;
-  for (int m = ln; live && m < n; m += kLineWave) {
+  const double *R = sm + mg_pcr(sm, n, ln, nl) * 4 * n;
+  for (int m = ln; live && m < n; m += nl) {
     int cc[3] = {c[0], c[1], c[2]};
     cc[ax] = m;
     u[mg_off(G, cc[0], cc[1], cc[2])] += R[3 * n + m] / R[n + m];
   }
 }
 
-// Lines of one colour along axis ax, one wavefront (workgroup) per line.
-__global__ __launch_bounds__(kLineWave) void k_mg_line(const MgGeo G, double *u, const double *__restrict__ f,
-                                                       const double *__restrict__ a, const double *__restrict__ a2,
-                                                       int ax, int colour) {
+// Lines of one colour along axis ax, one workgroup per line.
+__global__ __launch_bounds__(kLineThreads) void k_mg_line(const MgGeo G, double *u, const double *__restrict__ f,
+                                                          const double *__restrict__ a,
+                                                          const double *__restrict__ a2, int ax, int colour) {
   extern __shared__ double sm[];
   int c[3];
   if (!mg_line(G, ax, colour, blockIdx.x, c)) return;
-  mg_line_step(G, u, f, a, a2, ax, c, true, sm, threadIdx.x);
+  mg_line_step(G, u, f, a, a2, ax, c, true, sm, threadIdx.x, blockDim.x);
 }
 
 // Number of lines of colour `colour` along axis a.
@@ -480,12 +482,30 @@ __host__ __device__ __forceinline__ long mg_line_count(const MgGeo &G, int a, in
 
 // The coarsest-level solver of the line smoother: `sweeps` line sweeps by
 // one workgroup of NT threads, its wavefronts taking a colour's lines in
-// rounds (LDS: 8 n doubles per wavefront and axis), colours and axes
-// separated by barriers.
+// rounds, colours and axes separated by barriers.  Dynamic LDS: the
+// level's u, f (and the given a, a2) copied in and u copied back, then
+// 8 nmax doubles per wavefront for the line systems.
 __global__ __launch_bounds__(NT) void k_mg_line_coarse(const MgGeo G, double *u, const double *__restrict__ f,
                                                        const double *__restrict__ a, const double *__restrict__ a2,
-                                                       int sweeps) {
+                                                       int sweeps, int nmax) {
   extern __shared__ double sm[];
+  double *p = sm, *uu = p;
+  for (long e = threadIdx.x; e < G.nt; e += NT) p[e] = u[e];
+  p += G.nt;
+  for (long e = threadIdx.x; e < G.nt; e += NT) p[e] = f[e];
+  const double *ff = p, *aa = nullptr, *aa2 = nullptr;
+  p += G.nt;
+  if (a) {
+    for (long e = threadIdx.x; e < G.nt; e += NT) p[e] = a[e];
+    aa = p;
+    p += G.nt;
+  }
+  if (a2) {
+    for (long e = threadIdx.x; e < G.nt; e += NT) p[e] = a2[e];
+    aa2 = p;
+    p += G.nt;
+  }
+  __syncthreads();
   const int w = threadIdx.x / kLineWave, ln = threadIdx.x % kLineWave, nw = NT / kLineWave;
   for (int s = 0; s < sweeps; s++)
     for (int ax = 0; ax < G.ndim; ax++) {
@@ -495,11 +515,12 @@ __global__ __launch_bounds__(NT) void k_mg_line_coarse(const MgGeo G, double *u,
         for (long t0 = 0; t0 < nl; t0 += nw) {
           int c[3] = {0, 0, 0};
           const bool live = mg_line(G, ax, col, t0 + w, c);
-          mg_line_step(G, u, f, a, a2, ax, c, live, sm + (long)w * 8 * G.n[ax], ln);
+          mg_line_step(G, uu, ff, aa, aa2, ax, c, live, p + (long)w * 8 * nmax, ln, kLineWave);
           __syncthreads();
         }
       }
     }
+  for (long e = threadIdx.x; e < G.nt; e += NT) u[e] = uu[e];
 }
 
 // out = L(u) on the interior.
@@ -982,11 +1003,11 @@ __global__ __launch_bounds__(NT) void k_mgv_coarse(const MgGeo G, double *u, con
 // mirror ghost times the component's sign there -- and everything else
 // (the other components included) at its current value.
 __device__ __forceinline__ void mgv_line_step(const MgGeo &G, double *u, const double *__restrict__ f, int ax,
-                                              const int c[3], bool live, double *sm, int ln) {
+                                              const int c[3], bool live, double *sm, int ln, int nl) {
   const int n = G.n[ax];
   for (int q = 0; q < 3; q++) {
     const double kap = ax == q && q < G.ndim ? 4.0 / 3.0 : 1.0;
-    for (int m = ln; live && m < n; m += kLineWave) {
+    for (int m = ln; live && m < n; m += nl) {
       int cc[3] = {c[0], c[1], c[2]};
       cc[ax] = m;
       const long o = mg_off(G, cc[0], cc[1], cc[2]);
@@ -1010,8 +1031,8 @@ __device__ __forceinline__ void mgv_line_step(const MgGeo &G, double *u, const d
       sm[3 * n + m] = f[q * G.nt + o] - L[q];
     }
     __syncthreads();
-    const double *R = sm + mg_pcr(sm, n, ln) * 4 * n;
-    for (int m = ln; live && m < n; m += kLineWave) {
+    const double *R = sm + mg_pcr(sm, n, ln, nl) * 4 * n;
+    for (int m = ln; live && m < n; m += nl) {
       int cc[3] = {c[0], c[1], c[2]};
       cc[ax] = m;
       u[q * G.nt + mg_off(G, cc[0], cc[1], cc[2])] += R[3 * n + m] / R[n + m];
@@ -1020,17 +1041,26 @@ __device__ __forceinline__ void mgv_line_step(const MgGeo &G, double *u, const d
   }
 }
 
-__global__ __launch_bounds__(kLineWave) void k_mgv_line(const MgGeo G, double *u, const double *__restrict__ f,
-                                                        int ax, int colour) {
+__global__ __launch_bounds__(kLineThreads) void k_mgv_line(const MgGeo G, double *u, const double *__restrict__ f,
+                                                           int ax, int colour) {
   extern __shared__ double sm[];
   int c[3];
   if (!mg_line(G, ax, colour, blockIdx.x, c)) return;
-  mgv_line_step(G, u, f, ax, c, true, sm, threadIdx.x);
+  mgv_line_step(G, u, f, ax, c, true, sm, threadIdx.x, blockDim.x);
 }
 
+// Coarsest level of the vector equations (as k_mg_line_coarse): X and f
+// staged in LDS, then 8 nmax doubles per wavefront.
 __global__ __launch_bounds__(NT) void k_mgv_line_coarse(const MgGeo G, double *u, const double *__restrict__ f,
-                                                        int sweeps) {
+                                                        int sweeps, int nmax) {
   extern __shared__ double sm[];
+  const long n3 = 3 * G.nt;
+  for (long e = threadIdx.x; e < n3; e += NT) {
+    sm[e] = u[e];
+    sm[n3 + e] = f[e];
+  }
+  __syncthreads();
+  double *lines = sm + 2 * n3;
   const int w = threadIdx.x / kLineWave, ln = threadIdx.x % kLineWave, nw = NT / kLineWave;
   for (int s = 0; s < sweeps; s++)
     for (int ax = 0; ax < G.ndim; ax++) {
@@ -1040,10 +1070,11 @@ __global__ __launch_bounds__(NT) void k_mgv_line_coarse(const MgGeo G, double *u
         for (long t0 = 0; t0 < nl; t0 += nw) {
           int c[3] = {0, 0, 0};
           const bool live = mg_line(G, ax, col, t0 + w, c);
-          mgv_line_step(G, u, f, ax, c, live, sm + (long)w * 8 * G.n[ax], ln);
+          mgv_line_step(G, sm, sm + n3, ax, c, live, lines + (long)w * 8 * nmax, ln, kLineWave);
         }
       }
     }
+  for (long e = threadIdx.x; e < n3; e += NT) u[e] = sm[e];
 }
 
 __global__ __launch_bounds__(NT) void k_mgv_apply(const MgGeo G, const double *__restrict__ u,
@@ -1611,6 +1642,12 @@ void ghosts(const MgGeo &G, double *u, hipStream_t st) {
   if (gc) hipLaunchKernelGGL(k_mg_ghosts<1>, dim3(nblocks(gc)), dim3(NT), 0, st, G, u);
 }
 
+// Threads per line workgroup: a lane per cell up to kLineThreads.
+int line_threads(int n) {
+  const int t = (n + kLineWave - 1) / kLineWave * kLineWave;
+  return t < kLineThreads ? t : kLineThreads;
+}
+
 // Line sweeps: per sweep every non-periodic axis, per axis its colours.
 void line_sweeps(const MgGeo &G, double *u, const double *f, const double *a, const double *a2, int sweeps,
                  hipStream_t st) {
@@ -1619,17 +1656,23 @@ void line_sweeps(const MgGeo &G, double *u, const double *f, const double *a, co
       if (G.bc[ax][0] == GMUNU_MG_PERIODIC) continue;
       const size_t lds = 8 * (size_t)G.n[ax] * sizeof(double);
       for (int c = 0; c < 1 << (G.ndim - 1); c++)
-        hipLaunchKernelGGL(k_mg_line, dim3(mg_line_count(G, ax, c)), dim3(kLineWave), lds, st, G, u, f, a, a2, ax,
-                           c);
+        hipLaunchKernelGGL(k_mg_line, dim3(mg_line_count(G, ax, c)), dim3(line_threads(G.n[ax])), lds, st, G, u, f,
+                           a, a2, ax, c);
     }
 }
 
-// Dynamic LDS of a one-workgroup coarsest line solve (0: too long lines).
-size_t line_coarse_lds(const MgGeo &G) {
+// Longest line of a level.
+int line_nmax(const MgGeo &G) {
   int nmax = 1;
   for (int ax = 0; ax < G.ndim; ax++)
     if (G.bc[ax][0] != GMUNU_MG_PERIODIC) nmax = G.n[ax] > nmax ? G.n[ax] : nmax;
-  const size_t b = (size_t)(NT / kLineWave) * 8 * nmax * sizeof(double);
+  return nmax;
+}
+
+// Dynamic LDS of a one-workgroup coarsest line solve staging `arrays`
+// level arrays (0: does not fit).
+size_t line_coarse_lds(const MgGeo &G, int arrays) {
+  const size_t b = ((size_t)arrays * G.nt + (size_t)(NT / kLineWave) * 8 * line_nmax(G)) * sizeof(double);
   return b <= 64 * 1024 ? b : 0;
 }
 
@@ -1678,10 +1721,10 @@ constexpr long kCoarseLds = 64L * 1024;
 void coarse_solve(gmunu_mg *m, hipStream_t st) {
   const MgGeo &G = m->geo[0];
   if (G.line) {
-    const size_t lds = line_coarse_lds(G);
+    const size_t lds = line_coarse_lds(G, 2 + (m->a[0] ? 1 : 0) + (m->a2[0] ? 1 : 0));
     if (cells(G) <= 64L * NT && lds)
       hipLaunchKernelGGL(k_mg_line_coarse, dim3(1), dim3(NT), lds, st, G, m->u[0], m->f[0], m->a[0], m->a2[0],
-                         m->d.coarse);
+                         m->d.coarse, line_nmax(G));
     else
       line_sweeps(G, m->u[0], m->f[0], m->a[0], m->a2[0], m->d.coarse, st);
     return;
@@ -1815,7 +1858,8 @@ void vsweeps(const MgGeo &G, double *u, const double *f, int sweeps, hipStream_t
         if (G.bc[ax][0] == GMUNU_MG_PERIODIC) continue;
         const size_t lds = 8 * (size_t)G.n[ax] * sizeof(double);
         for (int c = 0; c < 1 << (G.ndim - 1); c++)
-          hipLaunchKernelGGL(k_mgv_line, dim3(mg_line_count(G, ax, c)), dim3(kLineWave), lds, st, G, u, f, ax, c);
+          hipLaunchKernelGGL(k_mgv_line, dim3(mg_line_count(G, ax, c)), dim3(line_threads(G.n[ax])), lds, st, G, u,
+                             f, ax, c);
       }
     return;
   }
@@ -1856,9 +1900,10 @@ void vcorrect(gmunu_mg *m, int l, hipStream_t st) {
 void vcoarse_solve(gmunu_mg *m, hipStream_t st) {
   const MgGeo &G = m->geo[0];
   if (G.line) {
-    const size_t lds = line_coarse_lds(G);
+    const size_t lds = line_coarse_lds(G, 6);
     if (cells(G) <= 64L * NT && lds)
-      hipLaunchKernelGGL(k_mgv_line_coarse, dim3(1), dim3(NT), lds, st, G, m->vu[0], m->vf[0], m->d.coarse);
+      hipLaunchKernelGGL(k_mgv_line_coarse, dim3(1), dim3(NT), lds, st, G, m->vu[0], m->vf[0], m->d.coarse,
+                         line_nmax(G));
     else
       vsweeps(G, m->vu[0], m->vf[0], m->d.coarse, st);
     return;
