@@ -346,6 +346,7 @@ __global__ __launch_bounds__(NT) void k_mg_coarse(const MgGeo G, double *u, cons
 
 constexpr int kLineWave = 64;
 constexpr int kLineThreads = 512;
+constexpr int kCoarseLineThreads = 1024;  // one-workgroup coarsest-level line solvers
 constexpr int kMaxLine = 1024;
 
 // Weights of the flux-form Laplacian from cell (I, J) (ghost-inclusive
@@ -379,9 +380,12 @@ __device__ __forceinline__ bool mg_line(const MgGeo &G, int a, int colour, long 
   const long h1 = b1 < G.ndim ? (G.n[b1] - p1 + 1) >> 1 : 1;
   const long h2 = b2 < G.ndim ? (G.n[b2] - p2 + 1) >> 1 : 1;
   if (t >= h1 * h2) return false;
-  c[a] = 0;
-  c[b1] = b1 < G.ndim ? 2 * (int)(t % h1) + p1 : 0;
-  c[b2] = b2 < G.ndim ? 2 * (int)(t / h1) + p2 : 0;
+  const int t1 = b1 < G.ndim ? 2 * (int)(t % h1) + p1 : 0;
+  const int t2 = b2 < G.ndim ? 2 * (int)(t / h1) + p2 : 0;
+  // (b1, b2) = (1, 2), (0, 2), (0, 1) for a = 0, 1, 2 (no dynamic indexing of c)
+  c[0] = a == 0 ? 0 : t1;
+  c[1] = a == 0 ? t1 : a == 1 ? 0 : t2;
+  c[2] = a == 2 ? 0 : t2;
   return true;
 }
 
@@ -433,8 +437,7 @@ __device__ __forceinline__ void mg_line_step(const MgGeo &G, double *u, const do
                                              const int c[3], bool live, double *sm, int ln, int nl) {
   const int n = G.n[ax];
   for (int m = ln; live && m < n; m += nl) {
-    int cc[3] = {c[0], c[1], c[2]};
-    cc[ax] = m;
+    const int cc[3] = {ax == 0 ? m : c[0], ax == 1 ? m : c[1], ax == 2 ? m : c[2]};
     const long o = mg_off(G, cc[0], cc[1], cc[2]);
     double dg, wm, wp;
     const double Lu = mg_L<false>(G, u, a ? a[o] : 0.0, a2 ? a2[o] : 0.0, cc[0], cc[1], cc[2], o, &dg);
@@ -456,8 +459,7 @@ __device__ __forceinline__ void mg_line_step(const MgGeo &G, double *u, const do
   __syncthreads();
   const double *R = sm + mg_pcr(sm, n, ln, nl) * 4 * n;
   for (int m = ln; live && m < n; m += nl) {
-    int cc[3] = {c[0], c[1], c[2]};
-    cc[ax] = m;
+    const int cc[3] = {ax == 0 ? m : c[0], ax == 1 ? m : c[1], ax == 2 ? m : c[2]};
     u[mg_off(G, cc[0], cc[1], cc[2])] += R[3 * n + m] / R[n + m];
   }
 }
@@ -481,32 +483,34 @@ __host__ __device__ __forceinline__ long mg_line_count(const MgGeo &G, int a, in
 }
 
 // The coarsest-level solver of the line smoother: `sweeps` line sweeps by
-// one workgroup of NT threads, its wavefronts taking a colour's lines in
-// rounds, colours and axes separated by barriers.  Dynamic LDS: the
-// level's u, f (and the given a, a2) copied in and u copied back, then
-// 8 nmax doubles per wavefront for the line systems.
-__global__ __launch_bounds__(NT) void k_mg_line_coarse(const MgGeo G, double *u, const double *__restrict__ f,
-                                                       const double *__restrict__ a, const double *__restrict__ a2,
-                                                       int sweeps, int nmax) {
+// one workgroup of kCoarseLineThreads threads, its wavefronts taking a
+// colour's lines in rounds, colours and axes separated by barriers.
+// Dynamic LDS: the level's u, f (and the given a, a2) copied in and u
+// copied back, then 8 nmax doubles per wavefront for the line systems.
+__global__ __launch_bounds__(kCoarseLineThreads) void k_mg_line_coarse(const MgGeo G, double *u,
+                                                                       const double *__restrict__ f,
+                                                                       const double *__restrict__ a,
+                                                                       const double *__restrict__ a2, int sweeps,
+                                                                       int nmax) {
   extern __shared__ double sm[];
   double *p = sm, *uu = p;
-  for (long e = threadIdx.x; e < G.nt; e += NT) p[e] = u[e];
+  for (long e = threadIdx.x; e < G.nt; e += kCoarseLineThreads) p[e] = u[e];
   p += G.nt;
-  for (long e = threadIdx.x; e < G.nt; e += NT) p[e] = f[e];
+  for (long e = threadIdx.x; e < G.nt; e += kCoarseLineThreads) p[e] = f[e];
   const double *ff = p, *aa = nullptr, *aa2 = nullptr;
   p += G.nt;
   if (a) {
-    for (long e = threadIdx.x; e < G.nt; e += NT) p[e] = a[e];
+    for (long e = threadIdx.x; e < G.nt; e += kCoarseLineThreads) p[e] = a[e];
     aa = p;
     p += G.nt;
   }
   if (a2) {
-    for (long e = threadIdx.x; e < G.nt; e += NT) p[e] = a2[e];
+    for (long e = threadIdx.x; e < G.nt; e += kCoarseLineThreads) p[e] = a2[e];
     aa2 = p;
     p += G.nt;
   }
   __syncthreads();
-  const int w = threadIdx.x / kLineWave, ln = threadIdx.x % kLineWave, nw = NT / kLineWave;
+  const int w = threadIdx.x / kLineWave, ln = threadIdx.x % kLineWave, nw = kCoarseLineThreads / kLineWave;
   for (int s = 0; s < sweeps; s++)
     for (int ax = 0; ax < G.ndim; ax++) {
       if (G.bc[ax][0] == GMUNU_MG_PERIODIC) continue;
@@ -520,7 +524,7 @@ __global__ __launch_bounds__(NT) void k_mg_line_coarse(const MgGeo G, double *u,
         }
       }
     }
-  for (long e = threadIdx.x; e < G.nt; e += NT) u[e] = uu[e];
+  for (long e = threadIdx.x; e < G.nt; e += kCoarseLineThreads) u[e] = uu[e];
 }
 
 // out = L(u) on the interior.
@@ -1008,8 +1012,7 @@ __device__ __forceinline__ void mgv_line_step(const MgGeo &G, double *u, const d
   for (int q = 0; q < 3; q++) {
     const double kap = ax == q && q < G.ndim ? 4.0 / 3.0 : 1.0;
     for (int m = ln; live && m < n; m += nl) {
-      int cc[3] = {c[0], c[1], c[2]};
-      cc[ax] = m;
+      const int cc[3] = {ax == 0 ? m : c[0], ax == 1 ? m : c[1], ax == 2 ? m : c[2]};
       const long o = mg_off(G, cc[0], cc[1], cc[2]);
       double L[3], idg[3], wm, wp;
       mgv_L(G, u, o, cc[0], cc[1], cc[2], L, idg);
@@ -1033,8 +1036,7 @@ __device__ __forceinline__ void mgv_line_step(const MgGeo &G, double *u, const d
     __syncthreads();
     const double *R = sm + mg_pcr(sm, n, ln, nl) * 4 * n;
     for (int m = ln; live && m < n; m += nl) {
-      int cc[3] = {c[0], c[1], c[2]};
-      cc[ax] = m;
+      const int cc[3] = {ax == 0 ? m : c[0], ax == 1 ? m : c[1], ax == 2 ? m : c[2]};
       u[q * G.nt + mg_off(G, cc[0], cc[1], cc[2])] += R[3 * n + m] / R[n + m];
     }
     __syncthreads();
@@ -1051,17 +1053,18 @@ __global__ __launch_bounds__(kLineThreads) void k_mgv_line(const MgGeo G, double
 
 // Coarsest level of the vector equations (as k_mg_line_coarse): X and f
 // staged in LDS, then 8 nmax doubles per wavefront.
-__global__ __launch_bounds__(NT) void k_mgv_line_coarse(const MgGeo G, double *u, const double *__restrict__ f,
-                                                        int sweeps, int nmax) {
+__global__ __launch_bounds__(kCoarseLineThreads) void k_mgv_line_coarse(const MgGeo G, double *u,
+                                                                        const double *__restrict__ f, int sweeps,
+                                                                        int nmax) {
   extern __shared__ double sm[];
   const long n3 = 3 * G.nt;
-  for (long e = threadIdx.x; e < n3; e += NT) {
+  for (long e = threadIdx.x; e < n3; e += kCoarseLineThreads) {
     sm[e] = u[e];
     sm[n3 + e] = f[e];
   }
   __syncthreads();
   double *lines = sm + 2 * n3;
-  const int w = threadIdx.x / kLineWave, ln = threadIdx.x % kLineWave, nw = NT / kLineWave;
+  const int w = threadIdx.x / kLineWave, ln = threadIdx.x % kLineWave, nw = kCoarseLineThreads / kLineWave;
   for (int s = 0; s < sweeps; s++)
     for (int ax = 0; ax < G.ndim; ax++) {
       if (G.bc[ax][0] == GMUNU_MG_PERIODIC) continue;
@@ -1074,7 +1077,7 @@ __global__ __launch_bounds__(NT) void k_mgv_line_coarse(const MgGeo G, double *u
         }
       }
     }
-  for (long e = threadIdx.x; e < n3; e += NT) u[e] = sm[e];
+  for (long e = threadIdx.x; e < n3; e += kCoarseLineThreads) u[e] = sm[e];
 }
 
 __global__ __launch_bounds__(NT) void k_mgv_apply(const MgGeo G, const double *__restrict__ u,
@@ -1672,7 +1675,8 @@ int line_nmax(const MgGeo &G) {
 // Dynamic LDS of a one-workgroup coarsest line solve staging `arrays`
 // level arrays (0: does not fit).
 size_t line_coarse_lds(const MgGeo &G, int arrays) {
-  const size_t b = ((size_t)arrays * G.nt + (size_t)(NT / kLineWave) * 8 * line_nmax(G)) * sizeof(double);
+  const size_t b =
+      ((size_t)arrays * G.nt + (size_t)(kCoarseLineThreads / kLineWave) * 8 * line_nmax(G)) * sizeof(double);
   return b <= 64 * 1024 ? b : 0;
 }
 
@@ -1723,8 +1727,8 @@ void coarse_solve(gmunu_mg *m, hipStream_t st) {
   if (G.line) {
     const size_t lds = line_coarse_lds(G, 2 + (m->a[0] ? 1 : 0) + (m->a2[0] ? 1 : 0));
     if (cells(G) <= 64L * NT && lds)
-      hipLaunchKernelGGL(k_mg_line_coarse, dim3(1), dim3(NT), lds, st, G, m->u[0], m->f[0], m->a[0], m->a2[0],
-                         m->d.coarse, line_nmax(G));
+      hipLaunchKernelGGL(k_mg_line_coarse, dim3(1), dim3(kCoarseLineThreads), lds, st, G, m->u[0], m->f[0],
+                         m->a[0], m->a2[0], m->d.coarse, line_nmax(G));
     else
       line_sweeps(G, m->u[0], m->f[0], m->a[0], m->a2[0], m->d.coarse, st);
     return;
@@ -1902,8 +1906,8 @@ void vcoarse_solve(gmunu_mg *m, hipStream_t st) {
   if (G.line) {
     const size_t lds = line_coarse_lds(G, 6);
     if (cells(G) <= 64L * NT && lds)
-      hipLaunchKernelGGL(k_mgv_line_coarse, dim3(1), dim3(NT), lds, st, G, m->vu[0], m->vf[0], m->d.coarse,
-                         line_nmax(G));
+      hipLaunchKernelGGL(k_mgv_line_coarse, dim3(1), dim3(kCoarseLineThreads), lds, st, G, m->vu[0], m->vf[0],
+                         m->d.coarse, line_nmax(G));
     else
       vsweeps(G, m->vu[0], m->vf[0], m->d.coarse, st);
     return;
