@@ -892,22 +892,6 @@ def test_line_smoother_is_block_gauss_seidel_over_lines(case):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-def vector_operator_matrix(p):
-    """The vector operator as a dense matrix over (component, interior
-    cell), column by column from the oracle's vapply on unit fields."""
-    shp = mg.shape(p)
-    nt = int(np.prod(shp))
-    inner = mg.interior(p, np.arange(nt).reshape(shp)).ravel()
-    cols = []
-    for q in range(3):
-        for k in inner:
-            e = np.zeros((3, nt))
-            e[q, k] = 1.0
-            L = mg.vapply(p, np.ascontiguousarray(e.reshape((3,) + shp)))
-            cols.append(np.concatenate([mg.interior(p, L[c]).ravel() for c in range(3)]))
-    return np.array(cols).T
-
-
 LINE_VECTOR = {
     "sph2d_eq": prob(2, SPH, (8, 6), (0, 0), (2, math.pi / 2), [[N, D], [N, N]]),
     "sph2d_shell": prob(2, SPH, (6, 8), (0.5, 0), (2.5, math.pi), [[D, D], [N, N]]),
@@ -928,7 +912,7 @@ def test_vector_line_smoother_is_block_gauss_seidel(case):
     rng = np.random.default_rng(6)
     sh = (3,) + mg.shape(p)
     X0, f = rng.standard_normal(sh), rng.standard_normal(sh)
-    A = vector_operator_matrix(p)
+    A = vector_operator_matrix(p).toarray()
     fi = np.concatenate([mg.interior(p, f[q]).ravel() for q in range(3)])
     x = np.concatenate([mg.interior(p, X0[q]).ravel() for q in range(3)])
     ref = _block_gauss_seidel(p, lambda v: fi - A @ v, lambda v: A, x, 2, ncomp=3)
