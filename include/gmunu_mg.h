@@ -15,8 +15,11 @@
  * has the Poisson equation of the cleaning (a = a2 = 0).  The vector
  * equation of the xCFC potential X and of the shift (section 2.6),
  *     L(X)^i = Lap X^i + (1/3) d_i d_j X^j = f^i,
- * is solved on Cartesian grids (second differences and the four-point mixed
- * difference of section 2.7; Newton-Gauss-Seidel over 2^ndim colours).
+ * is solved on Cartesian grids and on axisymmetric cylindrical (R, z) and
+ * spherical (r, theta) grids in orthonormal components (second differences,
+ * the four-point mixed difference of section 2.7 and the connection terms
+ * of the reference metric; Newton-Gauss-Seidel over 2^ndim colours, or line
+ * relaxation).
  *
  * Arrays: FP64 device memory, one ghost layer on each active axis, layout
  * [k][j][i] with i fastest: n[a] + 2 entries along an active axis, 1 along
@@ -95,9 +98,9 @@ int gmunu_mg_levels(const gmunu_mg *mg);
 /* Entries of one array of level l (l = levels - 1 is the finest). */
 long gmunu_mg_size(const gmunu_mg *mg, int level);
 
-/* Solve L(u) = f on the finest level in place (on a large finest level the
- * first call allocates colour-split copies of f, a and a2 that the
- * red-black sweeps read): an FAS full-multigrid cycle
+/* Solve L(u) = f on the finest level in place (with the point smoother, on
+ * a large finest level the first call allocates colour-split copies of f,
+ * a and a2 that the red-black sweeps read): an FAS full-multigrid cycle
  * from the current u first when fmg != 0, then FAS V-cycles until
  * max |f - L(u)| <= tol or max_cycles cycles were done (the FMG cycle
  * counts as one).  a and a2 may be NULL (zero); a2 needs power2 != 0
@@ -114,8 +117,9 @@ int gmunu_mg_residual_norm(gmunu_mg *mg, double *u, const double *f, const doubl
 
 /* Building blocks (finest level unless a level is given), for checking:
  * out = L(u) on the interior with u's ghosts as given; ghost fill; `sweeps`
- * red-black sweeps (on a large finest level f, a and a2 are first copied
- * into colour-split buffers of the hierarchy, as in the solve); restriction
+ * sweeps of the descriptor's smoother (red-black: on a large finest level f,
+ * a and a2 are first copied into colour-split buffers of the hierarchy, as
+ * in the solve; line relaxation), then the ghost fill; restriction
  * of level l into level l - 1 (volume-weighted mean of children); Kwak
  * prolongation of level l - 1 (ghosts as given) into level l. */
 int gmunu_mg_apply(gmunu_mg *mg, const double *u, const double *a, const double *a2, double *out, void *stream);
@@ -164,41 +168,57 @@ int gmunu_mg_cfc_solve(gmunu_mg *mpsi, gmunu_mg *malpha, const gmunu_grid_desc *
                        const double *prim, double *metric, double tol, int max_cycles, int *cycles_out,
                        void *stream);
 
-/* Vector equation L(X) = f of section 2.6 on Cartesian grids (EINVAL for
- * other coordinates or Robin faces; the descriptor's power, offset and
- * power2 are not used).  X and f: three arrays back to back (X^x, X^y, X^z); values across
- * the boundary come from each axis's rule, so ghost entries of X are not
- * read.  vapply: out = L(X) on the interior.  vsmooth: `sweeps` sweeps of
- * the 2^ndim colours, then X's ghosts filled.  vsolve: as gmunu_mg_solve
- * (per-component maximum norm); X's ghosts filled on return.  The first
- * vector call allocates the coarse levels' vector arrays. */
+/* Vector equation L(X) = f of section 2.6 on Cartesian grids, and on
+ * cylindrical and spherical grids with at most two active axes
+ * (axisymmetric: d/dphi = 0) in orthonormal components (X^R, X^z, X^phi;
+ * X^r, X^theta, X^phi).  EINVAL for Robin faces, for curvilinear grids with
+ * three active axes, and for spherical grids reaching r = 0 unless theta
+ * is active and ends at pi/2 (equatorial symmetry); the descriptor's
+ * power, offset and power2 are not used.  X and f: three arrays back to
+ * back.  Values across the boundary come from each axis's rule with
+ * per-component parity: Dirichlet faces flip every component, symmetry
+ * (Neumann) faces the normal one, and the cylindrical axis and polar axis
+ * also the phi component, the spherical centre every component; ghost
+ * entries of X are not read.  vapply: out = L(X) on the interior.
+ * vsmooth: `sweeps` sweeps of the descriptor's smoother (the 2^ndim
+ * colours, or line relaxation), then X's ghosts filled.  vsolve: as
+ * gmunu_mg_solve (per-component maximum norm); X's ghosts filled on
+ * return.  The first vector call allocates the coarse levels' vector
+ * arrays. */
 int gmunu_mg_vapply(gmunu_mg *mg, const double *X, double *out, void *stream);
 int gmunu_mg_vsmooth(gmunu_mg *mg, double *X, const double *f, int sweeps, void *stream);
 int gmunu_mg_vsolve(gmunu_mg *mg, double *X, const double *f, double tol, int max_cycles, int fmg, double *res_host,
                     int *cycles_out, void *stream);
 
-/* Section 2.6, Cartesian: A~^ij = d_i X^j + d_j X^i - (2/3) delta^ij d_k X^k
- * by centred differences (values across the boundary by the axis rules) on
- * the interior, as six arrays (xx, yy, zz, xy, xz, yz) in A6, and
- * A~_ij A~^ij in A2. */
+/* Section 2.6: A~^ij = D_i X^j + D_j X^i - (2/3) gamma^ij D_k X^k of the flat
+ * reference metric, by centred differences (values across the boundary by
+ * the vector rules) plus the connection terms in curvilinear coordinates,
+ * on the interior, in orthonormal components as six arrays (11, 22, 33,
+ * 12, 13, 23; Cartesian xx, yy, zz, xy, xz, yz) in A6, and A~_ij A~^ij in
+ * A2.  Grids as for the vector equation. */
 int gmunu_mg_xcfc_aij(gmunu_mg *mg, const double *X, double *A6, double *A2, void *stream);
 /* Source of the shift equation, 16 pi w S_i + 2 A~^ij d_j w with
- * w = alpha psi^-6 (centred gradient from w's stored ghost entries),
- * S = S~_i (three arrays), A6 as above; out: three arrays, interior. */
+ * w = alpha psi^-6 (centred gradient from w's stored ghost entries, in
+ * orthonormal components on curvilinear grids), S = S~_i (three arrays,
+ * orthonormal), A6 as above; out: three arrays, interior. */
 int gmunu_mg_xcfc_beta_rhs(gmunu_mg *mg, const double *w, const double *S, const double *A6, double *out,
                            void *stream);
 
 /* The xCFC metric solve of section 2.6 (steps 1 to 6) for a GRMHD state on a
- * Cartesian grid: X from L(X) = 8 pi S~_i (S~_i = q_{S_i}; X in/out: initial
- * guess and solution, three multigrid arrays of mvec), A~^ij from X, psi
+ * grid the vector equation accepts: X from L(X) = 8 pi S~_i (S~_i = q_{S_i},
+ * covariant, divided by the scale factor h_i on curvilinear grids to give
+ * orthonormal components; X in/out: initial guess and solution, three
+ * multigrid arrays of mvec, orthonormal), A~^ij from X, psi
  * from its equation with both terms (mpsi: p = -1, q = -7, c = 1), S~ with
  * the new psi as in gmunu_mg_cfc_solve, alpha psi (malpha: p = 1, c = 1,
  * its coefficient with the (7/8) A~_ij A~^ij psi^-8 term), then the shift
  * from L(beta) = 16 pi alpha psi^-6 S~_i + 2 A~^ij d_j(alpha psi^-6)
- * starting from the metric's shift.  psi, alpha and beta^i (metric variables
- * 0..4) are written to every cell of the GRMHD layout, ghost layers
- * extended by the boundary rules.  mvec, mpsi and malpha: hierarchies on
- * the interior grid of `hydro` (mvec Cartesian).  cycles_out (4 ints,
+ * starting from the metric's shift.  psi, alpha and the contravariant
+ * coordinate components beta^i = beta^(i) / h_i (metric variables 0..4)
+ * are written to every cell of the GRMHD layout, ghost layers extended by
+ * the boundary rules (per-component parity for the shift).  mvec, mpsi
+ * and malpha: hierarchies on the interior grid of `hydro` (mvec without
+ * Robin faces: X = beta = 0 on outer Dirichlet faces).  cycles_out (4 ints,
  * nullable): cycles of the X, psi, alpha psi and beta solves.  Scratch of
  * 17 finest arrays is allocated in mvec on the first call. */
 int gmunu_mg_xcfc_solve(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, const gmunu_grid_desc *hydro,
@@ -207,7 +227,7 @@ int gmunu_mg_xcfc_solve(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, const 
 
 /* max |L(psi - 1)| of the conformal-factor equation of section 2.6 with the
  * current metric and the state's conserved variables (U~ = q_tau + q_D;
- * with mvec and X, Cartesian, the A~_ij A~^ij psi^-7 term from X as well):
+ * with mvec and X the A~_ij A~^ij psi^-7 term from X as well):
  * the constraint residual that decides when the metric is re-solved during
  * an evolution (section 2.6, frequency of solving the metric).  mpsi: p =
  * -1, c = 1 (q = -7 with mvec).  Synchronous. */
@@ -217,7 +237,7 @@ int gmunu_mg_psi_residual(gmunu_mg *mvec, gmunu_mg *mpsi, const gmunu_grid_desc 
 /* A metric update inside a GRMHD evolution (lifting the frozen-metric
  * restriction, section 2.6 with the recovery of section 2.5): the metric
  * re-solved from the state's conserved variables -- the xCFC sequence of
- * gmunu_mg_xcfc_solve when mvec is given (X in/out, Cartesian grids), else
+ * gmunu_mg_xcfc_solve when mvec is given (X in/out), else
  * the scalar equations of gmunu_mg_cfc_solve (shift unchanged) -- then
  * gmunu_c2p of q on the new metric (q corrected where the recovery says so,
  * flags and nfatal_dev as there) and gmunu_fill_ghosts of prim.  ctx and
