@@ -8,8 +8,10 @@ d(r u)/dr = 0), levels (0: as many as the grid allows down to two cells on
 the shortest axis), pre, post, coarse (sweeps), power p, offset c and
 power2 q of L(u) = Lap(u) - a (u + c)^p - a2 (u + c)^q (a, a2 optional
 arrays).  The vector operator Lap X^i + (1/3) d_i d_j X^j of the xCFC shift
-and vector-potential equations (Cartesian grids) has its own calls
-(vapply, vsmooth, vsolve).  Arrays are numpy float64 with one ghost layer
+and vector-potential equations (Cartesian grids, and axisymmetric
+cylindrical and spherical grids in orthonormal components) has its own
+calls (vapply, vsmooth, vsolve).  Beside the paper's red-black point
+smoother, line_smooth and vline_smooth give line-relaxation sweeps.  Arrays are numpy float64 with one ghost layer
 on each active axis, shape (n2 + 2 g2, n1 + 2 g1, n0 + 2 g0); vector fields
 have a leading axis of 3.
 """
@@ -316,7 +318,9 @@ def fluid_stilde(psi, rho, wv, p, gamma):
 
 
 def xcfc_solve(pv, ps, pa, U, S, stilde, X, u_psi, u_ap, beta, tol=1e-12, max_cycles=60):
-    """The xCFC metric solve of section 2.6 on a Cartesian grid, steps 1 to 6
+    """The xCFC metric solve of section 2.6 on the grids of pv, ps, pa
+    (Cartesian, or axisymmetric cylindrical and spherical in orthonormal
+    components), steps 1 to 6
     in the paper's order, on multigrid-layout arrays:
       1. L(X)^i = 8 pi S~_i                          (vector problem pv)
       2. A~^ij from X, A2 = A~_ij A~^ij
@@ -529,7 +533,7 @@ def metric_update(hp, ppsi, palpha, q, prim, met, tol=1e-12, max_cycles=60, pvec
 def psi_residual(hp, ppsi, q, met, pvec=None, X=None):
     """max |L(psi - 1)| of the conformal-factor equation of section 2.6 with
     the metric as given (its interior) and U~ = q_tau + q_D; with pvec and X
-    (Cartesian) the A2 psi^-7 term from X."""
+    the A2 psi^-7 term from X."""
     U = _to_mg(ppsi, hp, q[4] + q[0])
     u = _to_mg(ppsi, hp, met[0] - 1.0)
     fill_ghosts(ppsi, u)

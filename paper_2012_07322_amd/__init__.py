@@ -660,7 +660,8 @@ class Multigrid:
                                      self._chk(a2, "a2", none_ok=True), int(sweeps), _stream()), "gmunu_mg_smooth")
         return u
 
-    # vector equation of xCFC (Cartesian): X, f of shape (3,) + shape()
+    # vector equation of xCFC (Cartesian, or axisymmetric cylindrical and
+    # spherical in orthonormal components): X, f of shape (3,) + shape()
     def vapply(self, X, out=None):
         out = self.empty(vector=True) if out is None else out
         _check(lib().gmunu_mg_vapply(self._h, self._chk(X, "X", vector=True), self._chk(out, "out", vector=True),
@@ -798,8 +799,9 @@ def evolve_dynamical(grid, q_n, q_s, prim, metric, mpsi, malpha, cfl, steps, eve
 
 
 def xcfc_solve(mvec, mpsi, malpha, grid_params, q, prim, metric, X, tol=1e-12, max_cycles=60):
-    """xCFC metric solve (X, psi, alpha, beta) for a GRMHD state on a
-    Cartesian grid; metric and X (mvec.empty(vector=True)) are updated in
+    """xCFC metric solve (X, psi, alpha, beta) for a GRMHD state on a grid
+    the vector equations accept (Cartesian, axisymmetric cylindrical or
+    spherical); metric and X (mvec.empty(vector=True)) are updated in
     place.  Returns the cycles of the four solves."""
     hd = make_desc(grid_params)
     cyc = (ctypes.c_int * 4)()
