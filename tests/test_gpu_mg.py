@@ -582,14 +582,15 @@ def test_metric_update_matches_the_oracle():
     assert _rel(host(prd)[L][:5], pro[L][:5]) <= 1e-10
 
 
-@pytest.mark.parametrize("kind", ["cfc_sph2d", "xcfc_cart3d"])
+@pytest.mark.parametrize("kind", ["cfc_sph2d", "cfc_sph2d_line", "xcfc_cart3d"])
 def test_evolution_with_metric_updates_matches_the_oracle(kind):
     """GRMHD steps with the metric re-solved every few steps (a pulsating TOV
-    star with the scalar CFC equations in 2D spherical coordinates; a
-    rotating star with the xCFC sequence on a Cartesian grid): state and
-    metric equal the oracle's evolution with the oracle's metric updates."""
+    star with the scalar CFC equations in 2D spherical coordinates, the GPU
+    hierarchies relaxing points or lines; a rotating star with the xCFC
+    sequence on a Cartesian grid): state and metric equal the oracle's
+    evolution with the oracle's (point-relaxation) metric updates."""
     import workloads as W
-    if kind == "cfc_sph2d":
+    if kind.startswith("cfc_sph2d"):
         hp, pr, met, q, ps, pa = _tov_state(32, 8, vpert=1e-3)
         pv, steps, every = None, 10, 5
     else:
@@ -602,7 +603,8 @@ def test_evolution_with_metric_updates_matches_the_oracle(kind):
         steps, every = 4, 2
     cfl = 0.4
     g = gmu.Grid(hp)
-    Mp, Ma = gmu.Multigrid(ps), gmu.Multigrid(pa)
+    lg = dict(smoother=gmu.MG_LINE, pre=2, post=2) if kind.endswith("_line") else {}
+    Mp, Ma = gmu.Multigrid(dict(ps, **lg)), gmu.Multigrid(dict(pa, **lg))
     Mv = gmu.Multigrid(pv) if pv else None
     Xg = Mv.empty(vector=True) if Mv else None
     qd, prd, md = dev(q), dev(pr), dev(met)
