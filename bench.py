@@ -517,7 +517,8 @@ def bench_xcfc_sph(nr=640, nth=64, rmax=30.0, omega=0.02, tol=1e-6, smoother=1, 
     falloff for psi and alpha psi, X = beta = 0 at r = 30; from the flat
     metric, and again warm, to the paper's typical metric-solver tolerance
     (1e-6).  Smoother: line relaxation (1; V(1,1) cycles, 4 coarsest-level
-    sweeps) or the paper's point smoother (0; V(4,4) and 50 recommended)."""
+    sweeps for psi and alpha psi, 2 for X and beta) or the paper's point
+    smoother (0; V(4,4) and 50 recommended)."""
     import torch
 
     import paper_2012_07322_amd as gmu
@@ -531,7 +532,8 @@ def bench_xcfc_sph(nr=640, nth=64, rmax=30.0, omega=0.02, tol=1e-6, smoother=1, 
     q = g.prim2con(prd, metd)
     base = dict(ndim=2, coord=2, n=[nr, nth, 1], xmin=[0.0, 0.0, 0.0], dx=[rmax / nr, math.pi / 2 / nth, 1.0],
                 pre=sweeps, post=sweeps, coarse=coarse or (4 if smoother else 50), smoother=smoother)
-    Mv = gmu.Multigrid(dict(base, bc=[[1, 0], [1, 1], [1, 1]]))
+    # the vector equations' coarsest level (Dirichlet at r = 30) converges in fewer line sweeps
+    Mv = gmu.Multigrid(dict(base, bc=[[1, 0], [1, 1], [1, 1]], coarse=coarse or (2 if smoother else 50)))
     Mp = gmu.Multigrid(dict(base, bc=[[1, 3], [1, 1], [1, 1]], power=-1, power2=-7, offset=1.0))
     Ma = gmu.Multigrid(dict(base, bc=[[1, 3], [1, 1], [1, 1]], power=1, offset=1.0))
     X = Mv.empty(vector=True)
@@ -554,7 +556,8 @@ def bench_xcfc_sph(nr=640, nth=64, rmax=30.0, omega=0.02, tol=1e-6, smoother=1, 
     out = {"workload": f"uniformly rotating polytropic star (K=100, Gamma=2, rho_c=1.28e-3, omega={omega:g}), spherical "
                        f"{nr}x{nth} on [0,{rmax:g}]x[0,pi/2], centre/axis/equator symmetry, Robin falloff, flat "
                        f"initial metric",
-           "smoother": "line" if smoother else "point", "sweeps": sweeps, "coarse_sweeps": base["coarse"],
+           "smoother": "line" if smoother else "point", "sweeps": sweeps,
+           "coarse_sweeps": {"vector": Mv.desc.coarse, "scalar": base["coarse"]},
            "tolerance": tol, "ms_per_update": ms, "cycles_X_psi_alphapsi_beta": list(cyc),
            "ms_per_warm_update": ms_w, "warm_cycles": list(cyc_w),
            "psi_centre": float(m[0].max()), "alpha_centre": float(m[1].min()),
