@@ -151,7 +151,8 @@ def test_multigrid_create_rejects_invalid_descriptors():
     bad = [dict(base, n=[12, 16, 1], levels=4),
            dict(base, coord=2, bc=[[1, 1], [3, 1], [1, 1]]), dict(base, bc=[[2, 0], [0, 0], [0, 0]]),
            dict(base, power=2), dict(base, coarse=0), dict(base, n=[16, 16, 2]), dict(base, ndim=4),
-           dict(base, power2=9), dict(base, n=[12, 16, 1], bc=[[2, 2], [0, 0], [0, 0]], levels=3)]
+           dict(base, power2=9), dict(base, n=[12, 16, 1], bc=[[2, 2], [0, 0], [0, 0]], levels=3),
+           dict(base, smoother=2), dict(base, n=[2048, 16, 1], dx=[1 / 2048, 1 / 16, 1], smoother=1)]
     for p in bad:
         h = ctypes.c_void_p()
         assert L.gmunu_mg_create(ctypes.byref(gmu.make_mg_desc(p)), ctypes.byref(h)) == -1, p
