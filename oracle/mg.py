@@ -49,6 +49,7 @@ class _Desc(ctypes.Structure):
         ("xmin", ctypes.c_double * 3), ("dx", ctypes.c_double * 3), ("bc", (ctypes.c_int * 2) * 3),
         ("levels", ctypes.c_int), ("pre", ctypes.c_int), ("post", ctypes.c_int), ("coarse", ctypes.c_int),
         ("power", ctypes.c_int), ("offset", ctypes.c_double), ("power2", ctypes.c_int),
+        ("smoother", ctypes.c_int),
     ]
 
 
@@ -87,7 +88,7 @@ def lib():
     return _lib
 
 
-DEFAULTS = dict(levels=0, pre=2, post=2, coarse=50, power=0, offset=0.0, power2=0)
+DEFAULTS = dict(levels=0, pre=2, post=2, coarse=50, power=0, offset=0.0, power2=0, smoother=0)
 
 
 def _coarsens(p, a, L):
@@ -122,6 +123,7 @@ def make_desc(p):
     d.pre, d.post, d.coarse, d.power = int(q["pre"]), int(q["post"]), int(q["coarse"]), int(q["power"])
     d.offset = float(q["offset"])
     d.power2 = int(q["power2"])
+    d.smoother = int(q["smoother"])
     for a in range(d.ndim):
         if not _coarsens(q, a, d.levels - 1):
             raise ValueError("grid not divisible for the requested levels (even counts on periodic axes)")

@@ -78,6 +78,7 @@ typedef struct {
   int power;         /* p */
   double offset;     /* c */
   int power2;        /* q of the optional second term a2 (u + c)^q */
+  int smoother;      /* 0: red-black points (the paper's); 1: line relaxation */
 } om_desc;
 
 /* one level of the hierarchy */
@@ -352,6 +353,15 @@ static void line_smooth(const om_desc *d, const lvl *L, double *u, const double 
   fill_ghosts(d, L, u);
 }
 
+/* The descriptor's smoother. */
+static void relax(const om_desc *d, const lvl *L, double *u, const double *f, const double *ac, const double *a2c,
+                  int sweeps) {
+  if (d->smoother)
+    line_smooth(d, L, u, f, ac, a2c, sweeps);
+  else
+    smooth(d, L, u, f, ac, a2c, sweeps);
+}
+
 /* r = f - L(u) on the interior (u's ghosts must be current). */
 static void residual(const om_desc *d, const lvl *L, const double *u, const double *f, const double *ac,
                      const double *a2c, double *r) {
@@ -490,14 +500,14 @@ static void correct(const om_desc *d, hier *H, int l) {
 
 static void vcycle(const om_desc *d, hier *H, int l) {
   if (l == 0) {
-    smooth(d, &H->L[0], H->u[0], H->f[0], H->a[0], H->a2[0], d->coarse);
+    relax(d, &H->L[0], H->u[0], H->f[0], H->a[0], H->a2[0], d->coarse);
     return;
   }
-  smooth(d, &H->L[l], H->u[l], H->f[l], H->a[l], H->a2[l], d->pre);
+  relax(d, &H->L[l], H->u[l], H->f[l], H->a[l], H->a2[l], d->pre);
   coarse_problem(d, H, l);
   vcycle(d, H, l - 1);
   correct(d, H, l);
-  smooth(d, &H->L[l], H->u[l], H->f[l], H->a[l], H->a2[l], d->post);
+  relax(d, &H->L[l], H->u[l], H->f[l], H->a[l], H->a2[l], d->post);
 }
 
 /* FAS full multigrid from the current solution: coarse problems down to
@@ -506,7 +516,7 @@ static void vcycle(const om_desc *d, hier *H, int l) {
 static void fmg(const om_desc *d, hier *H) {
   int top = d->levels - 1;
   for (int l = top; l > 0; l--) coarse_problem(d, H, l);
-  smooth(d, &H->L[0], H->u[0], H->f[0], H->a[0], H->a2[0], d->coarse);
+  relax(d, &H->L[0], H->u[0], H->f[0], H->a[0], H->a2[0], d->coarse);
   for (int l = 1; l <= top; l++) {
     correct(d, H, l);
     vcycle(d, H, l);
@@ -942,6 +952,13 @@ static void vline_smooth(const om_desc *d, const lvl *L, double *u, const double
   free(rhs);
 }
 
+static void vrelax(const om_desc *d, const lvl *L, double *u, const double *f, int sweeps) {
+  if (d->smoother)
+    vline_smooth(d, L, u, f, sweeps);
+  else
+    vsmooth(d, L, u, f, sweeps);
+}
+
 static void vresidual(const om_desc *d, const lvl *L, const double *u, const double *f, double *r) {
   for (int k = 0; k < L->n[2]; k++)
     for (int j = 0; j < L->n[1]; j++)
@@ -1008,20 +1025,20 @@ static void vcorrect(const om_desc *d, vhier *H, int l) {
 
 static void vvcycle(const om_desc *d, vhier *H, int l) {
   if (l == 0) {
-    vsmooth(d, &H->L[0], H->u[0], H->f[0], d->coarse);
+    vrelax(d, &H->L[0], H->u[0], H->f[0], d->coarse);
     return;
   }
-  vsmooth(d, &H->L[l], H->u[l], H->f[l], d->pre);
+  vrelax(d, &H->L[l], H->u[l], H->f[l], d->pre);
   vcoarse_problem(d, H, l);
   vvcycle(d, H, l - 1);
   vcorrect(d, H, l);
-  vsmooth(d, &H->L[l], H->u[l], H->f[l], d->post);
+  vrelax(d, &H->L[l], H->u[l], H->f[l], d->post);
 }
 
 static void vfmg(const om_desc *d, vhier *H) {
   int top = d->levels - 1;
   for (int l = top; l > 0; l--) vcoarse_problem(d, H, l);
-  vsmooth(d, &H->L[0], H->u[0], H->f[0], d->coarse);
+  vrelax(d, &H->L[0], H->u[0], H->f[0], d->coarse);
   for (int l = 1; l <= top; l++) {
     vcorrect(d, H, l);
     vvcycle(d, H, l);

@@ -932,3 +932,28 @@ def test_one_line_sweep_solves_a_linear_1d_problem(coord):
     mg.line_smooth(p, u, f, a, sweeps=1)
     L = mg.interior(p, mg.apply(p, u, a))
     assert np.abs(mg.interior(p, f) - L).max() <= 1e-12 * np.abs(L).max()
+
+
+def test_line_relaxation_cycles_reach_the_discrete_solution_on_anisotropic_cells():
+    """FAS cycles with line relaxation on the spherical layout of the paper's
+    2D rotating-star runs, coarsened (64 x 16 on [0, 30] x [0, pi/2]: cells
+    from r dtheta / dr = 0.05 at the centre to 26 at r = 30) reach the
+    direct sparse solution of the discrete system; each V(2,2)-cycle cuts
+    the residual by more than 5 until the rounding floor of this grid
+    (about 1e-11) is near, where point relaxation (section 2.7's smoother,
+    which the paper notes slows down on such grids) has not converged after
+    three times as many cycles."""
+    p = prob(2, SPH, (64, 16), (0.0, 0.0), (30.0, math.pi / 2), [[N, ROB], [N, N]], smoother=1)
+    x, y, _ = mg.centres(p)
+    f = np.ascontiguousarray(np.exp(-(x / 6) ** 2) * (1 + 0.5 * np.cos(y) ** 2))
+    u = np.zeros(mg.shape(p))
+    res = mg.solve(p, u, f, tol=1e-11, max_cycles=60)
+    assert res[-1] <= 1e-11
+    A = operator_matrix(p)
+    ex = spla.spsolve(A, mg.interior(p, f).ravel())
+    np.testing.assert_allclose(mg.interior(p, u).ravel(), ex, rtol=0, atol=1e-10 * np.abs(ex).max())
+    rates = np.array([res[c + 1] / res[c] for c in range(1, len(res) - 1) if res[c] > 1e-8])
+    assert len(rates) >= 5 and rates.max() < 0.2, rates
+    up = np.zeros(mg.shape(p))
+    resp = mg.solve(dict(p, smoother=0), up, f, tol=1e-11, max_cycles=3 * (len(res) - 1))
+    assert resp[-1] > 1e3 * 1e-11, resp[-1]
