@@ -836,21 +836,32 @@ def test_vector_line_sweep_parity(case):
 
 @pytest.mark.parametrize("case", sorted(SOLVES))
 def test_line_smoother_solve_reaches_the_oracle_solution(case):
-    """The line smoother changes the iteration, not the discrete solution:
-    solved to 1e-11 it matches the oracle's (point-smoother) solution."""
+    """Line-relaxation solves: the residual history equals the oracle's
+    line-relaxation cycles (to 1e-6 relative while above 1e-5), and the
+    solution equals both the oracle's line-relaxation solution and its
+    point-relaxation one (the smoother changes the iteration, not the
+    discrete solution)."""
     p, opt = SOLVES[case]
     p = dict(p, **LINE)
     f, a = solve_problem(p, opt.get("a", False))
+    fo, ao = np.ascontiguousarray(f), np.ascontiguousarray(a) if a is not None else None
     M = gmu.Multigrid(p)
     ug = torch.zeros(M.shape(), dtype=torch.float64, device="cuda")
     hg = M.solve(ug, dev(f), dev(a) if a is not None else None, tol=1e-11, max_cycles=100)
+    ul = np.zeros(mg.shape(p))
+    hl = mg.solve(p, ul, fo, ao, tol=1e-11, max_cycles=100)
     uo = np.zeros(mg.shape(p))
-    ho = mg.solve(p, uo, np.ascontiguousarray(f), np.ascontiguousarray(a) if a is not None else None, tol=1e-11,
-                  max_cycles=100)
-    note(f"  {case}: cycles line {len(hg) - 1}, oracle (points) {len(ho) - 1}")
-    assert hg[-1] <= 1e-11 and ho[-1] <= 1e-11
+    ho = mg.solve(dict(p, smoother=0), uo, fo, ao, tol=1e-11, max_cycles=100)
+    note(f"  {case}: cycles line {len(hg) - 1} (oracle {len(hl) - 1}), oracle points {len(ho) - 1}")
+    assert hg[-1] <= 1e-11 and hl[-1] <= 1e-11 and ho[-1] <= 1e-11
     scale = np.abs(mg.interior(p, uo)).max()
-    assert np.abs(mg.interior(p, host(ug)) - mg.interior(p, uo)).max() <= 1e-10 * scale
+    g = mg.interior(p, host(ug))
+    assert np.abs(g - mg.interior(p, ul)).max() <= 1e-10 * scale
+    assert np.abs(g - mg.interior(p, uo)).max() <= 1e-10 * scale
+    for x, y in zip(hg, hl):
+        if y < 1e-5:
+            break
+        assert abs(x - y) <= 1e-6 * y, (x, y)
 
 
 @pytest.mark.parametrize("case", sorted(VCASES))
@@ -862,13 +873,20 @@ def test_vector_line_smoother_solve_reaches_the_oracle_solution(case):
                                        0.5 + 0.0 * x]))
     Xg = M.empty(vector=True)
     hg = M.vsolve(Xg, dev(f), tol=1e-11, max_cycles=60)
+    Xl = np.zeros((3,) + mg.shape(p))
+    hl = mg.vsolve(p, Xl, f, tol=1e-11, max_cycles=60)
     Xo = np.zeros((3,) + mg.shape(p))
-    ho = mg.vsolve(p, Xo, f, tol=1e-11, max_cycles=60)
-    note(f"  {case}: cycles line {len(hg) - 1}, oracle (points) {len(ho) - 1}")
-    assert hg[-1] <= 1e-11 and ho[-1] <= 1e-11
+    ho = mg.vsolve(dict(p, smoother=0), Xo, f, tol=1e-11, max_cycles=60)
+    note(f"  {case}: cycles line {len(hg) - 1} (oracle {len(hl) - 1}), oracle points {len(ho) - 1}")
+    assert hg[-1] <= 1e-11 and hl[-1] <= 1e-11 and ho[-1] <= 1e-11
     g = host(Xg)
     for i in range(3):
+        assert np.abs(mg.interior(p, g[i]) - mg.interior(p, Xl[i])).max() <= 1e-10 * np.abs(Xo).max(), i
         assert np.abs(mg.interior(p, g[i]) - mg.interior(p, Xo[i])).max() <= 1e-10 * np.abs(Xo).max(), i
+    for x, y in zip(hg, hl):
+        if y < 1e-5:
+            break
+        assert abs(x - y) <= 1e-6 * y, (x, y)
 
 
 def test_line_smoother_on_the_rotating_star_grid():
