@@ -910,3 +910,35 @@ def test_line_smoother_on_the_rotating_star_grid():
     u = mg.fill_ghosts(p, host(ug).copy())
     r = mg.interior(p, f - mg.apply(p, u, a))
     assert np.abs(r).max() <= 1.1e-8
+
+
+@pytest.mark.parametrize("nr", [1024, 1000, 640])
+def test_line_sweep_parity_at_the_longest_lines(nr):
+    """Lines longer than a workgroup (512 lanes: two cells per lane) up to
+    the 1024-cell maximum, ragged (1000 cells: lanes with one and with two
+    cells, reduction strides past the last row) and the 640 cells of the
+    paper's spherical grid: two scalar and two vector line sweeps against
+    the oracle's.  Tolerance: two elimination orders differ by about eps
+    times the line systems' condition number.  The scalar equation carries
+    a mass term a (u + c), a in [50, 60], which keeps it near 1e2: 1e-12.
+    The vector lines have the 1D Laplacian's condition number, about n^2:
+    4 n^2 eps."""
+    p = prob(2, SPH, (nr, 4), (0.0, 0.0), (30.0, math.pi / 2), [[N, ROB], [N, N]], power=1, offset=1.0, **LINE)
+    M = gmu.Multigrid(p)
+    u, f, a = random_field(p, 41), random_field(p, 42), 55.0 + 5.0 * random_field(p, 43)
+    ug = dev(u)
+    M.smooth(ug, dev(f), dev(a), sweeps=2)
+    uo = mg.line_smooth(p, u.copy(), f, a, sweeps=2)
+    assert np.abs(host(ug) - uo).max() <= 1e-12 * np.abs(uo).max()
+    pv = dict(p, bc=[[N, D], [N, N], [N, N]], power=0, offset=0.0)
+    Mv = gmu.Multigrid(pv)
+    X, fv = random_field(pv, 44, True), random_field(pv, 45, True)
+    Xg = dev(X)
+    Mv.vsmooth(Xg, dev(fv), sweeps=2)
+    Xo = mg.vline_smooth(pv, X.copy(), fv, sweeps=2)
+    g = host(Xg)
+    tol = 4.0 * nr * nr * np.finfo(float).eps
+    for i in range(3):
+        d = np.abs(mg.interior(pv, g[i]) - mg.interior(pv, Xo[i])).max() / np.abs(Xo).max()
+        note(f"  n = {nr}: vector component {i} relative difference {d:.1e} (tolerance {tol:.1e})")
+        assert d <= tol, i
