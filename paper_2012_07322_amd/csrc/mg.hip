@@ -336,10 +336,13 @@ __global__ __launch_bounds__(NT) void k_mg_coarse(const MgGeo G, double *u, cons
 }
 
 // ---- Line relaxation --------------------------------------------------------
-// One workgroup per line (up to kLineThreads lanes, one or more cells per
-// lane).  The line's tridiagonal system (couplings toward the lower and
-// upper neighbour along the line, diagonal, right-hand side) is built in
-// LDS by the lanes, cell by cell, and solved by parallel cyclic reduction:
+// An alternative to the paper's point smoother for the anisotropic cells on
+// which section 2.7 notes that point smoothers converge slowly (spherical
+// polar grids).  One workgroup per line (up to kLineThreads lanes, one or
+// more cells per lane).  The line's tridiagonal system (couplings toward the
+// lower and upper neighbour along the line, diagonal, right-hand side) is
+// built in LDS by the lanes, cell by cell, and solved by parallel cyclic
+// reduction:
 // at stride s every row eliminates its couplings to the rows s below and s
 // above, so after ceil(log2 n) doublings each row holds one unknown.  Two
 // copies of the four arrays alternate between doublings.
