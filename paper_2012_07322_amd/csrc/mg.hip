@@ -342,10 +342,9 @@ __global__ __launch_bounds__(NT) void k_mg_coarse(const MgGeo G, double *u, cons
 // more cells per lane).  The line's tridiagonal system (couplings toward the
 // lower and upper neighbour along the line, diagonal, right-hand side) is
 // built in LDS by the lanes, cell by cell, and solved by parallel cyclic
-// reduction:
-// at stride s every row eliminates its couplings to the rows s below and s
-// above, so after ceil(log2 n) doublings each row holds one unknown.  Two
-// copies of the four arrays alternate between doublings.
+// reduction: at stride s every row eliminates its couplings to the rows s
+// below and s above, so after ceil(log2 n) doublings each row holds one
+// unknown.  Two copies of the four arrays alternate between doublings.
 
 constexpr int kLineWave = 64;
 constexpr int kLineThreads = 512;
