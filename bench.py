@@ -569,6 +569,81 @@ def bench_xcfc_sph(nr=640, nth=64, rmax=30.0, omega=0.02, tol=1e-6, smoother=1, 
     return out
 
 
+def bench_dynamical(n=256, half=24.0, omega=0.01, steps=100, every=50, eps=1e-3, tol=1e-6, cfl=0.4):
+    """GRMHD evolution on a metric re-solved from the evolved matter
+    (section 2.6; the Cowling approximation lifted): the rotating star of
+    the xCFC leg on the same box, its xCFC metric first solved from the TOV
+    metric (untimed), then `steps` SSPRK3 steps.  After each step the
+    conformal-factor residual is checked, and the metric is re-solved when
+    `every` steps have passed or the residual exceeds eps.  The solver
+    tolerance is 1e-6, and Delta n = 50 as in the paper's typical range.
+    The update is the xCFC solve, then the recovery on the new metric and
+    the ghost fill.  The steps, the residual checks and the updates are
+    timed separately."""
+    import torch
+
+    import paper_2012_07322_amd as gmu
+    import workloads as W
+
+    log(f"[bench] dynamical metric: rotating star on {n}^3, {steps} steps, metric every {every}")
+    hp, pr, met = W.rotating_star_3d(n, half, omega)
+    g = gmu.Grid(hp)
+    prd = torch.from_numpy(pr).cuda()
+    metd = torch.from_numpy(met).cuda()
+    del pr, met
+    g.fill_ghosts(prd)
+    q = g.prim2con(prd, metd)
+    base = dict(ndim=3, coord=0, n=[n] * 3, xmin=[-half] * 3, dx=[2.0 * half / n] * 3, bc=[[0, 0]] * 3)
+    rob = dict(base, bc=[[3, 3]] * 3)
+    Mv = gmu.Multigrid(base)
+    Mp = gmu.Multigrid(dict(rob, power=-1, power2=-7, offset=1.0))
+    Ma = gmu.Multigrid(dict(rob, power=1, offset=1.0))
+    X = Mv.empty(vector=True)
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    gmu.metric_update(g, Mp, Ma, q, prd, metd, mvec=Mv, X=X, nfatal=nf, tol=tol, max_cycles=200)
+    qs = torch.zeros_like(q)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    # warm-up of the step and residual kernels (one step of the evolution)
+    g.step(q, qs, prd, metd, cfl, 1e30, t, dt, None, nf)
+    gmu.psi_residual(g, Mp, q, metd, Mv, X)
+    torch.cuda.synchronize()
+    t_step = t_res = t_upd = 0.0
+    updates, since = [], 0
+    for s in range(1, steps + 1):
+        a0 = time.perf_counter()
+        g.step(q, qs, prd, metd, cfl, 1e30, t, dt, None, nf)
+        torch.cuda.synchronize()
+        a1 = time.perf_counter()
+        res = gmu.psi_residual(g, Mp, q, metd, Mv, X)
+        a2 = time.perf_counter()
+        t_step += a1 - a0
+        t_res += a2 - a1
+        since += 1
+        if since >= every or res > eps:
+            cyc = gmu.metric_update(g, Mp, Ma, q, prd, metd, mvec=Mv, X=X, nfatal=nf, tol=tol, max_cycles=200)
+            torch.cuda.synchronize()
+            t_upd += time.perf_counter() - a2
+            updates.append({"after_step": s, "psi_residual": res, "cycles_X_psi_alphapsi_beta": list(cyc)})
+            since = 0
+    total = t_step + t_res + t_upd
+    out = {"workload": f"uniformly rotating polytropic star (K=100, Gamma=2, rho_c=1.28e-3, omega={omega:g}), "
+                       f"Cartesian {n}^3 on [-{half:g},{half:g}]^3, xCFC metric re-solved every {every} steps or when "
+                       f"the psi residual exceeds {eps:g} (tolerance {tol:g})",
+           "steps": steps, "updates": updates, "ms_per_step": t_step / steps * 1e3,
+           "ms_per_residual_check": t_res / steps * 1e3,
+           "ms_per_metric_update": t_upd / max(len(updates), 1) * 1e3,
+           "metric_share_of_time": (t_res + t_upd) / total,
+           "cell_updates_per_s_with_metric": n ** 3 * 3 * steps / total, "nfatal": int(nf.item())}
+    log(f"[bench] dynamical metric: {out['ms_per_step']:.2f} ms/step, residual check "
+        f"{out['ms_per_residual_check']:.2f} ms, update {out['ms_per_metric_update']:.1f} ms, metric share "
+        f"{out['metric_share_of_time']:.3f}")
+    for M in (Mv, Mp, Ma):
+        M.close()
+    g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -589,6 +664,8 @@ def main():
     ap.add_argument("--serve-plain-open", type=int, default=100)
     ap.add_argument("--mg", type=int, default=256, help="multigrid grid size (0: skip)")
     ap.add_argument("--xcfc", type=int, default=256, help="xCFC metric-solve grid size (0: skip)")
+    ap.add_argument("--dynamical", type=int, default=256,
+                    help="grid size of the evolution with xCFC metric updates (0: skip)")
     ap.add_argument("--xcfc-sph", type=int, default=640,
                     help="radial cells of the spherical xCFC update (theta cells: a tenth; 0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -697,6 +774,9 @@ def main():
         torch.cuda.empty_cache()
     if args.xcfc_sph > 0:
         out["xcfc_spherical"] = bench_xcfc_sph(args.xcfc_sph, max(8, args.xcfc_sph // 10))
+        torch.cuda.empty_cache()
+    if args.dynamical > 0:
+        out["dynamical_metric"] = bench_dynamical(args.dynamical)
         torch.cuda.empty_cache()
     if args.serve_requests > 0:
         out["serving"] = bench_serve(args.serve_requests, probe=args.serve_probe, plain_n=args.serve_plain,
