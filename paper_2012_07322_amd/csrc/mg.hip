@@ -1212,12 +1212,14 @@ __global__ __launch_bounds__(NT) void k_mgv_aij(const MgGeo G, const double *__r
       A[a][b] = g[a][b] + g[b][a] - (a == b ? 2.0 / 3.0 * dv : 0.0);
       a2 += A[a][b] * A[a][b];
     }
-  A6[o] = A[0][0];
-  A6[G.nt + o] = A[1][1];
-  A6[2 * G.nt + o] = A[2][2];
-  A6[3 * G.nt + o] = A[0][1];
-  A6[4 * G.nt + o] = A[0][2];
-  A6[5 * G.nt + o] = A[1][2];
+  if (A6) {  // null: A2 alone (the residual check)
+    A6[o] = A[0][0];
+    A6[G.nt + o] = A[1][1];
+    A6[2 * G.nt + o] = A[2][2];
+    A6[3 * G.nt + o] = A[0][1];
+    A6[4 * G.nt + o] = A[0][2];
+    A6[5 * G.nt + o] = A[1][2];
+  }
   A2[o] = a2;
 }
 
@@ -2511,8 +2513,8 @@ int gmunu_mg_psi_residual(gmunu_mg *mvec, gmunu_mg *mpsi, const gmunu_grid_desc 
   const double *A2 = nullptr;
   if (mvec) {
     const MgGeo &V = mvec->geo[mvec->levels - 1];
-    double *A6 = mvec->xs + 9 * V.nt, *A2v = mvec->xs + 15 * V.nt;
-    hipLaunchKernelGGL(k_mgv_aij, dim3(nblocks(cells(V))), dim3(NT), 0, st, V, X, A6, A2v);
+    double *A2v = mvec->xs + 15 * V.nt;
+    hipLaunchKernelGGL(k_mgv_aij, dim3(nblocks(cells(V))), dim3(NT), 0, st, V, X, nullptr, A2v);
     A2 = A2v;
   }
   if (hipMemsetAsync(f, 0, (size_t)G.nt * sizeof(double), st) != hipSuccess) return GMUNU_EHIP;
