@@ -444,7 +444,7 @@ def bench_mg(n=256, half=200.0, vcycles=8, sweeps=10):
     return out
 
 
-def bench_xcfc(n=256, half=24.0, omega=0.01, sweeps=10):
+def bench_xcfc(n=256, half=24.0, omega=0.01, sweeps=10, coarse=10):
     """The xCFC metric solve of section 2.6 (steps 1 to 6: X, psi, alpha psi,
     beta) for a uniformly rotating polytropic star on a Cartesian n^3 box,
     from the flat initial guess (psi = alpha = 1, beta = X = 0) to a residual
@@ -464,7 +464,8 @@ def bench_xcfc(n=256, half=24.0, omega=0.01, sweeps=10):
     metd = torch.from_numpy(met).cuda()
     del pr
     q = g.prim2con(prd, metd)
-    base = dict(ndim=3, coord=0, n=[n] * 3, xmin=[-half] * 3, dx=[2.0 * half / n] * 3, bc=[[0, 0]] * 3)
+    base = dict(ndim=3, coord=0, n=[n] * 3, xmin=[-half] * 3, dx=[2.0 * half / n] * 3, bc=[[0, 0]] * 3,
+                coarse=coarse)
     rob = dict(base, bc=[[3, 3]] * 3)  # psi, alpha psi: u + x.grad u = 0 on the faces; X, beta: 0
     Mv = gmu.Multigrid(base)
     Mp = gmu.Multigrid(dict(rob, power=-1, power2=-7, offset=1.0))
@@ -569,7 +570,7 @@ def bench_xcfc_sph(nr=640, nth=64, rmax=30.0, omega=0.02, tol=1e-6, smoother=1, 
     return out
 
 
-def bench_dynamical(n=256, half=24.0, omega=0.01, steps=100, every=50, eps=1e-3, tol=1e-6, cfl=0.4):
+def bench_dynamical(n=256, half=24.0, omega=0.01, steps=100, every=50, eps=1e-3, tol=1e-6, cfl=0.4, coarse=10):
     """GRMHD evolution on a metric re-solved from the evolved matter
     (section 2.6; the Cowling approximation lifted): the rotating star of
     the xCFC leg on the same box, its xCFC metric first solved from the TOV
@@ -593,7 +594,8 @@ def bench_dynamical(n=256, half=24.0, omega=0.01, steps=100, every=50, eps=1e-3,
     del pr, met
     g.fill_ghosts(prd)
     q = g.prim2con(prd, metd)
-    base = dict(ndim=3, coord=0, n=[n] * 3, xmin=[-half] * 3, dx=[2.0 * half / n] * 3, bc=[[0, 0]] * 3)
+    base = dict(ndim=3, coord=0, n=[n] * 3, xmin=[-half] * 3, dx=[2.0 * half / n] * 3, bc=[[0, 0]] * 3,
+                coarse=coarse)
     rob = dict(base, bc=[[3, 3]] * 3)
     Mv = gmu.Multigrid(base)
     Mp = gmu.Multigrid(dict(rob, power=-1, power2=-7, offset=1.0))
