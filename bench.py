@@ -387,7 +387,7 @@ def bench_serve(nreq=1000, probe=300, plain_n=300, plain_open=100, concurrency=6
     }
 
 
-def bench_mg(n=256, half=200.0, vcycles=8, sweeps=10):
+def bench_mg(n=256, half=200.0, vcycles=8, sweeps=10, coarse=10):
     """The metric-solver measurement of section 4: the lapse equation of a
     static TOV star on a Cartesian n^3 box [-half, half]^3, solved from the
     flat initial guess (alpha psi = 1) with V(2,2) red-black cycles.  Times
@@ -403,6 +403,7 @@ def bench_mg(n=256, half=200.0, vcycles=8, sweeps=10):
 
     log(f"[bench] multigrid: lapse equation on {n}^3")
     p, a_np = W.lapse_equation(n, half)
+    p = dict(p, coarse=coarse)  # sweeps on the 2^3 coarsest level (one workgroup)
     M = gmu.Multigrid(p)
     a = torch.from_numpy(a_np).cuda()
     del a_np
