@@ -288,7 +288,8 @@ typedef struct gmunu_request {
   const double *prim;    /* initial primitives [8][layout of desc]; host or
                             device memory; ghost values are not used */
   const double *metric;  /* metric [5][layout], ghosts filled; host or device */
-  double t_end;          /* the solve ends when t reaches t_end ... */
+  double t_end;          /* the solve ends when t reaches t_end (>= 0; +inf:
+                            no end time, then max_steps must be > 0) ... */
   int max_steps;         /* ... or after max_steps steps (<= 0: no limit) */
   double *q_out;         /* nullable, host or device: final q [8][layout]
                             (interior cells meaningful) */
@@ -301,7 +302,9 @@ typedef struct gmunu_request {
 
 typedef struct gmunu_result {
   unsigned long long id, tag;
-  int status;     /* GMUNU_OK, GMUNU_ESTALL or GMUNU_ESTOP */
+  int status;     /* GMUNU_OK, GMUNU_ESTALL, GMUNU_ESTOP, or the GMUNU_E*
+                     code with which the batch refused this one solve at
+                     admission (the others go on) */
   int steps;      /* steps taken */
   unsigned int nfatal; /* fatal recoveries (cells x stages) during the solve */
   double t;       /* final time */
@@ -327,8 +330,9 @@ double gmunu_server_clock(void);
  * current device. */
 int gmunu_server_create(size_t hbm_bytes, int max_slots, double cfl, int steps_per_sync, gmunu_server **out);
 /* Queue a solve (non-blocking).  GMUNU_EINVAL if the descriptor is invalid
- * or asks for the limiter (solves run in a batch), or the solve can never fit
- * the arena; GMUNU_ESTOP after a worker error. */
+ * or asks for the limiter (solves run in a batch), if t_end is negative or
+ * NaN, or +inf with no step limit, or if the solve can never fit the arena;
+ * GMUNU_ESTOP after a worker error. */
 int gmunu_server_submit(gmunu_server *s, const gmunu_request *req, unsigned long long *id_out);
 /* Move up to `max` finished results into out; waits up to timeout_ms for the
  * first one if none is ready.  Returns the number moved (>= 0) or an error. */

@@ -1205,7 +1205,9 @@ double og_cfl_dt(const og_desc *d, const double *prim, const double *met, double
       }
   double dt = mx > 0.0 ? cfl / mx : t_end - t;
   if (t + dt > t_end) dt = t_end - t;
-  return dt;
+  /* at or past the end (t may land an ulp beyond t_end after the capped
+   * step): no step */
+  return dt > 0.0 ? dt : 0.0;
 }
 
 /* -------------------------------------------------------------- stepping */

@@ -666,11 +666,13 @@ __device__ __forceinline__ double block_max(double x) {
   return m;
 }
 
-// dt = cfl / max rate, capped at t_end - t (section 2.9).
+// dt = cfl / max rate, capped at t_end - t (section 2.9); 0 at or past the
+// end (the capped step may leave t an ulp beyond t_end, and a caller may pass
+// t_end < t), so that such a step changes nothing.
 __device__ __forceinline__ double dt_from_rate(double mx, double cfl, double t, double t_end) {
   double dt = mx > 0.0 ? cfl / mx : t_end - t;
   if (t + dt > t_end) dt = t_end - t;
-  return dt;
+  return dt > 0.0 ? dt : 0.0;
 }
 
 // CFL rate (section 2.9, maxsum) of interior cell number t of grid G.

@@ -208,7 +208,9 @@ struct gmunu_server {
     return true;
   }
 
-  // An idle lane takes its uploaded solves into its batch.
+  // An idle lane takes its uploaded solves into its batch.  A solve the
+  // batch rejects ends alone with the batch's error code (its slot and memory
+  // return); only a HIP error stops the server.
   bool join(Lane &L) {
     for (Req *r : L.joining) {
       gmunu_block blk;
@@ -219,8 +221,18 @@ struct gmunu_server {
       blk.metric = r->met;
       blk.flags = nullptr;
       blk.group = r->slot;
-      if (gmunu_batch_set_block(L.b, r->slot, &blk) != GMUNU_OK) return false;
-      if (gmunu_batch_set_group(L.b, r->slot, 0.0, r->r.t_end, r->r.max_steps) != GMUNU_OK) return false;
+      int rc = gmunu_batch_set_block(L.b, r->slot, &blk);
+      if (rc == GMUNU_OK) {
+        rc = gmunu_batch_set_group(L.b, r->slot, 0.0, r->r.t_end, r->r.max_steps);
+        if (rc != GMUNU_OK && gmunu_batch_clear_block(L.b, r->slot) != GMUNU_OK) return false;
+      }
+      if (rc == GMUNU_EHIP) return false;
+      if (rc != GMUNU_OK) {
+        L.give_back(r);
+        pool.release(r->off, r->bytes);
+        finish(r, rc);
+        continue;
+      }
       L.newly.push_back(r->slot);
       L.dirty = true;
       L.resident++;
@@ -457,7 +469,10 @@ int gmunu_server_submit(gmunu_server *s, const gmunu_request *req, unsigned long
   const int rc = validate_desc(req->desc);
   if (rc) return rc;
   if (req->desc.pp_limiter) return GMUNU_EINVAL;  // solves run in a batch
-  if (!(req->t_end >= 0.0) && req->max_steps <= 0) return GMUNU_EINVAL;
+  // the batch's rule for a group's end (t_end >= t = 0; NaN fails it), and
+  // some end: a finite t_end or a step limit
+  if (!(req->t_end >= 0.0)) return GMUNU_EINVAL;
+  if (std::isinf(req->t_end) && req->max_steps <= 0) return GMUNU_EINVAL;
   Req *r = new (std::nothrow) Req();
   if (!r) return GMUNU_ENOMEM;
   r->r = *req;

@@ -148,6 +148,79 @@ def test_batch_shared_dt_group_against_oracle():
                 assert np.abs(A[v] - Bq[v]).max() <= 1e-11 * den, (slot, v)
 
 
+
+def _oracle_init(p, pr, met):
+    po = pr.copy()
+    oracle.fill_ghosts(p, po)
+    q0 = oracle.prim2con(p, po, met)
+    q0, po, _, _ = oracle.c2p(p, q0, met)
+    oracle.fill_ghosts(p, po)
+    return q0, po
+
+
+def _l1_rel(p, a, b):
+    dV = oracle.interior(p, oracle.cell_volumes(p))
+    A, B = W.interior(p, a), W.interior(p, b)
+    out = []
+    for v in range(8):
+        den = (np.abs(B[v]) * dV).sum()
+        out.append((np.abs(A[v] - B[v]) * dV).sum() / den if den > 0 else np.abs(A[v]).max())
+    return np.array(out)
+
+
+def test_batch_multistep_against_oracle():
+    """Spherical and Cartesian 8^3 / 16^3 blocks inside the star, advanced by
+    the batch (a) ten steps with each block in its own group (its own dt) and
+    (b) five steps as one group sharing the minimum dt, against the oracle
+    advancing the same blocks (in (b) with the group's minimum of the oracle's
+    per-block dt each step): final times to 1e-12, volume-weighted relative L1
+    per conserved variable <= 1e-9."""
+    blocks = mixed_blocks(8, seed=5, r_range=(0.5, 5.0), box=2.5)
+    coords = {p["coord"] for p, _, _ in blocks}
+    assert coords == {W.CART, W.SPH}, coords
+    for p, pr, _ in blocks:
+        assert W.interior(p, pr)[0].min() > 1e4 * p["rho_atmo"]
+    # (a) own groups
+    B, views, _ = make_batch(blocks, list(range(len(blocks))))
+    for _ in range(10):
+        B.step(0.4)
+    torch.cuda.synchronize()
+    t, _ = B.times()
+    worst = 0.0
+    for slot, (p, pr, met) in enumerate(blocks):
+        q0, po = _oracle_init(p, pr, met)
+        steps, to, nf = oracle.evolve(p, q0, po, met, 0.4, 0.0, 1e30, 10)
+        assert steps == 10 and nf == 0
+        assert abs(t[slot] - to) <= 1e-12 * to, (slot, t[slot], to)
+        e = _l1_rel(p, views[slot][0].cpu().numpy(), q0)
+        worst = max(worst, e.max())
+        assert e.max() <= 1e-9, (slot, e)
+    note(f"  own groups, 10 steps: worst L1 rel {worst:.2e}")
+    # (b) one shared-dt group
+    B, views, _ = make_batch(blocks, [0] * len(blocks))
+    for _ in range(5):
+        B.step(0.4)
+    torch.cuda.synchronize()
+    t, _ = B.times()
+    st = [_oracle_init(p, pr, met) for p, pr, met in blocks]
+    to = 0.0
+    for _ in range(5):
+        dtg = min(oracle.cfl_dt(p, st[b][1], met, 0.4) for b, (p, _, met) in enumerate(blocks))
+        for b, (p, _, met) in enumerate(blocks):
+            q0, po = st[b]
+            qs = q0.copy()
+            for s in range(3):
+                assert oracle.rk_stage(p, s, dtg, q0, qs, po, met) == 0
+            st[b] = (qs.copy(), po)
+        to += dtg
+    assert abs(t[0] - to) <= 1e-12 * to, (t[0], to)
+    worst = 0.0
+    for b, (p, _, _) in enumerate(blocks):
+        e = _l1_rel(p, views[b][0].cpu().numpy(), st[b][0])
+        worst = max(worst, e.max())
+        assert e.max() <= 1e-9, (b, e)
+    note(f"  shared dt, 5 steps: worst L1 rel {worst:.2e}")
+
 def test_finished_group_left_untouched():
     blocks = blast_like_blocks()
     B, views, _ = make_batch(blocks, [0, 1, 2])
@@ -239,6 +312,31 @@ def test_single_grid_step_past_end_changes_nothing():
     assert float(t.item()) == t_end
     snap = [x.clone() for x in (qn, qs, prd, t)]
     for _ in range(3):
+        g.step(qn, qs, prd, metd, 0.4, t_end, t, dt)
+    torch.cuda.synchronize()
+    assert float(dt.item()) == 0.0
+    for a, b in zip(snap, (qn, qs, prd, t)):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("beyond", ["one_ulp", "caller_t_end_below_t"])
+def test_single_grid_time_beyond_end_changes_nothing(beyond):
+    """A capped final step can leave t an ulp past t_end, and a caller may pass
+    t_end < t: the next step's dt is 0 (never negative), so nothing changes."""
+    p, pr, met = W.mhd_shock_tube(64)
+    g = gmu.Grid(p)
+    prd, metd = torch.from_numpy(pr.copy()).cuda(), torch.from_numpy(met).cuda()
+    g.fill_ghosts(prd)
+    qn = g.prim2con(prd, metd)
+    g.c2p(qn, metd, prd)
+    g.fill_ghosts(prd)
+    qs = torch.zeros_like(qn)
+    t_end = 0.05
+    t0 = np.nextafter(t_end, 1.0) if beyond == "one_ulp" else 0.2
+    t = torch.full((1,), t0, dtype=torch.float64, device="cuda")
+    dt = torch.full_like(t, -1.0)
+    snap = [x.clone() for x in (qn, qs, prd, t)]
+    for _ in range(2):
         g.step(qn, qs, prd, metd, 0.4, t_end, t, dt)
     torch.cuda.synchronize()
     assert float(dt.item()) == 0.0

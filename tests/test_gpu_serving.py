@@ -122,3 +122,76 @@ def test_request_larger_than_the_arena_is_rejected():
     res = collect(S, 1)
     S.close()
     assert res[0]["status"] == 0 and res[0]["steps"] == 5
+
+
+def test_bad_request_among_good_ones():
+    """A request with no valid end (t_end NaN or negative with a step limit,
+    or +inf with none) is refused at submit; the good requests around it
+    still complete, and the server keeps taking work."""
+    S = gmu.Server(1 << 28, max_slots=4, cfl=0.4, steps_per_sync=2)
+    good = []
+    bad = [(float("nan"), 5), (-1.0, 5), (float("inf"), 0)]
+    for k, r in enumerate(mix()[:4]):
+        p, pr, met, te, ms = W.serving_problem(r, "cuda")
+        S.submit(p, pr, met, te, ms or 0, tag=k)
+        good.append(k)
+        te_bad, ms_bad = bad[k % len(bad)]
+        with pytest.raises(RuntimeError):
+            S.submit(p, pr, met, te_bad, ms_bad, tag=100 + k)
+    res = collect(S, len(good))
+    info = S.status()
+    assert info["error"] == 0
+    assert sorted(r["tag"] for r in res) == good
+    assert all(r["status"] == 0 for r in res)
+    # still taking work
+    p, pr, met, _, _ = W.serving_problem({"kind": 2, "n": 16, "seed": 3}, "cuda")
+    S.submit(p, pr, met, float("inf"), 3, tag=7)
+    res = collect(S, 1)
+    S.close()
+    assert res[0]["status"] == 0 and res[0]["steps"] == 3
+
+
+def test_served_results_against_the_oracle():
+    """One request of each kind, served in a mix, against the CPU oracle
+    advancing the same initial data: the 1D tube to t = 0.4 and the 2D and 3D
+    blasts for their 50 steps.  Volume-weighted relative L1 per conserved
+    variable <= 1e-9 (variables identically zero in the oracle must be zero),
+    identical step counts and final times to 1e-12."""
+    import oracle
+
+    reqs = [{"kind": 1, "n": 256, "seed": 21}, {"kind": 2, "n": 48, "seed": 22}, {"kind": 3, "n": 24, "seed": 23}]
+    probs = [W.serving_problem(r, "cuda") for r in reqs]
+    S = gmu.Server(1 << 30, max_slots=8, cfl=0.4, steps_per_sync=2)
+    outs = []
+    for k, (p, pr, met, te, ms) in enumerate(probs):
+        q_out = torch.empty_like(pr)
+        S.submit(p, pr, met, te, ms, q_out=q_out, tag=k)
+        outs.append(q_out)
+    res = {r["tag"]: r for r in collect(S, len(reqs))}
+    S.close()
+    for k, (p, pr, met, te, ms) in enumerate(probs):
+        r = res[k]
+        assert r["status"] == 0 and r["nfatal"] == 0
+        pro = pr.cpu().numpy().copy()
+        meto = met.cpu().numpy()
+        oracle.fill_ghosts(p, pro)
+        qo = oracle.prim2con(p, pro, meto)
+        qo, pro, _, _ = oracle.c2p(p, qo, meto)
+        oracle.fill_ghosts(p, pro)
+        steps, t_o, nf = oracle.evolve(p, qo, pro, meto, 0.4, 0.0, te, ms if ms else 100000)
+        qg = outs[k].cpu().numpy()
+        dV = oracle.interior(p, oracle.cell_volumes(p))
+        A, B = oracle.interior(p, qg), oracle.interior(p, qo)
+        e = []
+        for v in range(8):
+            den = (np.abs(B[v]) * dV).sum()
+            if den == 0.0:
+                assert np.all(A[v] == 0.0), (k, v)
+                e.append(0.0)
+            else:
+                e.append((np.abs(A[v] - B[v]) * dV).sum() / den)
+        note(f"  kind {reqs[k]['kind']} n {reqs[k]['n']}: steps served {r['steps']} oracle {steps}, "
+             f"t {r['t']:.15g} / {t_o:.15g}, L1 rel {np.array2string(np.array(e), precision=2)}")
+        assert r["steps"] == steps and nf == 0
+        assert abs(r["t"] - t_o) <= 1e-12 * max(t_o, 1e-300)
+        assert max(e) <= 1e-9
