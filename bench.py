@@ -180,7 +180,7 @@ def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True):
 
     def plain_step():
         for h, qn, qs, pr, met, tp, dtp in calls:
-            rc = L.gmunu_step(h, qn, qs, pr, met, cfl, 1e30, tp, dtp, None, None, st)
+            rc = L.gmunu_step(h, qn, qs, pr, met, None, cfl, 1e30, tp, dtp, None, None, st)
             if rc:
                 raise RuntimeError(f"gmunu_step failed ({rc})")
 

@@ -149,8 +149,20 @@ int gmunu_fill_ghosts(gmunu_ctx *ctx, double *prim, void *stream);
  * volume plus gravitational and geometric sources (section 2.1, the
  * discretised equation), from primitives whose ghosts are filled.  Ghost
  * entries of dqdt are untouched.  The positivity-preserving limiter acts on
- * a stage's Euler step and is not applied here. */
-int gmunu_rhs(gmunu_ctx *ctx, const double *prim, const double *metric, double *dqdt, void *stream);
+ * a stage's Euler step and is not applied here.
+ *
+ * kij (nullable, device): the extrinsic curvature K_ij that the energy and
+ * momentum sources of section 2.1 contain, 6 arrays [6][layout] of the
+ * covariant coordinate components (xx, xy, xz, yy, yz, zz in the grid's
+ * axis order), read on the interior cells only; the caller owns it (e.g. from
+ * its metric solver: section 2.6 approximates it by the traceless part of
+ * the conformal vector X^i).  NULL: K_ij follows from the shift by the CFC
+ * relation under maximal slicing, psi^4/(2 alpha) (D^_i beta_j + D^_j beta_i
+ * - 2/3 gamma^_ij D^_k beta^k) with the flat covariant derivative D^ of the
+ * reference metric gamma^ (not printed in the paper; zero for zero shift).
+ * GMUNU_EALIGN if kij is not 8-byte aligned. */
+int gmunu_rhs(gmunu_ctx *ctx, const double *prim, const double *metric, const double *kij, double *dqdt,
+              void *stream);
 
 /* Time step by the maxsum rule (section 2.9): dt = cfl / max over interior
  * cells of sum_axes max|lambda_a|/dx_a, capped at t_end - *t_dev, written to
@@ -167,10 +179,10 @@ int gmunu_cfl_dt(gmunu_ctx *ctx, const double *prim, const double *metric, doubl
  * also reads the base state of the neighbouring cells (q_n in stage 0, q_s
  * after): then q_out must not overlap the base, and GMUNU_EINVAL is returned
  * when it is the same pointer.  prim_out may alias prim_in.  dt is read from
- * dt_dev. */
+ * dt_dev.  kij: as in gmunu_rhs (nullable). */
 int gmunu_rk_stage(gmunu_ctx *ctx, int stage, const double *dt_dev, const double *q_n, const double *q_s,
                    double *q_out, const double *prim_in, double *prim_out, const double *metric,
-                   uint8_t *flags, unsigned int *nfatal_dev, void *stream);
+                   const double *kij, uint8_t *flags, unsigned int *nfatal_dev, void *stream);
 
 /* One full time step: dt = gmunu_cfl_dt(prim), the RK stages (q_n is
  * overwritten with q^{n+1}, q_s is scratch of the same size), prim ends
@@ -179,9 +191,10 @@ int gmunu_rk_stage(gmunu_ctx *ctx, int stage, const double *dt_dev, const double
  * computed dt is 0 and the step changes nothing (q_n, q_s, prim and flags
  * are left as they are), so a caller may issue steps past the end.  With the
  * limiter and SSPRK3 the middle stage writes a third state that the context
- * holds (allocated by gmunu_create). */
-int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, double cfl,
-               double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
+ * holds (allocated by gmunu_create).  kij: as in gmunu_rhs (nullable), the
+ * same for every stage of the step (the metric is frozen within a step). */
+int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, const double *kij,
+               double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
                void *stream);
 
 /* ------------------------------------------------------------------------

@@ -64,10 +64,10 @@ def lib():
         L.gmunu_prim2con.argtypes = [_P, _P, _P, _P, _P]
         L.gmunu_c2p.argtypes = [_P, _P, _P, _P, _P, _P, _P]
         L.gmunu_fill_ghosts.argtypes = [_P, _P, _P]
-        L.gmunu_rhs.argtypes = [_P, _P, _P, _P, _P]
+        L.gmunu_rhs.argtypes = [_P, _P, _P, _P, _P, _P]
         L.gmunu_cfl_dt.argtypes = [_P, _P, _P, D, D, _P, _P, _P]
-        L.gmunu_rk_stage.argtypes = [_P, I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
-        L.gmunu_step.argtypes = [_P, _P, _P, _P, _P, D, D, _P, _P, _P, _P, _P]
+        L.gmunu_rk_stage.argtypes = [_P, I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.gmunu_step.argtypes = [_P, _P, _P, _P, _P, _P, D, D, _P, _P, _P, _P, _P]
         L.gmunu_profile.argtypes = [_P, I, I]
         L.gmunu_profile_read.argtypes = [_P, _P, _P]
         _lib = L
@@ -168,10 +168,11 @@ class Grid:
         _check(lib().gmunu_fill_ghosts(self._h, self._chk(prim, 8, "prim"), _stream()), "gmunu_fill_ghosts")
         return prim
 
-    def rhs(self, prim, metric, out=None):
+    def rhs(self, prim, metric, out=None, kij=None):
+        """dq/dt (gmunu_rhs); kij: optional K_ij, shape (6,) + grid shape."""
         out = self.empty_state() if out is None else out
         _check(lib().gmunu_rhs(self._h, self._chk(prim, 8, "prim"), self._chk(metric, 5, "metric"),
-                               self._chk(out, 8, "dqdt"), _stream()), "gmunu_rhs")
+                               self._chk(kij, 6, "kij"), self._chk(out, 8, "dqdt"), _stream()), "gmunu_rhs")
         return out
 
     def cfl_dt(self, prim, metric, cfl, t_end=math.inf, t_dev=None, dt_dev=None):
@@ -180,13 +181,15 @@ class Grid:
                                   _ptr(t_dev, "t"), _ptr(dt_dev, "dt"), _stream()), "gmunu_cfl_dt")
         return dt_dev
 
-    def rk_stage(self, stage, dt_dev, q_n, q_s, q_out, prim_in, prim_out, metric, flags=None, nfatal=None):
+    def rk_stage(self, stage, dt_dev, q_n, q_s, q_out, prim_in, prim_out, metric, flags=None, nfatal=None,
+                 kij=None):
         fp = _ptr(flags, "flags", torch.uint8) if flags is not None else None
         npn = _ptr(nfatal, "nfatal", torch.int32) if nfatal is not None else None
         _check(lib().gmunu_rk_stage(self._h, stage, _ptr(dt_dev, "dt"), self._chk(q_n, 8, "q_n"),
                                     self._chk(q_s, 8, "q_s"), self._chk(q_out, 8, "q_out"),
                                     self._chk(prim_in, 8, "prim_in"), self._chk(prim_out, 8, "prim_out"),
-                                    self._chk(metric, 5, "metric"), fp, npn, _stream()), "gmunu_rk_stage")
+                                    self._chk(metric, 5, "metric"), self._chk(kij, 6, "kij"), fp, npn, _stream()),
+               "gmunu_rk_stage")
 
     KERNELS = ("stage", "c2p", "ghosts", "cfl", "other")
 
@@ -199,12 +202,12 @@ class Grid:
         _check(lib().gmunu_profile_read(self._h, ms, cnt), "gmunu_profile_read")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNELS)}
 
-    def step(self, q_n, q_s, prim, metric, cfl, t_end, t_dev, dt_dev, flags=None, nfatal=None):
+    def step(self, q_n, q_s, prim, metric, cfl, t_end, t_dev, dt_dev, flags=None, nfatal=None, kij=None):
         fp = _ptr(flags, "flags", torch.uint8) if flags is not None else None
         npn = _ptr(nfatal, "nfatal", torch.int32) if nfatal is not None else None
         _check(lib().gmunu_step(self._h, self._chk(q_n, 8, "q_n"), self._chk(q_s, 8, "q_s"),
-                                self._chk(prim, 8, "prim"), self._chk(metric, 5, "metric"), cfl, t_end,
-                                _ptr(t_dev, "t"), _ptr(dt_dev, "dt"), fp, npn, _stream()), "gmunu_step")
+                                self._chk(prim, 8, "prim"), self._chk(metric, 5, "metric"), self._chk(kij, 6, "kij"),
+                                cfl, t_end, _ptr(t_dev, "t"), _ptr(dt_dev, "dt"), fp, npn, _stream()), "gmunu_step")
 
 
     def run(self, prim, metric, cfl, t_end=1e30, max_steps=0, check_every=16):
@@ -223,7 +226,7 @@ class Grid:
         t = torch.zeros(1, dtype=torch.float64, device=prim.device)
         dt = torch.zeros_like(t)
         L, st = lib(), _stream()
-        args = (self._h, _ptr(qn, "q_n"), _ptr(qs, "q_s"), _ptr(prim, "prim"), self._chk(metric, 5, "metric"))
+        args = (self._h, _ptr(qn, "q_n"), _ptr(qs, "q_s"), _ptr(prim, "prim"), self._chk(metric, 5, "metric"), None)
         tp, dtp = _ptr(t, "t"), _ptr(dt, "dt")
         done = 0
         while True:

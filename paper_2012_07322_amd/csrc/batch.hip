@@ -101,7 +101,7 @@ __device__ __forceinline__ int find_entry(const int *start, int nent, int it, in
 }
 
 template <int TX, int TY, int TZ, int ND, int MODE, int REC, int R>
-__global__ __launch_bounds__(NT, 3) void k_bstage(const BlockRec *__restrict__ B, DList L,
+__global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC)>())) void k_bstage(const BlockRec *__restrict__ B, DList L,
                                                           const double *dts, double ca, double cb, int out_qn) {
   __shared__ double sF[stage_lds<TX, TY, TZ, ND, recon_halo(REC)>()];
   const int nent = L.meta[0];

@@ -79,18 +79,18 @@ __device__ __forceinline__ void xcd_tile(const Grid &G, int TX, int TY, int TZ, 
 // MODE 0: dqdt = L(prim).  MODE 1: q_out = ca q_n + cb (q_s + dt L(prim)),
 // with the positivity-preserving flux limiter when P = 1.
 // skipp (nullable): nothing is done when *skipp == 0 (a step past t_end).
+// One workgroup per tile.
 template <int TX, int TY, int TZ, int ND, int MODE, int REC, int R, int P>
-__global__ __launch_bounds__(NT, 3) void k_stage(const Grid G, const double *__restrict__ prim,
-                                                         const double *__restrict__ met, const double *qn,
-                                                         const double *qs, double *out,
-                                                         const double *__restrict__ dtp, double ca, double cb,
-                                                         const double *__restrict__ skipp) {
+__global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC)>())) void k_stage(
+    const Grid G, const double *__restrict__ prim, const double *__restrict__ met, const double *qn, const double *qs,
+    double *out, const double *__restrict__ dtp, double ca, double cb, const double *__restrict__ skipp,
+    const double *__restrict__ kij) {
   __shared__ double sF[stage_lds<TX, TY, TZ, ND, recon_halo(REC)>()];
   if (skipp && *skipp == 0.0) return;
   int bx, by, bz;
   xcd_tile(G, TX, TY, TZ, bx, by, bz);
-  stage_tile<TX, TY, TZ, ND, MODE, REC, R, P>(G, bx * TX, by * TY, bz * TZ, prim, met, qn, qs, out, dtp, ca, cb,
-                                            sF);
+  stage_tile<TX, TY, TZ, ND, MODE, REC, R, P>(G, bx * TX, by * TY, bz * TZ, prim, met, qn, qs, out, dtp, ca, cb, sF,
+                                            kij);
 }
 
 __global__ __launch_bounds__(NT) void k_c2p(const Grid G, double *q, const double *__restrict__ met, double *prim,
@@ -137,26 +137,26 @@ __global__ __launch_bounds__(NT) void k_cfl_finish(const double *part, int npart
 __global__ void k_advance(double *tp, const double *dtp) { *tp += *dtp; }
 
 template <int TX, int TY, int TZ, int ND, int MODE, int REC, int R, int P>
-void launch_stage_t(const gmunu_ctx *ctx, const double *prim, const double *met, const double *qn,
-                    const double *qs, double *out, const double *dtp, double ca, double cb, const double *skipp,
-                    hipStream_t st) {
+void launch_stage_t(const gmunu_ctx *ctx, const double *prim, const double *met, const double *kij,
+                    const double *qn, const double *qs, double *out, const double *dtp, double ca, double cb,
+                    const double *skipp, hipStream_t st) {
   const Grid &G = ctx->G;
   dim3 grid(((G.n[0] + TX - 1) / TX) * ((G.n[1] + TY - 1) / TY) * ((G.n[2] + TZ - 1) / TZ));
   hipLaunchKernelGGL((k_stage<TX, TY, TZ, ND, MODE, REC, R, P>), grid, dim3(NT), 0, st, G, prim, met, qn, qs, out,
-                     dtp, ca, cb, skipp);
+                     dtp, ca, cb, skipp, kij);
 }
 
 template <int MODE>
-void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, const double *qn,
-                  const double *qs, double *out, const double *dtp, double ca, double cb, const double *skipp,
-                  hipStream_t st) {
+void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, const double *kij,
+                  const double *qn, const double *qs, double *out, const double *dtp, double ca, double cb,
+                  const double *skipp, hipStream_t st) {
   const int rec = ctx->G.recon, lf = ctx->G.riemann == GMUNU_RIEMANN_TVDLF;
   // the limiter acts on the stage's Euler step, so the RHS alone (MODE 0) is unlimited
   const int pp = MODE == 1 && ctx->G.pp;
   switch (ctx->G.ndim * 16 + rec * 4 + lf * 2 + pp) {
 #define GM_CASE(NDIM, TX, TY, TZ, M, L, P)                                                                      \
   case NDIM * 16 + M * 4 + L * 2 + P:                                                                            \
-    launch_stage_t<TX, TY, TZ, NDIM, MODE, M, L, MODE == 1 && P>(ctx, prim, met, qn, qs, out, dtp, ca, cb,       \
+    launch_stage_t<TX, TY, TZ, NDIM, MODE, M, L, MODE == 1 && P>(ctx, prim, met, kij, qn, qs, out, dtp, ca, cb,  \
                                                                  skipp, st);                                      \
     break;
 #define GM_CASES_R(NDIM, TX, TY, TZ, M) \
@@ -170,7 +170,7 @@ void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, c
   GM_CASES_R(NDIM, TX, TY, TZ, 2)
     GM_CASES(1, 255, 1, 1)
     GM_CASES(2, 16, 15, 1)
-    GM_CASES(3, 8, 5, 5)
+    GM_CASES(3, 8, 6, 4)
 #undef GM_CASES
 #undef GM_CASES_R
 #undef GM_CASE
@@ -197,8 +197,8 @@ int launch_ghosts(gmunu_ctx *ctx, double *prim, const double *skipp, hipStream_t
 
 // One RK stage; with skipp non-null nothing is changed when *skipp == 0.
 int rk_stage_impl(gmunu_ctx *ctx, int stage, const double *dt_dev, const double *q_n, const double *q_s,
-                  double *q_out, const double *prim_in, double *prim_out, const double *metric, uint8_t *flags,
-                  unsigned int *nfatal_dev, const double *skipp, hipStream_t st) {
+                  double *q_out, const double *prim_in, double *prim_out, const double *metric, const double *kij,
+                  uint8_t *flags, unsigned int *nfatal_dev, const double *skipp, hipStream_t st) {
   const int nst = ctx->d.rk;
   double ca = 0.0, cb = 1.0;
   if (stage > 0) {
@@ -215,7 +215,7 @@ int rk_stage_impl(gmunu_ctx *ctx, int stage, const double *dt_dev, const double 
   }
   {
     ProfScope ps(ctx, st, GMUNU_K_STAGE);
-    launch_stage<1>(ctx, prim_in, metric, q_n, q_s, q_out, dt_dev, ca, cb, skipp, st);
+    launch_stage<1>(ctx, prim_in, metric, kij, q_n, q_s, q_out, dt_dev, ca, cb, skipp, st);
   }
   int rc = launch_status();
   if (rc) return rc;
@@ -311,12 +311,13 @@ int gmunu_fill_ghosts(gmunu_ctx *ctx, double *prim, void *stream) {
   return launch_ghosts(ctx, prim, nullptr, as_stream(stream));
 }
 
-int gmunu_rhs(gmunu_ctx *ctx, const double *prim, const double *metric, double *dqdt, void *stream) {
+int gmunu_rhs(gmunu_ctx *ctx, const double *prim, const double *metric, const double *kij, double *dqdt,
+              void *stream) {
   if (!ctx || !prim || !metric || !dqdt) return GMUNU_ENULL;
-  if (!aligned8(prim) || !aligned8(metric) || !aligned8(dqdt)) return GMUNU_EALIGN;
+  if (!aligned8(prim) || !aligned8(metric) || !aligned8(dqdt) || !aligned8(kij)) return GMUNU_EALIGN;
   {
     ProfScope ps(ctx, as_stream(stream), GMUNU_K_STAGE);
-    launch_stage<0>(ctx, prim, metric, nullptr, nullptr, dqdt, nullptr, 0.0, 0.0, nullptr, as_stream(stream));
+    launch_stage<0>(ctx, prim, metric, kij, nullptr, nullptr, dqdt, nullptr, 0.0, 0.0, nullptr, as_stream(stream));
   }
   return launch_status();
 }
@@ -340,20 +341,22 @@ int gmunu_cfl_dt(gmunu_ctx *ctx, const double *prim, const double *metric, doubl
 }
 
 int gmunu_rk_stage(gmunu_ctx *ctx, int stage, const double *dt_dev, const double *q_n, const double *q_s,
-                   double *q_out, const double *prim_in, double *prim_out, const double *metric, uint8_t *flags,
-                   unsigned int *nfatal_dev, void *stream) {
+                   double *q_out, const double *prim_in, double *prim_out, const double *metric, const double *kij,
+                   uint8_t *flags, unsigned int *nfatal_dev, void *stream) {
   if (!ctx || !dt_dev || !q_n || !q_out || !prim_in || !prim_out || !metric) return GMUNU_ENULL;
+  if (!aligned8(kij)) return GMUNU_EALIGN;
   if (stage > 0 && !q_s) return GMUNU_ENULL;
   if (stage < 0 || stage >= ctx->d.rk) return GMUNU_EINVAL;
   if (ctx->d.pp_limiter && q_out == (stage == 0 ? q_n : q_s)) return GMUNU_EINVAL;
-  return rk_stage_impl(ctx, stage, dt_dev, q_n, q_s, q_out, prim_in, prim_out, metric, flags, nfatal_dev, nullptr,
-                       as_stream(stream));
+  return rk_stage_impl(ctx, stage, dt_dev, q_n, q_s, q_out, prim_in, prim_out, metric, kij, flags, nfatal_dev,
+                       nullptr, as_stream(stream));
 }
 
-int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, double cfl,
-               double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
+int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, const double *kij,
+               double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
                void *stream) {
   if (!ctx || !q_n || !q_s || !prim || !metric || !t_dev || !dt_dev) return GMUNU_ENULL;
+  if (!aligned8(kij)) return GMUNU_EALIGN;
   int rc = gmunu_cfl_dt(ctx, prim, metric, cfl, t_end, t_dev, dt_dev, stream);
   if (rc) return rc;
   const int nst = ctx->d.rk;
@@ -364,8 +367,8 @@ int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const dou
   if (nst == 2) base[2] = q_n;
   if (nst == 3 && ctx->qt) base[2] = ctx->qt;
   for (int s = 0; s < nst; s++) {
-    rc = rk_stage_impl(ctx, s, dt_dev, q_n, base[s], base[s + 1], prim, prim, metric, flags, nfatal_dev, dt_dev,
-                       as_stream(stream));
+    rc = rk_stage_impl(ctx, s, dt_dev, q_n, base[s], base[s + 1], prim, prim, metric, kij, flags, nfatal_dev,
+                       dt_dev, as_stream(stream));
     if (rc) return rc;
   }
   {

@@ -46,13 +46,89 @@ __device__ __forceinline__ double pp_side(double u, double w, double fho, double
   return ((u - eps) + sgn * w * flf) / den;
 }
 
+// Where the stage kernel takes the metric from: staged in LDS with the
+// primitives (kMetLds), or read from memory by each face and cell; and
+// whether the conserved state of the RK combination is loaded at the start
+// of a tile (kPrefetchQ) or at its end.
+#ifndef GM_MET_LDS
+#define GM_MET_LDS 1
+#endif
+#ifndef GM_PREFETCH_Q
+#define GM_PREFETCH_Q 0
+#endif
+constexpr bool kMetLds = GM_MET_LDS;
+constexpr bool kPrefetchQ = GM_PREFETCH_Q;
+
+// Plus-shaped staged region of a TX x TY x TZ tile: the tile's cells and,
+// along each active axis, H cells on both sides of the tile (no edge or
+// corner cells: the face fluxes have no transverse stencil and the metric
+// derivatives are centred along one axis).  Seven boxes, each x-fastest:
+// centre (TX, TY, TZ), x-lo and x-hi (H, TY, TZ), y-lo and y-hi (TX, H, TZ),
+// z-lo and z-hi (TX, TY, H).  LDS holds NV primitives and the 5 metric
+// variables per region cell, variable-major.
+template <int TX, int TY, int TZ, int ND, int H>
+struct Plus {
+  static constexpr int HY = ND > 1 ? H : 0, HZ = ND > 2 ? H : 0;
+  static constexpr int NC = TX * TY * TZ, NXB = H * TY * TZ, NYB = TX * HY * TZ, NZB = TX * TY * HZ;
+  static constexpr int XL = NC, XH = XL + NXB, YL = XH + NXB, YH = YL + NYB, ZL = YH + NYB, ZH = ZL + NZB;
+  static constexpr int N = ZH + NZB;
+};
+
+// Tile-relative coordinates of region cell c.
+template <int TX, int TY, int TZ, int ND, int H>
+__device__ __forceinline__ void plus_cell(int c, int &x, int &y, int &z) {
+  using P = Plus<TX, TY, TZ, ND, H>;
+  if (c < P::XL) {
+    x = c % TX;
+    y = (c / TX) % TY;
+    z = c / (TX * TY);
+  } else if (c < P::YL) {
+    const bool hi = c >= P::XH;
+    const int l = c - (hi ? P::XH : P::XL);
+    x = l % H + (hi ? TX : -H);
+    y = (l / H) % TY;
+    z = l / (H * TY);
+  } else if (c < P::ZL) {
+    const bool hi = c >= P::YH;
+    const int l = c - (hi ? P::YH : P::YL);
+    x = l % TX;
+    y = (l / TX) % H + (hi ? TY : -H);
+    z = l / (TX * H);
+  } else {
+    const bool hi = c >= P::ZH;
+    const int l = c - (hi ? P::ZH : P::ZL);
+    x = l % TX;
+    y = (l / TX) % TY;
+    z = l / (TX * TY) + (hi ? TZ : -H);
+  }
+}
+
+// Region index of the cell at tile-relative position s along D, with the
+// other two coordinates of (x, y, z) inside the tile.
+template <int TX, int TY, int TZ, int ND, int H, int D>
+__device__ __forceinline__ int plus_line(int s, int x, int y, int z) {
+  using P = Plus<TX, TY, TZ, ND, H>;
+  if constexpr (D == 0) {
+    const int t = y + TY * z;
+    return s < 0 ? P::XL + (s + H) + H * t : s < TX ? s + TX * t : P::XH + (s - TX) + H * t;
+  } else if constexpr (D == 1) {
+    return s < 0 ? P::YL + x + TX * ((s + H) + H * z)
+                 : s < TY ? x + TX * (s + TY * z) : P::YH + x + TX * ((s - TY) + H * z);
+  } else {
+    return s < 0 ? P::ZL + x + TX * (y + TY * (s + H))
+                 : s < TZ ? x + TX * (y + TY * s) : P::ZH + x + TX * (y + TY * (s - TZ));
+  }
+}
+
 // Face flux times face factor through the lower face (along D) of cell
 // (i,j,k): reconstruction REC from the cells across the face (MC from four
 // cells, halo H = 2; MP5 or PPM from six, H = 3), metric as the mean of the
 // two adjacent centres, HLLE (R = 0) or TVDLF (R = 1).  The stencil comes
-// from the workgroup's staged region S (RC cells per variable, prim
-// variables 0-7, metric 8-12): r0 is the region index of the cell H below
-// the face, rs the region stride along D.
+// from the workgroup's staged region S (NP cells per variable, primitive
+// variables 0-7): ix[m], m = 0 .. 2H-1, is the region index of the cell
+// H - m below the face (ix[H-1], ix[H] are the two adjacent cells, whose
+// metric (psi, alpha, beta^1..3) is ma, mb).  nonflat is set when the two
+// adjacent cells differ in psi or alpha or either has a non-zero shift.
 //
 // P = 1 applies the positivity-preserving limiter (section 2.4): the flux is
 // blended with the first-order Lax-Friedrichs flux of the two adjacent cell
@@ -60,31 +136,29 @@ __device__ __forceinline__ double pp_side(double u, double w, double fho, double
 // both adjacent interior cells above eps (ghost cells are not advanced and do
 // not take part).
 template <int D, int REC, int R, int P = 0>
-__device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC, int r0, int rs, int i, int j,
-                                          int k, double *Fo, const PPBase &pb = PPBase{nullptr, 0.0}) {
+__device__ __forceinline__ void face_flux(const Grid &G, const double *S, int NP, const int *ix, const double *ma,
+                                          const double *mb, int i, int j, int k, double *Fo, bool &nonflat,
+                                          const PPBase &pb = PPBase{nullptr, 0.0}) {
   constexpr int H = recon_halo(REC);
   const int cd = (D == 0 ? i : D == 1 ? j : k) + G.g[D];
   // zero-area faces (r = 0, theta = 0 or pi) are evaluated like any other
   // and their flux replaced by 0 at the end; no load-dependent branch here
   const double fa = G.geo.fa[D][cd];
-  // the two cells adjacent to the face
-  const int r1 = r0 + (H - 1) * rs, r2 = r1 + rs;
+  const int r1 = ix[H - 1], r2 = ix[H];
   double pl[NV], pr[NV];
   if constexpr (REC == GMUNU_RECON_MC) {
-    const int r3 = r2 + rs;
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-      const double *Sv = S + v * RC;
-      const double a = Sv[r0], b = Sv[r1], e = Sv[r2], f = Sv[r3];
+      const double *Sv = S + v * NP;
+      const double a = Sv[ix[0]], b = Sv[r1], e = Sv[r2], f = Sv[ix[3]];
       pl[v] = b + 0.5 * mc_slope(a, b, e);
       pr[v] = e - 0.5 * mc_slope(b, e, f);
     }
   } else {
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-      const double *Sv = S + v * RC;
-      const double u0 = Sv[r0], u1 = Sv[r0 + rs], u2 = Sv[r1], u3 = Sv[r2], u4 = Sv[r2 + rs],
-                   u5 = Sv[r2 + 2 * rs];
+      const double *Sv = S + v * NP;
+      const double u0 = Sv[ix[0]], u1 = Sv[ix[1]], u2 = Sv[ix[2]], u3 = Sv[ix[3]], u4 = Sv[ix[4]], u5 = Sv[ix[5]];
       if constexpr (REC == GMUNU_RECON_MP5) {
         pl[v] = mp5_face(u0, u1, u2, u3, u4);
         pr[v] = mp5_face(u5, u4, u3, u2, u1);
@@ -98,17 +172,21 @@ __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC
     if (!(pl[0] > 0.0 && pl[4] > 0.0 && pr[0] > 0.0 && pr[4] > 0.0)) {
 #pragma unroll
       for (int v = 0; v < NV; v++) {
-        pl[v] = S[v * RC + r1];
-        pr[v] = S[v * RC + r2];
+        pl[v] = S[v * NP + r1];
+        pr[v] = S[v * NP + r2];
       }
     }
   }
-  const double *Sm = S + NV * RC;
-  const double psi = 0.5 * (Sm[r1] + Sm[r2]);
-  const double alpha = 0.5 * (Sm[RC + r1] + Sm[RC + r2]);
+  const double psi = 0.5 * (ma[0] + mb[0]);
+  const double alpha = 0.5 * (ma[1] + mb[1]);
   double beta[3];
+  bool shift = false;
 #pragma unroll
-  for (int a = 0; a < 3; a++) beta[a] = 0.5 * (Sm[(2 + a) * RC + r1] + Sm[(2 + a) * RC + r2]);
+  for (int a = 0; a < 3; a++) {
+    beta[a] = 0.5 * (ma[2 + a] + mb[2 + a]);
+    shift = shift || ma[2 + a] != 0.0 || mb[2 + a] != 0.0;
+  }
+  nonflat = nonflat || shift || ma[0] != mb[0] || ma[1] != mb[1];
   double g1 = 1.0, g2 = 1.0;
   if (G.coord != CART) {
     const double r2c = (D == 0) ? G.geo.r2f[i + G.g[0]] : G.geo.r2c[i + G.g[0]];
@@ -118,27 +196,37 @@ __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC
   const double psi2 = psi * psi, psi4 = psi2 * psi2, psi6 = psi4 * psi2;
   const double gD = D == 0 ? 1.0 : D == 1 ? g1 : g2;
   const double gud = rcp(psi4 * gD);
+  // both sides share the face metric, so the densitising factor psi^6 of U
+  // and F is taken out of the two states and applied once to the flux,
+  // together with the face factor
+  const double fs = fa * psi6;
   double UL[NV], FL[NV], UR[NV], FR[NV], lmL, lpL, lmR, lpR;
-  state_flux<D>(G.gam, G.gfac, pl, psi4, psi6, alpha, beta, g1, g2, gud, UL, FL, lmL, lpL);
-  state_flux<D>(G.gam, G.gfac, pr, psi4, psi6, alpha, beta, g1, g2, gud, UR, FR, lmR, lpR);
+  state_flux<D>(G.gam, G.gfac, pl, psi4, 1.0, alpha, beta, g1, g2, gud, UL, FL, lmL, lpL);
+  state_flux<D>(G.gam, G.gfac, pr, psi4, 1.0, alpha, beta, g1, g2, gud, UR, FR, lmR, lpR);
   if constexpr (R == GMUNU_RIEMANN_TVDLF) {
     // local Lax-Friedrichs: the largest speed magnitude of both states
     const double c = fmax(fmax(fabs(lmL), fabs(lpL)), fmax(fabs(lmR), fabs(lpR)));
+    const double h = 0.5 * fs, hc = h * c;
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-      const double f = (0.5 * (FL[v] + FR[v]) - 0.5 * c * (UR[v] - UL[v])) * fa;
+      const double f = h * (FL[v] + FR[v]) - hc * (UR[v] - UL[v]);
       Fo[v] = fa == 0.0 ? 0.0 : f;
     }
   } else {
+    // HLLE as three weights: F = cL F_L + cR F_R + cU (U_R - U_L), with
+    // cL = ap/(ap-am), cR = -am/(ap-am), cU = ap am/(ap-am); the mean of the
+    // two fluxes when both speed bounds vanish
     const double ap = fmax(0.0, fmax(lpL, lpR));
     const double am = fmin(0.0, fmin(lmL, lmR));
     const double den = ap - am;
     const bool avg = den < kTiny;
-    const double s = fa * rcp(avg ? 1.0 : den);
+    const double w = fs * rcp(avg ? 1.0 : den);
+    const double cL = avg ? 0.5 * fs : ap * w;
+    const double cR = avg ? 0.5 * fs : -am * w;
+    const double cU = avg ? 0.0 : ap * am * w;
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-      const double f =
-          avg ? 0.5 * (FL[v] + FR[v]) * fa : (ap * FL[v] - am * FR[v] + ap * am * (UR[v] - UL[v])) * s;
+      const double f = cL * FL[v] + cR * FR[v] + cU * (UR[v] - UL[v]);
       Fo[v] = fa == 0.0 ? 0.0 : f;
     }
   }
@@ -148,8 +236,8 @@ __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC
     double p0[NV], p1[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-      p0[v] = S[v * RC + r1];
-      p1[v] = S[v * RC + r2];
+      p0[v] = S[v * NP + r1];
+      p1[v] = S[v * NP + r2];
     }
     double U0[NV], F0[NV], U1[NV], F1[NV], lm0, lp0, lm1, lp1;
     state_flux<D>(G.gam, G.gfac, p0, psi4, psi6, alpha, beta, g1, g2, gud, U0, F0, lm0, lp0);
@@ -181,33 +269,35 @@ __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int RC
 
 // Gravitational sources (section 2.1) with centred metric derivatives, and
 // geometric sources <Gamma^l_ik> (f_S_l)^k with cell-centre fluxes
-// (Appendix A), added into s[].
-__device__ __forceinline__ void cell_sources(const Grid &G, const double *__restrict__ pb,
-                                             const double *__restrict__ mb, int i, int j, int k, unsigned rel,
-                                             double *s) {
-  const unsigned oc = rel * 8u;
-  const double psi = ld(mb, G.nv, 0, oc), alpha = ld(mb, G.nv, 1, oc);
+// (Appendix A), added into s[].  pr: the cell's primitives; m(v, a, o): the
+// metric variable v at the cell (a < 0) or at its neighbour o = -1 / +1
+// along axis a.  flat: the caller knows every metric derivative of the cell
+// is 0 and its shift is 0, so the gravitational sources vanish.  kij
+// (nullable): the extrinsic curvature K_ij of the cell (6 components xx, xy,
+// xz, yy, yz, zz, covariant); when null it follows from the shift by the CFC
+// relation under maximal slicing.
+template <typename MetFn>
+__device__ __forceinline__ void cell_sources(const Grid &G, const double *pr, MetFn m, bool flat, const double *kij,
+                                             int i, int j, double *s) {
+  const bool geom = G.coord != CART;
+  if (flat && !geom) return;
+  const double psi = m(0, -1, 0), alpha = m(1, -1, 0);
   double beta[3];
 #pragma unroll
-  for (int a = 0; a < 3; a++) beta[a] = ld(mb, G.nv, 2 + a, oc);
+  for (int a = 0; a < 3; a++) beta[a] = m(2 + a, -1, 0);
   double dpsi[3] = {0, 0, 0}, dal[3] = {0, 0, 0}, db[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  bool grav = (beta[0] != 0.0) || (beta[1] != 0.0) || (beta[2] != 0.0);
+  bool grav = !flat;
+  if (grav) {
 #pragma unroll
-  for (int a = 0; a < 3; a++) {
-    if (a < G.ndim) {
-      const unsigned op = oc + (unsigned)G.s[a] * 8u, om = oc - (unsigned)G.s[a] * 8u;
-      dpsi[a] = (ld(mb, G.nv, 0, op) - ld(mb, G.nv, 0, om)) * G.i2dx[a];
-      dal[a] = (ld(mb, G.nv, 1, op) - ld(mb, G.nv, 1, om)) * G.i2dx[a];
+    for (int a = 0; a < 3; a++) {
+      if (a < G.ndim) {
+        dpsi[a] = (m(0, a, 1) - m(0, a, -1)) * G.i2dx[a];
+        dal[a] = (m(1, a, 1) - m(1, a, -1)) * G.i2dx[a];
 #pragma unroll
-      for (int m = 0; m < 3; m++) db[a][m] = (ld(mb, G.nv, 2 + m, op) - ld(mb, G.nv, 2 + m, om)) * G.i2dx[a];
-      grav = grav || dpsi[a] != 0.0 || dal[a] != 0.0 || db[a][0] != 0.0 || db[a][1] != 0.0 || db[a][2] != 0.0;
+        for (int c = 0; c < 3; c++) db[a][c] = (m(2 + c, a, 1) - m(2 + c, a, -1)) * G.i2dx[a];
+      }
     }
   }
-  const bool geom = G.coord != CART;
-  if (!grav && !geom) return;
-  double pr[NV];
-#pragma unroll
-  for (int v = 0; v < NV; v++) pr[v] = ld(pb, G.nv, v, oc);
 
   double g1 = 1.0, g2 = 1.0;
   if (geom) ref_diag(G.coord, G.geo.r2c[i + G.g[0]], G.geo.s2c[j + G.g[1]], g1, g2);
@@ -248,9 +338,9 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
     for (int a = 0; a < 3; a++) {
       T0[a] = rhohs * u0 * ui[a] + ps * beta[a] * ia2 - b0 * bi[a];
 #pragma unroll
-      for (int m = 0; m < 3; m++)
-        T[a][m] = rhohs * ui[a] * ui[m] + ps * ((a == m ? rcp(gd[a]) : 0.0) - beta[a] * beta[m] * ia2) -
-                  bi[a] * bi[m];
+      for (int c = 0; c < 3; c++)
+        T[a][c] = rhohs * ui[a] * ui[c] + ps * ((a == c ? rcp(gd[a]) : 0.0) - beta[a] * beta[c] * ia2) -
+                  bi[a] * bi[c];
     }
     // covariant derivative of the shift with point Christoffel symbols
     double Gm[3][3][3];
@@ -259,7 +349,7 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
 #pragma unroll
       for (int b = 0; b < 3; b++)
 #pragma unroll
-        for (int m = 0; m < 3; m++) Gm[a][b][m] = 0.0;
+        for (int c = 0; c < 3; c++) Gm[a][b][c] = 0.0;
     if (G.coord == CYL) {
       const double R = G.geo.xc0[i + G.g[0]];
       Gm[0][2][2] = -R;
@@ -278,25 +368,34 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
-      for (int m = 0; m < 3; m++) nb[a][m] = db[a][m] + Gm[m][a][0] * beta[0] + Gm[m][a][1] * beta[1] + Gm[m][a][2] * beta[2];
-    const double divb = nb[0][0] + nb[1][1] + nb[2][2];
+      for (int c = 0; c < 3; c++)
+        nb[a][c] = db[a][c] + Gm[c][a][0] * beta[0] + Gm[c][a][1] * beta[1] + Gm[c][a][2] * beta[2];
     double K[3][3];
-    const double kf = psi4 * 0.5 * ia;
+    if (kij) {
+      const int map[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
 #pragma unroll
-    for (int a = 0; a < 3; a++)
+      for (int a = 0; a < 3; a++)
 #pragma unroll
-      for (int m = 0; m < 3; m++)
-        K[a][m] = kf * (ref[m] * nb[a][m] + ref[a] * nb[m][a] - (a == m ? (2.0 / 3.0) * ref[a] * divb : 0.0));
+        for (int c = 0; c < 3; c++) K[a][c] = kij[map[a][c]];
+    } else {
+      const double divb = nb[0][0] + nb[1][1] + nb[2][2];
+      const double kf = psi4 * 0.5 * ia;
+#pragma unroll
+      for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+          K[a][c] = kf * (ref[c] * nb[a][c] + ref[a] * nb[c][a] - (a == c ? (2.0 / 3.0) * ref[a] * divb : 0.0));
+    }
     const double pre = alpha * psi6;
     const double fourpsi3 = 4.0 * psi2 * psi;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
       double sv = -T00 * alpha * dal[a];
 #pragma unroll
-      for (int m = 0; m < 3; m++) {
-        const double T0low = gd[m] * (T00 * beta[m] + T0[m]);  // T^0_m
-        sv += T0low * nb[a][m];
-        sv += 0.5 * (T00 * beta[m] * beta[m] + 2.0 * T0[m] * beta[m] + T[m][m]) * fourpsi3 * dpsi[a] * ref[m];
+      for (int c = 0; c < 3; c++) {
+        const double T0low = gd[c] * (T00 * beta[c] + T0[c]);  // T^0_c
+        sv += T0low * nb[a][c];
+        sv += 0.5 * (T00 * beta[c] * beta[c] + 2.0 * T0[c] * beta[c] + T[c][c]) * fourpsi3 * dpsi[a] * ref[c];
       }
       s[1 + a] += pre * sv;
     }
@@ -306,10 +405,10 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
       bda += beta[a] * dal[a];
       double Kb = 0.0;
 #pragma unroll
-      for (int m = 0; m < 3; m++) {
-        Kbb += K[a][m] * beta[a] * beta[m];
-        TK += T[a][m] * K[a][m];
-        Kb += K[a][m] * beta[m];
+      for (int c = 0; c < 3; c++) {
+        Kbb += K[a][c] * beta[a] * beta[c];
+        TK += T[a][c] * K[a][c];
+        Kb += K[a][c] * beta[c];
       }
       T0K += T0[a] * (2.0 * Kb - dal[a]);
     }
@@ -320,14 +419,14 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
     // cell-centre momentum fluxes (f_S_l)^k = S_l vhat^k + delta alpha p* - alpha b_l B^k / W
     const double E = rhohs * W2;
     const double ab0 = alpha * b0;
-    double bd[3], S[3];
+    double bd[3], Sl[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
       bd[a] = gd[a] * pr[5 + a] * iW + ab0 * vd[a];
-      S[a] = E * vd[a] - ab0 * bd[a];
+      Sl[a] = E * vd[a] - ab0 * bd[a];
     }
     auto fS = [&](int l, int kk) {
-      double f = S[l] * vh[kk] - alpha * bd[l] * pr[5 + kk] * iW;
+      double f = Sl[l] * vh[kk] - alpha * bd[l] * pr[5 + kk] * iW;
       if (l == kk) f += alpha * ps;
       return psi6 * f;
     };
@@ -342,24 +441,10 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *__rest
   }
 }
 
-// Staged region of the face pass along D of a TX x TY x TZ tile: the tile's
-// cells plus H on each side along D (H = 2 for MC, 3 for MP5 and PPM).
-template <int TX, int TY, int TZ, int D, int H>
-constexpr int region_cells() {
-  return (TX + 2 * H * (D == 0)) * (TY + 2 * H * (D == 1)) * (TZ + 2 * H * (D == 2));
-}
-
 // Faces of the pass along D (the tile's lower faces plus the upper layer).
 template <int TX, int TY, int TZ, int D>
 constexpr int pass_faces() {
   return (TX + (D == 0)) * (TY + (D == 1)) * (TZ + (D == 2));
-}
-
-template <int TX, int TY, int TZ, int ND, int H>
-constexpr int max_region() {
-  constexpr int r0 = region_cells<TX, TY, TZ, 0, H>(), r1 = ND > 1 ? region_cells<TX, TY, TZ, 1, H>() : 0,
-                r2 = ND > 2 ? region_cells<TX, TY, TZ, 2, H>() : 0;
-  return r0 > r1 ? (r0 > r2 ? r0 : r2) : (r1 > r2 ? r1 : r2);
 }
 
 template <int TX, int TY, int TZ, int ND>
@@ -369,22 +454,23 @@ constexpr int max_faces() {
   return f0 > f1 ? (f0 > f2 ? f0 : f2) : (f1 > f2 ? f1 : f2);
 }
 
-// Separate flux buffer: when the staged region and the face fluxes both fit
-// in LDS for three workgroups per CU (160 KB), the fluxes get their own
-// buffer, so that one pass's fluxes are summed while the next pass's region
-// is staged (two barriers per pass instead of four).
-template <int TX, int TY, int TZ, int ND, int H>
-constexpr bool split_lds() {
-  return ((NV + 5) * max_region<TX, TY, TZ, ND, H>() + NV * max_faces<TX, TY, TZ, ND>()) * 8 * 3 <= 160 * 1024;
-}
-
-// LDS doubles per workgroup: the staged region (prim and metric) of the
-// largest pass, and the face fluxes (in a buffer of their own, or over the
-// region once it has been used).
+// LDS doubles per workgroup: the staged region (primitives, and the metric
+// when kMetLds) and the face fluxes of one pass.
 template <int TX, int TY, int TZ, int ND, int H = 2>
 constexpr int stage_lds() {
-  return (NV + 5) * max_region<TX, TY, TZ, ND, H>() +
-         (split_lds<TX, TY, TZ, ND, H>() ? NV * max_faces<TX, TY, TZ, ND>() : 0);
+  return (NV + (kMetLds ? 5 : 0)) * Plus<TX, TY, TZ, ND, H>::N + NV * max_faces<TX, TY, TZ, ND>();
+}
+
+// Workgroups per CU that the LDS of a tile shape allows (160 KB per CU), at
+// most GM_MAX_OCC.
+#ifndef GM_MAX_OCC
+#define GM_MAX_OCC 2
+#endif
+template <int TX, int TY, int TZ, int ND, int H = 2>
+constexpr int stage_occupancy() {
+  constexpr int per = stage_lds<TX, TY, TZ, ND, H>() * 8;
+  constexpr int n = (160 * 1024) / per;
+  return n > GM_MAX_OCC ? GM_MAX_OCC : n < 1 ? 1 : n;
 }
 
 // Tile shapes whose passes have at most one face per thread.
@@ -394,59 +480,115 @@ constexpr bool tile_fits() {
          (ND < 3 || pass_faces<TX, TY, TZ, 2>() <= NT) && TX * TY * TZ <= NT;
 }
 
-// Stage prim and metric of the pass's region (the tile plus H cells each
-// side along D) into S, coalesced, each value read once from memory.
-template <int TX, int TY, int TZ, int D, int H>
-__device__ __forceinline__ void stage_region(const Grid &G, const double *__restrict__ prim,
-                                             const double *__restrict__ met, double *S, int i0, int j0, int k0) {
-  constexpr int RX = TX + 2 * H * (D == 0), RY = TY + 2 * H * (D == 1), RZ = TZ + 2 * H * (D == 2),
-                RC = RX * RY * RZ;
-  // region origin: the tile origin moved H cells down along D
-  const int ai = i0 - H * (D == 0), aj = j0 - H * (D == 1), ak = k0 - H * (D == 2);
-  for (int c = threadIdx.x; c < RC; c += NT) {
-    const int ri = c % RX, rj = (c / RX) % RY, rk = c / (RX * RY);
-    const int gi = ai + ri, gj = aj + rj, gk = ak + rk;
+// The primitives (and with kMetLds the metric) of a tile's region in
+// registers on their way to LDS: loaded for the whole region at once, so
+// that it costs one memory latency, and possibly while the workgroup still
+// computes the previous tile.
+template <int TX, int TY, int TZ, int ND, int H>
+struct RegionRegs {
+  static constexpr int NP = Plus<TX, TY, TZ, ND, H>::N;
+  static constexpr int NIT = (NP + NT - 1) / NT;
+  static constexpr int NW = NV + (kMetLds ? 5 : 0);
+  double val[NIT][NW];
+  bool in[NIT];
+};
+
+// Load the region of the tile with origin (i0, j0, k0), coalesced, each
+// value read once from memory.
+template <int TX, int TY, int TZ, int ND, int H>
+__device__ __forceinline__ void region_load(const Grid &G, const double *__restrict__ prim,
+                                            const double *__restrict__ met, int i0, int j0, int k0,
+                                            RegionRegs<TX, TY, TZ, ND, H> &R) {
+  using RR = RegionRegs<TX, TY, TZ, ND, H>;
+#pragma unroll
+  for (int it = 0; it < RR::NIT; it++) {
+    const int c = threadIdx.x + it * NT;
+    int x, y, z;
+    plus_cell<TX, TY, TZ, ND, H>(c, x, y, z);
+    const int gi = i0 + x, gj = j0 + y, gk = k0 + z;
     // cells outside the array (ragged tiles) are not needed by any valid face
-    if (gi < G.n[0] + G.g[0] && gj < G.n[1] + G.g[1] && gk < G.n[2] + G.g[2]) {
+    R.in[it] = c < RR::NP && gi < G.n[0] + G.g[0] && gj < G.n[1] + G.g[1] && gk < G.n[2] + G.g[2];
+    // every path defines every register, so that no earlier value of R
+    // stays live across a caller's loop
+    if (R.in[it]) {
       const long o = cell_offset(G, gi, gj, gk);
 #pragma unroll
-      for (int v = 0; v < NV; v++) S[v * RC + c] = prim[v * G.nv + o];
+      for (int v = 0; v < NV; v++) R.val[it][v] = prim[v * G.nv + o];
+      if constexpr (kMetLds) {
 #pragma unroll
-      for (int w = 0; w < 5; w++) S[(NV + w) * RC + c] = met[w * G.nv + o];
+        for (int w = 0; w < 5; w++) R.val[it][NV + w] = met[w * G.nv + o];
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < RR::NW; v++) R.val[it][v] = 0.0;
     }
   }
 }
 
-// Flux divergence along D accumulated into acc of the thread's cell, from
-// the pass's region staged in S: (1) one face per thread, (2) the fluxes
-// through LDS (SF; SF == S reuses the region once every face is done) to the
-// cells on both sides of each face.  Begins after a barrier that follows the
-// staging; on return other threads may still read SF.
-template <int TX, int TY, int TZ, int D, int REC, int R, int P>
-__device__ __forceinline__ void face_pass(const Grid &G, const double *S, double *SF, int i0, int j0, int k0,
-                                          int tx, int ty, int tz, bool valid, double *acc, const PPBase &pb) {
+// Write a loaded region into the workgroup's LDS buffer S.
+template <int TX, int TY, int TZ, int ND, int H>
+__device__ __forceinline__ void region_store(const RegionRegs<TX, TY, TZ, ND, H> &R, double *S) {
+  using RR = RegionRegs<TX, TY, TZ, ND, H>;
+#pragma unroll
+  for (int it = 0; it < RR::NIT; it++) {
+    const int c = threadIdx.x + it * NT;
+    if (R.in[it]) {
+#pragma unroll
+      for (int v = 0; v < RR::NW; v++) S[v * RR::NP + c] = R.val[it][v];
+    }
+  }
+}
+
+// Face fluxes of the pass along D into registers (one face per thread; zero
+// for threads without a valid face).
+template <int TX, int TY, int TZ, int ND, int D, int REC, int R, int P>
+__device__ __forceinline__ void pass_fluxes(const Grid &G, const double *S, const double *__restrict__ met, int i0,
+                                            int j0, int k0, double *Fo, bool &nonflat, const PPBase &pb) {
   constexpr int H = recon_halo(REC);
-  constexpr int RX = TX + 2 * H * (D == 0), RY = TY + 2 * H * (D == 1), RZ = TZ + 2 * H * (D == 2),
-                RC = RX * RY * RZ;
+  constexpr int NP = Plus<TX, TY, TZ, ND, H>::N;
   constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2), NF = FX * FY * FZ;
-  const int tid = threadIdx.x;
-  // (1) face tid: region index of the cell H below it along D
-  double Fo[NV];
-  const int f = tid;
+  const int f = threadIdx.x;
   const int fx = f % FX, fy = (f / FX) % FY, fz = f / (FX * FY);
   const int ci = i0 + fx, cj = j0 + fy, ck = k0 + fz;
   const bool ok = f < NF && (D == 0 ? ci <= G.n[0] : ci < G.n[0]) && (D == 1 ? cj <= G.n[1] : cj < G.n[1]) &&
                   (D == 2 ? ck <= G.n[2] : ck < G.n[2]);
   if (ok) {
-    constexpr int rs = D == 0 ? 1 : D == 1 ? RX : RX * RY;
-    const int r0 = fx + RX * (fy + RY * fz);  // region coordinate = face coordinate - H + H along D
-    face_flux<D, REC, R, P>(G, S, RC, r0, rs, ci, cj, ck, Fo, pb);
+    const int sd = D == 0 ? fx : D == 1 ? fy : fz;
+    int ix[2 * H];
+#pragma unroll
+    for (int m = 0; m < 2 * H; m++) ix[m] = plus_line<TX, TY, TZ, ND, H, D>(sd - H + m, fx, fy, fz);
+    double ma[5], mb[5];
+    if constexpr (kMetLds) {
+      const double *Sm = S + NV * NP;
+#pragma unroll
+      for (int w = 0; w < 5; w++) {
+        ma[w] = Sm[w * NP + ix[H - 1]];
+        mb[w] = Sm[w * NP + ix[H]];
+      }
+    } else {
+      const long ob = cell_offset(G, ci, cj, ck), oa = ob - G.s[D];
+#pragma unroll
+      for (int w = 0; w < 5; w++) {
+        ma[w] = met[w * G.nv + oa];
+        mb[w] = met[w * G.nv + ob];
+      }
+    }
+    face_flux<D, REC, R, P>(G, S, NP, ix, ma, mb, ci, cj, ck, Fo, nonflat, pb);
   } else {
 #pragma unroll
     for (int v = 0; v < NV; v++) Fo[v] = 0.0;
   }
-  if (SF == S) __syncthreads();  // every face has read the region
-  // (2) fluxes through LDS
+}
+
+// The pass's fluxes through LDS (SF) into the flux divergence acc of the
+// thread's cell.  On entry every thread has finished reading SF of the
+// previous pass (the caller's barrier); on return other threads may still
+// read SF.
+template <int TX, int TY, int TZ, int D>
+__device__ __forceinline__ void pass_divergence(const Grid &G, double *SF, const double *Fo, int i0, int j0, int k0,
+                                                int tx, int ty, int tz, bool valid, double *acc) {
+  constexpr int FX = TX + (D == 0), FY = TY + (D == 1), FZ = TZ + (D == 2), NF = FX * FY * FZ;
+  const int f = threadIdx.x;
   if (f < NF) {
 #pragma unroll
     for (int v = 0; v < NV; v++) SF[v * NF + f] = Fo[v];
@@ -463,78 +605,131 @@ __device__ __forceinline__ void face_pass(const Grid &G, const double *S, double
 }
 
 // One RK stage (MODE 1: q_out = ca q_n + cb (q_s + dt L)) or the RHS alone
-// (MODE 0: out = L) on the tile of TX x TY x TZ cells with origin (i0,j0,k0).
-// Every thread of the workgroup (NT threads) must call it (it synchronises);
-// sF is the workgroup's LDS buffer of stage_lds<TX,TY,TZ,ND,recon_halo(REC)>()
-// doubles.
-template <int TX, int TY, int TZ, int ND, int MODE, int REC = 0, int R = 0, int P = 0>
-__device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0, const double *__restrict__ prim,
-                                           const double *__restrict__ met, const double *qn, const double *qs,
-                                           double *out, const double *__restrict__ dtp, double ca, double cb,
-                                           double *sF) {
+// (MODE 0: out = L) on the tile of TX x TY x TZ cells with origin (i0,j0,k0),
+// whose region (the tile plus REC's halo along each active axis) the
+// workgroup has just staged in sF (stage_lds<TX,TY,TZ,ND,recon_halo(REC)>()
+// doubles; the staging ordered by a barrier).  The three face passes run
+// from LDS, each followed by the exchange of its fluxes.  Every thread of the
+// workgroup (NT threads) must call it (it synchronises; on return sF may be
+// restaged).  kij (nullable): K_ij per cell, 6 arrays in the grid's layout.
+// prefetch: called by every thread after the sources, before the loads of
+// the RK combination (a persistent caller loads its next tile there).
+struct NoPrefetch {
+  __device__ void operator()() const {}
+};
+
+template <int TX, int TY, int TZ, int ND, int MODE, int REC = 0, int R = 0, int P = 0, typename Pre = NoPrefetch>
+__device__ __forceinline__ void stage_staged(const Grid &G, int i0, int j0, int k0, const double *__restrict__ met,
+                                             const double *qn, const double *qs, double *out,
+                                             const double *__restrict__ dtp, double ca, double cb, double *sF,
+                                             const double *__restrict__ kij = nullptr, Pre prefetch = Pre{}) {
   static_assert(tile_fits<TX, TY, TZ, ND>(), "tile passes must have at most one face per thread");
+  static_assert(P == 0 || MODE == 1, "the limiter needs the stage's Euler step");
+  constexpr int H = recon_halo(REC);
+  constexpr int NP = Plus<TX, TY, TZ, ND, H>::N;
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
   const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
   const bool valid = tid < TX * TY * TZ && (i < G.n[0]) && (j < G.n[1]) && (k < G.n[2]);
-  // tile base: the cell (i0 - g0, j0 - g1, k0 - g2); every access of this
-  // workgroup is at a non-negative offset from it
-  const long lo = cell_offset(G, i0 - G.g[0], j0 - G.g[1], k0 - G.g[2]);
-  const double *__restrict__ pb = prim + lo;
-  const double *__restrict__ mb = met + lo;
+  const long oc = valid ? cell_offset(G, i, j, k) : 0;
+  // the conserved state of the RK combination (kPrefetchQ: loaded first)
+  double un[NV], us[NV];
+  if (MODE == 1 && kPrefetchQ && valid) {
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+      un[v] = qn[v * G.nv + oc];
+      us[v] = ca == 0.0 ? 0.0 : qs[v * G.nv + oc];
+    }
+  }
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; v++) acc[v] = 0.0;
-  static_assert(P == 0 || MODE == 1, "the limiter needs the stage's Euler step");
   PPBase pp{nullptr, 0.0};
   if constexpr (P) pp = PPBase{ca == 0.0 ? qn : qs, *dtp};
-  // with a separate flux buffer a pass's fluxes are summed while the next
-  // region is staged; with a shared one the summation must end first
-  constexpr int H = recon_halo(REC);
-  constexpr bool split = split_lds<TX, TY, TZ, ND, H>();
-  double *SF = split ? sF + (NV + 5) * max_region<TX, TY, TZ, ND, H>() : sF;
-  stage_region<TX, TY, TZ, 0, H>(G, prim, met, sF, i0, j0, k0);
-  __syncthreads();
-  face_pass<TX, TY, TZ, 0, REC, R, P>(G, sF, SF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
+  double *SF = sF + (NV + (kMetLds ? 5 : 0)) * NP;
+  bool nonflat = false;
+  double Fo[NV];
+  pass_fluxes<TX, TY, TZ, ND, 0, REC, R, P>(G, sF, met, i0, j0, k0, Fo, nonflat, pp);
+  pass_divergence<TX, TY, TZ, 0>(G, SF, Fo, i0, j0, k0, tx, ty, tz, valid, acc);
   if constexpr (ND > 1) {
-    if constexpr (!split) __syncthreads();
-    stage_region<TX, TY, TZ, 1, H>(G, prim, met, sF, i0, j0, k0);
-    __syncthreads();
-    face_pass<TX, TY, TZ, 1, REC, R, P>(G, sF, SF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
+    pass_fluxes<TX, TY, TZ, ND, 1, REC, R, P>(G, sF, met, i0, j0, k0, Fo, nonflat, pp);
+    __syncthreads();  // every thread has summed the previous pass's fluxes
+    pass_divergence<TX, TY, TZ, 1>(G, SF, Fo, i0, j0, k0, tx, ty, tz, valid, acc);
   }
   if constexpr (ND > 2) {
-    if constexpr (!split) __syncthreads();
-    stage_region<TX, TY, TZ, 2, H>(G, prim, met, sF, i0, j0, k0);
+    pass_fluxes<TX, TY, TZ, ND, 2, REC, R, P>(G, sF, met, i0, j0, k0, Fo, nonflat, pp);
     __syncthreads();
-    face_pass<TX, TY, TZ, 2, REC, R, P>(G, sF, SF, i0, j0, k0, tx, ty, tz, valid, acc, pp);
+    pass_divergence<TX, TY, TZ, 2>(G, SF, Fo, i0, j0, k0, tx, ty, tz, valid, acc);
   }
-  // a workgroup that takes another tile next restages sF: with a shared
-  // buffer the summation must end first (with a separate one the next
-  // tile's first barrier orders the flux buffer)
-  if constexpr (!split) __syncthreads();
-  if (!valid) return;
-  const unsigned rel = (unsigned)((tz + G.g[2]) * G.s[2] + (ty + G.g[1]) * G.s[1] + (tx + G.g[0]));
-  cell_sources(G, pb, mb, i, j, k, rel, acc);
-  const unsigned oc = rel * 8u;
-  if (MODE == 0) {
+  // flat: no face of the tile joins cells of different psi or alpha, and no
+  // cell has a shift, so every centred metric derivative of its cells is 0
+  const bool flat = !__syncthreads_or(nonflat);
+  if (valid) {
+    const int c = tx + TX * (ty + TY * tz);
+    double prc[NV];
 #pragma unroll
-    for (int v = 0; v < NV; v++)
-      *reinterpret_cast<double *>(reinterpret_cast<char *>(out + lo + v * G.nv) + oc) = acc[v];
-  } else {
-    const double dt = *dtp;
-    const double *qnb = qn + lo;
-#pragma unroll
-    for (int v = 0; v < NV; v++) {
-      double *o = reinterpret_cast<double *>(reinterpret_cast<char *>(out + lo + v * G.nv) + oc);
-      const double un = ld(qnb, G.nv, v, oc);
-      if (ca == 0.0) {
-        *o = cb * (un + dt * acc[v]);
+    for (int v = 0; v < NV; v++) prc[v] = sF[v * NP + c];
+    const double *Sm = sF + NV * NP;
+    auto metv = [&](int w, int a, int o) -> double {
+      if (a >= ND) return 0.0;
+      if constexpr (kMetLds) {
+        if (a < 0) return Sm[w * NP + c];
+        const int p = a == 0 ? plus_line<TX, TY, TZ, ND, H, 0>(tx + o, tx, ty, tz)
+                             : a == 1 ? plus_line<TX, TY, TZ, ND, H, 1>(ty + o, tx, ty, tz)
+                                      : plus_line<TX, TY, TZ, ND, H, 2>(tz + o, tx, ty, tz);
+        return Sm[w * NP + p];
       } else {
-        const double us = ld(qs + lo, G.nv, v, oc);
-        *o = ca * un + cb * (us + dt * acc[v]);
+        return met[w * G.nv + oc + (a < 0 ? 0 : o * G.s[a])];
       }
+    };
+    double kc[6];
+    const double *kp = nullptr;
+    if (kij) {
+#pragma unroll
+      for (int m = 0; m < 6; m++) kc[m] = kij[m * G.nv + oc];
+      kp = kc;
+    }
+    cell_sources(G, prc, metv, flat && !kij, kp, i, j, acc);
+  }
+  // the caller's loads (the next tile's region) go out together with the
+  // loads of the RK combination, so that their latencies overlap
+  prefetch();
+  if (valid) {
+    if (MODE == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; v++) out[v * G.nv + oc] = acc[v];
+    } else {
+      if constexpr (!kPrefetchQ) {
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+          un[v] = qn[v * G.nv + oc];
+          us[v] = ca == 0.0 ? 0.0 : qs[v * G.nv + oc];
+        }
+      }
+      const double dt = *dtp;
+#pragma unroll
+      for (int v = 0; v < NV; v++)
+        out[v * G.nv + oc] = ca == 0.0 ? cb * (un[v] + dt * acc[v]) : ca * un[v] + cb * (us[v] + dt * acc[v]);
     }
   }
+  // a workgroup that takes another tile next restages sF: every thread must
+  // have finished reading it
+  __syncthreads();
+}
+
+// The same for a tile whose region is not staged yet: stage it, then the
+// stage.
+template <int TX, int TY, int TZ, int ND, int MODE, int REC = 0, int R = 0, int P = 0>
+__device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0, const double *__restrict__ prim,
+                                           const double *__restrict__ met, const double *qn, const double *qs,
+                                           double *out, const double *__restrict__ dtp, double ca, double cb,
+                                           double *sF, const double *__restrict__ kij = nullptr) {
+  constexpr int H = recon_halo(REC);
+  RegionRegs<TX, TY, TZ, ND, H> Rg;
+  region_load<TX, TY, TZ, ND, H>(G, prim, met, i0, j0, k0, Rg);
+  region_store<TX, TY, TZ, ND, H>(Rg, sF);
+  __syncthreads();
+  stage_staged<TX, TY, TZ, ND, MODE, REC, R, P>(G, i0, j0, k0, met, qn, qs, out, dtp, ca, cb, sF, kij);
 }
 
 // Primitive recovery of interior cell number t (x fastest) of grid G; a

@@ -67,7 +67,7 @@ def test_null_arguments_are_rejected():
     L = gmu.lib()
     assert L.gmunu_create(None, None) == -2
     assert L.gmunu_destroy(None) == -2
-    assert L.gmunu_rhs(None, None, None, None, None) == -2
+    assert L.gmunu_rhs(None, None, None, None, None, None) == -2
     assert L.gmunu_c2p(None, None, None, None, None, None, None) == -2
 
 
