@@ -71,6 +71,12 @@ def lib():
         L.og_fill_ghosts.argtypes = [P, P]
         L.og_rhs.argtypes = [P, P, P, P]
         L.og_rhs_cells.argtypes = [P, P, P, ctypes.c_long, P, P]
+        L.og_rhs_k.argtypes = [P, P, P, P, P]
+        L.og_rhs_cells_k.argtypes = [P, P, P, P, ctypes.c_long, P, P]
+        L.og_rhs_scale_cells_k.argtypes = [P, P, P, P, ctypes.c_long, P, P]
+        L.og_rk_stage_k.argtypes = [P, ctypes.c_int, ctypes.c_double, P, P, P, P, P, P]
+        L.og_rk_stage_k.restype = ctypes.c_long
+        L.og_sources_cell.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
         L.og_rhs_scale_cells.argtypes = [P, P, P, ctypes.c_long, P, P]
         L.og_cfl_dt.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.og_cfl_dt.restype = ctypes.c_double
@@ -168,30 +174,46 @@ def fill_ghosts(p, prim):
     return prim
 
 
-def rhs(p, prim, metric):
+def rhs(p, prim, metric, kij=None):
     d = make_desc(p)
-    prim, metric = _chk(prim), _chk(metric)
+    prim, metric, kij = _chk(prim), _chk(metric), _kij(kij)
     out = np.zeros_like(prim)
-    lib().og_rhs(_ref(d), _p(prim), _p(metric), _p(out))
+    lib().og_rhs_k(_ref(d), _p(prim), _p(metric), None if kij is None else _p(kij), _p(out))
     return out
 
 
-def rhs_cells(p, prim, metric, ijk):
+def _kij(kij):
+    """K_ij (6 arrays xx, xy, xz, yy, yz, zz in the grid's layout) or None."""
+    return None if kij is None else _chk(kij)
+
+
+def rhs_cells(p, prim, metric, ijk, kij=None):
     d = make_desc(p)
-    prim, metric = _chk(prim), _chk(metric)
+    prim, metric, kij = _chk(prim), _chk(metric), _kij(kij)
     ijk = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
     out = np.zeros((ijk.shape[0], 8))
-    lib().og_rhs_cells(_ref(d), _p(prim), _p(metric), ijk.shape[0], _p(ijk), _p(out))
+    lib().og_rhs_cells_k(_ref(d), _p(prim), _p(metric), None if kij is None else _p(kij), ijk.shape[0], _p(ijk),
+                         _p(out))
     return out
 
 
-def rhs_scale_cells(p, prim, metric, ijk):
+def rhs_scale_cells(p, prim, metric, ijk, kij=None):
     d = make_desc(p)
-    prim, metric = _chk(prim), _chk(metric)
+    prim, metric, kij = _chk(prim), _chk(metric), _kij(kij)
     ijk = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
     out = np.zeros((ijk.shape[0], 8))
-    lib().og_rhs_scale_cells(_ref(d), _p(prim), _p(metric), ijk.shape[0], _p(ijk), _p(out))
+    lib().og_rhs_scale_cells_k(_ref(d), _p(prim), _p(metric), None if kij is None else _p(kij), ijk.shape[0],
+                               _p(ijk), _p(out))
     return out
+
+
+def sources_cell(p, prim, metric, i, j, k, kij=None):
+    """(gravitational, geometric) source vectors of interior cell (i, j, k)."""
+    d = make_desc(p)
+    prim, metric, kij = _chk(prim), _chk(metric), _kij(kij)
+    g, e = np.zeros(8), np.zeros(8)
+    lib().og_sources_cell(_ref(d), _p(prim), _p(metric), None if kij is None else _p(kij), i, j, k, _p(g), _p(e))
+    return g, e
 
 
 def cfl_dt(p, prim, metric, cfl, t=0.0, t_end=float("inf")):
@@ -199,13 +221,14 @@ def cfl_dt(p, prim, metric, cfl, t=0.0, t_end=float("inf")):
     return float(lib().og_cfl_dt(_ref(d), _p(_chk(prim)), _p(_chk(metric)), cfl, t, t_end))
 
 
-def rk_stage(p, stage, dt, qn, qs, prim, metric, flags=None):
+def rk_stage(p, stage, dt, qn, qs, prim, metric, flags=None, kij=None):
     d = make_desc(p)
     for a in (qn, qs, prim):
         assert a.flags.c_contiguous and a.dtype == np.float64
-    metric = _chk(metric)
+    metric, kij = _chk(metric), _kij(kij)
     fp = _p(flags) if flags is not None else None
-    return int(lib().og_rk_stage(_ref(d), stage, dt, _p(qn), _p(qs), _p(prim), _p(metric), fp))
+    return int(lib().og_rk_stage_k(_ref(d), stage, dt, _p(qn), _p(qs), _p(prim), _p(metric),
+                                   None if kij is None else _p(kij), fp))
 
 
 def rk_update(p, stage, dt, qn, qs, prim, metric):

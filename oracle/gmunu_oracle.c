@@ -23,8 +23,13 @@
  *   - coordinates: 0 Cartesian (x,y,z); 1 cylindrical (R,z,phi);
  *     2 spherical (r,theta,phi).
  *
- * Parity unpinned: the extrinsic-curvature terms of the energy source (only
- * non-zero for a non-zero shift) are checked against the GPU path only.
+ * Every part is pinned by a test independent of this file: the
+ * gravitational sources (extrinsic-curvature and shift terms included)
+ * against the covariant conservation law of a stationary 4-metric, the whole
+ * discrete right-hand side against a 50-digit brute-force evaluation on
+ * 8-cell grids, the shift in fluxes and speeds against the translated exact
+ * Riemann solution, plus the closed forms, exact solutions and conservation
+ * laws listed in the tests.
  */
 #include <math.h>
 #include <stdint.h>
@@ -849,8 +854,9 @@ static void christoffel_point(int coord, double x1, double x2, double G[3][3][3]
  * (second-order, as the derivative stencils of section 2.7) and K_ij of the
  * CFC metric under maximal slicing from the shift (section 2.6).  The result
  * is added to s[]. */
-static void grav_sources_x(const og_desc *d, const double *met, const pstate *st, double psi, int i, int j, int k,
-                           const double ref[3], double x1, double x2, double s[NV], int absmode) {
+static void grav_sources_x(const og_desc *d, const double *met, const double *kij, const pstate *st, double psi,
+                           int i, int j, int k, const double ref[3], double x1, double x2, double s[NV],
+                           int absmode) {
 #define TERM(x) (absmode ? fabs(x) : (x))
   int cell[3] = {i, j, k};
   double dalpha[3] = {0, 0, 0}, dpsi[3] = {0, 0, 0}, dbeta[3][3] = {{0}};
@@ -877,16 +883,24 @@ static void grav_sources_x(const og_desc *d, const double *met, const pstate *st
       for (int l = 0; l < 3; l++) v += G[m][a][l] * beta[l];
       nb[a][m] = v;
     }
-  /* K_ij = psi^4/(2 alpha) (nb_i beta_j + nb_j beta_i - 2/3 ref_ij div beta) */
+  /* K_ij given by the caller (6 arrays xx, xy, xz, yy, yz, zz), else
+   * K_ij = psi^4/(2 alpha) (nb_i beta_j + nb_j beta_i - 2/3 ref_ij div beta) */
   double K[3][3];
-  double divb = nb[0][0] + nb[1][1] + nb[2][2];
-  double psi4 = psi * psi * psi * psi;
-  for (int a = 0; a < 3; a++)
-    for (int b = 0; b < 3; b++) {
-      double v = ref[b] * nb[a][b] + ref[a] * nb[b][a];
-      if (a == b) v -= 2.0 / 3.0 * ref[a] * divb;
-      K[a][b] = psi4 / (2.0 * alpha) * v;
-    }
+  if (kij) {
+    static const int comp[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    long c = at(d, i, j, k);
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) K[a][b] = kij[comp[a][b] * nt + c];
+  } else {
+    double divb = nb[0][0] + nb[1][1] + nb[2][2];
+    double psi4 = psi * psi * psi * psi;
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) {
+        double v = ref[b] * nb[a][b] + ref[a] * nb[b][a];
+        if (a == b) v -= 2.0 / 3.0 * ref[a] * divb;
+        K[a][b] = psi4 / (2.0 * alpha) * v;
+      }
+  }
   /* T^{mu nu} = rho h* u^mu u^nu + p* g^{mu nu} - b^mu b^nu */
   double W = st->W;
   double u[4], bu[4];
@@ -940,9 +954,9 @@ static void grav_sources_x(const og_desc *d, const double *met, const pstate *st
 #undef TERM
 }
 
-static void grav_sources(const og_desc *d, const double *met, const pstate *st, double psi, int i, int j, int k,
-                         const double ref[3], double x1, double x2, double s[NV]) {
-  grav_sources_x(d, met, st, psi, i, j, k, ref, x1, x2, s, 0);
+static void grav_sources(const og_desc *d, const double *met, const double *kij, const pstate *st, double psi, int i,
+                         int j, int k, const double ref[3], double x1, double x2, double s[NV]) {
+  grav_sources_x(d, met, kij, st, psi, i, j, k, ref, x1, x2, s, 0);
 }
 
 /* Geometric sources <Gamma^l_ik> (f_S_l)^k with the fluxes taken at the cell
@@ -988,17 +1002,17 @@ static void geom_sources(const og_desc *d, const pstate *st, int i, int j, int k
  * cell volume plus the gravitational and geometric sources (section 2.1,
  * the discretised equation; the minus sign on the flux bracket follows from
  * the conservation law and the positivity-limiter form of section 2.4). */
-static void rhs_cell_pp(const og_desc *d, const double *prim, const double *met, int i, int j, int k, double dq[NV],
-                        const pp_ctx *pp);
+static void rhs_cell_pp(const og_desc *d, const double *prim, const double *met, const double *kij, int i, int j,
+                        int k, double dq[NV], const pp_ctx *pp);
 
 void og_rhs_cell(const og_desc *d, const double *prim, const double *met, int i, int j, int k, double dq[NV]) {
-  rhs_cell_pp(d, prim, met, i, j, k, dq, NULL);
+  rhs_cell_pp(d, prim, met, NULL, i, j, k, dq, NULL);
 }
 
 /* The same with the positivity-preserving limiter on the face fluxes when
  * the descriptor asks for it and pp is given. */
-static void rhs_cell_pp(const og_desc *d, const double *prim, const double *met, int i, int j, int k, double dq[NV],
-                        const pp_ctx *pp) {
+static void rhs_cell_pp(const og_desc *d, const double *prim, const double *met, const double *kij, int i, int j,
+                        int k, double dq[NV], const pp_ctx *pp) {
   int cell[3] = {i, j, k};
   for (int v = 0; v < NV; v++) dq[v] = 0.0;
   double dV = cell_volume(d, i, j, k);
@@ -1018,26 +1032,58 @@ static void rhs_cell_pp(const og_desc *d, const double *prim, const double *met,
   pstate st;
   point_state(d->gamma, pr, m[0], m[1], m + 2, ref, &st);
   double s[NV] = {0};
-  grav_sources(d, met, &st, m[0], i, j, k, ref, x1, x2, s);
+  grav_sources(d, met, kij, &st, m[0], i, j, k, ref, x1, x2, s);
   geom_sources(d, &st, i, j, k, s);
   for (int v = 0; v < NV; v++) dq[v] += s[v];
 }
 
-void og_rhs(const og_desc *d, const double *prim, const double *met, double *dqdt) {
+/* The RHS on every interior cell; kij (nullable): K_ij per cell, 6 arrays in
+ * the grid's layout (xx, xy, xz, yy, yz, zz), else K_ij from the shift. */
+void og_rhs_k(const og_desc *d, const double *prim, const double *met, const double *kij, double *dqdt) {
   long nt = ntot(d);
   for (int k = 0; k < d->n[2]; k++)
     for (int j = 0; j < d->n[1]; j++)
       for (int i = 0; i < d->n[0]; i++) {
         double dq[NV];
-        og_rhs_cell(d, prim, met, i, j, k, dq);
+        rhs_cell_pp(d, prim, met, kij, i, j, k, dq, NULL);
         long c = at(d, i, j, k);
         for (int v = 0; v < NV; v++) dqdt[v * nt + c] = dq[v];
       }
 }
 
-/* RHS at a list of interior cells given as (i,j,k) triples; out is [n][8]. */
+void og_rhs(const og_desc *d, const double *prim, const double *met, double *dqdt) {
+  og_rhs_k(d, prim, met, NULL, dqdt);
+}
+
+/* RHS at a list of interior cells given as (i,j,k) triples; out is [n][8];
+ * kij as in og_rhs_k. */
+void og_rhs_cells_k(const og_desc *d, const double *prim, const double *met, const double *kij, long ncell,
+                    const int *ijk, double *out) {
+  for (long c = 0; c < ncell; c++)
+    rhs_cell_pp(d, prim, met, kij, ijk[3 * c], ijk[3 * c + 1], ijk[3 * c + 2], out + NV * c, NULL);
+}
+
 void og_rhs_cells(const og_desc *d, const double *prim, const double *met, long ncell, const int *ijk, double *out) {
-  for (long c = 0; c < ncell; c++) og_rhs_cell(d, prim, met, ijk[3 * c], ijk[3 * c + 1], ijk[3 * c + 2], out + NV * c);
+  og_rhs_cells_k(d, prim, met, NULL, ncell, ijk, out);
+}
+
+/* The gravitational and the geometric source terms of interior cell
+ * (i,j,k) separately (section 2.1, Appendix A), for checks; kij as in
+ * og_rhs_k. */
+void og_sources_cell(const og_desc *d, const double *prim, const double *met, const double *kij, int i, int j, int k,
+                     double grav[NV], double geom[NV]) {
+  long nt = ntot(d), c = at(d, i, j, k);
+  double pr[NV], m[5];
+  for (int v = 0; v < NV; v++) pr[v] = prim[v * nt + c];
+  load_metric(d, met, c, m);
+  double x1 = centre(d, 0, i), x2 = centre(d, 1, j);
+  double ref[3];
+  ref_metric(d->coord, x1, x2, ref);
+  pstate st;
+  point_state(d->gamma, pr, m[0], m[1], m + 2, ref, &st);
+  for (int v = 0; v < NV; v++) grav[v] = geom[v] = 0.0;
+  grav_sources(d, met, kij, &st, m[0], i, j, k, ref, x1, x2, grav);
+  geom_sources(d, &st, i, j, k, geom);
 }
 
 /* Error scale of each cell's RHS (test helper): the sum over the cell's
@@ -1045,7 +1091,8 @@ void og_rhs_cells(const og_desc *d, const double *prim, const double *met, long 
  * volume, plus the summed magnitudes of every source term.  A floating-point
  * evaluation of the RHS is accurate relative to this sum, not to the RHS
  * itself, which cancels to near zero in smooth or static regions. */
-void og_rhs_scale_cells(const og_desc *d, const double *prim, const double *met, long ncell, const int *ijk, double *out) {
+void og_rhs_scale_cells_k(const og_desc *d, const double *prim, const double *met, const double *kij, long ncell,
+                          const int *ijk, double *out) {
   long nt = ntot(d);
   for (long c = 0; c < ncell; c++) {
     int i = ijk[3 * c], j = ijk[3 * c + 1], k = ijk[3 * c + 2];
@@ -1069,10 +1116,14 @@ void og_rhs_scale_cells(const og_desc *d, const double *prim, const double *met,
     pstate st;
     point_state(d->gamma, pr, m[0], m[1], m + 2, ref, &st);
     double s1[NV] = {0}, s2[NV] = {0};
-    grav_sources_x(d, met, &st, m[0], i, j, k, ref, x1, x2, s1, 1);
+    grav_sources_x(d, met, kij, &st, m[0], i, j, k, ref, x1, x2, s1, 1);
     geom_sources_x(d, &st, i, j, k, s2, 1);
     for (int v = 0; v < NV; v++) o[v] += s1[v] + s2[v];
   }
+}
+
+void og_rhs_scale_cells(const og_desc *d, const double *prim, const double *met, long ncell, const int *ijk, double *out) {
+  og_rhs_scale_cells_k(d, prim, met, NULL, ncell, ijk, out);
 }
 
 /* ------------------------------------------------------ prim2con / c2p */
@@ -1223,8 +1274,8 @@ double og_cfl_dt(const og_desc *d, const double *prim, const double *met, double
  * recovery; og_rk_stage then recovers prim (c2p, which may rewrite q of
  * corrected cells) and fills its ghosts, and returns the number of fatal c2p
  * cells. */
-void og_rk_update(const og_desc *d, int stage, double dt, const double *qn, double *qs, const double *prim,
-                  const double *met) {
+void og_rk_update_k(const og_desc *d, int stage, double dt, const double *qn, double *qs, const double *prim,
+                    const double *met, const double *kij) {
   long nt = ntot(d);
   double a, b;
   if (stage == 0) { a = 0.0; b = 1.0; }
@@ -1238,7 +1289,7 @@ void og_rk_update(const og_desc *d, int stage, double dt, const double *qn, doub
     for (int j = 0; j < d->n[1]; j++)
       for (int i = 0; i < d->n[0]; i++) {
         double dq[NV];
-        rhs_cell_pp(d, prim, met, i, j, k, dq, &pp);
+        rhs_cell_pp(d, prim, met, kij, i, j, k, dq, &pp);
         long c = at(d, i, j, k);
         for (int v = 0; v < NV; v++) L[v * nt + c] = dq[v];
       }
@@ -1253,6 +1304,19 @@ void og_rk_update(const og_desc *d, int stage, double dt, const double *qn, doub
         }
       }
   free(L);
+}
+
+void og_rk_update(const og_desc *d, int stage, double dt, const double *qn, double *qs, const double *prim,
+                  const double *met) {
+  og_rk_update_k(d, stage, dt, qn, qs, prim, met, NULL);
+}
+
+long og_rk_stage_k(const og_desc *d, int stage, double dt, const double *qn, double *qs, double *prim,
+                   const double *met, const double *kij, uint8_t *flags) {
+  og_rk_update_k(d, stage, dt, qn, qs, prim, met, kij);
+  long nf = og_c2p(d, qs, met, prim, flags);
+  og_fill_ghosts(d, prim);
+  return nf;
 }
 
 long og_rk_stage(const og_desc *d, int stage, double dt, const double *qn, double *qs, double *prim,

@@ -309,16 +309,6 @@ def centres(p, level=None):
     return x1, x2, x3
 
 
-def fluid_stilde(psi, rho, wv, p, gamma):
-    """S~ = psi^6 (rho h W^2 v^2 + 3 p) of an ideal-gas fluid (section 2.6):
-    W^2 v^2 = psi^4 sum_i (W v^i)^2 with orthonormal components W v^i
-    (Cartesian ones, or h_i times the contravariant ones), rho h = rho +
-    gamma / (gamma - 1) p."""
-    rhoh = rho + gamma / (gamma - 1.0) * p
-    w2v2 = psi ** 4 * (wv[0] ** 2 + wv[1] ** 2 + wv[2] ** 2)
-    return psi ** 6 * (rhoh * w2v2 + 3.0 * p)
-
-
 def xcfc_solve(pv, ps, pa, U, S, stilde, X, u_psi, u_ap, beta, tol=1e-12, max_cycles=60):
     """The xCFC metric solve of section 2.6 on the grids of pv, ps, pa
     (Cartesian, or axisymmetric cylindrical and spherical in orthonormal
@@ -484,6 +474,22 @@ def fluid_stilde_curvilinear(hp, psi, prim):
     return psi ** 6 * ((rho + gam / (gam - 1.0) * p) * w2v2 + 3.0 * p)
 
 
+def stilde_fn(hp, pv, prim):
+    """S~ as a function of psi on the multigrid layout of pv, for the GRMHD
+    state prim: fluid_stilde_curvilinear on the interior cells, 0 on the
+    multigrid ghosts."""
+    L, I = _layout(hp), interior_slices(pv)
+
+    def f(ps_):
+        full = np.ones_like(prim[0])
+        full[L] = ps_[I]
+        out = np.zeros(shape(pv))
+        out[I] = fluid_stilde_curvilinear(hp, full, prim)[L]
+        return out
+
+    return f
+
+
 def metric_update(hp, ppsi, palpha, q, prim, met, tol=1e-12, max_cycles=60, pvec=None, X=None):
     """The metric of a GRMHD state re-solved from its conserved variables
     (section 2.6), then the primitives recovered on the new metric (section
@@ -508,11 +514,8 @@ def metric_update(hp, ppsi, palpha, q, prim, met, tol=1e-12, max_cycles=60, pvec
         # initial guess of alpha psi from the metric as given (the converged
         # solution does not depend on it beyond the tolerance)
         ua = _to_mg(palpha, hp, met[1] * met[0] - 1.0)
-        rho, P = _to_mg(pvec, hp, prim[0]), _to_mg(pvec, hp, prim[4])
-        # orthonormal components h_c W v^c, so that W^2 v^2 = psi^4 sum (W v)^2
-        wv = [_to_mg(pvec, hp, prim[1 + c] * hs[c]) for c in range(3)]
-        _, _, cyc = xcfc_solve(pvec, ppsi, palpha, U, S, lambda ps_: fluid_stilde(ps_, rho, wv, P, hp["gamma"]),
-                               X, up, ua, beta, tol, max_cycles)
+        _, _, cyc = xcfc_solve(pvec, ppsi, palpha, U, S, stilde_fn(hp, pvec, prim), X, up, ua, beta, tol,
+                               max_cycles)
         met[0] = 1.0 + extend(hp, ppsi, up)
         met[1] = (1.0 + extend(hp, palpha, ua)) / met[0]
         for c in range(3):

@@ -508,12 +508,10 @@ def test_xcfc_solve_matches_the_oracle():
 
     U = to_mg(q[4] + q[0])
     S = np.ascontiguousarray(np.stack([to_mg(q[1 + i]) for i in range(3)]))
-    rho, P = to_mg(pr[0]), to_mg(pr[4])
-    wv = [to_mg(pr[1 + i]) for i in range(3)]
     Xo, beta = np.zeros((3,) + mg.shape(pv)), np.zeros((3,) + mg.shape(pv))
     up, ua = np.zeros(mg.shape(pv)), np.zeros(mg.shape(pv))
-    psi, alpha, cyc_o = mg.xcfc_solve(pv, ps, pa, U, S, lambda ps_: mg.fluid_stilde(ps_, rho, wv, P, 2.0), Xo, up, ua,
-                                      beta, tol=1e-12, max_cycles=60)
+    psi, alpha, cyc_o = mg.xcfc_solve(pv, ps, pa, U, S, mg.stilde_fn(hp, pv, pr), Xo, up, ua, beta, tol=1e-12,
+                                      max_cycles=60)
     note(f"  oracle cycles {cyc_o}")
     Xh = host(Xg)
     I = lambda a: mg.interior(pv, a)  # noqa: E731

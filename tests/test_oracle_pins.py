@@ -418,6 +418,38 @@ def test_shock_tube_converges_to_exact_solution(bx):
     assert errs[0] / errs[1] > 2.8
 
 
+@pytest.mark.parametrize("beta", [0.3, -0.2])
+def test_shock_tube_with_uniform_shift_is_the_translated_solution(beta):
+    """Flat space with a uniform shift beta^x is Minkowski space seen from
+    coordinates in which the normal observers move at dx/dt = -beta; the
+    Eulerian velocity is measured by those observers, so the exact solution
+    is the unshifted one translated: rho(x, t) = rho_exact(x + beta t, t).
+    This pins the shift in the fluxes (alpha v - beta) and in the wave
+    speeds (coordinate speeds lambda - beta; the CFL step uses them too):
+    first-order L1 convergence to the translated solution, with errors like
+    the unshifted tube's."""
+    rs = RiemannSRHD((10, 40 / 3, 0), (1, 0, 0), 5 / 3)
+    errs = []
+    for n in (100, 400):
+        p, pr, met = W.srhd_shock_tube(n)
+        met[2] = beta
+        oracle.fill_ghosts(p, pr)
+        q = oracle.prim2con(p, pr, met)
+        s, t, nf = oracle.evolve(p, q, pr, met, 0.4, 0.0, 0.4)
+        assert nf == 0 and abs(t - 0.4) < 1e-14
+        prim = oracle.interior(p, pr)[:, 0, 0]
+        dx = p["dx"][0]
+        sh = beta * 0.4
+        ex = np.array([rs.cell_average(i * dx + sh, (i + 1) * dx + sh, 0.4, 0.5)[0] for i in range(n)])
+        errs.append(np.sum(np.abs(prim[0] - ex)) * dx)
+    assert errs[1] < 0.035
+    assert errs[0] / errs[1] > 2.8
+    # the untranslated solution is far from it (the pin sees the shift)
+    dx = p["dx"][0]
+    ex0 = np.array([rs.cell_average(i * dx, (i + 1) * dx, 0.4, 0.5)[0] for i in range(400)])
+    assert np.sum(np.abs(prim[0] - ex0)) * dx > 10 * errs[1]
+
+
 def test_alfven_wave_convergence_matches_paper_rates():
     """Circularly polarised Alfven wave (section 3.2.1): v_A = 1/2 exactly, so
     at t = 2 the exact state is the initial one.  HLL + MC + SSPRK2 rates of
