@@ -20,8 +20,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-updates/s per RK stage, FP64 256^3; p50/p99 latency, batched vs plain"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic HBM bytes of the stage kernel per interior cell: reads prim (8),
-# metric (5), q_n (8), q_s (8, stages after the first), writes q_out (8).
+FP64_PEAK_TFLOPS = 78.6
+# Algorithmic HBM bytes of one RK stage per interior cell (the unavoidable
+# traffic of a stage that keeps no primitives in memory): stage 1 reads q_n
+# (8 doubles) and the metric (5) and writes q_1 (8); stages 2 and 3 also read
+# q_n: 168, 232, 232 B, 211 B per cell-stage on average.  The roofline
+# fraction of the stage kernel and of the whole step use these.
+ALG_BYTES = {0: 21 * 8, 1: 29 * 8, 2: 29 * 8}
+# The bytes this design's stage kernel itself must move per interior cell:
+# it reads the primitives (8) that the separate recovery kernel wrote, the
+# metric (5), q_n (8), q_s (8, stages after the first), and writes q_out (8).
 STAGE_BYTES = {0: 29 * 8, 1: 37 * 8, 2: 37 * 8}
 
 
@@ -45,9 +53,10 @@ def stage_source_hash():
     return h.hexdigest()
 
 
-def kernel_traffic():
-    """HBM bytes per stage launch from the committed rocprofv3 counters, if
-    the kernel sources are unchanged since they were taken (else None)."""
+def kernel_counters():
+    """The committed rocprofv3 counter record of the stage kernel on this
+    workload (HBM bytes per launch, FP64 instruction counts), if the kernel
+    sources are unchanged since it was taken (else None)."""
 
     path = os.path.join(ROOT, "profiles", "k_stage_blast3d_256_traffic.json")
     if not os.path.exists(path):
@@ -55,7 +64,7 @@ def kernel_traffic():
     rec = json.load(open(path))
     if stage_source_hash() != rec.get("source_sha256"):
         return None
-    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return rec
 
 
 def log(*a):
@@ -88,14 +97,76 @@ def cpu_baseline(n, slab, seed=0):
     pr[0] = 0.01 * (1.0 + 1e-4 * W.uniform(seed, gidx))
     met = W.flat_metric(ps)
     oracle.fill_ghosts(ps, pr)
-    q = oracle.prim2con(ps, pr, met)
-    t0 = time.perf_counter()
-    steps, _, _ = oracle.evolve(ps, q, pr, met, 0.4, 0.0, 1e30, nsteps=1)
-    el = time.perf_counter() - t0
     cells = n * n * slab
-    return {"value": cells * 3 * steps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one SSPRK3 step (3 stages + CFL) of a {n}x{n}x{slab} slab through the blast centre, "
-                      f"{el:.1f} s on 1 host core"}
+    sample = f"one SSPRK3 step (3 stages + CFL) of a {n}x{n}x{slab} slab through the blast centre"
+    res = {}
+    # the oracle as it is, single threaded; then the same source built with
+    # OpenMP over its per-cell loops on every host core
+    for omp in (False, True):
+        oracle.use_openmp(omp)
+        nth = oracle.threads()
+        prc = pr.copy()
+        q = oracle.prim2con(ps, prc, met)
+        t0 = time.perf_counter()
+        steps, _, _ = oracle.evolve(ps, q, prc, met, 0.4, 0.0, 1e30, nsteps=1)
+        el = time.perf_counter() - t0
+        res[omp] = {"value": cells * 3 * steps / el, "unit": "cell-updates/s", "cores": nth, "kind": "oracle",
+                    "sample": f"{sample}, {el:.2f} s on {nth} host thread{'s' if nth > 1 else ''}"}
+    oracle.use_openmp(False)
+    out = dict(res[True])
+    out["host_cpus"] = os.cpu_count()
+    out["single_core"] = res[False]
+    return out
+
+
+def bench_star(nr=256, nth=128, steps=1000, cfl=0.4):
+    """The static magnetised TOV star on a 2D spherical (r, theta) grid,
+    Cowling (frozen metric), SSPRK3 steps: cell-updates/s per stage, the
+    rest-mass drift, the angular momentum sum, recovery flags at the end."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2012_07322_amd as gmu
+    import workloads as W
+
+    p, pr, met = W.magnetised_star_2d(nr, nth)
+    dev = torch.device("cuda:0")
+    g = gmu.Grid(p)
+    prim = torch.from_numpy(pr).to(dev)
+    metric = torch.from_numpy(met).to(dev)
+    g.fill_ghosts(prim)
+    qn = g.prim2con(prim, metric)
+    g.c2p(qn, metric, prim)
+    g.fill_ghosts(prim)
+    qs = torch.zeros_like(qn)
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    dt = torch.zeros_like(t)
+    nf = torch.zeros(1, dtype=torch.int32, device=dev)
+    fl = torch.zeros(g.shape, dtype=torch.uint8, device=dev)
+    dV = oracle.interior(p, oracle.cell_volumes(p))
+    q0 = oracle.interior(p, qn.cpu().numpy())
+    m0 = float((q0[0] * dV).sum())
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.step(qn, qs, prim, metric, cfl, 1e30, t, dt, fl, nf)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    q1 = oracle.interior(p, qn.cpu().numpy())
+    f1 = oracle.interior(p, fl.cpu().numpy())
+    m1 = float((q1[0] * dV).sum())
+    cells = nr * nth
+    flags = {name: int(((f1 & bit) != 0).sum()) for name, bit in
+             (("atmo", 1), ("eps_clamp", 2), ("v_clamp", 4), ("fatal", 8 | 16 | 32 | 64))}
+    g.close()
+    return {"workload": f"magnetised TOV star, spherical {nr}x{nth}, Cowling", "steps": steps,
+            "ms_per_step": ms / steps, "cell_updates_per_s": cells * 3 * steps / (ms * 1e-3),
+            "t_end": float(t.item()), "rest_mass_drift": (m1 - m0) / m0,
+            "angular_momentum_sum": float((q1[3] * dV).sum()), "flags_last_stage": flags,
+            "nfatal": int(nf.item())}
 
 
 def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True):
@@ -657,6 +728,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-slab", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--star-steps", type=int, default=1000,
+                    help="steps of the 256x128 spherical star (0: skip)")
     ap.add_argument("--blocks", type=int, default=3000,
                     help="AMR-style blocks for the batched-vs-plain comparison (0: skip)")
     ap.add_argument("--block-steps", type=int, default=5)
@@ -737,9 +810,18 @@ def main():
     stages = 3 * args.steps
     value = cells * stages / (ms * 1e-3)
     st_ms, st_cnt = prof["stage"]
-    bytes_total = cells * sum(STAGE_BYTES[s] for s in range(3)) * args.steps
-    achieved = bytes_total / (st_ms * 1e-3) / 1e9 if st_ms > 0 else None
-    traffic = kernel_traffic() if n == 256 else None
+    alg_total = cells * sum(ALG_BYTES[s] for s in range(3)) * args.steps
+    achieved = alg_total / (st_ms * 1e-3) / 1e9 if st_ms > 0 else None
+    design_total = cells * sum(STAGE_BYTES[s] for s in range(3)) * args.steps
+    design_gbs = design_total / (st_ms * 1e-3) / 1e9 if st_ms > 0 else None
+    step_gbs = alg_total / (ms * 1e-3) / 1e9
+    rec = kernel_counters() if n == 256 else None
+    traffic = rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"] if rec else None
+    valu = None
+    if rec and rec.get("fp64_flop_per_launch"):
+        tf = rec["fp64_flop_per_launch"] / (st_ms / max(st_cnt, 1) * 1e-3) / 1e12
+        valu = {"fp64_tflops": tf, "peak": FP64_PEAK_TFLOPS, "frac": tf / FP64_PEAK_TFLOPS,
+                "valu_busy": rec.get("valu_busy"), "from": rec.get("from")}
     breakdown = {k: {"ms_avg": (v[0] / v[1] if v[1] else None), "launches": v[1]} for k, v in prof.items()}
     out = {
         "metric": METRIC,
@@ -759,13 +841,22 @@ def main():
                    "cfl": args.cfl, "gamma": 4.0 / 3.0, "seed": args.seed},
         "roofline": {"bound": "hbm", "kernel": "k_stage", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS if achieved else None), "traffic": traffic,
-                     "bytes_per_cell_step": sum(STAGE_BYTES.values()), "stage_ms_avg": st_ms / max(st_cnt, 1)},
+                     "bytes_per_cell_stage": sum(ALG_BYTES.values()) / 3.0, "stage_ms_avg": st_ms / max(st_cnt, 1),
+                     "step": {"achieved": step_gbs, "frac": step_gbs / HBM_PEAK_GBS,
+                              "bytes_per_cell_step": sum(ALG_BYTES.values())},
+                     "design": {"bytes_per_cell_stage": sum(STAGE_BYTES.values()) / 3.0, "achieved": design_gbs,
+                                "frac": (design_gbs / HBM_PEAK_GBS if design_gbs else None)},
+                     "fp64_valu": valu},
         "breakdown": breakdown,
         "nfatal": nfatal,
     }
     del qn, qs, prim, metric
     g.close()
     torch.cuda.empty_cache()
+    if args.star_steps > 0:
+        log(f"[bench] star 256x128, {args.star_steps} steps")
+        out["star2d"] = bench_star(256, 128, args.star_steps, cfl=args.cfl)
+        torch.cuda.empty_cache()
     if args.blocks > 0:
         out["blocks"] = bench_blocks(args.blocks, steps=args.block_steps, cfl=args.cfl, seed=args.seed)
         torch.cuda.empty_cache()

@@ -23,15 +23,39 @@ FLAG_ATMO, FLAG_EPS_CLAMP, FLAG_V_CLAMP = 1, 2, 4
 FLAG_FATAL_RHO, FLAG_FATAL_EPS, FLAG_FATAL_V, FLAG_NOCONV = 8, 16, 32, 64
 
 
+_LIB_OMP = os.path.join(_HERE, "_build", "liboracle_omp.so")
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc into oracle/_build/liboracle.so."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+    """Compile the oracle with gcc into oracle/_build/liboracle.so (single
+    threaded: the checker), and the same source with -fopenmp into
+    liboracle_omp.so (its per-cell loops on all host cores: only for the
+    all-cores CPU timing)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC) and \
+            os.path.exists(_LIB_OMP) and os.path.getmtime(_LIB_OMP) >= os.path.getmtime(_SRC):
         return _LIB
     os.makedirs(os.path.dirname(_LIB), exist_ok=True)
-    tmp = _LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
-    os.replace(tmp, _LIB)
+    for out, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, *extra, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
     return _LIB
+
+
+def threads() -> int:
+    """Threads of the loaded build's per-cell loops."""
+    return int(lib().og_threads())
+
+
+def use_openmp(on: bool):
+    """Route the oracle's calls to the all-cores build (on) or back to the
+    single-threaded one; results are the same (cells are independent and the
+    time-step maximum is exact)."""
+    global _lib, _LIB
+    want = _LIB_OMP if on else os.path.join(_HERE, "_build", "liboracle.so")
+    if _LIB != want:
+        _LIB = want
+        _lib = None
 
 
 class _Desc(ctypes.Structure):
@@ -61,6 +85,7 @@ def lib():
         L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         L.og_desc_size.restype = ctypes.c_int
+        L.og_threads.restype = ctypes.c_int
         L.og_ntot.restype = ctypes.c_long
         L.og_ntot.argtypes = [P]
         L.og_index.restype = ctypes.c_long

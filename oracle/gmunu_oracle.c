@@ -1148,6 +1148,9 @@ void og_prim2con(const og_desc *d, const double *prim, const double *met, double
  * number of cells with a fatal flag. */
 long og_c2p(const og_desc *d, double *q, const double *met, double *prim, uint8_t *flags) {
   long nt = ntot(d), nfatal = 0;
+  /* cells are independent; the pragma only acts in the all-cores timing
+   * build (-fopenmp) */
+#pragma omp parallel for collapse(2) reduction(+ : nfatal)
   for (int k = 0; k < d->n[2]; k++)
     for (int j = 0; j < d->n[1]; j++)
       for (int i = 0; i < d->n[0]; i++) {
@@ -1236,6 +1239,7 @@ void og_fill_ghosts(const og_desc *d, double *prim) {
 double og_cfl_dt(const og_desc *d, const double *prim, const double *met, double cfl, double t, double t_end) {
   long nt = ntot(d);
   double mx = 0.0;
+#pragma omp parallel for collapse(2) reduction(max : mx)
   for (int k = 0; k < d->n[2]; k++)
     for (int j = 0; j < d->n[1]; j++)
       for (int i = 0; i < d->n[0]; i++) {
@@ -1285,6 +1289,7 @@ void og_rk_update_k(const og_desc *d, int stage, double dt, const double *qn, do
   double *L = (double *)malloc(sizeof(double) * NV * nt);
   /* the stage's Euler step starts from q_n in stage 0, from q_s after */
   pp_ctx pp = {dt, stage == 0 ? qn : qs};
+#pragma omp parallel for collapse(2)
   for (int k = 0; k < d->n[2]; k++)
     for (int j = 0; j < d->n[1]; j++)
       for (int i = 0; i < d->n[0]; i++) {
@@ -1293,6 +1298,7 @@ void og_rk_update_k(const og_desc *d, int stage, double dt, const double *qn, do
         long c = at(d, i, j, k);
         for (int v = 0; v < NV; v++) L[v * nt + c] = dq[v];
       }
+#pragma omp parallel for collapse(2)
   for (int k = 0; k < d->n[2]; k++)
     for (int j = 0; j < d->n[1]; j++)
       for (int i = 0; i < d->n[0]; i++) {
@@ -1385,6 +1391,14 @@ void og_cell_geometry(const og_desc *d, int i, int j, int k, double out[12]) {
     out[11] = 1.0 / R;
   }
 }
+
+/* Threads the per-cell loops use (1 unless built with -fopenmp). */
+#ifdef _OPENMP
+#include <omp.h>
+int og_threads(void) { return omp_get_max_threads(); }
+#else
+int og_threads(void) { return 1; }
+#endif
 
 long og_ntot(const og_desc *d) { return ntot(d); }
 long og_index(const og_desc *d, int i, int j, int k) { return at(d, i, j, k); }

@@ -59,7 +59,7 @@ def forward_error(Lg, L_or):
 EPS = np.finfo(np.float64).eps
 
 
-def rhs_check(p, pr, met, tol=1e-12, cells=None, fwd_tol=1e-12):
+def rhs_check(p, pr, met, tol=1e-12, cells=None, fwd_tol=1e-12, kij=None):
     """GPU RHS vs oracle RHS on all (or the given) interior cells.
 
     Two measures, both asserted.
@@ -77,11 +77,11 @@ def rhs_check(p, pr, met, tol=1e-12, cells=None, fwd_tol=1e-12):
     i.e. forward error <= 4 eps kappa with kappa = max(scale) / max|oracle|.
     fwd_tol=None asserts only (1) (exact RHS 0: uniform static states)."""
     g = gmu.Grid(p)
-    L_gpu = host(g.rhs(dev(pr), dev(met)))
+    L_gpu = host(g.rhs(dev(pr), dev(met), kij=None if kij is None else dev(kij)))
     if cells is None:
         cells = all_cells(p)
-    L_or = oracle.rhs_cells(p, pr, met, cells)
-    sc = oracle.rhs_scale_cells(p, pr, met, cells)
+    L_or = oracle.rhs_cells(p, pr, met, cells, kij=kij)
+    sc = oracle.rhs_scale_cells(p, pr, met, cells, kij=kij)
     gs = W.ghosts(p)
     Lg = L_gpu[:, cells[:, 2] + gs[2], cells[:, 1] + gs[1], cells[:, 0] + gs[0]].T
     err = np.abs(Lg - L_or) / (sc + 1e-300)
@@ -289,6 +289,67 @@ def test_rhs_parity_curvilinear_general_metric(coord, ndim, beta):
         p = W.grid(ndim, coord, n, [0, 0, 0], [1, 1, 1], [[1, 1]] * ndim)
     pr, met = smooth_random_state(p, beta_amp=beta)
     rhs_check(p, pr, met)
+
+
+def smooth_kij(p, amp=0.05):
+    """A smooth extrinsic-curvature field (6 covariant components) of the
+    size the shift of smooth_random_state produces."""
+    x1, x2, x3 = W.centres(p)
+    K = np.zeros((6,) + W.shape(p))
+    for m in range(6):
+        K[m] = amp * np.sin(0.7 * x1 + 0.3 * m) * np.cos(0.5 * x2 - 0.2 * m) + 0.3 * amp * np.sin(x3 + m)
+    return K
+
+
+@pytest.mark.parametrize("coord,ndim", [(W.CART, 3), (W.SPH, 2), (W.CYL, 3)])
+def test_rhs_parity_with_supplied_kij(coord, ndim):
+    """gmunu_rhs with a K_ij array (instead of K_ij from the shift) against
+    the oracle given the same K_ij; the supplied K_ij changes the result."""
+    n = [11, 9, 7][:ndim]
+    if coord == W.CYL:
+        p = W.grid(ndim, coord, n, [0.4, -1, 0], [2.0, 1, 2 * math.pi], [[1, 1]] * ndim)
+    elif coord == W.SPH:
+        p = W.grid(ndim, coord, n, [0.5, 0.3, 0], [2.5, math.pi - 0.3, 2 * math.pi], [[1, 1]] * ndim)
+    else:
+        p = W.grid(ndim, coord, n, [0, 0, 0], [1, 1, 1], [[1, 1]] * ndim)
+    pr, met = smooth_random_state(p, beta_amp=0.05)
+    K = smooth_kij(p)
+    rhs_check(p, pr, met, kij=K)
+    g = gmu.Grid(p)
+    a = host(g.rhs(dev(pr), dev(met), kij=dev(K)))
+    b = host(g.rhs(dev(pr), dev(met)))
+    assert np.abs(W.interior(p, a)[4] - W.interior(p, b)[4]).max() > 1e-6 * np.abs(W.interior(p, b)[4]).max()
+
+
+def test_stage_parity_with_supplied_kij():
+    """One RK stage (gmunu_rk_stage, stage 0 then stage 1) with a K_ij array
+    against the oracle's stages with the same K_ij; a misaligned K_ij
+    pointer is rejected."""
+    p = W.grid(2, W.SPH, [12, 10], [0.5, 0.3, 0], [2.5, math.pi - 0.3, 2 * math.pi], [[1, 1]] * 2)
+    pr, met = smooth_random_state(p, beta_amp=0.05)
+    K = smooth_kij(p)
+    oracle.fill_ghosts(p, pr)
+    q0 = oracle.prim2con(p, pr, met)
+    dt = 1e-3
+    g = gmu.Grid(p)
+    qn, prd, metd, Kd = dev(q0), dev(pr), dev(met), dev(K)
+    qs = torch.zeros_like(qn)
+    dtd = torch.full((1,), dt, dtype=torch.float64, device="cuda")
+    g.rk_stage(0, dtd, qn, qs, qs, prd, prd, metd, kij=Kd)
+    g.rk_stage(1, dtd, qn, qs, qs, prd, prd, metd, kij=Kd)
+    qo, po, qso = q0.copy(), pr.copy(), q0.copy()
+    oracle.rk_stage(p, 0, dt, qo, qso, po, met, kij=K)
+    oracle.rk_stage(p, 1, dt, qo, qso, po, met, kij=K)
+    A, B = W.interior(p, host(qs)), W.interior(p, qso)
+    err = max(np.abs(A[v] - B[v]).max() / (np.abs(B[v]).max() + 1e-300) for v in range(8))
+    note(f"  two stages with K_ij: max err / max |q| per variable = {err:.2e}")
+    assert err <= 1e-13
+    bad = torch.zeros(6 * K[0].size + 1, dtype=torch.float64, device="cuda")
+    import ctypes
+    L = gmu.lib()
+    rc = L.gmunu_rhs(g._h, ctypes.c_void_p(prd.data_ptr()), ctypes.c_void_p(metd.data_ptr()),
+                     ctypes.c_void_p(bad.data_ptr() + 4), ctypes.c_void_p(qs.data_ptr()), None)
+    assert rc == -3
 
 
 def test_rhs_parity_uniform_and_degenerate():

@@ -955,3 +955,20 @@ def test_pp_limiter_conserves_and_keeps_a_vacuum_forming_flow_positive():
     I = oracle.interior(p, q)
     assert I[0].min() > 0 and I[4].min() > 0
     assert abs(I[0].sum() - mass0) <= 1e-12 * mass0
+
+
+def test_openmp_build_gives_the_same_results():
+    """The all-cores build of the oracle (used only for CPU timing) runs the
+    same per-cell arithmetic: one SSPRK3 step of a small blast equals the
+    single-threaded oracle bit for bit."""
+    p, pr, met = W.blast_wave_3d(12)
+    out = []
+    for omp in (False, True):
+        oracle.use_openmp(omp)
+        prc = pr.copy()
+        oracle.fill_ghosts(p, prc)
+        q = oracle.prim2con(p, prc, met)
+        oracle.evolve(p, q, prc, met, 0.4, 0.0, 1e30, nsteps=2)
+        out.append((q, prc))
+    oracle.use_openmp(False)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
