@@ -197,6 +197,23 @@ int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const dou
                double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
                void *stream);
 
+/* One step as gmunu_step, without a context and without allocating: for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  The grid's geometry
+ * tables (computed on the device from desc at every call, with the device's
+ * sine and cosine; the same values as a context's for Cartesian grids, within
+ * an ulp for curvilinear ones) and the CFL partial maxima live in one
+ * file-scope device array per GPU of about 1.1 MB, held until the process
+ * ends.  Limit: at most 8192 cells per axis, ghosts included (GMUNU_EINVAL
+ * beyond); the positivity-preserving limiter is not available here (its
+ * middle SSPRK3 stage needs a third state: GMUNU_EINVAL).  Every call on one
+ * GPU shares that array: calls that may overlap on one GPU (different
+ * streams, or host threads) race and must be serialised by the caller.
+ * Arguments, layouts and errors otherwise as gmunu_step. */
+int gmunu_step_static(const gmunu_grid_desc *desc, double *q_n, double *q_s, double *prim, const double *metric,
+                      const double *kij, double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags,
+                      unsigned int *nfatal_dev, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched stage: many independent grids ("blocks": uneven AMR-style blocks
  * of one simulation, or many simulations) advanced together by persistent

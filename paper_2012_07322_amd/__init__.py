@@ -68,6 +68,7 @@ def lib():
         L.gmunu_cfl_dt.argtypes = [_P, _P, _P, D, D, _P, _P, _P]
         L.gmunu_rk_stage.argtypes = [_P, I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
         L.gmunu_step.argtypes = [_P, _P, _P, _P, _P, _P, D, D, _P, _P, _P, _P, _P]
+        L.gmunu_step_static.argtypes = [_P, _P, _P, _P, _P, _P, D, D, _P, _P, _P, _P, _P]
         L.gmunu_profile.argtypes = [_P, I, I]
         L.gmunu_profile_read.argtypes = [_P, _P, _P]
         _lib = L
@@ -241,6 +242,27 @@ class Grid:
             if float(t.item()) >= t_end:
                 break
         return qn, qs, float(t.item())
+
+
+def step_static(params, q_n, q_s, prim, metric, cfl, t_end, t_dev, dt_dev, flags=None, nfatal=None, kij=None):
+    """One step without a context (gmunu_step_static): geometry and CFL
+    partials in the library's static per-GPU scratch, nothing allocated."""
+    d = make_desc(params)
+    g = [d.ng if a < d.ndim else 0 for a in range(3)]
+    shp = (d.n[2] + 2 * g[2], d.n[1] + 2 * g[1], d.n[0] + 2 * g[0])
+
+    def chk(t, nv, what):
+        if t is None:
+            return None
+        if tuple(t.shape) != (nv,) + shp:
+            raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {(nv,) + shp}")
+        return _ptr(t, what)
+
+    fp = _ptr(flags, "flags", torch.uint8) if flags is not None else None
+    npn = _ptr(nfatal, "nfatal", torch.int32) if nfatal is not None else None
+    _check(lib().gmunu_step_static(ctypes.byref(d), chk(q_n, 8, "q_n"), chk(q_s, 8, "q_s"), chk(prim, 8, "prim"),
+                                   chk(metric, 5, "metric"), chk(kij, 6, "kij"), cfl, t_end, _ptr(t_dev, "t"),
+                                   _ptr(dt_dev, "dt"), fp, npn, _stream()), "gmunu_step_static")
 
 
 # ------------------------------------------------------------------- batch

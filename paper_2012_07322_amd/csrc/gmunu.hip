@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -224,6 +225,10 @@ int rk_stage_impl(gmunu_ctx *ctx, int stage, const double *dt_dev, const double 
   return launch_ghosts(ctx, prim_out, skipp, st);
 }
 
+int step_impl(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, const double *kij,
+              double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
+              void *stream);
+
 }  // namespace
 
 // --------------------------------------------------------------------- API
@@ -357,6 +362,18 @@ int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const dou
                void *stream) {
   if (!ctx || !q_n || !q_s || !prim || !metric || !t_dev || !dt_dev) return GMUNU_ENULL;
   if (!aligned8(kij)) return GMUNU_EALIGN;
+  return step_impl(ctx, q_n, q_s, prim, metric, kij, cfl, t_end, t_dev, dt_dev, flags, nfatal_dev, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The launches of one step (gmunu_step), on a context whose geometry tables
+// and CFL partials are in place.
+int step_impl(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, const double *kij,
+              double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
+              void *stream) {
   int rc = gmunu_cfl_dt(ctx, prim, metric, cfl, t_end, t_dev, dt_dev, stream);
   if (rc) return rc;
   const int nst = ctx->d.rk;
@@ -377,6 +394,10 @@ int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const dou
   }
   return launch_status();
 }
+
+}  // namespace
+
+extern "C" {
 
 int gmunu_profile(gmunu_ctx *ctx, int enable, int max_launches) {
   if (!ctx) return GMUNU_ENULL;
@@ -410,6 +431,163 @@ int gmunu_profile_read(gmunu_ctx *ctx, double *ms_out, long *count_out) {
   }
   ctx->nrec = 0;
   return GMUNU_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- allocation-free step
+
+namespace {
+
+// Capacity of the file-scope scratch: geometry tables of grids with at most
+// kStaticAxis cells per axis (ghosts included), then the CFL partials.
+constexpr int kStaticAxis = 8192;
+constexpr size_t kStaticGeo = 16 * (size_t)(kStaticAxis + 1);
+constexpr size_t kStaticWords = kStaticGeo + kCflParts;
+
+}  // namespace
+
+// The scratch of gmunu_step_static (one copy per GPU, held until the process
+// ends).  In host code this name is a stand-in, not a device address: host
+// code uses only the address hipGetSymbolAddress gives for the current
+// device (static_scratch()).
+static __device__ __align__(256) double scratch[kStaticWords];
+
+namespace {
+
+struct GeoParams {
+  int coord, nt[3], g[3];
+  double xmin[3], dx[3];
+};
+
+// The geometry tables of setup_grid (Appendix A), computed on the device:
+// one thread per table index.  The products and sums are rounded one at a
+// time as on the host; sines and cosines are the device's.
+__global__ __launch_bounds__(NT) void k_geo(const GeoParams p, double *tab, const GeoOffsets o) {
+  const int t = blockIdx.x * NT + threadIdx.x;
+  auto xc = [&](int a, int I) { return __dadd_rn(p.xmin[a], __dmul_rn((double)(I - p.g[a]) + 0.5, p.dx[a])); };
+  auto xf = [&](int a, int F) { return __dadd_rn(p.xmin[a], __dmul_rn((double)(F - p.g[a]), p.dx[a])); };
+  auto cv = [&](int a, int I) {
+    const double x = xc(a, I), d = p.dx[a];
+    if (p.coord == GMUNU_CYL && a == 0) return __dmul_rn(x, d);
+    if (p.coord == GMUNU_SPH && a == 0) return __dmul_rn(__dadd_rn(__dmul_rn(x, x), __ddiv_rn(__dmul_rn(d, d), 12.0)), d);
+    if (p.coord == GMUNU_SPH && a == 1) return __dmul_rn(__dmul_rn(2.0, sin(x)), sin(__dmul_rn(0.5, d)));
+    return d;
+  };
+  for (int a = 0; a < 3; a++) {
+    if (t < p.nt[a]) tab[o.icv[a] + t] = __ddiv_rn(1.0, cv(a, t));
+    if (t <= p.nt[a]) {
+      const double x = xf(a, t);
+      double f = 1.0;
+      if (p.coord == GMUNU_CYL && a == 0) f = x;
+      if (p.coord == GMUNU_SPH && a == 0) f = __dmul_rn(x, x);
+      if (p.coord == GMUNU_SPH && a == 1) f = sin(x);
+      tab[o.fa[a] + t] = f;
+    }
+  }
+  if (t < p.nt[0]) {
+    const double x = xc(0, t);
+    tab[o.r2c + t] = __dmul_rn(x, x);
+    tab[o.xc0 + t] = x;
+    double gA = 0.0, gB = 0.0;
+    if (p.coord == GMUNU_SPH) {
+      const double xp = xf(0, t + 1), xm = xf(0, t);
+      const double p2 = __dmul_rn(xp, xp), m2 = __dmul_rn(xm, xm), v = cv(0, t);
+      gA = __ddiv_rn(__dmul_rn(0.5, __dsub_rn(p2, m2)), v);
+      gB = __ddiv_rn(__dmul_rn(-0.25, __dsub_rn(__dmul_rn(p2, p2), __dmul_rn(m2, m2))), v);
+    } else if (p.coord == GMUNU_CYL) {
+      gA = __ddiv_rn(1.0, x);
+    }
+    tab[o.gA + t] = gA;
+    tab[o.gB + t] = gB;
+  }
+  if (t <= p.nt[0]) {
+    const double x = xf(0, t);
+    tab[o.r2f + t] = __dmul_rn(x, x);
+  }
+  if (t < p.nt[1]) {
+    const double x = xc(1, t), sn = sin(x);
+    tab[o.sc + t] = sn;
+    tab[o.cc + t] = cos(x);
+    tab[o.s2c + t] = __dmul_rn(sn, sn);
+    tab[o.gC + t] = p.coord == GMUNU_SPH ? __ddiv_rn(__dsub_rn(sin(xf(1, t + 1)), sin(xf(1, t))), cv(1, t)) : 0.0;
+  }
+  if (t <= p.nt[1]) {
+    const double sn = sin(xf(1, t));
+    tab[o.s2f + t] = __dmul_rn(sn, sn);
+  }
+}
+
+// Device address of the scratch on each device, taken once per device (the
+// first call with that device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+int static_scratch(double **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GMUNU_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return GMUNU_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GMUNU_EHIP;
+    g_scratch[dev] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch[dev];
+  return GMUNU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gmunu_step_static(const gmunu_grid_desc *desc, double *q_n, double *q_s, double *prim, const double *metric,
+                      const double *kij, double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags,
+                      unsigned int *nfatal_dev, void *stream) {
+  if (!desc || !q_n || !q_s || !prim || !metric || !t_dev || !dt_dev) return GMUNU_ENULL;
+  if (!aligned8(q_n) || !aligned8(q_s) || !aligned8(prim) || !aligned8(metric) || !aligned8(kij) ||
+      !aligned8(t_dev) || !aligned8(dt_dev))
+    return GMUNU_EALIGN;
+  int rc = validate_desc(*desc);
+  if (rc) return rc;
+  // the limiter's middle SSPRK3 stage needs a third state, which a context
+  // would hold
+  if (desc->pp_limiter) return GMUNU_EINVAL;
+  if (!(cfl > 0.0)) return GMUNU_EINVAL;
+  // a context on the stack: its vectors stay empty (no allocation)
+  gmunu_ctx ctx;
+  ctx.d = *desc;
+  ctx.prof = 0;
+  ctx.nrec = 0;
+  ctx.qt = nullptr;
+  grid_scalars(*desc, ctx.G);
+  for (int a = 0; a < 3; a++)
+    if (ctx.G.nt[a] > kStaticAxis) return GMUNU_EINVAL;  // beyond the scratch's tables
+  double *sp = nullptr;
+  rc = static_scratch(&sp);
+  if (rc) return rc;
+  size_t words = 0;
+  const GeoOffsets off = geo_layout(ctx.G.nt, words);
+  if (words > kStaticGeo) return GMUNU_EINVAL;
+  ctx.geo = sp;
+  ctx.acc = sp + kStaticGeo;
+  if (hipGetDevice(&ctx.device) != hipSuccess) return GMUNU_EHIP;
+  bind_geo(ctx.G, ctx.geo, off);
+  GeoParams gp;
+  gp.coord = desc->coord;
+  for (int a = 0; a < 3; a++) {
+    gp.nt[a] = ctx.G.nt[a];
+    gp.g[a] = ctx.G.g[a];
+    gp.xmin[a] = desc->xmin[a];
+    gp.dx[a] = desc->dx[a];
+  }
+  int len = 0;
+  for (int a = 0; a < 3; a++) len = ctx.G.nt[a] + 1 > len ? ctx.G.nt[a] + 1 : len;
+  hipLaunchKernelGGL(k_geo, dim3(nblocks(len)), dim3(NT), 0, as_stream(stream), gp, ctx.geo, off);
+  rc = launch_status();
+  if (rc) return rc;
+  return step_impl(&ctx, q_n, q_s, prim, metric, kij, cfl, t_end, t_dev, dt_dev, flags, nfatal_dev, stream);
 }
 
 }  // extern "C"

@@ -58,9 +58,8 @@ struct GeoOffsets {
   size_t icv[3], fa[3], r2c, r2f, s2c, s2f, xc0, sc, cc, gA, gB, gC;
 };
 
-// Fill G (all but the geometry pointers) and append the grid's 1D geometry
-// tables to tab.
-inline GeoOffsets setup_grid(const gmunu_grid_desc &d, Grid &G, std::vector<double> &tab) {
+// Fill G's scalar parameters (all but the geometry pointers).
+inline void grid_scalars(const gmunu_grid_desc &d, Grid &G) {
   std::memset(&G, 0, sizeof(G));
   G.ndim = d.ndim;
   G.coord = d.coord;
@@ -94,6 +93,41 @@ inline GeoOffsets setup_grid(const gmunu_grid_desc &d, Grid &G, std::vector<doub
   G.riemann = d.riemann;
   G.c2p = d.c2p;
   G.pp = d.pp_limiter;
+}
+
+// Offsets of the geometry tables of a grid with nt cells per axis (ghosts
+// included) in the packed order setup_grid writes them; total: the table's
+// length in doubles.
+inline GeoOffsets geo_layout(const int nt[3], size_t &total) {
+  GeoOffsets o;
+  size_t at = 0;
+  auto take = [&](size_t n) {
+    const size_t off = at;
+    at += n;
+    return off;
+  };
+  for (int a = 0; a < 3; a++) {
+    o.icv[a] = take(nt[a]);
+    o.fa[a] = take(nt[a] + 1);
+  }
+  o.r2c = take(nt[0]);
+  o.r2f = take(nt[0] + 1);
+  o.s2c = take(nt[1]);
+  o.s2f = take(nt[1] + 1);
+  o.xc0 = take(nt[0]);
+  o.sc = take(nt[1]);
+  o.cc = take(nt[1]);
+  o.gA = take(nt[0]);
+  o.gB = take(nt[0]);
+  o.gC = take(nt[1]);
+  total = at;
+  return o;
+}
+
+// Fill G (all but the geometry pointers) and append the grid's 1D geometry
+// tables to tab.
+inline GeoOffsets setup_grid(const gmunu_grid_desc &d, Grid &G, std::vector<double> &tab) {
+  grid_scalars(d, G);
 
   auto put = [&](const std::vector<double> &v) {
     size_t off = tab.size();

@@ -157,3 +157,23 @@ def test_multigrid_create_rejects_invalid_descriptors():
         h = ctypes.c_void_p()
         assert L.gmunu_mg_create(ctypes.byref(gmu.make_mg_desc(p)), ctypes.byref(h)) == -1, p
         assert not h.value
+
+
+def test_static_step_rejects_what_its_scratch_cannot_hold():
+    """gmunu_step_static refuses, before any device call, a grid with more
+    than 8192 cells per axis (its static tables) and the limiter (which
+    needs a third state)."""
+    import math
+
+    import workloads as W
+
+    L = gmu.lib()
+    buf = (ctypes.c_double * 16)()
+    a = ctypes.cast(buf, ctypes.c_void_p)
+    p = W.grid(1, W.CART, [8189], [0, 0, 0], [1, 1, 1], [[1, 1]])
+    rc = L.gmunu_step_static(ctypes.byref(gmu.make_desc(p)), a, a, a, a, None, 0.4, 1.0, a, a, None, None, None)
+    assert rc == -1
+    p = W.grid(1, W.CART, [64], [0, 0, 0], [1, 1, 1], [[1, 1]], pp_limiter=1)
+    rc = L.gmunu_step_static(ctypes.byref(gmu.make_desc(p)), a, a, a, a, None, 0.4, 1.0, a, a, None, None, None)
+    assert rc == -1
+    assert L.gmunu_step_static(None, a, a, a, a, None, 0.4, 1.0, a, a, None, None, None) == -2
