@@ -169,6 +169,72 @@ def bench_star(nr=256, nth=128, steps=1000, cfl=0.4):
             "nfatal": int(nf.item())}
 
 
+def bench_fused(n=256, steps=10, cfl=0.4, seed=0):
+    """The primitive recovery as its own kernel after each stage (what
+    gmunu_step does) against the recovery done by the stage kernel itself
+    in its epilogue (gmunu_rk_stage with separate input and output
+    primitives, ping-ponged): per-kernel times and whole steps, same steps
+    from the same initial data, results compared bit for bit."""
+    import torch
+
+    import paper_2012_07322_amd as gmu
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    p, pr, met = W.blast_wave_3d(n, seed=seed)
+    g = gmu.Grid(p)
+    metric = torch.from_numpy(met).to(dev)
+    res = {}
+    finals = []
+    for fused in (False, True):
+        prim = torch.from_numpy(pr).to(dev)
+        g.fill_ghosts(prim)
+        qn = g.prim2con(prim, metric)
+        g.c2p(qn, metric, prim)
+        g.fill_ghosts(prim)
+        qs = torch.zeros_like(qn)
+        other = prim.clone() if fused else None  # edge ghosts (never filled) as in prim
+        t = torch.zeros(1, dtype=torch.float64, device=dev)
+        dt = torch.zeros_like(t)
+
+        def one(prim, other):
+            if not fused:
+                g.step(qn, qs, prim, metric, cfl, 1e30, t, dt)
+                return prim, other
+            g.cfl_dt(prim, metric, cfl, 1e30, t, dt)
+            g.rk_stage(0, dt, qn, qs, qs, prim, other, metric)
+            g.rk_stage(1, dt, qn, qs, qs, other, prim, metric)
+            g.rk_stage(2, dt, qn, qs, qn, prim, other, metric)
+            t.add_(dt)
+            return other, prim
+
+        prim, other = one(prim, other)  # warm-up
+        torch.cuda.synchronize()
+        g.profile(True, max_launches=16 * steps + 16)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            prim, other = one(prim, other)
+        e1.record()
+        torch.cuda.synchronize()
+        prof = g.profile_read()
+        g.profile(False)
+        res["fused" if fused else "separate"] = {
+            "ms_per_step": e0.elapsed_time(e1) / steps,
+            "stage_ms": prof["stage"][0] / max(prof["stage"][1], 1),
+            "c2p_ms": prof["c2p"][0] / prof["c2p"][1] if prof["c2p"][1] else 0.0,
+            "ghosts_ms": prof["ghosts"][0] / max(prof["ghosts"][1], 1)}
+        finals.append((qn.cpu(), prim.cpu(), float(t.item())))
+        del qn, qs, prim, other
+        torch.cuda.empty_cache()
+    g.close()
+    res["bitwise_identical"] = bool(torch.equal(finals[0][0], finals[1][0]) and
+                                    torch.equal(finals[0][1], finals[1][1]) and finals[0][2] == finals[1][2])
+    res["step_speedup"] = res["separate"]["ms_per_step"] / res["fused"]["ms_per_step"]
+    res["workload"] = f"blast3d_{n}, {steps} steps"
+    return res
+
+
 def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True):
     """Many AMR-style blocks (8^3, 16^3, 32^3 interiors, spherical and
     Cartesian, TOV-profile magnetised states), each its own simulation with
@@ -728,6 +794,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-slab", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fused-steps", type=int, default=10,
+                    help="steps of the separate-vs-fused recovery comparison (0: skip)")
     ap.add_argument("--star-steps", type=int, default=1000,
                     help="steps of the 256x128 spherical star (0: skip)")
     ap.add_argument("--blocks", type=int, default=3000,
@@ -853,6 +921,10 @@ def main():
     del qn, qs, prim, metric
     g.close()
     torch.cuda.empty_cache()
+    if args.fused_steps > 0:
+        log(f"[bench] separate vs fused recovery, {args.fused_steps} steps")
+        out["fused_c2p"] = bench_fused(n, args.fused_steps, cfl=args.cfl, seed=args.seed)
+        torch.cuda.empty_cache()
     if args.star_steps > 0:
         log(f"[bench] star 256x128, {args.star_steps} steps")
         out["star2d"] = bench_star(256, 128, args.star_steps, cfl=args.cfl)

@@ -178,8 +178,13 @@ int gmunu_cfl_dt(gmunu_ctx *ctx, const double *prim, const double *metric, doubl
  * except that with the positivity-preserving limiter (section 2.4) the stage
  * also reads the base state of the neighbouring cells (q_n in stage 0, q_s
  * after): then q_out must not overlap the base, and GMUNU_EINVAL is returned
- * when it is the same pointer.  prim_out may alias prim_in.  dt is read from
- * dt_dev.  kij: as in gmunu_rhs (nullable). */
+ * when it is the same pointer.  prim_out may alias prim_in; when it is
+ * another array (not overlapping prim_in) and the limiter is off, the stage
+ * kernel does the recovery itself in its epilogue, with the same result bit
+ * for bit (this saves the recovery's pass over q and the metric but runs the
+ * iterative root finder at the stage kernel's occupancy: on a 256^3 blast it
+ * is slower than the separate recovery, which gmunu_step uses).  dt is read
+ * from dt_dev.  kij: as in gmunu_rhs (nullable). */
 int gmunu_rk_stage(gmunu_ctx *ctx, int stage, const double *dt_dev, const double *q_n, const double *q_s,
                    double *q_out, const double *prim_in, double *prim_out, const double *metric,
                    const double *kij, uint8_t *flags, unsigned int *nfatal_dev, void *stream);

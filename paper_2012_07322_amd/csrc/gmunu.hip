@@ -78,20 +78,21 @@ __device__ __forceinline__ void xcd_tile(const Grid &G, int TX, int TY, int TZ, 
 }
 
 // MODE 0: dqdt = L(prim).  MODE 1: q_out = ca q_n + cb (q_s + dt L(prim)),
-// with the positivity-preserving flux limiter when P = 1.
-// skipp (nullable): nothing is done when *skipp == 0 (a step past t_end).
-// One workgroup per tile.
+// with the positivity-preserving flux limiter when P = 1.  MODE 2: MODE 1
+// and then the primitive recovery of q_out into fc.prim (another array
+// than prim).  skipp (nullable): nothing is done when *skipp == 0 (a step
+// past t_end).  One workgroup per tile.
 template <int TX, int TY, int TZ, int ND, int MODE, int REC, int R, int P>
 __global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC)>())) void k_stage(
     const Grid G, const double *__restrict__ prim, const double *__restrict__ met, const double *qn, const double *qs,
     double *out, const double *__restrict__ dtp, double ca, double cb, const double *__restrict__ skipp,
-    const double *__restrict__ kij) {
+    const double *__restrict__ kij, FusedC2P fc) {
   __shared__ double sF[stage_lds<TX, TY, TZ, ND, recon_halo(REC)>()];
   if (skipp && *skipp == 0.0) return;
   int bx, by, bz;
   xcd_tile(G, TX, TY, TZ, bx, by, bz);
   stage_tile<TX, TY, TZ, ND, MODE, REC, R, P>(G, bx * TX, by * TY, bz * TZ, prim, met, qn, qs, out, dtp, ca, cb, sF,
-                                            kij);
+                                            kij, fc);
 }
 
 __global__ __launch_bounds__(NT) void k_c2p(const Grid G, double *q, const double *__restrict__ met, double *prim,
@@ -140,25 +141,25 @@ __global__ void k_advance(double *tp, const double *dtp) { *tp += *dtp; }
 template <int TX, int TY, int TZ, int ND, int MODE, int REC, int R, int P>
 void launch_stage_t(const gmunu_ctx *ctx, const double *prim, const double *met, const double *kij,
                     const double *qn, const double *qs, double *out, const double *dtp, double ca, double cb,
-                    const double *skipp, hipStream_t st) {
+                    const double *skipp, FusedC2P fc, hipStream_t st) {
   const Grid &G = ctx->G;
   dim3 grid(((G.n[0] + TX - 1) / TX) * ((G.n[1] + TY - 1) / TY) * ((G.n[2] + TZ - 1) / TZ));
   hipLaunchKernelGGL((k_stage<TX, TY, TZ, ND, MODE, REC, R, P>), grid, dim3(NT), 0, st, G, prim, met, qn, qs, out,
-                     dtp, ca, cb, skipp, kij);
+                     dtp, ca, cb, skipp, kij, fc);
 }
 
 template <int MODE>
 void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, const double *kij,
                   const double *qn, const double *qs, double *out, const double *dtp, double ca, double cb,
-                  const double *skipp, hipStream_t st) {
+                  const double *skipp, hipStream_t st, FusedC2P fc = FusedC2P{nullptr, nullptr, nullptr}) {
   const int rec = ctx->G.recon, lf = ctx->G.riemann == GMUNU_RIEMANN_TVDLF;
   // the limiter acts on the stage's Euler step, so the RHS alone (MODE 0) is unlimited
-  const int pp = MODE == 1 && ctx->G.pp;
+  const int pp = MODE != 0 && ctx->G.pp;
   switch (ctx->G.ndim * 16 + rec * 4 + lf * 2 + pp) {
 #define GM_CASE(NDIM, TX, TY, TZ, M, L, P)                                                                      \
   case NDIM * 16 + M * 4 + L * 2 + P:                                                                            \
     launch_stage_t<TX, TY, TZ, NDIM, MODE, M, L, MODE == 1 && P>(ctx, prim, met, kij, qn, qs, out, dtp, ca, cb,  \
-                                                                 skipp, st);                                      \
+                                                                 skipp, fc, st);                                  \
     break;
 #define GM_CASES_R(NDIM, TX, TY, TZ, M) \
   GM_CASE(NDIM, TX, TY, TZ, M, 0, 0)    \
@@ -214,14 +215,24 @@ int rk_stage_impl(gmunu_ctx *ctx, int stage, const double *dt_dev, const double 
       cb = 2.0 / 3.0;
     }
   }
+  // with separate input and output primitives (and no limiter) the stage
+  // kernel recovers the primitives itself; otherwise the recovery is its
+  // own kernel after the stage
+  const bool fuse = prim_out != prim_in && !ctx->G.pp;
   {
     ProfScope ps(ctx, st, GMUNU_K_STAGE);
-    launch_stage<1>(ctx, prim_in, metric, kij, q_n, q_s, q_out, dt_dev, ca, cb, skipp, st);
+    if (fuse)
+      launch_stage<2>(ctx, prim_in, metric, kij, q_n, q_s, q_out, dt_dev, ca, cb, skipp, st,
+                      FusedC2P{prim_out, flags, nfatal_dev});
+    else
+      launch_stage<1>(ctx, prim_in, metric, kij, q_n, q_s, q_out, dt_dev, ca, cb, skipp, st);
   }
   int rc = launch_status();
   if (rc) return rc;
-  rc = launch_c2p(ctx, q_out, metric, prim_out, flags, nfatal_dev, skipp, st);
-  if (rc) return rc;
+  if (!fuse) {
+    rc = launch_c2p(ctx, q_out, metric, prim_out, flags, nfatal_dev, skipp, st);
+    if (rc) return rc;
+  }
   return launch_ghosts(ctx, prim_out, skipp, st);
 }
 

@@ -618,13 +618,24 @@ struct NoPrefetch {
   __device__ void operator()() const {}
 };
 
+// Outputs of the primitive recovery when a stage does it in its epilogue
+// (MODE 2): prim must not be the primitives the stage reads (neighbouring
+// tiles still read those).
+struct FusedC2P {
+  double *prim;
+  uint8_t *flags;         // nullable
+  unsigned int *nfatal;   // nullable
+};
+
 template <int TX, int TY, int TZ, int ND, int MODE, int REC = 0, int R = 0, int P = 0, typename Pre = NoPrefetch>
 __device__ __forceinline__ void stage_staged(const Grid &G, int i0, int j0, int k0, const double *__restrict__ met,
                                              const double *qn, const double *qs, double *out,
                                              const double *__restrict__ dtp, double ca, double cb, double *sF,
-                                             const double *__restrict__ kij = nullptr, Pre prefetch = Pre{}) {
+                                             const double *__restrict__ kij = nullptr, Pre prefetch = Pre{},
+                                             FusedC2P fc = FusedC2P{nullptr, nullptr, nullptr}) {
   static_assert(tile_fits<TX, TY, TZ, ND>(), "tile passes must have at most one face per thread");
   static_assert(P == 0 || MODE == 1, "the limiter needs the stage's Euler step");
+  static_assert(MODE != 2 || kMetLds, "the fused recovery takes psi and alpha from the staged region");
   constexpr int H = recon_halo(REC);
   constexpr int NP = Plus<TX, TY, TZ, ND, H>::N;
   const int tid = threadIdx.x;
@@ -634,7 +645,7 @@ __device__ __forceinline__ void stage_staged(const Grid &G, int i0, int j0, int 
   const long oc = valid ? cell_offset(G, i, j, k) : 0;
   // the conserved state of the RK combination (kPrefetchQ: loaded first)
   double un[NV], us[NV];
-  if (MODE == 1 && kPrefetchQ && valid) {
+  if (MODE != 0 && kPrefetchQ && valid) {
 #pragma unroll
     for (int v = 0; v < NV; v++) {
       un[v] = qn[v * G.nv + oc];
@@ -707,9 +718,31 @@ __device__ __forceinline__ void stage_staged(const Grid &G, int i0, int j0, int 
         }
       }
       const double dt = *dtp;
+      double qo[NV];
 #pragma unroll
       for (int v = 0; v < NV; v++)
-        out[v * G.nv + oc] = ca == 0.0 ? cb * (un[v] + dt * acc[v]) : ca * un[v] + cb * (us[v] + dt * acc[v]);
+        qo[v] = ca == 0.0 ? cb * (un[v] + dt * acc[v]) : ca * un[v] + cb * (us[v] + dt * acc[v]);
+      if constexpr (MODE == 2) {
+        // the recovery of the new state (c2p_one's arithmetic on the same
+        // values: q from registers, psi and alpha from the staged region)
+        const int c = tx + TX * (ty + TY * tz);
+        const double *Sm = sF + NV * NP;
+        const double psi = Sm[c], alpha = Sm[NP + c];
+        double g1 = 1.0, g2 = 1.0;
+        if (G.coord != CART) ref_diag(G.coord, G.geo.r2c[i + G.g[0]], G.geo.s2c[j + G.g[1]], g1, g2);
+        double pr[NV];
+        const int fl = c2p_any(G, qo, psi, alpha, g1, g2, pr);
+#pragma unroll
+        for (int v = 0; v < NV; v++) fc.prim[v * G.nv + oc] = pr[v];
+        if (fl & FL_REWRITE) {
+          const double beta[3] = {Sm[2 * NP + c], Sm[3 * NP + c], Sm[4 * NP + c]};
+          prim_to_cons(G.gam, G.gfac, pr, psi, alpha, beta, g1, g2, qo);
+        }
+        if (fc.flags) fc.flags[oc] = (uint8_t)fl;
+        if ((fl & FL_FATAL) && fc.nfatal) atomicAdd(fc.nfatal, 1u);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; v++) out[v * G.nv + oc] = qo[v];
     }
   }
   // a workgroup that takes another tile next restages sF: every thread must
@@ -723,13 +756,15 @@ template <int TX, int TY, int TZ, int ND, int MODE, int REC = 0, int R = 0, int 
 __device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0, const double *__restrict__ prim,
                                            const double *__restrict__ met, const double *qn, const double *qs,
                                            double *out, const double *__restrict__ dtp, double ca, double cb,
-                                           double *sF, const double *__restrict__ kij = nullptr) {
+                                           double *sF, const double *__restrict__ kij = nullptr,
+                                           FusedC2P fc = FusedC2P{nullptr, nullptr, nullptr}) {
   constexpr int H = recon_halo(REC);
   RegionRegs<TX, TY, TZ, ND, H> Rg;
   region_load<TX, TY, TZ, ND, H>(G, prim, met, i0, j0, k0, Rg);
   region_store<TX, TY, TZ, ND, H>(Rg, sF);
   __syncthreads();
-  stage_staged<TX, TY, TZ, ND, MODE, REC, R, P>(G, i0, j0, k0, met, qn, qs, out, dtp, ca, cb, sF, kij);
+  stage_staged<TX, TY, TZ, ND, MODE, REC, R, P>(G, i0, j0, k0, met, qn, qs, out, dtp, ca, cb, sF, kij, NoPrefetch{},
+                                               fc);
 }
 
 // Primitive recovery of interior cell number t (x fastest) of grid G; a
