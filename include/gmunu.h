@@ -275,7 +275,10 @@ int gmunu_batch_init(gmunu_batch *b, const int *slots, int nslots, void *stream)
 /* One step for every group with dt > 0: dt per group (section 2.9), the RK
  * stages (q_n <- q^{n+1}, q_s scratch, prim consistent, ghosts filled),
  * t += dt, step count += 1.  use_graph != 0: capture once and replay
- * (captured again when cfl, nfatal_dev or a new tile shape appears). */
+ * (captured again when cfl, nfatal_dev or a new tile shape appears, or when
+ * a work list outgrows, or shrinks well below, the grid it was captured
+ * with: grids follow the committed work, so a batch of a few small blocks
+ * launches few workgroups). */
 int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int use_graph, void *stream);
 /* Copy the groups' t, last dt, step counts and fatal-recovery counts (cells
  * flagged FATAL_* summed over stages since the group's set_group) to host
@@ -306,10 +309,11 @@ int gmunu_profile_read(gmunu_ctx *ctx, double *ms_out /* [GMUNU_NK] */, long *co
  * the initial data on a copy stream while the GPU keeps stepping the
  * resident solves, and adds the solve to a lane: a gmunu_batch with its own
  * stream (each solve its own group with its own dt), one lane per
- * integrator and size class (at most 65536 interior cells, or more), so
- * small solves are not paced by large ones and both lanes run concurrently.
- * Each lane replays its captured step in rounds of about 2 ms of device
- * work (at least `steps_per_sync` replays).  A solve that reaches its end
+ * integrator and kind (1D solves, other solves of at most 65536 interior
+ * cells, larger ones), so small solves are not paced by large ones and the
+ * lanes run concurrently.  Each lane replays its captured steps (8 per
+ * replay for 1D solves, 2 for small, 1 for large) in rounds of about 2 ms
+ * of device work (at least `steps_per_sync` steps).  A solve that reaches its end
  * is copied out (copy stream), removed from the batch and its memory
  * returned; its result is then available to gmunu_server_poll.  Each solve
  * is advanced by exactly the arithmetic of gmunu_step on its own grid, so a
@@ -351,7 +355,7 @@ typedef struct gmunu_result {
 
 typedef struct gmunu_server_info {
   long submitted, admitted, completed, pending, resident;
-  long replays;        /* batched steps issued */
+  long replays;        /* batched steps issued (over all lanes) */
   size_t pool_bytes, pool_used, pool_peak;
   double busy_s;       /* worker time with at least one solve resident */
 } gmunu_server_info;
@@ -361,7 +365,7 @@ double gmunu_server_clock(void);
 /* hbm_bytes: arena for solve state (q_n, q_s, prim: 8 doubles per cell each,
  * metric 5; 232 bytes per cell with ghosts); max_slots: solves resident at
  * once per lane; cfl: Courant number of every solve; steps_per_sync >= 1:
- * least replays between completion checks.  Starts the worker on the
+ * least steps between completion checks.  Starts the worker on the
  * current device. */
 int gmunu_server_create(size_t hbm_bytes, int max_slots, double cfl, int steps_per_sync, gmunu_server **out);
 /* Queue a solve (non-blocking).  GMUNU_EINVAL if the descriptor is invalid

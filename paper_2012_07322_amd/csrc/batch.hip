@@ -178,29 +178,29 @@ __global__ __launch_bounds__(NT) void k_bcfl(const BlockRec *__restrict__ B, DLi
   }
 }
 
-// dt of each group: cfl / max rate over its items, capped at t_end - t,
-// zero for a group without blocks, past its end time or at its step limit.
+// dt of each group, one wavefront per group: cfl / max rate over its items,
+// capped at t_end - t, zero for a group without blocks, past its end time or
+// at its step limit.  A group with dt > 0 advances its time and step count
+// here: nothing later in the step reads them.
 __global__ __launch_bounds__(NT) void k_bcfl_finish(const int *__restrict__ gfirst, const int *__restrict__ gcount,
                                                     const double *__restrict__ part, int ngroups, double cfl,
-                                                    const double *t, const double *t_end, const int *nstep,
-                                                    const int *maxstep, double *dt) {
-  for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
-    const int f = gfirst[g], c = gcount[g];
-    double m = 0.0;
-    for (int k = threadIdx.x; k < c; k += NT) m = fmax(m, part[f + k]);
-    m = block_max(m);
-    if (threadIdx.x == 0) {
-      const double d = (c > 0 && nstep[g] < maxstep[g]) ? dt_from_rate(m, cfl, t[g], t_end[g]) : 0.0;
-      dt[g] = d > 0.0 ? d : 0.0;
+                                                    double *t, const double *t_end, int *nstep, const int *maxstep,
+                                                    double *dt) {
+  const int g = blockIdx.x * (NT / 64) + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= ngroups) return;  // uniform over the wavefront
+  const int f = gfirst[g], c = gcount[g];
+  double m = 0.0;
+  for (int k = lane; k < c; k += 64) m = fmax(m, part[f + k]);
+  m = wave_max(m);
+  if (lane == 0) {
+    const double d0 = (c > 0 && nstep[g] < maxstep[g]) ? dt_from_rate(m, cfl, t[g], t_end[g]) : 0.0;
+    const double d = d0 > 0.0 ? d0 : 0.0;
+    dt[g] = d;
+    if (d > 0.0) {
+      t[g] += d;
+      nstep[g] += 1;
     }
-  }
-}
-
-__global__ void k_badvance(double *t, int *nstep, const double *dt, int ngroups) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < ngroups && dt[g] > 0.0) {
-    t[g] += dt[g];
-    nstep[g] += 1;
   }
 }
 
@@ -268,6 +268,34 @@ struct HList {
   }
 };
 
+// Grid sizes of the kernels of one step: a persistent kernel gets about one
+// workgroup per item of its list (a power of two, at most its cap), so that a
+// step over a few small blocks does not launch thousands of idle workgroups.
+struct Shape {
+  int cfl = 1, c2p = 1, gh = 1;
+  int st[NSL];
+  Shape() {
+    for (int &g : st) g = 1;
+  }
+};
+
+int grid_for(long items, int cap) {
+  int g = 1;
+  while (g < items && g < cap) g <<= 1;
+  return std::min(g, cap);
+}
+
+// A step captured with grids `have` serves lists that want `want` while no
+// list outgrew its grid and none shrank below an eighth of a grid of more
+// than 64 workgroups (any grid size gives the same results).
+bool shape_fits(const Shape &have, const Shape &want) {
+  auto ok = [](int h, int w) { return w <= h && (8 * w > h || h <= 64); };
+  if (!ok(have.cfl, want.cfl) || !ok(have.c2p, want.c2p) || !ok(have.gh, want.gh)) return false;
+  for (int l = 0; l < NSL; l++)
+    if (!ok(have.st[l], want.st[l])) return false;
+  return true;
+}
+
 }  // namespace
 
 struct gmunu_batch {
@@ -307,6 +335,8 @@ struct gmunu_batch {
   double graph_cfl;
   unsigned graph_mask;
   unsigned int *graph_nfatal;
+  int graph_steps;
+  Shape graph_shape;
 
   DList list(int l) const {
     return DList{d_blk + (size_t)l * maxb, d_start + (size_t)l * (maxb + 1), d_meta + 2 * l};
@@ -370,19 +400,38 @@ bool upload_records(gmunu_batch *b, hipStream_t st) {
   return ok;
 }
 
-int persist_grid(const gmunu_batch *b, long items, int per_cu) {
-  const long g = (long)b->ncu * per_cu;
-  return (int)std::max(1L, std::min(g, std::max(items, 1L)));
+// Grids for the lists as last committed.  The caps keep each workgroup of a
+// large list to a few items, so that workgroups retire often and kernels of
+// other batches on the device (other streams) find free compute units.
+constexpr int kGridPerCu = 16;
+
+Shape step_shape(const gmunu_batch *b) {
+  const int cap = kGridPerCu * b->ncu;
+  Shape sh;
+  sh.cfl = grid_for(b->counts[L_CFL], cap);
+  sh.c2p = grid_for(b->counts[L_C2P], cap);
+  sh.gh = grid_for(b->counts[L_GH], cap);
+  for (int l = 0; l < NSL; l++) sh.st[l] = grid_for(b->counts[l], cap);
+  return sh;
 }
 
-// Enqueue one full step (cfl, stages, advance) on st, with the stage
-// kernels of the tile variants in `mask`.
-int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, unsigned mask, hipStream_t st) {
-  const int gsm = persist_grid(b, b->maxi, 8);
-  const int gst = b->ncu * 4;
-  hipLaunchKernelGGL(k_bcfl, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_CFL), b->d_part);
-  hipLaunchKernelGGL(k_bcfl_finish, dim3(std::min(b->maxg, 4096)), dim3(NT), 0, st, b->d_gfirst, b->d_gcount,
-                     b->d_part, b->maxg, cfl, b->d_t, b->d_tend, b->d_nstep, b->d_maxstep, b->d_dt);
+// Grids to capture for lists that want `w`: room to grow to twice the work
+// (at least 64 workgroups) before the next capture.
+Shape with_headroom(const gmunu_batch *b, const Shape &w) {
+  const int cap = kGridPerCu * b->ncu;
+  auto up = [cap](int g) { return std::min(cap, std::max(64, 2 * g)); };
+  Shape sh;
+  sh.cfl = up(w.cfl);
+  sh.c2p = up(w.c2p);
+  sh.gh = up(w.gh);
+  for (int l = 0; l < NSL; l++) sh.st[l] = up(w.st[l]);
+  return sh;
+}
+
+// Enqueue `steps` full steps (CFL and advance, stages) on st, with the stage
+// kernels of the lists in `mask` and the grids of `sh`.
+int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, unsigned mask, const Shape &sh, int steps,
+                 hipStream_t st) {
   // RK stages (same coefficients as gmunu_rk_stage); a batch holds one
   // integrator (checked at commit)
   int nst = 3;
@@ -391,29 +440,33 @@ int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, unsigned mask
       nst = b->blk[s].desc.rk;
       break;
     }
-  for (int s = 0; s < nst; s++) {
-    double ca = 0.0, cb = 1.0;
-    if (s > 0) {
-      if (nst == 2) {
-        ca = 0.5;
-        cb = 0.5;
-      } else if (s == 1) {
-        ca = 0.75;
-        cb = 0.25;
-      } else {
-        ca = 1.0 / 3.0;
-        cb = 2.0 / 3.0;
+  const int gfin = (b->maxg + NT / 64 - 1) / (NT / 64);
+  for (int k = 0; k < steps; k++) {
+    hipLaunchKernelGGL(k_bcfl, dim3(sh.cfl), dim3(NT), 0, st, b->d_rec, b->list(L_CFL), b->d_part);
+    hipLaunchKernelGGL(k_bcfl_finish, dim3(gfin), dim3(NT), 0, st, b->d_gfirst, b->d_gcount, b->d_part, b->maxg,
+                       cfl, b->d_t, b->d_tend, b->d_nstep, b->d_maxstep, b->d_dt);
+    for (int s = 0; s < nst; s++) {
+      double ca = 0.0, cb = 1.0;
+      if (s > 0) {
+        if (nst == 2) {
+          ca = 0.5;
+          cb = 0.5;
+        } else if (s == 1) {
+          ca = 0.75;
+          cb = 0.25;
+        } else {
+          ca = 1.0 / 3.0;
+          cb = 2.0 / 3.0;
+        }
       }
+      const int last = s == nst - 1;
+      for (int l = 0; l < NSL; l++)
+        if (mask & (1u << l)) launch_list_any<1>(l, b->d_rec, b->list(l), b->d_dt, ca, cb, last, sh.st[l], st);
+      hipLaunchKernelGGL(k_bc2p, dim3(sh.c2p), dim3(NT), 0, st, b->d_rec, b->list(L_C2P), b->d_dt, last, 0, nfatal,
+                         b->d_gfatal);
+      hipLaunchKernelGGL(k_bghosts, dim3(sh.gh), dim3(NT), 0, st, b->d_rec, b->list(L_GH), b->d_dt, 0);
     }
-    const int last = s == nst - 1;
-    for (int l = 0; l < NSL; l++)
-      if (mask & (1u << l)) launch_list_any<1>(l, b->d_rec, b->list(l), b->d_dt, ca, cb, last, gst, st);
-    hipLaunchKernelGGL(k_bc2p, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_C2P), b->d_dt, last, 0, nfatal,
-                       b->d_gfatal);
-    hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_GH), b->d_dt, 0);
   }
-  hipLaunchKernelGGL(k_badvance, dim3((b->maxg + NT - 1) / NT), dim3(NT), 0, st, b->d_t, b->d_nstep, b->d_dt,
-                     b->maxg);
   return launch_status();
 }
 
@@ -423,8 +476,11 @@ namespace gm {
 
 BatchItems batch_items_for(const gmunu_batch *b, const gmunu_grid_desc &d) {
   BatchItems r;
-  auto it = b->tuned.find(bucket_of(d));
-  const int v = it != b->tuned.end() ? it->second : default_variant(d);
+  int v = default_variant(d);
+  if (b) {
+    auto it = b->tuned.find(bucket_of(d));
+    if (it != b->tuned.end()) v = it->second;
+  }
   r.variant = list_of(v, d);
   r.stage = stage_items(d, v);
   r.cells = cell_items(d);
@@ -433,6 +489,49 @@ BatchItems batch_items_for(const gmunu_batch *b, const gmunu_grid_desc &d) {
 }
 
 long batch_max_items(const gmunu_batch *b) { return b->maxi; }
+
+hipStream_t batch_stream(const gmunu_batch *b) { return b->pstream; }
+
+int batch_step_graph(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int steps, hipStream_t st) {
+  if (!b) return GMUNU_ENULL;
+  if (!(cfl > 0.0) || steps < 1) return GMUNU_EINVAL;
+  // the captured step keeps the kernels of every variant used since the
+  // capture (an empty list costs one short launch), so blocks of new shapes
+  // coming and going do not force a capture each time
+  const unsigned mask = b->var_mask | (b->have_graph ? b->graph_mask : 0u);
+  const Shape want = step_shape(b);
+  if (!b->have_graph || b->graph_cfl != cfl || b->graph_mask != mask || b->graph_nfatal != nfatal_dev ||
+      b->graph_steps != steps || !shape_fits(b->graph_shape, want)) {
+    if (b->have_graph) {
+      (void)hipGraphExecDestroy(b->exec);
+      b->have_graph = false;
+    }
+    hipGraph_t graph;
+    if (hipStreamBeginCapture(b->pstream, hipStreamCaptureModeThreadLocal) != hipSuccess) return GMUNU_EHIP;
+    const Shape cap = with_headroom(b, want);
+    const int rc = enqueue_step(b, cfl, nfatal_dev, mask, cap, steps, b->pstream);
+    const bool ended = hipStreamEndCapture(b->pstream, &graph) == hipSuccess;
+    if (!ended || rc) {
+      if (ended) (void)hipGraphDestroy(graph);
+      return rc ? rc : GMUNU_EHIP;
+    }
+    const bool ok = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    (void)hipGraphDestroy(graph);
+    if (!ok) return GMUNU_EHIP;
+    b->have_graph = true;
+    b->graph_cfl = cfl;
+    b->graph_mask = mask;
+    b->graph_nfatal = nfatal_dev;
+    b->graph_steps = steps;
+    b->graph_shape = cap;
+  }
+  if (st == b->pstream) return hipGraphLaunch(b->exec, b->pstream) == hipSuccess ? GMUNU_OK : GMUNU_EHIP;
+  // order: caller's prior work -> replay on the private stream -> caller's later work
+  bool ok = hipEventRecord(b->ev_in, st) == hipSuccess && hipStreamWaitEvent(b->pstream, b->ev_in, 0) == hipSuccess &&
+            hipGraphLaunch(b->exec, b->pstream) == hipSuccess && hipEventRecord(b->ev_out, b->pstream) == hipSuccess &&
+            hipStreamWaitEvent(st, b->ev_out, 0) == hipSuccess;
+  return ok ? GMUNU_OK : GMUNU_EHIP;
+}
 
 }  // namespace gm
 
@@ -658,12 +757,12 @@ int gmunu_batch_init(gmunu_batch *b, const int *slots, int nslots, void *stream)
   ok = ok && upload_list(b, L_IC2P, hc, meta, st) && upload_list(b, L_IGH, hg, meta + 2, st);
   ok = ok && hipStreamSynchronize(st) == hipSuccess;
   if (!ok) return GMUNU_EHIP;
-  const int gsm = persist_grid(b, b->maxi, 8);
-  hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_IGH), b->d_dt, 1);
-  hipLaunchKernelGGL(k_bprim2con, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_IC2P));
-  hipLaunchKernelGGL(k_bc2p, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_IC2P), b->d_dt, 1, 1,
+  const int gc = grid_for(hc.total, kGridPerCu * b->ncu), gg = grid_for(hg.total, kGridPerCu * b->ncu);
+  hipLaunchKernelGGL(k_bghosts, dim3(gg), dim3(NT), 0, st, b->d_rec, b->list(L_IGH), b->d_dt, 1);
+  hipLaunchKernelGGL(k_bprim2con, dim3(gc), dim3(NT), 0, st, b->d_rec, b->list(L_IC2P));
+  hipLaunchKernelGGL(k_bc2p, dim3(gc), dim3(NT), 0, st, b->d_rec, b->list(L_IC2P), b->d_dt, 1, 1,
                      (unsigned int *)nullptr, (unsigned int *)nullptr);
-  hipLaunchKernelGGL(k_bghosts, dim3(gsm), dim3(NT), 0, st, b->d_rec, b->list(L_IGH), b->d_dt, 1);
+  hipLaunchKernelGGL(k_bghosts, dim3(gg), dim3(NT), 0, st, b->d_rec, b->list(L_IGH), b->d_dt, 1);
   return launch_status();
 }
 
@@ -680,7 +779,6 @@ int gmunu_batch_autotune(gmunu_batch *b, void *stream) {
     return GMUNU_EHIP;
   }
   int rc = upload_records(b, st) ? GMUNU_OK : GMUNU_EHIP;
-  const int gst = b->ncu * 4;
   for (auto &bk : buckets) {
     if (rc) break;
     const int nd = std::get<0>(bk.first);
@@ -700,6 +798,7 @@ int gmunu_batch_autotune(gmunu_batch *b, void *stream) {
         rc = GMUNU_EHIP;
         break;
       }
+      const int gst = grid_for(h.total, kGridPerCu * b->ncu);
       launch_list_any<0>(li, b->d_rec, b->list(li), b->d_dt, 0.0, 1.0, 0, gst, st);  // warm-up
       (void)hipEventRecord(e0, st);
       for (int r = 0; r < 3; r++) launch_list_any<0>(li, b->d_rec, b->list(li), b->d_dt, 0.0, 1.0, 0, gst, st);
@@ -733,37 +832,8 @@ int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int u
   if (!b) return GMUNU_ENULL;
   if (!(cfl > 0.0)) return GMUNU_EINVAL;
   hipStream_t st = as_stream(stream);
-  if (!use_graph) return enqueue_step(b, cfl, nfatal_dev, b->var_mask, st);
-  // the captured step keeps the kernels of every variant used since the
-  // capture (an empty list costs one short launch), so blocks of new shapes
-  // coming and going do not force a capture each time
-  const unsigned mask = b->var_mask | (b->have_graph ? b->graph_mask : 0u);
-  if (!b->have_graph || b->graph_cfl != cfl || b->graph_mask != mask || b->graph_nfatal != nfatal_dev) {
-    if (b->have_graph) {
-      (void)hipGraphExecDestroy(b->exec);
-      b->have_graph = false;
-    }
-    hipGraph_t graph;
-    if (hipStreamBeginCapture(b->pstream, hipStreamCaptureModeThreadLocal) != hipSuccess) return GMUNU_EHIP;
-    const int rc = enqueue_step(b, cfl, nfatal_dev, mask, b->pstream);
-    const bool ended = hipStreamEndCapture(b->pstream, &graph) == hipSuccess;
-    if (!ended || rc) {
-      if (ended) (void)hipGraphDestroy(graph);
-      return rc ? rc : GMUNU_EHIP;
-    }
-    const bool ok = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0) == hipSuccess;
-    (void)hipGraphDestroy(graph);
-    if (!ok) return GMUNU_EHIP;
-    b->have_graph = true;
-    b->graph_cfl = cfl;
-    b->graph_mask = mask;
-    b->graph_nfatal = nfatal_dev;
-  }
-  // order: caller's prior work -> replay on the private stream -> caller's later work
-  bool ok = hipEventRecord(b->ev_in, st) == hipSuccess && hipStreamWaitEvent(b->pstream, b->ev_in, 0) == hipSuccess &&
-            hipGraphLaunch(b->exec, b->pstream) == hipSuccess && hipEventRecord(b->ev_out, b->pstream) == hipSuccess &&
-            hipStreamWaitEvent(st, b->ev_out, 0) == hipSuccess;
-  return ok ? GMUNU_OK : GMUNU_EHIP;
+  if (!use_graph) return enqueue_step(b, cfl, nfatal_dev, b->var_mask, step_shape(b), 1, st);
+  return batch_step_graph(b, cfl, nfatal_dev, 1, st);
 }
 
 int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, int *nstep_host, unsigned int *nfatal_host,

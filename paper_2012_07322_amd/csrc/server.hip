@@ -2,13 +2,17 @@
 //
 // One worker thread owns the GPU side: a range pool over one device arena
 // (the HBM budget), a copy stream for uploads of admitted solves and
-// downloads of finished ones, and four lanes.  A lane is one gmunu_batch
-// (each solve one block in its own group) with its own stream; solves go to
-// a lane by integrator and by size: small solves (at most kSmallCells
-// interior cells) share a lane of their own, so a 1D tube that needs
-// thousands of steps is not paced by the large 3D solves, and the two lanes'
-// kernels run concurrently on the device.  Callers only touch the pending
-// queue and the result queue, both under one mutex.
+// downloads of finished ones, and up to six lanes.  A lane is one
+// gmunu_batch (each solve one block in its own group) whose stream carries
+// all of the lane's work; solves go to a lane by integrator and by kind: 1D
+// solves, other small solves (at most kSmallCells interior cells) and large
+// ones.  A 1D tube needs thousands of cheap steps, so its lane is not paced
+// by the multi-dimensional solves, and replays several steps per captured
+// graph (a step of such a lane costs little more than its launches).  The
+// lanes' kernels run concurrently on the device.  A lane and its stream are
+// made when its first solve arrives, so an unused integrator holds no
+// hardware queue.  Callers only touch the pending queue and the result
+// queue, both under one mutex.
 //
 // Loop: admit pending solves in arrival order while a slot, list capacity
 // and arena space are free (upload on the copy stream) -> for every lane
@@ -48,7 +52,8 @@ constexpr size_t kAlign = 256;
 constexpr long kSmallCells = 1L << 16;  // interior cells of a "small" solve
 constexpr double kRoundSeconds = 2e-3;  // device time per round of replays
 constexpr int kMaxRound = 64;           // replays per round, at most
-constexpr int NLANE = 4;                // (SSPRK2, SSPRK3) x (large, small)
+constexpr int NLANE = 6;                // (SSPRK2, SSPRK3) x (1D, small, large)
+constexpr int kLaneSteps[3] = {8, 2, 1};  // steps per replay: 1D, small, large
 
 struct Req {
   unsigned long long id = 0;
@@ -68,9 +73,10 @@ struct Req {
 // One batch, its stream and its slots.
 struct Lane {
   gmunu_batch *b = nullptr;
-  hipStream_t st = nullptr;
+  hipStream_t st = nullptr;  // the batch's own stream
   hipEvent_t ev = nullptr;
   bool inflight = false;
+  int steps = 1;  // steps per replay
   int round = 1;  // replays per round
   double t_launch = 0.0;
   std::vector<Req *> slot;  // resident or uploading, by slot
@@ -136,7 +142,22 @@ struct gmunu_server {
 
   static int lane_index(const gmunu_grid_desc &d) {
     const long cells = (long)d.n[0] * d.n[1] * d.n[2];
-    return (d.rk == 3 ? 2 : 0) + (cells <= kSmallCells ? 1 : 0);
+    const int kind = cells > kSmallCells ? 2 : d.ndim == 1 ? 0 : 1;
+    return (d.rk == 3 ? 3 : 0) + kind;
+  }
+
+  // Make lane k's batch, stream and event on first use.
+  bool ensure_lane(int k) {
+    Lane &L = lane[k];
+    if (L.b) return true;
+    if (gmunu_batch_create(max_slots, max_slots, maxi, &L.b) != GMUNU_OK) {
+      L.b = nullptr;
+      return false;
+    }
+    L.st = batch_stream(L.b);
+    L.steps = kLaneSteps[k % 3];
+    L.round = std::max(1, (spsync + L.steps - 1) / L.steps);
+    return hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) == hipSuccess;
   }
   Lane &lane_of(const Req *r) { return lane[r->lane]; }
   int resident_total() const {
@@ -311,7 +332,7 @@ struct gmunu_server {
       }
       const double per = dur / L.round;
       const int want = per > 0.0 ? (int)std::lround(kRoundSeconds / per) : kMaxRound;
-      L.round = std::max(spsync, std::min(kMaxRound, want));
+      L.round = std::max((spsync + L.steps - 1) / L.steps, std::min(kMaxRound, want));
       if (!check_lane(L)) return false;
       progress = true;
     }
@@ -333,12 +354,12 @@ struct gmunu_server {
       if (!L.resident) continue;
       L.t_launch = now_s();
       for (int k = 0; k < L.round; k++)
-        if (gmunu_batch_step(L.b, cfl, nullptr, 1, L.st) != GMUNU_OK) return false;
+        if (batch_step_graph(L.b, cfl, nullptr, L.steps, L.st) != GMUNU_OK) return false;
       if (hipEventRecord(L.ev, L.st) != hipSuccess) return false;
       L.inflight = true;
       progress = true;
       std::lock_guard<std::mutex> lk(mu);
-      info.replays += L.round;
+      info.replays += (long)L.round * L.steps;
     }
     return true;
   }
@@ -391,7 +412,7 @@ struct gmunu_server {
         }
       }
       bool ok = true, progress = !adm.empty();
-      for (Req *r : adm) ok = ok && start_load(r);
+      for (Req *r : adm) ok = ok && ensure_lane(r->lane) && start_load(r);
       ok = ok && finish_loads(progress) && poll_lanes(progress) && launch_lanes(progress) &&
            finish_unloads(progress);
       if (!ok) {
@@ -404,7 +425,8 @@ struct gmunu_server {
           std::this_thread::sleep_for(std::chrono::microseconds(20));
       }
     }
-    for (Lane &L : lane) (void)hipStreamSynchronize(L.st);
+    for (Lane &L : lane)
+      if (L.b) (void)hipStreamSynchronize(L.st);
     (void)hipStreamSynchronize(xs);
   }
 };
@@ -435,11 +457,6 @@ int gmunu_server_create(size_t hbm_bytes, int max_slots, double cfl, int steps_p
   s->pool.reset(hbm_bytes);
   ok = hipStreamCreateWithFlags(&s->xs, hipStreamNonBlocking) == hipSuccess;
   for (Lane &L : s->lane) {
-    if (!ok) break;
-    ok = hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) == hipSuccess &&
-         gmunu_batch_create(max_slots, max_slots, s->maxi, &L.b) == GMUNU_OK;
-    L.round = s->spsync;
     L.slot.assign(max_slots, nullptr);
     for (int k = max_slots - 1; k >= 0; k--) L.free_slots.push_back(k);
     L.t.assign(max_slots, 0.0);
@@ -448,11 +465,6 @@ int gmunu_server_create(size_t hbm_bytes, int max_slots, double cfl, int steps_p
     L.nf.assign(max_slots, 0u);
   }
   if (!ok) {
-    for (Lane &L : s->lane) {
-      if (L.b) gmunu_batch_destroy(L.b);
-      if (L.ev) (void)hipEventDestroy(L.ev);
-      if (L.st) (void)hipStreamDestroy(L.st);
-    }
     if (s->xs) (void)hipStreamDestroy(s->xs);
     (void)hipFree(s->arena);
     delete s;
@@ -483,7 +495,7 @@ int gmunu_server_submit(gmunu_server *s, const gmunu_request *req, unsigned long
   r->arr5 = RangePool::round_up(sizeof(double) * 5 * r->nv, kAlign);
   r->bytes = 3 * r->arr8 + r->arr5;
   r->lane = gmunu_server::lane_index(req->desc);
-  r->items = batch_items_for(s->lane[r->lane].b, req->desc);
+  r->items = batch_items_for(nullptr, req->desc);  // the server never tunes its batches
   if (r->bytes > s->pool.capacity() || r->items.stage > s->maxi || r->items.cells > s->maxi ||
       r->items.ghosts > s->maxi) {
     delete r;
@@ -548,9 +560,8 @@ int gmunu_server_destroy(gmunu_server *s) {
     delete r;
   }
   for (Lane &L : s->lane) {
-    if (L.b) gmunu_batch_destroy(L.b);
-    (void)hipEventDestroy(L.ev);
-    (void)hipStreamDestroy(L.st);
+    if (L.ev) (void)hipEventDestroy(L.ev);
+    if (L.b) gmunu_batch_destroy(L.b);  // also the lane's stream
   }
   (void)hipStreamDestroy(s->xs);
   const int rc = hipFree(s->arena) == hipSuccess ? GMUNU_OK : GMUNU_EHIP;
