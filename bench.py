@@ -235,7 +235,7 @@ def bench_fused(n=256, steps=10, cfl=0.4, seed=0):
     return res
 
 
-def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True):
+def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True, single_n=192):
     """Many AMR-style blocks (8^3, 16^3, 32^3 interiors, spherical and
     Cartesian, TOV-profile magnetised states), each its own simulation with
     its own time step, advanced (a) by the batched graph-captured step and
@@ -353,7 +353,54 @@ def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True):
     for g in grids:
         g.close()
     B.close()
+    if single_n:
+        res["same_physics_single_grid"] = _blocks_single_grid(ps, star, single_n, steps, cfl, dev)
+        ref = res["same_physics_single_grid"]["value"]
+        res["same_physics_single_grid"]["batched_over_single"] = res["batched"]["value"] / ref
+        log(f"[blocks] single grid of the same physics: {ref:.3e} cell-updates/s; "
+            f"batched / single = {res['batched']['value'] / ref:.3f}")
     return res
+
+
+def _blocks_single_grid(ps, star, n, steps, cfl, dev):
+    """The single-grid rate of the blocks' physics: one Cartesian and one
+    spherical n^3 grid carrying the same TOV-profile state (curved metric,
+    the same equation of state and atmosphere), gmunu_step per step; the
+    rate for the block mix is the cell-weighted harmonic mean over the two
+    coordinate systems."""
+    import numpy as np
+    import torch
+
+    import paper_2012_07322_amd as gmu
+    import workloads as W
+
+    kw = {k: ps[0][k] for k in ("gamma", "rk", "rho_atmo", "k_atmo", "gamma_atmo", "rho_low_factor", "alpha_bh")}
+    grids = {
+        "cartesian": W.grid(3, W.CART, [n] * 3, [-12.8] * 3, [12.8] * 3, [[W.OUTFLOW, W.OUTFLOW]] * 3, **kw),
+        "spherical": W.grid(3, W.SPH, [n] * 3, [0.5, 0.05, 0.0], [18.0, np.pi - 0.05, 2 * np.pi],
+                            [[W.OUTFLOW, W.OUTFLOW]] * 3, **kw),
+    }
+    out = {"n": n, "steps": steps}
+    for name, p in grids.items():
+        pr, met = W.amr_block_state(p, 0, star)
+        pr = torch.from_numpy(pr).to(dev)
+        met = torch.from_numpy(met).to(dev)
+        g = gmu.Grid(p)
+        g.run(pr, met, cfl, 1e30, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.run(pr, met, cfl, 1e30, steps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        g.close()
+        out[name] = n ** 3 * 3 * steps / sec
+    cells = {"cartesian": 0, "spherical": 0}
+    for p in ps:
+        cells["spherical" if p["coord"] == W.SPH else "cartesian"] += p["n"][0] * p["n"][1] * p["n"][2]
+    tot = sum(cells.values())
+    out["value"] = tot / sum(c / out[k] for k, c in cells.items() if c)
+    out["unit"] = "cell-updates/s"
+    return out
 
 
 def _pct(xs, q):

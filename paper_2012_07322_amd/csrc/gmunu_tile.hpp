@@ -274,11 +274,11 @@ __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int NP
 // along axis a.  flat: the caller knows every metric derivative of the cell
 // is 0 and its shift is 0, so the gravitational sources vanish.  kij
 // (nullable): the extrinsic curvature K_ij of the cell (6 components xx, xy,
-// xz, yy, yz, zz, covariant); when null it follows from the shift by the CFC
-// relation under maximal slicing.
+// xz, yy, yz, zz, covariant; component m at kij[m * kst]); when null it
+// follows from the shift by the CFC relation under maximal slicing.
 template <typename MetFn>
 __device__ __forceinline__ void cell_sources(const Grid &G, const double *pr, MetFn m, bool flat, const double *kij,
-                                             int i, int j, double *s) {
+                                             long kst, int i, int j, double *s) {
   const bool geom = G.coord != CART;
   if (flat && !geom) return;
   const double psi = m(0, -1, 0), alpha = m(1, -1, 0);
@@ -342,41 +342,41 @@ __device__ __forceinline__ void cell_sources(const Grid &G, const double *pr, Me
         T[a][c] = rhohs * ui[a] * ui[c] + ps * ((a == c ? rcp(gd[a]) : 0.0) - beta[a] * beta[c] * ia2) -
                   bi[a] * bi[c];
     }
-    // covariant derivative of the shift with point Christoffel symbols
-    double Gm[3][3][3];
+    // covariant derivative of the shift, nb[i][k] = d_i beta^k + Gamma^k_il
+    // beta^l, with the non-zero point Christoffel symbols of the coordinate
+    // system: cylindrical Gamma^R_phiphi = -R, Gamma^phi_Rphi = 1/R;
+    // spherical Gamma^r_thth = -r, Gamma^r_phph = -r sin^2, Gamma^th_rth =
+    // Gamma^ph_rph = 1/r, Gamma^th_phph = -sin cos, Gamma^ph_thph = cot
+    double nb[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
-      for (int b = 0; b < 3; b++)
-#pragma unroll
-        for (int c = 0; c < 3; c++) Gm[a][b][c] = 0.0;
+      for (int c = 0; c < 3; c++) nb[a][c] = db[a][c];
     if (G.coord == CYL) {
-      const double R = G.geo.xc0[i + G.g[0]];
-      Gm[0][2][2] = -R;
-      Gm[2][0][2] = Gm[2][2][0] = rcp(R);
+      const double R = G.geo.xc0[i + G.g[0]], iR = rcp(R);
+      nb[2][0] += -R * beta[2];
+      nb[0][2] += iR * beta[2];
+      nb[2][2] += iR * beta[0];
     } else if (G.coord == SPH) {
-      const double r = G.geo.xc0[i + G.g[0]];
-      const double sn = G.geo.sc1[j + G.g[1]], cs = G.geo.cc1[j + G.g[1]];
-      Gm[0][1][1] = -r;
-      Gm[0][2][2] = -r * sn * sn;
-      Gm[1][0][1] = Gm[1][1][0] = rcp(r);
-      Gm[1][2][2] = -sn * cs;
-      Gm[2][0][2] = Gm[2][2][0] = rcp(r);
-      Gm[2][1][2] = Gm[2][2][1] = cs * rcp(sn);
+      const double r = G.geo.xc0[i + G.g[0]], ir = rcp(r);
+      const double sn = G.geo.sc1[j + G.g[1]], cs = G.geo.cc1[j + G.g[1]], ct = cs * rcp(sn);
+      nb[1][0] += -r * beta[1];
+      nb[2][0] += -r * sn * sn * beta[2];
+      nb[0][1] += ir * beta[1];
+      nb[1][1] += ir * beta[0];
+      nb[2][1] += -sn * cs * beta[2];
+      nb[0][2] += ir * beta[2];
+      nb[2][2] += ir * beta[0];
+      nb[1][2] += ct * beta[2];
+      nb[2][2] += ct * beta[1];
     }
-    double nb[3][3];  // nb[i][k] = d_i beta^k + Gamma^k_il beta^l
-#pragma unroll
-    for (int a = 0; a < 3; a++)
-#pragma unroll
-      for (int c = 0; c < 3; c++)
-        nb[a][c] = db[a][c] + Gm[c][a][0] * beta[0] + Gm[c][a][1] * beta[1] + Gm[c][a][2] * beta[2];
     double K[3][3];
     if (kij) {
       const int map[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
 #pragma unroll
       for (int a = 0; a < 3; a++)
 #pragma unroll
-        for (int c = 0; c < 3; c++) K[a][c] = kij[map[a][c]];
+        for (int c = 0; c < 3; c++) K[a][c] = kij[map[a][c] * kst];
     } else {
       const double divb = nb[0][0] + nb[1][1] + nb[2][2];
       const double kf = psi4 * 0.5 * ia;
@@ -693,14 +693,7 @@ __device__ __forceinline__ void stage_staged(const Grid &G, int i0, int j0, int 
         return met[w * G.nv + oc + (a < 0 ? 0 : o * G.s[a])];
       }
     };
-    double kc[6];
-    const double *kp = nullptr;
-    if (kij) {
-#pragma unroll
-      for (int m = 0; m < 6; m++) kc[m] = kij[m * G.nv + oc];
-      kp = kc;
-    }
-    cell_sources(G, prc, metv, flat && !kij, kp, i, j, acc);
+    cell_sources(G, prc, metv, flat && !kij, kij ? kij + oc : nullptr, G.nv, i, j, acc);
   }
   // the caller's loads (the next tile's region) go out together with the
   // loads of the RK combination, so that their latencies overlap
