@@ -113,6 +113,16 @@ __device__ __forceinline__ double mc_slope(double a, double b, double c) {
   return (dl * dr > 0.0) ? copysign(m, cen) : 0.0;
 }
 
+// Half the monotonised-central slope, written minmod(dl, (dl + dr) / 4, dr):
+// scaling by powers of two is exact, so this is bit for bit 0.5 *
+// mc_slope(a, b, c), with two multiplications fewer.
+__device__ __forceinline__ double mc_half_slope(double a, double b, double c) {
+  const double dl = b - a, dr = c - b;
+  const double q = 0.25 * (dl + dr);
+  const double m = fmin(fmin(fabs(dl), fabs(q)), fabs(dr));
+  return (dl * dr > 0.0) ? copysign(m, q) : 0.0;
+}
+
 // MP5 (Suresh & Huynh 1997; the default reconstruction of section 3): the
 // left-biased interface value at i+1/2 from u_{i-2..i+2} = a..e.  The
 // fifth-order value is kept when it lies between u_i and the monotonicity

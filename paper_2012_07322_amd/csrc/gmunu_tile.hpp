@@ -151,8 +151,8 @@ __device__ __forceinline__ void face_flux(const Grid &G, const double *S, int NP
     for (int v = 0; v < NV; v++) {
       const double *Sv = S + v * NP;
       const double a = Sv[ix[0]], b = Sv[r1], e = Sv[r2], f = Sv[ix[3]];
-      pl[v] = b + 0.5 * mc_slope(a, b, e);
-      pr[v] = e - 0.5 * mc_slope(b, e, f);
+      pl[v] = b + mc_half_slope(a, b, e);
+      pr[v] = e - mc_half_slope(b, e, f);
     }
   } else {
 #pragma unroll
