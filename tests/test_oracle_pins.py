@@ -6,6 +6,7 @@ Riemann solver, exact wave solutions, closed forms, conservation laws,
 printed convergence rates of the paper).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -450,11 +451,25 @@ def test_shock_tube_with_uniform_shift_is_the_translated_solution(beta):
     assert np.sum(np.abs(prim[0] - ex0)) * dx > 10 * errs[1]
 
 
+def _golden(name):
+    """Rows of a whitespace-separated fixture under tests/golden ('#' starts
+    a comment)."""
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].split()
+            if line:
+                rows.append(line)
+    return rows
+
+
 def test_alfven_wave_convergence_matches_paper_rates():
     """Circularly polarised Alfven wave (section 3.2.1): v_A = 1/2 exactly, so
     at t = 2 the exact state is the initial one.  HLL + MC + SSPRK2 rates of
-    ||B^z(2) - B^z(0)||_1 against the printed R_N of Table 2 (2.32, 2.11,
-    2.04 at N = 64, 128, 256)."""
+    ||B^z(2) - B^z(0)||_1 against the printed R_N of Table 2
+    (tests/golden/alfven_table2.txt: 2.32, 2.11, 2.04 at N = 64, 128, 256).
+    The printed norms themselves are not reproduced (the oracle's are 6-9
+    times larger at the same N; the rates agree)."""
     assert W.alfven_speed2() == pytest.approx(0.25, abs=1e-15)
     errs = []
     for n in (32, 64, 128, 256):
@@ -466,7 +481,9 @@ def test_alfven_wave_convergence_matches_paper_rates():
         assert nf == 0 and abs(t - 2.0) < 1e-13
         errs.append(np.mean(np.abs(oracle.interior(p, pr)[7] - bz0)))
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
-    np.testing.assert_allclose(rates, [2.32, 2.11, 2.04], atol=0.1)
+    table = {int(r[0]): r for r in _golden("alfven_table2.txt")}
+    printed = [float(table[n][2]) for n in (64, 128, 256)]
+    np.testing.assert_allclose(rates, printed, atol=0.1)
 
 
 def test_smooth_wave_second_order():
@@ -522,12 +539,13 @@ def test_static_star_residual_converges_second_order():
 
 def test_tov_fixture_matches_printed_star_numbers():
     """The star fixture reproduces the numbers the paper prints for its
-    migration test (section 3.3): the SU star (rho_c = 8e-3) has isotropic
-    radius 4.267, and its stable partner of equal baryon mass has
-    rho_c = 1.346e-3."""
-    su = W.tov_isotropic(8e-3)
-    assert su["R_iso"] == pytest.approx(4.267, abs=1e-3)
-    st = W.tov_isotropic(1.346e-3)
+    migration test (section 3.3, tests/golden/migration_stars.txt): the
+    unstable star (rho_c = 8e-3) has isotropic radius 4.267, and its stable
+    partner of equal baryon mass has rho_c = 1.346e-3."""
+    g = {r[0]: float(r[1]) for r in _golden("migration_stars.txt")}
+    su = W.tov_isotropic(g["rho_c_unstable"])
+    assert su["R_iso"] == pytest.approx(g["radius_unstable"], abs=1e-3)
+    st = W.tov_isotropic(g["rho_c_stable"])
     assert st["Mb"] == pytest.approx(su["Mb"], rel=3e-4)
 
 
