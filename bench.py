@@ -235,7 +235,7 @@ def bench_fused(n=256, steps=10, cfl=0.4, seed=0):
     return res
 
 
-def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True, single_n=192):
+def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True, single_n=192, classes=False):
     """Many AMR-style blocks (8^3, 16^3, 32^3 interiors, spherical and
     Cartesian, TOV-profile magnetised states), each its own simulation with
     its own time step, advanced (a) by the batched graph-captured step and
@@ -353,6 +353,8 @@ def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True, si
     for g in grids:
         g.close()
     B.close()
+    if classes:
+        res["by_class"] = _blocks_by_class(ps, views, steps, cfl, tune)
     if single_n:
         res["same_physics_single_grid"] = _blocks_single_grid(ps, star, single_n, steps, cfl, dev)
         ref = res["same_physics_single_grid"]["value"]
@@ -360,6 +362,43 @@ def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True, si
         log(f"[blocks] single grid of the same physics: {ref:.3e} cell-updates/s; "
             f"batched / single = {res['batched']['value'] / ref:.3f}")
     return res
+
+
+def _blocks_by_class(ps, views, steps, cfl, tune):
+    """The batched rate of each (size, coordinates) class of blocks alone: a
+    batch of only that class's blocks, restarted from their current state."""
+    import torch
+
+    import paper_2012_07322_amd as gmu
+    import workloads as W
+
+    out = {}
+    for n in sorted({p["n"][0] for p in ps}):
+        for coord, cname in ((W.CART, "cartesian"), (W.SPH, "spherical")):
+            idx = [b for b, p in enumerate(ps) if p["n"][0] == n and p["coord"] == coord]
+            if not idx:
+                continue
+            B = gmu.Batch(len(idx), len(idx), 1 << 19)
+            for k, b in enumerate(idx):
+                v = views[b]
+                B.set_block(k, ps[b], v["qn_b"], v["qs_b"], v["pr_b"], v["met"], k)
+                B.set_group(k, 0.0, 1e30)
+            B.commit()
+            B.init()
+            if tune:
+                B.autotune()
+            B.step(cfl)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                B.step(cfl)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / steps
+            B.close()
+            cells = sum(ps[b]["n"][0] * ps[b]["n"][1] * ps[b]["n"][2] for b in idx)
+            out[f"{n}^3 {cname}"] = {"blocks": len(idx), "ms_per_step": sec * 1e3, "value": 3 * cells / sec}
+            log(f"[blocks]   {n}^3 {cname}: {len(idx)} blocks, {3 * cells / sec:.3e} cell-updates/s")
+    return out
 
 
 def _blocks_single_grid(ps, star, n, steps, cfl, dev):
@@ -492,7 +531,7 @@ def _drive_plain(reqs, offsets, dev, cfl):
 
 
 def bench_serve(nreq=1000, probe=300, plain_n=300, plain_open=100, concurrency=64, load=0.8, seed=0,
-                budget_gb=64.0, slots=512, spsync=2, cfl=0.4):
+                budget_gb=64.0, slots=512, spsync=2, cfl=0.4, rate=None):
     """Serving workload: independent 1D shock tubes (200-4096 cells, to
     t = 0.4) and 2D / 3D blast waves (64^2-1024^2, 32^3-128^3, 50 steps),
     Poisson arrivals.  (1) Capacity: the first `probe` requests with
@@ -541,7 +580,10 @@ def bench_serve(nreq=1000, probe=300, plain_n=300, plain_open=100, concurrency=6
             r["cells"] = _serve_cells(reqs[r["k"]], steps[r["k"]])
     cap_plain = summary(precs, pt0, pbusy)
     log(f"[serve]   plain {cap_plain['req_per_s']:.1f} req/s")
-    rate = load * cap["req_per_s"]
+    if rate is None:
+        rate = load * cap["req_per_s"]
+    else:
+        load = rate / cap["req_per_s"]
     offs = [r["arrival"] / rate for r in reqs[:nreq]]
     log(f"[serve] open loop: {nreq} requests at {rate:.1f} req/s ({load:.0%} of the server's capacity)")
     recs, t0 = _drive_server(S, reqs[:nreq], dev, offsets=offs)
@@ -560,6 +602,8 @@ def bench_serve(nreq=1000, probe=300, plain_n=300, plain_open=100, concurrency=6
     same = min(probe, plain_n)
     return {
         "workload": "serving_poisson", "seed": seed, "budget_gib": budget_gb, "slots_per_lane": slots,
+        "stream": ("the full 10,000-request stream" if nreq >= 10000 else
+                   f"a sample: the first {nreq} requests of the 10,000-request stream"),
         "steps_per_sync": spsync, "cfl": cfl,
         "mix": "1D tube N in [200,4096] to t=0.4; 2D blast N^2, N in [64,1024]; 3D blast N^3, N in [32,128]; "
                "50 steps; dimension equally likely, N uniform",
@@ -848,11 +892,15 @@ def main():
     ap.add_argument("--blocks", type=int, default=3000,
                     help="AMR-style blocks for the batched-vs-plain comparison (0: skip)")
     ap.add_argument("--block-steps", type=int, default=5)
+    ap.add_argument("--block-classes", action="store_true",
+                    help="also time the batch on each (size, coordinates) class of blocks alone")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="open-loop requests for the serving measurement (0: skip)")
     ap.add_argument("--serve-probe", type=int, default=300)
     ap.add_argument("--serve-plain", type=int, default=300)
     ap.add_argument("--serve-plain-open", type=int, default=100)
+    ap.add_argument("--serve-rate", type=float, default=None,
+                    help="open-loop arrival rate in req/s (default: 80%% of the measured capacity)")
     ap.add_argument("--mg", type=int, default=256, help="multigrid grid size (0: skip)")
     ap.add_argument("--xcfc", type=int, default=256, help="xCFC metric-solve grid size (0: skip)")
     ap.add_argument("--dynamical", type=int, default=256,
@@ -977,7 +1025,8 @@ def main():
         out["star2d"] = bench_star(256, 128, args.star_steps, cfl=args.cfl)
         torch.cuda.empty_cache()
     if args.blocks > 0:
-        out["blocks"] = bench_blocks(args.blocks, steps=args.block_steps, cfl=args.cfl, seed=args.seed)
+        out["blocks"] = bench_blocks(args.blocks, steps=args.block_steps, cfl=args.cfl, seed=args.seed,
+                                     classes=args.block_classes)
         torch.cuda.empty_cache()
     if args.mg > 0:
         out["multigrid"] = bench_mg(args.mg)
@@ -993,7 +1042,8 @@ def main():
         torch.cuda.empty_cache()
     if args.serve_requests > 0:
         out["serving"] = bench_serve(args.serve_requests, probe=args.serve_probe, plain_n=args.serve_plain,
-                                     plain_open=args.serve_plain_open, seed=args.seed, cfl=args.cfl)
+                                     plain_open=args.serve_plain_open, seed=args.seed, cfl=args.cfl,
+                                     rate=args.serve_rate)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on a {n}x{n}x{args.cpu_slab} slab")
