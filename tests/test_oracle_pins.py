@@ -893,6 +893,64 @@ def test_pp_limiter_keeps_the_euler_update_positive(riemann=0):
     assert q1[0].min() > 0.0 and q1[4].min() > 0.0
 
 
+_PP_MIN_RULE = """    double theta = 1.0;
+    const int comp[2] = {QD, QTAU};
+    for (int m = 0; m < 2; m++) {
+      int v = comp[m];
+      double fho = out[v], fl = flf[v] * area;
+      if (in0) theta = fmin(theta, pp_theta(pp->qbase[v * nt + idx[2]], dV0, pp->dt, fho, fl, -1.0));
+      if (in1) theta = fmin(theta, pp_theta(pp->qbase[v * nt + idx[3]], dV1, pp->dt, fho, fl, +1.0));
+    }
+"""
+_PP_MAX_RULE = """    double thv[2] = {1.0, 1.0};
+    const int comp[2] = {QD, QTAU};
+    for (int m = 0; m < 2; m++) {
+      int v = comp[m];
+      double fho = out[v], fl = flf[v] * area;
+      if (in0) thv[m] = fmin(thv[m], pp_theta(pp->qbase[v * nt + idx[2]], dV0, pp->dt, fho, fl, -1.0));
+      if (in1) thv[m] = fmin(thv[m], pp_theta(pp->qbase[v * nt + idx[3]], dV1, pp->dt, fho, fl, +1.0));
+    }
+    double theta = fmax(thv[0], thv[1]);
+"""
+
+
+def test_pp_limiter_literal_maximum_rule_loses_positivity(tmp_path):
+    """Reading of section 2.4: the paper takes the larger of the weights that
+    D and tau each allow; the oracle takes the smaller.  In the evacuating
+    cell the high-order flux keeps D positive (its weight is 1) while it
+    drives tau below zero, so the literal rule picks 1 and limits nothing:
+    an oracle compiled with that rule leaves tau of the cell negative after
+    the stage's Euler update, where the oracle as written keeps both D and
+    tau positive."""
+    import subprocess
+
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "gmunu_oracle.c")).read()
+    assert src.count(_PP_MIN_RULE) == 1
+    c = tmp_path / "pp_max_rule.c"
+    c.write_text(src.replace(_PP_MIN_RULE, _PP_MAX_RULE))
+    so = tmp_path / "pp_max_rule.so"
+    subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", str(so), str(c), "-lm"])
+
+    def euler_stage():
+        p, q, pr, met = _evacuating_cell(1)
+        dt = oracle.cfl_dt(p, pr, met, 0.4)
+        qs = q.copy()
+        # the stage's conserved update before the recovery
+        oracle.rk_update(p, 0, dt, q, qs, pr, met)
+        return oracle.interior(p, qs)
+
+    q_min = euler_stage()
+    saved = (oracle._LIB, oracle._lib)
+    try:
+        oracle._LIB, oracle._lib = str(so), None
+        q_max = euler_stage()
+    finally:
+        oracle._LIB, oracle._lib = saved
+    assert q_min[0].min() > 0.0 and q_min[4].min() > 0.0
+    assert q_max[0].min() > 0.0
+    assert q_max[4].min() < 0.0
+
+
 def test_pp_limiter_acts_on_boundary_faces():
     """An evacuating cell next to the boundary, dense ghosts leaving it: the
     boundary face must be limited from its interior side alone for the cell
