@@ -39,6 +39,10 @@ struct BlockRec {
   uint8_t *flags;
   int group;
   int active;
+  // ghosts of the x faces (the first xghosts in ghost_one's numbering)
+  // filled by the recovery kernel of a step, 0 when the ghost kernel fills
+  // them (see row_local_x_ghosts)
+  long xghosts;
 };
 
 // Compiled tile shapes (256 threads; each pass has at most 256 faces) and
@@ -122,17 +126,33 @@ __global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC
 }
 
 // Recovery on 256-cell items: from q_n (use_qn) or q_s.  force: ignore dt.
+// xfill: a block with xghosts > 0 (its items are whole x-rows) also gets the
+// x-face ghosts of the item's rows, which read only cells of their own row,
+// once the workgroup has recovered them.
 __global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, DList L, const double *dts, int use_qn,
-                                             int force, unsigned int *nfatal, unsigned int *gfatal) {
+                                             int force, unsigned int *nfatal, unsigned int *gfatal, int xfill) {
   const int nent = L.meta[0], n = L.meta[1];
   int e = -1;
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     e = find_entry(L.start, nent, it, e);
     const BlockRec &b = B[L.blk[e]];
-    if (!force && dts[b.group] == 0.0) continue;
+    if (!force && dts[b.group] == 0.0) continue;  // the same for the whole item
     const long t = (long)(it - L.start[e]) * NT + threadIdx.x;
     if (t < interior_count(b.G))
       c2p_one(b.G, use_qn ? b.qn : b.qs, b.met, b.prim, b.flags, nfatal, t, gfatal ? gfatal + b.group : nullptr);
+    if (xfill && b.xghosts > 0) {
+      __syncthreads();  // the item's primitives, recovered by other threads
+      const int n0 = b.G.n[0], ng = b.G.g[0];
+      const long rows = interior_count(b.G) / n0, per = NT / n0;
+      const long r0 = (long)(it - L.start[e]) * per;
+      const int nr = (int)(rows - r0 < per ? rows - r0 : per);
+      // ghost_one numbers the x-face ghosts (side, layer, row)
+      for (int q = threadIdx.x; q < 2 * ng * nr; q += NT) {
+        const int sl = q / nr, ro = q - sl * nr;
+        ghost_one(b.G, b.prim, (long)sl * rows + r0 + ro);
+      }
+      __syncthreads();  // before the next item's recovery reuses the threads
+    }
   }
 }
 
@@ -151,6 +171,9 @@ __global__ __launch_bounds__(NT) void k_bprim2con(const BlockRec *__restrict__ B
   }
 }
 
+// Ghost fill on 256-ghost items.  force: ignore dt, and fill every ghost
+// (an init); otherwise a block's first xghosts ghosts (filled by the
+// recovery kernel) are skipped.
 __global__ __launch_bounds__(NT) void k_bghosts(const BlockRec *__restrict__ B, DList L, const double *dts,
                                                 int force) {
   const int nent = L.meta[0], n = L.meta[1];
@@ -159,7 +182,7 @@ __global__ __launch_bounds__(NT) void k_bghosts(const BlockRec *__restrict__ B, 
     e = find_entry(L.start, nent, it, e);
     const BlockRec &b = B[L.blk[e]];
     if (!force && dts[b.group] == 0.0) continue;
-    const long t = (long)(it - L.start[e]) * NT + threadIdx.x;
+    const long t = (long)(it - L.start[e]) * NT + threadIdx.x + (force ? 0 : b.xghosts);
     if (t < ghost_count(b.G)) ghost_one(b.G, b.prim, t);
   }
 }
@@ -249,12 +272,31 @@ long stage_items(const gmunu_grid_desc &d, int v) {
 
 long cell_items(const gmunu_grid_desc &d) { return ceil_div((long)d.n[0] * d.n[1] * d.n[2], NT); }
 
-long ghost_items(const gmunu_grid_desc &d) {
+// x-face ghosts that the recovery kernel of a step fills: every 256-cell
+// item of the block is whole x-rows (n0 divides 256) and the x boundary
+// rules read only the ghost's own row (periodic, outflow, reflect); else 0.
+// Rows shorter than 16 cells stay with the ghost kernel (measured: an item
+// of 32 rows of 8 spends more on the added barriers than it saves).
+long row_local_x_ghosts(const gmunu_grid_desc &d) {
+  const int n0 = d.n[0];
+  if (n0 < 16 || n0 > NT || NT % n0) return 0;
+  for (int s = 0; s < 2; s++) {
+    const int bc = d.bc[0][s];
+    if (bc != GMUNU_BC_PERIODIC && bc != GMUNU_BC_OUTFLOW && bc != GMUNU_BC_REFLECT) return 0;
+  }
+  return 2L * d.ng * ((long)d.n[1] * d.n[2]);
+}
+
+long ghost_cells(const gmunu_grid_desc &d) {
   const long nin = (long)d.n[0] * d.n[1] * d.n[2];
   long tot = 0;
   for (int a = 0; a < d.ndim; a++) tot += 2L * d.ng * (nin / d.n[a]);
-  return ceil_div(tot, NT);
+  return tot;
 }
+
+// Items of the ghost list of a step (init: all ghosts).
+long ghost_items(const gmunu_grid_desc &d) { return ceil_div(ghost_cells(d) - row_local_x_ghosts(d), NT); }
+long ghost_items_all(const gmunu_grid_desc &d) { return ceil_div(ghost_cells(d), NT); }
 
 // Host copy of one list's entry table.
 struct HList {
@@ -463,7 +505,7 @@ int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, unsigned mask
       for (int l = 0; l < NSL; l++)
         if (mask & (1u << l)) launch_list_any<1>(l, b->d_rec, b->list(l), b->d_dt, ca, cb, last, sh.st[l], st);
       hipLaunchKernelGGL(k_bc2p, dim3(sh.c2p), dim3(NT), 0, st, b->d_rec, b->list(L_C2P), b->d_dt, last, 0, nfatal,
-                         b->d_gfatal);
+                         b->d_gfatal, 1);
       hipLaunchKernelGGL(k_bghosts, dim3(sh.gh), dim3(NT), 0, st, b->d_rec, b->list(L_GH), b->d_dt, 0);
     }
   }
@@ -656,6 +698,7 @@ int gmunu_batch_set_block(gmunu_batch *b, int slot, const gmunu_block *blk) {
   r.flags = blk->flags;
   r.group = blk->group;
   r.active = 1;
+  r.xghosts = row_local_x_ghosts(blk->desc);
   b->rec[slot] = r;
   b->blk[slot] = *blk;
   b->used[slot] = 1;
@@ -749,7 +792,7 @@ int gmunu_batch_init(gmunu_batch *b, const int *slots, int nslots, void *stream)
   for (int s = 0; s < b->maxb; s++) {
     if (!b->used[s] || !sel[s]) continue;
     hc.add(s, cell_items(b->blk[s].desc));
-    hg.add(s, ghost_items(b->blk[s].desc));
+    hg.add(s, ghost_items_all(b->blk[s].desc));
   }
   if (hc.total > b->maxi || hg.total > b->maxi) return GMUNU_EINVAL;
   int meta[4];
@@ -761,7 +804,7 @@ int gmunu_batch_init(gmunu_batch *b, const int *slots, int nslots, void *stream)
   hipLaunchKernelGGL(k_bghosts, dim3(gg), dim3(NT), 0, st, b->d_rec, b->list(L_IGH), b->d_dt, 1);
   hipLaunchKernelGGL(k_bprim2con, dim3(gc), dim3(NT), 0, st, b->d_rec, b->list(L_IC2P));
   hipLaunchKernelGGL(k_bc2p, dim3(gc), dim3(NT), 0, st, b->d_rec, b->list(L_IC2P), b->d_dt, 1, 1,
-                     (unsigned int *)nullptr, (unsigned int *)nullptr);
+                     (unsigned int *)nullptr, (unsigned int *)nullptr, 0);
   hipLaunchKernelGGL(k_bghosts, dim3(gg), dim3(NT), 0, st, b->d_rec, b->list(L_IGH), b->d_dt, 1);
   return launch_status();
 }
