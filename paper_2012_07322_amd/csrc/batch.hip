@@ -41,8 +41,10 @@ struct BlockRec {
   int active;
   // ghosts of the x faces (the first xghosts in ghost_one's numbering)
   // filled by the recovery kernel of a step, 0 when the ghost kernel fills
-  // them (see row_local_x_ghosts)
+  // them; xends: by the first and last item of a 1D block rather than row
+  // by row (see recovery_x_ghosts)
   long xghosts;
+  int xends;
 };
 
 // Compiled tile shapes (256 threads; each pass has at most 256 faces) and
@@ -126,9 +128,11 @@ __global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC
 }
 
 // Recovery on 256-cell items: from q_n (use_qn) or q_s.  force: ignore dt.
-// xfill: a block with xghosts > 0 (its items are whole x-rows) also gets the
-// x-face ghosts of the item's rows, which read only cells of their own row,
-// once the workgroup has recovered them.
+// xfill: a block with xghosts > 0 also gets its x-face ghosts once the
+// workgroup has recovered their sources: row by row when its items are
+// whole x-rows (each ghost reads only its own row), or, in 1D (xends), the
+// ghosts whose sources lie in the first item by that item and the others
+// by the last item.
 __global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, DList L, const double *dts, int use_qn,
                                              int force, unsigned int *nfatal, unsigned int *gfatal, int xfill) {
   const int nent = L.meta[0], n = L.meta[1];
@@ -140,7 +144,22 @@ __global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, DLi
     const long t = (long)(it - L.start[e]) * NT + threadIdx.x;
     if (t < interior_count(b.G))
       c2p_one(b.G, use_qn ? b.qn : b.qs, b.met, b.prim, b.flags, nfatal, t, gfatal ? gfatal + b.group : nullptr);
-    if (xfill && b.xghosts > 0) {
+    if (xfill && b.xghosts > 0 && b.xends) {
+      const int ii = it - L.start[e], ni = L.start[e + 1] - L.start[e];
+      if (ii == 0 || ii == ni - 1) {
+        __syncthreads();  // the item's primitives, recovered by other threads
+        const int ng = b.G.g[0];
+        if (threadIdx.x < 2 * ng) {
+          // ghost q: side q / ng; its sources are at the lower end of the
+          // line (first item) for an outflow or reflecting lower face and
+          // a periodic upper face, else at the upper end (last item)
+          const int side = threadIdx.x / ng, bc = b.G.bc[0][side];
+          const bool lower = side == 0 ? bc != BC_PERIODIC : bc == BC_PERIODIC;
+          if (lower ? ii == 0 : ii == ni - 1) ghost_one(b.G, b.prim, threadIdx.x);
+        }
+        __syncthreads();  // before the next item's recovery reuses the threads
+      }
+    } else if (xfill && b.xghosts > 0) {
       __syncthreads();  // the item's primitives, recovered by other threads
       const int n0 = b.G.n[0], ng = b.G.g[0];
       const long rows = interior_count(b.G) / n0, per = NT / n0;
@@ -272,19 +291,29 @@ long stage_items(const gmunu_grid_desc &d, int v) {
 
 long cell_items(const gmunu_grid_desc &d) { return ceil_div((long)d.n[0] * d.n[1] * d.n[2], NT); }
 
-// x-face ghosts that the recovery kernel of a step fills: every 256-cell
-// item of the block is whole x-rows (n0 divides 256) and the x boundary
-// rules read only the ghost's own row (periodic, outflow, reflect); else 0.
-// Rows shorter than 16 cells stay with the ghost kernel (measured: an item
-// of 32 rows of 8 spends more on the added barriers than it saves).
-long row_local_x_ghosts(const gmunu_grid_desc &d) {
+// x-face ghosts that the recovery kernel of a step fills (else 0), when the
+// x boundary rules read only cells of the ghost's own row (periodic,
+// outflow, reflect) and (a) every 256-cell item of the block is whole
+// x-rows (n0 divides 256; rows shorter than 16 cells stay with the ghost
+// kernel: an item of 32 rows of 8 spends more on the added barriers than it
+// saves), or (b) the block is 1D and each face's sources lie in its first
+// or its last item (*ends set): outflow reads the end cell, reflect the
+// ng cells at its end, periodic the ng cells at the other end, so the last
+// item must hold the last ng cells when a reflecting upper or a periodic
+// lower face reads them.
+long recovery_x_ghosts(const gmunu_grid_desc &d, int *ends = nullptr) {
   const int n0 = d.n[0];
-  if (n0 < 16 || n0 > NT || NT % n0) return 0;
+  if (ends) *ends = 0;
   for (int s = 0; s < 2; s++) {
     const int bc = d.bc[0][s];
     if (bc != GMUNU_BC_PERIODIC && bc != GMUNU_BC_OUTFLOW && bc != GMUNU_BC_REFLECT) return 0;
   }
-  return 2L * d.ng * ((long)d.n[1] * d.n[2]);
+  if (n0 >= 16 && n0 <= NT && NT % n0 == 0) return 2L * d.ng * ((long)d.n[1] * d.n[2]);
+  if (d.ndim != 1) return 0;
+  const bool tail_read = d.bc[0][1] == GMUNU_BC_REFLECT || d.bc[0][0] == GMUNU_BC_PERIODIC;
+  if (tail_read && n0 % NT != 0 && n0 % NT < d.ng) return 0;
+  if (ends) *ends = 1;
+  return 2L * d.ng;
 }
 
 long ghost_cells(const gmunu_grid_desc &d) {
@@ -295,7 +324,7 @@ long ghost_cells(const gmunu_grid_desc &d) {
 }
 
 // Items of the ghost list of a step (init: all ghosts).
-long ghost_items(const gmunu_grid_desc &d) { return ceil_div(ghost_cells(d) - row_local_x_ghosts(d), NT); }
+long ghost_items(const gmunu_grid_desc &d) { return ceil_div(ghost_cells(d) - recovery_x_ghosts(d), NT); }
 long ghost_items_all(const gmunu_grid_desc &d) { return ceil_div(ghost_cells(d), NT); }
 
 // Host copy of one list's entry table.
@@ -314,7 +343,7 @@ struct HList {
 // workgroup per item of its list (a power of two, at most its cap), so that a
 // step over a few small blocks does not launch thousands of idle workgroups.
 struct Shape {
-  int cfl = 1, c2p = 1, gh = 1;
+  int cfl = 1, c2p = 1, gh = 0;  // gh = 0: no ghost kernel (an empty ghost list)
   int st[NSL];
   Shape() {
     for (int &g : st) g = 1;
@@ -329,10 +358,12 @@ int grid_for(long items, int cap) {
 
 // A step captured with grids `have` serves lists that want `want` while no
 // list outgrew its grid and none shrank below an eighth of a grid of more
-// than 64 workgroups (any grid size gives the same results).
+// than 64 workgroups (any grid size gives the same results); a ghost list
+// that emptied is still launched, empty.
 bool shape_fits(const Shape &have, const Shape &want) {
   auto ok = [](int h, int w) { return w <= h && (8 * w > h || h <= 64); };
-  if (!ok(have.cfl, want.cfl) || !ok(have.c2p, want.c2p) || !ok(have.gh, want.gh)) return false;
+  if (!ok(have.cfl, want.cfl) || !ok(have.c2p, want.c2p)) return false;
+  if (want.gh && !ok(have.gh, want.gh)) return false;
   for (int l = 0; l < NSL; l++)
     if (!ok(have.st[l], want.st[l])) return false;
   return true;
@@ -452,7 +483,7 @@ Shape step_shape(const gmunu_batch *b) {
   Shape sh;
   sh.cfl = grid_for(b->counts[L_CFL], cap);
   sh.c2p = grid_for(b->counts[L_C2P], cap);
-  sh.gh = grid_for(b->counts[L_GH], cap);
+  sh.gh = b->counts[L_GH] ? grid_for(b->counts[L_GH], cap) : 0;
   for (int l = 0; l < NSL; l++) sh.st[l] = grid_for(b->counts[l], cap);
   return sh;
 }
@@ -465,7 +496,7 @@ Shape with_headroom(const gmunu_batch *b, const Shape &w) {
   Shape sh;
   sh.cfl = up(w.cfl);
   sh.c2p = up(w.c2p);
-  sh.gh = up(w.gh);
+  sh.gh = w.gh ? up(w.gh) : 0;
   for (int l = 0; l < NSL; l++) sh.st[l] = up(w.st[l]);
   return sh;
 }
@@ -506,7 +537,7 @@ int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, unsigned mask
         if (mask & (1u << l)) launch_list_any<1>(l, b->d_rec, b->list(l), b->d_dt, ca, cb, last, sh.st[l], st);
       hipLaunchKernelGGL(k_bc2p, dim3(sh.c2p), dim3(NT), 0, st, b->d_rec, b->list(L_C2P), b->d_dt, last, 0, nfatal,
                          b->d_gfatal, 1);
-      hipLaunchKernelGGL(k_bghosts, dim3(sh.gh), dim3(NT), 0, st, b->d_rec, b->list(L_GH), b->d_dt, 0);
+      if (sh.gh) hipLaunchKernelGGL(k_bghosts, dim3(sh.gh), dim3(NT), 0, st, b->d_rec, b->list(L_GH), b->d_dt, 0);
     }
   }
   return launch_status();
@@ -698,7 +729,7 @@ int gmunu_batch_set_block(gmunu_batch *b, int slot, const gmunu_block *blk) {
   r.flags = blk->flags;
   r.group = blk->group;
   r.active = 1;
-  r.xghosts = row_local_x_ghosts(blk->desc);
+  r.xghosts = recovery_x_ghosts(blk->desc, &r.xends);
   b->rec[slot] = r;
   b->blk[slot] = *blk;
   b->used[slot] = 1;

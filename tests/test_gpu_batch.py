@@ -114,6 +114,44 @@ def test_batch_equals_each_block_alone(tune, graph):
         assert np.array_equal(pa, pb), f"block {slot} prim differs"
 
 
+def _tube(n, bc_lo, bc_hi):
+    p, pr, met = W.mhd_shock_tube(n)
+    p["bc"] = [[bc_lo, bc_hi]] + [list(b) for b in p["bc"][1:]]
+    if W.PERIODIC in (bc_lo, bc_hi):
+        p["bc"][0] = [W.PERIODIC, W.PERIODIC]
+    return p, pr, met
+
+
+def test_x_ghosts_filled_by_the_recovery_equal_alone():
+    """Blocks whose x-face ghosts the recovery kernel fills (rows of 16-256
+    cells dividing 256; 1D lines, from their first and last items) and
+    blocks whose ghosts stay with the ghost kernel (a 1D line whose last
+    item holds fewer cells than a reflecting upper face reads, 8-cell rows):
+    outflow, reflecting and periodic x faces, all bitwise equal to the same
+    grid advanced alone after several steps."""
+    blocks = [_tube(300, W.OUTFLOW, W.OUTFLOW), _tube(300, W.REFLECT, W.OUTFLOW), _tube(300, W.OUTFLOW, W.REFLECT),
+              _tube(512, W.PERIODIC, W.PERIODIC), _tube(257, W.OUTFLOW, W.REFLECT), _tube(257, W.PERIODIC, W.PERIODIC),
+              _tube(200, W.REFLECT, W.REFLECT), _tube(64, W.OUTFLOW, W.OUTFLOW), _tube(1, W.OUTFLOW, W.OUTFLOW)]
+    p2, pr2, met2 = W.blast_wave_2d(32)
+    blocks.append((p2, pr2, met2))
+    blocks += mixed_blocks(4, seed=5)
+    groups = list(range(len(blocks)))
+    B, views, _ = make_batch(blocks, groups)
+    items, _ = B.info()
+    note(f"  ghost items of the step: {int(items[2])}")
+    nst = 4
+    for _ in range(nst):
+        B.step(0.4)
+    torch.cuda.synchronize()
+    t_b, _ = B.times()
+    for slot, (p, pr, met) in enumerate(blocks):
+        qa, pa, ta = alone(p, pr, met, nst)
+        qb, pb = views[slot][0].cpu().numpy(), views[slot][1].cpu().numpy()
+        assert t_b[slot] == ta, slot
+        assert np.array_equal(W.interior(p, qa), W.interior(p, qb)), f"block {slot} q differs"
+        assert np.array_equal(pa, pb), f"block {slot} prim differs"
+
+
 def test_batch_shared_dt_group_against_oracle():
     # blocks inside the star (density far above the atmosphere floor, where
     # the atmosphere threshold cannot flip between the two implementations)
