@@ -45,6 +45,7 @@ struct BlockRec {
   // by row (see recovery_x_ghosts)
   long xghosts;
   int xends;
+  int cfl_start;  // the block's first item in the CFL list (set at commit)
 };
 
 // Compiled tile shapes (256 threads; each pass has at most 256 faces) and
@@ -132,9 +133,15 @@ __global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC
 // workgroup has recovered their sources: row by row when its items are
 // whole x-rows (each ghost reads only its own row), or, in 1D (xends), the
 // ghosts whose sources lie in the first item by that item and the others
-// by the last item.
+// by the last item.  part non-null (the last stage of a step followed by
+// another step of the same launch sequence): the item's CFL rate maximum,
+// from the primitives just recovered (nothing changes the interior
+// primitives before the next step), at its place in the CFL list, so that
+// the next step needs no CFL kernel.  Items skipped for dt = 0 write none:
+// their group's dt stays 0 in the next step whatever its maxima.
 __global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, DList L, const double *dts, int use_qn,
-                                             int force, unsigned int *nfatal, unsigned int *gfatal, int xfill) {
+                                             int force, unsigned int *nfatal, unsigned int *gfatal, int xfill,
+                                             double *part) {
   const int nent = L.meta[0], n = L.meta[1];
   int e = -1;
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
@@ -171,6 +178,11 @@ __global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, DLi
         ghost_one(b.G, b.prim, (long)sl * rows + r0 + ro);
       }
       __syncthreads();  // before the next item's recovery reuses the threads
+    }
+    if (part) {
+      const double r = t < interior_count(b.G) ? cfl_one(b.G, b.prim, b.met, t) : 0.0;
+      const double m = block_max(r);
+      if (threadIdx.x == 0) part[b.cfl_start + (it - L.start[e])] = m;
     }
   }
 }
@@ -515,7 +527,9 @@ int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, unsigned mask
     }
   const int gfin = (b->maxg + NT / 64 - 1) / (NT / 64);
   for (int k = 0; k < steps; k++) {
-    hipLaunchKernelGGL(k_bcfl, dim3(sh.cfl), dim3(NT), 0, st, b->d_rec, b->list(L_CFL), b->d_part);
+    // CFL maxima: by the CFL kernel in the first step, by the last
+    // recovery of the previous step after that
+    if (k == 0) hipLaunchKernelGGL(k_bcfl, dim3(sh.cfl), dim3(NT), 0, st, b->d_rec, b->list(L_CFL), b->d_part);
     hipLaunchKernelGGL(k_bcfl_finish, dim3(gfin), dim3(NT), 0, st, b->d_gfirst, b->d_gcount, b->d_part, b->maxg,
                        cfl, b->d_t, b->d_tend, b->d_nstep, b->d_maxstep, b->d_dt);
     for (int s = 0; s < nst; s++) {
@@ -535,8 +549,9 @@ int enqueue_step(gmunu_batch *b, double cfl, unsigned int *nfatal, unsigned mask
       const int last = s == nst - 1;
       for (int l = 0; l < NSL; l++)
         if (mask & (1u << l)) launch_list_any<1>(l, b->d_rec, b->list(l), b->d_dt, ca, cb, last, sh.st[l], st);
+      double *part = last && k + 1 < steps ? b->d_part : nullptr;
       hipLaunchKernelGGL(k_bc2p, dim3(sh.c2p), dim3(NT), 0, st, b->d_rec, b->list(L_C2P), b->d_dt, last, 0, nfatal,
-                         b->d_gfatal, 1);
+                         b->d_gfatal, 1, part);
       if (sh.gh) hipLaunchKernelGGL(k_bghosts, dim3(sh.gh), dim3(NT), 0, st, b->d_rec, b->list(L_GH), b->d_dt, 0);
     }
   }
@@ -778,7 +793,13 @@ int gmunu_batch_commit(gmunu_batch *b, void *stream) {
   std::vector<int> gfirst(b->maxg), gcount(b->maxg);
   for (int g = 0; g < b->maxg; g++) {
     gfirst[g] = (int)h[L_CFL].total;
-    for (int s : by_group[g]) h[L_CFL].add(s, cell_items(b->blk[s].desc));
+    for (int s : by_group[g]) {
+      if (b->rec[s].cfl_start != (int)h[L_CFL].total) {
+        b->rec[s].cfl_start = (int)h[L_CFL].total;
+        b->touch(s);
+      }
+      h[L_CFL].add(s, cell_items(b->blk[s].desc));
+    }
     gcount[g] = (int)(h[L_CFL].total - gfirst[g]);
   }
   unsigned mask = 0;
@@ -835,7 +856,7 @@ int gmunu_batch_init(gmunu_batch *b, const int *slots, int nslots, void *stream)
   hipLaunchKernelGGL(k_bghosts, dim3(gg), dim3(NT), 0, st, b->d_rec, b->list(L_IGH), b->d_dt, 1);
   hipLaunchKernelGGL(k_bprim2con, dim3(gc), dim3(NT), 0, st, b->d_rec, b->list(L_IC2P));
   hipLaunchKernelGGL(k_bc2p, dim3(gc), dim3(NT), 0, st, b->d_rec, b->list(L_IC2P), b->d_dt, 1, 1,
-                     (unsigned int *)nullptr, (unsigned int *)nullptr, 0);
+                     (unsigned int *)nullptr, (unsigned int *)nullptr, 0, (double *)nullptr);
   hipLaunchKernelGGL(k_bghosts, dim3(gg), dim3(NT), 0, st, b->d_rec, b->list(L_IGH), b->d_dt, 1);
   return launch_status();
 }
