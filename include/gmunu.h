@@ -231,7 +231,12 @@ int gmunu_step_static(const gmunu_grid_desc *desc, double *q_n, double *q_s, dou
  * Blocks live in slots.  gmunu_batch_set_block / clear_block edit the host
  * table; gmunu_batch_commit uploads it (synchronous on `stream`).  Kernels
  * read the item counts from device memory, so a captured step stays valid
- * across commits.  A group whose dt is 0 (t >= t_end, or no time set) is
+ * across commits.  A step is the CFL kernel (maxima per item, then one
+ * wavefront per group for its dt and time), and per RK stage the stage
+ * kernels, the recovery kernel (which also fills the x-face ghosts of blocks
+ * whose 256-cell items are whole x-rows, and the ghosts of 1D lines, when
+ * their boundary rules read only the ghost's own row) and the ghost kernel
+ * for the rest.  A group whose dt is 0 (t >= t_end, or no time set) is
  * left untouched by a step.  Every block uses its own grid description and
  * arrays exactly as a single-grid context would.
  * ------------------------------------------------------------------------ */
@@ -285,8 +290,9 @@ int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int u
  * arrays of max_groups entries (each nullable); synchronises `stream`. */
 int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, int *nstep_host, unsigned int *nfatal_host,
                       void *stream);
-/* Number of committed items per list: [stage, c2p, ghosts]; tile variant
- * chosen per block (out_variant[slot], -1 for empty slots). */
+/* Number of committed items per list: [stage, c2p, ghosts] (ghosts of a
+ * step: the x-face ghosts that the recovery kernel fills are not counted);
+ * tile variant chosen per block (out_variant[slot], -1 for empty slots). */
 int gmunu_batch_info(gmunu_batch *b, long *items_out, int *out_variant);
 
 /* Kernel timing, for measurement only (not for use under graph capture).
