@@ -85,6 +85,40 @@ def test_served_results_equal_alone_under_memory_pressure():
         assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
 
 
+def test_every_lane_equal_alone():
+    """Solves of both integrators and of every kind of lane (1D lines, small
+    multi-dimensional solves, large ones above 65 536 interior cells) in
+    one server: each lane is made on its first solve, and every result
+    equals the same solve advanced alone bit for bit."""
+    spec = [(1, 300, 3), (1, 200, 2), (2, 40, 3), (2, 40, 2), (3, 14, 2), (2, 272, 3), (2, 264, 2),
+            (3, 12, 3), (1, 513, 2)]
+    probs = []
+    for i, (kind, n, rk) in enumerate(spec):
+        p, pr, met, te, ms = W.serving_problem({"kind": kind, "n": n, "seed": 40 + i, "arrival": 0.0}, "cuda")
+        p["rk"] = rk
+        if kind > 1:
+            ms = 6  # the large 2D solves stay short
+        probs.append((p, pr, met, te, ms))
+    S = gmu.Server(1 << 30, max_slots=8, cfl=0.4, steps_per_sync=2)
+    outs = []
+    for k, (p, pr, met, te, ms) in enumerate(probs):
+        q_out, p_out = torch.empty_like(pr), torch.empty_like(pr)
+        S.submit(p, pr, met, te, ms, q_out=q_out, prim_out=p_out, tag=k)
+        outs.append((q_out, p_out))
+    res = collect(S, len(probs))
+    info = S.status()
+    S.close()
+    assert info["error"] == 0
+    by_tag = {r["tag"]: r for r in res}
+    for k, (p, pr, met, te, ms) in enumerate(probs):
+        r = by_tag[k]
+        assert r["status"] == 0 and r["nfatal"] == 0, r
+        qa, pa, ta = alone(p, pr, met, te, ms)
+        assert r["t"] == ta, (k, r["t"], ta)
+        assert torch.equal(W.interior(p, qa), W.interior(p, outs[k][0])), f"request {k}: q differs"
+        assert torch.equal(pa, outs[k][1]), f"request {k}: prim differs"
+
+
 def test_host_buffers_and_late_arrivals():
     # inputs and outputs in host memory; a second wave submitted while the
     # first is running joins the running batch
