@@ -285,6 +285,13 @@ int gmunu_batch_init(gmunu_batch *b, const int *slots, int nslots, void *stream)
  * with: grids follow the committed work, so a batch of a few small blocks
  * launches few workgroups). */
 int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int use_graph, void *stream);
+/* nsteps >= 1 steps, each exactly as gmunu_batch_step with use_graph != 0,
+ * replayed from one captured graph of nsteps steps (captured again when
+ * nsteps changes).  Within the replay the CFL maxima of every step after
+ * the first are computed by the previous step's last recovery from the
+ * primitives it has just written, the values the CFL kernel would read:
+ * the results equal nsteps calls of gmunu_batch_step bit for bit. */
+int gmunu_batch_steps(gmunu_batch *b, double cfl, int nsteps, unsigned int *nfatal_dev, void *stream);
 /* Copy the groups' t, last dt, step counts and fatal-recovery counts (cells
  * flagged FATAL_* summed over stages since the group's set_group) to host
  * arrays of max_groups entries (each nullable); synchronises `stream`. */

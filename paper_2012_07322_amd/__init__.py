@@ -284,6 +284,7 @@ def _batch_sigs(L):
     L.gmunu_batch_autotune.argtypes = [_P, _P]
     L.gmunu_batch_init.argtypes = [_P, _P, I, _P]
     L.gmunu_batch_step.argtypes = [_P, D, _P, I, _P]
+    L.gmunu_batch_steps.argtypes = [_P, D, I, _P, _P]
     L.gmunu_batch_times.argtypes = [_P, _P, _P, _P, _P, _P]
     L.gmunu_batch_info.argtypes = [_P, _P, _P]
 
@@ -383,6 +384,11 @@ class Batch:
     def step(self, cfl, nfatal=None, use_graph=True):
         npn = _ptr(nfatal, "nfatal", torch.int32) if nfatal is not None else None
         _check(lib().gmunu_batch_step(self._h, cfl, npn, 1 if use_graph else 0, _stream()), "gmunu_batch_step")
+
+    def steps(self, cfl, nsteps, nfatal=None):
+        """nsteps steps from one captured graph (gmunu_batch_steps)."""
+        npn = _ptr(nfatal, "nfatal", torch.int32) if nfatal is not None else None
+        _check(lib().gmunu_batch_steps(self._h, cfl, int(nsteps), npn, _stream()), "gmunu_batch_steps")
 
     def times(self, with_steps=False):
         """(t, dt) per group; with_steps: (t, dt, steps, fatal recoveries)."""

@@ -931,6 +931,12 @@ int gmunu_batch_step(gmunu_batch *b, double cfl, unsigned int *nfatal_dev, int u
   return batch_step_graph(b, cfl, nfatal_dev, 1, st);
 }
 
+int gmunu_batch_steps(gmunu_batch *b, double cfl, int nsteps, unsigned int *nfatal_dev, void *stream) {
+  if (!b) return GMUNU_ENULL;
+  if (!(cfl > 0.0) || nsteps < 1) return GMUNU_EINVAL;
+  return batch_step_graph(b, cfl, nfatal_dev, nsteps, as_stream(stream));
+}
+
 int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, int *nstep_host, unsigned int *nfatal_host,
                       void *stream) {
   if (!b) return GMUNU_ENULL;

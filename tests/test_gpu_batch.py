@@ -152,6 +152,39 @@ def test_x_ghosts_filled_by_the_recovery_equal_alone():
         assert np.array_equal(pa, pb), f"block {slot} prim differs"
 
 
+def test_multi_step_replay_equals_single_steps():
+    """gmunu_batch_steps (several steps from one graph, the CFL maxima of
+    each later step from the previous step's last recovery) equals the same
+    number of gmunu_batch_step calls bit for bit, with groups that reach
+    their end time or step limit inside the replay."""
+    blocks = mixed_blocks(6, seed=9) + blast_like_blocks()
+    groups = list(range(len(blocks)))
+    outs = []
+    for multi in (False, True):
+        B, views, ar = make_batch(blocks, groups)
+        B.set_group(1, 0.0, 1e30, max_steps=3)
+        B.set_group(2, 0.0, 2e-3)
+        B.commit()
+        if multi:
+            B.steps(0.4, 5)
+            B.steps(0.4, 2)
+        else:
+            for _ in range(7):
+                B.step(0.4)
+        torch.cuda.synchronize()
+        t, dt, ns, _ = B.times(with_steps=True)
+        outs.append((t[:len(blocks)].copy(), ns[:len(blocks)].copy(),
+                     [(v[0].cpu().numpy(), v[1].cpu().numpy()) for v in views]))
+        B.close()
+        del ar
+    (t0, n0, s0), (t1, n1, s1) = outs
+    assert np.array_equal(t0, t1) and np.array_equal(n0, n1)
+    assert n0[1] == 3 and t0[2] == 2e-3
+    for slot, (p, _, _) in enumerate(blocks):
+        assert np.array_equal(W.interior(p, s0[slot][0]), W.interior(p, s1[slot][0])), slot
+        assert np.array_equal(s0[slot][1], s1[slot][1]), slot
+
+
 def test_batch_shared_dt_group_against_oracle():
     # blocks inside the star (density far above the atmosphere floor, where
     # the atmosphere threshold cannot flip between the two implementations)
