@@ -233,10 +233,10 @@ int gmunu_step_static(const gmunu_grid_desc *desc, double *q_n, double *q_s, dou
  * read the item counts from device memory, so a captured step stays valid
  * across commits.  A step is the CFL kernel (maxima per item, then one
  * wavefront per group for its dt and time), and per RK stage the stage
- * kernels, the recovery kernel (which also fills the x-face ghosts of blocks
- * whose 256-cell items are whole x-rows, and the ghosts of 1D lines, when
- * their boundary rules read only the ghost's own row) and the ghost kernel
- * for the rest.  A group whose dt is 0 (t >= t_end, or no time set) is
+ * kernels, the recovery kernel (whose threads also write the x-face ghosts
+ * copied from the cells they recover, when both x faces are periodic,
+ * outflow or reflecting and a row holds at least ng cells) and the ghost
+ * kernel for the rest.  A group whose dt is 0 (t >= t_end, or no time set) is
  * left untouched by a step.  Every block uses its own grid description and
  * arrays exactly as a single-grid context would.
  * ------------------------------------------------------------------------ */

@@ -41,10 +41,8 @@ struct BlockRec {
   int active;
   // ghosts of the x faces (the first xghosts in ghost_one's numbering)
   // filled by the recovery kernel of a step, 0 when the ghost kernel fills
-  // them; xends: by the first and last item of a 1D block rather than row
-  // by row (see recovery_x_ghosts)
+  // them (see recovery_x_ghosts)
   long xghosts;
-  int xends;
   int cfl_start;  // the block's first item in the CFL list (set at commit)
 };
 
@@ -129,11 +127,9 @@ __global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC
 }
 
 // Recovery on 256-cell items: from q_n (use_qn) or q_s.  force: ignore dt.
-// xfill: a block with xghosts > 0 also gets its x-face ghosts once the
-// workgroup has recovered their sources: row by row when its items are
-// whole x-rows (each ghost reads only its own row), or, in 1D (xends), the
-// ghosts whose sources lie in the first item by that item and the others
-// by the last item.  part non-null (the last stage of a step followed by
+// xfill: in a block with xghosts > 0 the thread that recovers a cell also
+// writes the x-face ghosts copied from it (no barrier, no re-read).  part
+// non-null (the last stage of a step followed by
 // another step of the same launch sequence): the item's CFL rate maximum,
 // from the primitives just recovered (nothing changes the interior
 // primitives before the next step), at its place in the CFL list, so that
@@ -150,35 +146,8 @@ __global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, DLi
     if (!force && dts[b.group] == 0.0) continue;  // the same for the whole item
     const long t = (long)(it - L.start[e]) * NT + threadIdx.x;
     if (t < interior_count(b.G))
-      c2p_one(b.G, use_qn ? b.qn : b.qs, b.met, b.prim, b.flags, nfatal, t, gfatal ? gfatal + b.group : nullptr);
-    if (xfill && b.xghosts > 0 && b.xends) {
-      const int ii = it - L.start[e], ni = L.start[e + 1] - L.start[e];
-      if (ii == 0 || ii == ni - 1) {
-        __syncthreads();  // the item's primitives, recovered by other threads
-        const int ng = b.G.g[0];
-        if (threadIdx.x < 2 * ng) {
-          // ghost q: side q / ng; its sources are at the lower end of the
-          // line (first item) for an outflow or reflecting lower face and
-          // a periodic upper face, else at the upper end (last item)
-          const int side = threadIdx.x / ng, bc = b.G.bc[0][side];
-          const bool lower = side == 0 ? bc != BC_PERIODIC : bc == BC_PERIODIC;
-          if (lower ? ii == 0 : ii == ni - 1) ghost_one(b.G, b.prim, threadIdx.x);
-        }
-        __syncthreads();  // before the next item's recovery reuses the threads
-      }
-    } else if (xfill && b.xghosts > 0) {
-      __syncthreads();  // the item's primitives, recovered by other threads
-      const int n0 = b.G.n[0], ng = b.G.g[0];
-      const long rows = interior_count(b.G) / n0, per = NT / n0;
-      const long r0 = (long)(it - L.start[e]) * per;
-      const int nr = (int)(rows - r0 < per ? rows - r0 : per);
-      // ghost_one numbers the x-face ghosts (side, layer, row)
-      for (int q = threadIdx.x; q < 2 * ng * nr; q += NT) {
-        const int sl = q / nr, ro = q - sl * nr;
-        ghost_one(b.G, b.prim, (long)sl * rows + r0 + ro);
-      }
-      __syncthreads();  // before the next item's recovery reuses the threads
-    }
+      c2p_one(b.G, use_qn ? b.qn : b.qs, b.met, b.prim, b.flags, nfatal, t, gfatal ? gfatal + b.group : nullptr,
+              xfill && b.xghosts > 0);
     if (part) {
       const double r = t < interior_count(b.G) ? cfl_one(b.G, b.prim, b.met, t) : 0.0;
       const double m = block_max(r);
@@ -303,29 +272,20 @@ long stage_items(const gmunu_grid_desc &d, int v) {
 
 long cell_items(const gmunu_grid_desc &d) { return ceil_div((long)d.n[0] * d.n[1] * d.n[2], NT); }
 
-// x-face ghosts that the recovery kernel of a step fills (else 0), when the
-// x boundary rules read only cells of the ghost's own row (periodic,
-// outflow, reflect) and (a) every 256-cell item of the block is whole
-// x-rows (n0 divides 256; rows shorter than 16 cells stay with the ghost
-// kernel: an item of 32 rows of 8 spends more on the added barriers than it
-// saves), or (b) the block is 1D and each face's sources lie in its first
-// or its last item (*ends set): outflow reads the end cell, reflect the
-// ng cells at its end, periodic the ng cells at the other end, so the last
-// item must hold the last ng cells when a reflecting upper or a periodic
-// lower face reads them.
-long recovery_x_ghosts(const gmunu_grid_desc &d, int *ends = nullptr) {
-  const int n0 = d.n[0];
-  if (ends) *ends = 0;
+// x-face ghosts that the recovery kernel of a step fills (else 0): every
+// x-face ghost when both x faces are periodic, outflow or reflecting (each
+// ghost a copy of one cell of its own row, sign-flipped for reflection) and
+// the row holds at least ng cells (every source interior).  The recovering
+// thread writes them from its registers, into the cache lines its row's
+// primitives already occupy; a ghost kernel would gather them row by row,
+// one cache line per variable per ghost.
+long recovery_x_ghosts(const gmunu_grid_desc &d) {
   for (int s = 0; s < 2; s++) {
     const int bc = d.bc[0][s];
     if (bc != GMUNU_BC_PERIODIC && bc != GMUNU_BC_OUTFLOW && bc != GMUNU_BC_REFLECT) return 0;
   }
-  if (n0 >= 16 && n0 <= NT && NT % n0 == 0) return 2L * d.ng * ((long)d.n[1] * d.n[2]);
-  if (d.ndim != 1) return 0;
-  const bool tail_read = d.bc[0][1] == GMUNU_BC_REFLECT || d.bc[0][0] == GMUNU_BC_PERIODIC;
-  if (tail_read && n0 % NT != 0 && n0 % NT < d.ng) return 0;
-  if (ends) *ends = 1;
-  return 2L * d.ng;
+  if (d.n[0] < d.ng) return 0;
+  return 2L * d.ng * ((long)d.n[1] * d.n[2]);
 }
 
 long ghost_cells(const gmunu_grid_desc &d) {
@@ -744,7 +704,7 @@ int gmunu_batch_set_block(gmunu_batch *b, int slot, const gmunu_block *blk) {
   r.flags = blk->flags;
   r.group = blk->group;
   r.active = 1;
-  r.xghosts = recovery_x_ghosts(blk->desc, &r.xends);
+  r.xghosts = recovery_x_ghosts(blk->desc);
   b->rec[slot] = r;
   b->blk[slot] = *blk;
   b->used[slot] = 1;

@@ -122,18 +122,42 @@ def _tube(n, bc_lo, bc_hi):
     return p, pr, met
 
 
+def _xbc_block(n, bc_lo, bc_hi, seed=0):
+    """A Cartesian block of extents n with the given x faces (outflow on the
+    other axes) and a smooth state with a non-zero shift."""
+    nd = len(n)
+    lo, hi = [-0.4, -0.3, -0.2], [0.5, 0.6, 0.7]
+    if W.PERIODIC in (bc_lo, bc_hi):
+        bc_lo = bc_hi = W.PERIODIC
+    bc = [[bc_lo, bc_hi]] + [[W.OUTFLOW, W.OUTFLOW]] * (nd - 1)
+    hi = [hi[a] if a < nd else lo[a] + 1.0 for a in range(3)]
+    p = W.grid(nd, W.CART, list(n), lo, hi, bc, gamma=5.0 / 3.0, rk=3, rho_atmo=1e-12, k_atmo=1.0,
+               gamma_atmo=5.0 / 3.0)
+    from test_gpu_parity import smooth_random_state
+
+    pr, met = smooth_random_state(p, seed=seed, beta_amp=0.02)
+    return p, pr, met
+
+
 def test_x_ghosts_filled_by_the_recovery_equal_alone():
-    """Blocks whose x-face ghosts the recovery kernel fills (rows of 16-256
-    cells dividing 256; 1D lines, from their first and last items) and
-    blocks whose ghosts stay with the ghost kernel (a 1D line whose last
-    item holds fewer cells than a reflecting upper face reads, 8-cell rows):
-    outflow, reflecting and periodic x faces, all bitwise equal to the same
-    grid advanced alone after several steps."""
+    """Blocks whose x-face ghosts the recovery kernel writes from the
+    recovered cells (periodic, outflow and reflecting x faces, rows of at
+    least ng cells: 1D lines, and 2D and 3D blocks with rows of 2, 3, 8, 24,
+    255 cells and more), and blocks whose x ghosts stay with the ghost kernel
+    (rows shorter than ng), all bitwise equal to the same grid advanced alone
+    after several steps."""
     blocks = [_tube(300, W.OUTFLOW, W.OUTFLOW), _tube(300, W.REFLECT, W.OUTFLOW), _tube(300, W.OUTFLOW, W.REFLECT),
               _tube(512, W.PERIODIC, W.PERIODIC), _tube(257, W.OUTFLOW, W.REFLECT), _tube(257, W.PERIODIC, W.PERIODIC),
-              _tube(200, W.REFLECT, W.REFLECT), _tube(64, W.OUTFLOW, W.OUTFLOW), _tube(1, W.OUTFLOW, W.OUTFLOW)]
+              _tube(200, W.REFLECT, W.REFLECT), _tube(64, W.OUTFLOW, W.OUTFLOW), _tube(1, W.OUTFLOW, W.OUTFLOW),
+              _tube(2, W.REFLECT, W.REFLECT), _tube(3, W.PERIODIC, W.PERIODIC)]
     p2, pr2, met2 = W.blast_wave_2d(32)
     blocks.append((p2, pr2, met2))
+    for k, (n, lo, hi) in enumerate([((24, 10), W.PERIODIC, W.PERIODIC), ((8, 12), W.REFLECT, W.OUTFLOW),
+                                     ((2, 9), W.REFLECT, W.REFLECT), ((3, 7), W.PERIODIC, W.PERIODIC),
+                                     ((1, 16), W.OUTFLOW, W.OUTFLOW), ((255, 3), W.OUTFLOW, W.REFLECT),
+                                     ((8, 6, 5), W.OUTFLOW, W.REFLECT), ((24, 4, 3), W.PERIODIC, W.PERIODIC),
+                                     ((2, 5, 4), W.REFLECT, W.OUTFLOW), ((1, 4, 4), W.OUTFLOW, W.OUTFLOW)]):
+        blocks.append(_xbc_block(n, lo, hi, seed=k))
     blocks += mixed_blocks(4, seed=5)
     groups = list(range(len(blocks)))
     B, views, _ = make_batch(blocks, groups)
