@@ -442,6 +442,85 @@ def _blocks_single_grid(ps, star, n, steps, cfl, dev):
     return out
 
 
+def bench_block_tiling(n=192, sizes=(32, 16, 8), steps=3, cfl=0.4, seed=0):
+    """The same cells whole and in blocks: the blocks' TOV-profile state on
+    an n^3 Cartesian and an n^3 spherical grid, advanced by gmunu_step, and
+    the same domains cut into m^3 blocks (m in sizes, one group per block)
+    advanced by the batched step.  Every block is a piece of the whole grid
+    with its cells' own states, so the two rates differ only by what the
+    blocks add (ghost layers per block, tile padding, work lists)."""
+    import numpy as np
+    import torch
+
+    import paper_2012_07322_amd as gmu
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    star = W.tov_isotropic(1.28e-3)
+    kw = dict(gamma=2.0, rk=3, rho_atmo=1e-10, k_atmo=100.0, gamma_atmo=2.0, rho_low_factor=100.0, alpha_bh=1e-2)
+    doms = {"cartesian": (W.CART, [-12.8] * 3, [12.8] * 3),
+            "spherical": (W.SPH, [0.5, 0.05, 0.0], [18.0, np.pi - 0.05, 2 * np.pi])}
+    bc = [[W.OUTFLOW, W.OUTFLOW]] * 3
+    sizes = [m for m in sizes if n % m == 0]
+    out = {"n": n, "steps": steps, "unit": "cell-updates/s"}
+    for name, (coord, lo, hi) in doms.items():
+        p = W.grid(3, coord, [n] * 3, lo, hi, bc, **kw)
+        pr, met = W.amr_block_state(p, 0, star, seed=seed)
+        pr = torch.from_numpy(pr).to(dev)
+        met = torch.from_numpy(met).to(dev)
+        g = gmu.Grid(p)
+        g.run(pr, met, cfl, 1e30, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.run(pr, met, cfl, 1e30, steps)
+        torch.cuda.synchronize()
+        whole = 3 * n ** 3 * steps / (time.perf_counter() - t0)
+        g.close()
+        del pr, met
+        res = {"single_grid": whole}
+        h = [(hi[a] - lo[a]) / n for a in range(3)]
+        for m in sizes:
+            nb1 = n // m
+            ps = []
+            for k in range(nb1):
+                for j in range(nb1):
+                    for i in range(nb1):
+                        x0 = [lo[a] + (i, j, k)[a] * m * h[a] for a in range(3)]
+                        x1 = [lo[a] + ((i, j, k)[a] + 1) * m * h[a] for a in range(3)]
+                        ps.append(W.grid(3, coord, [m] * 3, x0, x1, bc, **kw))
+            shapes = [gmu.state_shape(q) for q in ps]
+            ar = gmu.Arena(gmu.Arena.size_of([x for s in shapes for x in [(8,) + s] * 3 + [(5,) + s]]), device=dev)
+            B = gmu.Batch(len(ps), len(ps), 1 << 20)
+            for b, q in enumerate(ps):
+                bpr, bmet = W.amr_block_state(q, b, star, seed=seed)
+                s = shapes[b]
+                qn, qs, prd = (ar.take((8,) + s) for _ in range(3))
+                md = ar.take((5,) + s)
+                prd.copy_(torch.from_numpy(bpr))
+                md.copy_(torch.from_numpy(bmet))
+                qs.zero_()
+                B.set_block(b, q, qn, qs, prd, md, b)
+                B.set_group(b, 0.0, 1e30)
+            B.commit()
+            B.init()
+            B.autotune()
+            B.step(cfl)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                B.step(cfl)
+            torch.cuda.synchronize()
+            rate = 3 * n ** 3 * steps / (time.perf_counter() - t0)
+            B.close()
+            del ar
+            torch.cuda.empty_cache()
+            res[f"{m}^3"] = {"blocks": len(ps), "value": rate, "over_single": rate / whole}
+            log(f"[tiling] {name} {n}^3 as {len(ps)} blocks of {m}^3: {rate:.3e} cell-updates/s, "
+                f"{rate / whole:.3f} of the whole grid ({whole:.3e})")
+        out[name] = res
+    return out
+
+
 def _pct(xs, q):
     import numpy as np
 
@@ -894,6 +973,8 @@ def main():
     ap.add_argument("--block-steps", type=int, default=5)
     ap.add_argument("--block-classes", action="store_true",
                     help="also time the batch on each (size, coordinates) class of blocks alone")
+    ap.add_argument("--block-tiling", type=int, default=0,
+                    help="n: also compare an n^3 grid whole and cut into 32^3, 16^3, 8^3 blocks (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="open-loop requests for the serving measurement (0: skip)")
     ap.add_argument("--serve-probe", type=int, default=300)
@@ -1027,6 +1108,10 @@ def main():
     if args.blocks > 0:
         out["blocks"] = bench_blocks(args.blocks, steps=args.block_steps, cfl=args.cfl, seed=args.seed,
                                      classes=args.block_classes)
+        torch.cuda.empty_cache()
+    if args.block_tiling > 0:
+        out["block_tiling"] = bench_block_tiling(args.block_tiling, steps=args.block_steps, cfl=args.cfl,
+                                                 seed=args.seed)
         torch.cuda.empty_cache()
     if args.mg > 0:
         out["multigrid"] = bench_mg(args.mg)
