@@ -888,7 +888,9 @@ def bench_dynamical(n=256, half=24.0, omega=0.01, steps=100, every=50, eps=1e-3,
     tolerance is 1e-6, and Delta n = 50 as in the paper's typical range.
     The update is the xCFC solve, then the recovery on the new metric and
     the ghost fill.  The steps, the residual checks and the updates are
-    timed separately."""
+    timed separately; then the same evolution from the same state runs
+    through evolve_dynamical (the steps between re-solves in device chunks)
+    and is compared with the first bit for bit."""
     import torch
 
     import paper_2012_07322_amd as gmu
@@ -918,6 +920,7 @@ def bench_dynamical(n=256, half=24.0, omega=0.01, steps=100, every=50, eps=1e-3,
     g.step(q, qs, prd, metd, cfl, 1e30, t, dt, None, nf)
     gmu.psi_residual(g, Mp, q, metd, Mv, X)
     torch.cuda.synchronize()
+    start = [x.clone() for x in (q, qs, prd, metd, X, t, dt, nf)]
     t_step = t_res = t_upd = 0.0
     updates, since = [], 0
     for s in range(1, steps + 1):
@@ -937,6 +940,28 @@ def bench_dynamical(n=256, half=24.0, omega=0.01, steps=100, every=50, eps=1e-3,
             updates.append({"after_step": s, "psi_residual": res, "cycles_X_psi_alphapsi_beta": list(cyc)})
             since = 0
     total = t_step + t_res + t_upd
+    # the same evolution from the same state with the steps between
+    # re-solves in device chunks (evolve_dynamical: the residual of every
+    # step checked on the device, one host synchronisation per chunk)
+    nfatal = int(nf.item())
+    end = [x.clone() for x in (q, prd, metd, X, t)]
+    for x, x0 in zip((q, qs, prd, metd, X, t, dt, nf), start):
+        x.copy_(x0)
+    del start
+    torch.cuda.synchronize()
+    a0 = time.perf_counter()
+    upd_c = gmu.evolve_dynamical(g, q, qs, prd, metd, Mp, Ma, cfl, steps, every=every, eps=eps, mvec=Mv, X=X,
+                                 t_dev=t, dt_dev=dt, nfatal=nf, tol=tol, max_cycles=200)
+    torch.cuda.synchronize()
+    total_c = time.perf_counter() - a0
+    same = all(torch.equal(a, b) for a, b in zip(end, [q, prd, metd, X, t]))
+    del end
+    chunked = {"s_total": total_c, "updates_after_steps": upd_c,
+               "same_updates": upd_c == [u["after_step"] for u in updates], "bitwise_equal": same,
+               "nfatal": int(nf.item()),
+               "cell_updates_per_s_with_metric": n ** 3 * 3 * steps / total_c}
+    log(f"[bench] dynamical metric, device chunks: {total_c:.3f} s against {total:.3f} s per step on the host; "
+        f"updates {upd_c}, bitwise equal {same}")
     out = {"workload": f"uniformly rotating polytropic star (K=100, Gamma=2, rho_c=1.28e-3, omega={omega:g}), "
                        f"Cartesian {n}^3 on [-{half:g},{half:g}]^3, xCFC metric re-solved every {every} steps or when "
                        f"the psi residual exceeds {eps:g} (tolerance {tol:g})",
@@ -944,7 +969,8 @@ def bench_dynamical(n=256, half=24.0, omega=0.01, steps=100, every=50, eps=1e-3,
            "ms_per_residual_check": t_res / steps * 1e3,
            "ms_per_metric_update": t_upd / max(len(updates), 1) * 1e3,
            "metric_share_of_time": (t_res + t_upd) / total,
-           "cell_updates_per_s_with_metric": n ** 3 * 3 * steps / total, "nfatal": int(nf.item())}
+           "cell_updates_per_s_with_metric": n ** 3 * 3 * steps / total, "nfatal": nfatal,
+           "device_chunks": chunked}
     log(f"[bench] dynamical metric: {out['ms_per_step']:.2f} ms/step, residual check "
         f"{out['ms_per_residual_check']:.2f} ms, update {out['ms_per_metric_update']:.1f} ms, metric share "
         f"{out['metric_share_of_time']:.3f}")

@@ -249,6 +249,26 @@ int gmunu_mg_metric_update(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, gmu
                            uint8_t *flags, unsigned int *nfatal_dev, double tol, int max_cycles, int *cycles_out,
                            void *stream);
 
+/* Up to nsteps GRMHD steps on the current metric, as an evolution with a
+ * dynamical metric takes them between re-solves (section 2.6, frequency of
+ * solving the metric): each step is gmunu_step (K_ij from the shift) followed
+ * by the conformal-factor residual of gmunu_mg_psi_residual, both on the
+ * device.  After the first step whose residual exceeds eps the remaining
+ * steps of the call change nothing (their dt is 0; *t_dev is restored at
+ * the end), so the states equal those of the loop that checks the residual
+ * on the host after every step and stops at the first trigger -- with one
+ * host synchronisation per call instead of one per step.  *steps_out: the
+ * steps taken (the trigger step when *triggered_out is 1, else nsteps).
+ * t_end must be finite; t_dev and dt_dev are required.  The caller then
+ * re-solves the metric (gmunu_mg_metric_update) when triggered or when its
+ * step count since the last re-solve is reached.  Synchronous; the step
+ * and residual arguments as for gmunu_step and gmunu_mg_psi_residual. */
+int gmunu_mg_dynamical_steps(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_ctx *ctx, const gmunu_grid_desc *hydro,
+                             double *q_n, double *q_s, double *prim, const double *metric, const double *X,
+                             double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags,
+                             unsigned int *nfatal_dev, int nsteps, double eps, int *steps_out, int *triggered_out,
+                             void *stream);
+
 #ifdef __cplusplus
 }
 #endif

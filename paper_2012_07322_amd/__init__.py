@@ -592,6 +592,8 @@ def _mg_sigs(L):
     L.gmunu_mg_xcfc_solve.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, D, I, _P, _P]
     L.gmunu_mg_metric_update.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, D, I, _P, _P]
     L.gmunu_mg_psi_residual.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P]
+    L.gmunu_mg_dynamical_steps.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, D, D, _P, _P, _P, _P, I, D, _P, _P,
+                                           _P]
 
 
 def make_mg_desc(p: dict) -> MgDesc:
@@ -808,21 +810,44 @@ def psi_residual(grid, mpsi, q, metric, mvec=None, X=None):
     return out.value
 
 
+def dynamical_steps(grid, q_n, q_s, prim, metric, mpsi, cfl, nsteps, eps, t_dev, dt_dev, t_end=1e30, mvec=None,
+                    X=None, flags=None, nfatal=None):
+    """Up to nsteps steps, each followed by the conformal-factor residual on
+    the device; the steps after the first one whose residual exceeds eps
+    change nothing (gmunu_mg_dynamical_steps).  Returns (steps taken,
+    whether the residual triggered)."""
+    fp = _ptr(flags, "flags", torch.uint8) if flags is not None else None
+    npn = _ptr(nfatal, "nfatal", torch.int32) if nfatal is not None else None
+    done, trig = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib().gmunu_mg_dynamical_steps(mvec._h if mvec is not None else None, mpsi._h, grid._h,
+                                          ctypes.byref(grid.desc), grid._chk(q_n, 8, "q_n"), grid._chk(q_s, 8, "q_s"),
+                                          grid._chk(prim, 8, "prim"), grid._chk(metric, 5, "metric"),
+                                          mvec._chk(X, "X", vector=True) if mvec is not None else None, float(cfl),
+                                          float(t_end), _ptr(t_dev, "t"), _ptr(dt_dev, "dt"), fp, npn, int(nsteps),
+                                          float(eps), ctypes.byref(done), ctypes.byref(trig), _stream()),
+           "gmunu_mg_dynamical_steps")
+    return done.value, bool(trig.value)
+
+
 def evolve_dynamical(grid, q_n, q_s, prim, metric, mpsi, malpha, cfl, steps, every=50, eps=1e-3, mvec=None, X=None,
                      t_dev=None, dt_dev=None, flags=None, nfatal=None, tol=1e-6, max_cycles=60):
     """GRMHD steps on a metric re-solved from the evolved matter (section
     2.6): after each step the metric is updated when `every` steps have
     passed since the last update or when the conformal-factor residual
-    exceeds eps.  Returns the step numbers (1-based) after which it was
-    updated."""
+    exceeds eps.  The steps between updates run in chunks on the device
+    (dynamical_steps: one host synchronisation per chunk, the residual of
+    every step checked there).  Returns the step numbers (1-based) after
+    which it was updated."""
     dev = q_n.device
     t_dev = torch.zeros(1, dtype=torch.float64, device=dev) if t_dev is None else t_dev
     dt_dev = torch.zeros(1, dtype=torch.float64, device=dev) if dt_dev is None else dt_dev
-    updates, since = [], 0
-    for s in range(1, steps + 1):
-        grid.step(q_n, q_s, prim, metric, cfl, 1e30, t_dev, dt_dev, flags, nfatal)
-        since += 1
-        if since >= every or psi_residual(grid, mpsi, q_n, metric, mvec, X) > eps:
+    updates, s, since = [], 0, 0
+    while s < steps:
+        done, trig = dynamical_steps(grid, q_n, q_s, prim, metric, mpsi, cfl, min(steps - s, max(every, 1) - since), eps,
+                                     t_dev, dt_dev, mvec=mvec, X=X, flags=flags, nfatal=nfatal)
+        s += done
+        since += done
+        if trig or since >= every:
             metric_update(grid, mpsi, malpha, q_n, prim, metric, mvec, X, flags, nfatal, tol, max_cycles)
             updates.append(s)
             since = 0

@@ -31,6 +31,9 @@ namespace {
 
 constexpr int kMaxLevels = 16;
 constexpr int kNormParts = 16384;
+// after the norm's result: the state of a chunk of dynamical-metric steps
+// (gmunu_mg_dynamical_steps: trigger step, time at that step)
+constexpr int kGateSlots = 2;
 
 // One level as the kernels see it.
 struct MgGeo {
@@ -1771,7 +1774,9 @@ void fmg(gmunu_mg *m, hipStream_t st) {
   }
 }
 
-int norm(gmunu_mg *m, double *out, hipStream_t st) {
+// The finest-level residual norm's kernels: the result lands in
+// part[kNormParts].
+void norm_enqueue(gmunu_mg *m, hipStream_t st) {
   const int top = m->levels - 1;
   const MgGeo &G = m->geo[top];
   const long nb = nblocks(cells(G));
@@ -1779,6 +1784,10 @@ int norm(gmunu_mg *m, double *out, hipStream_t st) {
   hipLaunchKernelGGL(k_mg_norm, dim3(np), dim3(NT), 0, st, G, m->u[top], m->f[top], m->a[top], m->a2[top],
                      m->part);
   hipLaunchKernelGGL(k_mg_norm_finish, dim3(1), dim3(NT), 0, st, m->part, np);
+}
+
+int norm(gmunu_mg *m, double *out, hipStream_t st) {
+  norm_enqueue(m, st);
   if (hipMemcpyAsync(out, m->part + kNormParts, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return GMUNU_EHIP;
@@ -2098,7 +2107,7 @@ int gmunu_mg_create(const gmunu_mg_desc *desc, gmunu_mg **out) {
   m->ev = nullptr;
   for (auto &sl : m->slot) sl = gmunu_mg::Slot{nullptr, false, nullptr, nullptr, nullptr, nullptr};
   m->next_slot = 0;
-  bool ok = (m->tab = alloc(tab.size())) != nullptr && (m->part = alloc(kNormParts + 1)) != nullptr;
+  bool ok = (m->tab = alloc(tab.size())) != nullptr && (m->part = alloc(kNormParts + 1 + kGateSlots)) != nullptr;
   // coarse levels: u, f, a, r (restricted residual) and uo (restricted u);
   // the finest level only uo (the cleaning's divergence when the caller
   // passes none)
@@ -2494,9 +2503,15 @@ int gmunu_mg_xcfc_solve(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, const 
   return launch_status();
 }
 
-int gmunu_mg_psi_residual(gmunu_mg *mvec, gmunu_mg *mpsi, const gmunu_grid_desc *hydro, const double *q,
-                          const double *metric, const double *X, double *norm_out, void *stream) {
-  if (!mpsi || !hydro || !q || !metric || !norm_out || (mvec && !X)) return GMUNU_ENULL;
+}  // extern "C"
+
+namespace {
+
+// The kernels of gmunu_mg_psi_residual: the residual lands in
+// mpsi->part[kNormParts].
+int psi_residual_enqueue(gmunu_mg *mvec, gmunu_mg *mpsi, const gmunu_grid_desc *hydro, const double *q,
+                         const double *metric, const double *X, hipStream_t st) {
+  if (!mpsi || !hydro || !q || !metric || (mvec && !X)) return GMUNU_ENULL;
   if (!aligned8(q) || !aligned8(metric) || (X && !aligned8(X))) return GMUNU_EALIGN;
   Hydro H;
   int rc = hydro_of(mpsi, hydro, H);
@@ -2507,7 +2522,6 @@ int gmunu_mg_psi_residual(gmunu_mg *mvec, gmunu_mg *mpsi, const gmunu_grid_desc 
   if (!bridge_scratch(mpsi)) return GMUNU_ENOMEM;
   if (mvec && !mvec->xs && !alloc_zeroed(mvec, 17 * (size_t)mvec->geo[mvec->levels - 1].nt, &mvec->xs))
     return GMUNU_ENOMEM;
-  hipStream_t st = as_stream(stream);
   const MgGeo &G = mpsi->geo[mpsi->levels - 1];
   double *u = mpsi->br, *a = mpsi->br + G.nt, *f = mpsi->br + 2 * G.nt, *a2 = mpsi->br + 3 * G.nt;
   const double *A2 = nullptr;
@@ -2521,7 +2535,75 @@ int gmunu_mg_psi_residual(gmunu_mg *mvec, gmunu_mg *mpsi, const gmunu_grid_desc 
   // which 0 (the conformal factor) reads no primitives
   hipLaunchKernelGGL(k_br_cfc_coef, dim3(nblocks(cells(G))), dim3(NT), 0, st, G, H, q, nullptr, metric, 0, A2, a, a2,
                      u);
-  return gmunu_mg_residual_norm(mpsi, u, f, a, A2 ? a2 : nullptr, norm_out, stream);
+  const int top = mpsi->levels - 1;
+  mpsi->u[top] = u;
+  mpsi->f[top] = f;
+  mpsi->a[top] = a;
+  mpsi->a2[top] = A2 ? a2 : nullptr;
+  norm_enqueue(mpsi, st);
+  return launch_status();
+}
+
+__global__ void k_dyn_reset(double *g) {
+  g[0] = 0.0;
+  g[1] = 0.0;
+}
+
+// After step `step` of a chunk: the first step whose residual exceeds eps
+// is recorded (g[0]) with the time after it (g[1]), and t becomes +inf, so
+// that every later step of the chunk computes dt = 0 (its cap t_end - t,
+// t_end finite, is negative) and changes nothing.
+__global__ void k_dyn_gate(const double *res, double eps, double step, double *t, double *g) {
+  if (g[0] == 0.0 && *res > eps) {
+    g[0] = step;
+    g[1] = *t;
+    *t = INFINITY;
+  }
+}
+
+__global__ void k_dyn_restore(double *t, const double *g) {
+  if (g[0] != 0.0) *t = g[1];
+}
+
+}  // namespace
+
+extern "C" {
+
+int gmunu_mg_psi_residual(gmunu_mg *mvec, gmunu_mg *mpsi, const gmunu_grid_desc *hydro, const double *q,
+                          const double *metric, const double *X, double *norm_out, void *stream) {
+  if (!norm_out) return GMUNU_ENULL;
+  hipStream_t st = as_stream(stream);
+  const int rc = psi_residual_enqueue(mvec, mpsi, hydro, q, metric, X, st);
+  if (rc) return rc;
+  if (hipMemcpyAsync(norm_out, mpsi->part + kNormParts, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return GMUNU_EHIP;
+  return launch_status();
+}
+
+int gmunu_mg_dynamical_steps(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_ctx *ctx, const gmunu_grid_desc *hydro,
+                             double *q_n, double *q_s, double *prim, const double *metric, const double *X,
+                             double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags,
+                             unsigned int *nfatal_dev, int nsteps, double eps, int *steps_out, int *triggered_out,
+                             void *stream) {
+  if (!ctx || !mpsi || !hydro || !t_dev || !dt_dev || !steps_out || !triggered_out) return GMUNU_ENULL;
+  if (nsteps < 1 || !std::isfinite(t_end)) return GMUNU_EINVAL;
+  hipStream_t st = as_stream(stream);
+  double *g = mpsi->part + kNormParts + 1;
+  hipLaunchKernelGGL(k_dyn_reset, dim3(1), dim3(1), 0, st, g);
+  for (int s = 1; s <= nsteps; s++) {
+    int rc = gmunu_step(ctx, q_n, q_s, prim, metric, nullptr, cfl, t_end, t_dev, dt_dev, flags, nfatal_dev, stream);
+    if (!rc) rc = psi_residual_enqueue(mvec, mpsi, hydro, q_n, metric, X, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_dyn_gate, dim3(1), dim3(1), 0, st, mpsi->part + kNormParts, eps, (double)s, t_dev, g);
+  }
+  hipLaunchKernelGGL(k_dyn_restore, dim3(1), dim3(1), 0, st, t_dev, g);
+  double h[2];
+  if (hipMemcpyAsync(h, g, sizeof h, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+    return GMUNU_EHIP;
+  *triggered_out = h[0] != 0.0;
+  *steps_out = h[0] != 0.0 ? (int)h[0] : nsteps;
+  return launch_status();
 }
 
 int gmunu_mg_metric_update(gmunu_mg *mvec, gmunu_mg *mpsi, gmunu_mg *malpha, gmunu_ctx *ctx,

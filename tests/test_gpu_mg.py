@@ -698,6 +698,65 @@ def test_psi_residual_matches_the_oracle():
     assert abs(rg - ro) <= 1e-12 * ro, (rg, ro)
 
 
+def _per_step_dynamical(g, qd, qs, prd, md, Mp, Ma, steps, every, eps, t, dt, nf):
+    """The evolution loop that checks the residual on the host after every
+    step (the definition the chunked device loop must reproduce)."""
+    updates, since = [], 0
+    for s in range(1, steps + 1):
+        g.step(qd, qs, prd, md, 0.4, 1e30, t, dt, None, nf)
+        since += 1
+        if since >= every or gmu.psi_residual(g, Mp, qd, md) > eps:
+            gmu.metric_update(g, Mp, Ma, qd, prd, md, nfatal=nf, tol=1e-12, max_cycles=300)
+            updates.append(s)
+            since = 0
+    return updates
+
+
+def test_dynamical_chunks_equal_the_per_step_loop():
+    """evolve_dynamical runs the steps between metric re-solves in chunks on
+    the device (gmunu_mg_dynamical_steps: the residual after every step
+    checked there, the steps after a trigger turned into no-ops, one host
+    synchronisation per chunk).  Against the loop that checks the residual
+    on the host after every step: the same update steps, and states, metric,
+    time and fatal count equal bit for bit, for residual-triggered updates,
+    count-triggered ones (every = 7, 1) and both mixed."""
+    hp, pr, met, q, ps, pa = _tov_state(32, 8, vpert=2e-2)
+    r0 = mg.psi_residual(hp, ps, q, met)
+    for eps, every, steps in ((1.05 * r0, 1000, 24), (1e300, 7, 17), (1.2 * r0, 5, 23), (1e300, 1, 3)):
+        outs = []
+        for chunked in (True, False):
+            g = gmu.Grid(hp)
+            Mp, Ma = gmu.Multigrid(ps), gmu.Multigrid(pa)
+            qd, prd, md = dev(q), dev(pr), dev(met)
+            qs = torch.zeros_like(qd)
+            t = torch.zeros(1, dtype=torch.float64, device="cuda")
+            dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+            nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+            if chunked:
+                upd = gmu.evolve_dynamical(g, qd, qs, prd, md, Mp, Ma, 0.4, steps, every=every, eps=eps, t_dev=t,
+                                           dt_dev=dt, nfatal=nf, tol=1e-12, max_cycles=300)
+            else:
+                upd = _per_step_dynamical(g, qd, qs, prd, md, Mp, Ma, steps, every, eps, t, dt, nf)
+            torch.cuda.synchronize()
+            outs.append((upd, host(qd), host(prd), host(md), float(t.item()), int(nf.item())))
+        (u1, q1, p1, m1, t1, n1), (u2, q2, p2, m2, t2, n2) = outs
+        note(f"  eps {eps:.3e} every {every}: updates chunked {u1} per step {u2}, t {t1:.6e}")
+        assert u1 == u2
+        assert t1 == t2 and n1 == n2 == 0
+        assert np.array_equal(q1, q2) and np.array_equal(p1, p2) and np.array_equal(m1, m2)
+    # a chunk reports its trigger step, and leaves the time of that step
+    g = gmu.Grid(hp)
+    Mp = gmu.Multigrid(ps)
+    qd, prd, md = dev(q), dev(pr), dev(met)
+    qs = torch.zeros_like(qd)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    done, trig = gmu.dynamical_steps(g, qd, qs, prd, md, Mp, 0.4, 12, 0.0, t, dt)
+    assert trig and done == 1 and 0.0 < float(t.item()) < 1e30
+    done, trig = gmu.dynamical_steps(g, qd, qs, prd, md, Mp, 0.4, 3, 1e300, t, dt)
+    assert not trig and done == 3
+
+
 def test_adaptive_metric_updates_follow_the_residual():
     """evolve_dynamical on a pulsating TOV star with Delta n = 1000 and a
     residual threshold: the metric is re-solved exactly after the steps at
