@@ -4,9 +4,12 @@ Workload: the 3D relativistic magnetised blast wave at 256^3 (FP64, SSPRK3,
 MC + HLLE, CFL 0.4), inputs resident in HBM before the timed region.  One
 "step" is the whole hot path: CFL time step + three RK stages, each stage
 = stage kernel (reconstruction, fluxes, sources, RK combine) + primitive
-recovery + ghost fill.
+recovery + ghost fill.  The timed steps are one gmunu_steps call (the CFL
+maxima of each step after the first come from the previous step's last
+recovery).
 
-Prints one JSON line (see the design doc for the roofline figures' derivation).
+Prints one JSON line; the roofline object prices the stage kernel's
+algorithmic bytes (ALG_BYTES) against the HBM peak.
 """
 import argparse
 import json
@@ -1056,8 +1059,8 @@ def main():
     nf = torch.zeros(1, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} steps")
-    for _ in range(args.warmup):
-        g.step(qn, qs, prim, metric, args.cfl, 1e30, t, dt, None, nf)
+    if args.warmup > 0:
+        g.steps(qn, qs, prim, metric, args.cfl, 1e30, t, dt, args.warmup, None, nf)
     torch.cuda.synchronize()
     g.profile(True, max_launches=16 * args.steps + 64)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -1065,8 +1068,7 @@ def main():
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     e0.record()
-    for _ in range(args.steps):
-        g.step(qn, qs, prim, metric, args.cfl, 1e30, t, dt, None, nf)
+    g.steps(qn, qs, prim, metric, args.cfl, 1e30, t, dt, args.steps, None, nf)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0

@@ -202,6 +202,17 @@ int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const dou
                double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
                void *stream);
 
+/* nsteps calls of gmunu_step with the same arguments, with the same result
+ * bit for bit, in fewer launches: the last recovery of each step but the last
+ * also writes the CFL maxima of the primitives it has just recovered (which
+ * nothing changes before the next step's dt, section 2.9), so only the first
+ * step launches the CFL kernel.  Time and dt stay on the device as in
+ * gmunu_step (the call is capturable like it).  nsteps >= 1 (GMUNU_EINVAL
+ * otherwise). */
+int gmunu_steps(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, const double *kij,
+                double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
+                int nsteps, void *stream);
+
 /* One step as gmunu_step, without a context and without allocating: for
  * callers that cannot allocate device memory (code under HIP graph capture,
  * serving loops, harnesses that forbid hipMalloc).  The grid's geometry

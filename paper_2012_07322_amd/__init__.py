@@ -68,6 +68,7 @@ def lib():
         L.gmunu_cfl_dt.argtypes = [_P, _P, _P, D, D, _P, _P, _P]
         L.gmunu_rk_stage.argtypes = [_P, I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
         L.gmunu_step.argtypes = [_P, _P, _P, _P, _P, _P, D, D, _P, _P, _P, _P, _P]
+        L.gmunu_steps.argtypes = [_P, _P, _P, _P, _P, _P, D, D, _P, _P, _P, _P, I, _P]
         L.gmunu_step_static.argtypes = [_P, _P, _P, _P, _P, _P, D, D, _P, _P, _P, _P, _P]
         L.gmunu_profile.argtypes = [_P, I, I]
         L.gmunu_profile_read.argtypes = [_P, _P, _P]
@@ -210,10 +211,19 @@ class Grid:
                                 self._chk(prim, 8, "prim"), self._chk(metric, 5, "metric"), self._chk(kij, 6, "kij"),
                                 cfl, t_end, _ptr(t_dev, "t"), _ptr(dt_dev, "dt"), fp, npn, _stream()), "gmunu_step")
 
+    def steps(self, q_n, q_s, prim, metric, cfl, t_end, t_dev, dt_dev, nsteps, flags=None, nfatal=None, kij=None):
+        """nsteps gmunu_step calls in one (gmunu_steps: the CFL kernel only in
+        the first step)."""
+        fp = _ptr(flags, "flags", torch.uint8) if flags is not None else None
+        npn = _ptr(nfatal, "nfatal", torch.int32) if nfatal is not None else None
+        _check(lib().gmunu_steps(self._h, self._chk(q_n, 8, "q_n"), self._chk(q_s, 8, "q_s"),
+                                 self._chk(prim, 8, "prim"), self._chk(metric, 5, "metric"), self._chk(kij, 6, "kij"),
+                                 cfl, t_end, _ptr(t_dev, "t"), _ptr(dt_dev, "dt"), fp, npn, int(nsteps), _stream()),
+               "gmunu_steps")
 
     def run(self, prim, metric, cfl, t_end=1e30, max_steps=0, check_every=16):
-        """Advance one solve on its own (one launch sequence per step):
-        ghosts of prim filled, q_n from prim, prim recovered, then gmunu_step
+        """Advance one solve on its own: ghosts of prim filled, q_n from
+        prim, prim recovered, then gmunu_steps in runs of `check_every` steps
         until t reaches t_end or max_steps steps were taken (steps past t_end
         change nothing, so t is checked every `check_every` steps).  prim is
         updated in place; returns (q_n, q_s, t)."""
@@ -234,8 +244,7 @@ class Grid:
             k = max_steps - done if max_steps > 0 else check_every
             if max_steps > 0 and t_end < 1e300:
                 k = min(k, check_every)
-            for _ in range(k):
-                _check(L.gmunu_step(*args, cfl, t_end, tp, dtp, None, None, st), "gmunu_step")
+            _check(L.gmunu_steps(*args, cfl, t_end, tp, dtp, None, None, k, st), "gmunu_steps")
             done += k
             if max_steps > 0 and done >= max_steps:
                 break

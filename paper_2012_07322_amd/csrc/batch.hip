@@ -272,22 +272,6 @@ long stage_items(const gmunu_grid_desc &d, int v) {
 
 long cell_items(const gmunu_grid_desc &d) { return ceil_div((long)d.n[0] * d.n[1] * d.n[2], NT); }
 
-// x-face ghosts that the recovery kernel of a step fills (else 0): every
-// x-face ghost when both x faces are periodic, outflow or reflecting (each
-// ghost a copy of one cell of its own row, sign-flipped for reflection) and
-// the row holds at least ng cells (every source interior).  The recovering
-// thread writes them from its registers, into the cache lines its row's
-// primitives already occupy; a ghost kernel would gather them row by row,
-// one cache line per variable per ghost.
-long recovery_x_ghosts(const gmunu_grid_desc &d) {
-  for (int s = 0; s < 2; s++) {
-    const int bc = d.bc[0][s];
-    if (bc != GMUNU_BC_PERIODIC && bc != GMUNU_BC_OUTFLOW && bc != GMUNU_BC_REFLECT) return 0;
-  }
-  if (d.n[0] < d.ng) return 0;
-  return 2L * d.ng * ((long)d.n[1] * d.n[2]);
-}
-
 long ghost_cells(const gmunu_grid_desc &d) {
   const long nin = (long)d.n[0] * d.n[1] * d.n[2];
   long tot = 0;

@@ -36,6 +36,8 @@ struct gmunu_ctx {
   int device;
   double *geo;                 // packed 1D geometry tables (device)
   double *acc;                 // CFL partial maxima (device, kCflParts words)
+  double *c2pmax;              // CFL maxima per recovery workgroup (gmunu_steps; null in gmunu_step_static)
+  long xghosts;                // x-face ghosts the recovery of a step writes (recovery_x_ghosts)
   double *qt;                  // limiter only: third conserved state for the middle SSPRK3 stage
   // launch timing (measurement only)
   int prof;
@@ -95,11 +97,22 @@ __global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC
                                             kij, fc);
 }
 
+// Recovery of one interior cell per thread.  xg: also write the x-face
+// ghosts copied from the recovered cells.  part (nullable): the
+// workgroup's maximum CFL rate of the primitives just recovered, at
+// part[blockIdx.x] (the next step's CFL maxima, when nothing changes the
+// interior primitives before it).
 __global__ __launch_bounds__(NT) void k_c2p(const Grid G, double *q, const double *__restrict__ met, double *prim,
-                                            uint8_t *flags, unsigned int *nfatal, const double *__restrict__ skipp) {
+                                            uint8_t *flags, unsigned int *nfatal, const double *__restrict__ skipp,
+                                            int xg, double *part) {
   if (skipp && *skipp == 0.0) return;
   const long t = (long)blockIdx.x * NT + threadIdx.x;
-  if (t < interior_count(G)) c2p_one(G, q, met, prim, flags, nfatal, t);
+  const bool in = t < interior_count(G);
+  if (in) c2p_one(G, q, met, prim, flags, nfatal, t, nullptr, xg != 0);
+  if (part) {
+    const double m = block_max(in ? cfl_one(G, prim, met, t) : 0.0);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+  }
 }
 
 __global__ __launch_bounds__(NT) void k_prim2con(const Grid G, const double *__restrict__ prim,
@@ -108,10 +121,12 @@ __global__ __launch_bounds__(NT) void k_prim2con(const Grid G, const double *__r
   if (c < G.nv) prim2con_one(G, prim, met, q, c);
 }
 
+// Ghost fill, one ghost per thread, from ghost number `skip` on (the x-face
+// ghosts come first; the recovery may have written them).
 __global__ __launch_bounds__(NT) void k_ghosts(const Grid G, double *prim, long total,
-                                               const double *__restrict__ skipp) {
+                                               const double *__restrict__ skipp, long skip) {
   if (skipp && *skipp == 0.0) return;
-  const long t = (long)blockIdx.x * NT + threadIdx.x;
+  const long t = (long)blockIdx.x * NT + threadIdx.x + skip;
   if (t < total) ghost_one(G, prim, t);
 }
 
@@ -128,10 +143,21 @@ __global__ __launch_bounds__(NT) void k_cfl(const Grid G, const double *__restri
 }
 
 // dt = cfl / max(part), capped at t_end - t.
+// Eight independent maxima per thread keep eight loads in flight (the
+// partials of gmunu_steps are one per recovery workgroup: 65536 at 256^3);
+// the maximum does not depend on the order.
 __global__ __launch_bounds__(NT) void k_cfl_finish(const double *part, int nparts, double cfl, double t_end,
                                                    const double *tp, double *dtp) {
+  double mu[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int b = threadIdx.x;
+  for (; b + 7 * NT < nparts; b += 8 * NT) {
+#pragma unroll
+    for (int u = 0; u < 8; u++) mu[u] = fmax(mu[u], part[b + u * NT]);
+  }
+  for (; b < nparts; b += NT) mu[0] = fmax(mu[0], part[b]);
   double m = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += NT) m = fmax(m, part[b]);
+#pragma unroll
+  for (int u = 0; u < 8; u++) m = fmax(m, mu[u]);
   m = block_max(m);
   if (threadIdx.x == 0) *dtp = dt_from_rate(m, cfl, tp ? *tp : 0.0, t_end);
 }
@@ -182,25 +208,28 @@ void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, c
 }
 
 int launch_c2p(gmunu_ctx *ctx, double *q, const double *metric, double *prim, uint8_t *flags,
-               unsigned int *nfatal_dev, const double *skipp, hipStream_t st) {
+               unsigned int *nfatal_dev, const double *skipp, hipStream_t st, int xg = 0, double *part = nullptr) {
   ProfScope ps(ctx, st, GMUNU_K_C2P);
   hipLaunchKernelGGL(k_c2p, dim3(nblocks(interior_cells(ctx->G))), dim3(NT), 0, st, ctx->G, q, metric, prim, flags,
-                     nfatal_dev, skipp);
+                     nfatal_dev, skipp, xg, part);
   return launch_status();
 }
 
-int launch_ghosts(gmunu_ctx *ctx, double *prim, const double *skipp, hipStream_t st) {
+int launch_ghosts(gmunu_ctx *ctx, double *prim, const double *skipp, hipStream_t st, long skip = 0) {
   const long tot = ghost_total(ctx->G);
-  if (tot == 0) return GMUNU_OK;
+  if (tot - skip <= 0) return GMUNU_OK;
   ProfScope ps(ctx, st, GMUNU_K_GHOSTS);
-  hipLaunchKernelGGL(k_ghosts, dim3(nblocks(tot)), dim3(NT), 0, st, ctx->G, prim, tot, skipp);
+  hipLaunchKernelGGL(k_ghosts, dim3(nblocks(tot - skip)), dim3(NT), 0, st, ctx->G, prim, tot, skipp, skip);
   return launch_status();
 }
 
 // One RK stage; with skipp non-null nothing is changed when *skipp == 0.
+// part (nullable, separate recovery only): the recovery also writes the
+// next step's CFL maxima there (k_c2p).
 int rk_stage_impl(gmunu_ctx *ctx, int stage, const double *dt_dev, const double *q_n, const double *q_s,
                   double *q_out, const double *prim_in, double *prim_out, const double *metric, const double *kij,
-                  uint8_t *flags, unsigned int *nfatal_dev, const double *skipp, hipStream_t st) {
+                  uint8_t *flags, unsigned int *nfatal_dev, const double *skipp, hipStream_t st,
+                  double *part = nullptr) {
   const int nst = ctx->d.rk;
   double ca = 0.0, cb = 1.0;
   if (stage > 0) {
@@ -229,16 +258,15 @@ int rk_stage_impl(gmunu_ctx *ctx, int stage, const double *dt_dev, const double 
   }
   int rc = launch_status();
   if (rc) return rc;
-  if (!fuse) {
-    rc = launch_c2p(ctx, q_out, metric, prim_out, flags, nfatal_dev, skipp, st);
-    if (rc) return rc;
-  }
-  return launch_ghosts(ctx, prim_out, skipp, st);
+  if (fuse) return launch_ghosts(ctx, prim_out, skipp, st);
+  rc = launch_c2p(ctx, q_out, metric, prim_out, flags, nfatal_dev, skipp, st, ctx->xghosts > 0, part);
+  if (rc) return rc;
+  return launch_ghosts(ctx, prim_out, skipp, st, ctx->xghosts);
 }
 
 int step_impl(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, const double *kij,
               double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
-              void *stream);
+              void *stream, bool cfl_from_part = false, double *part_out = nullptr);
 
 }  // namespace
 
@@ -255,6 +283,8 @@ int gmunu_create(const gmunu_grid_desc *desc, gmunu_ctx **out) {
   ctx->d = *desc;
   ctx->prof = 0;
   ctx->nrec = 0;
+  ctx->c2pmax = nullptr;
+  ctx->xghosts = recovery_x_ghosts(*desc);
   if (hipGetDevice(&ctx->device) != hipSuccess) {
     delete ctx;
     return GMUNU_EHIP;
@@ -270,6 +300,12 @@ int gmunu_create(const gmunu_grid_desc *desc, gmunu_ctx **out) {
     delete ctx;
     return GMUNU_ENOMEM;
   }
+  if (hipMalloc(&ctx->c2pmax, nblocks(interior_cells(ctx->G)) * sizeof(double)) != hipSuccess) {
+    (void)hipFree(ctx->geo);
+    (void)hipFree(ctx->acc);
+    delete ctx;
+    return GMUNU_ENOMEM;
+  }
   // with the limiter a stage reads the base state of neighbouring cells, so
   // its output may not overwrite its base: the step needs a third state
   ctx->qt = nullptr;
@@ -277,6 +313,7 @@ int gmunu_create(const gmunu_grid_desc *desc, gmunu_ctx **out) {
       hipMalloc(&ctx->qt, (size_t)NV * ctx->G.nv * sizeof(double)) != hipSuccess) {
     (void)hipFree(ctx->geo);
     (void)hipFree(ctx->acc);
+    (void)hipFree(ctx->c2pmax);
     delete ctx;
     return GMUNU_ENOMEM;
   }
@@ -284,6 +321,7 @@ int gmunu_create(const gmunu_grid_desc *desc, gmunu_ctx **out) {
       hipMemset(ctx->acc, 0, kCflParts * sizeof(double)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(ctx->geo);
     (void)hipFree(ctx->acc);
+    (void)hipFree(ctx->c2pmax);
     if (ctx->qt) (void)hipFree(ctx->qt);
     delete ctx;
     return GMUNU_EHIP;
@@ -299,6 +337,7 @@ int gmunu_destroy(gmunu_ctx *ctx) {
   for (auto e : ctx->ev) (void)hipEventDestroy(e);
   if (hipFree(ctx->geo) != hipSuccess) rc = GMUNU_EHIP;
   if (hipFree(ctx->acc) != hipSuccess) rc = GMUNU_EHIP;
+  if (hipFree(ctx->c2pmax) != hipSuccess) rc = GMUNU_EHIP;
   if (ctx->qt && hipFree(ctx->qt) != hipSuccess) rc = GMUNU_EHIP;
   delete ctx;
   return rc;
@@ -376,16 +415,42 @@ int gmunu_step(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const dou
   return step_impl(ctx, q_n, q_s, prim, metric, kij, cfl, t_end, t_dev, dt_dev, flags, nfatal_dev, stream);
 }
 
+int gmunu_steps(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, const double *kij,
+                double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
+                int nsteps, void *stream) {
+  if (!ctx || !q_n || !q_s || !prim || !metric || !t_dev || !dt_dev) return GMUNU_ENULL;
+  if (!aligned8(kij)) return GMUNU_EALIGN;
+  if (nsteps < 1) return GMUNU_EINVAL;
+  for (int k = 0; k < nsteps; k++) {
+    const int rc = step_impl(ctx, q_n, q_s, prim, metric, kij, cfl, t_end, t_dev, dt_dev, flags, nfatal_dev, stream,
+                             k > 0, k + 1 < nsteps ? ctx->c2pmax : nullptr);
+    if (rc) return rc;
+  }
+  return GMUNU_OK;
+}
+
 }  // extern "C"
 
 namespace {
 
 // The launches of one step (gmunu_step), on a context whose geometry tables
-// and CFL partials are in place.
+// and CFL partials are in place.  cfl_from_part: the CFL maxima are those
+// the previous step's last recovery wrote to ctx->c2pmax (no CFL kernel);
+// part_out (nullable): this step's last recovery writes the next step's
+// maxima there.
 int step_impl(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, const double *kij,
               double cfl, double t_end, double *t_dev, double *dt_dev, uint8_t *flags, unsigned int *nfatal_dev,
-              void *stream) {
-  int rc = gmunu_cfl_dt(ctx, prim, metric, cfl, t_end, t_dev, dt_dev, stream);
+              void *stream, bool cfl_from_part, double *part_out) {
+  int rc;
+  if (cfl_from_part) {
+    if (!(cfl > 0.0)) return GMUNU_EINVAL;
+    ProfScope ps(ctx, as_stream(stream), GMUNU_K_OTHER);
+    hipLaunchKernelGGL(k_cfl_finish, dim3(1), dim3(NT), 0, as_stream(stream), ctx->c2pmax,
+                       (int)nblocks(interior_cells(ctx->G)), cfl, t_end, t_dev, dt_dev);
+    rc = launch_status();
+  } else {
+    rc = gmunu_cfl_dt(ctx, prim, metric, cfl, t_end, t_dev, dt_dev, stream);
+  }
   if (rc) return rc;
   const int nst = ctx->d.rk;
   // stage s reads base[s] and writes base[s + 1] (q_n last); without the
@@ -396,7 +461,7 @@ int step_impl(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const doub
   if (nst == 3 && ctx->qt) base[2] = ctx->qt;
   for (int s = 0; s < nst; s++) {
     rc = rk_stage_impl(ctx, s, dt_dev, q_n, base[s], base[s + 1], prim, prim, metric, kij, flags, nfatal_dev,
-                       dt_dev, as_stream(stream));
+                       dt_dev, as_stream(stream), s == nst - 1 ? part_out : nullptr);
     if (rc) return rc;
   }
   {
@@ -572,6 +637,8 @@ int gmunu_step_static(const gmunu_grid_desc *desc, double *q_n, double *q_s, dou
   ctx.prof = 0;
   ctx.nrec = 0;
   ctx.qt = nullptr;
+  ctx.c2pmax = nullptr;
+  ctx.xghosts = recovery_x_ghosts(*desc);
   grid_scalars(*desc, ctx.G);
   for (int a = 0; a < 3; a++)
     if (ctx.G.nt[a] > kStaticAxis) return GMUNU_EINVAL;  // beyond the scratch's tables
