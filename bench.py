@@ -238,7 +238,7 @@ def bench_fused(n=256, steps=10, cfl=0.4, seed=0):
     return res
 
 
-def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True, single_n=192, classes=False):
+def bench_blocks(nblocks=3000, steps=5, cfl=0.4, seed=0, tune=True, single_n=192, classes=False):
     """Many AMR-style blocks (8^3, 16^3, 32^3 interiors, spherical and
     Cartesian, TOV-profile magnetised states), each its own simulation with
     its own time step, advanced (a) by the batched graph-captured step and
@@ -287,13 +287,15 @@ def bench_blocks(nblocks=3000, steps=5, warmup=1, cfl=0.4, seed=0, tune=True, si
         torch.cuda.synchronize()
         tune_s = time.perf_counter() - t0
     items, var = B.info()
-    for _ in range(warmup):
-        B.step(cfl)
+    # the timed steps are one replay of a graph of `steps` steps
+    # (gmunu_batch_steps: the CFL kernel in the first only); the warm-up
+    # takes as many steps and captures that graph
+    warmup = steps
+    B.steps(cfl, steps)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(steps):
-        B.step(cfl)
+    B.steps(cfl, steps)
     e1.record()
     torch.cuda.synchronize()
     ms_b = e0.elapsed_time(e1)
@@ -390,11 +392,10 @@ def _blocks_by_class(ps, views, steps, cfl, tune):
             B.init()
             if tune:
                 B.autotune()
-            B.step(cfl)
+            B.steps(cfl, steps)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for _ in range(steps):
-                B.step(cfl)
+            B.steps(cfl, steps)
             torch.cuda.synchronize()
             sec = (time.perf_counter() - t0) / steps
             B.close()
@@ -402,6 +403,21 @@ def _blocks_by_class(ps, views, steps, cfl, tune):
             out[f"{n}^3 {cname}"] = {"blocks": len(idx), "ms_per_step": sec * 1e3, "value": 3 * cells / sec}
             log(f"[blocks]   {n}^3 {cname}: {len(idx)} blocks, {3 * cells / sec:.3e} cell-updates/s")
     return out
+
+
+def _time_single_grid(g, pr, met, cfl, steps):
+    """Seconds for `steps` steps of one grid as one gmunu_steps call, after
+    a warm-up run (initialisation and as many steps) outside the timing."""
+    import torch
+
+    qn, qs, _ = g.run(pr, met, cfl, 1e30, steps)
+    t = torch.zeros(1, dtype=torch.float64, device=pr.device)
+    dt = torch.zeros_like(t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.steps(qn, qs, pr, met, cfl, 1e30, t, dt, steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
 
 
 def _blocks_single_grid(ps, star, n, steps, cfl, dev):
@@ -428,12 +444,7 @@ def _blocks_single_grid(ps, star, n, steps, cfl, dev):
         pr = torch.from_numpy(pr).to(dev)
         met = torch.from_numpy(met).to(dev)
         g = gmu.Grid(p)
-        g.run(pr, met, cfl, 1e30, 1)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g.run(pr, met, cfl, 1e30, steps)
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t0
+        sec = _time_single_grid(g, pr, met, cfl, steps)
         g.close()
         out[name] = n ** 3 * 3 * steps / sec
     cells = {"cartesian": 0, "spherical": 0}
@@ -472,12 +483,7 @@ def bench_block_tiling(n=192, sizes=(32, 16, 8), steps=3, cfl=0.4, seed=0):
         pr = torch.from_numpy(pr).to(dev)
         met = torch.from_numpy(met).to(dev)
         g = gmu.Grid(p)
-        g.run(pr, met, cfl, 1e30, 1)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g.run(pr, met, cfl, 1e30, steps)
-        torch.cuda.synchronize()
-        whole = 3 * n ** 3 * steps / (time.perf_counter() - t0)
+        whole = 3 * n ** 3 * steps / _time_single_grid(g, pr, met, cfl, steps)
         g.close()
         del pr, met
         res = {"single_grid": whole}
@@ -507,11 +513,10 @@ def bench_block_tiling(n=192, sizes=(32, 16, 8), steps=3, cfl=0.4, seed=0):
             B.commit()
             B.init()
             B.autotune()
-            B.step(cfl)
+            B.steps(cfl, steps)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for _ in range(steps):
-                B.step(cfl)
+            B.steps(cfl, steps)
             torch.cuda.synchronize()
             rate = 3 * n ** 3 * steps / (time.perf_counter() - t0)
             B.close()
