@@ -244,10 +244,11 @@ int gmunu_step_static(const gmunu_grid_desc *desc, double *q_n, double *q_s, dou
  * read the item counts from device memory, so a captured step stays valid
  * across commits.  A step is the CFL kernel (maxima per item, then one
  * wavefront per group for its dt and time), and per RK stage the stage
- * kernels, the recovery kernel (whose threads also write the x-face ghosts
- * copied from the cells they recover, when both x faces are periodic,
- * outflow or reflecting and a row holds at least ng cells) and the ghost
- * kernel for the rest.  A group whose dt is 0 (t >= t_end, or no time set) is
+ * kernels, the recovery kernel (whose threads also write the face ghosts
+ * copied from the cells they recover, on the leading axes -- x, x and y, or
+ * all three -- whose faces are periodic, outflow or reflecting and that hold
+ * at least ng cells) and the ghost kernel for the rest (none when the
+ * recovery writes every ghost).  A group whose dt is 0 (t >= t_end, or no time set) is
  * left untouched by a step.  Every block uses its own grid description and
  * arrays exactly as a single-grid context would.
  * ------------------------------------------------------------------------ */
@@ -309,7 +310,7 @@ int gmunu_batch_steps(gmunu_batch *b, double cfl, int nsteps, unsigned int *nfat
 int gmunu_batch_times(gmunu_batch *b, double *t_host, double *dt_host, int *nstep_host, unsigned int *nfatal_host,
                       void *stream);
 /* Number of committed items per list: [stage, c2p, ghosts] (ghosts of a
- * step: the x-face ghosts that the recovery kernel fills are not counted);
+ * step: the ghosts that the recovery kernel writes are not counted);
  * tile variant chosen per block (out_variant[slot], -1 for empty slots). */
 int gmunu_batch_info(gmunu_batch *b, long *items_out, int *out_variant);
 

@@ -39,10 +39,11 @@ struct BlockRec {
   uint8_t *flags;
   int group;
   int active;
-  // ghosts of the x faces (the first xghosts in ghost_one's numbering)
-  // filled by the recovery kernel of a step, 0 when the ghost kernel fills
-  // them (see recovery_x_ghosts)
-  long xghosts;
+  // face ghosts of the first raxes axes (the first rghosts in ghost_one's
+  // numbering) written by the recovery kernel of a step; the ghost kernel
+  // fills the rest (recovery_ghosts)
+  long rghosts;
+  int raxes;
   int cfl_start;  // the block's first item in the CFL list (set at commit)
 };
 
@@ -127,8 +128,8 @@ __global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC
 }
 
 // Recovery on 256-cell items: from q_n (use_qn) or q_s.  force: ignore dt.
-// xfill: in a block with xghosts > 0 the thread that recovers a cell also
-// writes the x-face ghosts copied from it (no barrier, no re-read).  part
+// gfill: the thread that recovers a cell also writes the face ghosts of the
+// block's first raxes axes copied from it (no barrier, no re-read).  part
 // non-null (the last stage of a step followed by
 // another step of the same launch sequence): the item's CFL rate maximum,
 // from the primitives just recovered (nothing changes the interior
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC
 // the next step needs no CFL kernel.  Items skipped for dt = 0 write none:
 // their group's dt stays 0 in the next step whatever its maxima.
 __global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, DList L, const double *dts, int use_qn,
-                                             int force, unsigned int *nfatal, unsigned int *gfatal, int xfill,
+                                             int force, unsigned int *nfatal, unsigned int *gfatal, int gfill,
                                              double *part) {
   const int nent = L.meta[0], n = L.meta[1];
   int e = -1;
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, DLi
     const long t = (long)(it - L.start[e]) * NT + threadIdx.x;
     if (t < interior_count(b.G))
       c2p_one(b.G, use_qn ? b.qn : b.qs, b.met, b.prim, b.flags, nfatal, t, gfatal ? gfatal + b.group : nullptr,
-              xfill && b.xghosts > 0);
+              gfill ? b.raxes : 0);
     if (part) {
       const double r = t < interior_count(b.G) ? cfl_one(b.G, b.prim, b.met, t) : 0.0;
       const double m = block_max(r);
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(NT) void k_bprim2con(const BlockRec *__restrict__ B
 }
 
 // Ghost fill on 256-ghost items.  force: ignore dt, and fill every ghost
-// (an init); otherwise a block's first xghosts ghosts (filled by the
+// (an init); otherwise a block's first rghosts ghosts (filled by the
 // recovery kernel) are skipped.
 __global__ __launch_bounds__(NT) void k_bghosts(const BlockRec *__restrict__ B, DList L, const double *dts,
                                                 int force) {
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(NT) void k_bghosts(const BlockRec *__restrict__ B, 
     e = find_entry(L.start, nent, it, e);
     const BlockRec &b = B[L.blk[e]];
     if (!force && dts[b.group] == 0.0) continue;
-    const long t = (long)(it - L.start[e]) * NT + threadIdx.x + (force ? 0 : b.xghosts);
+    const long t = (long)(it - L.start[e]) * NT + threadIdx.x + (force ? 0 : b.rghosts);
     if (t < ghost_count(b.G)) ghost_one(b.G, b.prim, t);
   }
 }
@@ -280,7 +281,10 @@ long ghost_cells(const gmunu_grid_desc &d) {
 }
 
 // Items of the ghost list of a step (init: all ghosts).
-long ghost_items(const gmunu_grid_desc &d) { return ceil_div(ghost_cells(d) - recovery_x_ghosts(d), NT); }
+long ghost_items(const gmunu_grid_desc &d) {
+  int axes;
+  return ceil_div(ghost_cells(d) - recovery_ghosts(d, &axes), NT);
+}
 long ghost_items_all(const gmunu_grid_desc &d) { return ceil_div(ghost_cells(d), NT); }
 
 // Host copy of one list's entry table.
@@ -688,7 +692,7 @@ int gmunu_batch_set_block(gmunu_batch *b, int slot, const gmunu_block *blk) {
   r.flags = blk->flags;
   r.group = blk->group;
   r.active = 1;
-  r.xghosts = recovery_x_ghosts(blk->desc);
+  r.rghosts = recovery_ghosts(blk->desc, &r.raxes);
   b->rec[slot] = r;
   b->blk[slot] = *blk;
   b->used[slot] = 1;

@@ -37,7 +37,8 @@ struct gmunu_ctx {
   double *geo;                 // packed 1D geometry tables (device)
   double *acc;                 // CFL partial maxima (device, kCflParts words)
   double *c2pmax;              // CFL maxima per recovery workgroup (gmunu_steps; null in gmunu_step_static)
-  long xghosts;                // x-face ghosts the recovery of a step writes (recovery_x_ghosts)
+  long rghosts;                // face ghosts the recovery of a step writes (recovery_ghosts)
+  int raxes;                   // on that many leading axes
   double *qt;                  // limiter only: third conserved state for the middle SSPRK3 stage
   // launch timing (measurement only)
   int prof;
@@ -97,18 +98,19 @@ __global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC
                                             kij, fc);
 }
 
-// Recovery of one interior cell per thread.  xg: also write the x-face
-// ghosts copied from the recovered cells.  part (nullable): the
+// Recovery of one interior cell per thread.  gaxes: also write the face
+// ghosts of the first gaxes axes copied from the recovered cells.  part
+// (nullable): the
 // workgroup's maximum CFL rate of the primitives just recovered, at
 // part[blockIdx.x] (the next step's CFL maxima, when nothing changes the
 // interior primitives before it).
 __global__ __launch_bounds__(NT) void k_c2p(const Grid G, double *q, const double *__restrict__ met, double *prim,
                                             uint8_t *flags, unsigned int *nfatal, const double *__restrict__ skipp,
-                                            int xg, double *part) {
+                                            int gaxes, double *part) {
   if (skipp && *skipp == 0.0) return;
   const long t = (long)blockIdx.x * NT + threadIdx.x;
   const bool in = t < interior_count(G);
-  if (in) c2p_one(G, q, met, prim, flags, nfatal, t, nullptr, xg != 0);
+  if (in) c2p_one(G, q, met, prim, flags, nfatal, t, nullptr, gaxes);
   if (part) {
     const double m = block_max(in ? cfl_one(G, prim, met, t) : 0.0);
     if (threadIdx.x == 0) part[blockIdx.x] = m;
@@ -121,8 +123,9 @@ __global__ __launch_bounds__(NT) void k_prim2con(const Grid G, const double *__r
   if (c < G.nv) prim2con_one(G, prim, met, q, c);
 }
 
-// Ghost fill, one ghost per thread, from ghost number `skip` on (the x-face
-// ghosts come first; the recovery may have written them).
+// Ghost fill, one ghost per thread, from ghost number `skip` on (ghosts are
+// numbered axis by axis; the recovery may have written those of the
+// leading axes).
 __global__ __launch_bounds__(NT) void k_ghosts(const Grid G, double *prim, long total,
                                                const double *__restrict__ skipp, long skip) {
   if (skipp && *skipp == 0.0) return;
@@ -208,10 +211,10 @@ void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, c
 }
 
 int launch_c2p(gmunu_ctx *ctx, double *q, const double *metric, double *prim, uint8_t *flags,
-               unsigned int *nfatal_dev, const double *skipp, hipStream_t st, int xg = 0, double *part = nullptr) {
+               unsigned int *nfatal_dev, const double *skipp, hipStream_t st, int gaxes = 0, double *part = nullptr) {
   ProfScope ps(ctx, st, GMUNU_K_C2P);
   hipLaunchKernelGGL(k_c2p, dim3(nblocks(interior_cells(ctx->G))), dim3(NT), 0, st, ctx->G, q, metric, prim, flags,
-                     nfatal_dev, skipp, xg, part);
+                     nfatal_dev, skipp, gaxes, part);
   return launch_status();
 }
 
@@ -259,9 +262,9 @@ int rk_stage_impl(gmunu_ctx *ctx, int stage, const double *dt_dev, const double 
   int rc = launch_status();
   if (rc) return rc;
   if (fuse) return launch_ghosts(ctx, prim_out, skipp, st);
-  rc = launch_c2p(ctx, q_out, metric, prim_out, flags, nfatal_dev, skipp, st, ctx->xghosts > 0, part);
+  rc = launch_c2p(ctx, q_out, metric, prim_out, flags, nfatal_dev, skipp, st, ctx->raxes, part);
   if (rc) return rc;
-  return launch_ghosts(ctx, prim_out, skipp, st, ctx->xghosts);
+  return launch_ghosts(ctx, prim_out, skipp, st, ctx->rghosts);
 }
 
 int step_impl(gmunu_ctx *ctx, double *q_n, double *q_s, double *prim, const double *metric, const double *kij,
@@ -284,7 +287,7 @@ int gmunu_create(const gmunu_grid_desc *desc, gmunu_ctx **out) {
   ctx->prof = 0;
   ctx->nrec = 0;
   ctx->c2pmax = nullptr;
-  ctx->xghosts = recovery_x_ghosts(*desc);
+  ctx->rghosts = recovery_ghosts(*desc, &ctx->raxes);
   if (hipGetDevice(&ctx->device) != hipSuccess) {
     delete ctx;
     return GMUNU_EHIP;
@@ -638,7 +641,7 @@ int gmunu_step_static(const gmunu_grid_desc *desc, double *q_n, double *q_s, dou
   ctx.nrec = 0;
   ctx.qt = nullptr;
   ctx.c2pmax = nullptr;
-  ctx.xghosts = recovery_x_ghosts(*desc);
+  ctx.rghosts = recovery_ghosts(*desc, &ctx.raxes);
   grid_scalars(*desc, ctx.G);
   for (int a = 0; a < 3; a++)
     if (ctx.G.nt[a] > kStaticAxis) return GMUNU_EINVAL;  // beyond the scratch's tables

@@ -225,21 +225,31 @@ inline long ghost_total(const Grid &G) {
 
 inline unsigned nblocks(long n) { return (unsigned)((n + NT - 1) / NT); }
 
-// x-face ghosts that the recovery kernel of a step writes from the cells it
+// Face ghosts that the recovery kernel of a step writes from the cells it
 // recovers (else 0; the ghost kernel then skips them, as they come first in
-// ghost_one's numbering): every x-face ghost when both x faces are
-// periodic, outflow or reflecting (each ghost a copy of one cell of its own
-// row, sign-flipped for reflection) and a row holds at least ng cells
-// (every source interior).  The recovering thread stores them into the
-// cache lines its row's primitives already occupy; a ghost kernel would
-// gather them row by row, one cache line per variable per ghost.
-inline long recovery_x_ghosts(const gmunu_grid_desc &d) {
-  for (int s = 0; s < 2; s++) {
-    const int bc = d.bc[0][s];
-    if (bc != GMUNU_BC_PERIODIC && bc != GMUNU_BC_OUTFLOW && bc != GMUNU_BC_REFLECT) return 0;
+// ghost_one's numbering): those of the leading axes (x; x and y; all three)
+// whose faces are periodic, outflow or reflecting (each ghost a copy of one
+// cell of its own line, sign-flipped for reflection) and that hold at least
+// ng cells (every source interior).  *axes: how many axes.  The recovering
+// thread stores them from its registers, into cache lines its line's
+// primitives already occupy along x, and as whole rows along y and z; a
+// ghost kernel would read every source again (and gather x-face ghosts one
+// cache line per variable per ghost).
+inline long recovery_ghosts(const gmunu_grid_desc &d, int *axes) {
+  const long nin = (long)d.n[0] * d.n[1] * d.n[2];
+  long tot = 0;
+  int a = 0;
+  for (; a < d.ndim; a++) {
+    bool ok = d.n[a] >= d.ng;
+    for (int s = 0; s < 2; s++) {
+      const int bc = d.bc[a][s];
+      ok = ok && (bc == GMUNU_BC_PERIODIC || bc == GMUNU_BC_OUTFLOW || bc == GMUNU_BC_REFLECT);
+    }
+    if (!ok) break;
+    tot += 2L * d.ng * (nin / d.n[a]);
   }
-  if (d.n[0] < d.ng) return 0;
-  return 2L * d.ng * ((long)d.n[1] * d.n[2]);
+  *axes = a;
+  return tot;
 }
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }

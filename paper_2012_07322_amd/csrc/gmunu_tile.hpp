@@ -760,50 +760,56 @@ __device__ __forceinline__ void stage_tile(const Grid &G, int i0, int j0, int k0
                                                fc);
 }
 
-// The x-face ghosts whose source is interior cell (i, j, k), written from
-// that cell's primitives pr by ghost_one's rules: an outflow face copies its
-// end cell into every layer, a periodic face takes layer l from the cell l
-// in from the other end, a reflecting face from the cell l in from its own
-// end with the x components of velocity and field negated.  Only for
-// periodic, outflow and reflecting x faces and n0 >= ng (every source
+// The face-adjacent ghosts of the first `axes` axes whose source is interior
+// cell (i, j, k), written from that cell's primitives pr by ghost_one's
+// rules: an outflow face copies its end cell into every layer, a periodic
+// face takes layer l from the cell l in from the other end, a reflecting
+// face from the cell l in from its own end with the axis's components of
+// velocity and field negated.  Only for axes whose faces are periodic,
+// outflow or reflecting and that hold at least ng cells (every source
 // interior); each ghost has one source, so one thread writes it.
-__device__ __forceinline__ void x_ghosts_from(const Grid &G, double *prim, const double *pr, int i, int j, int k) {
-  const int na = G.n[0], ng = G.g[0];
+__device__ __forceinline__ void face_ghosts_from(const Grid &G, double *prim, const double *pr, int i, int j, int k,
+                                                 int axes) {
   const long nv = G.nv;
-  for (int side = 0; side < 2; side++) {
-    const int bc = G.bc[0][side];
-    if (bc != BC_OUTFLOW && bc != BC_PERIODIC && bc != BC_REFLECT) continue;
-    int l0, l1;  // layers [l0, l1) of this side sourced by cell i
-    if (bc == BC_OUTFLOW) {
-      if (i != (side == 0 ? 0 : na - 1)) continue;
-      l0 = 0;
-      l1 = ng;
-    } else {
-      l0 = (bc == BC_PERIODIC) == (side == 0) ? na - 1 - i : i;
-      if (l0 >= ng) continue;
-      l1 = l0 + 1;
-    }
-    const double s = bc == BC_REFLECT ? -1.0 : 1.0;
-    for (int l = l0; l < l1; l++) {
-      const long cd = cell_offset(G, side == 0 ? -1 - l : na + l, j, k);
-      prim[cd] = pr[0];
-      prim[4 * nv + cd] = pr[4];
-      prim[nv + cd] = s * pr[1];
-      prim[5 * nv + cd] = s * pr[5];
-      prim[2 * nv + cd] = pr[2];
-      prim[6 * nv + cd] = pr[6];
-      prim[3 * nv + cd] = pr[3];
-      prim[7 * nv + cd] = pr[7];
+  const int cell[3] = {i, j, k};
+  for (int a = 0; a < axes; a++) {
+    const int na = G.n[a], ng = G.g[a], ca = cell[a];
+    for (int side = 0; side < 2; side++) {
+      const int bc = G.bc[a][side];
+      if (bc != BC_OUTFLOW && bc != BC_PERIODIC && bc != BC_REFLECT) continue;
+      int l0, l1;  // layers [l0, l1) of this side sourced by the cell
+      if (bc == BC_OUTFLOW) {
+        if (ca != (side == 0 ? 0 : na - 1)) continue;
+        l0 = 0;
+        l1 = ng;
+      } else {
+        l0 = (bc == BC_PERIODIC) == (side == 0) ? na - 1 - ca : ca;
+        if (l0 >= ng) continue;
+        l1 = l0 + 1;
+      }
+      const double s = bc == BC_REFLECT ? -1.0 : 1.0;
+      for (int l = l0; l < l1; l++) {
+        const int gi = side == 0 ? -1 - l : na + l;
+        const long cd = cell_offset(G, a == 0 ? gi : i, a == 1 ? gi : j, a == 2 ? gi : k);
+        prim[cd] = pr[0];
+        prim[4 * nv + cd] = pr[4];
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+          prim[(1 + m) * nv + cd] = m == a ? s * pr[1 + m] : pr[1 + m];
+          prim[(5 + m) * nv + cd] = m == a ? s * pr[5 + m] : pr[5 + m];
+        }
+      }
     }
   }
 }
 
 // Primitive recovery of interior cell number t (x fastest) of grid G; a
-// fatal outcome increments *nfatal and *nfatal2 (each nullable).  xg: also
-// write the x-face ghosts this cell is the source of (x_ghosts_from).
+// fatal outcome increments *nfatal and *nfatal2 (each nullable).  gaxes:
+// also write the face ghosts of the first gaxes axes that this cell is the
+// source of (face_ghosts_from; 0: none).
 __device__ __forceinline__ void c2p_one(const Grid &G, double *q, const double *__restrict__ met, double *prim,
                                         uint8_t *flags, unsigned int *nfatal, long t,
-                                        unsigned int *nfatal2 = nullptr, bool xg = false) {
+                                        unsigned int *nfatal2 = nullptr, int gaxes = 0) {
   const int i = (int)(t % G.n[0]);
   const int j = (int)((t / G.n[0]) % G.n[1]);
   const int k = (int)(t / ((long)G.n[0] * G.n[1]));
@@ -817,7 +823,7 @@ __device__ __forceinline__ void c2p_one(const Grid &G, double *q, const double *
   const int fl = c2p_any(G, qc, psi, alpha, g1, g2, pr);
 #pragma unroll
   for (int v = 0; v < NV; v++) prim[v * G.nv + c] = pr[v];
-  if (xg) x_ghosts_from(G, prim, pr, i, j, k);
+  if (gaxes > 0) face_ghosts_from(G, prim, pr, i, j, k, gaxes);
   if (fl & FL_REWRITE) {
     double U[NV];
     const double beta[3] = {met[2 * G.nv + c], met[3 * G.nv + c], met[4 * G.nv + c]};

@@ -1,7 +1,7 @@
 """gmunu_steps (several steps in one call, the CFL maxima of each later step
 written by the previous step's last recovery) against the same number of
-gmunu_step calls, and the x-face ghosts that the recovery writes against
-the ghost kernel's fill.
+gmunu_step calls, and the face ghosts that the recovery writes against the
+ghost kernel's fill.
 
 Both are the same arithmetic on the same data, so the comparisons are bit
 for bit: conserved variables, primitives with every ghost layer, flags,
@@ -23,13 +23,13 @@ def _xbc(p, lo, hi):
     return p
 
 
-def _smooth(nd, coord, n, bc_x, **kw):
+def _smooth(nd, coord, n, bc_x, bc_rest=None, lo=None, hi=None, **kw):
     if coord == W.CART:
-        lo, hi = [-0.4, -0.3, -0.2], [0.5, 0.6, 0.7]
+        lo, hi = lo or [-0.4, -0.3, -0.2], hi or [0.5, 0.6, 0.7]
     else:  # a shell segment away from the centre and the axis
-        lo, hi = [1.0, 0.6, 0.0], [2.0, 2.2, 1.5]
+        lo, hi = lo or [1.0, 0.6, 0.0], hi or [2.0, 2.2, 1.5]
     hi = [hi[a] if a < nd else lo[a] + (1.0 if coord == W.CART or a < 2 else 2 * np.pi) for a in range(3)]
-    bc = [list(bc_x)] + [[W.OUTFLOW, W.OUTFLOW]] * (nd - 1)
+    bc = [list(bc_x)] + [list(b) for b in (bc_rest or [[W.OUTFLOW, W.OUTFLOW]] * (nd - 1))]
     p = W.grid(nd, coord, list(n), lo, hi, bc, gamma=5.0 / 3.0, rk=kw.pop("rk", 3), rho_atmo=1e-12, k_atmo=1.0,
                gamma_atmo=5.0 / 3.0, **kw)
     pr, met = smooth_random_state(p, seed=len(n), beta_amp=0.02)
@@ -52,6 +52,11 @@ def _cases():
     out["cart 3d reflect"] = _smooth(3, W.CART, (9, 7, 5), (W.REFLECT, W.OUTFLOW))
     out["cart 2d periodic n0=2"] = _smooth(2, W.CART, (2, 12), (W.PERIODIC, W.PERIODIC))
     out["cart 2d n0=1"] = _smooth(2, W.CART, (1, 16), (W.OUTFLOW, W.OUTFLOW))
+    out["cart 3d y periodic z reflect"] = _smooth(3, W.CART, (6, 8, 5), (W.OUTFLOW, W.REFLECT),
+                                                  [[W.PERIODIC, W.PERIODIC], [W.REFLECT, W.REFLECT]])
+    out["cart 3d ny=1"] = _smooth(3, W.CART, (8, 1, 6), (W.REFLECT, W.OUTFLOW))
+    out["sph 2d axis"] = _smooth(2, W.SPH, (16, 12), (W.OUTFLOW, W.OUTFLOW), [[W.AXIS, W.REFLECT]],
+                                 lo=[1.0, 0.0, 0.0], hi=[2.0, 0.5 * np.pi, 0.0])
     return out
 
 
@@ -98,9 +103,11 @@ def test_steps_equal_single_steps(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_recovery_x_ghosts_equal_the_ghost_kernel(name):
-    """After steps whose recovery wrote the x-face ghosts, the ghost kernel
-    refilling every face leaves the primitives unchanged."""
+def test_recovery_ghosts_equal_the_ghost_kernel(name):
+    """After steps whose recovery wrote the face ghosts of the leading axes
+    it can (all three, x only when y sits on the polar axis or holds fewer
+    than ng cells, none when x does), the ghost kernel refilling every face
+    leaves the primitives unchanged."""
     p, pr, met = CASES[name]
     g = gmu.Grid(p)
     qn, qs, prd, metd, t, dt, fl, nf = _start(g, pr, met)
