@@ -64,8 +64,9 @@ constexpr bool kPrefetchQ = GM_PREFETCH_Q;
 // corner cells: the face fluxes have no transverse stencil and the metric
 // derivatives are centred along one axis).  Seven boxes, each x-fastest:
 // centre (TX, TY, TZ), x-lo and x-hi (H, TY, TZ), y-lo and y-hi (TX, H, TZ),
-// z-lo and z-hi (TX, TY, H).  LDS holds NV primitives and the 5 metric
-// variables per region cell, variable-major.
+// z-lo and z-hi (TX, TY, H).  LDS holds the NV primitives of every region
+// cell, variable-major, then (kMetLds) the 5 metric variables of the region
+// of halo met_halo() (met_index).
 template <int TX, int TY, int TZ, int ND, int H>
 struct Plus {
   static constexpr int HY = ND > 1 ? H : 0, HZ = ND > 2 ? H : 0;
@@ -117,6 +118,26 @@ __device__ __forceinline__ int plus_line(int s, int x, int y, int z) {
   } else {
     return s < 0 ? P::ZL + x + TX * (y + TY * (s + H))
                  : s < TZ ? x + TX * (y + TY * s) : P::ZH + x + TX * (y + TY * (s - TZ));
+  }
+}
+
+// The metric is staged on the plus region of halo MH: MH = H (the
+// primitives' region, same indices) or MH = 1, which is all that is read (a
+// face takes the metric of its two adjacent cells and the sources'
+// derivatives are centred).  Index in the metric's region of region cell c
+// at tile-relative (x, y, z), or -1 for a cell beyond MH; the centre box has
+// the same indices in both regions.
+template <int TX, int TY, int TZ, int ND, int H, int MH>
+__device__ __forceinline__ int met_index(int c, int x, int y, int z) {
+  static_assert(MH == H || MH == 1, "the metric is staged on the primitives' region or on halo 1");
+  if constexpr (MH == H) {
+    return c;
+  } else {
+    if (x >= 0 && x < TX && y >= 0 && y < TY && z >= 0 && z < TZ) return x + TX * (y + TY * z);
+    if (x == -1 || x == TX) return plus_line<TX, TY, TZ, ND, 1, 0>(x, x, y, z);
+    if (y == -1 || y == TY) return plus_line<TX, TY, TZ, ND, 1, 1>(y, x, y, z);
+    if (z == -1 || z == TZ) return plus_line<TX, TY, TZ, ND, 1, 2>(z, x, y, z);
+    return -1;
   }
 }
 
@@ -454,11 +475,25 @@ constexpr int max_faces() {
   return f0 > f1 ? (f0 > f2 ? f0 : f2) : (f1 > f2 ? f1 : f2);
 }
 
-// LDS doubles per workgroup: the staged region (primitives, and the metric
-// when kMetLds) and the face fluxes of one pass.
+// LDS doubles per workgroup: the staged region's primitives, the metric on
+// the region of halo MH (kMetLds), and the face fluxes of one pass.
+template <int TX, int TY, int TZ, int ND, int H, int MH>
+constexpr int stage_lds_mh() {
+  return NV * Plus<TX, TY, TZ, ND, H>::N + (kMetLds ? 5 * Plus<TX, TY, TZ, ND, MH>::N : 0) +
+         NV * max_faces<TX, TY, TZ, ND>();
+}
+
+// The metric's halo: the primitives' (no index arithmetic of its own) when
+// two workgroups then fit the 160 KB of LDS of a CU, else 1 (for the 8x8x3
+// and 16x4x3 tiles, whose full regions would leave one workgroup per CU).
+template <int TX, int TY, int TZ, int ND, int H>
+constexpr int met_halo() {
+  return stage_lds_mh<TX, TY, TZ, ND, H, H>() * 8 * 2 <= 160 * 1024 ? H : 1;
+}
+
 template <int TX, int TY, int TZ, int ND, int H = 2>
 constexpr int stage_lds() {
-  return (NV + (kMetLds ? 5 : 0)) * Plus<TX, TY, TZ, ND, H>::N + NV * max_faces<TX, TY, TZ, ND>();
+  return stage_lds_mh<TX, TY, TZ, ND, H, met_halo<TX, TY, TZ, ND, H>()>();
 }
 
 // Workgroups per CU that the LDS of a tile shape allows (160 KB per CU), at
@@ -515,8 +550,9 @@ __device__ __forceinline__ void region_load(const Grid &G, const double *__restr
 #pragma unroll
       for (int v = 0; v < NV; v++) R.val[it][v] = prim[v * G.nv + o];
       if constexpr (kMetLds) {
+        const bool m = met_index<TX, TY, TZ, ND, H, met_halo<TX, TY, TZ, ND, H>()>(c, x, y, z) >= 0;
 #pragma unroll
-        for (int w = 0; w < 5; w++) R.val[it][NV + w] = met[w * G.nv + o];
+        for (int w = 0; w < 5; w++) R.val[it][NV + w] = m ? met[w * G.nv + o] : 0.0;
       }
     } else {
 #pragma unroll
@@ -529,12 +565,23 @@ __device__ __forceinline__ void region_load(const Grid &G, const double *__restr
 template <int TX, int TY, int TZ, int ND, int H>
 __device__ __forceinline__ void region_store(const RegionRegs<TX, TY, TZ, ND, H> &R, double *S) {
   using RR = RegionRegs<TX, TY, TZ, ND, H>;
+  constexpr int MH = met_halo<TX, TY, TZ, ND, H>();
+  constexpr int NPM = Plus<TX, TY, TZ, ND, MH>::N;
 #pragma unroll
   for (int it = 0; it < RR::NIT; it++) {
     const int c = threadIdx.x + it * NT;
     if (R.in[it]) {
 #pragma unroll
-      for (int v = 0; v < RR::NW; v++) S[v * RR::NP + c] = R.val[it][v];
+      for (int v = 0; v < NV; v++) S[v * RR::NP + c] = R.val[it][v];
+      if constexpr (kMetLds) {
+        int x = 0, y = 0, z = 0;
+        if constexpr (MH != H) plus_cell<TX, TY, TZ, ND, H>(c, x, y, z);
+        const int m = met_index<TX, TY, TZ, ND, H, MH>(c, x, y, z);
+        if (m >= 0) {
+#pragma unroll
+          for (int w = 0; w < 5; w++) S[NV * RR::NP + w * NPM + m] = R.val[it][NV + w];
+        }
+      }
     }
   }
 }
@@ -559,11 +606,15 @@ __device__ __forceinline__ void pass_fluxes(const Grid &G, const double *S, cons
     for (int m = 0; m < 2 * H; m++) ix[m] = plus_line<TX, TY, TZ, ND, H, D>(sd - H + m, fx, fy, fz);
     double ma[5], mb[5];
     if constexpr (kMetLds) {
+      constexpr int MH = met_halo<TX, TY, TZ, ND, H>();
+      constexpr int NPM = Plus<TX, TY, TZ, ND, MH>::N;
       const double *Sm = S + NV * NP;
+      const int ja = MH == H ? ix[H - 1] : plus_line<TX, TY, TZ, ND, MH, D>(sd - 1, fx, fy, fz);
+      const int jb = MH == H ? ix[H] : plus_line<TX, TY, TZ, ND, MH, D>(sd, fx, fy, fz);
 #pragma unroll
       for (int w = 0; w < 5; w++) {
-        ma[w] = Sm[w * NP + ix[H - 1]];
-        mb[w] = Sm[w * NP + ix[H]];
+        ma[w] = Sm[w * NPM + ja];
+        mb[w] = Sm[w * NPM + jb];
       }
     } else {
       const long ob = cell_offset(G, ci, cj, ck), oa = ob - G.s[D];
@@ -657,7 +708,9 @@ __device__ __forceinline__ void stage_staged(const Grid &G, int i0, int j0, int 
   for (int v = 0; v < NV; v++) acc[v] = 0.0;
   PPBase pp{nullptr, 0.0};
   if constexpr (P) pp = PPBase{ca == 0.0 ? qn : qs, *dtp};
-  double *SF = sF + (NV + (kMetLds ? 5 : 0)) * NP;
+  constexpr int MH = met_halo<TX, TY, TZ, ND, H>();
+  constexpr int NPM = Plus<TX, TY, TZ, ND, MH>::N;
+  double *SF = sF + NV * NP + (kMetLds ? 5 * NPM : 0);
   bool nonflat = false;
   double Fo[NV];
   pass_fluxes<TX, TY, TZ, ND, 0, REC, R, P>(G, sF, met, i0, j0, k0, Fo, nonflat, pp);
@@ -684,11 +737,11 @@ __device__ __forceinline__ void stage_staged(const Grid &G, int i0, int j0, int 
     auto metv = [&](int w, int a, int o) -> double {
       if (a >= ND) return 0.0;
       if constexpr (kMetLds) {
-        if (a < 0) return Sm[w * NP + c];
-        const int p = a == 0 ? plus_line<TX, TY, TZ, ND, H, 0>(tx + o, tx, ty, tz)
-                             : a == 1 ? plus_line<TX, TY, TZ, ND, H, 1>(ty + o, tx, ty, tz)
-                                      : plus_line<TX, TY, TZ, ND, H, 2>(tz + o, tx, ty, tz);
-        return Sm[w * NP + p];
+        if (a < 0) return Sm[w * NPM + c];
+        const int p = a == 0 ? plus_line<TX, TY, TZ, ND, MH, 0>(tx + o, tx, ty, tz)
+                             : a == 1 ? plus_line<TX, TY, TZ, ND, MH, 1>(ty + o, tx, ty, tz)
+                                      : plus_line<TX, TY, TZ, ND, MH, 2>(tz + o, tx, ty, tz);
+        return Sm[w * NPM + p];
       } else {
         return met[w * G.nv + oc + (a < 0 ? 0 : o * G.s[a])];
       }
@@ -720,7 +773,7 @@ __device__ __forceinline__ void stage_staged(const Grid &G, int i0, int j0, int 
         // values: q from registers, psi and alpha from the staged region)
         const int c = tx + TX * (ty + TY * tz);
         const double *Sm = sF + NV * NP;
-        const double psi = Sm[c], alpha = Sm[NP + c];
+        const double psi = Sm[c], alpha = Sm[NPM + c];
         double g1 = 1.0, g2 = 1.0;
         if (G.coord != CART) ref_diag(G.coord, G.geo.r2c[i + G.g[0]], G.geo.s2c[j + G.g[1]], g1, g2);
         double pr[NV];
@@ -728,7 +781,7 @@ __device__ __forceinline__ void stage_staged(const Grid &G, int i0, int j0, int 
 #pragma unroll
         for (int v = 0; v < NV; v++) fc.prim[v * G.nv + oc] = pr[v];
         if (fl & FL_REWRITE) {
-          const double beta[3] = {Sm[2 * NP + c], Sm[3 * NP + c], Sm[4 * NP + c]};
+          const double beta[3] = {Sm[2 * NPM + c], Sm[3 * NPM + c], Sm[4 * NPM + c]};
           prim_to_cons(G.gam, G.gfac, pr, psi, alpha, beta, g1, g2, qo);
         }
         if (fc.flags) fc.flags[oc] = (uint8_t)fl;
