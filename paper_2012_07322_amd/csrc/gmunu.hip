@@ -201,7 +201,7 @@ void launch_stage(const gmunu_ctx *ctx, const double *prim, const double *met, c
   GM_CASES_R(NDIM, TX, TY, TZ, 2)
     GM_CASES(1, 255, 1, 1)
     GM_CASES(2, 16, 15, 1)
-    GM_CASES(3, 8, 6, 4)
+    GM_CASES(3, 16, 4, 3)
 #undef GM_CASES
 #undef GM_CASES_R
 #undef GM_CASE

@@ -1,7 +1,8 @@
 """Edge cases of the GPU path against the oracle: the smallest grids (one
 cell along an axis), extents one below, at and one above a tile edge (the
-stage kernel's tiles are 255 cells in 1D, 16 x 15 in 2D and 8 x 6 x 4 in
-3D), several steps on such grids, an empty batch and an idle server.
+stage kernel's tiles are 255 cells in 1D, 16 x 15 in 2D and 16 x 4 x 3 in
+3D; the batch's 3D tiles also 8 x 6 x 4, 8 x 8 x 3 and 8 x 5 x 5), several
+steps on such grids, an empty batch and an idle server.
 
 Tolerances as in test_gpu_parity: the right-hand side at 1e-12 of each
 cell's error scale and 1e-12 forward error per variable; ten steps at
@@ -30,7 +31,8 @@ def _grid(n, coord=W.CART):
 
 SHAPES = [(1,), (2,), (254,), (255,), (256,), (511,),
           (1, 1), (16, 15), (15, 14), (17, 16), (1, 40), (40, 1),
-          (1, 1, 1), (8, 6, 4), (7, 5, 3), (9, 7, 5), (1, 6, 9), (17, 13, 2)]
+          (1, 1, 1), (8, 6, 4), (7, 5, 3), (9, 7, 5), (1, 6, 9), (17, 13, 2),
+          (16, 4, 3), (15, 3, 2), (17, 5, 4), (32, 8, 6)]
 
 
 @pytest.mark.parametrize("n", SHAPES, ids=["x".join(map(str, s)) for s in SHAPES])
