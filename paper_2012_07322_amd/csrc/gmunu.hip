@@ -1,19 +1,23 @@
 // GRMHD finite-volume step for MI355X (gfx950): single-grid kernels and the
 // C ABI.
 //
-// One RK stage is three launches on the caller's stream:
-//   k_stage   per tile of cells (8x5x5 in 3D, 16x15 in 2D, 255 in 1D, so
-//             that each direction's faces fit one per thread): per direction
-//             the tile's stencil region of prim and metric is staged in LDS,
-//             each face is reconstructed (MC, MP5 or PPM) and its HLLE or
-//             TVDLF flux (optionally positivity-limited) computed once,
-//             fluxes are exchanged through LDS into the flux-area divergence;
-//             then gravitational + geometric sources and the RK combination;
-//   k_c2p     per interior cell: primitive recovery with error handling;
-//   k_ghosts  per face-adjacent ghost cell: boundary fill of the primitives.
+// One RK stage is up to three launches on the caller's stream:
+//   k_stage   per tile of cells (16x4x3 in 3D, 16x15 in 2D, 255 in 1D, so
+//             that each direction's faces fit one per thread): the tile's
+//             plus-shaped region of prim and metric is staged in LDS once,
+//             then per direction each face is reconstructed (MC, MP5 or
+//             PPM) and its HLLE or TVDLF flux (optionally positivity-limited)
+//             computed once, fluxes exchanged through LDS into the flux-area
+//             divergence; then gravitational + geometric sources and the RK
+//             combination;
+//   k_c2p     per interior cell: primitive recovery with error handling,
+//             writing the face ghosts its cell is the source of on the axes
+//             whose boundary rules copy a cell of the line;
+//   k_ghosts  per remaining face-adjacent ghost cell: boundary fill.
 // The time step is a per-cell rate reduced by wavefront shuffles to one
-// maximum per workgroup (a fixed number of grid-stride workgroups), then by
-// one workgroup that writes dt: no atomics, no memset, graph-capturable.
+// maximum per workgroup (a fixed number of grid-stride workgroups, or in
+// gmunu_steps the previous step's last recovery), then by one workgroup that
+// writes dt: no atomics, no memset, graph-capturable.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -100,10 +104,9 @@ __global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC
 
 // Recovery of one interior cell per thread.  gaxes: also write the face
 // ghosts of the first gaxes axes copied from the recovered cells.  part
-// (nullable): the
-// workgroup's maximum CFL rate of the primitives just recovered, at
-// part[blockIdx.x] (the next step's CFL maxima, when nothing changes the
-// interior primitives before it).
+// (nullable): the workgroup's maximum CFL rate of the primitives just
+// recovered, at part[blockIdx.x] (the next step's CFL maxima, when nothing
+// changes the interior primitives before it).
 __global__ __launch_bounds__(NT) void k_c2p(const Grid G, double *q, const double *__restrict__ met, double *prim,
                                             uint8_t *flags, unsigned int *nfatal, const double *__restrict__ skipp,
                                             int gaxes, double *part) {

@@ -484,8 +484,9 @@ constexpr int stage_lds_mh() {
 }
 
 // The metric's halo: the primitives' (no index arithmetic of its own) when
-// two workgroups then fit the 160 KB of LDS of a CU, else 1 (for the 8x8x3
-// and 16x4x3 tiles, whose full regions would leave one workgroup per CU).
+// two workgroups then fit the 160 KB of LDS of a CU, else 1 (the 8x8x3 and
+// 16x4x3 tiles among others, whose full regions would leave one workgroup
+// per CU).
 template <int TX, int TY, int TZ, int ND, int H>
 constexpr int met_halo() {
   return stage_lds_mh<TX, TY, TZ, ND, H, H>() * 8 * 2 <= 160 * 1024 ? H : 1;
