@@ -130,11 +130,10 @@ __global__ __launch_bounds__(NT, (stage_occupancy<TX, TY, TZ, ND, recon_halo(REC
 // Recovery on 256-cell items: from q_n (use_qn) or q_s.  force: ignore dt.
 // gfill: the thread that recovers a cell also writes the face ghosts of the
 // block's first raxes axes copied from it (no barrier, no re-read).  part
-// non-null (the last stage of a step followed by
-// another step of the same launch sequence): the item's CFL rate maximum,
-// from the primitives just recovered (nothing changes the interior
-// primitives before the next step), at its place in the CFL list, so that
-// the next step needs no CFL kernel.  Items skipped for dt = 0 write none:
+// non-null (the last stage of a step followed by another step of the same
+// launch sequence): the item's CFL rate maximum, from the primitives just
+// recovered (nothing changes the interior primitives before the next step),
+// at its place in the CFL list, so that the next step needs no CFL kernel.  Items skipped for dt = 0 write none:
 // their group's dt stays 0 in the next step whatever its maxima.
 __global__ __launch_bounds__(NT) void k_bc2p(const BlockRec *__restrict__ B, DList L, const double *dts, int use_qn,
                                              int force, unsigned int *nfatal, unsigned int *gfatal, int gfill,
