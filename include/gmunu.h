@@ -284,6 +284,15 @@ int gmunu_batch_commit(gmunu_batch *b, void *stream);
  * blocks and keep the fastest (writes q_s of the blocks as scratch);
  * recommits.  Results do not depend on the choice. */
 int gmunu_batch_autotune(gmunu_batch *b, void *stream);
+/* Pin the tile shape of the stage kernel for the class of blocks of
+ * descriptor d (same ndim, n, recon and riemann), as the autotuner would:
+ * blocks of that class already in the batch and those set later use it,
+ * from the next commit on.  Compiled shapes (tx, ty, tz): MC in 3D 8x8x3,
+ * 8x5x5, 16x4x3, 8x6x4, in 2D 16x15x1, 32x7x1, 8x28x1, in 1D 255x1x1; MP5
+ * and PPM 8x5x5, 16x15x1, 255x1x1.  For reproducible timings and tests
+ * (a tuning control, not in the paper); results do not depend on the shape.
+ * GMUNU_EINVAL for a shape not compiled for d's ndim and reconstruction. */
+int gmunu_batch_set_tile(gmunu_batch *b, const gmunu_grid_desc *d, int tx, int ty, int tz);
 /* Initial data of the given committed slots (all if slots is NULL): fill the
  * ghosts of prim, q_n = prim2con(prim) on the interior, recover prim from
  * q_n, fill the ghosts again.  Other slots are not touched; synchronises

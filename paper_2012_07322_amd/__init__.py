@@ -291,6 +291,7 @@ def _batch_sigs(L):
     L.gmunu_batch_set_group.argtypes = [_P, I, D, D, I]
     L.gmunu_batch_commit.argtypes = [_P, _P]
     L.gmunu_batch_autotune.argtypes = [_P, _P]
+    L.gmunu_batch_set_tile.argtypes = [_P, _P, I, I, I]
     L.gmunu_batch_init.argtypes = [_P, _P, I, _P]
     L.gmunu_batch_step.argtypes = [_P, D, _P, I, _P]
     L.gmunu_batch_steps.argtypes = [_P, D, I, _P, _P]
@@ -382,6 +383,13 @@ class Batch:
 
     def autotune(self):
         _check(lib().gmunu_batch_autotune(self._h, _stream()), "gmunu_batch_autotune")
+
+    def set_tile(self, params, tx, ty, tz):
+        """Pin the stage tile shape for the class of blocks of `params`
+        (gmunu_batch_set_tile); applied at the next commit."""
+        d = make_desc(params)
+        _check(lib().gmunu_batch_set_tile(self._h, ctypes.byref(d), int(tx), int(ty), int(tz)),
+               "gmunu_batch_set_tile")
 
     def init(self, slots=None):
         if slots is None:

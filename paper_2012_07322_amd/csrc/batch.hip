@@ -711,6 +711,24 @@ int gmunu_batch_clear_block(gmunu_batch *b, int slot) {
   return GMUNU_OK;
 }
 
+int gmunu_batch_set_tile(gmunu_batch *b, const gmunu_grid_desc *d, int tx, int ty, int tz) {
+  if (!b || !d) return GMUNU_ENULL;
+  int v = -1;
+  for (int k = 0; k < NVAR; k++)
+    if (kVar[k].tx == tx && kVar[k].ty == ty && kVar[k].tz == tz && kVar[k].nd == d->ndim &&
+        kVar[k].rec == d->recon)
+      v = k;
+  if (v < 0) return GMUNU_EINVAL;
+  const auto key = bucket_of(*d);
+  b->tuned[key] = v;
+  for (int s = 0; s < b->maxb; s++)
+    if (b->used[s] && bucket_of(b->blk[s].desc) == key && b->var[s] != v) {
+      b->var[s] = v;
+      b->touch(s);
+    }
+  return GMUNU_OK;
+}
+
 int gmunu_batch_set_group(gmunu_batch *b, int group, double t, double t_end, int max_steps) {
   if (!b) return GMUNU_ENULL;
   if (group < 0 || group >= b->maxg || !(t_end >= t)) return GMUNU_EINVAL;

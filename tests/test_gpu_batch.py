@@ -176,6 +176,50 @@ def test_x_ghosts_filled_by_the_recovery_equal_alone():
         assert np.array_equal(pa, pb), f"block {slot} prim differs"
 
 
+# every compiled tile shape of the batched stage: (ndim, reconstruction,
+# (tx, ty, tz)), in the order of the library's variant table
+TILES = [(3, 0, (8, 8, 3)), (3, 0, (8, 5, 5)), (3, 0, (16, 4, 3)), (3, 0, (8, 6, 4)), (2, 0, (16, 15, 1)),
+         (2, 0, (32, 7, 1)), (2, 0, (8, 28, 1)), (1, 0, (255, 1, 1)), (3, 1, (8, 5, 5)), (2, 1, (16, 15, 1)),
+         (1, 1, (255, 1, 1)), (3, 2, (8, 5, 5)), (2, 2, (16, 15, 1)), (1, 2, (255, 1, 1))]
+
+
+@pytest.mark.parametrize("k", range(len(TILES)), ids=[f"{t[0]}d-rec{t[1]}-{'x'.join(map(str, t[2]))}" for t in TILES])
+def test_every_tile_shape_equals_alone(k):
+    """Each compiled tile shape pinned with gmunu_batch_set_tile (those that
+    stage the metric on a one-cell halo among them) on ragged blocks of its
+    dimension and reconstruction: bitwise equal to the blocks advanced
+    alone after three steps."""
+    from test_gpu_parity import smooth_random_state
+
+    nd, rec, tile = TILES[k]
+    shapes = {3: [(13, 11, 9), (8, 8, 8), (17, 5, 7)], 2: [(40, 33), (17, 60)], 1: [(300,), (511,)]}[nd]
+    blocks = []
+    for m, n in enumerate(shapes):
+        lo, hi = [-0.4, -0.3, -0.2], [0.5, 0.6, 0.7]
+        hi = [hi[a] if a < nd else lo[a] + 1.0 for a in range(3)]
+        p = W.grid(nd, W.CART, list(n), lo, hi, [[W.OUTFLOW, W.OUTFLOW]] * nd, gamma=5.0 / 3.0, rk=3,
+                   rho_atmo=1e-12, k_atmo=1.0, gamma_atmo=5.0 / 3.0, ng=2 if rec == 0 else 3, recon=rec,
+                   riemann=m % 2)
+        pr, met = smooth_random_state(p, seed=m, beta_amp=0.02)
+        blocks.append((p, pr, met))
+    B, views, _ = make_batch(blocks, list(range(len(blocks))))
+    for p, _, _ in blocks:
+        B.set_tile(p, *tile)
+    B.commit()
+    _, var = B.info()
+    assert var[:len(blocks)].tolist() == [k] * len(blocks)
+    for _ in range(3):
+        B.step(0.4)
+    torch.cuda.synchronize()
+    t_b, _ = B.times()
+    for slot, (p, pr, met) in enumerate(blocks):
+        qa, pa, ta = alone(p, pr, met, 3)
+        qb, pb = views[slot][0].cpu().numpy(), views[slot][1].cpu().numpy()
+        assert t_b[slot] == ta, slot
+        assert np.array_equal(W.interior(p, qa), W.interior(p, qb)), f"block {slot} q differs"
+        assert np.array_equal(pa, pb), f"block {slot} prim differs"
+
+
 def test_multi_step_replay_equals_single_steps():
     """gmunu_batch_steps (several steps from one graph, the CFL maxima of
     each later step from the previous step's last recovery) equals the same
