@@ -125,6 +125,19 @@ def test_server_rejects_bad_arguments_before_touching_the_device():
     assert L.gmunu_server_clock() > 0.0
 
 
+def test_step_batch_and_metric_entry_points_reject_null_arguments():
+    """gmunu_steps, gmunu_batch_set_tile and gmunu_mg_dynamical_steps check
+    their handles and pointers before any device call."""
+    L = gmu.lib()
+    gmu._batch_sigs(L)
+    gmu._mg_sigs(L)
+    assert L.gmunu_steps(None, None, None, None, None, None, 0.4, 1e30, None, None, None, None, 1, None) == -2
+    assert L.gmunu_batch_set_tile(None, None, 8, 8, 3) == -2
+    n, trig = ctypes.c_int(0), ctypes.c_int(0)
+    assert L.gmunu_mg_dynamical_steps(None, None, None, None, None, None, None, None, None, 0.4, 1.0, None, None,
+                                      None, None, 1, 1e-3, ctypes.byref(n), ctypes.byref(trig), None) == -2
+
+
 def test_range_pool_host_logic():
     """The server's arena allocator (header-only, host code) under random
     alloc / release: ranges aligned, disjoint, inside the arena, and merged
